@@ -1,0 +1,235 @@
+/*
+ * stereo.h - C ABI of the MI355X dense ZNCC stereo library (libstereo_mi355x.so).
+ *
+ * Method: Zhou & Jagadeesan, "Real-time Dense Reconstruction of Tissue
+ * Surface from Stereo Optical Video" (arXiv 2007.12623), Section II:
+ * ZNCC local matching over a square window for every pixel and candidate
+ * disparity (II-A), winner-take-all, outlier removal and hole filling
+ * (II-B), improved Laplacian smoothing (II-C, Eqs. 1-3).  On top: a
+ * parabola sub-pixel offset, a left-right consistency check, a batched
+ * persistent launch, FP16/BF16 storage and a differentiable refinement.
+ *
+ * Conventions shared by every entry point
+ *  - Images are rectified 8-bit grey levels, row-major with a row pitch in
+ *    bytes (pitch >= W).  Left pixel (x, y) at disparity d matches right
+ *    pixel (x - d, y); d may be negative.  A window of odd size win lies
+ *    around each pixel (half size h = win / 2).
+ *  - Unless stated otherwise every data pointer is a DEVICE pointer owned by
+ *    the caller; outputs are written densely (row stride W elements).
+ *    Host pointers are marked "host".
+ *  - Work is enqueued on `stream` (a hipStream_t passed as void*, NULL = the
+ *    default stream) and the call returns without synchronising; results are
+ *    valid once the stream has reached that point.
+ *  - Arguments are checked on the host before any device call; invalid ones
+ *    return ST_EINVAL and touch nothing.  Launch failures return ST_EHIP.
+ *    st_last_error() describes the last failure of the calling thread.
+ *  - A handle owns its scratch memory (grown on demand, ST_ENOMEM if it
+ *    cannot grow).  Calls on one handle must not run concurrently from
+ *    several host threads or overlap on several streams.
+ */
+#ifndef STEREO_MI355X_H
+#define STEREO_MI355X_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  ST_OK = 0,
+  ST_EINVAL = -1,       /* bad argument (checked before any device work) */
+  ST_ENOMEM = -2,       /* device scratch could not be allocated */
+  ST_EHIP = -3,         /* a HIP runtime call or kernel launch failed */
+  ST_ENODEV = -4,       /* no usable gfx950 device */
+  ST_EUNSUPPORTED = -5  /* valid request this build does not implement */
+} st_status;
+
+typedef enum { ST_FP32 = 0, ST_FP16 = 1, ST_BF16 = 2 } st_precision;
+
+typedef struct st_handle_s *st_handle;
+
+/* Pipeline parameters.  st_default_params() fills the paper's constants. */
+typedef struct {
+  int32_t struct_size;        /* sizeof(st_params): ABI guard */
+  int32_t subpixel;           /* 1: parabola offset added to matched pixels */
+  int32_t lr_check;           /* 1: left-right consistency check */
+  int32_t lr_tol;             /* max |oL - oR| kept (1 px) */
+  int32_t radial_iters;       /* outlier/fill alternations (3, Section II-B);
+                                 0 = a single fill pass, no outlier removal */
+  int32_t radial_r0;          /* first outlier radius (10 px) */
+  int32_t radial_dr;          /* radius step per alternation (10 px) */
+  float radial_thresh;        /* neighbour disparity step bound (2.5) */
+  int32_t fill_radial_r;      /* radial fill search radius (50 px) */
+  int32_t fill_min_lines;     /* complete lines needed by the radial fill (2) */
+  int32_t fill_disk_r;        /* disk fill radius (20 px) */
+  float fill_disk_min_frac;   /* valid fraction of in-image disk cells (0.25) */
+  int32_t smooth_radius;      /* half size R of the (2R+1)^2 smoothing window (15) */
+  int32_t smooth_iters;       /* improved Laplacian iterations K (3; 0 = none) */
+  float smooth_alpha;         /* Eq. (2) weight (0.1) */
+  int32_t precision;          /* st_precision of image and cost storage */
+  int32_t debug_outputs;      /* 1: keep intermediates for stereo_debug_get */
+} st_params;
+
+/* Fill *p with the paper's constants (Section II, Appendix of constants):
+ * 3 alternations r = 10, 20, 30, threshold 2.5, fill radii 50 and 20,
+ * smoothing radius 15, alpha 0.1, K = 3, FP32. */
+void st_default_params(st_params *p);
+
+/* Create a handle bound to HIP device `device`.  *out receives the handle.
+ * ST_ENODEV when the device does not exist or is not gfx950. */
+st_status st_create(st_handle *out, int device);
+/* Release a handle and its scratch (synchronises the device first). */
+void st_destroy(st_handle h);
+
+/* Message for the last failing call of this thread ("" if none). */
+const char *st_last_error(void);
+
+/*
+ * Whole stereo path of Section II for one rectified pair.
+ *  left, right : H x W uint8 with row pitch `pitch` bytes
+ *  dmin..dmax  : candidate disparities, 8 <= dmax - dmin + 1 <= 256
+ *  win         : odd window size, 3..15 (15 keeps every window sum exact in
+ *                24 bits and the ZNCC numerator inside int32)
+ *  disparity   : H x W float out; NaN where invalid
+ *  valid_mask  : H x W uint8 out; 0 invalid, 1 matched, 2 filled
+ * Requires H >= win and W >= win.
+ */
+st_status stereo_match(st_handle h, const uint8_t *left, const uint8_t *right, int H, int W,
+                       int pitch, int dmin, int dmax, int win, const st_params *params,
+                       float *disparity, uint8_t *valid_mask, void *stream);
+
+/* One pair of a batch: same meaning as the stereo_match arguments. */
+typedef struct {
+  const uint8_t *left, *right;
+  int32_t H, W, pitch, dmin, dmax, win;
+  float *disparity;
+  uint8_t *valid_mask;
+} st_pair;
+
+/*
+ * Many pairs of uneven size, disparity range and window in one persistent
+ * matcher launch (a work queue over row bands, column spans and disparity
+ * chunks, longest tasks first) followed by batched post-processing.  The
+ * sequence of launches for a given batch layout is captured once into a
+ * HIP graph and replayed on later calls with the same layout and pointers.
+ *  pairs : host array of n_pairs descriptors (device image/output pointers)
+ * Results equal stereo_match on each pair, bit for bit.
+ */
+st_status stereo_match_batched(st_handle h, const st_pair *pairs, int n_pairs,
+                               const st_params *params, void *stream);
+
+/*
+ * Differentiable sub-pixel refinement: energy of a float disparity field
+ *   E(d) = sum_{p in Omega} (1 - Z_p(d)) + lambda_tv * TV(d)
+ * R_w(q) is the right row linearly interpolated at q_x - d(q) (clamped to
+ * [0, W-1]); Z_p is the ZNCC of the left window and the R_w window around p;
+ * Omega holds the pixels with mask != 0 whose whole window is inside the
+ * image, has mask != 0 everywhere and non-zero left variance; TV sums
+ * |d(q+e) - d(q)| over right and down neighbours that both have mask != 0.
+ *  d     : H x W float (device)        mask : H x W uint8 (device)
+ *  Z     : H x W float out, NaN outside Omega (may be NULL)
+ *  E     : one double out (device)
+ */
+st_status stereo_refine_forward(st_handle h, const uint8_t *left, const uint8_t *right,
+                                const float *d, const uint8_t *mask, int H, int W, int pitch,
+                                int win, float lambda_tv, float *Z, double *E, void *stream);
+/* dE/dd for the same energy (hand-written backward), H x W float out.
+ * Subgradient 0 at the kinks of |.| and of the interpolation. */
+st_status stereo_refine_backward(st_handle h, const uint8_t *left, const uint8_t *right,
+                                 const float *d, const uint8_t *mask, int H, int W, int pitch,
+                                 int win, float lambda_tv, float *grad_d, void *stream);
+/* One clamped gradient step d <- d - clamp(tau * g, -max_step, max_step) on
+ * pixels with mask != 0 (device arrays, H x W). */
+st_status stereo_refine_step(st_handle h, float *d, const float *grad_d, const uint8_t *mask,
+                             int H, int W, float tau, float max_step, void *stream);
+
+/*
+ * Device pointer of an intermediate of the last stereo_match call made with
+ * debug_outputs = 1 (the handle owns the memory; valid until the next call):
+ *  "o_wta" int16 H x W   left-reference WTA disparity
+ *  "m_wta" uint8         1 where some candidate is valid
+ *  "o_r"   int16         right-reference WTA disparity (indexed by xr)
+ *  "m_r"   uint8
+ *  "zbest" double        exact ZNCC at o_wta      "zm", "zp" double: at o_wta -+ 1 (NaN if none)
+ *  "delta" float         parabola offset
+ *  "m_lr"  uint8         mask after the left-right check
+ *  "o_post" int16, "m_post" uint8   disparity and mask after outlier removal/fills
+ * ST_EINVAL for an unknown name or when no debug run is held.
+ */
+st_status stereo_debug_get(st_handle h, const char *name, void **dev_ptr);
+
+/* ---- single stages, for stage-wise checks; all arrays H x W, dense ---- */
+
+/* Window statistics (Section II-A): S = sum I, SS = sum I^2 over the window
+ * of every pixel whose window lies inside the image (0 elsewhere), and
+ * inv = 1/sqrt(win^2*SS - S^2) computed in FP64 (NaN where the window leaves
+ * the image or has zero variance). */
+st_status st_window_stats(st_handle h, const uint8_t *img, int H, int W, int pitch, int win,
+                          int32_t *S, int32_t *SS, float *inv, void *stream);
+
+/* ZNCC matching and winner-take-all in both references (Section II-A).
+ *  oL, mL : argmax_d z(x, y, d) and 1 if any candidate is valid
+ *  oR, mR : for right pixel xr, argmax_d z(xr + d, y, d)
+ * Candidates whose windows leave the image or have zero variance are
+ * invalid; ties within 2^-18 of each other may resolve to either.
+ * precision selects FP32 or FP16/BF16 image and cost storage. */
+st_status st_match_wta(st_handle h, const uint8_t *left, const uint8_t *right, int H, int W,
+                       int pitch, int dmin, int dmax, int win, int precision, int16_t *oL,
+                       uint8_t *mL, int16_t *oR, uint8_t *mR, void *stream);
+
+/* Exact ZNCC at oL-1, oL, oL+1 (int32 sums, FP64 normalisation) and the
+ * parabola offset delta; zm/zp NaN where the neighbour is not a valid
+ * candidate.  Any of zbest/zm/zp may be NULL. */
+st_status st_subpixel(st_handle h, const uint8_t *left, const uint8_t *right, int H, int W,
+                      int pitch, int dmin, int dmax, int win, const int16_t *oL,
+                      const uint8_t *mL, double *zbest, double *zm, double *zp, float *delta,
+                      void *stream);
+
+/* Left-right check: mask_out = mL && |oL(x) - oR(x - oL(x))| <= tol. */
+st_status st_lr_check(st_handle h, const int16_t *oL, const uint8_t *mL, const int16_t *oR,
+                      const uint8_t *mR, int H, int W, int tol, uint8_t *mask_out, void *stream);
+
+/* Radial outlier removal with radius r (Section II-B); mask codes of kept
+ * pixels are preserved.  m_out must not alias m_in. */
+st_status st_radial_outlier(st_handle h, const int16_t *o, const uint8_t *m_in, int H, int W,
+                            int r, float thresh, uint8_t *m_out, void *stream);
+
+/* Hole filling (Section II-B): radial then disk; filled pixels get code 2.
+ * o_out/m_out must not alias the inputs. */
+st_status st_fill(st_handle h, const int16_t *o_in, const uint8_t *m_in, int H, int W,
+                  int radial_r, int min_lines, int disk_r, float min_frac, int16_t *o_out,
+                  uint8_t *m_out, void *stream);
+
+/* Improved Laplacian smoothing (Section II-C, Eqs. 1-3) of s over pixels
+ * with m != 0 and a (2R+1)^2 window, K iterations, computed in FP64;
+ * out is NaN where m == 0. */
+st_status st_hc_smooth(st_handle h, const float *s, const uint8_t *m, int H, int W, int R, int K,
+                       float alpha, float *out, void *stream);
+
+/* ---- tuning ---- */
+
+/* Time the matcher's tile variants (band height, disparities per lane) for
+ * one problem shape on the handle's device and remember the fastest for
+ * that (win, disparity-count bucket, width bucket, precision).  The table
+ * is saved to / loaded from the JSON file named by the environment variable
+ * STEREO_TUNE_CACHE when it is set.  *best_cfg (host, may be NULL) receives
+ * the chosen variant id. */
+st_status st_autotune(st_handle h, int H, int W, int dmin, int dmax, int win, int precision,
+                      int *best_cfg, void *stream);
+
+/* Force a matcher variant for later calls on this handle (-1 = automatic).
+ * Variant ids are 0..st_num_variants()-1. */
+st_status st_set_variant(st_handle h, int variant);
+int st_num_variants(void);
+/* Host string describing variant v ("DC=16,TY=8"), "" if out of range. */
+const char *st_variant_name(int v);
+
+/* Build information (host string). */
+const char *st_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STEREO_MI355X_H */

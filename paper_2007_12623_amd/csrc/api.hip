@@ -1,0 +1,1068 @@
+// C ABI of the stereo library (declared in include/stereo.h): argument
+// checks, handle and scratch management, orchestration of the stages of the
+// paper's Section II pipeline, the batched persistent launch with graph
+// replay, the matcher autotuner and the refinement entry points.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "stereo.h"
+
+using namespace st;
+
+// ---------------------------------------------------------------- errors
+static thread_local std::string g_err;
+
+static st_status fail(st_status s, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+#define ARG(cond, ...)                          \
+  do {                                          \
+    if (!(cond)) return fail(ST_EINVAL, __VA_ARGS__); \
+  } while (0)
+
+#define HIPCK(call)                                                                       \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess) {                                                               \
+      if (h) h->keys_dirty = true;                                                        \
+      return fail(ST_EHIP, "%s failed: %s", #call, hipGetErrorString(e_));                \
+    }                                                                                     \
+  } while (0)
+
+// ---------------------------------------------------------------- variants
+struct Variant {
+  int DC, TY;
+};
+static const Variant kVariants[] = {{16, 4}, {16, 8}, {16, 16}, {16, 32},
+                                    {8, 4},  {8, 8},  {8, 16},  {8, 32}};
+static const int kNumVariants = (int)(sizeof kVariants / sizeof kVariants[0]);
+
+// ---------------------------------------------------------------- handle
+struct DevBuf {
+  void *p = nullptr;
+  size_t n = 0;
+};
+
+struct BatchCache {
+  std::vector<st_pair> pairs;
+  st_params params{};
+  int variant = -2;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  DevBuf ws, keys, tables;
+};
+
+struct st_handle_s {
+  int device = 0;
+  int ncu = 256;
+  hipStream_t cap_stream = nullptr;
+  DevBuf ws, keys, rws;
+  bool keys_dirty = false;
+  int variant = -1;
+  std::map<std::string, int> tune;
+  std::map<std::string, void *> dbg;
+  BatchCache batch;
+};
+
+static bool fault_alloc() {
+  const char *e = getenv("STEREO_FAULT");
+  return e && strcmp(e, "alloc") == 0;
+}
+
+// Grow a device buffer to at least `need` bytes (contents are not kept).
+static st_status grow(st_handle h, DevBuf &b, size_t need, bool zero) {
+  if (b.n >= need && b.p) return ST_OK;
+  if (fault_alloc()) return fail(ST_ENOMEM, "device allocation of %zu bytes failed (injected)", need);
+  if (b.p) {
+    hipDeviceSynchronize();
+    hipFree(b.p);
+    b.p = nullptr;
+    b.n = 0;
+  }
+  void *p = nullptr;
+  if (hipMalloc(&p, need) != hipSuccess || !p) {
+    hipGetLastError();
+    return fail(ST_ENOMEM, "device allocation of %zu bytes failed", need);
+  }
+  if (zero && hipMemset(p, 0, need) != hipSuccess) {
+    hipFree(p);
+    return fail(ST_EHIP, "hipMemset of scratch failed");
+  }
+  b.p = p;
+  b.n = need;
+  (void)h;
+  return ST_OK;
+}
+
+static void release(DevBuf &b) {
+  if (b.p) hipFree(b.p);
+  b.p = nullptr;
+  b.n = 0;
+}
+
+// ---------------------------------------------------------------- checks
+static st_status check_shape(int H, int W, int pitch, int dmin, int dmax, int win) {
+  ARG(win >= 3 && win <= 15 && (win & 1), "win must be odd and in [3, 15] (got %d)", win);
+  ARG(dmax >= dmin, "dmax < dmin (%d < %d)", dmax, dmin);
+  ARG(dmax - dmin + 1 >= 8 && dmax - dmin + 1 <= 256,
+      "dmax - dmin + 1 must be in [8, 256] (got %d)", dmax - dmin + 1);
+  ARG(dmin >= -4096 && dmax <= 4096, "disparities beyond +-4096 are not supported");
+  ARG(H >= win && W >= win, "image %dx%d smaller than the window %d", W, H, win);
+  ARG((long long)H * W <= (1LL << 28), "image too large");
+  ARG(pitch >= W, "pitch %d < width %d", pitch, W);
+  return ST_OK;
+}
+
+static st_status check_params(const st_params *p) {
+  ARG(p, "params is NULL");
+  ARG(p->struct_size == (int32_t)sizeof(st_params), "params.struct_size %d != %d", p->struct_size,
+      (int)sizeof(st_params));
+  ARG(p->precision >= 0 && p->precision <= 2, "unknown precision %d", p->precision);
+  ARG(p->lr_tol >= 0, "lr_tol < 0");
+  ARG(p->radial_iters >= 0 && p->radial_iters <= 64, "radial_iters out of range");
+  ARG(p->radial_r0 >= 1 && p->radial_dr >= 0 && p->radial_r0 + 64 * p->radial_dr <= 4096,
+      "radial radii out of range");
+  ARG(p->fill_radial_r >= 0 && p->fill_radial_r <= 4096, "fill_radial_r out of range");
+  ARG(p->fill_min_lines >= 1 && p->fill_min_lines <= 4, "fill_min_lines must be in [1, 4]");
+  ARG(p->fill_disk_r >= 0 && p->fill_disk_r <= 2048, "fill_disk_r out of range");
+  ARG(p->fill_disk_min_frac >= 0.0f && p->fill_disk_min_frac <= 1.0f, "fill_disk_min_frac not in [0,1]");
+  ARG(p->smooth_radius >= 0 && p->smooth_radius <= 2048, "smooth_radius out of range");
+  ARG(p->smooth_iters >= 0 && p->smooth_iters <= 64, "smooth_iters out of range");
+  return ST_OK;
+}
+
+// ---------------------------------------------------------------- geometry
+static int round_up(int v, int m) { return ((v + m - 1) / m) * m; }
+static int pmod(int a, int m) { return ((a % m) + m) % m; }
+
+// Spans, bands, chunks and plane padding of one pair for the matcher.
+static void make_geom(MatchPair &P, int H, int W, int win, int dmin, int dmax, int DC, int TY) {
+  const int h = win / 2, K = KC;
+  P.H = H;
+  P.W = W;
+  P.win = win;
+  P.dmin = dmin;
+  P.dmax = dmax;
+  P.DC = DC;
+  P.TY = TY;
+  // lane columns x0 = xs + 8 l with xs = dmin - 1 (mod 8): the right-image
+  // segment of every lane then starts on a 4-column boundary, except in a
+  // last chunk that had to be shifted down to end at dmax
+  const int target = h - K, r = pmod(dmin - 1, 8);
+  P.xs0 = target - pmod(target - r, 8);
+  const int span = OUT_LANES * K;
+  P.nspan = std::max(1, ceil_div(W - h - (P.xs0 + K), span));
+  P.nband = ceil_div(H - 2 * h, TY);
+  const int D = dmax - dmin + 1;
+  P.nchunk = ceil_div(D, DC);
+  const int xs_last = P.xs0 + (P.nspan - 1) * span;
+  const int Lmax = xs_last + WV * K;
+  P.padL = P.xs0 < 0 ? -P.xs0 : pmod(-P.xs0, 8);
+  P.strideL = round_up(P.padL + std::max(W, Lmax), 16);
+  const int d0_last = dmin + std::min((P.nchunk - 1) * DC, D - DC);
+  const int Rmin = P.xs0 - d0_last - (DC - 1);
+  const int Rmax = xs_last + WV * K - dmin + 8;  // dword-rounded segment reads
+  P.padR = round_up(std::max(0, -Rmin), 4);
+  P.strideR = round_up(P.padR + std::max(W, Rmax), 16);
+  P.first_task = 0;
+}
+
+static int pick_variant(st_handle h, int H, int W, int win, int dmin, int dmax, int prec);
+
+// ---------------------------------------------------------------- scratch layout
+struct Carve {
+  size_t off = 0;
+  size_t take(size_t bytes) {
+    off = (off + 255) & ~(size_t)255;
+    const size_t o = off;
+    off += bytes;
+    return o;
+  }
+};
+
+// Offsets of every per-pair buffer inside one scratch region.
+struct PairLayout {
+  size_t Lp, NLp, Rp, negSL, invL, SRp, invR, SL, SSL, SR, SSR, oR, mR, ob[3], mb[3], zbest,
+      zm, zp, delta, pc, ps, f, dbg_mlr, dbg_o, dbg_m;
+  size_t total;
+};
+
+static PairLayout layout(const MatchPair &P, int prec, bool debug) {
+  PairLayout Lo{};
+  Carve c;
+  const size_t N = (size_t)P.H * P.W;
+  const size_t nl = (size_t)P.strideL * P.H, nr = (size_t)P.strideR * P.H;
+  const int RB = prec == P_I16 ? 1 : 2;
+  Lo.Lp = c.take(2 * nl);
+  Lo.NLp = c.take(2 * nl);
+  Lo.Rp = c.take(RB * nr + 64);
+  Lo.negSL = c.take(4 * nl);
+  Lo.invL = c.take(4 * nl);
+  Lo.SRp = c.take(4 * nr);
+  Lo.invR = c.take(4 * nr);
+  Lo.SL = c.take(4 * N);
+  Lo.SSL = c.take(4 * N);
+  Lo.SR = c.take(4 * N);
+  Lo.SSR = c.take(4 * N);
+  Lo.oR = c.take(2 * N);
+  Lo.mR = c.take(N);
+  for (int i = 0; i < 3; ++i) {
+    Lo.ob[i] = c.take(2 * N);
+    Lo.mb[i] = c.take(N);
+  }
+  Lo.zbest = c.take(8 * N);
+  Lo.zm = c.take(8 * N);
+  Lo.zp = c.take(8 * N);
+  Lo.delta = c.take(4 * N);
+  Lo.pc = c.take(4 * (size_t)P.H * (P.W + 1));
+  Lo.ps = c.take(4 * (size_t)P.H * (P.W + 1));
+  Lo.f = c.take(6 * 8 * N);
+  if (debug) {
+    Lo.dbg_mlr = c.take(N);
+    Lo.dbg_o = c.take(2 * N);
+    Lo.dbg_m = c.take(N);
+  }
+  Lo.total = c.take(0);
+  return Lo;
+}
+
+template <class T>
+static T *at(void *base, size_t off) {
+  return (T *)((char *)base + off);
+}
+
+static void fill_views(const PairLayout &Lo, void *base, uint32_t *keys, MatchPair &M, PrepPair &Pp,
+                       PostPair &Q, const uint8_t *left, const uint8_t *right, int pitch) {
+  const size_t N = (size_t)M.H * M.W;
+  M.Lp = at<void>(base, Lo.Lp);
+  M.NLp = at<void>(base, Lo.NLp);
+  M.Rp = at<void>(base, Lo.Rp);
+  M.negSL = at<int32_t>(base, Lo.negSL);
+  M.invL = at<float>(base, Lo.invL);
+  M.SR = at<int32_t>(base, Lo.SRp);
+  M.invR = at<float>(base, Lo.invR);
+  M.keyL = keys;
+  M.keyR = keys + N;
+
+  Pp = PrepPair{};
+  Pp.L = left;
+  Pp.R = right;
+  Pp.H = M.H;
+  Pp.W = M.W;
+  Pp.pitch = pitch;
+  Pp.win = M.win;
+  Pp.Lp = at<void>(base, Lo.Lp);
+  Pp.NLp = at<void>(base, Lo.NLp);
+  Pp.Rp = at<void>(base, Lo.Rp);
+  Pp.negSL = at<int32_t>(base, Lo.negSL);
+  Pp.invL = at<float>(base, Lo.invL);
+  Pp.SRp = at<int32_t>(base, Lo.SRp);
+  Pp.invR = at<float>(base, Lo.invR);
+  Pp.strideL = M.strideL;
+  Pp.padL = M.padL;
+  Pp.strideR = M.strideR;
+  Pp.padR = M.padR;
+  Pp.SL = at<int32_t>(base, Lo.SL);
+  Pp.SSL = at<int32_t>(base, Lo.SSL);
+  Pp.SR = at<int32_t>(base, Lo.SR);
+  Pp.SSR = at<int32_t>(base, Lo.SSR);
+
+  Q = PostPair{};
+  Q.left = left;
+  Q.right = right;
+  Q.H = M.H;
+  Q.W = M.W;
+  Q.pitch = pitch;
+  Q.win = M.win;
+  Q.dmin = M.dmin;
+  Q.dmax = M.dmax;
+  Q.SL = Pp.SL;
+  Q.SSL = Pp.SSL;
+  Q.SR = Pp.SR;
+  Q.SSR = Pp.SSR;
+  Q.keyL = keys;
+  Q.keyR = keys + N;
+  Q.oR = at<int16_t>(base, Lo.oR);
+  Q.mR = at<uint8_t>(base, Lo.mR);
+  for (int i = 0; i < 3; ++i) {
+    Q.ob[i] = at<int16_t>(base, Lo.ob[i]);
+    Q.mb[i] = at<uint8_t>(base, Lo.mb[i]);
+  }
+  Q.zbest = at<double>(base, Lo.zbest);
+  Q.zm = at<double>(base, Lo.zm);
+  Q.zp = at<double>(base, Lo.zp);
+  Q.delta = at<float>(base, Lo.delta);
+  Q.pc = at<int32_t>(base, Lo.pc);
+  Q.ps = at<int32_t>(base, Lo.ps);
+  Q.f = at<double>(base, Lo.f);
+}
+
+// ---------------------------------------------------------------- pipeline
+// Where the single-pair path copies intermediates for stereo_debug_get.
+struct DebugSink {
+  void *mlr, *o, *m;
+  size_t N;
+};
+
+// Every stage after the matcher, identical for the single and the batched
+// path: decode, sub-pixel, left-right check, outlier removal / hole filling
+// (ping-pong buffers 1 and 2; buffer 0 keeps the WTA result), smoothing.
+static hipError_t post_stages(const PostLaunch &L, const st_params &p, const DebugSink *dbg) {
+  hipError_t e = hipSuccess;
+  auto ck = [&](hipError_t x) {
+    if (x != hipSuccess && e == hipSuccess) e = x;
+  };
+  ck(post_decode(L));
+  if (p.subpixel) ck(post_subpixel(L));
+  int cur = 0;
+  if (p.lr_check) {
+    ck(post_lr(L, p.lr_tol, 1));
+    cur = 1;
+  }
+  if (dbg) ck(hipMemcpyAsync(dbg->mlr, L.one.mb[cur], dbg->N, hipMemcpyDeviceToDevice, L.s));
+  if (p.radial_iters <= 0) {
+    const int tmp = cur == 1 ? 2 : 1, dst = cur == 0 ? 2 : cur;
+    ck(post_fill(L, p.fill_radial_r, p.fill_min_lines, p.fill_disk_r, p.fill_disk_min_frac, cur,
+                 tmp, dst));
+    cur = dst;
+  } else {
+    for (int it = 0; it < p.radial_iters; ++it) {
+      const int r = p.radial_r0 + it * p.radial_dr;
+      const int nxt = cur == 1 ? 2 : 1;
+      ck(post_outlier(L, r, p.radial_thresh, cur, nxt));
+      const int tmp = nxt == 1 ? 2 : 1;
+      ck(post_fill(L, p.fill_radial_r, p.fill_min_lines, p.fill_disk_r, p.fill_disk_min_frac, nxt,
+                   tmp, nxt));
+      cur = nxt;
+    }
+  }
+  if (dbg) {
+    ck(hipMemcpyAsync(dbg->o, L.one.ob[cur], 2 * dbg->N, hipMemcpyDeviceToDevice, L.s));
+    ck(hipMemcpyAsync(dbg->m, L.one.mb[cur], dbg->N, hipMemcpyDeviceToDevice, L.s));
+  }
+  ck(post_hc(L, cur, p.smooth_radius, p.smooth_iters, p.smooth_alpha, p.subpixel));
+  return e;
+}
+
+static int variant_DC(int v) { return kVariants[v].DC; }
+static int variant_TY(int v) { return kVariants[v].TY; }
+
+extern "C" {
+
+void st_default_params(st_params *p) {
+  if (!p) return;
+  memset(p, 0, sizeof *p);
+  p->struct_size = sizeof(st_params);
+  p->subpixel = 1;
+  p->lr_check = 1;
+  p->lr_tol = 1;
+  p->radial_iters = 3;
+  p->radial_r0 = 10;
+  p->radial_dr = 10;
+  p->radial_thresh = 2.5f;
+  p->fill_radial_r = 50;
+  p->fill_min_lines = 2;
+  p->fill_disk_r = 20;
+  p->fill_disk_min_frac = 0.25f;
+  p->smooth_radius = 15;
+  p->smooth_iters = 3;
+  p->smooth_alpha = 0.1f;
+  p->precision = ST_FP32;
+  p->debug_outputs = 0;
+}
+
+const char *st_last_error(void) { return g_err.c_str(); }
+
+const char *st_version(void) { return "stereo_mi355x 1.0 (gfx950, HIP)"; }
+
+int st_num_variants(void) { return kNumVariants; }
+
+const char *st_variant_name(int v) {
+  static thread_local char buf[64];
+  if (v < 0 || v >= kNumVariants) return "";
+  snprintf(buf, sizeof buf, "DC=%d,TY=%d", kVariants[v].DC, kVariants[v].TY);
+  return buf;
+}
+
+static void load_tune(st_handle h);
+
+st_status st_create(st_handle *out, int device) {
+  ARG(out, "out is NULL");
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) {
+    hipGetLastError();
+    return fail(ST_ENODEV, "no HIP device");
+  }
+  ARG(device >= 0, "device < 0");
+  if (device >= n) return fail(ST_ENODEV, "device %d does not exist (%d devices)", device, n);
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess)
+    return fail(ST_ENODEV, "cannot query device %d", device);
+  if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(ST_ENODEV, "device %d is %s, this library is built for gfx950", device,
+                prop.gcnArchName);
+  st_handle h = new st_handle_s();
+  h->device = device;
+  h->ncu = prop.multiProcessorCount;
+  hipSetDevice(device);
+  if (hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+    delete h;
+    return fail(ST_EHIP, "cannot create the capture stream");
+  }
+  load_tune(h);
+  *out = h;
+  return ST_OK;
+}
+
+static void drop_batch(BatchCache &b) {
+  if (b.exec) hipGraphExecDestroy(b.exec);
+  if (b.graph) hipGraphDestroy(b.graph);
+  b.exec = nullptr;
+  b.graph = nullptr;
+  b.pairs.clear();
+  b.variant = -2;
+}
+
+void st_destroy(st_handle h) {
+  if (!h) return;
+  hipSetDevice(h->device);
+  hipDeviceSynchronize();
+  drop_batch(h->batch);
+  release(h->batch.ws);
+  release(h->batch.keys);
+  release(h->batch.tables);
+  release(h->ws);
+  release(h->keys);
+  release(h->rws);
+  if (h->cap_stream) hipStreamDestroy(h->cap_stream);
+  delete h;
+}
+
+// Prepare scratch for one pair and fill the device views.
+static st_status setup_single(st_handle h, const uint8_t *left, const uint8_t *right, int H, int W,
+                              int pitch, int dmin, int dmax, int win, int prec, int variant,
+                              bool debug, MatchPair &M, PrepPair &Pp, PostPair &Q, PairLayout &Lo,
+                              hipStream_t s) {
+  make_geom(M, H, W, win, dmin, dmax, variant_DC(variant), variant_TY(variant));
+  Lo = layout(M, prec, debug);
+  st_status rc = grow(h, h->ws, Lo.total, false);
+  if (rc) return rc;
+  const size_t N = (size_t)H * W;
+  if (h->keys.n < 8 * N) {
+    rc = grow(h, h->keys, 8 * N, true);
+    if (rc) return rc;
+    h->keys_dirty = false;
+  }
+  if (h->keys_dirty) {
+    HIPCK(launch_fill_u32((uint32_t *)h->keys.p, (int)(2 * N), 0u, s));
+    h->keys_dirty = false;
+  }
+  fill_views(Lo, h->ws.p, (uint32_t *)h->keys.p, M, Pp, Q, left, right, pitch);
+  return ST_OK;
+}
+
+static st_status run_front(st_handle h, const MatchPair &M, const PrepPair &Pp, int prec,
+                           hipStream_t s) {
+  HIPCK(launch_prep(Pp, nullptr, 1, M.H, std::max(M.strideL, M.strideR), M.W, prec, s));
+  HIPCK(launch_match(M, prec, s));
+  return ST_OK;
+}
+
+static PostLaunch single_launch(const PostPair &Q, hipStream_t s) {
+  PostLaunch L;
+  L.one = Q;
+  L.many = nullptr;
+  L.npairs = 1;
+  L.maxH = Q.H;
+  L.maxW = Q.W;
+  L.s = s;
+  return L;
+}
+
+st_status stereo_match(st_handle h, const uint8_t *left, const uint8_t *right, int H, int W,
+                       int pitch, int dmin, int dmax, int win, const st_params *params,
+                       float *disparity, uint8_t *valid_mask, void *stream) {
+  st_status rc = check_shape(H, W, pitch, dmin, dmax, win);
+  if (rc) return rc;
+  rc = check_params(params);
+  if (rc) return rc;
+  ARG(left && right && disparity && valid_mask, "NULL image or output pointer");
+  ARG(h, "NULL handle");
+  hipSetDevice(h->device);
+  hipStream_t s = (hipStream_t)stream;
+  const int prec = params->precision;
+  const bool debug = params->debug_outputs != 0;
+  const int v = pick_variant(h, H, W, win, dmin, dmax, prec);
+  MatchPair M;
+  PrepPair Pp;
+  PostPair Q;
+  PairLayout Lo;
+  rc = setup_single(h, left, right, H, W, pitch, dmin, dmax, win, prec, v, debug, M, Pp, Q, Lo, s);
+  if (rc) return rc;
+  h->dbg.clear();
+  rc = run_front(h, M, Pp, prec, s);
+  if (rc) return rc;
+  Q.disparity = disparity;
+  Q.valid_mask = valid_mask;
+  PostLaunch L = single_launch(Q, s);
+  DebugSink sink{at<void>(h->ws.p, Lo.dbg_mlr), at<void>(h->ws.p, Lo.dbg_o),
+                 at<void>(h->ws.p, Lo.dbg_m), (size_t)H * W};
+  HIPCK(post_stages(L, *params, debug ? &sink : nullptr));
+  if (debug) {
+    h->dbg["o_wta"] = Q.ob[0];
+    h->dbg["m_wta"] = Q.mb[0];
+    h->dbg["o_r"] = Q.oR;
+    h->dbg["m_r"] = Q.mR;
+    h->dbg["zbest"] = Q.zbest;
+    h->dbg["zm"] = Q.zm;
+    h->dbg["zp"] = Q.zp;
+    h->dbg["delta"] = Q.delta;
+    h->dbg["m_lr"] = at<void>(h->ws.p, Lo.dbg_mlr);
+    h->dbg["o_post"] = at<void>(h->ws.p, Lo.dbg_o);
+    h->dbg["m_post"] = at<void>(h->ws.p, Lo.dbg_m);
+  }
+  return ST_OK;
+}
+
+st_status stereo_debug_get(st_handle h, const char *name, void **dev_ptr) {
+  ARG(h && name && dev_ptr, "NULL argument");
+  auto it = h->dbg.find(name);
+  ARG(it != h->dbg.end(), "no debug buffer '%s' (run stereo_match with debug_outputs = 1)", name);
+  *dev_ptr = it->second;
+  return ST_OK;
+}
+
+// ---------------------------------------------------------------- single stages
+st_status st_window_stats(st_handle h, const uint8_t *img, int H, int W, int pitch, int win,
+                          int32_t *S, int32_t *SS, float *inv, void *stream) {
+  ARG(win >= 3 && win <= 15 && (win & 1), "win must be odd and in [3, 15]");
+  ARG(H >= 1 && W >= 1 && pitch >= W, "bad image shape");
+  ARG(img && S && SS && inv, "NULL pointer");
+  ARG(h, "NULL handle");
+  hipSetDevice(h->device);
+  HIPCK(launch_window_stats_dense(img, H, W, pitch, win, S, SS, inv, (hipStream_t)stream));
+  return ST_OK;
+}
+
+st_status st_match_wta(st_handle h, const uint8_t *left, const uint8_t *right, int H, int W,
+                       int pitch, int dmin, int dmax, int win, int precision, int16_t *oL,
+                       uint8_t *mL, int16_t *oR, uint8_t *mR, void *stream) {
+  st_status rc = check_shape(H, W, pitch, dmin, dmax, win);
+  if (rc) return rc;
+  ARG(precision >= 0 && precision <= 2, "unknown precision %d", precision);
+  ARG(left && right && oL && mL && oR && mR, "NULL pointer");
+  ARG(h, "NULL handle");
+  hipSetDevice(h->device);
+  hipStream_t s = (hipStream_t)stream;
+  const int v = pick_variant(h, H, W, win, dmin, dmax, precision);
+  MatchPair M;
+  PrepPair Pp;
+  PostPair Q;
+  PairLayout Lo;
+  rc = setup_single(h, left, right, H, W, pitch, dmin, dmax, win, precision, v, false, M, Pp, Q, Lo, s);
+  if (rc) return rc;
+  rc = run_front(h, M, Pp, precision, s);
+  if (rc) return rc;
+  Q.ob[0] = oL;
+  Q.mb[0] = mL;
+  Q.oR = oR;
+  Q.mR = mR;
+  HIPCK(post_decode(single_launch(Q, s)));
+  return ST_OK;
+}
+
+st_status st_subpixel(st_handle h, const uint8_t *left, const uint8_t *right, int H, int W,
+                      int pitch, int dmin, int dmax, int win, const int16_t *oL,
+                      const uint8_t *mL, double *zbest, double *zm, double *zp, float *delta,
+                      void *stream) {
+  st_status rc = check_shape(H, W, pitch, dmin, dmax, win);
+  if (rc) return rc;
+  ARG(left && right && oL && mL && delta, "NULL pointer");
+  ARG(h, "NULL handle");
+  hipSetDevice(h->device);
+  hipStream_t s = (hipStream_t)stream;
+  const size_t N = (size_t)H * W;
+  HIPCK(grow(h, h->ws, 16 * N + 1024, false) == ST_OK ? hipSuccess : hipErrorOutOfMemory);
+  PostPair Q{};
+  Q.left = left;
+  Q.right = right;
+  Q.H = H;
+  Q.W = W;
+  Q.pitch = pitch;
+  Q.win = win;
+  Q.dmin = dmin;
+  Q.dmax = dmax;
+  int32_t *base = (int32_t *)h->ws.p;
+  Q.SL = base;
+  Q.SSL = base + N;
+  Q.SR = base + 2 * N;
+  Q.SSR = base + 3 * N;
+  HIPCK(launch_window_stats_dense(left, H, W, pitch, win, base, base + N, nullptr, s));
+  HIPCK(launch_window_stats_dense(right, H, W, pitch, win, base + 2 * N, base + 3 * N, nullptr, s));
+  Q.ob[0] = const_cast<int16_t *>(oL);
+  Q.mb[0] = const_cast<uint8_t *>(mL);
+  Q.zbest = zbest;
+  Q.zm = zm;
+  Q.zp = zp;
+  Q.delta = delta;
+  HIPCK(post_subpixel(single_launch(Q, s)));
+  return ST_OK;
+}
+
+st_status st_lr_check(st_handle h, const int16_t *oL, const uint8_t *mL, const int16_t *oR,
+                      const uint8_t *mR, int H, int W, int tol, uint8_t *mask_out, void *stream) {
+  ARG(H >= 1 && W >= 1 && tol >= 0, "bad shape or tolerance");
+  ARG(oL && mL && oR && mR && mask_out, "NULL pointer");
+  ARG(h, "NULL handle");
+  hipSetDevice(h->device);
+  const size_t N = (size_t)H * W;
+  HIPCK(grow(h, h->ws, 2 * N + 256, false) == ST_OK ? hipSuccess : hipErrorOutOfMemory);
+  PostPair Q{};
+  Q.H = H;
+  Q.W = W;
+  Q.ob[0] = const_cast<int16_t *>(oL);
+  Q.mb[0] = const_cast<uint8_t *>(mL);
+  Q.oR = const_cast<int16_t *>(oR);
+  Q.mR = const_cast<uint8_t *>(mR);
+  Q.ob[1] = (int16_t *)h->ws.p;
+  Q.mb[1] = mask_out;
+  HIPCK(post_lr(single_launch(Q, (hipStream_t)stream), tol, 1));
+  return ST_OK;
+}
+
+st_status st_radial_outlier(st_handle h, const int16_t *o, const uint8_t *m_in, int H, int W,
+                            int r, float thresh, uint8_t *m_out, void *stream) {
+  ARG(H >= 1 && W >= 1 && r >= 1 && r <= 4096, "bad shape or radius");
+  ARG(o && m_in && m_out, "NULL pointer");
+  ARG(m_out != m_in, "m_out aliases m_in");
+  ARG(h, "NULL handle");
+  hipSetDevice(h->device);
+  const size_t N = (size_t)H * W;
+  HIPCK(grow(h, h->ws, 2 * N + 256, false) == ST_OK ? hipSuccess : hipErrorOutOfMemory);
+  PostPair Q{};
+  Q.H = H;
+  Q.W = W;
+  Q.ob[1] = const_cast<int16_t *>(o);
+  Q.mb[1] = const_cast<uint8_t *>(m_in);
+  Q.ob[2] = (int16_t *)h->ws.p;
+  Q.mb[2] = m_out;
+  HIPCK(post_outlier(single_launch(Q, (hipStream_t)stream), r, thresh, 1, 2));
+  return ST_OK;
+}
+
+st_status st_fill(st_handle h, const int16_t *o_in, const uint8_t *m_in, int H, int W,
+                  int radial_r, int min_lines, int disk_r, float min_frac, int16_t *o_out,
+                  uint8_t *m_out, void *stream) {
+  ARG(H >= 1 && W >= 1 && radial_r >= 0 && disk_r >= 0 && min_lines >= 1 && min_lines <= 4,
+      "bad shape or fill parameters");
+  ARG(min_frac >= 0.0f && min_frac <= 1.0f, "min_frac not in [0, 1]");
+  ARG(o_in && m_in && o_out && m_out, "NULL pointer");
+  ARG((const void *)o_out != (const void *)o_in && (const void *)m_out != (const void *)m_in,
+      "outputs alias inputs");
+  ARG(h, "NULL handle");
+  hipSetDevice(h->device);
+  const size_t N = (size_t)H * W;
+  Carve c;
+  const size_t ot = c.take(2 * N), mt = c.take(N), pc = c.take(4 * (size_t)H * (W + 1)),
+               ps = c.take(4 * (size_t)H * (W + 1)), tot = c.take(0);
+  HIPCK(grow(h, h->ws, tot, false) == ST_OK ? hipSuccess : hipErrorOutOfMemory);
+  PostPair Q{};
+  Q.H = H;
+  Q.W = W;
+  Q.ob[0] = const_cast<int16_t *>(o_in);
+  Q.mb[0] = const_cast<uint8_t *>(m_in);
+  Q.ob[1] = at<int16_t>(h->ws.p, ot);
+  Q.mb[1] = at<uint8_t>(h->ws.p, mt);
+  Q.ob[2] = o_out;
+  Q.mb[2] = m_out;
+  Q.pc = at<int32_t>(h->ws.p, pc);
+  Q.ps = at<int32_t>(h->ws.p, ps);
+  HIPCK(post_fill(single_launch(Q, (hipStream_t)stream), radial_r, min_lines, disk_r, min_frac, 0, 1, 2));
+  return ST_OK;
+}
+
+st_status st_hc_smooth(st_handle h, const float *s_in, const uint8_t *m, int H, int W, int R,
+                       int K, float alpha, float *out, void *stream) {
+  ARG(H >= 1 && W >= 1 && R >= 0 && R <= 2048 && K >= 0 && K <= 64, "bad shape or parameters");
+  ARG(s_in && m && out, "NULL pointer");
+  ARG(h, "NULL handle");
+  hipSetDevice(h->device);
+  const size_t N = (size_t)H * W;
+  HIPCK(grow(h, h->ws, 6 * 8 * N + 256, false) == ST_OK ? hipSuccess : hipErrorOutOfMemory);
+  PostPair Q{};
+  Q.H = H;
+  Q.W = W;
+  Q.mb[0] = const_cast<uint8_t *>(m);
+  Q.s_in = s_in;
+  Q.f = (double *)h->ws.p;
+  Q.disparity = out;
+  Q.valid_mask = nullptr;
+  HIPCK(post_hc(single_launch(Q, (hipStream_t)stream), 0, R, K, alpha, 0));
+  return ST_OK;
+}
+
+// ---------------------------------------------------------------- batched
+st_status stereo_match_batched(st_handle h, const st_pair *pairs, int n_pairs,
+                               const st_params *params, void *stream) {
+  ARG(pairs && n_pairs >= 1 && n_pairs <= 65535, "bad pair list");
+  st_status rc = check_params(params);
+  if (rc) return rc;
+  for (int i = 0; i < n_pairs; ++i) {
+    const st_pair &q = pairs[i];
+    rc = check_shape(q.H, q.W, q.pitch, q.dmin, q.dmax, q.win);
+    if (rc) return fail(ST_EINVAL, "pair %d: %s", i, g_err.c_str());
+    ARG(q.left && q.right && q.disparity && q.valid_mask, "pair %d: NULL pointer", i);
+  }
+  ARG(h, "NULL handle");
+  hipSetDevice(h->device);
+  hipStream_t s = (hipStream_t)stream;
+  const int prec = params->precision;
+  BatchCache &B = h->batch;
+  const int vforce = h->variant;
+  bool same = B.exec && (int)B.pairs.size() == n_pairs && B.variant == vforce &&
+              memcmp(&B.params, params, sizeof(st_params)) == 0 &&
+              memcmp(B.pairs.data(), pairs, sizeof(st_pair) * n_pairs) == 0;
+  if (same) {
+    HIPCK(hipGraphLaunch(B.exec, s));
+    return ST_OK;
+  }
+  drop_batch(B);
+  // one disparity chunk size for the whole launch, band height per pair
+  int minD = 256;
+  for (int i = 0; i < n_pairs; ++i) minD = std::min(minD, pairs[i].dmax - pairs[i].dmin + 1);
+  int DC = minD >= 16 ? 16 : 8;
+  if (vforce >= 0) DC = std::min(DC, variant_DC(vforce));
+  std::vector<MatchPair> M(n_pairs);
+  std::vector<PrepPair> Pp(n_pairs);
+  std::vector<PostPair> Q(n_pairs);
+  std::vector<PairLayout> Lo(n_pairs);
+  std::vector<size_t> base(n_pairs), kbase(n_pairs);
+  size_t total = 0, ktotal = 0;
+  int maxH = 0, maxW = 0, maxCols = 0;
+  for (int i = 0; i < n_pairs; ++i) {
+    const st_pair &q = pairs[i];
+    int TY = vforce >= 0 ? variant_TY(vforce) : 32;
+    if (vforce < 0) {
+      auto it = h->tune.find("batched");
+      if (it != h->tune.end()) TY = variant_TY(it->second);
+    }
+    make_geom(M[i], q.H, q.W, q.win, q.dmin, q.dmax, DC, TY);
+    Lo[i] = layout(M[i], prec, false);
+    total = (total + 255) & ~(size_t)255;
+    base[i] = total;
+    total += Lo[i].total;
+    kbase[i] = ktotal;
+    ktotal += 2 * (size_t)q.H * q.W;
+    maxH = std::max(maxH, q.H);
+    maxW = std::max(maxW, q.W);
+    maxCols = std::max(maxCols, std::max(M[i].strideL, M[i].strideR));
+  }
+  rc = grow(h, B.ws, total, false);
+  if (rc) return rc;
+  rc = grow(h, B.keys, 4 * ktotal, true);
+  if (rc) return rc;
+  // task queue: (pair, group, chunk), longest first (rows in the band)
+  std::vector<int4> tasks;
+  std::vector<int> cost;
+  for (int i = 0; i < n_pairs; ++i) {
+    const MatchPair &P = M[i];
+    const int hh = P.win / 2;
+    for (int g = 0; g < P.nband * P.nspan; ++g) {
+      const int band = g / P.nspan;
+      const int rows = std::min(P.TY, P.H - hh - (hh + band * P.TY));
+      for (int c = 0; c < P.nchunk; ++c) {
+        tasks.push_back(make_int4(i, g, c, 0));
+        cost.push_back(rows + hh + 1);
+      }
+    }
+  }
+  std::vector<int> order(tasks.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+  std::vector<int4> sorted(tasks.size());
+  for (size_t i = 0; i < order.size(); ++i) sorted[i] = tasks[order[i]];
+  // device tables
+  Carve c;
+  const size_t tM = c.take(sizeof(MatchPair) * n_pairs), tP = c.take(sizeof(PrepPair) * n_pairs),
+               tQ = c.take(sizeof(PostPair) * n_pairs), tT = c.take(sizeof(int4) * sorted.size()),
+               tC = c.take(16), tTot = c.take(0);
+  rc = grow(h, B.tables, tTot, false);
+  if (rc) return rc;
+  for (int i = 0; i < n_pairs; ++i) {
+    fill_views(Lo[i], at<void>(B.ws.p, base[i]), (uint32_t *)B.keys.p + kbase[i], M[i], Pp[i], Q[i],
+               pairs[i].left, pairs[i].right, pairs[i].pitch);
+    Q[i].disparity = pairs[i].disparity;
+    Q[i].valid_mask = pairs[i].valid_mask;
+  }
+  HIPCK(hipMemcpy(at<void>(B.tables.p, tM), M.data(), sizeof(MatchPair) * n_pairs, hipMemcpyHostToDevice));
+  HIPCK(hipMemcpy(at<void>(B.tables.p, tP), Pp.data(), sizeof(PrepPair) * n_pairs, hipMemcpyHostToDevice));
+  HIPCK(hipMemcpy(at<void>(B.tables.p, tQ), Q.data(), sizeof(PostPair) * n_pairs, hipMemcpyHostToDevice));
+  HIPCK(hipMemcpy(at<void>(B.tables.p, tT), sorted.data(), sizeof(int4) * sorted.size(), hipMemcpyHostToDevice));
+  // resident waves of the persistent matcher
+  const int per_cu = std::max(1, match_persistent_occupancy(DC, prec));
+  const int nblocks = h->ncu * per_cu;
+  // capture the whole sequence once, replay it on later calls
+  hipStream_t cs = h->cap_stream;
+  HIPCK(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
+  hipError_t e = hipSuccess;
+  auto ck = [&](hipError_t x) { if (x != hipSuccess && e == hipSuccess) e = x; };
+  ck(launch_prep(Pp[0], at<PrepPair>(B.tables.p, tP), n_pairs, maxH, maxCols, maxW, prec, cs));
+  ck(launch_match_persistent(at<MatchPair>(B.tables.p, tM), at<int4>(B.tables.p, tT), (int)sorted.size(),
+                             at<int>(B.tables.p, tC), DC, prec, nblocks, cs));
+  PostLaunch L;
+  L.one = Q[0];
+  L.many = at<PostPair>(B.tables.p, tQ);
+  L.npairs = n_pairs;
+  L.maxH = maxH;
+  L.maxW = maxW;
+  L.s = cs;
+  ck(post_stages(L, *params, nullptr));
+  hipGraph_t g = nullptr;
+  hipError_t ee = hipStreamEndCapture(cs, &g);
+  if (e != hipSuccess || ee != hipSuccess) {
+    if (g) hipGraphDestroy(g);
+    h->keys_dirty = true;
+    return fail(ST_EHIP, "capture of the batched launch failed: %s",
+                hipGetErrorString(e != hipSuccess ? e : ee));
+  }
+  hipGraphExec_t ex = nullptr;
+  if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
+    hipGraphDestroy(g);
+    return fail(ST_EHIP, "hipGraphInstantiate failed");
+  }
+  B.graph = g;
+  B.exec = ex;
+  B.pairs.assign(pairs, pairs + n_pairs);
+  B.params = *params;
+  B.variant = vforce;
+  HIPCK(hipGraphLaunch(B.exec, s));
+  return ST_OK;
+}
+
+// ---------------------------------------------------------------- refinement
+static st_status refine_setup(st_handle h, const uint8_t *left, const uint8_t *right,
+                              const float *d, const uint8_t *mask, int H, int W, int pitch,
+                              int win, float lambda_tv, RefineArgs &A) {
+  ARG(win >= 3 && win <= 15 && (win & 1), "win must be odd and in [3, 15]");
+  ARG(H >= win && W >= win && pitch >= W && (long long)H * W <= (1LL << 26), "bad image shape");
+  ARG(left && right && d && mask, "NULL pointer");
+  ARG(lambda_tv >= 0.0f, "lambda_tv < 0");
+  ARG(h, "NULL handle");
+  hipSetDevice(h->device);
+  const size_t N = (size_t)H * W;
+  const size_t need = (size_t)refine_planes() * 8 * N + 8 * (size_t)refine_partials(H, W) + 512;
+  st_status rc = grow(h, h->rws, need, false);
+  if (rc) return rc;
+  A = RefineArgs{};
+  A.L = left;
+  A.R = right;
+  A.d = d;
+  A.mask = mask;
+  A.H = H;
+  A.W = W;
+  A.pitch = pitch;
+  A.win = win;
+  A.lambda = lambda_tv;
+  A.f = (double *)h->rws.p;
+  A.partial = A.f + (size_t)refine_planes() * N;
+  return ST_OK;
+}
+
+st_status stereo_refine_forward(st_handle h, const uint8_t *left, const uint8_t *right,
+                                const float *d, const uint8_t *mask, int H, int W, int pitch,
+                                int win, float lambda_tv, float *Z, double *E, void *stream) {
+  ARG(E, "E is NULL");
+  RefineArgs A;
+  st_status rc = refine_setup(h, left, right, d, mask, H, W, pitch, win, lambda_tv, A);
+  if (rc) return rc;
+  A.Z = Z;
+  A.E = E;
+  HIPCK(launch_refine_forward(A, (hipStream_t)stream));
+  return ST_OK;
+}
+
+st_status stereo_refine_backward(st_handle h, const uint8_t *left, const uint8_t *right,
+                                 const float *d, const uint8_t *mask, int H, int W, int pitch,
+                                 int win, float lambda_tv, float *grad_d, void *stream) {
+  ARG(grad_d, "grad_d is NULL");
+  RefineArgs A;
+  st_status rc = refine_setup(h, left, right, d, mask, H, W, pitch, win, lambda_tv, A);
+  if (rc) return rc;
+  A.grad = grad_d;
+  HIPCK(launch_refine_backward(A, (hipStream_t)stream));
+  return ST_OK;
+}
+
+st_status stereo_refine_step(st_handle h, float *d, const float *grad_d, const uint8_t *mask,
+                             int H, int W, float tau, float max_step, void *stream) {
+  ARG(d && grad_d && mask, "NULL pointer");
+  ARG(H >= 1 && W >= 1 && (long long)H * W <= (1LL << 28), "bad shape");
+  ARG(tau >= 0.0f && max_step >= 0.0f, "negative step parameters");
+  ARG(h, "NULL handle");
+  hipSetDevice(h->device);
+  HIPCK(launch_refine_step(d, grad_d, mask, H * W, tau, max_step, (hipStream_t)stream));
+  return ST_OK;
+}
+
+// ---------------------------------------------------------------- tuning
+st_status st_set_variant(st_handle h, int variant) {
+  ARG(h, "NULL handle");
+  ARG(variant >= -1 && variant < kNumVariants, "variant %d out of range", variant);
+  h->variant = variant;
+  return ST_OK;
+}
+
+}  // extern "C"
+
+static std::string tune_key(int H, int W, int win, int dmin, int dmax, int prec) {
+  (void)H;
+  const int D = dmax - dmin + 1;
+  char b[96];
+  snprintf(b, sizeof b, "w%d_D%d_W%d_p%d", win, round_up(D, 32), round_up(W, 256), prec);
+  return b;
+}
+
+// Variant used when nothing is forced: the tuned one for this shape bucket,
+// else the largest band height that still gives every SIMD two waves.
+static int pick_variant(st_handle h, int H, int W, int win, int dmin, int dmax, int prec) {
+  const int D = dmax - dmin + 1;
+  if (h->variant >= 0 && variant_DC(h->variant) <= D) return h->variant;
+  auto it = h->tune.find(tune_key(H, W, win, dmin, dmax, prec));
+  if (it != h->tune.end() && variant_DC(it->second) <= D) return it->second;
+  const int DC = D >= 16 ? 16 : 8;
+  const int tys[4] = {32, 16, 8, 4};
+  for (int i = 0; i < 4; ++i) {
+    MatchPair P;
+    make_geom(P, H, W, win, dmin, dmax, DC, tys[i]);
+    const long long waves = (long long)P.nspan * P.nband * P.nchunk;
+    if (waves >= 8LL * h->ncu || i == 3) {
+      for (int v = 0; v < kNumVariants; ++v)
+        if (kVariants[v].DC == DC && kVariants[v].TY == tys[i]) return v;
+    }
+  }
+  return 0;
+}
+
+static void save_tune(st_handle h) {
+  const char *path = getenv("STEREO_TUNE_CACHE");
+  if (!path || !*path) return;
+  std::ofstream f(path);
+  if (!f) return;
+  f << "{\n";
+  size_t i = 0;
+  for (auto &kv : h->tune) {
+    f << "  \"" << kv.first << "\": " << kv.second << (++i < h->tune.size() ? "," : "") << "\n";
+  }
+  f << "}\n";
+}
+
+// Reads the flat {"key": int, ...} object written by save_tune.
+static void load_tune(st_handle h) {
+  const char *path = getenv("STEREO_TUNE_CACHE");
+  if (!path || !*path) return;
+  std::ifstream f(path);
+  if (!f) return;
+  std::stringstream ss;
+  ss << f.rdbuf();
+  const std::string s = ss.str();
+  size_t p = 0;
+  while ((p = s.find('"', p)) != std::string::npos) {
+    const size_t q = s.find('"', p + 1);
+    if (q == std::string::npos) break;
+    const std::string key = s.substr(p + 1, q - p - 1);
+    const size_t colon = s.find(':', q);
+    if (colon == std::string::npos) break;
+    const int v = atoi(s.c_str() + colon + 1);
+    if (v >= 0 && v < kNumVariants) h->tune[key] = v;
+    p = colon + 1;
+  }
+}
+
+extern "C" st_status st_autotune(st_handle h, int H, int W, int dmin, int dmax, int win,
+                                 int precision, int *best_cfg, void *stream) {
+  st_status rc = check_shape(H, W, W, dmin, dmax, win);
+  if (rc) return rc;
+  ARG(precision >= 0 && precision <= 2, "unknown precision");
+  ARG(h, "NULL handle");
+  hipSetDevice(h->device);
+  hipStream_t s = (hipStream_t)stream;
+  // seeded test pattern: a smooth texture and its shift by a quarter range
+  const size_t N = (size_t)H * W;
+  std::vector<uint8_t> img(2 * N);
+  uint32_t st = 12345u;
+  for (size_t i = 0; i < N; ++i) {
+    st = st * 1664525u + 1013904223u;
+    img[i] = (uint8_t)(st >> 24);
+  }
+  const int shift = (dmin + dmax) / 2;
+  for (int y = 0; y < H; ++y)
+    for (int x = 0; x < W; ++x) {
+      const int xs = std::min(std::max(x + shift, 0), W - 1);
+      img[N + (size_t)y * W + x] = img[(size_t)y * W + xs];
+    }
+  uint8_t *dimg = nullptr;
+  HIPCK(hipMalloc(&dimg, 2 * N));
+  hipError_t e = hipMemcpy(dimg, img.data(), 2 * N, hipMemcpyHostToDevice);
+  if (e != hipSuccess) { hipFree(dimg); HIPCK(e); }
+  const int D = dmax - dmin + 1;
+  int best = -1;
+  double best_ms = 1e30;
+  hipEvent_t e0, e1;
+  hipEventCreate(&e0);
+  hipEventCreate(&e1);
+  for (int v = 0; v < kNumVariants; ++v) {
+    if (variant_DC(v) > D) continue;
+    MatchPair M;
+    PrepPair Pp;
+    PostPair Q;
+    PairLayout Lo;
+    rc = setup_single(h, dimg, dimg + N, H, W, W, dmin, dmax, win, precision, v, false, M, Pp, Q, Lo, s);
+    if (rc) break;
+    launch_prep(Pp, nullptr, 1, H, std::max(M.strideL, M.strideR), W, precision, s);
+    PostLaunch L = single_launch(Q, s);
+    double ms_min = 1e30;
+    for (int rep = 0; rep < 4; ++rep) {
+      hipEventRecord(e0, s);
+      launch_match(M, precision, s);
+      hipEventRecord(e1, s);
+      post_decode(L);
+      hipEventSynchronize(e1);
+      float ms = 0;
+      hipEventElapsedTime(&ms, e0, e1);
+      if (rep > 0) ms_min = std::min(ms_min, (double)ms);
+    }
+    if (ms_min < best_ms) {
+      best_ms = ms_min;
+      best = v;
+    }
+  }
+  hipStreamSynchronize(s);
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  hipFree(dimg);
+  if (rc) return rc;
+  if (best < 0) return fail(ST_EUNSUPPORTED, "no matcher variant fits this shape");
+  h->tune[tune_key(H, W, win, dmin, dmax, precision)] = best;
+  save_tune(h);
+  if (best_cfg) *best_cfg = best;
+  return ST_OK;
+}

@@ -1,0 +1,117 @@
+// Shared device/host definitions of the MI355X ZNCC stereo library.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace st {
+
+constexpr int WV = 64;        // wavefront size on gfx950
+constexpr int KC = 8;         // image columns owned by one lane of the matcher
+constexpr int OUT_LANES = 62; // lanes 1..62 of a wave produce output; 0 and 63 are halos
+
+enum Prec { P_I16 = 0, P_F16 = 1, P_BF16 = 2 };
+
+// Geometry and device pointers of one prepared pair, as the matcher sees it.
+// Planes are padded row-major arrays: image column x lives at index x + pad.
+//   L planes / L stats: stride strideL, pad padL  (padL chosen so that the
+//                       first column of every lane is 16-byte aligned)
+//   R plane  / R stats: stride strideR, pad padR  (multiple of 4)
+struct MatchPair {
+  const void *Lp;      // int16 n*(L-128) | fp16/bf16 (L-128)
+  const void *NLp;     // the negation of Lp
+  const void *Rp;      // uint8 R | fp16/bf16 R
+  const int32_t *negSL;  // 128*n - S_L (int path) or 128*n - S_L as well (fp path)
+  const float *invL;     // 1/sqrt(varN_L), NaN where the candidate set is empty
+  const int32_t *SR;     // S_R
+  const float *invR;     // 1/sqrt(varN_R), NaN where invalid
+  uint32_t *keyL;        // H*W merged left-reference keys
+  uint32_t *keyR;        // H*W merged right-reference keys
+  int32_t H, W, win, dmin, dmax;
+  int32_t strideL, padL, strideR, padR;
+  int32_t xs0;          // first column of lane 0 of span 0
+  int32_t nspan, nband, nchunk, TY, DC;
+  int32_t first_task;   // index of this pair's first task in a batched queue
+};
+
+// Dense per-pair view used by the post-processing kernels.  A batched
+// launch reads entry blockIdx.z of a device table; a single-pair launch gets
+// the descriptor by value.
+struct PostPair {
+  const uint8_t *left, *right;
+  int32_t H, W, pitch, win, dmin, dmax;
+  const int32_t *SL, *SSL, *SR, *SSR;  // dense window sums (0 outside)
+  uint32_t *keyL, *keyR;               // merged WTA keys (cleared by decode)
+  int16_t *oR;
+  uint8_t *mR;
+  int16_t *ob[3];                      // [0] WTA disparity, [1] [2] ping-pong
+  uint8_t *mb[3];                      // masks, same roles
+  double *zbest, *zm, *zp;             // may be null
+  float *delta;
+  int32_t *pc, *ps;                    // row prefix sums, H x (W+1)
+  double *f;                           // 6 smoothing planes of H x W
+  const float *s_in;                   // optional smoothing input (stage entry)
+  float *disparity;
+  uint8_t *valid_mask;
+};
+
+// Inputs and outputs of the plane/statistics preparation of one pair.
+struct PrepPair {
+  const uint8_t *L, *R;
+  int32_t H, W, pitch, win;
+  void *Lp, *NLp, *Rp;                   // padded image planes
+  int32_t *negSL, *SRp;                  // padded statistics planes
+  float *invL, *invR;
+  int32_t strideL, padL, strideR, padR;
+  int32_t *SL, *SSL, *SR, *SSR;          // dense window sums
+  float *invLd, *invRd;                  // dense inverse deviations (may be null)
+};
+
+// A pixel-parallel launch over one pair (descriptor by value) or a batch
+// (device table, grid.z = pair, grid sized for the largest pair).
+struct PostLaunch {
+  PostPair one;
+  const PostPair *many;  // null for a single pair
+  int npairs, maxH, maxW;
+  hipStream_t s;
+};
+
+struct RefineArgs {
+  const uint8_t *L, *R;
+  const float *d;
+  const uint8_t *mask;
+  int H, W, pitch, win;
+  double lambda;
+  double *f;        // planes of H*W doubles
+  double *partial;  // one double per block of the energy kernel
+  float *Z;         // may be null
+  double *E;
+  float *grad;
+};
+
+__host__ __device__ inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
+
+// ---- host launchers (one per stage); all return hipGetLastError()
+hipError_t launch_prep(const PrepPair &one, const PrepPair *many, int npairs, int maxH,
+                       int maxCols, int maxW, int prec, hipStream_t s);
+hipError_t launch_match(const MatchPair &P, int prec, hipStream_t s);
+hipError_t launch_match_persistent(const MatchPair *pairs_dev, const int4 *tasks_dev, int ntasks,
+                                   int *counter_dev, int DC, int prec, int nblocks, hipStream_t s);
+int match_persistent_occupancy(int DC, int prec);  // resident blocks per CU
+hipError_t launch_window_stats_dense(const uint8_t *img, int H, int W, int pitch, int win,
+                                     int32_t *S, int32_t *SS, float *inv, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t *p, int N, uint32_t v, hipStream_t s);
+hipError_t post_decode(const PostLaunch &L);
+hipError_t post_subpixel(const PostLaunch &L);
+hipError_t post_lr(const PostLaunch &L, int tol, int dst);
+hipError_t post_outlier(const PostLaunch &L, int r, float thresh, int src, int dst);
+hipError_t post_fill(const PostLaunch &L, int radial_r, int min_lines, int disk_r, float frac,
+                     int src, int tmp, int dst);
+hipError_t post_hc(const PostLaunch &L, int src, int R, int K, float alpha, int use_delta);
+int refine_planes();
+int refine_partials(int H, int W);
+hipError_t launch_refine_forward(const RefineArgs &A, hipStream_t s);
+hipError_t launch_refine_backward(const RefineArgs &A, hipStream_t s);
+hipError_t launch_refine_step(float *d, const float *g, const uint8_t *mask, int N, float tau,
+                              float ms, hipStream_t s);
+
+}  // namespace st

@@ -1,0 +1,574 @@
+// Dense ZNCC matching with winner-take-all in the left and right reference
+// (Section II-A of the paper: every pixel tests every candidate disparity over
+// a square window).  The paper's kernel gives one thread per pixel and
+// caches image rows in shared memory; this one is laid out for gfx950:
+//
+//  * a wave owns a span of 64*8 columns, one chunk of DC disparities and a
+//    band of rows; lane l owns columns x0 .. x0+7 (x0 = xs + 8 l);
+//  * vertical window sums V(c, d) = sum_v n(L-128)(c, y+v) * R(c-d, y+v) are
+//    running sums in registers: one v_dot2_i32_i16 adds the entering row and
+//    removes the leaving one;
+//  * horizontal window sums slide along the lane's 8 columns; the h columns
+//    on either side come from the neighbouring lanes through DPP wave shifts
+//    (so lanes 0 and 63 only serve as halos);
+//  * the ZNCC numerator n*S_LR - S_L*S_R is exact in int32 (24-bit mads);
+//    normalisation by the FP64-computed 1/sqrt(varN) happens in fp32;
+//  * the winner-take-all key is z + 2 in fp32 with the disparity index in the
+//    4 low mantissa bits, so one v_max3 updates a running argmax with two
+//    candidates; invalid candidates carry NaN, which v_max ignores;
+//  * right-reference maxima accumulate along the diagonals x - d and are
+//    merged across lanes with DPP before a global atomic max;
+//  * partial results of the disparity chunks merge through 32-bit atomic
+//    max on keys (quantised z, then 255 - (d - dmin)).
+#include "common.h"
+
+namespace st {
+
+// ---------------------------------------------------------------- helpers
+__device__ __forceinline__ int from_left(int v) {   // lane i receives lane i-1 (wave_shr:1)
+  return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xF, 0xF, true);
+}
+__device__ __forceinline__ int from_right(int v) {  // lane i receives lane i+1 (wave_shl:1)
+  return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xF, 0xF, true);
+}
+__device__ __forceinline__ float from_left(float v) {
+  return __builtin_bit_cast(float, from_left(__builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ float from_right(float v) {
+  return __builtin_bit_cast(float, from_right(__builtin_bit_cast(int, v)));
+}
+// max that ignores a quiet-NaN operand (lowers to v_max_f32 / v_max3_f32)
+__device__ __forceinline__ float kmax(float a, float b) {
+  return __builtin_amdgcn_fmed3f(a, b, __builtin_inff());
+}
+__device__ __forceinline__ int s24(int v) { return __builtin_amdgcn_sbfe(v, 0, 24); }
+
+typedef short short2v __attribute__((ext_vector_type(2)));
+typedef _Float16 half2v __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
+
+// byte selectors for v_perm_b32(S0 = hi source, S1 = lo source)
+// 16-bit halves: lo16 <- S1 half h, hi16 <- S0 half h
+__device__ __forceinline__ constexpr uint32_t sel16(int h) { return h ? 0x07060302u : 0x05040100u; }
+// 8-bit lanes zero-extended: lo16 <- S1 byte b, hi16 <- S0 byte b
+__device__ __forceinline__ constexpr uint32_t sel8(int b) {
+  return (uint32_t)b | 0x0C00u | ((uint32_t)(4 + b) << 16) | 0x0C000000u;
+}
+
+template <int PREC> struct Img;
+template <> struct Img<P_I16> {
+  using Acc = int;
+  static constexpr int RB = 1;  // bytes per R element
+  __device__ static Acc dot(uint32_t l, uint32_t r, Acc c) {
+    return __builtin_amdgcn_sdot2(__builtin_bit_cast(short2v, l), __builtin_bit_cast(short2v, r), c, false);
+  }
+};
+template <> struct Img<P_F16> {
+  using Acc = float;
+  static constexpr int RB = 2;
+  __device__ static Acc dot(uint32_t l, uint32_t r, Acc c) {
+    return __builtin_amdgcn_fdot2(__builtin_bit_cast(half2v, l), __builtin_bit_cast(half2v, r), c, false);
+  }
+};
+template <> struct Img<P_BF16> {
+  using Acc = float;
+  static constexpr int RB = 2;
+  __device__ static Acc dot(uint32_t l, uint32_t r, Acc c) {
+    return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2v, l), __builtin_bit_cast(bf16x2v, r), c, false);
+  }
+};
+
+// Global key of a lane-local key: quantised z (bits of z+2 above the index
+// field), then 255 - (d - dmin) so that ties prefer the smaller disparity.
+__device__ __forceinline__ uint32_t global_key(float k, int dd0) {
+  uint32_t b = __builtin_bit_cast(uint32_t, k);
+  int j = 15 - (int)(b & 15u);
+  uint32_t q = b > 0x3F800000u ? (b - 0x3F800000u) >> 4 : 0u;
+  return 0x80000000u | (q << 8) | (uint32_t)(255 - (dd0 + j));
+}
+
+__device__ __forceinline__ void amax(uint32_t *p, uint32_t v) {
+  __hip_atomic_fetch_max(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Load N dwords from a 4-byte aligned address.
+template <int N>
+__device__ __forceinline__ void load_dw(uint32_t (&dst)[N], const void *p) {
+  const uint32_t *q = (const uint32_t *)__builtin_assume_aligned(p, 4);
+#pragma unroll
+  for (int i = 0; i < N; ++i) dst[i] = q[i];
+}
+
+// Load N dwords starting `sh` bytes (0..3, uniform) after the 4-byte aligned
+// address p: one extra dword, then v_alignbyte per dword.
+template <int N>
+__device__ __forceinline__ void load_dw_shifted(uint32_t (&dst)[N], const void *p, int sh) {
+  const uint32_t *q = (const uint32_t *)__builtin_assume_aligned(p, 4);
+  uint32_t t[N + 1];
+#pragma unroll
+  for (int i = 0; i <= N; ++i) t[i] = q[i];
+#pragma unroll
+  for (int i = 0; i < N; ++i) dst[i] = __builtin_amdgcn_alignbyte(t[i + 1], t[i], sh);
+}
+
+// ---------------------------------------------------------------- one task
+// Rows [y0, y1) of the span starting at column xs, disparities d0 .. d0+DC-1.
+template <int WIN, int DC, int PREC>
+__device__ __forceinline__ void match_task(const MatchPair &P, int y0, int y1, int xs, int d0,
+                                           int lane) {
+  constexpr int H = WIN / 2;
+  constexpr int K = KC;
+  constexpr int T = K + DC - 1;                 // R columns touched by a lane
+  using IM = Img<PREC>;
+  using Acc = typename IM::Acc;
+  constexpr int RB = IM::RB;
+  constexpr int NLD = K / 2;                    // dwords of one L row segment (int16/fp16)
+  constexpr int NRD = (T * RB + 3) / 4;         // dwords of one R row segment
+  const int n = WIN * WIN;
+
+  const int x0 = xs + lane * K;
+  const int colL = x0 + P.padL;                 // multiple of 8
+  const int colR = x0 - d0 - (DC - 1) + P.padR;
+  const int rsh = (RB * colR) & 3;              // byte misalignment (wave-uniform)
+  const bool halo = (lane == 0) || (lane == WV - 1);
+  const char *Lb = (const char *)P.Lp + 2 * (size_t)colL;
+  const char *NLb = (const char *)P.NLp + 2 * (size_t)colL;
+  const char *Rb = (const char *)P.Rp + (RB * (size_t)colR - rsh);
+  const size_t sL = 2 * (size_t)P.strideL, sR = RB * (size_t)P.strideR;
+
+  Acc V[DC][K];
+#pragma unroll
+  for (int j = 0; j < DC; ++j)
+#pragma unroll
+    for (int c = 0; c < K; ++c) V[j][c] = 0;
+
+  // ---- vertical sums of the first row: rows y0-H .. y0+H, two at a time
+  for (int r = y0 - H; r <= y0 + H; r += 2) {
+    const bool two = r + 1 <= y0 + H;
+    uint32_t la[NLD], lb[NLD], ra[NRD], rb[NRD];
+    load_dw(la, Lb + sL * r);
+    load_dw_shifted(ra, Rb + sR * r, rsh);
+    if (two) {
+      load_dw(lb, Lb + sL * (r + 1));
+      load_dw_shifted(rb, Rb + sR * (r + 1), rsh);
+    } else {
+#pragma unroll
+      for (int i = 0; i < NLD; ++i) lb[i] = 0;
+#pragma unroll
+      for (int i = 0; i < NRD; ++i) rb[i] = 0;
+    }
+    uint32_t lp[K], rp[T];
+#pragma unroll
+    for (int c = 0; c < K; ++c) lp[c] = __builtin_amdgcn_perm(lb[c / 2], la[c / 2], sel16(c & 1));
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      if constexpr (RB == 1) rp[t] = __builtin_amdgcn_perm(rb[t / 4], ra[t / 4], sel8(t & 3));
+      else rp[t] = __builtin_amdgcn_perm(rb[t / 2], ra[t / 2], sel16(t & 1));
+    }
+#pragma unroll
+    for (int j = 0; j < DC; ++j)
+#pragma unroll
+      for (int c = 0; c < K; ++c) V[j][c] = IM::dot(lp[c], rp[c - j + DC - 1], V[j][c]);
+  }
+
+  const int W = P.W;
+  const int dd0 = d0 - P.dmin;
+  for (int y = y0; y < y1; ++y) {
+    if (y > y0) {
+      // entering row y+H (+), leaving row y-H-1 (-)
+      const int ra_ = y + H, rl_ = y - H - 1;
+      uint32_t la[NLD], lo[NLD], ra[NRD], ro[NRD];
+      load_dw(la, Lb + sL * ra_);
+      load_dw(lo, NLb + sL * rl_);
+      load_dw_shifted(ra, Rb + sR * ra_, rsh);
+      load_dw_shifted(ro, Rb + sR * rl_, rsh);
+      uint32_t lp[K], rp[T];
+#pragma unroll
+      for (int c = 0; c < K; ++c) lp[c] = __builtin_amdgcn_perm(lo[c / 2], la[c / 2], sel16(c & 1));
+#pragma unroll
+      for (int t = 0; t < T; ++t) {
+        if constexpr (RB == 1) rp[t] = __builtin_amdgcn_perm(ro[t / 4], ra[t / 4], sel8(t & 3));
+        else rp[t] = __builtin_amdgcn_perm(ro[t / 2], ra[t / 2], sel16(t & 1));
+      }
+#pragma unroll
+      for (int j = 0; j < DC; ++j)
+#pragma unroll
+        for (int c = 0; c < K; ++c) V[j][c] = IM::dot(lp[c], rp[c - j + DC - 1], V[j][c]);
+    }
+
+    // ---- per-row statistics
+    int nsl[K];
+    float il[K];
+    {
+      const int32_t *ns = P.negSL + (size_t)y * P.strideL + colL;
+      const float *iv = P.invL + (size_t)y * P.strideL + colL;
+#pragma unroll
+      for (int c = 0; c < K; ++c) {
+        nsl[c] = ns[c];
+        il[c] = halo ? __builtin_nanf("") : iv[c];
+      }
+    }
+    const int32_t *srp = P.SR + (size_t)y * P.strideR + colR;
+    const float *irp = P.invR + (size_t)y * P.strideR + colR;
+
+    // ---- horizontal sums at the lane's first column
+    Acc S[DC];
+#pragma unroll
+    for (int j = 0; j < DC; ++j) {
+      Acc s = V[j][0];
+#pragma unroll
+      for (int c = 1; c <= H; ++c) s += V[j][c];
+#pragma unroll
+      for (int c = K - H; c < K; ++c) s += from_left(V[j][c]);
+      S[j] = s;
+    }
+
+    float bestL[K];
+    float Pd[T];
+#pragma unroll
+    for (int c = 0; c < K; ++c) bestL[c] = 0.0f;
+#pragma unroll
+    for (int t = 0; t < T; ++t) Pd[t] = 0.0f;
+
+    // ---- diagonal sweep: diagonal t holds the evaluations (i, j) with
+    //      i - j + DC - 1 = t, all of which share right column x0 - d0 + t - DC + 1
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      const int sr = srp[t];
+      const float ir = irp[t];
+#pragma unroll
+      for (int j = 0; j < DC; ++j) {
+        const int i = t - (DC - 1) + j;
+        if (i < 0 || i >= K) continue;
+        if (i > 0) {
+          const int ca = i + H, cs = i - H - 1;
+          Acc add = ca < K ? V[j][ca] : from_right(V[j][ca - K]);
+          Acc sub = cs >= 0 ? V[j][cs] : from_left(V[j][cs + K]);
+          S[j] = S[j] + add - sub;
+        }
+        int num;
+        if constexpr (PREC == P_I16) {
+          num = s24(nsl[i]) * s24(sr) + S[j];
+        } else {
+          num = s24((int)S[j]) * n + s24(nsl[i]) * s24(sr);
+        }
+        const float zl = (float)num * ir;
+        float zq;
+        if constexpr (PREC == P_I16) {
+          zq = __builtin_fmaf(zl, il[i], 2.0f);
+        } else if constexpr (PREC == P_F16) {
+          zq = (float)(_Float16)(zl * il[i]) + 2.0f;
+        } else {
+          uint32_t u = __builtin_bit_cast(uint32_t, zl * il[i]);
+          u = (u + 0x7FFFu + ((u >> 16) & 1u)) & 0xFFFF0000u;
+          zq = __builtin_bit_cast(float, u) + 2.0f;
+        }
+        const float key = __builtin_bit_cast(
+            float, (__builtin_bit_cast(uint32_t, zq) & ~15u) | (uint32_t)(15 - j));
+        bestL[i] = kmax(bestL[i], key);
+        Pd[t] = kmax(Pd[t], key);
+      }
+    }
+
+    // ---- right reference: fold diagonals of higher lanes into this lane's
+    //      home diagonals t in [DC-1, T).  Increasing t order chains the
+    //      contributions of several lanes in one pass.
+#pragma unroll
+    for (int t = 0; t < DC - 1; ++t) Pd[t + K] = kmax(Pd[t + K], from_right(Pd[t]));
+
+    // ---- emit: left reference per pixel, right reference per home column
+    uint32_t *kl = P.keyL + (size_t)y * W + x0;
+    if (!halo) {
+#pragma unroll
+      for (int c = 0; c < K; ++c)
+        if (bestL[c] >= 0.5f) amax(kl + c, global_key(bestL[c], dd0));
+    }
+    uint32_t *kr = P.keyR + (size_t)y * W + (x0 - d0);
+#pragma unroll
+    for (int m = 0; m < K; ++m)
+      if (Pd[m + DC - 1] >= 0.5f) amax(kr + m, global_key(Pd[m + DC - 1], dd0));
+    if (lane == 0) {
+#pragma unroll
+      for (int m = -(DC - 1); m < 0; ++m)
+        if (Pd[m + DC - 1] >= 0.5f) amax(kr + m, global_key(Pd[m + DC - 1], dd0));
+    }
+  }
+}
+
+// ---------------------------------------------------------------- task decode
+__device__ __forceinline__ void task_coords(const MatchPair &P, int g, int c, int &y0, int &y1,
+                                            int &xs, int &d0) {
+  const int h = P.win / 2;
+  const int band = g / P.nspan, span = g - band * P.nspan;
+  y0 = h + band * P.TY;
+  y1 = min(y0 + P.TY, P.H - h);
+  xs = P.xs0 + span * (OUT_LANES * KC);
+  const int D = P.dmax - P.dmin + 1;
+  d0 = P.dmin + min(c * P.DC, D - P.DC);
+}
+
+// One wave per task.  Blocks b with equal b % 8 run on one XCD; each XCD
+// gets whole (band, span) groups so that the chunks of a group share its L2.
+template <int WIN, int DC, int PREC>
+__global__ __launch_bounds__(64) void match_kernel(MatchPair P, int ngroups) {
+  const int b = blockIdx.x;
+  const int xcd = b & 7;
+  const int r = b >> 3;
+  const int c = r % P.nchunk;
+  const int g = (r / P.nchunk) * 8 + xcd;
+  if (g >= ngroups) return;
+  int y0, y1, xs, d0;
+  task_coords(P, g, c, y0, y1, xs, d0);
+  match_task<WIN, DC, PREC>(P, y0, y1, xs, d0, threadIdx.x);
+}
+
+// Persistent form: waves pull tasks (pair, group, chunk) from a queue until
+// it is empty.  Every wave reaches the exit once the counter passes ntasks.
+template <int DC, int PREC>
+__global__ __launch_bounds__(64) void match_persistent_kernel(const MatchPair *pairs,
+                                                              const int4 *tasks, int ntasks,
+                                                              int *counter) {
+  const int lane = threadIdx.x;
+  for (;;) {
+    int t = 0;
+    if (lane == 0) t = atomicAdd(counter, 1);
+    t = __builtin_amdgcn_readfirstlane(t);
+    if (t >= ntasks) break;
+    const int4 tk = tasks[t];
+    const MatchPair P = pairs[tk.x];
+    int y0, y1, xs, d0;
+    task_coords(P, tk.y, tk.z, y0, y1, xs, d0);
+    switch (P.win) {
+      case 3: match_task<3, DC, PREC>(P, y0, y1, xs, d0, lane); break;
+      case 5: match_task<5, DC, PREC>(P, y0, y1, xs, d0, lane); break;
+      case 7: match_task<7, DC, PREC>(P, y0, y1, xs, d0, lane); break;
+      case 9: match_task<9, DC, PREC>(P, y0, y1, xs, d0, lane); break;
+      case 11: match_task<11, DC, PREC>(P, y0, y1, xs, d0, lane); break;
+      case 13: match_task<13, DC, PREC>(P, y0, y1, xs, d0, lane); break;
+      default: match_task<15, DC, PREC>(P, y0, y1, xs, d0, lane); break;
+    }
+  }
+}
+
+__global__ void reset_counter_kernel(int *counter) { *counter = 0; }
+
+// ---------------------------------------------------------------- preparation
+// Padded image planes and the padding of the statistics planes of one pair
+// (descriptor by value) or of a batch (table, pair = blockIdx.z).
+template <int PREC, bool B>
+__global__ void prep_planes_kernel(PrepPair one, const PrepPair *many) {
+  const PrepPair &P = B ? many[blockIdx.z] : one;
+  const int y = blockIdx.y;
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (y >= P.H) return;
+  const int W = P.W;
+  const int n = P.win * P.win;
+  const float qnan = __builtin_nanf("");
+  if (c < P.strideL) {
+    const int x = c - P.padL;
+    const bool in = x >= 0 && x < W;
+    const int v = in ? (int)P.L[(size_t)y * P.pitch + x] - 128 : 0;
+    const size_t k = (size_t)y * P.strideL + c;
+    if constexpr (PREC == P_I16) {
+      ((int16_t *)P.Lp)[k] = (int16_t)(n * v);
+      ((int16_t *)P.NLp)[k] = (int16_t)(-n * v);
+    } else if constexpr (PREC == P_F16) {
+      ((_Float16 *)P.Lp)[k] = (_Float16)(float)v;
+      ((_Float16 *)P.NLp)[k] = (_Float16)(float)(-v);
+    } else {
+      ((uint16_t *)P.Lp)[k] = (uint16_t)(__builtin_bit_cast(uint32_t, (float)v) >> 16);
+      ((uint16_t *)P.NLp)[k] = (uint16_t)(__builtin_bit_cast(uint32_t, (float)(-v)) >> 16);
+    }
+    if (!in) { P.negSL[k] = 0; P.invL[k] = qnan; }
+  }
+  if (c < P.strideR) {
+    const int x = c - P.padR;
+    const bool in = x >= 0 && x < W;
+    const int v = in ? (int)P.R[(size_t)y * P.pitch + x] : 0;
+    const size_t k = (size_t)y * P.strideR + c;
+    if constexpr (PREC == P_I16) {
+      ((uint8_t *)P.Rp)[k] = (uint8_t)v;
+    } else if constexpr (PREC == P_F16) {
+      ((_Float16 *)P.Rp)[k] = (_Float16)(float)v;
+    } else {
+      ((uint16_t *)P.Rp)[k] = (uint16_t)(__builtin_bit_cast(uint32_t, (float)v) >> 16);
+    }
+    if (!in) { P.SRp[k] = 0; P.invR[k] = qnan; }
+  }
+}
+
+// Window sums S = sum I, SS = sum I^2 (exact ints) and 1/sqrt(n SS - S^2)
+// computed in FP64, for every pixel of one image; 0 / NaN where the window
+// leaves the image, NaN where it is flat.  side 0: left image (padded plane
+// holds 128 n - S), side 1: right image (padded plane holds S), side 2:
+// dense outputs only (PrepPair fields SL, SSL, invLd).
+constexpr int WS_BX = 32, WS_BY = 8, WS_HMAX = 7;
+template <bool B>
+__global__ __launch_bounds__(256) void window_stats_kernel(PrepPair one, const PrepPair *many,
+                                                           int side) {
+  const PrepPair &P = B ? many[blockIdx.z] : one;
+  __shared__ uint8_t tile[WS_BY + 2 * WS_HMAX][WS_BX + 2 * WS_HMAX];
+  __shared__ int cs[WS_BY][WS_BX + 2 * WS_HMAX];
+  __shared__ int css[WS_BY][WS_BX + 2 * WS_HMAX];
+  const int H = P.H, W = P.W, win = P.win, h = win / 2;
+  const int bx = blockIdx.x * WS_BX, by = blockIdx.y * WS_BY;
+  if (bx >= W || by >= H) return;  // uniform per block
+  const uint8_t *img = side == 1 ? P.R : P.L;
+  const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * WS_BX + tx;
+  const int TW = WS_BX + 2 * h, TH = WS_BY + 2 * h;
+  for (int i = tid; i < TW * TH; i += 256) {
+    const int r = i / TW, c = i - r * TW;
+    const int gy = by - h + r, gx = bx - h + c;
+    tile[r][c] = (gy >= 0 && gy < H && gx >= 0 && gx < W) ? img[(size_t)gy * P.pitch + gx] : 0;
+  }
+  __syncthreads();
+  for (int i = tid; i < WS_BY * TW; i += 256) {
+    const int r = i / TW, c = i - r * TW;
+    int s = 0, ss = 0;
+    for (int v = 0; v < win; ++v) {
+      const int p = tile[r + v][c];
+      s += p;
+      ss += p * p;
+    }
+    cs[r][c] = s;
+    css[r][c] = ss;
+  }
+  __syncthreads();
+  const int x = bx + tx, y = by + ty;
+  if (x >= W || y >= H) return;
+  int s = 0, ss = 0;
+  for (int u = 0; u < win; ++u) {
+    s += cs[ty][tx + u];
+    ss += css[ty][tx + u];
+  }
+  const bool inside = x >= h && x <= W - 1 - h && y >= h && y <= H - 1 - h;
+  float iv = __builtin_nanf("");
+  if (!inside) {
+    s = 0;
+    ss = 0;
+  } else {
+    const long long n = (long long)win * win;
+    const long long varN = n * ss - (long long)s * s;
+    if (varN > 0) iv = (float)(1.0 / sqrt((double)varN));
+  }
+  const size_t k = (size_t)y * W + x;
+  if (side == 1) {
+    P.SR[k] = s;
+    P.SSR[k] = ss;
+    if (P.invRd) P.invRd[k] = iv;
+    const size_t kp = (size_t)y * P.strideR + x + P.padR;
+    P.SRp[kp] = s;
+    P.invR[kp] = iv;
+  } else {
+    P.SL[k] = s;
+    P.SSL[k] = ss;
+    if (P.invLd) P.invLd[k] = iv;
+    if (side == 0) {
+      const size_t kp = (size_t)y * P.strideL + x + P.padL;
+      P.negSL[kp] = 128 * win * win - s;
+      P.invL[kp] = iv;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- host launchers
+template <int WIN, int DC, int PREC>
+static hipError_t launch_match_t(const MatchPair &P, hipStream_t s) {
+  const int ngroups = P.nband * P.nspan;
+  const int blocks = 8 * ceil_div(ngroups, 8) * P.nchunk;
+  hipLaunchKernelGGL((match_kernel<WIN, DC, PREC>), dim3(blocks), dim3(64), 0, s, P, ngroups);
+  return hipGetLastError();
+}
+
+template <int DC, int PREC>
+static hipError_t launch_match_w(const MatchPair &P, hipStream_t s) {
+  switch (P.win) {
+    case 3: return launch_match_t<3, DC, PREC>(P, s);
+    case 5: return launch_match_t<5, DC, PREC>(P, s);
+    case 7: return launch_match_t<7, DC, PREC>(P, s);
+    case 9: return launch_match_t<9, DC, PREC>(P, s);
+    case 11: return launch_match_t<11, DC, PREC>(P, s);
+    case 13: return launch_match_t<13, DC, PREC>(P, s);
+    case 15: return launch_match_t<15, DC, PREC>(P, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_match(const MatchPair &P, int prec, hipStream_t s) {
+  if (P.DC == 16) {
+    if (prec == P_I16) return launch_match_w<16, P_I16>(P, s);
+    if (prec == P_F16) return launch_match_w<16, P_F16>(P, s);
+    return launch_match_w<16, P_BF16>(P, s);
+  }
+  if (prec == P_I16) return launch_match_w<8, P_I16>(P, s);
+  if (prec == P_F16) return launch_match_w<8, P_F16>(P, s);
+  return launch_match_w<8, P_BF16>(P, s);
+}
+
+hipError_t launch_match_persistent(const MatchPair *pairs_dev, const int4 *tasks_dev, int ntasks,
+                                   int *counter_dev, int DC, int prec, int nblocks,
+                                   hipStream_t s) {
+  hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, counter_dev);
+#define PK(dc, pr)                                                                         \
+  hipLaunchKernelGGL((match_persistent_kernel<dc, pr>), dim3(nblocks), dim3(64), 0, s, pairs_dev, \
+                     tasks_dev, ntasks, counter_dev)
+  if (DC == 16) {
+    if (prec == P_I16) PK(16, P_I16); else if (prec == P_F16) PK(16, P_F16); else PK(16, P_BF16);
+  } else {
+    if (prec == P_I16) PK(8, P_I16); else if (prec == P_F16) PK(8, P_F16); else PK(8, P_BF16);
+  }
+#undef PK
+  return hipGetLastError();
+}
+
+int match_persistent_occupancy(int DC, int prec) {
+  int n = 0;
+  hipError_t e;
+  if (DC == 16) {
+    if (prec == P_I16) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, match_persistent_kernel<16, P_I16>, 64, 0);
+    else if (prec == P_F16) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, match_persistent_kernel<16, P_F16>, 64, 0);
+    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, match_persistent_kernel<16, P_BF16>, 64, 0);
+  } else {
+    if (prec == P_I16) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, match_persistent_kernel<8, P_I16>, 64, 0);
+    else if (prec == P_F16) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, match_persistent_kernel<8, P_F16>, 64, 0);
+    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, match_persistent_kernel<8, P_BF16>, 64, 0);
+  }
+  if (e != hipSuccess) { (void)hipGetLastError(); return 4; }
+  return n;
+}
+
+hipError_t launch_prep(const PrepPair &one, const PrepPair *many, int npairs, int maxH,
+                       int maxCols, int maxW, int prec, hipStream_t s) {
+  const dim3 grid(ceil_div(maxCols, 256), maxH, npairs);
+#define PP(pr)                                                                                \
+  do {                                                                                        \
+    if (many) hipLaunchKernelGGL((prep_planes_kernel<pr, true>), grid, dim3(256), 0, s, one, many); \
+    else hipLaunchKernelGGL((prep_planes_kernel<pr, false>), grid, dim3(256), 0, s, one, many);     \
+  } while (0)
+  if (prec == P_I16) PP(P_I16); else if (prec == P_F16) PP(P_F16); else PP(P_BF16);
+#undef PP
+  const dim3 gs(ceil_div(maxW, WS_BX), ceil_div(maxH, WS_BY), npairs);
+  for (int side = 0; side < 2; ++side) {
+    if (many) hipLaunchKernelGGL(window_stats_kernel<true>, gs, dim3(WS_BX, WS_BY), 0, s, one, many, side);
+    else hipLaunchKernelGGL(window_stats_kernel<false>, gs, dim3(WS_BX, WS_BY), 0, s, one, many, side);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_window_stats_dense(const uint8_t *img, int H, int W, int pitch, int win,
+                                     int32_t *S, int32_t *SS, float *inv, hipStream_t s) {
+  PrepPair P = {};
+  P.L = img;
+  P.H = H;
+  P.W = W;
+  P.pitch = pitch;
+  P.win = win;
+  P.SL = S;
+  P.SSL = SS;
+  P.invLd = inv;
+  const dim3 gs(ceil_div(W, WS_BX), ceil_div(H, WS_BY), 1);
+  hipLaunchKernelGGL(window_stats_kernel<false>, gs, dim3(WS_BX, WS_BY), 0, s, P, (const PrepPair *)nullptr, 2);
+  return hipGetLastError();
+}
+
+}  // namespace st

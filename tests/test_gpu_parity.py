@@ -1,0 +1,227 @@
+"""HIP path against the CPU oracle, stage by stage and end to end.
+
+Bars: integer disparities and masks bit-exact wherever the oracle's top-2
+ZNCC gap exceeds 1e-5 (the matcher quantises z + 2 to 2^-18 before its
+argmax); ZNCC values and sub-pixel offsets within 1e-5; smoothed
+disparities within max(1e-5, 1 ulp).  Sizes span several tiles, ragged
+edges, signed disparity ranges and every window size.
+"""
+import numpy as np
+import pytest
+
+from gpu_util import cu, dilate, np_, tie_mask
+from paper_2007_12623_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_2007_12623_amd import binding
+    return binding
+
+
+def _pair(H, W, D, seed):
+    p = synth.make_pair(H, W, D, seed)
+    return p["left"], p["right"]
+
+
+CASES = [
+    # (H, W, dmin, dmax, win, seed)
+    (240, 320, 0, 31, 7, 1001),     # the 320x240 workload
+    (37, 150, -5, 27, 5, 11),       # ragged, negative disparities
+    (61, 530, 3, 70, 3, 12),        # two spans, 68 candidates
+    (45, 200, 0, 15, 9, 13),        # D = 16
+    (50, 190, -12, -5, 11, 14),     # D = 8, all negative
+    (40, 260, 0, 40, 13, 15),
+    (48, 300, 10, 60, 15, 16),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[f"{c[0]}x{c[1]}_d{c[2]}..{c[3]}_w{c[4]}" for c in CASES])
+def test_window_stats(B, orc, case):
+    H, W, dmin, dmax, win, seed = case
+    L, _ = _pair(H, W, max(dmax, 8), seed)
+    S, SS, inv = B.st_window_stats(cu(L), win)
+    rS, rSS, rV, ins = orc.window_stats(L, win)
+    assert np.array_equal(np_(S), rS.astype(np.int32))
+    assert np.array_equal(np_(SS), rSS.astype(np.int32))
+    g = np_(inv)
+    ok = (ins == 1) & (rV > 0)
+    ref = (1.0 / np.sqrt(rV[ok].astype(np.float64))).astype(np.float32)
+    assert np.all(np.isnan(g[~ok]))
+    np.testing.assert_array_max_ulp(g[ok], ref, maxulp=1)
+
+
+def _check_wta(out, ref, oL, mL, oR, mR):
+    assert np.array_equal(mL, ref["mL"]), "left validity"
+    assert np.array_equal(mR, ref["mR"]), "right validity"
+    sel = (ref["mL"] == 1) & ~tie_mask(ref["gap"])
+    bad = np.nonzero(oL[sel] != ref["oL"][sel])[0]
+    assert bad.size == 0, f"{bad.size} left disparities differ"
+    selr = (ref["mR"] == 1) & ~tie_mask(ref["gapR"])
+    badr = np.nonzero(oR[selr] != ref["oR"][selr])[0]
+    assert badr.size == 0, f"{badr.size} right disparities differ"
+
+
+@pytest.mark.parametrize("case", CASES, ids=[f"{c[0]}x{c[1]}_d{c[2]}..{c[3]}_w{c[4]}" for c in CASES])
+def test_match_wta(B, orc, case):
+    H, W, dmin, dmax, win, seed = case
+    L, R = _pair(H, W, max(dmax, 8), seed)
+    oL, mL, oR, mR = (np_(t) for t in B.st_match_wta(cu(L), cu(R), dmin, dmax, win))
+    ref = orc.match(L, R, dmin, dmax, win)
+    _check_wta(None, ref, oL, mL, oR, mR)
+
+
+def test_match_wta_every_variant(B, orc):
+    H, W, dmin, dmax, win, seed = 70, 420, 0, 47, 7, 21
+    L, R = _pair(H, W, dmax, seed)
+    ref = orc.match(L, R, dmin, dmax, win)
+    h = B.Handle(0)
+    try:
+        for v in range(B.st_num_variants()):
+            B.st_set_variant(v, handle=h)
+            oL, mL, oR, mR = (np_(t) for t in B.st_match_wta(cu(L), cu(R), dmin, dmax, win, handle=h))
+            _check_wta(None, ref, oL, mL, oR, mR)
+    finally:
+        h.close()
+
+
+def test_match_wta_integer_shift_exact(B):
+    r = np.random.default_rng(3)
+    H, W, k = 64, 300, 9
+    wide = r.integers(0, 256, size=(H, W + k), dtype=np.uint8)
+    L, R = wide[:, :W].copy(), wide[:, k:].copy()
+    oL, mL, oR, mR = (np_(t) for t in B.st_match_wta(cu(L), cu(R), 0, 23, 7))
+    h = 3
+    assert (oL[h:H - h, h + k:W - h] == k).all()
+    assert (oR[h:H - h, h:W - h - k] == k).all()
+
+
+def test_match_full_size_frame(B, orc):
+    """960x540, 128 candidates, 11x11: the whole frame against the oracle."""
+    seq = synth.c2_sequence(1)
+    L, R = seq[0]["left"], seq[0]["right"]
+    oL, mL, oR, mR = (np_(t) for t in B.st_match_wta(cu(L), cu(R), 0, 127, 11))
+    ref = orc.match(L, R, 0, 127, 11)
+    _check_wta(None, ref, oL, mL, oR, mR)
+
+
+def test_subpixel_exact_z(B, orc):
+    L, R = _pair(60, 250, 31, 31)
+    ref = orc.match(L, R, 0, 31, 7)
+    zb, zm, zp, dl = (np_(t) for t in B.st_subpixel(cu(L), cu(R), 0, 31, 7,
+                                                       cu(ref["oL"].astype(np.int16)), cu(ref["mL"])))
+    v = ref["mL"] == 1
+    np.testing.assert_allclose(zb[v], ref["zbest"][v], atol=1e-12)
+    np.testing.assert_allclose(zm[v], ref["zm"][v], atol=1e-12)
+    np.testing.assert_allclose(zp[v], ref["zp"][v], atol=1e-12)
+    rd = orc.subpixel(ref["oL"], ref["mL"], ref["zm"], ref["zbest"], ref["zp"], 0, 31)
+    assert np.abs(dl[v] - rd[v]).max() <= 1e-5
+    assert (dl[~v] == 0).all()
+
+
+def _maps(orc, L, R, dmin, dmax, win):
+    ref = orc.match(L, R, dmin, dmax, win)
+    return ref
+
+
+def test_lr_check_stage(B, orc):
+    L, R = _pair(120, 300, 31, 41)
+    ref = orc.match(L, R, 0, 31, 7)
+    args = [cu(ref["oL"].astype(np.int16)), cu(ref["mL"]), cu(ref["oR"].astype(np.int16)), cu(ref["mR"])]
+    for tol in (0, 1, 3):
+        g = np_(B.st_lr_check(*args, tol=tol))
+        assert np.array_equal(g, orc.lr_check(ref["oL"], ref["mL"], ref["oR"], ref["mR"], tol))
+
+
+def test_outlier_and_fill_stages(B, orc):
+    L, R = _pair(140, 330, 31, 42)
+    ref = orc.match(L, R, 0, 31, 7)
+    m = orc.lr_check(ref["oL"], ref["mL"], ref["oR"], ref["mR"], 1)
+    o = ref["oL"]
+    for r in (1, 10, 20, 30):
+        g = np_(B.st_radial_outlier(cu(o.astype(np.int16)), cu(m), r, 2.5))
+        assert np.array_equal(g, orc.radial_outlier(o, m, r, 2.5)), f"outlier r={r}"
+    m2 = orc.radial_outlier(o, m, 10, 2.5)
+    for args in ((50, 2, 20, 0.25), (5, 1, 3, 0.5), (0, 2, 20, 0.25), (50, 4, 0, 0.0)):
+        go, gm = B.st_fill(cu(o.astype(np.int16)), cu(m2), *args)
+        ro, rm = orc.fill(o, m2, *args)
+        assert np.array_equal(np_(gm), rm), f"fill mask {args}"
+        assert np.array_equal(np_(go)[rm > 0], ro[rm > 0]), f"fill values {args}"
+
+
+@pytest.mark.parametrize("R,K", [(2, 1), (15, 3), (4, 2), (0, 1), (3, 0)])
+def test_hc_smooth_stage(B, orc, R, K):
+    r = np.random.default_rng(R * 10 + K)
+    H, W = 90, 170
+    s = (r.normal(40.0, 6.0, size=(H, W))).astype(np.float32)
+    m = (r.random((H, W)) > 0.15).astype(np.uint8) * np.where(r.random((H, W)) > 0.5, 1, 2).astype(np.uint8)
+    g = np_(B.st_hc_smooth(cu(s), cu(m), R, K, 0.1))
+    ref = orc.hc_smooth(s.astype(np.float64), m, R, K, 0.1)
+    v = m > 0
+    assert np.isnan(g[~v]).all()
+    tol = np.maximum(1e-5, np.spacing(np.abs(ref[v]).astype(np.float32)).astype(np.float64))
+    assert np.all(np.abs(g[v] - ref[v]) <= tol)
+
+
+def _end_to_end(B, orc, L, R, dmin, dmax, win, params_gpu, params_orc, dil):
+    h = B.Handle(0)
+    try:
+        params_gpu.debug_outputs = 1
+        disp, mask = B.stereo_match(cu(L), cu(R), dmin, dmax, win, params_gpu, handle=h)
+        disp, mask = np_(disp), np_(mask)
+        H, W = L.shape
+        import torch
+        o_wta = np_(B.stereo_debug_get("o_wta", (H, W), torch.int16, handle=h))
+        dl = np_(B.stereo_debug_get("delta", (H, W), torch.float32, handle=h))
+    finally:
+        h.close()
+    rdisp, rmask, inter = orc.pipeline(L, R, dmin, dmax, win, params_orc, intermediates=True)
+    ref = orc.match(L, R, dmin, dmax, win)
+    ties = tie_mask(ref["gap"]) & (ref["mL"] == 1)
+    # right-reference near ties affect the left pixels that look at them
+    tr = tie_mask(ref["gapR"]) & (ref["mR"] == 1)
+    Hh, Ww = L.shape
+    yy, xx = np.nonzero(ref["mL"] == 1)
+    xr = xx - ref["oL"][yy, xx]
+    okr = (xr >= 0) & (xr < Ww)
+    tl = np.zeros_like(ties)
+    tl[yy[okr], xx[okr]] = tr[yy[okr], xr[okr]]
+    near = dilate(ties | tl, dil)
+    far = ~near
+    assert np.array_equal(o_wta[(ref["mL"] == 1) & ~ties], ref["oL"][(ref["mL"] == 1) & ~ties])
+    assert np.array_equal(mask[far], rmask[far]), f"mask differs on {(mask[far] != rmask[far]).sum()} px"
+    v = far & (rmask > 0)
+    tol = np.maximum(1e-5, np.spacing(np.abs(rdisp[v]).astype(np.float32)).astype(np.float64))
+    bad = np.abs(disp[v] - rdisp[v]) > tol
+    assert not bad.any(), f"{bad.sum()} disparities differ, max {np.abs(disp[v] - rdisp[v]).max():.3g}"
+    agree = (mask == rmask).mean()
+    assert agree > 0.995
+    if params_orc.subpixel:
+        sv = (inter["m_wta"] == 1) & (o_wta == inter["o_wta"])
+        assert np.abs(dl[sv] - inter["delta"][sv]).max() <= 1e-5
+    return far.mean()
+
+
+def test_end_to_end_small_workload(B, orc):
+    p = synth.c1_pair()
+    frac = _end_to_end(B, orc, p["left"], p["right"], 0, 31, 7, B.preset("small"),
+                       orc.params_c1(), dil=60)
+    assert frac > 0.5
+
+
+def test_end_to_end_full_pipeline(B, orc):
+    """960x540 / 128 / 11x11 with 3 outlier-fill alternations and R=15, K=3."""
+    seq = synth.c2_sequence(1)
+    frac = _end_to_end(B, orc, seq[0]["left"], seq[0]["right"], 0, 127, 11, B.preset("full"),
+                       orc.params_c2(), dil=130)
+    assert frac > 0.3
+
+
+def test_pipeline_options(B, orc):
+    """Pipeline with the left-right check and sub-pixel switched off."""
+    L, R = _pair(100, 260, 31, 51)
+    pg = B.preset("small", lr_check=0, subpixel=0, radial_iters=2, radial_r0=3, radial_dr=2)
+    po = orc.params_c1(lr_check=0, subpixel=0, radial_iters=2, radial_r0=3, radial_dr=2)
+    _end_to_end(B, orc, L, R, 0, 31, 7, pg, po, dil=40)
