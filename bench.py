@@ -1,0 +1,194 @@
+"""Throughput of the dense ZNCC stereo path on one MI355X.
+
+One step = the whole path (ZNCC matching + WTA in both references, exact
+sub-pixel offsets, left-right check, 3 outlier-removal / hole-filling
+alternations, improved Laplacian smoothing) over the 30-frame 960x540
+sequence, disparities 0..127, 11x11 window, FP32 path, run as one batched
+persistent launch replayed from a HIP graph.  Inputs are seeded synthetic
+pairs already resident in HBM.  Prints one JSON line.
+
+value = pixel*disparity evaluations per second of the whole step
+(30 * 960*540*128 per step); the matcher kernel is also timed alone with HIP
+events on its stream for the roofline figure.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# per-evaluation VALU lane-operations of the incremental ZNCC scheme that the
+# roofline counts as useful work (vertical update 2, horizontal update 2,
+# exact numerator 2, normalisation 2, argmax 2)
+OPS_PER_EVAL = 10
+# MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz, one non-packed 32-bit op per lane-cycle
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+FRAMES = 30
+H, W, DMIN, DMAX, WIN = 540, 960, 0, 127, 11
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--frames", type=int, default=FRAMES)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the FP16/BF16, single-pair, uneven-batch and refinement lines")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    return ap.parse_args()
+
+
+def cpu_baseline(seq, seconds):
+    """The oracle as it stands, on the host cores, over whole frames of the
+    same workload until about `seconds` have passed (at least one frame)."""
+    from oracle import oracle
+    oracle.build()
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    n = 0
+    for fr in seq:
+        oracle.pipeline(fr["left"], fr["right"], DMIN, DMAX, WIN, oracle.params_c2())
+        n += 1
+        if time.perf_counter() - t0 >= seconds:
+            break
+    dt = time.perf_counter() - t0
+    evals = n * H * W * (DMAX - DMIN + 1)
+    return {"value": round(evals / dt / 1e9, 4), "unit": "Gdisp-evals/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"{n} of {len(seq)} frames, whole pipeline, {dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported in this build "
+              "(pairs and row bands would shard across GPUs with no exchange).", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_2007_12623_amd import binding as B
+    from paper_2007_12623_amd import synth
+
+    seq = synth.c2_sequence(args.frames)
+    dev = torch.device("cuda:0")
+    pairs = []
+    for fr in seq:
+        pairs.append({"left": torch.from_numpy(fr["left"]).to(dev),
+                      "right": torch.from_numpy(fr["right"]).to(dev),
+                      "dmin": DMIN, "dmax": DMAX, "win": WIN})
+    params = B.preset("full")
+    h = B.Handle(0)
+    stream = torch.cuda.current_stream()
+    evals_per_step = args.frames * H * W * (DMAX - DMIN + 1)
+
+    for _ in range(max(1, args.warmup)):
+        B.stereo_match_batched(pairs, params, handle=h)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        B.stereo_match_batched(pairs, params, handle=h)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_step = e0.elapsed_time(e1) / args.steps
+    value = evals_per_step / (ms_step / 1e3) / 1e9
+
+    # the matcher kernel alone, HIP events on its own stream
+    matcher_ms = B.stereo_time_matcher(pairs, params, reps=max(5, args.steps // 2), handle=h)
+    achieved = evals_per_step * OPS_PER_EVAL / (matcher_ms / 1e3) / 1e12
+
+    out = {
+        "metric": "Gdisp-evals/s and ms per 960x540x128 pair; fp16/batched vs fp32 plain",
+        "value": round(value, 2),
+        "unit": "Gdisp-evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "ms_per_pair": round(ms_step / args.frames, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32+fp32",
+        "data": "synthetic",
+        "config": {"workload": f"960x540 stereo sequence, {args.frames} frames, disparities "
+                               "0-127, 11x11 ZNCC, LR check, 3 outlier/fill alternations, "
+                               "smoothing R=15 K=3, FP32, batched persistent launch",
+                   "frames": args.frames, "H": H, "W": W, "dmin": DMIN, "dmax": DMAX,
+                   "win": WIN},
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": VALU_PEAK_TOPS,
+                     "unit": "TOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
+                     "traffic": None, "kernel": "match_persistent_kernel",
+                     "kernel_ms": round(matcher_ms, 4), "ops_per_eval": OPS_PER_EVAL},
+    }
+    if not args.no_extras:
+        out["extras"] = extras(B, torch, np, synth, seq, pairs, h)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(seq, args.cpu_seconds)
+    h.close()
+    print(json.dumps(out), flush=True)
+
+
+def _time(fn, torch, reps=10):
+    fn()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def extras(B, torch, np, synth, seq, pairs, h):
+    """Comparisons reported beside the headline: the plain per-pair path, FP16
+    and BF16 storage, the uneven 64-pair batch, the refinement step."""
+    ev = H * W * (DMAX - DMIN + 1)
+    res = {}
+    params = B.preset("full")
+    L0, R0 = pairs[0]["left"], pairs[0]["right"]
+    # plain path: one stereo_match call per pair
+    ms = _time(lambda: B.stereo_match(L0, R0, DMIN, DMAX, WIN, params, handle=h), torch)
+    res["plain_fp32_ms_per_pair"] = round(ms, 4)
+    res["plain_fp32_gevals"] = round(ev / ms / 1e6, 2)
+    for name, prec in (("fp16", B.ST_FP16), ("bf16", B.ST_BF16)):
+        p = B.preset("full", precision=prec)
+        ms_b = B.stereo_time_matcher(pairs, p, reps=5, handle=h) / len(pairs)
+        res[f"matcher_{name}_ms_per_pair"] = round(ms_b, 4)
+    res["matcher_fp32_ms_per_pair"] = round(
+        B.stereo_time_matcher(pairs, params, reps=5, handle=h) / len(pairs), 4)
+    # uneven batch: 64 pairs of 4 shapes, 32..192 disparities, 7x7 / 11x11
+    batch = synth.c4_batch()
+    bp = [{"left": torch.from_numpy(q["left"]).cuda(), "right": torch.from_numpy(q["right"]).cuda(),
+           "dmin": q["dmin"], "dmax": q["dmax"], "win": q["win"]} for q in batch]
+    bev = sum(q["H"] * q["W"] * (q["dmax"] - q["dmin"] + 1) for q in batch)
+    ms = _time(lambda: B.stereo_match_batched(bp, params, handle=h), torch, reps=5)
+    res["uneven64_ms_per_batch"] = round(ms, 3)
+    res["uneven64_gevals"] = round(bev / ms / 1e6, 2)
+    ms_m = B.stereo_time_matcher(bp, params, reps=5, handle=h)
+    res["uneven64_matcher_ms"] = round(ms_m, 3)
+    res["uneven64_matcher_gevals"] = round(bev / ms_m / 1e6, 2)
+    # refinement: forward + backward + step on the 960x540 frame
+    d = torch.rand((H, W), device="cuda", dtype=torch.float32) * 100 + 10
+    m = torch.ones((H, W), device="cuda", dtype=torch.uint8)
+
+    def step():
+        B.stereo_refine_forward(L0, R0, d, m, WIN, 0.1, handle=h)
+        g = B.stereo_refine_backward(L0, R0, d, m, WIN, 0.1, handle=h)
+        B.stereo_refine_step(d, g, m, 0.0, 0.25, handle=h)
+    res["refine_ms_per_step"] = round(_time(step, torch), 4)
+    return res
+
+
+if __name__ == "__main__":
+    main()

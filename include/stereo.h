@@ -135,7 +135,8 @@ st_status stereo_refine_forward(st_handle h, const uint8_t *left, const uint8_t 
                                 const float *d, const uint8_t *mask, int H, int W, int pitch,
                                 int win, float lambda_tv, float *Z, double *E, void *stream);
 /* dE/dd for the same energy (hand-written backward), H x W float out.
- * Subgradient 0 at the kinks of |.| and of the interpolation. */
+ * At an integer interpolation coordinate the slope of the segment to the
+ * right is used; |.| contributes 0 where a difference is exactly 0. */
 st_status stereo_refine_backward(st_handle h, const uint8_t *left, const uint8_t *right,
                                  const float *d, const uint8_t *mask, int H, int W, int pitch,
                                  int win, float lambda_tv, float *grad_d, void *stream);
@@ -217,6 +218,13 @@ st_status st_hc_smooth(st_handle h, const float *s, const uint8_t *m, int H, int
  * the chosen variant id. */
 st_status st_autotune(st_handle h, int H, int W, int dmin, int dmax, int win, int precision,
                       int *best_cfg, void *stream);
+
+/* Average duration in milliseconds (*ms_out, host) of the batched matcher
+ * kernel alone, timed with HIP events on `stream` around each of `reps`
+ * launches, for the batch described as in stereo_match_batched (which is run
+ * first, so every output is also produced).  For measurement harnesses. */
+st_status stereo_time_matcher(st_handle h, const st_pair *pairs, int n_pairs,
+                              const st_params *params, int reps, float *ms_out, void *stream);
 
 /* Force a matcher variant for later calls on this handle (-1 = automatic).
  * Variant ids are 0..st_num_variants()-1. */

@@ -96,6 +96,9 @@ def _setup(L):
     L.or_refine_energy.argtypes = [u8, u8, C.c_int, C.c_int, C.c_int, C.c_int, f64, u8,
                                    C.c_double, vp]
     L.or_refine_energy.restype = C.c_double
+    L.or_refine_energy_local.argtypes = [u8, u8, C.c_int, C.c_int, C.c_int, C.c_int, f64, u8,
+                                         C.c_double, C.c_int, C.c_int]
+    L.or_refine_energy_local.restype = C.c_double
 
 
 def _c(a, dt):
@@ -202,3 +205,11 @@ def refine_energy(left, right, d, valid, win, lam=0.1, want_z=False):
     E = lib().or_refine_energy(L, R, H, W, W, win, d, v, lam,
                                Z.ctypes.data if want_z else None)
     return (E, Z) if want_z else E
+
+
+def refine_energy_local(left, right, d, valid, win, lam, qx, qy):
+    """Terms of the refinement energy that depend on d(qy, qx)."""
+    L = _c(left, np.uint8); R = _c(right, np.uint8)
+    H, W = L.shape
+    return lib().or_refine_energy_local(L, R, H, W, W, win, _c(d, np.float64),
+                                        _c(valid, np.uint8), lam, int(qx), int(qy))

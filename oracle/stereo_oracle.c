@@ -657,3 +657,61 @@ double or_refine_energy(const uint8_t *L, const uint8_t *R, int H, int W, int pi
   free(rw);
   return E + lambda * tv;
 }
+
+/*
+ * The part of the refinement energy that depends on d(q): the windows of
+ * Omega that contain q (their ZNCC reads R_w(q)) and the TV pairs that
+ * contain q.  E(d) - E_local(d, q) does not depend on d(q), so central
+ * differences of E_local at q equal those of E; it makes the check of a
+ * full-size gradient cheap.  Same definitions as or_refine_energy.
+ */
+double or_refine_energy_local(const uint8_t *L, const uint8_t *R, int H, int W, int pitch,
+                              int win, const double *d, const uint8_t *valid, double lambda,
+                              int qx, int qy) {
+  int h = win / 2;
+  int n = win * win;
+  double E = 0.0;
+  for (int py = qy - h; py <= qy + h; ++py)
+    for (int px = qx - h; px <= qx + h; ++px) {
+      if (py < 0 || py >= H || px < 0 || px >= W) continue;
+      if (!valid[(int64_t)py * W + px] || !inside(H, W, h, py, px)) continue;
+      int all = 1;
+      double ma = 0, mb = 0;
+      double bw[15 * 15];
+      for (int v = -h; v <= h && all; ++v)
+        for (int u = -h; u <= h; ++u) {
+          int64_t q = (int64_t)(py + v) * W + px + u;
+          if (!valid[q]) { all = 0; break; }
+          double uu = (double)(px + u) - d[q];
+          if (uu < 0.0) uu = 0.0;
+          if (uu > W - 1.0) uu = W - 1.0;
+          int i0 = (int)floor(uu);
+          double t = uu - i0;
+          double r0 = R[(int64_t)(py + v) * pitch + i0];
+          double r1 = i0 + 1 < W ? R[(int64_t)(py + v) * pitch + i0 + 1] : r0;
+          double rw = r0 * (1.0 - t) + r1 * t;
+          bw[(v + h) * win + (u + h)] = rw;
+          ma += L[(int64_t)(py + v) * pitch + px + u];
+          mb += rw;
+        }
+      if (!all) continue;
+      ma /= n; mb /= n;
+      double sab = 0, saa = 0, sbb = 0;
+      for (int v = -h; v <= h; ++v)
+        for (int u = -h; u <= h; ++u) {
+          double a = L[(int64_t)(py + v) * pitch + px + u] - ma;
+          double b = bw[(v + h) * win + (u + h)] - mb;
+          sab += a * b; saa += a * a; sbb += b * b;
+        }
+      if (saa == 0.0) continue;
+      E += 1.0 - (sbb == 0.0 ? 0.0 : sab / sqrt(saa * sbb));
+    }
+  int64_t k = (int64_t)qy * W + qx;
+  if (valid[k]) {
+    if (qx + 1 < W && valid[k + 1]) E += lambda * fabs(d[k + 1] - d[k]);
+    if (qy + 1 < H && valid[k + W]) E += lambda * fabs(d[k + W] - d[k]);
+    if (qx > 0 && valid[k - 1]) E += lambda * fabs(d[k] - d[k - 1]);
+    if (qy > 0 && valid[k - W]) E += lambda * fabs(d[k] - d[k - W]);
+  }
+  return E;
+}

@@ -24,7 +24,8 @@ EXPORTS = ("st_default_params", "st_create", "st_destroy", "st_last_error", "ste
            "stereo_match_batched", "stereo_refine_forward", "stereo_refine_backward",
            "stereo_refine_step", "stereo_debug_get", "st_window_stats", "st_match_wta",
            "st_subpixel", "st_lr_check", "st_radial_outlier", "st_fill", "st_hc_smooth",
-           "st_autotune", "st_set_variant", "st_num_variants", "st_variant_name", "st_version")
+           "st_autotune", "st_set_variant", "st_num_variants", "st_variant_name", "st_version",
+           "stereo_time_matcher")
 
 
 class StereoError(RuntimeError):
@@ -84,6 +85,8 @@ def lib() -> C.CDLL:
             "st_hc_smooth": (i32, [vp, vp, vp, i32, i32, i32, i32, f32, vp, vp]),
             "st_autotune": (i32, [vp, i32, i32, i32, i32, i32, i32, C.POINTER(i32), vp]),
             "st_set_variant": (i32, [vp, i32]),
+            "stereo_time_matcher": (i32, [vp, C.POINTER(st_pair), i32, C.POINTER(st_params), i32,
+                                          C.POINTER(C.c_float), vp]),
             "st_num_variants": (i32, []),
             "st_variant_name": (C.c_char_p, [i32]),
         }
@@ -199,9 +202,16 @@ def stereo_match(left, right, dmin, dmax, win, params=None, disparity=None, vali
 def stereo_match_batched(pairs, params=None, handle=None, stream=None):
     """pairs: list of dicts with left, right (uint8 device tensors), dmin, dmax,
     win and optional disparity / valid_mask outputs.  Returns the outputs."""
-    import torch
     if params is None:
         params = st_default_params()
+    arr, outs = _pair_array(pairs)
+    _check(lib().stereo_match_batched(_h(handle), arr, len(pairs), C.byref(params),
+                                      _stream(stream)))
+    return outs
+
+
+def _pair_array(pairs):
+    import torch
     arr = (st_pair * len(pairs))()
     outs = []
     for i, q in enumerate(pairs):
@@ -211,14 +221,26 @@ def stereo_match_batched(pairs, params=None, handle=None, stream=None):
         m = q.get("valid_mask")
         if d is None:
             d = torch.empty((H, W), dtype=torch.float32, device=L.device)
+            q["disparity"] = d
         if m is None:
             m = torch.empty((H, W), dtype=torch.uint8, device=L.device)
+            q["valid_mask"] = m
         arr[i] = st_pair(L.data_ptr(), R.data_ptr(), H, W, L.stride(0), q["dmin"], q["dmax"],
                          q["win"], d.data_ptr(), m.data_ptr())
         outs.append((d, m))
-    _check(lib().stereo_match_batched(_h(handle), arr, len(pairs), C.byref(params),
-                                      _stream(stream)))
-    return outs
+    return arr, outs
+
+
+def stereo_time_matcher(pairs, params=None, reps=10, handle=None, stream=None) -> float:
+    """Average ms of the batched matcher kernel alone (HIP events on the stream).
+    Output tensors are attached to the pair dicts on first use."""
+    if params is None:
+        params = st_default_params()
+    arr, _ = _pair_array(pairs)
+    ms = C.c_float(0.0)
+    _check(lib().stereo_time_matcher(_h(handle), arr, len(pairs), C.byref(params), reps,
+                                     C.byref(ms), _stream(stream)))
+    return ms.value
 
 
 def stereo_debug_get(name, shape, dtype, handle=None):

@@ -507,8 +507,9 @@ hipError_t launch_match(const MatchPair &P, int prec, hipStream_t s) {
 
 hipError_t launch_match_persistent(const MatchPair *pairs_dev, const int4 *tasks_dev, int ntasks,
                                    int *counter_dev, int DC, int prec, int nblocks,
-                                   hipStream_t s) {
+                                   hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, counter_dev);
+  if (ev0) hipEventRecord(ev0, s);
 #define PK(dc, pr)                                                                         \
   hipLaunchKernelGGL((match_persistent_kernel<dc, pr>), dim3(nblocks), dim3(64), 0, s, pairs_dev, \
                      tasks_dev, ntasks, counter_dev)
@@ -518,6 +519,7 @@ hipError_t launch_match_persistent(const MatchPair *pairs_dev, const int4 *tasks
     if (prec == P_I16) PK(8, P_I16); else if (prec == P_F16) PK(8, P_F16); else PK(8, P_BF16);
   }
 #undef PK
+  if (ev1) hipEventRecord(ev1, s);
   return hipGetLastError();
 }
 

@@ -63,21 +63,23 @@ def _texture_canvas(rng: np.random.Generator, Hc: int, Wc: int) -> np.ndarray:
 
 
 def _flat_patches(rng, canvas, H, W, oy, ox):
-    """Two non-overlapping 40x40 low-texture patches inside the image window
-    whose top-left canvas corner is (oy, ox)."""
+    """Two non-overlapping low-texture patches (40x40, or a quarter of the
+    smaller image side for images under 80 px) inside the image window whose
+    top-left canvas corner is (oy, ox)."""
+    ps = PATCH if min(H, W) >= 2 * PATCH else max(2, min(H, W) // 4)
     placed = []
     tries = 0
     while len(placed) < 2 and tries < 1000:
         tries += 1
-        py = int(rng.integers(0, H - PATCH + 1))
-        px = int(rng.integers(0, W - PATCH + 1))
-        if any(abs(py - qy) < PATCH and abs(px - qx) < PATCH for qy, qx in placed):
+        py = int(rng.integers(0, H - ps + 1))
+        px = int(rng.integers(0, W - ps + 1))
+        if any(abs(py - qy) < ps and abs(px - qx) < ps for qy, qx in placed):
             continue
         placed.append((py, px))
     for py, px in placed:
-        sl = (slice(oy + py, oy + py + PATCH), slice(ox + px, ox + px + PATCH))
+        sl = (slice(oy + py, oy + py + ps), slice(ox + px, ox + px + ps))
         m = np.rint(canvas[sl].mean())
-        noise = rng.integers(-2, 3, size=(PATCH, PATCH))
+        noise = rng.integers(-2, 3, size=(ps, ps))
         canvas[sl] = np.clip(m + noise, 0, 255)
     return placed
 

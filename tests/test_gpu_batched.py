@@ -1,0 +1,107 @@
+"""Batched persistent launch: equal to the per-pair path bit for bit, stable
+across graph replays, and independent of the matcher's tile variant."""
+import numpy as np
+import pytest
+
+from gpu_util import cu, np_
+from paper_2007_12623_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_2007_12623_amd import binding
+    return binding
+
+
+def _mini_batch():
+    # uneven shapes, ranges (one with D < 16) and windows
+    spec = [(120, 200, 0, 31, 7), (90, 330, 0, 47, 11), (64, 96, -4, 11, 5),
+            (150, 610, 5, 90, 9), (75, 128, 0, 7, 3), (100, 260, 0, 63, 13)]
+    out = []
+    for i, (H, W, dmin, dmax, win) in enumerate(spec):
+        p = synth.make_pair(H, W, max(dmax, 8), 500 + i)
+        out.append({"left": cu(p["left"]), "right": cu(p["right"]), "dmin": dmin, "dmax": dmax,
+                    "win": win})
+    return out
+
+
+def test_batched_equals_single(B):
+    import torch
+    batch = _mini_batch()
+    params = B.preset("full", radial_r0=5, radial_dr=5, smooth_radius=4)
+    h = B.Handle(0)
+    try:
+        outs = B.stereo_match_batched(batch, params, handle=h)
+        torch.cuda.synchronize()
+        for q, (d, m) in zip(batch, outs):
+            ds, ms = B.stereo_match(q["left"], q["right"], q["dmin"], q["dmax"], q["win"], params,
+                                    handle=h)
+            assert np.array_equal(np_(m), np_(ms))
+            assert np.array_equal(np_(d), np_(ds), equal_nan=True)
+    finally:
+        h.close()
+
+
+def test_graph_replay_reads_live_inputs(B):
+    import torch
+    batch = _mini_batch()[:3]
+    params = B.preset("small")
+    h = B.Handle(0)
+    try:
+        first = [(np_(d), np_(m)) for d, m in B.stereo_match_batched(batch, params, handle=h)]
+        for _ in range(3):
+            again = B.stereo_match_batched(batch, params, handle=h)   # graph replay
+            torch.cuda.synchronize()
+            for (d0, m0), (d1, m1) in zip(first, again):
+                assert np.array_equal(m0, np_(m1))
+                assert np.array_equal(d0, np_(d1), equal_nan=True)
+        # same pointers, new image contents: the replay must see them
+        batch[0]["right"].copy_(torch.roll(batch[0]["right"], 1, dims=1))
+        d1, m1 = B.stereo_match_batched(batch, params, handle=h)[0]
+        ds, ms = B.stereo_match(batch[0]["left"], batch[0]["right"], batch[0]["dmin"],
+                                batch[0]["dmax"], batch[0]["win"], params, handle=h)
+        assert np.array_equal(np_(m1), np_(ms))
+        assert np.array_equal(np_(d1), np_(ds), equal_nan=True)
+    finally:
+        h.close()
+
+
+def test_matcher_variants_bit_identical(B):
+    p = synth.make_pair(130, 700, 95, 77)
+    L, R = cu(p["left"]), cu(p["right"])
+    h = B.Handle(0)
+    try:
+        ref = None
+        for v in range(B.st_num_variants()):
+            B.st_set_variant(v, handle=h)
+            got = [np_(t) for t in B.st_match_wta(L, R, 0, 95, 11, handle=h)]
+            if ref is None:
+                ref = got
+            for a, b in zip(ref, got):
+                assert np.array_equal(a, b), B.st_variant_name(v)
+    finally:
+        h.close()
+
+
+def test_uneven_batch_of_64(B):
+    """The 64-pair batch of four shapes, 32..192 candidates, 7x7 and 11x11:
+    spot-check 8 pairs against the per-pair path."""
+    import torch
+    batch = synth.c4_batch()
+    pairs = [{"left": cu(q["left"]), "right": cu(q["right"]), "dmin": q["dmin"], "dmax": q["dmax"],
+              "win": q["win"]} for q in batch]
+    params = B.preset("full")
+    h = B.Handle(0)
+    try:
+        outs = B.stereo_match_batched(pairs, params, handle=h)
+        torch.cuda.synchronize()
+        for i in range(0, 64, 8):
+            q = pairs[i]
+            ds, ms = B.stereo_match(q["left"], q["right"], q["dmin"], q["dmax"], q["win"], params,
+                                    handle=h)
+            assert np.array_equal(np_(outs[i][1]), np_(ms)), i
+            assert np.array_equal(np_(outs[i][0]), np_(ds), equal_nan=True), i
+    finally:
+        h.close()

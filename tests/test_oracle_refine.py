@@ -80,3 +80,20 @@ def test_autograd_gradient_matches_central_differences(orc):
         assert g[y, x] == pytest.approx(fd, rel=1e-5, abs=1e-7)
         checked += 1
     assert checked > 30
+
+
+def test_local_energy_differences_equal_global(orc):
+    L, R = _pair(8)
+    H, W = L.shape
+    r = np.random.default_rng(9)
+    d = 4.0 + r.uniform(-0.8, 0.8, size=(H, W))
+    valid = np.ones((H, W), np.uint8)
+    valid[:, :7] = 0
+    valid[r.random((H, W)) < 0.05] = 0
+    for (y, x) in zip(r.integers(0, H, 25), r.integers(0, W, 25)):
+        dp = d.copy(); dp[y, x] += 0.01
+        dm = d.copy(); dm[y, x] -= 0.013
+        g = orc.refine_energy(L, R, dp, valid, 5, 0.1) - orc.refine_energy(L, R, dm, valid, 5, 0.1)
+        lo = (orc.refine_energy_local(L, R, dp, valid, 5, 0.1, x, y) -
+              orc.refine_energy_local(L, R, dm, valid, 5, 0.1, x, y))
+        assert lo == pytest.approx(g, abs=1e-9)
