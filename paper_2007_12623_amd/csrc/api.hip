@@ -51,8 +51,7 @@ static st_status fail(st_status s, const char *fmt, ...) {
 struct Variant {
   int DC, TY;
 };
-static const Variant kVariants[] = {{16, 4}, {16, 8}, {16, 16}, {16, 32},
-                                    {8, 4},  {8, 8},  {8, 16},  {8, 32}};
+static const Variant kVariants[] = {{8, 2}, {8, 4}, {8, 8}, {8, 16}, {8, 32}, {8, 64}};
 static const int kNumVariants = (int)(sizeof kVariants / sizeof kVariants[0]);
 
 // ---------------------------------------------------------------- handle
@@ -65,12 +64,16 @@ struct BatchCache {
   std::vector<st_pair> pairs;
   st_params params{};
   int variant = -2;
-  // what the matcher launch of this batch needs, for stereo_time_matcher
+  // what the matcher launches of this batch need, for stereo_time_matcher:
+  // one persistent launch per window size present in the batch
+  struct Group {
+    int win, off, ntasks, nblocks;
+  };
+  std::vector<Group> groups;
   MatchPair *tM = nullptr;
   int4 *tT = nullptr;
   int *tC = nullptr;
-  int ntasks = 0, DC = 16, prec = 0, nblocks = 0;
-  long long evals = 0;
+  int prec = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   DevBuf ws, keys, tables;
@@ -753,10 +756,7 @@ st_status stereo_match_batched(st_handle h, const st_pair *pairs, int n_pairs,
   }
   drop_batch(B);
   // one disparity chunk size for the whole launch, band height per pair
-  int minD = 256;
-  for (int i = 0; i < n_pairs; ++i) minD = std::min(minD, pairs[i].dmax - pairs[i].dmin + 1);
-  int DC = minD >= 16 ? 16 : 8;
-  if (vforce >= 0) DC = std::min(DC, variant_DC(vforce));
+  const int DC = 8;
   std::vector<MatchPair> M(n_pairs);
   std::vector<PrepPair> Pp(n_pairs);
   std::vector<PostPair> Q(n_pairs);
@@ -786,9 +786,9 @@ st_status stereo_match_batched(st_handle h, const st_pair *pairs, int n_pairs,
   if (rc) return rc;
   rc = grow(h, B.keys, 4 * ktotal, true);
   if (rc) return rc;
-  // task queue: (pair, group, chunk), longest first (rows in the band)
-  std::vector<int4> tasks;
-  std::vector<int> cost;
+  // task queues, one per window size: (pair, group, chunk), longest first
+  std::map<int, std::vector<std::pair<int, int4>>> byw;
+  std::map<int, long long> wcost;
   for (int i = 0; i < n_pairs; ++i) {
     const MatchPair &P = M[i];
     const int hh = P.win / 2;
@@ -796,21 +796,33 @@ st_status stereo_match_batched(st_handle h, const st_pair *pairs, int n_pairs,
       const int band = g / P.nspan;
       const int rows = std::min(P.TY, P.H - hh - (hh + band * P.TY));
       for (int c = 0; c < P.nchunk; ++c) {
-        tasks.push_back(make_int4(i, g, c, 0));
-        cost.push_back(rows + hh + 1);
+        byw[P.win].push_back({rows + hh + 1, make_int4(i, g, c, 0)});
+        wcost[P.win] += rows + hh + 1;
       }
     }
   }
-  std::vector<int> order(tasks.size());
-  for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
-  std::vector<int4> sorted(tasks.size());
-  for (size_t i = 0; i < order.size(); ++i) sorted[i] = tasks[order[i]];
+  std::vector<int> wins;
+  for (auto &kv : byw) wins.push_back(kv.first);
+  std::sort(wins.begin(), wins.end(), [&](int a, int b) { return wcost[a] > wcost[b]; });
+  std::vector<int4> sorted;
+  std::vector<BatchCache::Group> groups;
+  for (int w : wins) {
+    auto &v = byw[w];
+    std::stable_sort(v.begin(), v.end(), [](const std::pair<int, int4> &a,
+                                            const std::pair<int, int4> &b) { return a.first > b.first; });
+    BatchCache::Group gr;
+    gr.win = w;
+    gr.off = (int)sorted.size();
+    gr.ntasks = (int)v.size();
+    gr.nblocks = h->ncu * std::max(1, match_persistent_occupancy(w, prec));
+    for (auto &e : v) sorted.push_back(e.second);
+    groups.push_back(gr);
+  }
   // device tables
   Carve c;
   const size_t tM = c.take(sizeof(MatchPair) * n_pairs), tP = c.take(sizeof(PrepPair) * n_pairs),
                tQ = c.take(sizeof(PostPair) * n_pairs), tT = c.take(sizeof(int4) * sorted.size()),
-               tC = c.take(16), tTot = c.take(0);
+               tC = c.take(4 * groups.size() + 16), tTot = c.take(0);
   rc = grow(h, B.tables, tTot, false);
   if (rc) return rc;
   for (int i = 0; i < n_pairs; ++i) {
@@ -824,16 +836,16 @@ st_status stereo_match_batched(st_handle h, const st_pair *pairs, int n_pairs,
   HIPCK(hipMemcpy(at<void>(B.tables.p, tQ), Q.data(), sizeof(PostPair) * n_pairs, hipMemcpyHostToDevice));
   HIPCK(hipMemcpy(at<void>(B.tables.p, tT), sorted.data(), sizeof(int4) * sorted.size(), hipMemcpyHostToDevice));
   // resident waves of the persistent matcher
-  const int per_cu = std::max(1, match_persistent_occupancy(DC, prec));
-  const int nblocks = h->ncu * per_cu;
   // capture the whole sequence once, replay it on later calls
   hipStream_t cs = h->cap_stream;
   HIPCK(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
   hipError_t e = hipSuccess;
   auto ck = [&](hipError_t x) { if (x != hipSuccess && e == hipSuccess) e = x; };
   ck(launch_prep(Pp[0], at<PrepPair>(B.tables.p, tP), n_pairs, maxH, maxCols, maxW, prec, cs));
-  ck(launch_match_persistent(at<MatchPair>(B.tables.p, tM), at<int4>(B.tables.p, tT), (int)sorted.size(),
-                             at<int>(B.tables.p, tC), DC, prec, nblocks, cs, nullptr, nullptr));
+  for (size_t gi = 0; gi < groups.size(); ++gi)
+    ck(launch_match_persistent(at<MatchPair>(B.tables.p, tM), at<int4>(B.tables.p, tT) + groups[gi].off,
+                               groups[gi].ntasks, at<int>(B.tables.p, tC) + gi, groups[gi].win, prec,
+                               groups[gi].nblocks, cs, nullptr, nullptr));
   PostLaunch L;
   L.one = Q[0];
   L.many = at<PostPair>(B.tables.p, tQ);
@@ -860,10 +872,8 @@ st_status stereo_match_batched(st_handle h, const st_pair *pairs, int n_pairs,
   B.tM = at<MatchPair>(B.tables.p, tM);
   B.tT = at<int4>(B.tables.p, tT);
   B.tC = at<int>(B.tables.p, tC);
-  B.ntasks = (int)sorted.size();
-  B.DC = DC;
+  B.groups = groups;
   B.prec = prec;
-  B.nblocks = nblocks;
   B.pairs.assign(pairs, pairs + n_pairs);
   B.params = *params;
   B.variant = vforce;
@@ -886,12 +896,16 @@ st_status stereo_time_matcher(st_handle h, const st_pair *pairs, int n_pairs,
   double total = 0.0;
   hipError_t e = hipSuccess;
   for (int r = 0; r < reps && e == hipSuccess; ++r) {
-    // the counter reset is a separate tiny kernel ahead of the timed launch
-    e = launch_match_persistent(B.tM, B.tT, B.ntasks, B.tC, B.DC, B.prec, B.nblocks, s, e0, e1);
-    if (e == hipSuccess) e = hipEventSynchronize(e1);
-    float ms = 0.0f;
-    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-    total += ms;
+    // each counter reset is a one-lane kernel ahead of its timed launch
+    for (size_t gi = 0; gi < B.groups.size() && e == hipSuccess; ++gi) {
+      const BatchCache::Group &g = B.groups[gi];
+      e = launch_match_persistent(B.tM, B.tT + g.off, g.ntasks, B.tC + gi, g.win, B.prec,
+                                  g.nblocks, s, e0, e1);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.0f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      total += ms;
+    }
   }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
@@ -993,13 +1007,13 @@ static int pick_variant(st_handle h, int H, int W, int win, int dmin, int dmax, 
   if (h->variant >= 0 && variant_DC(h->variant) <= D) return h->variant;
   auto it = h->tune.find(tune_key(H, W, win, dmin, dmax, prec));
   if (it != h->tune.end() && variant_DC(it->second) <= D) return it->second;
-  const int DC = D >= 16 ? 16 : 8;
-  const int tys[4] = {32, 16, 8, 4};
-  for (int i = 0; i < 4; ++i) {
+  const int DC = 8;
+  const int tys[5] = {64, 32, 16, 8, 4};
+  for (int i = 0; i < 5; ++i) {
     MatchPair P;
     make_geom(P, H, W, win, dmin, dmax, DC, tys[i]);
     const long long waves = (long long)P.nspan * P.nband * P.nchunk;
-    if (waves >= 8LL * h->ncu || i == 3) {
+    if (waves >= 8LL * h->ncu || i == 4) {
       for (int v = 0; v < kNumVariants; ++v)
         if (kVariants[v].DC == DC && kVariants[v].TY == tys[i]) return v;
     }

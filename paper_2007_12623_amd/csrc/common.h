@@ -94,11 +94,12 @@ __host__ __device__ inline int ceil_div(int a, int b) { return (a + b - 1) / b; 
 hipError_t launch_prep(const PrepPair &one, const PrepPair *many, int npairs, int maxH,
                        int maxCols, int maxW, int prec, hipStream_t s);
 hipError_t launch_match(const MatchPair &P, int prec, hipStream_t s);
-// ev0/ev1 (may be null) are recorded on s just before and after the matcher
+// One persistent matcher launch over the tasks of one window size; ev0/ev1
+// (may be null) are recorded on s just before and after it.
 hipError_t launch_match_persistent(const MatchPair *pairs_dev, const int4 *tasks_dev, int ntasks,
-                                   int *counter_dev, int DC, int prec, int nblocks, hipStream_t s,
+                                   int *counter_dev, int win, int prec, int nblocks, hipStream_t s,
                                    hipEvent_t ev0, hipEvent_t ev1);
-int match_persistent_occupancy(int DC, int prec);  // resident blocks per CU
+int match_persistent_occupancy(int win, int prec);  // resident blocks per CU
 hipError_t launch_window_stats_dense(const uint8_t *img, int H, int W, int pitch, int win,
                                      int32_t *S, int32_t *SS, float *inv, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, int N, uint32_t v, hipStream_t s);

@@ -3,21 +3,21 @@
 // a square window).  The paper's kernel gives one thread per pixel and
 // caches image rows in shared memory; this one is laid out for gfx950:
 //
-//  * a wave owns a span of 64*8 columns, one chunk of DC disparities and a
+//  * a wave owns a span of 64*8 columns, one chunk of 8 disparities and a
 //    band of rows; lane l owns columns x0 .. x0+7 (x0 = xs + 8 l);
 //  * vertical window sums V(c, d) = sum_v n(L-128)(c, y+v) * R(c-d, y+v) are
 //    running sums in registers: one v_dot2_i32_i16 adds the entering row and
 //    removes the leaving one;
-//  * horizontal window sums slide along the lane's 8 columns; the h columns
-//    on either side come from the neighbouring lanes through DPP wave shifts
-//    (so lanes 0 and 63 only serve as halos);
+//  * horizontal window sums come from prefix sums over the lane's 8 columns;
+//    the h columns on either side arrive as one partial sum from each
+//    neighbouring lane through the LDS crossbar (lanes 0 and 63 are halos);
 //  * the ZNCC numerator n*S_LR - S_L*S_R is exact in int32 (24-bit mads);
 //    normalisation by the FP64-computed 1/sqrt(varN) happens in fp32;
 //  * the winner-take-all key is z + 2 in fp32 with the disparity index in the
 //    4 low mantissa bits, so one v_max3 updates a running argmax with two
 //    candidates; invalid candidates carry NaN, which v_max ignores;
 //  * right-reference maxima accumulate along the diagonals x - d and are
-//    merged across lanes with DPP before a global atomic max;
+//    merged across neighbouring lanes before a global atomic max;
 //  * partial results of the disparity chunks merge through 32-bit atomic
 //    max on keys (quantised z, then 255 - (d - dmin)).
 #include "common.h"
@@ -25,11 +25,14 @@
 namespace st {
 
 // ---------------------------------------------------------------- helpers
-__device__ __forceinline__ int from_left(int v) {   // lane i receives lane i-1 (wave_shr:1)
-  return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xF, 0xF, true);
+// Neighbour-lane values through the LDS crossbar (ds_bpermute): the LDS pipe
+// is otherwise idle in this kernel, so the exchange costs no VALU issue slots.
+// Lane 0 reads lane 63 and back; both are halo lanes whose outputs are unused.
+__device__ __forceinline__ int from_left(int v) {   // lane i receives lane i-1
+  return __builtin_amdgcn_ds_bpermute(((int)__lane_id() - 1) << 2, v);
 }
-__device__ __forceinline__ int from_right(int v) {  // lane i receives lane i+1 (wave_shl:1)
-  return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xF, 0xF, true);
+__device__ __forceinline__ int from_right(int v) {  // lane i receives lane i+1
+  return __builtin_amdgcn_ds_bpermute(((int)__lane_id() + 1) << 2, v);
 }
 __device__ __forceinline__ float from_left(float v) {
   return __builtin_bit_cast(float, from_left(__builtin_bit_cast(int, v)));
@@ -196,7 +199,7 @@ __device__ __forceinline__ void match_task(const MatchPair &P, int y0, int y1, i
         for (int c = 0; c < K; ++c) V[j][c] = IM::dot(lp[c], rp[c - j + DC - 1], V[j][c]);
     }
 
-    // ---- per-row statistics
+    // ---- per-row statistics: left pixels of the lane, right columns of the segment
     int nsl[K];
     float il[K];
     {
@@ -208,19 +211,16 @@ __device__ __forceinline__ void match_task(const MatchPair &P, int y0, int y1, i
         il[c] = halo ? __builtin_nanf("") : iv[c];
       }
     }
-    const int32_t *srp = P.SR + (size_t)y * P.strideR + colR;
-    const float *irp = P.invR + (size_t)y * P.strideR + colR;
-
-    // ---- horizontal sums at the lane's first column
-    Acc S[DC];
+    int sr[T];
+    float ir[T];
+    {
+      const int32_t *srp = P.SR + (size_t)y * P.strideR + colR;
+      const float *irp = P.invR + (size_t)y * P.strideR + colR;
 #pragma unroll
-    for (int j = 0; j < DC; ++j) {
-      Acc s = V[j][0];
-#pragma unroll
-      for (int c = 1; c <= H; ++c) s += V[j][c];
-#pragma unroll
-      for (int c = K - H; c < K; ++c) s += from_left(V[j][c]);
-      S[j] = s;
+      for (int t = 0; t < T; ++t) {
+        sr[t] = srp[t];
+        ir[t] = irp[t];
+      }
     }
 
     float bestL[K];
@@ -230,29 +230,41 @@ __device__ __forceinline__ void match_task(const MatchPair &P, int y0, int y1, i
 #pragma unroll
     for (int t = 0; t < T; ++t) Pd[t] = 0.0f;
 
-    // ---- diagonal sweep: diagonal t holds the evaluations (i, j) with
-    //      i - j + DC - 1 = t, all of which share right column x0 - d0 + t - DC + 1
+    // ---- per chunk disparity j: horizontal window sums of the lane's
+    //      columns (own columns through prefix sums; the h columns beyond each
+    //      side as one partial sum from the neighbouring lane: suffix sums of
+    //      the left lane, prefix sums of the right lane), then the keys.
+    //      Evaluation (i, j) uses right column t = i - j + DC - 1.
 #pragma unroll
-    for (int t = 0; t < T; ++t) {
-      const int sr = srp[t];
-      const float ir = irp[t];
+    for (int j = 0; j < DC; ++j) {
+      Acc Pf[K + 1];
+      Pf[0] = 0;
 #pragma unroll
-      for (int j = 0; j < DC; ++j) {
-        const int i = t - (DC - 1) + j;
-        if (i < 0 || i >= K) continue;
-        if (i > 0) {
-          const int ca = i + H, cs = i - H - 1;
-          Acc add = ca < K ? V[j][ca] : from_right(V[j][ca - K]);
-          Acc sub = cs >= 0 ? V[j][cs] : from_left(V[j][cs + K]);
-          S[j] = S[j] + add - sub;
-        }
+      for (int c = 0; c < K; ++c) Pf[c + 1] = c == 0 ? V[j][0] : Pf[c] + V[j][c];
+      Acc Sf[H + 1];
+      Sf[0] = 0;
+#pragma unroll
+      for (int k = 1; k <= H; ++k) Sf[k] = k == 1 ? V[j][K - 1] : Sf[k - 1] + V[j][K - k];
+      Acc hl[H + 1], hr[H + 1];
+#pragma unroll
+      for (int k = 1; k <= H; ++k) {
+        hl[k] = from_left(Sf[k]);
+        hr[k] = from_right(Pf[k]);
+      }
+#pragma unroll
+      for (int i = 0; i < K; ++i) {
+        const int lo = i - H, hi = i + H + 1;   // own columns [max(lo,0), min(hi,K))
+        Acc Sij = (lo > 0) ? Pf[hi < K ? hi : K] - Pf[lo] : Pf[hi < K ? hi : K];
+        if (lo < 0) Sij = Sij + hl[-lo];
+        if (hi > K) Sij = Sij + hr[hi - K];
+        const int t = i - j + DC - 1;
         int num;
         if constexpr (PREC == P_I16) {
-          num = s24(nsl[i]) * s24(sr) + S[j];
+          num = s24(nsl[i]) * s24(sr[t]) + Sij;
         } else {
-          num = s24((int)S[j]) * n + s24(nsl[i]) * s24(sr);
+          num = s24((int)Sij) * n + s24(nsl[i]) * s24(sr[t]);
         }
-        const float zl = (float)num * ir;
+        const float zl = (float)num * ir[t];
         float zq;
         if constexpr (PREC == P_I16) {
           zq = __builtin_fmaf(zl, il[i], 2.0f);
@@ -322,9 +334,10 @@ __global__ __launch_bounds__(64) void match_kernel(MatchPair P, int ngroups) {
   match_task<WIN, DC, PREC>(P, y0, y1, xs, d0, threadIdx.x);
 }
 
-// Persistent form: waves pull tasks (pair, group, chunk) from a queue until
-// it is empty.  Every wave reaches the exit once the counter passes ntasks.
-template <int DC, int PREC>
+// Persistent form: waves pull tasks (pair, group, chunk) of one window size
+// from a queue until it is empty.  Every wave reaches the exit once the
+// counter passes ntasks.
+template <int WIN, int DC, int PREC>
 __global__ __launch_bounds__(64) void match_persistent_kernel(const MatchPair *pairs,
                                                               const int4 *tasks, int ntasks,
                                                               int *counter) {
@@ -338,15 +351,7 @@ __global__ __launch_bounds__(64) void match_persistent_kernel(const MatchPair *p
     const MatchPair P = pairs[tk.x];
     int y0, y1, xs, d0;
     task_coords(P, tk.y, tk.z, y0, y1, xs, d0);
-    switch (P.win) {
-      case 3: match_task<3, DC, PREC>(P, y0, y1, xs, d0, lane); break;
-      case 5: match_task<5, DC, PREC>(P, y0, y1, xs, d0, lane); break;
-      case 7: match_task<7, DC, PREC>(P, y0, y1, xs, d0, lane); break;
-      case 9: match_task<9, DC, PREC>(P, y0, y1, xs, d0, lane); break;
-      case 11: match_task<11, DC, PREC>(P, y0, y1, xs, d0, lane); break;
-      case 13: match_task<13, DC, PREC>(P, y0, y1, xs, d0, lane); break;
-      default: match_task<15, DC, PREC>(P, y0, y1, xs, d0, lane); break;
-    }
+    match_task<WIN, DC, PREC>(P, y0, y1, xs, d0, lane);
   }
 }
 
@@ -495,48 +500,63 @@ static hipError_t launch_match_w(const MatchPair &P, hipStream_t s) {
 }
 
 hipError_t launch_match(const MatchPair &P, int prec, hipStream_t s) {
-  if (P.DC == 16) {
-    if (prec == P_I16) return launch_match_w<16, P_I16>(P, s);
-    if (prec == P_F16) return launch_match_w<16, P_F16>(P, s);
-    return launch_match_w<16, P_BF16>(P, s);
-  }
+  if (P.DC != 8) return hipErrorInvalidValue;
   if (prec == P_I16) return launch_match_w<8, P_I16>(P, s);
   if (prec == P_F16) return launch_match_w<8, P_F16>(P, s);
   return launch_match_w<8, P_BF16>(P, s);
 }
 
+template <int WIN>
+static void launch_pw(const MatchPair *pairs_dev, const int4 *tasks_dev, int ntasks, int *counter,
+                      int prec, int nblocks, hipStream_t s) {
+  if (prec == P_I16)
+    hipLaunchKernelGGL((match_persistent_kernel<WIN, 8, P_I16>), dim3(nblocks), dim3(64), 0, s, pairs_dev, tasks_dev, ntasks, counter);
+  else if (prec == P_F16)
+    hipLaunchKernelGGL((match_persistent_kernel<WIN, 8, P_F16>), dim3(nblocks), dim3(64), 0, s, pairs_dev, tasks_dev, ntasks, counter);
+  else
+    hipLaunchKernelGGL((match_persistent_kernel<WIN, 8, P_BF16>), dim3(nblocks), dim3(64), 0, s, pairs_dev, tasks_dev, ntasks, counter);
+}
+
+// One persistent launch over the tasks of one window size.
 hipError_t launch_match_persistent(const MatchPair *pairs_dev, const int4 *tasks_dev, int ntasks,
-                                   int *counter_dev, int DC, int prec, int nblocks,
+                                   int *counter_dev, int win, int prec, int nblocks,
                                    hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, counter_dev);
-  if (ev0) hipEventRecord(ev0, s);
-#define PK(dc, pr)                                                                         \
-  hipLaunchKernelGGL((match_persistent_kernel<dc, pr>), dim3(nblocks), dim3(64), 0, s, pairs_dev, \
-                     tasks_dev, ntasks, counter_dev)
-  if (DC == 16) {
-    if (prec == P_I16) PK(16, P_I16); else if (prec == P_F16) PK(16, P_F16); else PK(16, P_BF16);
-  } else {
-    if (prec == P_I16) PK(8, P_I16); else if (prec == P_F16) PK(8, P_F16); else PK(8, P_BF16);
+  if (ev0) (void)hipEventRecord(ev0, s);
+  switch (win) {
+    case 3: launch_pw<3>(pairs_dev, tasks_dev, ntasks, counter_dev, prec, nblocks, s); break;
+    case 5: launch_pw<5>(pairs_dev, tasks_dev, ntasks, counter_dev, prec, nblocks, s); break;
+    case 7: launch_pw<7>(pairs_dev, tasks_dev, ntasks, counter_dev, prec, nblocks, s); break;
+    case 9: launch_pw<9>(pairs_dev, tasks_dev, ntasks, counter_dev, prec, nblocks, s); break;
+    case 11: launch_pw<11>(pairs_dev, tasks_dev, ntasks, counter_dev, prec, nblocks, s); break;
+    case 13: launch_pw<13>(pairs_dev, tasks_dev, ntasks, counter_dev, prec, nblocks, s); break;
+    default: launch_pw<15>(pairs_dev, tasks_dev, ntasks, counter_dev, prec, nblocks, s); break;
   }
-#undef PK
-  if (ev1) hipEventRecord(ev1, s);
+  if (ev1) (void)hipEventRecord(ev1, s);
   return hipGetLastError();
 }
 
-int match_persistent_occupancy(int DC, int prec) {
+template <int WIN>
+static int occ_w(int prec) {
   int n = 0;
   hipError_t e;
-  if (DC == 16) {
-    if (prec == P_I16) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, match_persistent_kernel<16, P_I16>, 64, 0);
-    else if (prec == P_F16) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, match_persistent_kernel<16, P_F16>, 64, 0);
-    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, match_persistent_kernel<16, P_BF16>, 64, 0);
-  } else {
-    if (prec == P_I16) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, match_persistent_kernel<8, P_I16>, 64, 0);
-    else if (prec == P_F16) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, match_persistent_kernel<8, P_F16>, 64, 0);
-    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, match_persistent_kernel<8, P_BF16>, 64, 0);
-  }
+  if (prec == P_I16) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, match_persistent_kernel<WIN, 8, P_I16>, 64, 0);
+  else if (prec == P_F16) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, match_persistent_kernel<WIN, 8, P_F16>, 64, 0);
+  else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, match_persistent_kernel<WIN, 8, P_BF16>, 64, 0);
   if (e != hipSuccess) { (void)hipGetLastError(); return 4; }
   return n;
+}
+
+int match_persistent_occupancy(int win, int prec) {
+  switch (win) {
+    case 3: return occ_w<3>(prec);
+    case 5: return occ_w<5>(prec);
+    case 7: return occ_w<7>(prec);
+    case 9: return occ_w<9>(prec);
+    case 11: return occ_w<11>(prec);
+    case 13: return occ_w<13>(prec);
+    default: return occ_w<15>(prec);
+  }
 }
 
 hipError_t launch_prep(const PrepPair &one, const PrepPair *many, int npairs, int maxH,

@@ -31,11 +31,15 @@ def test_forward_matches_oracle(B, orc, win, lam):
     L, R, d, v = _small()
     E, Z = B.stereo_refine_forward(cu(L), cu(R), cu(d), cu(v), win, lam, want_z=True)
     Eo, Zo = orc.refine_energy(L, R, d.astype(np.float64), v, win, lam, want_z=True)
-    assert float(E.item()) == pytest.approx(Eo, rel=1e-10, abs=1e-9)
     Zg = np_(Z)
     fin = ~np.isnan(Zo)
     assert np.array_equal(~np.isnan(Zg), fin)
+    dz = np.abs(Zg[fin] - Zo[fin])
+    k = int(np.argmax(dz))
+    print(f"max |dZ| {dz.max():.3g} at {np.argwhere(fin)[k]}, Z {Zo[fin][k]:.9f}; "
+          f"E {float(E.item()):.12g} vs {Eo:.12g}")
     np.testing.assert_allclose(Zg[fin], Zo[fin], atol=2e-7)
+    assert float(E.item()) == pytest.approx(Eo, rel=1e-10, abs=1e-9)
 
 
 @pytest.mark.parametrize("win,lam", [(5, 0.1), (7, 0.0), (11, 0.5)])
