@@ -359,6 +359,50 @@ __global__ void box_h_kernel(PostPair one, const PostPair *many, int R, int seg,
   }
 }
 
+// Row box sums through LDS: one block per row stages the row, takes an
+// inclusive prefix sum and writes out(x) = P(min(x+R, W-1)) - P(x-R-1),
+// with coalesced loads and stores.  Rows up to BOXH_MAXW wide.
+constexpr int BOXH_MAXW = 4096;
+template <bool B>
+__global__ __launch_bounds__(256) void box_h_lds_kernel(PostPair one, const PostPair *many, int R,
+                                                        int in, int out) {
+  PAIR;
+  __shared__ double row[BOXH_MAXW];
+  __shared__ double part[256];
+  const int y = blockIdx.x;
+  const int H = P.H, W = P.W;
+  if (y >= H) return;
+  const size_t N = (size_t)W * H;
+  const double *src = P.f + in * N + (size_t)y * W;
+  double *dst = P.f + out * N + (size_t)y * W;
+  const int t = threadIdx.x;
+  for (int x = t; x < W; x += 256) row[x] = src[x];
+  __syncthreads();
+  // each thread scans a contiguous segment, then the segment totals
+  const int per = ceil_div(W, 256);
+  const int x0 = min(t * per, W), x1 = min(x0 + per, W);
+  double acc = 0.0;
+  for (int x = x0; x < x1; ++x) {
+    acc += row[x];
+    row[x] = acc;
+  }
+  part[t] = acc;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    const double v = t >= off ? part[t - off] : 0.0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  const double base = t ? part[t - 1] : 0.0;
+  for (int x = x0; x < x1; ++x) row[x] += base;
+  __syncthreads();
+  for (int x = t; x < W; x += 256) {
+    const int a = min(x + R, W - 1), b = x - R - 1;
+    dst[x] = row[a] - (b >= 0 ? row[b] : 0.0);
+  }
+}
+
 // a = A(s) = box(s m) / box(m) on valid pixels (Eq. 1)
 template <bool B>
 __global__ void hc_a_kernel(PostPair one, const PostPair *many, int src) {
@@ -439,8 +483,11 @@ static void box2d(const PostLaunch &L, int R, int in, int out) {
   const int seg = 32;
   LAUNCH(box_v_kernel, dim3(ceil_div(L.maxW, 64), ceil_div(L.maxH, seg), L.npairs), dim3(64), R,
          seg, in, F_TMP);
-  LAUNCH(box_h_kernel, dim3(ceil_div(L.maxH, 64), ceil_div(L.maxW, seg), L.npairs), dim3(64), R,
-         seg, F_TMP, out);
+  if (L.maxW <= BOXH_MAXW)
+    LAUNCH(box_h_lds_kernel, dim3(L.maxH, 1, L.npairs), dim3(256), R, F_TMP, out);
+  else
+    LAUNCH(box_h_kernel, dim3(ceil_div(L.maxH, 64), ceil_div(L.maxW, seg), L.npairs), dim3(64), R,
+           seg, F_TMP, out);
 }
 
 // Improved Laplacian smoothing of (ob[src], delta, mb[src]) or s_in; writes
