@@ -243,6 +243,8 @@ static PairLayout layout(const MatchPair &P, int prec, bool debug) {
   Lo.delta = c.take(4 * N);
   Lo.pc = c.take(4 * (size_t)P.H * (P.W + 1));
   Lo.ps = c.take(4 * (size_t)P.H * (P.W + 1));
+  // the smoothing's FP64 planes; before the smoothing starts the same bytes
+  // hold the radial scans (8 x 4 bytes of nearest hits, 4 x 1 byte of runs)
   Lo.f = c.take(6 * 8 * N);
   if (debug) {
     Lo.dbg_mlr = c.take(N);
@@ -322,6 +324,8 @@ static void fill_views(const PairLayout &Lo, void *base, uint32_t *keys, MatchPa
   Q.pc = at<int32_t>(base, Lo.pc);
   Q.ps = at<int32_t>(base, Lo.ps);
   Q.f = at<double>(base, Lo.f);
+  Q.hits = at<uint32_t>(base, Lo.f);
+  Q.pass = at<uint8_t>(base, Lo.f + 32 * N);
 }
 
 // ---------------------------------------------------------------- pipeline
@@ -666,13 +670,16 @@ st_status st_radial_outlier(st_handle h, const int16_t *o, const uint8_t *m_in, 
   ARG(h, "NULL handle");
   hipSetDevice(h->device);
   const size_t N = (size_t)H * W;
-  HIPCK(grow(h, h->ws, 2 * N + 256, false) == ST_OK ? hipSuccess : hipErrorOutOfMemory);
+  Carve c;
+  const size_t ot = c.take(2 * N), pt = c.take(4 * N), tot = c.take(0);
+  HIPCK(grow(h, h->ws, tot, false) == ST_OK ? hipSuccess : hipErrorOutOfMemory);
   PostPair Q{};
   Q.H = H;
   Q.W = W;
   Q.ob[1] = const_cast<int16_t *>(o);
   Q.mb[1] = const_cast<uint8_t *>(m_in);
-  Q.ob[2] = (int16_t *)h->ws.p;
+  Q.ob[2] = at<int16_t>(h->ws.p, ot);
+  Q.pass = at<uint8_t>(h->ws.p, pt);
   Q.mb[2] = m_out;
   HIPCK(post_outlier(single_launch(Q, (hipStream_t)stream), r, thresh, 1, 2));
   return ST_OK;
@@ -692,7 +699,7 @@ st_status st_fill(st_handle h, const int16_t *o_in, const uint8_t *m_in, int H, 
   const size_t N = (size_t)H * W;
   Carve c;
   const size_t ot = c.take(2 * N), mt = c.take(N), pc = c.take(4 * (size_t)H * (W + 1)),
-               ps = c.take(4 * (size_t)H * (W + 1)), tot = c.take(0);
+               ps = c.take(4 * (size_t)H * (W + 1)), ht = c.take(32 * N), tot = c.take(0);
   HIPCK(grow(h, h->ws, tot, false) == ST_OK ? hipSuccess : hipErrorOutOfMemory);
   PostPair Q{};
   Q.H = H;
@@ -705,6 +712,7 @@ st_status st_fill(st_handle h, const int16_t *o_in, const uint8_t *m_in, int H, 
   Q.mb[2] = m_out;
   Q.pc = at<int32_t>(h->ws.p, pc);
   Q.ps = at<int32_t>(h->ws.p, ps);
+  Q.hits = at<uint32_t>(h->ws.p, ht);
   HIPCK(post_fill(single_launch(Q, (hipStream_t)stream), radial_r, min_lines, disk_r, min_frac, 0, 1, 2));
   return ST_OK;
 }

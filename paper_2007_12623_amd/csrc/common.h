@@ -48,6 +48,8 @@ struct PostPair {
   double *zbest, *zm, *zp;             // may be null
   float *delta;
   int32_t *pc, *ps;                    // row prefix sums, H x (W+1)
+  uint32_t *hits;                      // 8 planes: nearest valid pixel per direction
+  uint8_t *pass;                       // 4 planes: outlier runs per line type
   double *f;                           // 6 smoothing planes of H x W
   const float *s_in;                   // optional smoothing input (stage entry)
   float *disparity;

@@ -4,6 +4,8 @@
 // not depend on scheduling.  Integer results are exact; smoothing runs in
 // FP64.  Each kernel serves one pair (descriptor by value) or a batch (table
 // in device memory, pair = blockIdx.z).
+#include <algorithm>
+
 #include "common.h"
 
 namespace st {
@@ -57,23 +59,81 @@ __global__ void fill_u32_kernel(uint32_t *p, int N, uint32_t v) {
 // n*S_LR - S_L*S_R, FP64 normalisation), then the parabola offset
 // delta = (zm - zp) / (2 (zm - 2 z0 + zp)) clamped to [-1/2, 1/2]; 0 at the
 // ends of the range, when a neighbour is missing or the curvature is >= 0.
+// A block covers 128 pixels of one row: it stages the window rows of the left
+// image and the right columns its disparities reach in LDS once, then every
+// thread slides a 3-value window over the right row for the three sums.
+constexpr int SP_TX = 128, SP_MAXWIN = 15;
 template <bool B>
-__global__ void subpixel_kernel(PostPair one, const PostPair *many) {
+__global__ __launch_bounds__(SP_TX) void subpixel_kernel(PostPair one, const PostPair *many) {
   PAIR;
-  PIX;
+  __shared__ uint8_t Ls[SP_MAXWIN][SP_TX + 16];
+  __shared__ uint8_t Rs[SP_MAXWIN][SP_TX + 256 + 24];
+  __shared__ int s_omin, s_omax;
+  const int tx = threadIdx.x;
+  const int x0 = blockIdx.x * SP_TX, y = blockIdx.y;
+  if (x0 >= P.W || y >= P.H) return;  // uniform per block
+  const int W = P.W, H = P.H, win = P.win, h = win / 2;
+  const int x = x0 + tx;
+  const bool in = x < W;
+  const size_t k = (size_t)y * W + x;
+  const bool valid = in && P.mb[0][k];
+  const int o = valid ? (int)P.ob[0][k] : 0;
+  if (tx == 0) {
+    s_omin = 1 << 30;
+    s_omax = -(1 << 30);
+  }
+  __syncthreads();
+  if (valid) {
+    atomicMin(&s_omin, o);
+    atomicMax(&s_omax, o);
+  }
+  __syncthreads();
+  const int omin = s_omin, omax = s_omax;
   const double qn = __builtin_nan("");
-  if (!P.mb[0][k]) {
+  if (omin <= omax) {
+    const int LW = SP_TX + 2 * h, RW = SP_TX + (omax - omin) + 2 + 2 * h;
+    const int lx0 = x0 - h, rx0 = x0 - omax - 1 - h;
+    for (int i = tx; i < win * LW; i += SP_TX) {
+      const int r = i / LW, c = i - r * LW;
+      const int gy = y - h + r, gx = lx0 + c;
+      Ls[r][c] = (gy >= 0 && gy < H && gx >= 0 && gx < W) ? P.left[(size_t)gy * P.pitch + gx] : 0;
+    }
+    for (int i = tx; i < win * RW; i += SP_TX) {
+      const int r = i / RW, c = i - r * RW;
+      const int gy = y - h + r, gx = rx0 + c;
+      Rs[r][c] = (gy >= 0 && gy < H && gx >= 0 && gx < W) ? P.right[(size_t)gy * P.pitch + gx] : 0;
+    }
+  }
+  __syncthreads();
+  if (!in) return;
+  if (!valid) {
     if (P.zbest) P.zbest[k] = qn;
     if (P.zm) P.zm[k] = qn;
     if (P.zp) P.zp[k] = qn;
     P.delta[k] = 0.0f;
     return;
   }
-  const int win = P.win, h = win / 2;
+  // Rs[v][q] holds R(y - h + v, x - h + u - o) for q = tx + u + omax + 1 - o
+  int sm = 0, s0 = 0, sp = 0;  // sums at d = o - 1, o, o + 1
+  const int qb = tx + omax + 1 - o;
+  for (int v = 0; v < win; ++v) {
+    const uint8_t *lr = &Ls[v][tx];
+    const uint8_t *rr = &Rs[v][qb];
+    int rprev = rr[-1], rcur = rr[0];
+    for (int u = 0; u < win; ++u) {
+      const int rnext = rr[u + 1];
+      const int l = lr[u];
+      sp += l * rprev;
+      s0 += l * rcur;
+      sm += l * rnext;
+      rprev = rcur;
+      rcur = rnext;
+    }
+  }
   const long long n = (long long)win * win;
-  const int o = P.ob[0][k];
   const long long sl = P.SL[k];
   const long long varL = n * (long long)P.SSL[k] - sl * sl;
+  const int slr[3] = {sm, s0, sp};
   double z[3];
   for (int q = 0; q < 3; ++q) {
     const int d = o + q - 1;
@@ -84,13 +144,7 @@ __global__ void subpixel_kernel(PostPair one, const PostPair *many) {
     const long long sr = P.SR[kr];
     const long long varR = n * (long long)P.SSR[kr] - sr * sr;
     if (varR <= 0) continue;
-    int slr = 0;
-    for (int v = -h; v <= h; ++v) {
-      const uint8_t *lr = P.left + (size_t)(y + v) * P.pitch + x - h;
-      const uint8_t *rr = P.right + (size_t)(y + v) * P.pitch + xr - h;
-      for (int u = 0; u < win; ++u) slr += (int)lr[u] * (int)rr[u];
-    }
-    const long long num = n * (long long)slr - sl * sr;
+    const long long num = n * (long long)slr[q] - sl * sr;
     z[q] = (double)num / sqrt((double)varL * (double)varR);
   }
   if (P.zbest) P.zbest[k] = z[1];
@@ -130,48 +184,174 @@ __global__ void lr_check_kernel(PostPair one, const PostPair *many, int tol, int
 
 __constant__ int c_dir8[8][2] = {{1, 0}, {-1, 0}, {0, 1}, {0, -1}, {1, 1}, {-1, -1}, {1, -1}, {-1, 1}};
 
-// ---------------------------------------------------------------- radial outliers
-// A valid pixel is kept if along at least one of the 8 radial directions
-// all of the next r pixels are inside the image and valid, and consecutive
-// disparities differ by less than thresh (Section II-B).
-template <bool B>
-__global__ void radial_outlier_kernel(PostPair one, const PostPair *many, int r, float thresh,
-                                      int src, int dst) {
-  PAIR;
-  PIX;
-  const int16_t *o = P.ob[src];
-  const uint8_t *m = P.mb[src];
-  const uint8_t mk = m[k];
-  P.ob[dst][k] = o[k];
-  if (!mk) { P.mb[dst][k] = 0; return; }
-  bool any = false;
-  for (int dir = 0; dir < 8 && !any; ++dir) {
-    const int ux = c_dir8[dir][0], uy = c_dir8[dir][1];
-    const int ex = x + r * ux, ey = y + r * uy;
-    if (ex < 0 || ex >= W || ey < 0 || ey >= H) continue;
-    int prev = o[k];
-    bool pass = true;
-    for (int s = 1; s <= r; ++s) {
-      const size_t q = (size_t)(y + s * uy) * W + (x + s * ux);
-      if (!m[q]) { pass = false; break; }
-      const int v = o[q];
-      const int dv = v - prev;
-      if (!((float)(dv < 0 ? -dv : dv) < thresh)) { pass = false; break; }
-      prev = v;
-    }
-    any = pass;
+// ---------------------------------------------------------------- radial line scans
+// The 8 radial directions come in 4 line types: rows, columns, diagonals
+// (x - y const) and anti-diagonals (x + y const); c_dir8[2t] steps forward
+// along a line of type t, c_dir8[2t+1] backward.  A thread owns one segment
+// of SEG positions of one line and scans it, plus a look-ahead of `reach`
+// positions, in both directions; segments are independent.
+constexpr int SEG = 64;
+
+struct LineGeom {
+  int x, y, dx, dy, len;
+};
+
+__device__ __forceinline__ int nlines(int t, int H, int W) {
+  return t == 0 ? H : (t == 1 ? W : W + H - 1);
+}
+__device__ __forceinline__ int maxlen(int t, int H, int W) {
+  return t == 0 ? W : (t == 1 ? H : min(W, H));
+}
+__device__ __forceinline__ LineGeom line_geom(int t, int l, int H, int W) {
+  LineGeom g;
+  if (t == 0) { g.x = 0; g.y = l; g.dx = 1; g.dy = 0; g.len = W; }
+  else if (t == 1) { g.x = l; g.y = 0; g.dx = 0; g.dy = 1; g.len = H; }
+  else if (t == 2) {  // x - y = l - (H - 1), step (1, 1)
+    const int c = l - (H - 1);
+    g.x = max(0, c); g.y = max(0, -c); g.dx = 1; g.dy = 1;
+    g.len = min(W - g.x, H - g.y);
+  } else {            // x + y = l, step (1, -1)
+    g.x = max(0, l - (H - 1)); g.y = min(l, H - 1); g.dx = 1; g.dy = -1;
+    g.len = min(W - g.x, g.y + 1);
   }
-  P.mb[dst][k] = any ? mk : 0;
+  return g;
 }
 
-// ---------------------------------------------------------------- hole filling
-// (i) radial: first valid pixel within R steps along each of the 8
-// directions; complete lines (both opposite directions hit) give
-// (va*sb + vb*sa)/(sa+sb); with >= min_lines complete lines the hole takes
-// their mean, an exact rational rounded half to even; code 2.
+// Thread index -> (line type, line, segment); false when out of range.
+__device__ __forceinline__ bool scan_task(int idx, int H, int W, int &t, int &l, int &sg) {
+  for (t = 0; t < 4; ++t) {
+    const int nl = nlines(t, H, W), ns = ceil_div(maxlen(t, H, W), SEG);
+    if (idx < nl * ns) {
+      sg = idx / nl;
+      l = idx - sg * nl;
+      return true;
+    }
+    idx -= nl * ns;
+  }
+  return false;
+}
+
+__device__ __forceinline__ int scan_tasks(int H, int W) {
+  int n = 0;
+  for (int t = 0; t < 4; ++t) n += nlines(t, H, W) * ceil_div(maxlen(t, H, W), SEG);
+  return n;
+}
+
+// Outlier runs: for direction u, run(p) = number of consecutive steps
+// p -> p+u -> ... that land on valid pixels whose disparity differs from the
+// previous one by less than thresh.  p passes u when run(p) >= r.  Writes
+// pass[t][p] = bit 0 (forward direction) | bit 1 (backward direction).
 template <bool B>
-__global__ void fill_radial_kernel(PostPair one, const PostPair *many, int R, int min_lines,
-                                   int src, int dst) {
+__global__ void outlier_scan_kernel(PostPair one, const PostPair *many, int r, float thresh, int src) {
+  PAIR;
+  const int H = P.H, W = P.W;
+  int t, l, sg;
+  if (!scan_task(blockIdx.x * blockDim.x + threadIdx.x, H, W, t, l, sg)) return;
+  const LineGeom g = line_geom(t, l, H, W);
+  const int a = sg * SEG;
+  if (a >= g.len) return;
+  const int b = min(g.len, a + SEG);
+  const int16_t *o = P.ob[src];
+  const uint8_t *m = P.mb[src];
+  const size_t N = (size_t)W * H;
+  uint8_t *pass = P.pass + (size_t)t * N;
+  const int lstep = g.dy * W + g.dx;
+  const long long base = (long long)g.y * W + g.x;
+  // forward: walk from the far end of the look-ahead towards a
+  {
+    const int e = min(g.len - 1, b - 1 + r);
+    int run = 0, onext = 0;
+    bool vnext = false;
+    for (int p = e; p >= a; --p) {
+      const long long k = base + (long long)p * lstep;
+      const int op = o[k];
+      if (p < e) {
+        const int dv = onext - op;
+        run = (vnext && (float)(dv < 0 ? -dv : dv) < thresh) ? min(run + 1, r) : 0;
+      }
+      if (p < b) pass[k] = run >= r ? 1 : 0;
+      onext = op;
+      vnext = m[k] != 0;
+    }
+  }
+  // backward
+  {
+    const int e = max(0, a - r);
+    int run = 0, oprev = 0;
+    bool vprev = false;
+    for (int p = e; p < b; ++p) {
+      const long long k = base + (long long)p * lstep;
+      const int op = o[k];
+      if (p > e) {
+        const int dv = oprev - op;
+        run = (vprev && (float)(dv < 0 ? -dv : dv) < thresh) ? min(run + 1, r) : 0;
+      }
+      if (p >= a && run >= r) pass[k] |= 2;
+      oprev = op;
+      vprev = m[k] != 0;
+    }
+  }
+}
+
+// A valid pixel stays when some direction passes (Section II-B).
+template <bool B>
+__global__ void outlier_combine_kernel(PostPair one, const PostPair *many, int src, int dst) {
+  PAIR;
+  PIX;
+  const size_t N = (size_t)W * H;
+  const uint8_t mk = P.mb[src][k];
+  P.ob[dst][k] = P.ob[src][k];
+  const bool any = (P.pass[k] | P.pass[N + k] | P.pass[2 * N + k] | P.pass[3 * N + k]) != 0;
+  P.mb[dst][k] = (mk && any) ? mk : 0;
+}
+
+// Nearest valid pixel within R steps in each direction of a line type:
+// hits[2t (+1)][p] = (steps << 16) | (uint16 disparity), 0 when none.
+template <bool B>
+__global__ void fill_scan_kernel(PostPair one, const PostPair *many, int R, int src) {
+  PAIR;
+  const int H = P.H, W = P.W;
+  int t, l, sg;
+  if (!scan_task(blockIdx.x * blockDim.x + threadIdx.x, H, W, t, l, sg)) return;
+  const LineGeom g = line_geom(t, l, H, W);
+  const int a = sg * SEG;
+  if (a >= g.len) return;
+  const int b = min(g.len, a + SEG);
+  const int16_t *o = P.ob[src];
+  const uint8_t *m = P.mb[src];
+  const size_t N = (size_t)W * H;
+  uint32_t *hf = P.hits + (size_t)(2 * t) * N, *hb = P.hits + (size_t)(2 * t + 1) * N;
+  const int lstep = g.dy * W + g.dx;
+  const long long base = (long long)g.y * W + g.x;
+  {
+    const int e = min(g.len - 1, b - 1 + R);
+    int q = -1;
+    uint32_t vq = 0;
+    for (int p = e; p >= a; --p) {
+      const long long k = base + (long long)p * lstep;
+      if (p < b) hf[k] = (q >= 0 && q - p <= R) ? ((uint32_t)(q - p) << 16) | vq : 0u;
+      if (m[k]) { q = p; vq = (uint16_t)o[k]; }
+    }
+  }
+  {
+    const int e = max(0, a - R);
+    int q = -1;
+    uint32_t vq = 0;
+    for (int p = e; p < b; ++p) {
+      const long long k = base + (long long)p * lstep;
+      if (p >= a) hb[k] = (q >= 0 && p - q <= R) ? ((uint32_t)(p - q) << 16) | vq : 0u;
+      if (m[k]) { q = p; vq = (uint16_t)o[k]; }
+    }
+  }
+}
+
+// (i) radial fill from the scanned hits: complete lines (both opposite
+// directions hit) give (va*sb + vb*sa)/(sa+sb); with >= min_lines complete
+// lines the hole takes their mean, an exact rational rounded half to even;
+// code 2.
+template <bool B>
+__global__ void fill_radial_kernel(PostPair one, const PostPair *many, int min_lines, int src,
+                                   int dst) {
   PAIR;
   PIX;
   const int16_t *o = P.ob[src];
@@ -179,28 +359,17 @@ __global__ void fill_radial_kernel(PostPair one, const PostPair *many, int R, in
   P.ob[dst][k] = o[k];
   P.mb[dst][k] = m[k];
   if (m[k]) return;
-  int v[8], s[8];
-  bool hit[8];
-  for (int dir = 0; dir < 8; ++dir) {
-    hit[dir] = false;
-    v[dir] = 0;
-    s[dir] = 0;
-    const int ux = c_dir8[dir][0], uy = c_dir8[dir][1];
-    for (int st = 1; st <= R; ++st) {
-      const int qx = x + st * ux, qy = y + st * uy;
-      if (qx < 0 || qx >= W || qy < 0 || qy >= H) break;
-      const size_t q = (size_t)qy * W + qx;
-      if (m[q]) { hit[dir] = true; v[dir] = o[q]; s[dir] = st; break; }
-    }
-  }
+  const size_t N = (size_t)W * H;
   long long num = 0, den = 1;
   int lines = 0;
-  for (int l = 0; l < 4; ++l) {
-    const int a = 2 * l, b = 2 * l + 1;
-    if (!(hit[a] && hit[b])) continue;
-    const long long ln = (long long)v[a] * s[b] + (long long)v[b] * s[a];
-    const long long ld = s[a] + s[b];
-    num = num * ld + ln * den;
+  for (int ln = 0; ln < 4; ++ln) {
+    const uint32_t ha = P.hits[(size_t)(2 * ln) * N + k], hb = P.hits[(size_t)(2 * ln + 1) * N + k];
+    if (!ha || !hb) continue;
+    const long long sa = ha >> 16, sb = hb >> 16;
+    const long long va = (int16_t)(ha & 0xFFFFu), vb = (int16_t)(hb & 0xFFFFu);
+    const long long lnum = va * sb + vb * sa;
+    const long long ld = sa + sb;
+    num = num * ld + lnum * den;
     den = den * ld;
     ++lines;
   }
@@ -459,21 +628,33 @@ hipError_t post_decode(const PostLaunch &L) {
   return hipGetLastError();
 }
 hipError_t post_subpixel(const PostLaunch &L) {
-  LAUNCH(subpixel_kernel, pixgrid(L), dim3(128));
+  LAUNCH(subpixel_kernel, dim3(ceil_div(L.maxW, SP_TX), L.maxH, L.npairs), dim3(SP_TX));
   return hipGetLastError();
 }
 hipError_t post_lr(const PostLaunch &L, int tol, int dst) {
   LAUNCH(lr_check_kernel, pixgrid(L), dim3(128), tol, dst);
   return hipGetLastError();
 }
+static dim3 scangrid(const PostLaunch &L) {
+  int n = 0;
+  for (int t = 0; t < 4; ++t) {
+    const int nl = t == 0 ? L.maxH : (t == 1 ? L.maxW : L.maxW + L.maxH - 1);
+    const int ml = t == 0 ? L.maxW : (t == 1 ? L.maxH : std::min(L.maxW, L.maxH));
+    n += nl * ceil_div(ml, SEG);
+  }
+  return dim3(ceil_div(n, 64), 1, L.npairs);
+}
+
 hipError_t post_outlier(const PostLaunch &L, int r, float thresh, int src, int dst) {
-  LAUNCH(radial_outlier_kernel, pixgrid(L), dim3(128), r, thresh, src, dst);
+  LAUNCH(outlier_scan_kernel, scangrid(L), dim3(64), r, thresh, src);
+  LAUNCH(outlier_combine_kernel, pixgrid(L), dim3(128), src, dst);
   return hipGetLastError();
 }
 // radial fill src -> tmp, disk fill tmp -> dst (dst may equal src)
 hipError_t post_fill(const PostLaunch &L, int radial_r, int min_lines, int disk_r, float frac,
                      int src, int tmp, int dst) {
-  LAUNCH(fill_radial_kernel, pixgrid(L), dim3(128), radial_r, min_lines, src, tmp);
+  LAUNCH(fill_scan_kernel, scangrid(L), dim3(64), radial_r, src);
+  LAUNCH(fill_radial_kernel, pixgrid(L), dim3(128), min_lines, src, tmp);
   LAUNCH(row_prefix_kernel, dim3(L.maxH, 1, L.npairs), dim3(256), tmp);
   LAUNCH(fill_disk_kernel, pixgrid(L), dim3(128), disk_r, frac, tmp, dst);
   return hipGetLastError();

@@ -9,7 +9,7 @@ edges, signed disparity ranges and every window size.
 import numpy as np
 import pytest
 
-from gpu_util import cu, dilate, np_, tie_mask
+from gpu_util import cu, np_, tie_mask
 from paper_2007_12623_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -135,8 +135,11 @@ def test_lr_check_stage(B, orc):
         assert np.array_equal(g, orc.lr_check(ref["oL"], ref["mL"], ref["oR"], ref["mR"], tol))
 
 
-def test_outlier_and_fill_stages(B, orc):
-    L, R = _pair(140, 330, 31, 42)
+@pytest.mark.parametrize("H,W", [(140, 330), (300, 70), (23, 700)])
+def test_outlier_and_fill_stages(B, orc, H, W):
+    """Rows, columns and both diagonals cut into 64-pixel scan segments:
+    shapes with lines shorter and longer than one segment."""
+    L, R = _pair(H, W, 31, 42)
     ref = orc.match(L, R, 0, 31, 7)
     m = orc.lr_check(ref["oL"], ref["mL"], ref["oR"], ref["mR"], 1)
     o = ref["oL"]
@@ -165,58 +168,92 @@ def test_hc_smooth_stage(B, orc, R, K):
     assert np.all(np.abs(g[v] - ref[v]) <= tol)
 
 
-def _end_to_end(B, orc, L, R, dmin, dmax, win, params_gpu, params_orc, dil):
+def _end_to_end(B, orc, L, R, dmin, dmax, win, params_gpu, params_orc):
+    """The whole GPU path, stage by stage: each stage of the oracle is run on
+    the GPU's own input to that stage and must give the GPU's output (masks
+    and integer disparities bit-exact, the smoothed disparities within
+    max(1e-5, 1 ulp)), so that a matcher near-tie, where two candidates are
+    equal up to rounding, cannot spread through the later stages unseen.
+    The agreement of the final masks with the oracle's own pipeline from the
+    images is reported and must stay above 99%."""
+    import torch
+    H, W = L.shape
     h = B.Handle(0)
     try:
         params_gpu.debug_outputs = 1
         disp, mask = B.stereo_match(cu(L), cu(R), dmin, dmax, win, params_gpu, handle=h)
         disp, mask = np_(disp), np_(mask)
-        H, W = L.shape
-        import torch
-        o_wta = np_(B.stereo_debug_get("o_wta", (H, W), torch.int16, handle=h))
-        dl = np_(B.stereo_debug_get("delta", (H, W), torch.float32, handle=h))
+
+        def get(name, dt):
+            return np_(B.stereo_debug_get(name, (H, W), dt, handle=h))
+        o_wta, m_wta = get("o_wta", torch.int16).astype(np.int32), get("m_wta", torch.uint8)
+        o_r, m_r = get("o_r", torch.int16).astype(np.int32), get("m_r", torch.uint8)
+        dl = get("delta", torch.float32).astype(np.float64)
+        m_lr = get("m_lr", torch.uint8)
+        o_post, m_post = get("o_post", torch.int16).astype(np.int32), get("m_post", torch.uint8)
     finally:
         h.close()
-    rdisp, rmask, inter = orc.pipeline(L, R, dmin, dmax, win, params_orc, intermediates=True)
+    po = params_orc
+    # matching: validity exact, winners exact away from near-ties
     ref = orc.match(L, R, dmin, dmax, win)
-    ties = tie_mask(ref["gap"]) & (ref["mL"] == 1)
-    # right-reference near ties affect the left pixels that look at them
-    tr = tie_mask(ref["gapR"]) & (ref["mR"] == 1)
-    Hh, Ww = L.shape
-    yy, xx = np.nonzero(ref["mL"] == 1)
-    xr = xx - ref["oL"][yy, xx]
-    okr = (xr >= 0) & (xr < Ww)
-    tl = np.zeros_like(ties)
-    tl[yy[okr], xx[okr]] = tr[yy[okr], xr[okr]]
-    near = dilate(ties | tl, dil)
-    far = ~near
-    assert np.array_equal(o_wta[(ref["mL"] == 1) & ~ties], ref["oL"][(ref["mL"] == 1) & ~ties])
-    assert np.array_equal(mask[far], rmask[far]), f"mask differs on {(mask[far] != rmask[far]).sum()} px"
-    v = far & (rmask > 0)
-    tol = np.maximum(1e-5, np.spacing(np.abs(rdisp[v]).astype(np.float32)).astype(np.float64))
-    bad = np.abs(disp[v] - rdisp[v]) > tol
-    assert not bad.any(), f"{bad.sum()} disparities differ, max {np.abs(disp[v] - rdisp[v]).max():.3g}"
+    assert np.array_equal(m_wta, ref["mL"]) and np.array_equal(m_r, ref["mR"])
+    sel = (ref["mL"] == 1) & ~tie_mask(ref["gap"])
+    assert np.array_equal(o_wta[sel], ref["oL"][sel])
+    selr = (ref["mR"] == 1) & ~tie_mask(ref["gapR"])
+    assert np.array_equal(o_r[selr], ref["oR"][selr])
+    # sub-pixel offsets where the winners agree
+    if po.subpixel:
+        dref = orc.subpixel(ref["oL"], ref["mL"], ref["zm"], ref["zbest"], ref["zp"], dmin, dmax)
+        sv = (m_wta == 1) & (o_wta == ref["oL"])
+        assert np.abs(dl[sv] - dref[sv]).max() <= 1e-5
+    else:
+        dl = np.zeros_like(dl)
+    # left-right check on the GPU's two winner maps
+    mlr_ref = orc.lr_check(o_wta, m_wta, o_r, m_r, po.lr_tol) if po.lr_check else m_wta
+    assert np.array_equal(m_lr, mlr_ref)
+    # outlier removal / hole filling alternations from the GPU's checked map
+    o, m = o_wta.copy(), m_lr.copy()
+    fill = dict(radial_r=po.fill_radial_r, min_lines=po.fill_min_lines, disk_r=po.fill_disk_r,
+                min_frac=float(np.float32(po.fill_disk_frac)))
+    if po.radial_iters <= 0:
+        o, m = orc.fill(o, m, **fill)
+    for it in range(po.radial_iters):
+        m = orc.radial_outlier(o, m, po.radial_r0 + it * po.radial_dr, po.radial_thresh)
+        o, m = orc.fill(o, m, **fill)
+    assert np.array_equal(m_post, m), f"masks differ on {(m_post != m).sum()} px"
+    assert np.array_equal(o_post[m > 0], o[m > 0])
+    # smoothing of o + delta
+    s = np.where(m == 1, o + dl, o.astype(np.float64))
+    if po.smooth_iters > 0:
+        dref = orc.hc_smooth(s, m, po.smooth_radius, po.smooth_iters,
+                             float(np.float32(po.smooth_alpha)))
+    else:
+        dref = s
+    assert np.array_equal(mask, m)
+    v = m > 0
+    assert np.isnan(disp[~v]).all()
+    tol = np.maximum(1e-5, np.spacing(np.abs(dref[v]).astype(np.float32)).astype(np.float64))
+    bad = np.abs(disp[v] - dref[v]) > tol
+    assert not bad.any(), f"{bad.sum()} disparities differ, max {np.abs(disp[v] - dref[v]).max():.3g}"
+    # whole path against the oracle's pipeline from the images
+    rdisp, rmask = orc.pipeline(L, R, dmin, dmax, win, po)
     agree = (mask == rmask).mean()
-    assert agree > 0.995
-    if params_orc.subpixel:
-        sv = (inter["m_wta"] == 1) & (o_wta == inter["o_wta"])
-        assert np.abs(dl[sv] - inter["delta"][sv]).max() <= 1e-5
-    return far.mean()
+    both = (mask > 0) & (rmask > 0)
+    close = (np.abs(disp[both] - rdisp[both]) <= 1e-4).mean()
+    print(f"final masks agree on {agree:.5f} of pixels; disparities within 1e-4 on {close:.5f}")
+    assert agree > 0.99
 
 
 def test_end_to_end_small_workload(B, orc):
     p = synth.c1_pair()
-    frac = _end_to_end(B, orc, p["left"], p["right"], 0, 31, 7, B.preset("small"),
-                       orc.params_c1(), dil=60)
-    assert frac > 0.5
+    _end_to_end(B, orc, p["left"], p["right"], 0, 31, 7, B.preset("small"), orc.params_c1())
 
 
 def test_end_to_end_full_pipeline(B, orc):
     """960x540 / 128 / 11x11 with 3 outlier-fill alternations and R=15, K=3."""
     seq = synth.c2_sequence(1)
-    frac = _end_to_end(B, orc, seq[0]["left"], seq[0]["right"], 0, 127, 11, B.preset("full"),
-                       orc.params_c2(), dil=130)
-    assert frac > 0.3
+    _end_to_end(B, orc, seq[0]["left"], seq[0]["right"], 0, 127, 11, B.preset("full"),
+                orc.params_c2())
 
 
 def test_pipeline_options(B, orc):
@@ -224,4 +261,4 @@ def test_pipeline_options(B, orc):
     L, R = _pair(100, 260, 31, 51)
     pg = B.preset("small", lr_check=0, subpixel=0, radial_iters=2, radial_r0=3, radial_dr=2)
     po = orc.params_c1(lr_check=0, subpixel=0, radial_iters=2, radial_r0=3, radial_dr=2)
-    _end_to_end(B, orc, L, R, 0, 31, 7, pg, po, dil=40)
+    _end_to_end(B, orc, L, R, 0, 31, 7, pg, po)

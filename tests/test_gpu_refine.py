@@ -30,7 +30,8 @@ def _small(seed=5):
 def test_forward_matches_oracle(B, orc, win, lam):
     L, R, d, v = _small()
     E, Z = B.stereo_refine_forward(cu(L), cu(R), cu(d), cu(v), win, lam, want_z=True)
-    Eo, Zo = orc.refine_energy(L, R, d.astype(np.float64), v, win, lam, want_z=True)
+    lam32 = float(np.float32(lam))   # the library takes lambda as a float
+    Eo, Zo = orc.refine_energy(L, R, d.astype(np.float64), v, win, lam32, want_z=True)
     Zg = np_(Z)
     fin = ~np.isnan(Zo)
     assert np.array_equal(~np.isnan(Zg), fin)
@@ -47,7 +48,7 @@ def test_backward_matches_autograd(B, win, lam):
     from oracle import refine_autograd as ra
     L, R, d, v = _small(6)
     g = np_(B.stereo_refine_backward(cu(L), cu(R), cu(d), cu(v), win, lam))
-    _, gr = ra.energy_and_grad(L, R, d.astype(np.float64), v, win, lam)
+    _, gr = ra.energy_and_grad(L, R, d.astype(np.float64), v, win, float(np.float32(lam)))
     np.testing.assert_allclose(g, gr, rtol=1e-4, atol=1e-5)
 
 
