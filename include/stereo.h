@@ -210,9 +210,9 @@ st_status st_hc_smooth(st_handle h, const float *s, const uint8_t *m, int H, int
 
 /* ---- tuning ---- */
 
-/* Time the matcher's tile variants (band height, disparities per lane) for
- * one problem shape on the handle's device and remember the fastest for
- * that (win, disparity-count bucket, width bucket, precision).  The table
+/* Time the matcher's tile variants (band height, disparity chunks per
+ * workgroup) for one problem shape on the handle's device and remember the
+ * fastest for that (win, disparity-count bucket, width bucket, precision).  The table
  * is saved to / loaded from the JSON file named by the environment variable
  * STEREO_TUNE_CACHE when it is set.  *best_cfg (host, may be NULL) receives
  * the chosen variant id. */
@@ -230,7 +230,8 @@ st_status stereo_time_matcher(st_handle h, const st_pair *pairs, int n_pairs,
  * Variant ids are 0..st_num_variants()-1. */
 st_status st_set_variant(st_handle h, int variant);
 int st_num_variants(void);
-/* Host string describing variant v ("DC=16,TY=8"), "" if out of range. */
+/* Host string describing variant v ("TY=16,CG=8": band height, disparity
+ * chunks of 8 per workgroup), "" if out of range. */
 const char *st_variant_name(int v);
 
 /* Build information (host string). */

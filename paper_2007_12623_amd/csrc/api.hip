@@ -48,10 +48,14 @@ static st_status fail(st_status s, const char *fmt, ...) {
   } while (0)
 
 // ---------------------------------------------------------------- variants
+// Matcher tilings: band height TY and chunks per workgroup task CG, in the
+// order the default choice prefers them (fewer key merges and fewer
+// vertical-sum restarts first).  Every disparity chunk is 8 wide.
 struct Variant {
-  int DC, TY;
+  int TY, CG;
 };
-static const Variant kVariants[] = {{8, 2}, {8, 4}, {8, 8}, {8, 16}, {8, 32}, {8, 64}};
+static const Variant kVariants[] = {{16, 16}, {16, 8}, {8, 16}, {8, 8}, {16, 4},
+                                    {8, 4},   {16, 2}, {8, 2},  {4, 4}, {4, 2}};
 static const int kNumVariants = (int)(sizeof kVariants / sizeof kVariants[0]);
 
 // ---------------------------------------------------------------- handle
@@ -68,6 +72,7 @@ struct BatchCache {
   // one persistent launch per window size present in the batch
   struct Group {
     int win, off, ntasks, nblocks;
+    size_t lds;
   };
   std::vector<Group> groups;
   MatchPair *tM = nullptr;
@@ -163,7 +168,8 @@ static int round_up(int v, int m) { return ((v + m - 1) / m) * m; }
 static int pmod(int a, int m) { return ((a % m) + m) % m; }
 
 // Spans, bands, chunks and plane padding of one pair for the matcher.
-static void make_geom(MatchPair &P, int H, int W, int win, int dmin, int dmax, int DC, int TY) {
+static void make_geom(MatchPair &P, int H, int W, int win, int dmin, int dmax, int DC, int TY,
+                      int CG) {
   const int h = win / 2, K = KC;
   P.H = H;
   P.W = W;
@@ -192,6 +198,13 @@ static void make_geom(MatchPair &P, int H, int W, int win, int dmin, int dmax, i
   P.padR = round_up(std::max(0, -Rmin), 4);
   P.strideR = round_up(P.padR + std::max(W, Rmax), 16);
   P.first_task = 0;
+  // chunk groups and the right key tile: 512 + 7 + (d0 of the group's last
+  // chunk - d0 of its first) columns in slots of rp, rp = 4 (mod 8)
+  P.CG = std::max(1, std::min(CG, P.nchunk));
+  P.ncg = ceil_div(P.nchunk, P.CG);
+  const int rw = WV * KC + (DC - 1) + DC * (P.CG - 1);
+  P.rp = ceil_div(rw, 8);
+  P.rp += (4 - P.rp % 8 + 8) % 8;
 }
 
 static int pick_variant(st_handle h, int H, int W, int win, int dmin, int dmax, int prec);
@@ -375,8 +388,9 @@ static hipError_t post_stages(const PostLaunch &L, const st_params &p, const Deb
   return e;
 }
 
-static int variant_DC(int v) { return kVariants[v].DC; }
 static int variant_TY(int v) { return kVariants[v].TY; }
+static int variant_CG(int v) { return kVariants[v].CG; }
+static constexpr int kDC = 8;
 
 extern "C" {
 
@@ -411,7 +425,7 @@ int st_num_variants(void) { return kNumVariants; }
 const char *st_variant_name(int v) {
   static thread_local char buf[64];
   if (v < 0 || v >= kNumVariants) return "";
-  snprintf(buf, sizeof buf, "DC=%d,TY=%d", kVariants[v].DC, kVariants[v].TY);
+  snprintf(buf, sizeof buf, "TY=%d,CG=%d", kVariants[v].TY, kVariants[v].CG);
   return buf;
 }
 
@@ -475,7 +489,7 @@ static st_status setup_single(st_handle h, const uint8_t *left, const uint8_t *r
                               int pitch, int dmin, int dmax, int win, int prec, int variant,
                               bool debug, MatchPair &M, PrepPair &Pp, PostPair &Q, PairLayout &Lo,
                               hipStream_t s) {
-  make_geom(M, H, W, win, dmin, dmax, variant_DC(variant), variant_TY(variant));
+  make_geom(M, H, W, win, dmin, dmax, kDC, variant_TY(variant), variant_CG(variant));
   Lo = layout(M, prec, debug);
   st_status rc = grow(h, h->ws, Lo.total, false);
   if (rc) return rc;
@@ -774,12 +788,12 @@ st_status stereo_match_batched(st_handle h, const st_pair *pairs, int n_pairs,
   int maxH = 0, maxW = 0, maxCols = 0;
   for (int i = 0; i < n_pairs; ++i) {
     const st_pair &q = pairs[i];
-    int TY = vforce >= 0 ? variant_TY(vforce) : 32;
+    int v = vforce >= 0 ? vforce : 0;
     if (vforce < 0) {
       auto it = h->tune.find("batched");
-      if (it != h->tune.end()) TY = variant_TY(it->second);
+      if (it != h->tune.end()) v = it->second;
     }
-    make_geom(M[i], q.H, q.W, q.win, q.dmin, q.dmax, DC, TY);
+    make_geom(M[i], q.H, q.W, q.win, q.dmin, q.dmax, DC, variant_TY(v), variant_CG(v));
     Lo[i] = layout(M[i], prec, false);
     total = (total + 255) & ~(size_t)255;
     base[i] = total;
@@ -794,18 +808,23 @@ st_status stereo_match_batched(st_handle h, const st_pair *pairs, int n_pairs,
   if (rc) return rc;
   rc = grow(h, B.keys, 4 * ktotal, true);
   if (rc) return rc;
-  // task queues, one per window size: (pair, group, chunk), longest first
+  // task queues, one per window size: (pair, group, chunk group), longest
+  // first; the cost counts rows evaluated plus vertical-sum restarts
   std::map<int, std::vector<std::pair<int, int4>>> byw;
   std::map<int, long long> wcost;
+  std::map<int, size_t> wlds;
   for (int i = 0; i < n_pairs; ++i) {
     const MatchPair &P = M[i];
     const int hh = P.win / 2;
+    wlds[P.win] = std::max(wlds[P.win], match_lds_bytes(P));
     for (int g = 0; g < P.nband * P.nspan; ++g) {
       const int band = g / P.nspan;
       const int rows = std::min(P.TY, P.H - hh - (hh + band * P.TY));
-      for (int c = 0; c < P.nchunk; ++c) {
-        byw[P.win].push_back({rows + hh + 1, make_int4(i, g, c, 0)});
-        wcost[P.win] += rows + hh + 1;
+      for (int c = 0; c < P.ncg; ++c) {
+        const int nc = std::min(P.CG, P.nchunk - c * P.CG);
+        const int cost = nc * (rows + 2 * hh);
+        byw[P.win].push_back({cost, make_int4(i, g, c, 0)});
+        wcost[P.win] += cost;
       }
     }
   }
@@ -822,7 +841,8 @@ st_status stereo_match_batched(st_handle h, const st_pair *pairs, int n_pairs,
     gr.win = w;
     gr.off = (int)sorted.size();
     gr.ntasks = (int)v.size();
-    gr.nblocks = h->ncu * std::max(1, match_persistent_occupancy(w, prec));
+    gr.lds = wlds[w];
+    gr.nblocks = h->ncu * match_persistent_occupancy(w, prec, gr.lds);
     for (auto &e : v) sorted.push_back(e.second);
     groups.push_back(gr);
   }
@@ -853,7 +873,7 @@ st_status stereo_match_batched(st_handle h, const st_pair *pairs, int n_pairs,
   for (size_t gi = 0; gi < groups.size(); ++gi)
     ck(launch_match_persistent(at<MatchPair>(B.tables.p, tM), at<int4>(B.tables.p, tT) + groups[gi].off,
                                groups[gi].ntasks, at<int>(B.tables.p, tC) + gi, groups[gi].win, prec,
-                               groups[gi].nblocks, cs, nullptr, nullptr));
+                               groups[gi].nblocks, groups[gi].lds, cs, nullptr, nullptr));
   PostLaunch L;
   L.one = Q[0];
   L.many = at<PostPair>(B.tables.p, tQ);
@@ -908,7 +928,7 @@ st_status stereo_time_matcher(st_handle h, const st_pair *pairs, int n_pairs,
     for (size_t gi = 0; gi < B.groups.size() && e == hipSuccess; ++gi) {
       const BatchCache::Group &g = B.groups[gi];
       e = launch_match_persistent(B.tM, B.tT + g.off, g.ntasks, B.tC + gi, g.win, B.prec,
-                                  g.nblocks, s, e0, e1);
+                                  g.nblocks, g.lds, s, e0, e1);
       if (e == hipSuccess) e = hipEventSynchronize(e1);
       float ms = 0.0f;
       if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
@@ -1009,24 +1029,24 @@ static std::string tune_key(int H, int W, int win, int dmin, int dmax, int prec)
 }
 
 // Variant used when nothing is forced: the tuned one for this shape bucket,
-// else the largest band height that still gives every SIMD two waves.
+// else the first in preference order that gives every CU two workgroups.
 static int pick_variant(st_handle h, int H, int W, int win, int dmin, int dmax, int prec) {
-  const int D = dmax - dmin + 1;
-  if (h->variant >= 0 && variant_DC(h->variant) <= D) return h->variant;
+  if (h->variant >= 0) return h->variant;
   auto it = h->tune.find(tune_key(H, W, win, dmin, dmax, prec));
-  if (it != h->tune.end() && variant_DC(it->second) <= D) return it->second;
-  const int DC = 8;
-  const int tys[5] = {64, 32, 16, 8, 4};
-  for (int i = 0; i < 5; ++i) {
+  if (it != h->tune.end()) return it->second;
+  int best = 0;
+  long long best_n = -1;
+  for (int v = 0; v < kNumVariants; ++v) {
     MatchPair P;
-    make_geom(P, H, W, win, dmin, dmax, DC, tys[i]);
-    const long long waves = (long long)P.nspan * P.nband * P.nchunk;
-    if (waves >= 8LL * h->ncu || i == 4) {
-      for (int v = 0; v < kNumVariants; ++v)
-        if (kVariants[v].DC == DC && kVariants[v].TY == tys[i]) return v;
+    make_geom(P, H, W, win, dmin, dmax, kDC, variant_TY(v), variant_CG(v));
+    const long long n = (long long)P.nspan * P.nband * P.ncg;
+    if (n >= 2LL * h->ncu) return v;
+    if (n > best_n) {
+      best_n = n;
+      best = v;
     }
   }
-  return 0;
+  return best;
 }
 
 static void save_tune(st_handle h) {
@@ -1090,14 +1110,12 @@ extern "C" st_status st_autotune(st_handle h, int H, int W, int dmin, int dmax, 
   HIPCK(hipMalloc(&dimg, 2 * N));
   hipError_t e = hipMemcpy(dimg, img.data(), 2 * N, hipMemcpyHostToDevice);
   if (e != hipSuccess) { hipFree(dimg); HIPCK(e); }
-  const int D = dmax - dmin + 1;
   int best = -1;
   double best_ms = 1e30;
   hipEvent_t e0, e1;
   hipEventCreate(&e0);
   hipEventCreate(&e1);
   for (int v = 0; v < kNumVariants; ++v) {
-    if (variant_DC(v) > D) continue;
     MatchPair M;
     PrepPair Pp;
     PostPair Q;

@@ -8,6 +8,7 @@ namespace st {
 constexpr int WV = 64;        // wavefront size on gfx950
 constexpr int KC = 8;         // image columns owned by one lane of the matcher
 constexpr int OUT_LANES = 62; // lanes 1..62 of a wave produce output; 0 and 63 are halos
+constexpr int NWAVE = 4;      // waves of a matcher workgroup
 
 enum Prec { P_I16 = 0, P_F16 = 1, P_BF16 = 2 };
 
@@ -30,6 +31,8 @@ struct MatchPair {
   int32_t strideL, padL, strideR, padR;
   int32_t xs0;          // first column of lane 0 of span 0
   int32_t nspan, nband, nchunk, TY, DC;
+  int32_t CG, ncg;      // chunks per workgroup task, chunk groups
+  int32_t rp;           // slot stride of the right key tile (4 mod 8)
   int32_t first_task;   // index of this pair's first task in a batched queue
 };
 
@@ -99,9 +102,11 @@ hipError_t launch_match(const MatchPair &P, int prec, hipStream_t s);
 // One persistent matcher launch over the tasks of one window size; ev0/ev1
 // (may be null) are recorded on s just before and after it.
 hipError_t launch_match_persistent(const MatchPair *pairs_dev, const int4 *tasks_dev, int ntasks,
-                                   int *counter_dev, int win, int prec, int nblocks, hipStream_t s,
-                                   hipEvent_t ev0, hipEvent_t ev1);
-int match_persistent_occupancy(int win, int prec);  // resident blocks per CU
+                                   int *counter_dev, int win, int prec, int nblocks, size_t lds,
+                                   hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
+// resident matcher workgroups per CU with `lds` bytes of key tiles each
+int match_persistent_occupancy(int win, int prec, size_t lds);
+size_t match_lds_bytes(const MatchPair &P);  // key tiles of one workgroup
 hipError_t launch_window_stats_dense(const uint8_t *img, int H, int W, int pitch, int win,
                                      int32_t *S, int32_t *SS, float *inv, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, int N, uint32_t v, hipStream_t s);

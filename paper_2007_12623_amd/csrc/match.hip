@@ -17,9 +17,14 @@
 //    4 low mantissa bits, so one v_max3 updates a running argmax with two
 //    candidates; invalid candidates carry NaN, which v_max ignores;
 //  * right-reference maxima accumulate along the diagonals x - d and are
-//    merged across neighbouring lanes before a global atomic max;
-//  * partial results of the disparity chunks merge through 32-bit atomic
-//    max on keys (quantised z, then 255 - (d - dmin)).
+//    merged across neighbouring lanes;
+//  * a workgroup of 4 waves owns one (band, span) and a group of disparity
+//    chunks; its waves merge their keys (quantised z, then 255 - (d - dmin))
+//    with LDS atomic max into key tiles of the band, which go to global
+//    memory once per band: plain stores for the left keys when the group
+//    holds every chunk, one atomic max per right column otherwise.
+#include <algorithm>
+
 #include "common.h"
 
 namespace st {
@@ -90,23 +95,49 @@ __device__ __forceinline__ uint32_t global_key(float k, int dd0) {
   return 0x80000000u | (q << 8) | (uint32_t)(255 - (dd0 + j));
 }
 
-__device__ __forceinline__ void amax(uint32_t *p, uint32_t v) {
+// Explicit address spaces: loads through generic pointers become flat
+// instructions, which also count on the LDS wait counter, so every wait for
+// a crossbar exchange would wait for memory as well.
+#define GLOBAL __attribute__((address_space(1)))
+#define LDS __attribute__((address_space(3)))
+
+__device__ __forceinline__ void gmax(GLOBAL uint32_t *p, uint32_t v) {
   __hip_atomic_fetch_max(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ __forceinline__ void lmax(LDS uint32_t *p, uint32_t v) {
+  __hip_atomic_fetch_max(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
 
-// Load N dwords from a 4-byte aligned address.
+// Key tiles of one workgroup task in LDS.
+//   left:  key of lane l, column c of row r at lt[r*8*LTP + c*LTP + l]
+//   right: tile column q (image column rbase + q) of row r at
+//          rt[r*8*rp + (q & 7)*rp + (q >> 3)]
+// LTP and rp are 4 (mod 8): a wave's atomics (lanes at consecutive slots)
+// and the write-out (threads at consecutive columns) are both free of bank
+// conflicts.
+constexpr int LTP = 68;
+struct KeyTile {
+  LDS uint32_t *lt;
+  LDS uint32_t *rt;
+  int rp, y0, rbase;
+};
+
+// Load N dwords at byte offset `off` (a multiple of 4) of a wave-uniform
+// base: the base stays in scalar registers and each lane keeps a 32-bit
+// offset.
 template <int N>
-__device__ __forceinline__ void load_dw(uint32_t (&dst)[N], const void *p) {
-  const uint32_t *q = (const uint32_t *)__builtin_assume_aligned(p, 4);
+__device__ __forceinline__ void load_dw(uint32_t (&dst)[N], const GLOBAL char *base, uint32_t off) {
+  const GLOBAL uint32_t *q = (const GLOBAL uint32_t *)(base + off);
 #pragma unroll
   for (int i = 0; i < N; ++i) dst[i] = q[i];
 }
 
-// Load N dwords starting `sh` bytes (0..3, uniform) after the 4-byte aligned
-// address p: one extra dword, then v_alignbyte per dword.
+// Load N dwords starting `sh` bytes (0..3, uniform) after byte offset `off`
+// (a multiple of 4): one extra dword, then v_alignbyte per dword.
 template <int N>
-__device__ __forceinline__ void load_dw_shifted(uint32_t (&dst)[N], const void *p, int sh) {
-  const uint32_t *q = (const uint32_t *)__builtin_assume_aligned(p, 4);
+__device__ __forceinline__ void load_dw_shifted(uint32_t (&dst)[N], const GLOBAL char *base,
+                                                uint32_t off, int sh) {
+  const GLOBAL uint32_t *q = (const GLOBAL uint32_t *)(base + off);
   uint32_t t[N + 1];
 #pragma unroll
   for (int i = 0; i <= N; ++i) t[i] = q[i];
@@ -115,10 +146,11 @@ __device__ __forceinline__ void load_dw_shifted(uint32_t (&dst)[N], const void *
 }
 
 // ---------------------------------------------------------------- one task
-// Rows [y0, y1) of the span starting at column xs, disparities d0 .. d0+DC-1.
+// Rows [y0, y1) of the span starting at column xs, disparities d0 .. d0+DC-1;
+// keys go to the workgroup's tiles.
 template <int WIN, int DC, int PREC>
-__device__ __forceinline__ void match_task(const MatchPair &P, int y0, int y1, int xs, int d0,
-                                           int lane) {
+__device__ __forceinline__ void match_rows(const MatchPair &P, int y0, int y1, int xs, int d0,
+                                           int lane, const KeyTile &kt) {
   constexpr int H = WIN / 2;
   constexpr int K = KC;
   constexpr int T = K + DC - 1;                 // R columns touched by a lane
@@ -134,10 +166,12 @@ __device__ __forceinline__ void match_task(const MatchPair &P, int y0, int y1, i
   const int colR = x0 - d0 - (DC - 1) + P.padR;
   const int rsh = (RB * colR) & 3;              // byte misalignment (wave-uniform)
   const bool halo = (lane == 0) || (lane == WV - 1);
-  const char *Lb = (const char *)P.Lp + 2 * (size_t)colL;
-  const char *NLb = (const char *)P.NLp + 2 * (size_t)colL;
-  const char *Rb = (const char *)P.Rp + (RB * (size_t)colR - rsh);
-  const size_t sL = 2 * (size_t)P.strideL, sR = RB * (size_t)P.strideR;
+  // planes are under 4 GiB: byte offsets of the lane's segments fit 32 bits
+  const GLOBAL char *Lg = (const GLOBAL char *)P.Lp;
+  const GLOBAL char *NLg = (const GLOBAL char *)P.NLp;
+  const GLOBAL char *Rg = (const GLOBAL char *)P.Rp;
+  const uint32_t Lo = 2u * (uint32_t)colL, Ro = (uint32_t)(RB * colR - rsh);
+  const uint32_t sL = 2u * (uint32_t)P.strideL, sR = (uint32_t)(RB * P.strideR);
 
   Acc V[DC][K];
 #pragma unroll
@@ -149,11 +183,11 @@ __device__ __forceinline__ void match_task(const MatchPair &P, int y0, int y1, i
   for (int r = y0 - H; r <= y0 + H; r += 2) {
     const bool two = r + 1 <= y0 + H;
     uint32_t la[NLD], lb[NLD], ra[NRD], rb[NRD];
-    load_dw(la, Lb + sL * r);
-    load_dw_shifted(ra, Rb + sR * r, rsh);
+    load_dw(la, Lg, Lo + sL * r);
+    load_dw_shifted(ra, Rg, Ro + sR * r, rsh);
     if (two) {
-      load_dw(lb, Lb + sL * (r + 1));
-      load_dw_shifted(rb, Rb + sR * (r + 1), rsh);
+      load_dw(lb, Lg, Lo + sL * (r + 1));
+      load_dw_shifted(rb, Rg, Ro + sR * (r + 1), rsh);
     } else {
 #pragma unroll
       for (int i = 0; i < NLD; ++i) lb[i] = 0;
@@ -174,17 +208,16 @@ __device__ __forceinline__ void match_task(const MatchPair &P, int y0, int y1, i
       for (int c = 0; c < K; ++c) V[j][c] = IM::dot(lp[c], rp[c - j + DC - 1], V[j][c]);
   }
 
-  const int W = P.W;
   const int dd0 = d0 - P.dmin;
   for (int y = y0; y < y1; ++y) {
     if (y > y0) {
       // entering row y+H (+), leaving row y-H-1 (-)
       const int ra_ = y + H, rl_ = y - H - 1;
       uint32_t la[NLD], lo[NLD], ra[NRD], ro[NRD];
-      load_dw(la, Lb + sL * ra_);
-      load_dw(lo, NLb + sL * rl_);
-      load_dw_shifted(ra, Rb + sR * ra_, rsh);
-      load_dw_shifted(ro, Rb + sR * rl_, rsh);
+      load_dw(la, Lg, Lo + sL * ra_);
+      load_dw(lo, NLg, Lo + sL * rl_);
+      load_dw_shifted(ra, Rg, Ro + sR * ra_, rsh);
+      load_dw_shifted(ro, Rg, Ro + sR * rl_, rsh);
       uint32_t lp[K], rp[T];
 #pragma unroll
       for (int c = 0; c < K; ++c) lp[c] = __builtin_amdgcn_perm(lo[c / 2], la[c / 2], sel16(c & 1));
@@ -203,8 +236,9 @@ __device__ __forceinline__ void match_task(const MatchPair &P, int y0, int y1, i
     int nsl[K];
     float il[K];
     {
-      const int32_t *ns = P.negSL + (size_t)y * P.strideL + colL;
-      const float *iv = P.invL + (size_t)y * P.strideL + colL;
+      const uint32_t o = 4u * (uint32_t)(y * P.strideL + colL);
+      const GLOBAL int32_t *ns = (const GLOBAL int32_t *)((const GLOBAL char *)P.negSL + o);
+      const GLOBAL float *iv = (const GLOBAL float *)((const GLOBAL char *)P.invL + o);
 #pragma unroll
       for (int c = 0; c < K; ++c) {
         nsl[c] = ns[c];
@@ -214,8 +248,9 @@ __device__ __forceinline__ void match_task(const MatchPair &P, int y0, int y1, i
     int sr[T];
     float ir[T];
     {
-      const int32_t *srp = P.SR + (size_t)y * P.strideR + colR;
-      const float *irp = P.invR + (size_t)y * P.strideR + colR;
+      const uint32_t o = 4u * (uint32_t)(y * P.strideR + colR);
+      const GLOBAL int32_t *srp = (const GLOBAL int32_t *)((const GLOBAL char *)P.SR + o);
+      const GLOBAL float *irp = (const GLOBAL float *)((const GLOBAL char *)P.invR + o);
 #pragma unroll
       for (int t = 0; t < T; ++t) {
         sr[t] = srp[t];
@@ -288,70 +323,128 @@ __device__ __forceinline__ void match_task(const MatchPair &P, int y0, int y1, i
 #pragma unroll
     for (int t = 0; t < DC - 1; ++t) Pd[t + K] = kmax(Pd[t + K], from_right(Pd[t]));
 
-    // ---- emit: left reference per pixel, right reference per home column
-    uint32_t *kl = P.keyL + (size_t)y * W + x0;
+    // ---- emit into the tiles: left reference per pixel, right reference
+    //      per home column (lane 0 also the 7 columns left of its home)
+    LDS uint32_t *lrow = kt.lt + (y - kt.y0) * (8 * LTP) + lane;
     if (!halo) {
 #pragma unroll
       for (int c = 0; c < K; ++c)
-        if (bestL[c] >= 0.5f) amax(kl + c, global_key(bestL[c], dd0));
+        if (bestL[c] >= 0.5f) lmax(lrow + c * LTP, global_key(bestL[c], dd0));
     }
-    uint32_t *kr = P.keyR + (size_t)y * W + (x0 - d0);
+    LDS uint32_t *rrow = kt.rt + (y - kt.y0) * (8 * kt.rp);
+    const int q0 = x0 - d0 - kt.rbase;  // tile column of home diagonal 0; q0 & 7 is wave-uniform
 #pragma unroll
     for (int m = 0; m < K; ++m)
-      if (Pd[m + DC - 1] >= 0.5f) amax(kr + m, global_key(Pd[m + DC - 1], dd0));
+      if (Pd[m + DC - 1] >= 0.5f) {
+        const int q = q0 + m;
+        lmax(rrow + (q & 7) * kt.rp + (q >> 3), global_key(Pd[m + DC - 1], dd0));
+      }
     if (lane == 0) {
 #pragma unroll
       for (int m = -(DC - 1); m < 0; ++m)
-        if (Pd[m + DC - 1] >= 0.5f) amax(kr + m, global_key(Pd[m + DC - 1], dd0));
+        if (Pd[m + DC - 1] >= 0.5f) {
+          const int q = q0 + m;
+          lmax(rrow + (q & 7) * kt.rp + (q >> 3), global_key(Pd[m + DC - 1], dd0));
+        }
     }
   }
 }
 
-// ---------------------------------------------------------------- task decode
-__device__ __forceinline__ void task_coords(const MatchPair &P, int g, int c, int &y0, int &y1,
-                                            int &xs, int &d0) {
-  const int h = P.win / 2;
+// ---------------------------------------------------------------- workgroup task
+// Band `g` (band * nspan + span) of a pair, chunk group `cg`: the chunks
+// cg*CG .. min((cg+1)*CG, nchunk)-1.  The 4 waves take (chunk, sub-band)
+// items in turn; with fewer chunks than waves the band is cut into
+// sub-bands so that every wave has work.
+template <int WIN, int DC, int PREC>
+__device__ __forceinline__ void wg_task(const MatchPair &P, int g, int cg, LDS uint32_t *lds) {
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & (WV - 1);
+  constexpr int NT = NWAVE * WV;
+  const int h = WIN / 2;
   const int band = g / P.nspan, span = g - band * P.nspan;
-  y0 = h + band * P.TY;
-  y1 = min(y0 + P.TY, P.H - h);
-  xs = P.xs0 + span * (OUT_LANES * KC);
+  const int y0 = h + band * P.TY;
+  const int y1 = min(y0 + P.TY, P.H - h);
+  const int rows = y1 - y0;
+  const int xs = P.xs0 + span * (OUT_LANES * KC);
   const int D = P.dmax - P.dmin + 1;
-  d0 = P.dmin + min(c * P.DC, D - P.DC);
+  const int cf = cg * P.CG, cl = min(cf + P.CG, P.nchunk) - 1, nc = cl - cf + 1;
+  const int d0f = P.dmin + min(cf * DC, D - DC), d0l = P.dmin + min(cl * DC, D - DC);
+  KeyTile kt;
+  kt.lt = lds;
+  kt.rt = lds + P.TY * 8 * LTP;
+  kt.rp = P.rp;
+  kt.y0 = y0;
+  kt.rbase = xs - d0l - (DC - 1);
+  const int RW = WV * KC + (DC - 1) + (d0l - d0f);  // right tile columns in use
+
+  for (int i = tid; i < rows * 8 * LTP; i += NT) kt.lt[i] = 0u;
+  for (int i = tid; i < rows * 8 * kt.rp; i += NT) kt.rt[i] = 0u;
+  __syncthreads();
+
+  const int SB = nc >= NWAVE ? 1 : NWAVE / nc;
+  const int TYs = ceil_div(rows, SB);
+  const int items = nc * SB;
+  for (int it = wave; it < items; it += NWAVE) {
+    const int c = cf + it % nc, sb = it / nc;
+    const int ya = y0 + sb * TYs, yb = min(ya + TYs, y1);
+    if (ya < yb) match_rows<WIN, DC, PREC>(P, ya, yb, xs, P.dmin + min(c * DC, D - DC), lane, kt);
+  }
+  __syncthreads();
+
+  // write-out: output columns xs+8 .. xs+503 of the left tile; every used
+  // column of the right tile
+  const bool whole = P.ncg == 1;
+  GLOBAL uint32_t *kl = (GLOBAL uint32_t *)P.keyL;
+  GLOBAL uint32_t *kr = (GLOBAL uint32_t *)P.keyR;
+  for (int r = 0; r < rows; ++r) {
+    const size_t rowoff = (size_t)(y0 + r) * P.W;
+    for (int xr = KC + tid; xr < (OUT_LANES + 1) * KC; xr += NT) {
+      const int x = xs + xr;
+      if (x < 0 || x >= P.W) continue;
+      const uint32_t v = kt.lt[r * 8 * LTP + (xr & 7) * LTP + (xr >> 3)];
+      if (whole) kl[rowoff + x] = v;
+      else if (v) gmax(kl + rowoff + x, v);
+    }
+    for (int q = tid; q < RW; q += NT) {
+      const uint32_t v = kt.rt[r * 8 * kt.rp + (q & 7) * kt.rp + (q >> 3)];
+      const int x = kt.rbase + q;
+      if (v && x >= 0 && x < P.W) gmax(kr + rowoff + x, v);
+    }
+  }
 }
 
-// One wave per task.  Blocks b with equal b % 8 run on one XCD; each XCD
-// gets whole (band, span) groups so that the chunks of a group share its L2.
+// One workgroup per task.  Blocks b with equal b % 8 run on one XCD; each
+// XCD gets whole (band, span) groups so that their chunk groups share its L2.
 template <int WIN, int DC, int PREC>
-__global__ __launch_bounds__(64) void match_kernel(MatchPair P, int ngroups) {
+__global__ __launch_bounds__(NWAVE * WV) __attribute__((amdgpu_waves_per_eu(2)))
+void match_kernel(MatchPair P, int ngroups) {
+  extern __shared__ uint32_t lds_dyn[];
   const int b = blockIdx.x;
   const int xcd = b & 7;
   const int r = b >> 3;
-  const int c = r % P.nchunk;
-  const int g = (r / P.nchunk) * 8 + xcd;
+  const int cg = r % P.ncg;
+  const int g = (r / P.ncg) * 8 + xcd;
   if (g >= ngroups) return;
-  int y0, y1, xs, d0;
-  task_coords(P, g, c, y0, y1, xs, d0);
-  match_task<WIN, DC, PREC>(P, y0, y1, xs, d0, threadIdx.x);
+  wg_task<WIN, DC, PREC>(P, g, cg, (LDS uint32_t *)lds_dyn);
 }
 
-// Persistent form: waves pull tasks (pair, group, chunk) of one window size
-// from a queue until it is empty.  Every wave reaches the exit once the
-// counter passes ntasks.
+// Persistent form: workgroups pull tasks (pair, group, chunk group) of one
+// window size from a queue until it is empty.  Every workgroup reaches the
+// exit once the counter passes ntasks.
 template <int WIN, int DC, int PREC>
-__global__ __launch_bounds__(64) void match_persistent_kernel(const MatchPair *pairs,
-                                                              const int4 *tasks, int ntasks,
-                                                              int *counter) {
-  const int lane = threadIdx.x;
+__global__ __launch_bounds__(NWAVE * WV) __attribute__((amdgpu_waves_per_eu(2)))
+void match_persistent_kernel(const MatchPair *__restrict__ pairs, const int4 *__restrict__ tasks,
+                             int ntasks, int *__restrict__ counter) {
+  extern __shared__ uint32_t lds_dyn[];
+  __shared__ int next;
   for (;;) {
-    int t = 0;
-    if (lane == 0) t = atomicAdd(counter, 1);
-    t = __builtin_amdgcn_readfirstlane(t);
+    // the previous task's barriers keep this store behind every read of `next`
+    if (threadIdx.x == 0) next = atomicAdd(counter, 1);
+    __syncthreads();
+    const int t = __builtin_amdgcn_readfirstlane(next);
     if (t >= ntasks) break;
     const int4 tk = tasks[t];
     const MatchPair P = pairs[tk.x];
-    int y0, y1, xs, d0;
-    task_coords(P, tk.y, tk.z, y0, y1, xs, d0);
-    match_task<WIN, DC, PREC>(P, y0, y1, xs, d0, lane);
+    wg_task<WIN, DC, PREC>(P, tk.y, tk.z, (LDS uint32_t *)lds_dyn);
   }
 }
 
@@ -477,11 +570,21 @@ __global__ __launch_bounds__(256) void window_stats_kernel(PrepPair one, const P
 }
 
 // ---------------------------------------------------------------- host launchers
+size_t match_lds_bytes(const MatchPair &P) { return 4 * (size_t)P.TY * 8 * (LTP + P.rp); }
+
+template <class F>
+static hipError_t allow_lds(F *kern, size_t bytes) {
+  return hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
 template <int WIN, int DC, int PREC>
 static hipError_t launch_match_t(const MatchPair &P, hipStream_t s) {
   const int ngroups = P.nband * P.nspan;
-  const int blocks = 8 * ceil_div(ngroups, 8) * P.nchunk;
-  hipLaunchKernelGGL((match_kernel<WIN, DC, PREC>), dim3(blocks), dim3(64), 0, s, P, ngroups);
+  const int blocks = 8 * ceil_div(ngroups, 8) * P.ncg;
+  const size_t lds = match_lds_bytes(P);
+  hipError_t e = allow_lds(match_kernel<WIN, DC, PREC>, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((match_kernel<WIN, DC, PREC>), dim3(blocks), dim3(NWAVE * WV), lds, s, P, ngroups);
   return hipGetLastError();
 }
 
@@ -506,56 +609,73 @@ hipError_t launch_match(const MatchPair &P, int prec, hipStream_t s) {
   return launch_match_w<8, P_BF16>(P, s);
 }
 
-template <int WIN>
-static void launch_pw(const MatchPair *pairs_dev, const int4 *tasks_dev, int ntasks, int *counter,
-                      int prec, int nblocks, hipStream_t s) {
-  if (prec == P_I16)
-    hipLaunchKernelGGL((match_persistent_kernel<WIN, 8, P_I16>), dim3(nblocks), dim3(64), 0, s, pairs_dev, tasks_dev, ntasks, counter);
-  else if (prec == P_F16)
-    hipLaunchKernelGGL((match_persistent_kernel<WIN, 8, P_F16>), dim3(nblocks), dim3(64), 0, s, pairs_dev, tasks_dev, ntasks, counter);
-  else
-    hipLaunchKernelGGL((match_persistent_kernel<WIN, 8, P_BF16>), dim3(nblocks), dim3(64), 0, s, pairs_dev, tasks_dev, ntasks, counter);
-}
-
-// One persistent launch over the tasks of one window size.
-hipError_t launch_match_persistent(const MatchPair *pairs_dev, const int4 *tasks_dev, int ntasks,
-                                   int *counter_dev, int win, int prec, int nblocks,
-                                   hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
-  hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, counter_dev);
-  if (ev0) (void)hipEventRecord(ev0, s);
-  switch (win) {
-    case 3: launch_pw<3>(pairs_dev, tasks_dev, ntasks, counter_dev, prec, nblocks, s); break;
-    case 5: launch_pw<5>(pairs_dev, tasks_dev, ntasks, counter_dev, prec, nblocks, s); break;
-    case 7: launch_pw<7>(pairs_dev, tasks_dev, ntasks, counter_dev, prec, nblocks, s); break;
-    case 9: launch_pw<9>(pairs_dev, tasks_dev, ntasks, counter_dev, prec, nblocks, s); break;
-    case 11: launch_pw<11>(pairs_dev, tasks_dev, ntasks, counter_dev, prec, nblocks, s); break;
-    case 13: launch_pw<13>(pairs_dev, tasks_dev, ntasks, counter_dev, prec, nblocks, s); break;
-    default: launch_pw<15>(pairs_dev, tasks_dev, ntasks, counter_dev, prec, nblocks, s); break;
-  }
-  if (ev1) (void)hipEventRecord(ev1, s);
+template <int WIN, int PREC>
+static hipError_t launch_pwp(const MatchPair *pairs_dev, const int4 *tasks_dev, int ntasks,
+                             int *counter, int nblocks, size_t lds, hipStream_t s) {
+  hipError_t e = allow_lds(match_persistent_kernel<WIN, 8, PREC>, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((match_persistent_kernel<WIN, 8, PREC>), dim3(nblocks), dim3(NWAVE * WV), lds, s,
+                     pairs_dev, tasks_dev, ntasks, counter);
   return hipGetLastError();
 }
 
 template <int WIN>
-static int occ_w(int prec) {
-  int n = 0;
-  hipError_t e;
-  if (prec == P_I16) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, match_persistent_kernel<WIN, 8, P_I16>, 64, 0);
-  else if (prec == P_F16) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, match_persistent_kernel<WIN, 8, P_F16>, 64, 0);
-  else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, match_persistent_kernel<WIN, 8, P_BF16>, 64, 0);
-  if (e != hipSuccess) { (void)hipGetLastError(); return 4; }
-  return n;
+static hipError_t launch_pw(const MatchPair *pairs_dev, const int4 *tasks_dev, int ntasks,
+                            int *counter, int prec, int nblocks, size_t lds, hipStream_t s) {
+  if (prec == P_I16) return launch_pwp<WIN, P_I16>(pairs_dev, tasks_dev, ntasks, counter, nblocks, lds, s);
+  if (prec == P_F16) return launch_pwp<WIN, P_F16>(pairs_dev, tasks_dev, ntasks, counter, nblocks, lds, s);
+  return launch_pwp<WIN, P_BF16>(pairs_dev, tasks_dev, ntasks, counter, nblocks, lds, s);
 }
 
-int match_persistent_occupancy(int win, int prec) {
+// One persistent launch over the tasks of one window size.
+hipError_t launch_match_persistent(const MatchPair *pairs_dev, const int4 *tasks_dev, int ntasks,
+                                   int *counter_dev, int win, int prec, int nblocks, size_t lds,
+                                   hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+  hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, counter_dev);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (ev0) (void)hipEventRecord(ev0, s);
   switch (win) {
-    case 3: return occ_w<3>(prec);
-    case 5: return occ_w<5>(prec);
-    case 7: return occ_w<7>(prec);
-    case 9: return occ_w<9>(prec);
-    case 11: return occ_w<11>(prec);
-    case 13: return occ_w<13>(prec);
-    default: return occ_w<15>(prec);
+    case 3: e = launch_pw<3>(pairs_dev, tasks_dev, ntasks, counter_dev, prec, nblocks, lds, s); break;
+    case 5: e = launch_pw<5>(pairs_dev, tasks_dev, ntasks, counter_dev, prec, nblocks, lds, s); break;
+    case 7: e = launch_pw<7>(pairs_dev, tasks_dev, ntasks, counter_dev, prec, nblocks, lds, s); break;
+    case 9: e = launch_pw<9>(pairs_dev, tasks_dev, ntasks, counter_dev, prec, nblocks, lds, s); break;
+    case 11: e = launch_pw<11>(pairs_dev, tasks_dev, ntasks, counter_dev, prec, nblocks, lds, s); break;
+    case 13: e = launch_pw<13>(pairs_dev, tasks_dev, ntasks, counter_dev, prec, nblocks, lds, s); break;
+    default: e = launch_pw<15>(pairs_dev, tasks_dev, ntasks, counter_dev, prec, nblocks, lds, s); break;
+  }
+  if (ev1) (void)hipEventRecord(ev1, s);
+  return e;
+}
+
+template <int WIN, int PREC>
+static int occ_wp(size_t lds) {
+  int n = 0;
+  if (allow_lds(match_persistent_kernel<WIN, 8, PREC>, lds) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, match_persistent_kernel<WIN, 8, PREC>,
+                                                   NWAVE * WV, lds) != hipSuccess) {
+    (void)hipGetLastError();
+    return 1;
+  }
+  return std::max(1, n);
+}
+
+template <int WIN>
+static int occ_w(int prec, size_t lds) {
+  if (prec == P_I16) return occ_wp<WIN, P_I16>(lds);
+  if (prec == P_F16) return occ_wp<WIN, P_F16>(lds);
+  return occ_wp<WIN, P_BF16>(lds);
+}
+
+int match_persistent_occupancy(int win, int prec, size_t lds) {
+  switch (win) {
+    case 3: return occ_w<3>(prec, lds);
+    case 5: return occ_w<5>(prec, lds);
+    case 7: return occ_w<7>(prec, lds);
+    case 9: return occ_w<9>(prec, lds);
+    case 11: return occ_w<11>(prec, lds);
+    case 13: return occ_w<13>(prec, lds);
+    default: return occ_w<15>(prec, lds);
   }
 }
 

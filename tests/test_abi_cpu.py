@@ -37,7 +37,7 @@ def test_default_params_are_the_papers_constants():
     assert p.smooth_radius == 15 and abs(p.smooth_alpha - 0.1) < 1e-7
     assert p.precision == B.ST_FP32
     assert B.lib().st_version().startswith(b"stereo_mi355x")
-    assert B.st_num_variants() >= 4 and B.st_variant_name(0).startswith("DC=")
+    assert B.st_num_variants() >= 4 and B.st_variant_name(0).startswith("TY=")
     assert B.st_variant_name(-1) == ""
 
 
