@@ -5,6 +5,17 @@
 
 namespace st {
 
+// Explicit address spaces for device code: loads through generic pointers
+// become flat instructions, which count on the LDS wait counter as well and
+// may alias LDS, so the compiler can neither overlap them with LDS traffic
+// nor move them past LDS stores.
+#define GLOBAL __attribute__((address_space(1)))
+#define LDS __attribute__((address_space(3)))
+template <class T>
+__device__ __forceinline__ const GLOBAL T *gro(const T *p) { return (const GLOBAL T *)p; }
+template <class T>
+__device__ __forceinline__ GLOBAL T *grw(T *p) { return (GLOBAL T *)p; }
+
 constexpr int WV = 64;        // wavefront size on gfx950
 constexpr int KC = 8;         // image columns owned by one lane of the matcher
 constexpr int OUT_LANES = 62; // lanes 1..62 of a wave produce output; 0 and 63 are halos

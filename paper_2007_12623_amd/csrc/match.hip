@@ -86,20 +86,17 @@ template <> struct Img<P_BF16> {
   }
 };
 
-// Global key of a lane-local key: quantised z (bits of z+2 above the index
-// field), then 255 - (d - dmin) so that ties prefer the smaller disparity.
-__device__ __forceinline__ uint32_t global_key(float k, int dd0) {
-  uint32_t b = __builtin_bit_cast(uint32_t, k);
-  int j = 15 - (int)(b & 15u);
-  uint32_t q = b > 0x3F800000u ? (b - 0x3F800000u) >> 4 : 0u;
-  return 0x80000000u | (q << 8) | (uint32_t)(255 - (dd0 + j));
+// Global key of a lane-local key: 0x80000000 | q << 8 | 255 - (d - dmin),
+// q = quantised z (the bits of z+2 above the index field, counted from 1.0),
+// so that ties prefer the smaller disparity.  With j = 15 - (b & 15) and
+// c = 0x80000000 + 240 - (d0 - dmin), the low part is (b & 15) + c and
+// q << 8 = ((b - 0x3F800000) << 4) & ~0xFF, where b is clamped to 1.0.
+__device__ __forceinline__ uint32_t key_base(int dd0) { return 0x80000000u + 240u - (uint32_t)dd0; }
+__device__ __forceinline__ uint32_t global_key(float k, uint32_t c) {
+  const uint32_t b = __builtin_bit_cast(uint32_t, k);
+  const uint32_t hi = (max(b, 0x3F800000u) << 4) + 0x08000000u;  // (b' - 0x3F800000) << 4
+  return (hi & 0xFFFFFF00u) | ((b & 15u) + c);
 }
-
-// Explicit address spaces: loads through generic pointers become flat
-// instructions, which also count on the LDS wait counter, so every wait for
-// a crossbar exchange would wait for memory as well.
-#define GLOBAL __attribute__((address_space(1)))
-#define LDS __attribute__((address_space(3)))
 
 __device__ __forceinline__ void gmax(GLOBAL uint32_t *p, uint32_t v) {
   __hip_atomic_fetch_max(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -208,7 +205,7 @@ __device__ __forceinline__ void match_rows(const MatchPair &P, int y0, int y1, i
       for (int c = 0; c < K; ++c) V[j][c] = IM::dot(lp[c], rp[c - j + DC - 1], V[j][c]);
   }
 
-  const int dd0 = d0 - P.dmin;
+  const uint32_t kc = key_base(d0 - P.dmin);
   for (int y = y0; y < y1; ++y) {
     if (y > y0) {
       // entering row y+H (+), leaving row y-H-1 (-)
@@ -329,7 +326,7 @@ __device__ __forceinline__ void match_rows(const MatchPair &P, int y0, int y1, i
     if (!halo) {
 #pragma unroll
       for (int c = 0; c < K; ++c)
-        if (bestL[c] >= 0.5f) lmax(lrow + c * LTP, global_key(bestL[c], dd0));
+        if (bestL[c] >= 0.5f) lmax(lrow + c * LTP, global_key(bestL[c], kc));
     }
     LDS uint32_t *rrow = kt.rt + (y - kt.y0) * (8 * kt.rp);
     const int q0 = x0 - d0 - kt.rbase;  // tile column of home diagonal 0; q0 & 7 is wave-uniform
@@ -337,14 +334,14 @@ __device__ __forceinline__ void match_rows(const MatchPair &P, int y0, int y1, i
     for (int m = 0; m < K; ++m)
       if (Pd[m + DC - 1] >= 0.5f) {
         const int q = q0 + m;
-        lmax(rrow + (q & 7) * kt.rp + (q >> 3), global_key(Pd[m + DC - 1], dd0));
+        lmax(rrow + (q & 7) * kt.rp + (q >> 3), global_key(Pd[m + DC - 1], kc));
       }
     if (lane == 0) {
 #pragma unroll
       for (int m = -(DC - 1); m < 0; ++m)
         if (Pd[m + DC - 1] >= 0.5f) {
           const int q = q0 + m;
-          lmax(rrow + (q & 7) * kt.rp + (q >> 3), global_key(Pd[m + DC - 1], dd0));
+          lmax(rrow + (q & 7) * kt.rp + (q >> 3), global_key(Pd[m + DC - 1], kc));
         }
     }
   }

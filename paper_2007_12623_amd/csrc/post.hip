@@ -37,7 +37,7 @@ __device__ __forceinline__ long long round_half_even(long long num, long long de
 // Merged keys -> WTA disparities and masks (ob[0], mb[0], oR, mR); the keys
 // are cleared for the next matcher run.
 template <bool B>
-__global__ void decode_kernel(PostPair one, const PostPair *many) {
+__global__ void decode_kernel(PostPair one, const PostPair *__restrict__ many) {
   PAIR;
   PIX;
   const uint32_t a = P.keyL[k], b = P.keyR[k];
@@ -60,15 +60,85 @@ __global__ void fill_u32_kernel(uint32_t *p, int N, uint32_t v) {
 // delta = (zm - zp) / (2 (zm - 2 z0 + zp)) clamped to [-1/2, 1/2]; 0 at the
 // ends of the range, when a neighbour is missing or the curvature is >= 0.
 // A block covers 128 pixels of one row: it stages the window rows of the left
-// image and the right columns its disparities reach in LDS once, then every
-// thread slides a 3-value window over the right row for the three sums.
+// image and the right columns its disparities reach in LDS once; every thread
+// then reads its window rows as packed bytes and forms the three sums with
+// v_dot4_u32_u8 (4 products per instruction, exact in 32 bits).
 constexpr int SP_TX = 128, SP_MAXWIN = 15;
+constexpr int SP_LROW = SP_TX + 24, SP_RROW = SP_TX + 256 + 32;
+
+// Copy the bytes [g, g + len) of one image row to an LDS row as whole
+// dwords starting at the dword-aligned address below g, one dword per thread
+// (len + 3 < 4 * SP_TX); the byte offset of g in the LDS row is g & 3.
+// Bytes outside [lo, hi), the image buffer, are not read (a dword that is not
+// wholly inside is assembled byte by byte) and come out as 0.
+__device__ __forceinline__ void stage_row(uint8_t *dst, const GLOBAL uint8_t *g, int len,
+                                          const GLOBAL uint8_t *lo, const GLOBAL uint8_t *hi,
+                                          int tid) {
+  const int mis = (int)((uintptr_t)g & 3);
+  if (tid >= ((mis + len + 3) >> 2)) return;
+  const GLOBAL uint8_t *p = g - mis + 4 * tid;
+  uint32_t v;
+  if (p >= lo && p + 4 <= hi) {
+    v = *(const GLOBAL uint32_t *)p;
+  } else {
+    v = 0;
+    for (int j = 0; j < 4; ++j)
+      if (p + j >= lo && p + j < hi) v |= (uint32_t)p[j] << (8 * j);
+  }
+  ((uint32_t *)dst)[tid] = v;
+}
+
+// Sums over one staged window of L(u) R(u + e) for e = 0, 1, 2, i.e. at the
+// disparities o + 1, o, o - 1.  ND dwords hold the win bytes of an L row
+// (the bytes past win are masked to 0); the R row starts at byte rs.
+template <int ND>
+__device__ __forceinline__ void sp_sums(const uint8_t (*Ls)[SP_LROW], const uint8_t (*Rs)[SP_RROW],
+                                        const int *misL, const int *misR, int win, int tx, int rs0,
+                                        int &sp, int &s0, int &sm) {
+  const uint32_t lmask = (win & 3) ? (1u << (8 * (win & 3))) - 1u : 0xFFFFFFFFu;
+  uint32_t a0 = 0, a1 = 0, a2 = 0;
+  for (int v = 0; v < win; ++v) {
+    const int lb = tx + misL[v], rs = rs0 + misR[v];
+    const int la = lb & ~3, lsh = lb & 3, ra = rs & ~3, rsh = rs & 3;
+    const bool up1 = rsh + 1 >= 4, up2 = rsh + 2 >= 4;
+    const int sh1 = (rsh + 1) & 3, sh2 = (rsh + 2) & 3;
+    const uint32_t *lw = (const uint32_t *)&Ls[v][la];
+    const uint32_t *rw = (const uint32_t *)&Rs[v][ra];
+    uint32_t lt[ND + 1], rt[ND + 2];
+#pragma unroll
+    for (int i = 0; i <= ND; ++i) lt[i] = lw[i];
+#pragma unroll
+    for (int i = 0; i < ND + 2; ++i) rt[i] = rw[i];
+    uint32_t l[ND];
+#pragma unroll
+    for (int i = 0; i < ND; ++i) l[i] = __builtin_amdgcn_alignbyte(lt[i + 1], lt[i], lsh);
+    l[ND - 1] &= lmask;
+    // R windows shifted by e bytes: alignbyte within a dword pair, and the
+    // next pair when rsh + e reaches 4
+    uint32_t A1[ND + 1], A2[ND + 1];
+#pragma unroll
+    for (int i = 0; i <= ND; ++i) {
+      A1[i] = __builtin_amdgcn_alignbyte(rt[i + 1], rt[i], sh1);
+      A2[i] = __builtin_amdgcn_alignbyte(rt[i + 1], rt[i], sh2);
+    }
+#pragma unroll
+    for (int i = 0; i < ND; ++i) {
+      a0 = __builtin_amdgcn_udot4(l[i], __builtin_amdgcn_alignbyte(rt[i + 1], rt[i], rsh), a0, false);
+      a1 = __builtin_amdgcn_udot4(l[i], up1 ? A1[i + 1] : A1[i], a1, false);
+      a2 = __builtin_amdgcn_udot4(l[i], up2 ? A2[i + 1] : A2[i], a2, false);
+    }
+  }
+  sp = (int)a0;
+  s0 = (int)a1;
+  sm = (int)a2;
+}
+
 template <bool B>
-__global__ __launch_bounds__(SP_TX) void subpixel_kernel(PostPair one, const PostPair *many) {
+__global__ __launch_bounds__(SP_TX) void subpixel_kernel(PostPair one, const PostPair *__restrict__ many) {
   PAIR;
-  __shared__ uint8_t Ls[SP_MAXWIN][SP_TX + 16];
-  __shared__ uint8_t Rs[SP_MAXWIN][SP_TX + 256 + 24];
-  __shared__ int s_omin, s_omax;
+  __shared__ __align__(16) uint8_t Ls[SP_MAXWIN][SP_LROW];
+  __shared__ __align__(16) uint8_t Rs[SP_MAXWIN][SP_RROW];
+  __shared__ int s_omin, s_omax, misL[SP_MAXWIN], misR[SP_MAXWIN];
   const int tx = threadIdx.x;
   const int x0 = blockIdx.x * SP_TX, y = blockIdx.y;
   if (x0 >= P.W || y >= P.H) return;  // uniform per block
@@ -91,17 +161,24 @@ __global__ __launch_bounds__(SP_TX) void subpixel_kernel(PostPair one, const Pos
   const int omin = s_omin, omax = s_omax;
   const double qn = __builtin_nan("");
   if (omin <= omax) {
+    // Ls[r][misL[r] + c] = L(y-h+r, x0-h+c), Rs[r][misR[r] + c] = R(y-h+r, x0-omax-1-h+c).
+    // Bytes of columns outside the image only enter sums whose z is
+    // discarded (a valid pixel's windows at o lie inside the image).
     const int LW = SP_TX + 2 * h, RW = SP_TX + (omax - omin) + 2 + 2 * h;
     const int lx0 = x0 - h, rx0 = x0 - omax - 1 - h;
-    for (int i = tx; i < win * LW; i += SP_TX) {
-      const int r = i / LW, c = i - r * LW;
-      const int gy = y - h + r, gx = lx0 + c;
-      Ls[r][c] = (gy >= 0 && gy < H && gx >= 0 && gx < W) ? P.left[(size_t)gy * P.pitch + gx] : 0;
-    }
-    for (int i = tx; i < win * RW; i += SP_TX) {
-      const int r = i / RW, c = i - r * RW;
-      const int gy = y - h + r, gx = rx0 + c;
-      Rs[r][c] = (gy >= 0 && gy < H && gx >= 0 && gx < W) ? P.right[(size_t)gy * P.pitch + gx] : 0;
+    const GLOBAL uint8_t *Lg = gro(P.left), *Rg = gro(P.right);
+    const size_t span = (size_t)(H - 1) * P.pitch + W;
+#pragma unroll
+    for (int r = 0; r < SP_MAXWIN; ++r) {
+      if (r < win) {
+        const size_t row = (size_t)(y - h + r) * P.pitch;  // inside: the block has a valid pixel
+        stage_row(Ls[r], Lg + row + lx0, LW, Lg, Lg + span, tx);
+        stage_row(Rs[r], Rg + row + rx0, RW, Rg, Rg + span, tx);
+        if (tx == 0) {
+          misL[r] = (int)((uintptr_t)(Lg + row + lx0) & 3);
+          misR[r] = (int)((uintptr_t)(Rg + row + rx0) & 3);
+        }
+      }
     }
   }
   __syncthreads();
@@ -113,22 +190,14 @@ __global__ __launch_bounds__(SP_TX) void subpixel_kernel(PostPair one, const Pos
     P.delta[k] = 0.0f;
     return;
   }
-  // Rs[v][q] holds R(y - h + v, x - h + u - o) for q = tx + u + omax + 1 - o
+  // window column u of the thread at d = o + 1 - e is Rs[v][rs + e + u]
+  const int rs = tx + omax - o;
   int sm = 0, s0 = 0, sp = 0;  // sums at d = o - 1, o, o + 1
-  const int qb = tx + omax + 1 - o;
-  for (int v = 0; v < win; ++v) {
-    const uint8_t *lr = &Ls[v][tx];
-    const uint8_t *rr = &Rs[v][qb];
-    int rprev = rr[-1], rcur = rr[0];
-    for (int u = 0; u < win; ++u) {
-      const int rnext = rr[u + 1];
-      const int l = lr[u];
-      sp += l * rprev;
-      s0 += l * rcur;
-      sm += l * rnext;
-      rprev = rcur;
-      rcur = rnext;
-    }
+  switch ((win + 3) >> 2) {
+    case 1: sp_sums<1>(Ls, Rs, misL, misR, win, tx, rs, sp, s0, sm); break;
+    case 2: sp_sums<2>(Ls, Rs, misL, misR, win, tx, rs, sp, s0, sm); break;
+    case 3: sp_sums<3>(Ls, Rs, misL, misR, win, tx, rs, sp, s0, sm); break;
+    default: sp_sums<4>(Ls, Rs, misL, misR, win, tx, rs, sp, s0, sm); break;
   }
   const long long n = (long long)win * win;
   const long long sl = P.SL[k];
@@ -165,7 +234,7 @@ __global__ __launch_bounds__(SP_TX) void subpixel_kernel(PostPair one, const Pos
 // (ob[0], mb[0]) and (oR, mR) -> (ob[dst], mb[dst]): kept when the right
 // pixel x - oL points back within tol.
 template <bool B>
-__global__ void lr_check_kernel(PostPair one, const PostPair *many, int tol, int dst) {
+__global__ void lr_check_kernel(PostPair one, const PostPair *__restrict__ many, int tol, int dst) {
   PAIR;
   PIX;
   const int16_t *oL = P.ob[0];
@@ -182,45 +251,141 @@ __global__ void lr_check_kernel(PostPair one, const PostPair *many, int tol, int
   P.mb[dst][k] = keep;
 }
 
-__constant__ int c_dir8[8][2] = {{1, 0}, {-1, 0}, {0, 1}, {0, -1}, {1, 1}, {-1, -1}, {1, -1}, {-1, 1}};
 
 // ---------------------------------------------------------------- radial line scans
 // The 8 radial directions come in 4 line types: rows, columns, diagonals
-// (x - y const) and anti-diagonals (x + y const); c_dir8[2t] steps forward
-// along a line of type t, c_dir8[2t+1] backward.  A thread owns one segment
-// of SEG positions of one line and scans it, plus a look-ahead of `reach`
-// positions, in both directions; segments are independent.
+// (x - y const) and anti-diagonals (x + y const), each a pair of opposite
+// directions.  Per pixel and direction the scans give
+//   outlier: whether the r steps from the pixel all land on valid pixels,
+//            each within thresh of the previous one (plane pass[t], bit 0
+//            forward, bit 1 backward);
+//   fill:    the nearest valid pixel within R steps, as (steps << 16) |
+//            uint16 disparity, 0 when there is none (planes hits[2t],
+//            hits[2t+1]).
+// Rows: a wave covers 64 columns of a row, lanes are columns, and ballot
+// masks give the next break or valid pixel; the look-ahead runs over the
+// following 64-column blocks until every lane is settled.  Columns and
+// diagonals: a thread scans SEG rows of one line (plus the look-ahead) and
+// the lanes of a wave are neighbouring lines, so each step reads
+// consecutive columns of one row.
 constexpr int SEG = 64;
 
-struct LineGeom {
-  int x, y, dx, dy, len;
-};
+__device__ __forceinline__ uint64_t ballot64(bool p) { return __ballot(p); }
+__device__ __forceinline__ int ctz64(uint64_t v) { return __builtin_ctzll(v); }
+__device__ __forceinline__ int top64(uint64_t v) { return 63 - __builtin_clzll(v); }
 
-__device__ __forceinline__ int nlines(int t, int H, int W) {
-  return t == 0 ? H : (t == 1 ? W : W + H - 1);
+// forward / backward step failure of the outlier test at column p of a row:
+// the neighbour is outside, invalid or too far in disparity
+__device__ __forceinline__ bool step_breaks(const GLOBAL int16_t *o, const GLOBAL uint8_t *m, int p,
+                                            int q, int W, float thresh) {
+  if (q < 0 || q >= W || p < 0 || p >= W) return true;
+  if (!m[q]) return true;
+  const int dv = o[q] - o[p];
+  return !((float)(dv < 0 ? -dv : dv) < thresh);
 }
-__device__ __forceinline__ int maxlen(int t, int H, int W) {
-  return t == 0 ? W : (t == 1 ? H : min(W, H));
-}
-__device__ __forceinline__ LineGeom line_geom(int t, int l, int H, int W) {
-  LineGeom g;
-  if (t == 0) { g.x = 0; g.y = l; g.dx = 1; g.dy = 0; g.len = W; }
-  else if (t == 1) { g.x = l; g.y = 0; g.dx = 0; g.dy = 1; g.len = H; }
-  else if (t == 2) {  // x - y = l - (H - 1), step (1, 1)
-    const int c = l - (H - 1);
-    g.x = max(0, c); g.y = max(0, -c); g.dx = 1; g.dy = 1;
-    g.len = min(W - g.x, H - g.y);
-  } else {            // x + y = l, step (1, -1)
-    g.x = max(0, l - (H - 1)); g.y = min(l, H - 1); g.dx = 1; g.dy = -1;
-    g.len = min(W - g.x, g.y + 1);
+
+template <bool B>
+__global__ __launch_bounds__(64) void outlier_rows_kernel(PostPair one, const PostPair *__restrict__ many, int r,
+                                                          float thresh, int src) {
+  PAIR;
+  const int H = P.H, W = P.W;
+  const int y = blockIdx.y, xb = blockIdx.x * 64, lane = threadIdx.x;
+  if (y >= H || xb >= W) return;  // whole wave
+  const GLOBAL int16_t *o = gro(P.ob[src]) + (size_t)y * W;
+  const GLOBAL uint8_t *m = gro(P.mb[src]) + (size_t)y * W;
+  const int x = xb + lane;
+  // forward: distance to the first break at or after x must reach r
+  int df = 0;
+  bool open = true;
+  for (int k = 0; ; ++k) {
+    const int p0 = xb + 64 * k;
+    const uint64_t bm = ballot64(step_breaks(o, m, p0 + lane, p0 + lane + 1, W, thresh));
+    if (open) {
+      const uint64_t rest = k == 0 ? bm >> lane << lane : bm;  // breaks at >= x
+      if (rest) { df = p0 + ctz64(rest) - x; open = false; }
+      else if (p0 + 64 - x >= r) { df = r; open = false; }
+    }
+    if (!__any(open)) break;
   }
-  return g;
+  // backward: distance from the last break at or before x
+  int db = 0;
+  open = true;
+  for (int k = 0; ; ++k) {
+    const int p0 = xb - 64 * k;
+    const uint64_t bm = ballot64(step_breaks(o, m, p0 + lane, p0 + lane - 1, W, thresh));
+    if (open) {
+      const uint64_t low = k == 0 ? (lane == 63 ? bm : bm & ((2ull << lane) - 1)) : bm;  // <= x
+      if (low) { db = x - (p0 + top64(low)); open = false; }
+      else if (x - (p0 - 1) >= r) { db = r; open = false; }
+    }
+    if (!__any(open)) break;
+  }
+  if (x < W && m[x]) P.pass[(size_t)y * W + x] = (df >= r ? 1 : 0) | (db >= r ? 2 : 0);
 }
 
-// Thread index -> (line type, line, segment); false when out of range.
-__device__ __forceinline__ bool scan_task(int idx, int H, int W, int &t, int &l, int &sg) {
-  for (t = 0; t < 4; ++t) {
-    const int nl = nlines(t, H, W), ns = ceil_div(maxlen(t, H, W), SEG);
+template <bool B>
+__global__ __launch_bounds__(64) void fill_rows_kernel(PostPair one, const PostPair *__restrict__ many, int R,
+                                                       int src) {
+  PAIR;
+  const int H = P.H, W = P.W;
+  const int y = blockIdx.y, xb = blockIdx.x * 64, lane = threadIdx.x;
+  if (y >= H || xb >= W) return;  // whole wave
+  const GLOBAL int16_t *o = gro(P.ob[src]) + (size_t)y * W;
+  const GLOBAL uint8_t *m = gro(P.mb[src]) + (size_t)y * W;
+  const int x = xb + lane;
+  int qf = -1, qb = -1;
+  bool open = true;
+  for (int k = 0; ; ++k) {
+    const int p0 = xb + 64 * k, p = p0 + lane;
+    const uint64_t vm = ballot64(p < W && m[p]);
+    if (open) {
+      const uint64_t rest = k == 0 ? (lane == 63 ? 0ull : vm >> (lane + 1) << (lane + 1)) : vm;  // > x
+      if (rest) { qf = p0 + ctz64(rest); open = false; }
+      else if (p0 + 64 - x > R || p0 + 64 >= W) open = false;
+    }
+    if (!__any(open)) break;
+  }
+  open = true;
+  for (int k = 0; ; ++k) {
+    const int p0 = xb - 64 * k, p = p0 + lane;
+    const uint64_t vm = ballot64(p >= 0 && p < W && m[p]);
+    if (open) {
+      const uint64_t low = k == 0 ? vm & ((1ull << lane) - 1) : vm;  // < x
+      if (low) { qb = p0 + top64(low); open = false; }
+      else if (x - (p0 - 1) > R || p0 <= 0) open = false;
+    }
+    if (!__any(open)) break;
+  }
+  if (x >= W || m[x]) return;
+  const size_t N = (size_t)W * H, k = (size_t)y * W + x;
+  P.hits[k] = (qf >= 0 && qf - x <= R) ? ((uint32_t)(qf - x) << 16) | (uint16_t)o[qf] : 0u;
+  P.hits[N + k] = (qb >= 0 && x - qb <= R) ? ((uint32_t)(x - qb) << 16) | (uint16_t)o[qb] : 0u;
+}
+
+// Columns (t = 1), diagonals (t = 2, x = y + l - (H-1)) and anti-diagonals
+// (t = 3, x = l - y), stepped in increasing y.  Line l crosses rows
+// [ylo, yhi); its pixel in row y has the flat index y * (W + dx) + c0.
+struct VLine {
+  int ylo, yhi, st, c0;
+};
+__device__ __forceinline__ VLine vline(int t, int l, int H, int W) {
+  VLine v;
+  if (t == 1) { v.ylo = 0; v.yhi = H; v.st = W; v.c0 = l; }
+  else if (t == 2) {
+    const int c = l - (H - 1);
+    v.ylo = max(0, -c); v.yhi = min(H, W - c); v.st = W + 1; v.c0 = c;
+  } else {
+    v.ylo = max(0, l - (W - 1)); v.yhi = min(H, l + 1); v.st = W - 1; v.c0 = l;
+  }
+  return v;
+}
+__device__ __forceinline__ int vlines(int t, int H, int W) { return t == 1 ? W : W + H - 1; }
+
+// Thread index -> (line type 1..3, line, row segment); false past the end.
+__device__ __forceinline__ bool vscan_task(int idx, int H, int W, int &t, int &l, int &sg) {
+  const int ns = ceil_div(H, SEG);
+  for (t = 1; t < 4; ++t) {
+    const int nl = vlines(t, H, W);
     if (idx < nl * ns) {
       sg = idx / nl;
       l = idx - sg * nl;
@@ -231,71 +396,143 @@ __device__ __forceinline__ bool scan_task(int idx, int H, int W, int &t, int &l,
   return false;
 }
 
-__device__ __forceinline__ int scan_tasks(int H, int W) {
-  int n = 0;
-  for (int t = 0; t < 4; ++t) n += nlines(t, H, W) * ceil_div(maxlen(t, H, W), SEG);
-  return n;
-}
-
-// Outlier runs: for direction u, run(p) = number of consecutive steps
-// p -> p+u -> ... that land on valid pixels whose disparity differs from the
-// previous one by less than thresh.  p passes u when run(p) >= r.  Writes
-// pass[t][p] = bit 0 (forward direction) | bit 1 (backward direction).
+// Each scan first runs through the look-ahead rows (state only), then through
+// its own rows, writing results only where a later kernel reads them: pass
+// for valid pixels, hits for holes.  The loops are branch-free so that the
+// loads of an unrolled group issue together.
 template <bool B>
-__global__ void outlier_scan_kernel(PostPair one, const PostPair *many, int r, float thresh, int src) {
+__global__ void outlier_vscan_kernel(PostPair one, const PostPair *__restrict__ many, int r,
+                                     float thresh, int src) {
   PAIR;
   const int H = P.H, W = P.W;
   int t, l, sg;
-  if (!scan_task(blockIdx.x * blockDim.x + threadIdx.x, H, W, t, l, sg)) return;
-  const LineGeom g = line_geom(t, l, H, W);
-  const int a = sg * SEG;
-  if (a >= g.len) return;
-  const int b = min(g.len, a + SEG);
-  const int16_t *o = P.ob[src];
-  const uint8_t *m = P.mb[src];
-  const size_t N = (size_t)W * H;
-  uint8_t *pass = P.pass + (size_t)t * N;
-  const int lstep = g.dy * W + g.dx;
-  const long long base = (long long)g.y * W + g.x;
-  // forward: walk from the far end of the look-ahead towards a
-  {
-    const int e = min(g.len - 1, b - 1 + r);
-    int run = 0, onext = 0;
-    bool vnext = false;
-    for (int p = e; p >= a; --p) {
-      const long long k = base + (long long)p * lstep;
+  if (!vscan_task(blockIdx.x * blockDim.x + threadIdx.x, H, W, t, l, sg)) return;
+  const VLine L = vline(t, l, H, W);
+  const int a = max(L.ylo, sg * SEG), b = min(L.yhi, sg * SEG + SEG);
+  if (a >= b) return;
+  const GLOBAL int16_t *__restrict__ o = gro(P.ob[src]);
+  const GLOBAL uint8_t *__restrict__ m = gro(P.mb[src]);
+  GLOBAL uint8_t *__restrict__ pass = grw(P.pass) + (size_t)t * W * H;
+  // run = consecutive good steps from y along the scan direction, capped at r
+  auto step = [&](int op, int onb, bool vnb, int run) {
+    const int dv = onb - op;
+    const bool good = vnb & ((float)(dv < 0 ? -dv : dv) < thresh);
+    return good ? min(run + 1, r) : 0;
+  };
+  {  // forward (+y), walked from the end of the look-ahead back to a
+    const int e = min(L.yhi - 1, b - 1 + r);
+    int k = e * L.st + L.c0;
+    int on = o[k], run = 0;
+    bool vn = m[k] != 0;
+    if (e < b && vn) pass[k] = 0;
+    int y = e - 1;
+    k -= L.st;
+#pragma unroll 8
+    for (; y >= b; --y, k -= L.st) {
       const int op = o[k];
-      if (p < e) {
-        const int dv = onext - op;
-        run = (vnext && (float)(dv < 0 ? -dv : dv) < thresh) ? min(run + 1, r) : 0;
-      }
-      if (p < b) pass[k] = run >= r ? 1 : 0;
-      onext = op;
-      vnext = m[k] != 0;
+      const bool v = m[k] != 0;
+      run = step(op, on, vn, run);
+      on = op;
+      vn = v;
+    }
+#pragma unroll 8
+    for (; y >= a; --y, k -= L.st) {
+      const int op = o[k];
+      const bool v = m[k] != 0;
+      run = step(op, on, vn, run);
+      on = op;
+      vn = v;
+      if (v) pass[k] = run >= r ? 1 : 0;
     }
   }
-  // backward
-  {
-    const int e = max(0, a - r);
-    int run = 0, oprev = 0;
-    bool vprev = false;
-    for (int p = e; p < b; ++p) {
-      const long long k = base + (long long)p * lstep;
+  {  // backward (-y); when e == a the first row has no step (run 0 < r)
+    const int e = max(L.ylo, a - r);
+    int k = e * L.st + L.c0;
+    int on = o[k], run = 0;
+    bool vn = m[k] != 0;
+    int y = e + 1;
+    k += L.st;
+#pragma unroll 8
+    for (; y < a; ++y, k += L.st) {
       const int op = o[k];
-      if (p > e) {
-        const int dv = oprev - op;
-        run = (vprev && (float)(dv < 0 ? -dv : dv) < thresh) ? min(run + 1, r) : 0;
-      }
-      if (p >= a && run >= r) pass[k] |= 2;
-      oprev = op;
-      vprev = m[k] != 0;
+      const bool v = m[k] != 0;
+      run = step(op, on, vn, run);
+      on = op;
+      vn = v;
+    }
+#pragma unroll 8
+    for (; y < b; ++y, k += L.st) {
+      const int op = o[k];
+      const bool v = m[k] != 0;
+      run = step(op, on, vn, run);
+      on = op;
+      vn = v;
+      if (v && run >= r) pass[k] |= 2;
+    }
+  }
+}
+
+template <bool B>
+__global__ void fill_vscan_kernel(PostPair one, const PostPair *__restrict__ many, int R, int src) {
+  PAIR;
+  const int H = P.H, W = P.W;
+  int t, l, sg;
+  if (!vscan_task(blockIdx.x * blockDim.x + threadIdx.x, H, W, t, l, sg)) return;
+  const VLine L = vline(t, l, H, W);
+  const int a = max(L.ylo, sg * SEG), b = min(L.yhi, sg * SEG + SEG);
+  if (a >= b) return;
+  const GLOBAL int16_t *__restrict__ o = gro(P.ob[src]);
+  const GLOBAL uint8_t *__restrict__ m = gro(P.mb[src]);
+  const size_t N = (size_t)W * H;
+  GLOBAL uint32_t *__restrict__ hf = grw(P.hits) + (size_t)(2 * t) * N;
+  GLOBAL uint32_t *__restrict__ hb = grw(P.hits) + (size_t)(2 * t + 1) * N;
+  {  // nearest valid pixel in +y
+    const int e = min(L.yhi - 1, b - 1 + R);
+    int q = -1;
+    uint32_t vq = 0;
+    int y = e, k = e * L.st + L.c0;
+#pragma unroll 8
+    for (; y >= b; --y, k -= L.st) {
+      const bool v = m[k] != 0;
+      const uint32_t ov = (uint16_t)o[k];
+      q = v ? y : q;
+      vq = v ? ov : vq;
+    }
+#pragma unroll 8
+    for (; y >= a; --y, k -= L.st) {
+      const bool v = m[k] != 0;
+      const uint32_t ov = (uint16_t)o[k];
+      if (!v) hf[k] = (q >= 0 && q - y <= R) ? ((uint32_t)(q - y) << 16) | vq : 0u;
+      q = v ? y : q;
+      vq = v ? ov : vq;
+    }
+  }
+  {  // nearest valid pixel in -y
+    const int e = max(L.ylo, a - R);
+    int q = -1;
+    uint32_t vq = 0;
+    int y = e, k = e * L.st + L.c0;
+#pragma unroll 8
+    for (; y < a; ++y, k += L.st) {
+      const bool v = m[k] != 0;
+      const uint32_t ov = (uint16_t)o[k];
+      q = v ? y : q;
+      vq = v ? ov : vq;
+    }
+#pragma unroll 8
+    for (; y < b; ++y, k += L.st) {
+      const bool v = m[k] != 0;
+      const uint32_t ov = (uint16_t)o[k];
+      if (!v) hb[k] = (q >= 0 && y - q <= R) ? ((uint32_t)(y - q) << 16) | vq : 0u;
+      q = v ? y : q;
+      vq = v ? ov : vq;
     }
   }
 }
 
 // A valid pixel stays when some direction passes (Section II-B).
 template <bool B>
-__global__ void outlier_combine_kernel(PostPair one, const PostPair *many, int src, int dst) {
+__global__ void outlier_combine_kernel(PostPair one, const PostPair *__restrict__ many, int src, int dst) {
   PAIR;
   PIX;
   const size_t N = (size_t)W * H;
@@ -305,52 +542,12 @@ __global__ void outlier_combine_kernel(PostPair one, const PostPair *many, int s
   P.mb[dst][k] = (mk && any) ? mk : 0;
 }
 
-// Nearest valid pixel within R steps in each direction of a line type:
-// hits[2t (+1)][p] = (steps << 16) | (uint16 disparity), 0 when none.
-template <bool B>
-__global__ void fill_scan_kernel(PostPair one, const PostPair *many, int R, int src) {
-  PAIR;
-  const int H = P.H, W = P.W;
-  int t, l, sg;
-  if (!scan_task(blockIdx.x * blockDim.x + threadIdx.x, H, W, t, l, sg)) return;
-  const LineGeom g = line_geom(t, l, H, W);
-  const int a = sg * SEG;
-  if (a >= g.len) return;
-  const int b = min(g.len, a + SEG);
-  const int16_t *o = P.ob[src];
-  const uint8_t *m = P.mb[src];
-  const size_t N = (size_t)W * H;
-  uint32_t *hf = P.hits + (size_t)(2 * t) * N, *hb = P.hits + (size_t)(2 * t + 1) * N;
-  const int lstep = g.dy * W + g.dx;
-  const long long base = (long long)g.y * W + g.x;
-  {
-    const int e = min(g.len - 1, b - 1 + R);
-    int q = -1;
-    uint32_t vq = 0;
-    for (int p = e; p >= a; --p) {
-      const long long k = base + (long long)p * lstep;
-      if (p < b) hf[k] = (q >= 0 && q - p <= R) ? ((uint32_t)(q - p) << 16) | vq : 0u;
-      if (m[k]) { q = p; vq = (uint16_t)o[k]; }
-    }
-  }
-  {
-    const int e = max(0, a - R);
-    int q = -1;
-    uint32_t vq = 0;
-    for (int p = e; p < b; ++p) {
-      const long long k = base + (long long)p * lstep;
-      if (p >= a) hb[k] = (q >= 0 && p - q <= R) ? ((uint32_t)(p - q) << 16) | vq : 0u;
-      if (m[k]) { q = p; vq = (uint16_t)o[k]; }
-    }
-  }
-}
-
 // (i) radial fill from the scanned hits: complete lines (both opposite
 // directions hit) give (va*sb + vb*sa)/(sa+sb); with >= min_lines complete
 // lines the hole takes their mean, an exact rational rounded half to even;
 // code 2.
 template <bool B>
-__global__ void fill_radial_kernel(PostPair one, const PostPair *many, int min_lines, int src,
+__global__ void fill_radial_kernel(PostPair one, const PostPair *__restrict__ many, int min_lines, int src,
                                    int dst) {
   PAIR;
   PIX;
@@ -382,7 +579,7 @@ __global__ void fill_radial_kernel(PostPair one, const PostPair *many, int min_l
 // Row prefix sums of the valid count and of the valid disparities of
 // (ob[src], mb[src]): pc[y][x+1] = sum_{x' <= x} [m != 0]; pc[y][0] = 0.
 template <bool B>
-__global__ __launch_bounds__(256) void row_prefix_kernel(PostPair one, const PostPair *many,
+__global__ __launch_bounds__(256) void row_prefix_kernel(PostPair one, const PostPair *__restrict__ many,
                                                          int src) {
   PAIR;
   __shared__ int sc[256], ss[256];
@@ -430,33 +627,46 @@ __device__ __forceinline__ int isqrt_floor(int v) {
 
 // (ii) disk: holes with at least ceil(frac * in-image disk cells) valid
 // pixels within radius R take their mean, rounded half to even; code 2.
-// Disk sums come from the row prefix sums, one segment per disk row.
+// Disk sums come from the row prefix sums, one segment per disk row; the
+// half-widths floor(sqrt(R^2 - dy^2)) of the disk rows are tabulated once
+// per block (for |dy| <= DISK_TAB) instead of per pixel and row.
+constexpr int DISK_TAB = 512;
+
 template <bool B>
-__global__ void fill_disk_kernel(PostPair one, const PostPair *many, int R, float frac, int src,
-                                 int dst) {
+__global__ __launch_bounds__(128) void fill_disk_kernel(PostPair one, const PostPair *__restrict__ many, int R,
+                                                        float frac, int src, int dst) {
   PAIR;
+  __shared__ int hw[2 * DISK_TAB + 1];
+  const int RT = min(R, DISK_TAB);
+  for (int i = threadIdx.x; i <= 2 * RT; i += blockDim.x) {
+    const int dy = i - RT;
+    hw[i] = isqrt_floor(R * R - dy * dy);
+  }
+  __syncthreads();
   PIX;
-  const int16_t *o = P.ob[src];
-  const uint8_t *m = P.mb[src];
-  P.ob[dst][k] = o[k];
-  P.mb[dst][k] = m[k];
+  const GLOBAL int16_t *o = gro(P.ob[src]);
+  const GLOBAL uint8_t *m = gro(P.mb[src]);
+  grw(P.ob[dst])[k] = o[k];
+  grw(P.mb[dst])[k] = m[k];
   if (m[k]) return;
   long long cells = 0, cnt = 0, sum = 0;
-  for (int dy = -R; dy <= R; ++dy) {
+  const int ya = max(-R, -y), yb = min(R, H - 1 - y);
+  const GLOBAL int32_t *__restrict__ pc = gro(P.pc);
+  const GLOBAL int32_t *__restrict__ ps = gro(P.ps);
+#pragma unroll 8
+  for (int dy = ya; dy <= yb; ++dy) {
     const int qy = y + dy;
-    if (qy < 0 || qy >= H) continue;
-    const int w = isqrt_floor(R * R - dy * dy);
+    const int w = (dy >= -RT && dy <= RT) ? hw[dy + RT] : isqrt_floor(R * R - dy * dy);
     const int xl = max(0, x - w), xh = min(W - 1, x + w);
-    if (xl > xh) continue;
     cells += xh - xl + 1;
-    const int32_t *pcr = P.pc + (size_t)qy * (W + 1), *psr = P.ps + (size_t)qy * (W + 1);
-    cnt += pcr[xh + 1] - pcr[xl];
-    sum += psr[xh + 1] - psr[xl];
+    const size_t rb = (size_t)qy * (W + 1);
+    cnt += pc[rb + xh + 1] - pc[rb + xl];
+    sum += ps[rb + xh + 1] - ps[rb + xl];
   }
   const double need = ceil((double)frac * (double)cells);
   if (cnt > 0 && (double)cnt >= need) {
-    P.ob[dst][k] = (int16_t)round_half_even(sum, cnt);
-    P.mb[dst][k] = 2;
+    grw(P.ob[dst])[k] = (int16_t)round_half_even(sum, cnt);
+    grw(P.mb[dst])[k] = 2;
   }
 }
 
@@ -467,7 +677,7 @@ enum { F_S = 0, F_IN = 1, F_CNT = 2, F_TMP = 3, F_A = 4, F_D = 5 };
 // s = o + delta for matched pixels (code 1), o for filled ones (code 2), or
 // the given s_in; plane F_IN <- s*m, F_D <- m (ones, used for the counts).
 template <bool B>
-__global__ void hc_init_kernel(PostPair one, const PostPair *many, int src, int use_delta) {
+__global__ void hc_init_kernel(PostPair one, const PostPair *__restrict__ many, int src, int use_delta) {
   PAIR;
   PIX;
   const size_t N = (size_t)W * H;
@@ -485,7 +695,7 @@ __global__ void hc_init_kernel(PostPair one, const PostPair *many, int src, int 
 // Box sums over a (2R+1) window along columns: a thread owns one column and
 // a segment of seg rows, seeds the window sum, then slides it.
 template <bool B>
-__global__ void box_v_kernel(PostPair one, const PostPair *many, int R, int seg, int in, int out) {
+__global__ void box_v_kernel(PostPair one, const PostPair *__restrict__ many, int R, int seg, int in, int out) {
   PAIR;
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y0 = blockIdx.y * seg;
@@ -507,7 +717,7 @@ __global__ void box_v_kernel(PostPair one, const PostPair *many, int R, int seg,
 }
 
 template <bool B>
-__global__ void box_h_kernel(PostPair one, const PostPair *many, int R, int seg, int in, int out) {
+__global__ void box_h_kernel(PostPair one, const PostPair *__restrict__ many, int R, int seg, int in, int out) {
   PAIR;
   const int y = blockIdx.x * blockDim.x + threadIdx.x;
   const int x0 = blockIdx.y * seg;
@@ -533,7 +743,7 @@ __global__ void box_h_kernel(PostPair one, const PostPair *many, int R, int seg,
 // with coalesced loads and stores.  Rows up to BOXH_MAXW wide.
 constexpr int BOXH_MAXW = 4096;
 template <bool B>
-__global__ __launch_bounds__(256) void box_h_lds_kernel(PostPair one, const PostPair *many, int R,
+__global__ __launch_bounds__(256) void box_h_lds_kernel(PostPair one, const PostPair *__restrict__ many, int R,
                                                         int in, int out) {
   PAIR;
   __shared__ double row[BOXH_MAXW];
@@ -574,7 +784,7 @@ __global__ __launch_bounds__(256) void box_h_lds_kernel(PostPair one, const Post
 
 // a = A(s) = box(s m) / box(m) on valid pixels (Eq. 1)
 template <bool B>
-__global__ void hc_a_kernel(PostPair one, const PostPair *many, int src) {
+__global__ void hc_a_kernel(PostPair one, const PostPair *__restrict__ many, int src) {
   PAIR;
   PIX;
   const size_t N = (size_t)W * H;
@@ -584,7 +794,7 @@ __global__ void hc_a_kernel(PostPair one, const PostPair *many, int src) {
 // b = a - alpha*s - (1-alpha)*d_prev on valid pixels, 0 elsewhere (Eq. 2);
 // d_prev is s in the first iteration.
 template <bool B>
-__global__ void hc_b_kernel(PostPair one, const PostPair *many, int src, double alpha, int first) {
+__global__ void hc_b_kernel(PostPair one, const PostPair *__restrict__ many, int src, double alpha, int first) {
   PAIR;
   PIX;
   const size_t N = (size_t)W * H;
@@ -595,7 +805,7 @@ __global__ void hc_b_kernel(PostPair one, const PostPair *many, int src, double 
 
 // d = a - A(b) (Eq. 3)
 template <bool B>
-__global__ void hc_d_kernel(PostPair one, const PostPair *many, int src) {
+__global__ void hc_d_kernel(PostPair one, const PostPair *__restrict__ many, int src) {
   PAIR;
   PIX;
   const size_t N = (size_t)W * H;
@@ -603,7 +813,7 @@ __global__ void hc_d_kernel(PostPair one, const PostPair *many, int src) {
 }
 
 template <bool B>
-__global__ void hc_out_kernel(PostPair one, const PostPair *many, int src, int plane) {
+__global__ void hc_out_kernel(PostPair one, const PostPair *__restrict__ many, int src, int plane) {
   PAIR;
   PIX;
   const size_t N = (size_t)W * H;
@@ -635,25 +845,23 @@ hipError_t post_lr(const PostLaunch &L, int tol, int dst) {
   LAUNCH(lr_check_kernel, pixgrid(L), dim3(128), tol, dst);
   return hipGetLastError();
 }
-static dim3 scangrid(const PostLaunch &L) {
-  int n = 0;
-  for (int t = 0; t < 4; ++t) {
-    const int nl = t == 0 ? L.maxH : (t == 1 ? L.maxW : L.maxW + L.maxH - 1);
-    const int ml = t == 0 ? L.maxW : (t == 1 ? L.maxH : std::min(L.maxW, L.maxH));
-    n += nl * ceil_div(ml, SEG);
-  }
+static dim3 rowgrid(const PostLaunch &L) { return dim3(ceil_div(L.maxW, 64), L.maxH, L.npairs); }
+static dim3 vscangrid(const PostLaunch &L) {
+  const int n = (L.maxW + 2 * (L.maxW + L.maxH - 1)) * ceil_div(L.maxH, SEG);
   return dim3(ceil_div(n, 64), 1, L.npairs);
 }
 
 hipError_t post_outlier(const PostLaunch &L, int r, float thresh, int src, int dst) {
-  LAUNCH(outlier_scan_kernel, scangrid(L), dim3(64), r, thresh, src);
+  LAUNCH(outlier_rows_kernel, rowgrid(L), dim3(64), r, thresh, src);
+  LAUNCH(outlier_vscan_kernel, vscangrid(L), dim3(64), r, thresh, src);
   LAUNCH(outlier_combine_kernel, pixgrid(L), dim3(128), src, dst);
   return hipGetLastError();
 }
 // radial fill src -> tmp, disk fill tmp -> dst (dst may equal src)
 hipError_t post_fill(const PostLaunch &L, int radial_r, int min_lines, int disk_r, float frac,
                      int src, int tmp, int dst) {
-  LAUNCH(fill_scan_kernel, scangrid(L), dim3(64), radial_r, src);
+  LAUNCH(fill_rows_kernel, rowgrid(L), dim3(64), radial_r, src);
+  LAUNCH(fill_vscan_kernel, vscangrid(L), dim3(64), radial_r, src);
   LAUNCH(fill_radial_kernel, pixgrid(L), dim3(128), min_lines, src, tmp);
   LAUNCH(row_prefix_kernel, dim3(L.maxH, 1, L.npairs), dim3(256), tmp);
   LAUNCH(fill_disk_kernel, pixgrid(L), dim3(128), disk_r, frac, tmp, dst);
