@@ -11,13 +11,18 @@
 namespace st {
 
 #define PAIR const PostPair &P = B ? many[blockIdx.z] : one
-#define PIX                                                     \
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;         \
-  const int y = blockIdx.y;                                     \
-  if (x >= P.W || y >= P.H) return;                             \
-  const int W = P.W, H = P.H;                                   \
-  const size_t k = (size_t)y * W + x;                           \
-  (void)H
+// Per-pixel kernels: a block of PIX_T threads covers PIX_SEG columns of one
+// row, PIX_SEG / PIX_T pixels per thread at stride PIX_T (coalesced).  Few,
+// fat blocks: with one short-lived block per 128 pixels these kernels were
+// limited by the rate at which waves are launched, not by work.
+constexpr int PIX_T = 256, PIX_SEG = 1024;
+template <class F>
+__device__ __forceinline__ void for_pixels(const PostPair &P, F f) {
+  const int y = blockIdx.y;
+  if (y >= P.H) return;
+  const int x1 = min(P.W, (int)(blockIdx.x + 1) * PIX_SEG);
+  for (int x = blockIdx.x * PIX_SEG + threadIdx.x; x < x1; x += PIX_T) f(x, y, (size_t)y * P.W + x);
+}
 
 __device__ __forceinline__ long long floordiv_ll(long long a, long long b) {
   long long q = a / b, r = a % b;
@@ -39,14 +44,18 @@ __device__ __forceinline__ long long round_half_even(long long num, long long de
 template <bool B>
 __global__ void decode_kernel(PostPair one, const PostPair *__restrict__ many) {
   PAIR;
-  PIX;
-  const uint32_t a = P.keyL[k], b = P.keyR[k];
-  P.ob[0][k] = a ? (int16_t)(P.dmin + 255 - (int)(a & 255u)) : 0;
-  P.mb[0][k] = a ? 1 : 0;
-  P.oR[k] = b ? (int16_t)(P.dmin + 255 - (int)(b & 255u)) : 0;
-  P.mR[k] = b ? 1 : 0;
-  P.keyL[k] = 0;
-  P.keyR[k] = 0;
+  const int W = P.W, H = P.H;
+  (void)W;
+  (void)H;
+  for_pixels(P, [&](int x, int y, size_t k) {
+    const uint32_t a = P.keyL[k], b = P.keyR[k];
+    P.ob[0][k] = a ? (int16_t)(P.dmin + 255 - (int)(a & 255u)) : 0;
+    P.mb[0][k] = a ? 1 : 0;
+    P.oR[k] = b ? (int16_t)(P.dmin + 255 - (int)(b & 255u)) : 0;
+    P.mR[k] = b ? 1 : 0;
+    P.keyL[k] = 0;
+    P.keyR[k] = 0;
+  });
 }
 
 __global__ void fill_u32_kernel(uint32_t *p, int N, uint32_t v) {
@@ -236,19 +245,23 @@ __global__ __launch_bounds__(SP_TX) void subpixel_kernel(PostPair one, const Pos
 template <bool B>
 __global__ void lr_check_kernel(PostPair one, const PostPair *__restrict__ many, int tol, int dst) {
   PAIR;
-  PIX;
-  const int16_t *oL = P.ob[0];
-  uint8_t keep = 0;
-  if (P.mb[0][k]) {
-    const int xr = x - oL[k];
-    if (xr >= 0 && xr < W) {
-      const size_t kr = (size_t)y * W + xr;
-      const int diff = (int)oL[k] - (int)P.oR[kr];
-      if (P.mR[kr] && (diff < 0 ? -diff : diff) <= tol) keep = 1;
+  const int W = P.W, H = P.H;
+  (void)W;
+  (void)H;
+  for_pixels(P, [&](int x, int y, size_t k) {
+    const int16_t *oL = P.ob[0];
+    uint8_t keep = 0;
+    if (P.mb[0][k]) {
+      const int xr = x - oL[k];
+      if (xr >= 0 && xr < W) {
+        const size_t kr = (size_t)y * W + xr;
+        const int diff = (int)oL[k] - (int)P.oR[kr];
+        if (P.mR[kr] && (diff < 0 ? -diff : diff) <= tol) keep = 1;
+      }
     }
-  }
-  P.ob[dst][k] = oL[k];
-  P.mb[dst][k] = keep;
+    P.ob[dst][k] = oL[k];
+    P.mb[dst][k] = keep;
+  });
 }
 
 
@@ -534,12 +547,16 @@ __global__ void fill_vscan_kernel(PostPair one, const PostPair *__restrict__ man
 template <bool B>
 __global__ void outlier_combine_kernel(PostPair one, const PostPair *__restrict__ many, int src, int dst) {
   PAIR;
-  PIX;
-  const size_t N = (size_t)W * H;
-  const uint8_t mk = P.mb[src][k];
-  P.ob[dst][k] = P.ob[src][k];
-  const bool any = (P.pass[k] | P.pass[N + k] | P.pass[2 * N + k] | P.pass[3 * N + k]) != 0;
-  P.mb[dst][k] = (mk && any) ? mk : 0;
+  const int W = P.W, H = P.H;
+  (void)W;
+  (void)H;
+  for_pixels(P, [&](int x, int y, size_t k) {
+    const size_t N = (size_t)W * H;
+    const uint8_t mk = P.mb[src][k];
+    P.ob[dst][k] = P.ob[src][k];
+    const bool any = (P.pass[k] | P.pass[N + k] | P.pass[2 * N + k] | P.pass[3 * N + k]) != 0;
+    P.mb[dst][k] = (mk && any) ? mk : 0;
+  });
 }
 
 // (i) radial fill from the scanned hits: complete lines (both opposite
@@ -550,30 +567,34 @@ template <bool B>
 __global__ void fill_radial_kernel(PostPair one, const PostPair *__restrict__ many, int min_lines, int src,
                                    int dst) {
   PAIR;
-  PIX;
-  const int16_t *o = P.ob[src];
-  const uint8_t *m = P.mb[src];
-  P.ob[dst][k] = o[k];
-  P.mb[dst][k] = m[k];
-  if (m[k]) return;
-  const size_t N = (size_t)W * H;
-  long long num = 0, den = 1;
-  int lines = 0;
-  for (int ln = 0; ln < 4; ++ln) {
-    const uint32_t ha = P.hits[(size_t)(2 * ln) * N + k], hb = P.hits[(size_t)(2 * ln + 1) * N + k];
-    if (!ha || !hb) continue;
-    const long long sa = ha >> 16, sb = hb >> 16;
-    const long long va = (int16_t)(ha & 0xFFFFu), vb = (int16_t)(hb & 0xFFFFu);
-    const long long lnum = va * sb + vb * sa;
-    const long long ld = sa + sb;
-    num = num * ld + lnum * den;
-    den = den * ld;
-    ++lines;
-  }
-  if (lines >= min_lines && lines > 0) {
-    P.ob[dst][k] = (int16_t)round_half_even(num, den * lines);
-    P.mb[dst][k] = 2;
-  }
+  const int W = P.W, H = P.H;
+  (void)W;
+  (void)H;
+  for_pixels(P, [&](int x, int y, size_t k) {
+    const int16_t *o = P.ob[src];
+    const uint8_t *m = P.mb[src];
+    P.ob[dst][k] = o[k];
+    P.mb[dst][k] = m[k];
+    if (m[k]) return;
+    const size_t N = (size_t)W * H;
+    long long num = 0, den = 1;
+    int lines = 0;
+    for (int ln = 0; ln < 4; ++ln) {
+      const uint32_t ha = P.hits[(size_t)(2 * ln) * N + k], hb = P.hits[(size_t)(2 * ln + 1) * N + k];
+      if (!ha || !hb) continue;
+      const long long sa = ha >> 16, sb = hb >> 16;
+      const long long va = (int16_t)(ha & 0xFFFFu), vb = (int16_t)(hb & 0xFFFFu);
+      const long long lnum = va * sb + vb * sa;
+      const long long ld = sa + sb;
+      num = num * ld + lnum * den;
+      den = den * ld;
+      ++lines;
+    }
+    if (lines >= min_lines && lines > 0) {
+      P.ob[dst][k] = (int16_t)round_half_even(num, den * lines);
+      P.mb[dst][k] = 2;
+    }
+  });
 }
 
 // Row prefix sums of the valid count and of the valid disparities of
@@ -633,7 +654,7 @@ __device__ __forceinline__ int isqrt_floor(int v) {
 constexpr int DISK_TAB = 512;
 
 template <bool B>
-__global__ __launch_bounds__(128) void fill_disk_kernel(PostPair one, const PostPair *__restrict__ many, int R,
+__global__ __launch_bounds__(PIX_T) void fill_disk_kernel(PostPair one, const PostPair *__restrict__ many, int R,
                                                         float frac, int src, int dst) {
   PAIR;
   __shared__ int hw[2 * DISK_TAB + 1];
@@ -643,31 +664,35 @@ __global__ __launch_bounds__(128) void fill_disk_kernel(PostPair one, const Post
     hw[i] = isqrt_floor(R * R - dy * dy);
   }
   __syncthreads();
-  PIX;
-  const GLOBAL int16_t *o = gro(P.ob[src]);
-  const GLOBAL uint8_t *m = gro(P.mb[src]);
-  grw(P.ob[dst])[k] = o[k];
-  grw(P.mb[dst])[k] = m[k];
-  if (m[k]) return;
-  long long cells = 0, cnt = 0, sum = 0;
-  const int ya = max(-R, -y), yb = min(R, H - 1 - y);
-  const GLOBAL int32_t *__restrict__ pc = gro(P.pc);
-  const GLOBAL int32_t *__restrict__ ps = gro(P.ps);
+  const int W = P.W, H = P.H;
+  (void)W;
+  (void)H;
+  for_pixels(P, [&](int x, int y, size_t k) {
+    const GLOBAL int16_t *o = gro(P.ob[src]);
+    const GLOBAL uint8_t *m = gro(P.mb[src]);
+    grw(P.ob[dst])[k] = o[k];
+    grw(P.mb[dst])[k] = m[k];
+    if (m[k]) return;
+    long long cells = 0, cnt = 0, sum = 0;
+    const int ya = max(-R, -y), yb = min(R, H - 1 - y);
+    const GLOBAL int32_t *__restrict__ pc = gro(P.pc);
+    const GLOBAL int32_t *__restrict__ ps = gro(P.ps);
 #pragma unroll 8
-  for (int dy = ya; dy <= yb; ++dy) {
-    const int qy = y + dy;
-    const int w = (dy >= -RT && dy <= RT) ? hw[dy + RT] : isqrt_floor(R * R - dy * dy);
-    const int xl = max(0, x - w), xh = min(W - 1, x + w);
-    cells += xh - xl + 1;
-    const size_t rb = (size_t)qy * (W + 1);
-    cnt += pc[rb + xh + 1] - pc[rb + xl];
-    sum += ps[rb + xh + 1] - ps[rb + xl];
-  }
-  const double need = ceil((double)frac * (double)cells);
-  if (cnt > 0 && (double)cnt >= need) {
-    grw(P.ob[dst])[k] = (int16_t)round_half_even(sum, cnt);
-    grw(P.mb[dst])[k] = 2;
-  }
+    for (int dy = ya; dy <= yb; ++dy) {
+      const int qy = y + dy;
+      const int w = (dy >= -RT && dy <= RT) ? hw[dy + RT] : isqrt_floor(R * R - dy * dy);
+      const int xl = max(0, x - w), xh = min(W - 1, x + w);
+      cells += xh - xl + 1;
+      const size_t rb = (size_t)qy * (W + 1);
+      cnt += pc[rb + xh + 1] - pc[rb + xl];
+      sum += ps[rb + xh + 1] - ps[rb + xl];
+    }
+    const double need = ceil((double)frac * (double)cells);
+    if (cnt > 0 && (double)cnt >= need) {
+      grw(P.ob[dst])[k] = (int16_t)round_half_even(sum, cnt);
+      grw(P.mb[dst])[k] = 2;
+    }
+  });
 }
 
 // ---------------------------------------------------------------- smoothing (FP64)
@@ -679,17 +704,21 @@ enum { F_S = 0, F_IN = 1, F_CNT = 2, F_TMP = 3, F_A = 4, F_D = 5 };
 template <bool B>
 __global__ void hc_init_kernel(PostPair one, const PostPair *__restrict__ many, int src, int use_delta) {
   PAIR;
-  PIX;
-  const size_t N = (size_t)W * H;
-  const uint8_t mk = P.mb[src][k];
-  double v = 0.0;
-  if (mk) {
-    if (P.s_in) v = (double)P.s_in[k];
-    else v = (mk == 1 && use_delta) ? (double)P.ob[src][k] + (double)P.delta[k] : (double)P.ob[src][k];
-  }
-  P.f[F_S * N + k] = v;
-  P.f[F_IN * N + k] = mk ? v : 0.0;
-  P.f[F_D * N + k] = mk ? 1.0 : 0.0;
+  const int W = P.W, H = P.H;
+  (void)W;
+  (void)H;
+  for_pixels(P, [&](int x, int y, size_t k) {
+    const size_t N = (size_t)W * H;
+    const uint8_t mk = P.mb[src][k];
+    double v = 0.0;
+    if (mk) {
+      if (P.s_in) v = (double)P.s_in[k];
+      else v = (mk == 1 && use_delta) ? (double)P.ob[src][k] + (double)P.delta[k] : (double)P.ob[src][k];
+    }
+    P.f[F_S * N + k] = v;
+    P.f[F_IN * N + k] = mk ? v : 0.0;
+    P.f[F_D * N + k] = mk ? 1.0 : 0.0;
+  });
 }
 
 // Box sums over a (2R+1) window along columns: a thread owns one column and
@@ -702,17 +731,21 @@ __global__ void box_v_kernel(PostPair one, const PostPair *__restrict__ many, in
   const int H = P.H, W = P.W;
   if (x >= W || y0 >= H) return;
   const size_t N = (size_t)W * H;
-  const double *fi = P.f + in * N;
-  double *fo = P.f + out * N;
+  const GLOBAL double *__restrict__ fi = gro(P.f) + in * N;
+  GLOBAL double *__restrict__ fo = grw(P.f) + out * N;
   double s = 0.0;
-  for (int v = y0 - R; v <= y0 + R; ++v)
-    if (v >= 0 && v < H) s += fi[(size_t)v * W + x];
+  const int va = max(0, y0 - R), vb = min(H - 1, y0 + R);
+#pragma unroll 8
+  for (int v = va; v <= vb; ++v) s += fi[(size_t)v * W + x];
   const int y1 = min(y0 + seg, H);
+#pragma unroll 4
   for (int y = y0; y < y1; ++y) {
     fo[(size_t)y * W + x] = s;
     const int a = y + R + 1, b = y - R;
-    if (a < H) s += fi[(size_t)a * W + x];
-    if (b >= 0) s -= fi[(size_t)b * W + x];
+    const double ea = a < H ? fi[(size_t)a * W + x] : 0.0;
+    const double eb = b >= 0 ? fi[(size_t)b * W + x] : 0.0;
+    s += ea;
+    s -= eb;
   }
 }
 
@@ -786,9 +819,13 @@ __global__ __launch_bounds__(256) void box_h_lds_kernel(PostPair one, const Post
 template <bool B>
 __global__ void hc_a_kernel(PostPair one, const PostPair *__restrict__ many, int src) {
   PAIR;
-  PIX;
-  const size_t N = (size_t)W * H;
-  P.f[F_A * N + k] = P.mb[src][k] ? P.f[F_IN * N + k] / P.f[F_CNT * N + k] : 0.0;
+  const int W = P.W, H = P.H;
+  (void)W;
+  (void)H;
+  for_pixels(P, [&](int x, int y, size_t k) {
+    const size_t N = (size_t)W * H;
+    P.f[F_A * N + k] = P.mb[src][k] ? P.f[F_IN * N + k] / P.f[F_CNT * N + k] : 0.0;
+  });
 }
 
 // b = a - alpha*s - (1-alpha)*d_prev on valid pixels, 0 elsewhere (Eq. 2);
@@ -796,34 +833,46 @@ __global__ void hc_a_kernel(PostPair one, const PostPair *__restrict__ many, int
 template <bool B>
 __global__ void hc_b_kernel(PostPair one, const PostPair *__restrict__ many, int src, double alpha, int first) {
   PAIR;
-  PIX;
-  const size_t N = (size_t)W * H;
-  const double s = P.f[F_S * N + k];
-  const double dp = first ? s : P.f[F_D * N + k];
-  P.f[F_IN * N + k] = P.mb[src][k] ? P.f[F_A * N + k] - alpha * s - (1.0 - alpha) * dp : 0.0;
+  const int W = P.W, H = P.H;
+  (void)W;
+  (void)H;
+  for_pixels(P, [&](int x, int y, size_t k) {
+    const size_t N = (size_t)W * H;
+    const double s = P.f[F_S * N + k];
+    const double dp = first ? s : P.f[F_D * N + k];
+    P.f[F_IN * N + k] = P.mb[src][k] ? P.f[F_A * N + k] - alpha * s - (1.0 - alpha) * dp : 0.0;
+  });
 }
 
 // d = a - A(b) (Eq. 3)
 template <bool B>
 __global__ void hc_d_kernel(PostPair one, const PostPair *__restrict__ many, int src) {
   PAIR;
-  PIX;
-  const size_t N = (size_t)W * H;
-  P.f[F_D * N + k] = P.mb[src][k] ? P.f[F_A * N + k] - P.f[F_IN * N + k] / P.f[F_CNT * N + k] : 0.0;
+  const int W = P.W, H = P.H;
+  (void)W;
+  (void)H;
+  for_pixels(P, [&](int x, int y, size_t k) {
+    const size_t N = (size_t)W * H;
+    P.f[F_D * N + k] = P.mb[src][k] ? P.f[F_A * N + k] - P.f[F_IN * N + k] / P.f[F_CNT * N + k] : 0.0;
+  });
 }
 
 template <bool B>
 __global__ void hc_out_kernel(PostPair one, const PostPair *__restrict__ many, int src, int plane) {
   PAIR;
-  PIX;
-  const size_t N = (size_t)W * H;
-  const uint8_t mk = P.mb[src][k];
-  P.disparity[k] = mk ? (float)P.f[plane * N + k] : __builtin_nanf("");
-  if (P.valid_mask) P.valid_mask[k] = mk;
+  const int W = P.W, H = P.H;
+  (void)W;
+  (void)H;
+  for_pixels(P, [&](int x, int y, size_t k) {
+    const size_t N = (size_t)W * H;
+    const uint8_t mk = P.mb[src][k];
+    P.disparity[k] = mk ? (float)P.f[plane * N + k] : __builtin_nanf("");
+    if (P.valid_mask) P.valid_mask[k] = mk;
+  });
 }
 
 // ---------------------------------------------------------------- host side
-static inline dim3 pixgrid(const PostLaunch &L) { return dim3(ceil_div(L.maxW, 128), L.maxH, L.npairs); }
+static inline dim3 pixgrid(const PostLaunch &L) { return dim3(ceil_div(L.maxW, PIX_SEG), L.maxH, L.npairs); }
 
 #define LAUNCH(kern, grid, block, ...)                                                   \
   do {                                                                                   \
@@ -834,7 +883,7 @@ static inline dim3 pixgrid(const PostLaunch &L) { return dim3(ceil_div(L.maxW, 1
   } while (0)
 
 hipError_t post_decode(const PostLaunch &L) {
-  LAUNCH(decode_kernel, pixgrid(L), dim3(128));
+  LAUNCH(decode_kernel, pixgrid(L), dim3(PIX_T));
   return hipGetLastError();
 }
 hipError_t post_subpixel(const PostLaunch &L) {
@@ -842,7 +891,7 @@ hipError_t post_subpixel(const PostLaunch &L) {
   return hipGetLastError();
 }
 hipError_t post_lr(const PostLaunch &L, int tol, int dst) {
-  LAUNCH(lr_check_kernel, pixgrid(L), dim3(128), tol, dst);
+  LAUNCH(lr_check_kernel, pixgrid(L), dim3(PIX_T), tol, dst);
   return hipGetLastError();
 }
 static dim3 rowgrid(const PostLaunch &L) { return dim3(ceil_div(L.maxW, 64), L.maxH, L.npairs); }
@@ -854,7 +903,7 @@ static dim3 vscangrid(const PostLaunch &L) {
 hipError_t post_outlier(const PostLaunch &L, int r, float thresh, int src, int dst) {
   LAUNCH(outlier_rows_kernel, rowgrid(L), dim3(64), r, thresh, src);
   LAUNCH(outlier_vscan_kernel, vscangrid(L), dim3(64), r, thresh, src);
-  LAUNCH(outlier_combine_kernel, pixgrid(L), dim3(128), src, dst);
+  LAUNCH(outlier_combine_kernel, pixgrid(L), dim3(PIX_T), src, dst);
   return hipGetLastError();
 }
 // radial fill src -> tmp, disk fill tmp -> dst (dst may equal src)
@@ -862,9 +911,9 @@ hipError_t post_fill(const PostLaunch &L, int radial_r, int min_lines, int disk_
                      int src, int tmp, int dst) {
   LAUNCH(fill_rows_kernel, rowgrid(L), dim3(64), radial_r, src);
   LAUNCH(fill_vscan_kernel, vscangrid(L), dim3(64), radial_r, src);
-  LAUNCH(fill_radial_kernel, pixgrid(L), dim3(128), min_lines, src, tmp);
+  LAUNCH(fill_radial_kernel, pixgrid(L), dim3(PIX_T), min_lines, src, tmp);
   LAUNCH(row_prefix_kernel, dim3(L.maxH, 1, L.npairs), dim3(256), tmp);
-  LAUNCH(fill_disk_kernel, pixgrid(L), dim3(128), disk_r, frac, tmp, dst);
+  LAUNCH(fill_disk_kernel, pixgrid(L), dim3(PIX_T), disk_r, frac, tmp, dst);
   return hipGetLastError();
 }
 
@@ -882,16 +931,16 @@ static void box2d(const PostLaunch &L, int R, int in, int out) {
 // Improved Laplacian smoothing of (ob[src], delta, mb[src]) or s_in; writes
 // disparity (NaN where invalid) and valid_mask.
 hipError_t post_hc(const PostLaunch &L, int src, int R, int K, float alpha, int use_delta) {
-  LAUNCH(hc_init_kernel, pixgrid(L), dim3(128), src, use_delta);
+  LAUNCH(hc_init_kernel, pixgrid(L), dim3(PIX_T), src, use_delta);
   box2d(L, R, F_D, F_CNT);  // counts of valid pixels
   box2d(L, R, F_IN, F_IN);  // box(s m)
-  LAUNCH(hc_a_kernel, pixgrid(L), dim3(128), src);
+  LAUNCH(hc_a_kernel, pixgrid(L), dim3(PIX_T), src);
   for (int it = 0; it < K; ++it) {
-    LAUNCH(hc_b_kernel, pixgrid(L), dim3(128), src, (double)alpha, it == 0 ? 1 : 0);
+    LAUNCH(hc_b_kernel, pixgrid(L), dim3(PIX_T), src, (double)alpha, it == 0 ? 1 : 0);
     box2d(L, R, F_IN, F_IN);
-    LAUNCH(hc_d_kernel, pixgrid(L), dim3(128), src);
+    LAUNCH(hc_d_kernel, pixgrid(L), dim3(PIX_T), src);
   }
-  LAUNCH(hc_out_kernel, pixgrid(L), dim3(128), src, K > 0 ? (int)F_D : (int)F_S);
+  LAUNCH(hc_out_kernel, pixgrid(L), dim3(PIX_T), src, K > 0 ? (int)F_D : (int)F_S);
   return hipGetLastError();
 }
 
