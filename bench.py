@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the FP16/BF16, single-pair, uneven-batch and refinement lines")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one plain 256 MiB device copy (calibrates HBM byte counters)")
     return ap.parse_args()
 
 
@@ -88,6 +90,12 @@ def main():
     stream = torch.cuda.current_stream()
     evals_per_step = args.frames * H * W * (DMAX - DMIN + 1)
 
+    if args.copy_probe:
+        a = torch.empty(64 << 20, dtype=torch.int32, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     for _ in range(max(1, args.warmup)):
         B.stereo_match_batched(pairs, params, handle=h)
     torch.cuda.synchronize()
@@ -178,6 +186,16 @@ def extras(B, torch, np, synth, seq, pairs, h):
     ms_m = B.stereo_time_matcher(bp, params, reps=5, handle=h)
     res["uneven64_matcher_ms"] = round(ms_m, 3)
     res["uneven64_matcher_gevals"] = round(bev / ms_m / 1e6, 2)
+    # the paper's candidate range -20..80 (101 values), whole path, one pair
+    pp = synth.paper_pair()
+    Lp, Rp = torch.from_numpy(pp["left"]).cuda(), torch.from_numpy(pp["right"]).cuda()
+    ms = _time(lambda: B.stereo_match(Lp, Rp, -20, 80, WIN, params, handle=h), torch)
+    res["paper_range_ms_per_pair"] = round(ms, 4)
+    res["paper_range_gevals"] = round(H * W * 101 / ms / 1e6, 2)
+    # disparity to 3-D points
+    disp, _ = B.stereo_match(Lp, Rp, -20, 80, WIN, params, handle=h)
+    Q = np.array([[1, 0, 0, -W / 2], [0, 1, 0, -H / 2], [0, 0, 0, 1000.0], [0, 0, 0.2, 0]])
+    res["reproject_ms_per_pair"] = round(_time(lambda: B.st_reproject(disp, Q, handle=h), torch), 4)
     # refinement: forward + backward + step on the 960x540 frame
     d = torch.rand((H, W), device="cuda", dtype=torch.float32) * 100 + 10
     m = torch.ones((H, W), device="cuda", dtype=torch.uint8)

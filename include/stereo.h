@@ -208,6 +208,22 @@ st_status st_fill(st_handle h, const int16_t *o_in, const uint8_t *m_in, int H, 
 st_status st_hc_smooth(st_handle h, const float *s, const uint8_t *m, int H, int W, int R, int K,
                        float alpha, float *out, void *stream);
 
+/* ---- disparity to 3-D points ---- */
+
+/* Reprojection of a disparity map to 3-D points (Section II: after stereo
+ * calibration the depths follow directly from the disparities; the paper's
+ * conversion is the one of Matlab's reconstructScene).  Q is the 4x4
+ * reprojection matrix of the rectified pair (host memory, 16 doubles,
+ * row-major): pixel (x, y) with disparity d gives
+ *   [X Y Z W]^T = Q [x y d 1]^T,   point = (X/W, Y/W, Z/W),
+ * so that for a horizontal rig (focal length f, baseline B, principal point
+ * (cx, cy)) Z = f B / d.  disparity: device, H x W float, NaN = invalid;
+ * xyz: device, H x W x 3 float (x, y, z interleaved), written by the call.
+ * A point is NaN where d is NaN or W == 0.  Arithmetic in FP64, stored as
+ * float.  ST_EINVAL for NULL pointers or a bad shape. */
+st_status st_reproject(st_handle h, const float *disparity, int H, int W, const double *Q,
+                       float *xyz, void *stream);
+
 /* ---- tuning ---- */
 
 /* Time the matcher's tile variants (band height, disparity chunks per

@@ -89,6 +89,13 @@ def _setup(L):
     L.or_fill.restype = C.c_int
     L.or_hc_smooth.argtypes = [C.c_int, C.c_int, f64, u8, C.c_int, C.c_int, C.c_double, f64]
     L.or_hc_smooth.restype = C.c_int
+    L.or_research.argtypes = [u8, u8] + [C.c_int] * 6 + [i32, u8, f64, C.c_int, C.c_double, i32]
+    L.or_research.restype = None
+    L.or_hc_research.argtypes = ([u8, u8] + [C.c_int] * 6 + [i32, u8, C.c_int, C.c_int, C.c_double,
+                                                             C.c_double, C.c_int, f64])
+    L.or_hc_research.restype = C.c_int
+    L.or_reproject.argtypes = [C.c_int, C.c_int, f64, f64, f64]
+    L.or_reproject.restype = None
     vp = C.c_void_p
     L.or_pipeline.argtypes = [u8, u8] + [C.c_int] * 6 + [C.POINTER(Params), f64, u8,
                                                           vp, vp, vp, vp, vp]
@@ -175,6 +182,38 @@ def hc_smooth(s, m, R, K, alpha=0.1):
     out = np.zeros((H, W), np.float64)
     rc = lib().or_hc_smooth(H, W, s, m, R, K, alpha, out)
     assert rc == 0, rc
+    return out
+
+
+def research(left, right, dmin, dmax, win, o, m, d, range_=5, eta=0.01):
+    """One Eq. (4) re-search of every valid pixel around d (float64 H x W)."""
+    L = _c(left, np.uint8); R = _c(right, np.uint8)
+    H, W = L.shape
+    out = np.zeros((H, W), np.int32)
+    lib().or_research(L, R, H, W, W, win, dmin, dmax, _c(o, np.int32), _c(m, np.uint8),
+                      _c(d, np.float64), range_, eta, out)
+    return out
+
+
+def hc_research(left, right, dmin, dmax, win, o, m, R, K, alpha=0.1, eta=0.01, range_=5):
+    """Eqs. (1)-(4): returns (d^K, final o)."""
+    L = _c(left, np.uint8); Rr = _c(right, np.uint8)
+    H, W = L.shape
+    oo = _c(o, np.int32).copy()
+    out = np.zeros((H, W), np.float64)
+    rc = lib().or_hc_research(L, Rr, H, W, W, win, dmin, dmax, oo, _c(m, np.uint8), R, K, alpha,
+                              eta, range_, out)
+    assert rc == 0, rc
+    return out, oo
+
+
+def reproject(disp, Q):
+    """H x W disparities (NaN = invalid) -> H x W x 3 points, Q 4x4 row-major."""
+    d = _c(disp, np.float64)
+    H, W = d.shape
+    q = _c(np.asarray(Q, dtype=np.float64).reshape(16), np.float64)
+    out = np.zeros((H, W, 3), np.float64)
+    lib().or_reproject(H, W, d, q, out)
     return out
 
 

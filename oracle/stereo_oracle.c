@@ -507,6 +507,122 @@ int or_hc_smooth(int H, int W, const double *s, const uint8_t *m, int R, int K, 
   return OR_OK;
 }
 
+/*
+ * Exact ZNCC of the left window at (x, y) and the right window at (x - d, y)
+ * by direct sums (Section II-A): (n*S_LR - S_L*S_R) / sqrt(varN_L * varN_R)
+ * with int64 sums.  Returns NAN when either window leaves the image or has
+ * zero variance (the candidate is not valid).
+ */
+static double zncc_at(const uint8_t *L, const uint8_t *R, int H, int W, int pitch, int win, int y,
+                      int x, int d) {
+  int h = win / 2, xr = x - d;
+  if (!inside(H, W, h, y, x) || xr < h || xr > W - 1 - h) return NAN;
+  int64_t n = (int64_t)win * win, sl = 0, sll = 0, sr = 0, srr = 0, slr = 0;
+  for (int v = -h; v <= h; ++v)
+    for (int u = -h; u <= h; ++u) {
+      int64_t a = L[(int64_t)(y + v) * pitch + x + u], b = R[(int64_t)(y + v) * pitch + xr + u];
+      sl += a; sll += a * a; sr += b; srr += b * b; slr += a * b;
+    }
+  int64_t vl = n * sll - sl * sl, vr = n * srr - sr * sr;
+  if (vl <= 0 || vr <= 0) return NAN;
+  return (double)(n * slr - sl * sr) / sqrt((double)vl * (double)vr);
+}
+
+/*
+ * The re-search of Eq. (4) (Section II-C) for every valid pixel: among the
+ * integer candidates o* in [d - range, d + range] (and in [dmin, dmax]) whose
+ * ZNCC is defined, take the one minimising
+ *     f_zncc(o*) + eta * (o* - d)^2,   f_zncc = 1 / max(z, 1e-3)
+ * (the paper's reciprocal ZNCC, held finite where z <= 0); ties go to the
+ * smaller o*.  A pixel without any defined candidate keeps its o.
+ * o_in / o_out: H*W int32 (may alias), m: mask, d: H*W.
+ */
+void or_research(const uint8_t *L, const uint8_t *R, int H, int W, int pitch, int win, int dmin,
+                 int dmax, const int32_t *o_in, const uint8_t *m, const double *d, int range,
+                 double eta, int32_t *o_out) {
+#pragma omp parallel for
+  for (int y = 0; y < H; ++y)
+    for (int x = 0; x < W; ++x) {
+      int64_t k = (int64_t)y * W + x;
+      int32_t o = o_in[k];
+      if (m[k]) {
+        double lo = ceil(d[k] - range), hi = floor(d[k] + range);
+        if (lo < dmin) lo = dmin;
+        if (hi > dmax) hi = dmax;
+        double best = INFINITY;
+        for (int c = (int)lo; c <= (int)hi; ++c) {
+          double z = zncc_at(L, R, H, W, pitch, win, y, x, c);
+          if (isnan(z)) continue;
+          double cost = 1.0 / (z > 1e-3 ? z : 1e-3) + eta * (c - d[k]) * (c - d[k]);
+          if (cost < best) { best = cost; o = c; }
+        }
+      }
+      o_out[k] = o;
+    }
+}
+
+/*
+ * The refinement of Section II-C with the discrete disparities updated in
+ * every iteration (Eqs. (1)-(4)):  d^0 = o;  for k = 1..K:
+ *     a   = average of o over the valid neighbours          (Eq. 1)
+ *     b   = a - alpha*o - (1 - alpha)*d^{k-1}              (Eq. 2)
+ *     d^k = a - average of b over the valid neighbours      (Eq. 3)
+ *     o   = re-search around d^k                            (Eq. 4; k < K,
+ *           the last update could not change d^K)
+ * o (int32, in/out: the final discrete disparities), out = d^K (NaN where
+ * invalid).
+ */
+int or_hc_research(const uint8_t *L, const uint8_t *R, int H, int W, int pitch, int win, int dmin,
+                   int dmax, int32_t *o, const uint8_t *m, int Rs, int K, double alpha, double eta,
+                   int range, double *out) {
+  int64_t N = (int64_t)H * W;
+  double *od = malloc(sizeof(double) * (size_t)N), *a = malloc(sizeof(double) * (size_t)N);
+  double *b = malloc(sizeof(double) * (size_t)N), *ab = malloc(sizeof(double) * (size_t)N);
+  double *dprev = malloc(sizeof(double) * (size_t)N);
+  if (!od || !a || !b || !ab || !dprev) {
+    free(od); free(a); free(b); free(ab); free(dprev);
+    return OR_ENOMEM;
+  }
+  for (int64_t k = 0; k < N; ++k) dprev[k] = m[k] ? (double)o[k] : NAN;
+  for (int it = 0; it < K; ++it) {
+    for (int64_t k = 0; k < N; ++k) od[k] = (double)o[k];
+    masked_mean(H, W, od, m, Rs, a);
+    for (int64_t k = 0; k < N; ++k)
+      b[k] = m[k] ? a[k] - alpha * od[k] - (1.0 - alpha) * dprev[k] : 0.0;
+    masked_mean(H, W, b, m, Rs, ab);
+    for (int64_t k = 0; k < N; ++k) dprev[k] = m[k] ? a[k] - ab[k] : NAN;
+    if (it < K - 1) or_research(L, R, H, W, pitch, win, dmin, dmax, o, m, dprev, range, eta, o);
+  }
+  if (K == 0)
+    for (int64_t k = 0; k < N; ++k) dprev[k] = m[k] ? (double)o[k] : NAN;
+  memcpy(out, dprev, sizeof(double) * (size_t)N);
+  free(od); free(a); free(b); free(ab); free(dprev);
+  return OR_OK;
+}
+
+/*
+ * Disparity to 3-D points (Section II: after stereo calibration the depths
+ * follow directly from the disparities; the paper's conversion is the one of
+ * Matlab's reconstructScene).  Q is the 4x4 reprojection matrix of the
+ * rectified pair, row-major: [X Y Z W]^T = Q [x y d 1]^T and the point is
+ * (X/W, Y/W, Z/W).  A NaN disparity or W == 0 gives a NaN point.
+ * xyz: H*W*3, interleaved.
+ */
+void or_reproject(int H, int W, const double *disp, const double *Q, double *xyz) {
+  for (int y = 0; y < H; ++y)
+    for (int x = 0; x < W; ++x) {
+      int64_t k = (int64_t)y * W + x;
+      double d = disp[k];
+      double v[4] = {(double)x, (double)y, d, 1.0}, r[4];
+      for (int i = 0; i < 4; ++i) {
+        r[i] = 0.0;
+        for (int j = 0; j < 4; ++j) r[i] += Q[4 * i + j] * v[j];
+      }
+      int ok = !isnan(d) && r[3] != 0.0;
+      for (int c = 0; c < 3; ++c) xyz[3 * k + c] = ok ? r[c] / r[3] : NAN;
+    }
+}
+
 /* Parameters of the whole pipeline (paper constants in the comments). */
 typedef struct {
   int32_t subpixel;       /* 1 */

@@ -11,6 +11,8 @@ from __future__ import annotations
 import ctypes as C
 import os
 
+import numpy as np
+
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libstereo_mi355x.so")
 
@@ -23,7 +25,7 @@ STATUS_NAMES = {0: "ST_OK", -1: "ST_EINVAL", -2: "ST_ENOMEM", -3: "ST_EHIP", -4:
 EXPORTS = ("st_default_params", "st_create", "st_destroy", "st_last_error", "stereo_match",
            "stereo_match_batched", "stereo_refine_forward", "stereo_refine_backward",
            "stereo_refine_step", "stereo_debug_get", "st_window_stats", "st_match_wta",
-           "st_subpixel", "st_lr_check", "st_radial_outlier", "st_fill", "st_hc_smooth",
+           "st_subpixel", "st_lr_check", "st_radial_outlier", "st_fill", "st_hc_smooth", "st_reproject",
            "st_autotune", "st_set_variant", "st_num_variants", "st_variant_name", "st_version",
            "stereo_time_matcher")
 
@@ -83,6 +85,7 @@ def lib() -> C.CDLL:
             "st_radial_outlier": (i32, [vp, vp, vp, i32, i32, i32, f32, vp, vp]),
             "st_fill": (i32, [vp, vp, vp, i32, i32, i32, i32, i32, f32, vp, vp, vp]),
             "st_hc_smooth": (i32, [vp, vp, vp, i32, i32, i32, i32, f32, vp, vp]),
+            "st_reproject": (i32, [vp, vp, i32, i32, vp, vp, vp]),
             "st_autotune": (i32, [vp, i32, i32, i32, i32, i32, i32, C.POINTER(i32), vp]),
             "st_set_variant": (i32, [vp, i32]),
             "stereo_time_matcher": (i32, [vp, C.POINTER(st_pair), i32, C.POINTER(st_params), i32,
@@ -346,6 +349,21 @@ def st_hc_smooth(s, m, R, K, alpha=0.1, handle=None, stream=None):
     _check(lib().st_hc_smooth(_h(handle), s.data_ptr(), m.data_ptr(), H, W, R, K, alpha,
                               out.data_ptr(), _stream(stream)))
     return out
+
+
+def st_reproject(disparity, Q, handle=None, stream=None):
+    """Disparity map (H x W float, device) -> H x W x 3 points with the 4x4
+    reprojection matrix Q (any array-like of 16 numbers, row-major)."""
+    import torch
+    H, W = disparity.shape
+    qv = np.asarray(Q, dtype=np.float64).ravel()
+    if qv.size != 16:
+        raise ValueError("Q must hold 16 numbers")
+    q = (C.c_double * 16)(*qv.tolist())
+    xyz = torch.empty((H, W, 3), dtype=torch.float32, device=disparity.device)
+    _check(lib().st_reproject(_h(handle), disparity.data_ptr(), H, W, q, xyz.data_ptr(),
+                              _stream(stream)))
+    return xyz
 
 
 def st_autotune(H, W, dmin, dmax, win, precision=ST_FP32, handle=None, stream=None) -> int:

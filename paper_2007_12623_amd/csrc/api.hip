@@ -731,6 +731,18 @@ st_status st_fill(st_handle h, const int16_t *o_in, const uint8_t *m_in, int H, 
   return ST_OK;
 }
 
+st_status st_reproject(st_handle h, const float *disparity, int H, int W, const double *Q,
+                       float *xyz, void *stream) {
+  ARG(H >= 1 && W >= 1 && (long long)H * W <= (1LL << 28), "bad shape");
+  ARG(disparity && Q && xyz, "NULL pointer");
+  ARG(h, "NULL handle");
+  hipSetDevice(h->device);
+  Mat4 M;
+  for (int i = 0; i < 16; ++i) M.q[i] = Q[i];
+  HIPCK(launch_reproject(disparity, H, W, M, xyz, (hipStream_t)stream));
+  return ST_OK;
+}
+
 st_status st_hc_smooth(st_handle h, const float *s_in, const uint8_t *m, int H, int W, int R,
                        int K, float alpha, float *out, void *stream) {
   ARG(H >= 1 && W >= 1 && R >= 0 && R <= 2048 && K >= 0 && K <= 64, "bad shape or parameters");

@@ -121,6 +121,10 @@ size_t match_lds_bytes(const MatchPair &P);  // key tiles of one workgroup
 hipError_t launch_window_stats_dense(const uint8_t *img, int H, int W, int pitch, int win,
                                      int32_t *S, int32_t *SS, float *inv, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, int N, uint32_t v, hipStream_t s);
+struct Mat4 {
+  double q[16];
+};
+hipError_t launch_reproject(const float *disp, int H, int W, const Mat4 &Q, float *xyz, hipStream_t s);
 hipError_t post_decode(const PostLaunch &L);
 hipError_t post_subpixel(const PostLaunch &L);
 hipError_t post_lr(const PostLaunch &L, int tol, int dst);

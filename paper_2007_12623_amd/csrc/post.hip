@@ -815,6 +815,134 @@ __global__ __launch_bounds__(256) void box_h_lds_kernel(PostPair one, const Post
   }
 }
 
+// ---- fused smoothing passes: one kernel per masked mean, for R <= HCF_RMAX.
+// A block of 256 threads owns 256 columns (output columns are the middle
+// 256 - 2R) and a segment of rows.  Each thread keeps the vertical window sum
+// of its column while stepping down the rows (adding the entering row,
+// subtracting the leaving one, both computed from the inputs on the fly); the
+// horizontal window sum is a difference of a block-wide prefix sum (wave scan
+// plus wave totals in LDS).  Pass 0 writes a = A(s) (Eq. 1) and the valid
+// counts; pass 1 takes b = a - alpha s - (1-alpha) d_prev (Eq. 2) and writes
+// d = a - A(b) (Eq. 3), in the last iteration straight to the outputs.
+constexpr int HCF_T = 256, HCF_RMAX = 64, HCF_SY = 64;
+enum { F_C = 1, F_D0 = 2, F_D1 = 3 };  // planes of P.f used with F_A below
+
+__device__ __forceinline__ double hc_s_at(const PostPair &P, size_t k, uint8_t mk, int src,
+                                          int use_delta) {
+  if (P.s_in) return (double)gro(P.s_in)[k];
+  const double o = (double)gro(P.ob[src])[k];
+  return (mk == 1 && use_delta) ? o + (double)gro(P.delta)[k] : o;
+}
+
+// Block-wide inclusive prefix sum of one double per thread; buf is a
+// 256-entry LDS row, wt 4 wave totals.  Returns after the row is in buf.
+__device__ __forceinline__ void block_prefix(double v, double *buf, double *wt) {
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const double u = __shfl_up(v, o, 64);
+    if (lane >= o) v += u;
+  }
+  if (lane == 63) wt[wave] = v;
+  __syncthreads();
+  double base = 0.0;
+  for (int w = 0; w < wave; ++w) base += wt[w];
+  buf[t] = v + base;
+  __syncthreads();
+}
+
+template <bool B, int PASS>
+__device__ __forceinline__ void hc_box(PostPair one, const PostPair *__restrict__ many, int src,
+                                       int use_delta, int R, double alpha, int dprev, int dout,
+                                       int last) {
+  PAIR;
+  __shared__ double pre[2][HCF_T], prw[2][HCF_T], wt[2][4], wtw[2][4];
+  const int H = P.H, W = P.W;
+  const int nout = HCF_T - 2 * R;
+  const int xo = blockIdx.x * nout, y0 = blockIdx.y * HCF_SY;
+  if (xo >= W || y0 >= H) return;  // uniform per block
+  const size_t N = (size_t)W * H;
+  const int t = threadIdx.x;
+  const int c = xo - R + t;  // this thread's column
+  const bool cin = c >= 0 && c < W;
+  const GLOBAL uint8_t *m = gro(P.mb[src]);
+  const GLOBAL double *fA = gro(P.f) + (size_t)F_A * N;
+  const GLOBAL double *fD = gro(P.f) + (size_t)(dprev < 0 ? 0 : dprev) * N;
+  // window input of row r at this column: (value, count)
+  auto in = [&](int r, double &w) -> double {
+    w = 0.0;
+    if (!cin || r < 0 || r >= H) return 0.0;
+    const size_t k = (size_t)r * W + c;
+    const uint8_t mk = m[k];
+    if (!mk) return 0.0;
+    w = 1.0;
+    const double sv = hc_s_at(P, k, mk, src, use_delta);
+    if (PASS == 0) return sv;
+    const double dp = dprev < 0 ? sv : fD[k];
+    return fA[k] - alpha * sv - (1.0 - alpha) * dp;
+  };
+  double sv = 0.0, sw = 0.0, w;
+  for (int r = y0 - R; r < y0 + R; ++r) {
+    sv += in(r, w);
+    sw += w;
+  }
+  const int y1 = min(y0 + HCF_SY, H);
+  for (int y = y0; y < y1; ++y) {
+    const int b = y & 1;
+    sv += in(y + R, w);
+    sw += w;
+    block_prefix(sv, pre[b], wt[b]);
+    if (PASS == 0) block_prefix(sw, prw[b], wtw[b]);
+    const int x = c;  // output column of thread t when R <= t < HCF_T - R
+    if (t >= R && t < HCF_T - R && cin) {
+      const size_t k = (size_t)y * W + x;
+      const uint8_t mk = m[k];
+      const double bv = pre[b][t + R] - (t - R - 1 >= 0 ? pre[b][t - R - 1] : 0.0);
+      if (PASS == 0) {
+        const double bw = prw[b][t + R] - (t - R - 1 >= 0 ? prw[b][t - R - 1] : 0.0);
+        grw(P.f)[(size_t)F_A * N + k] = mk ? bv / bw : 0.0;
+        grw(P.f)[(size_t)F_C * N + k] = bw;
+      } else {
+        const double d = mk ? fA[k] - bv / gro(P.f)[(size_t)F_C * N + k] : 0.0;
+        if (last) {
+          grw(P.disparity)[k] = mk ? (float)d : __builtin_nanf("");
+          if (P.valid_mask) grw(P.valid_mask)[k] = mk;  // the smoothing stage entry has none
+        } else {
+          grw(P.f)[(size_t)dout * N + k] = d;
+        }
+      }
+    }
+    sv -= in(y - R, w);
+    sw -= w;
+  }
+}
+
+template <bool B>
+__global__ __launch_bounds__(HCF_T) void hc_mean_s_kernel(PostPair one, const PostPair *__restrict__ many,
+                                                          int src, int use_delta, int R) {
+  hc_box<B, 0>(one, many, src, use_delta, R, 0.0, -1, 0, 0);
+}
+template <bool B>
+__global__ __launch_bounds__(HCF_T) void hc_iter_kernel(PostPair one, const PostPair *__restrict__ many,
+                                                        int src, int use_delta, int R, double alpha,
+                                                        int dprev, int dout, int last) {
+  hc_box<B, 1>(one, many, src, use_delta, R, alpha, dprev, dout, last);
+}
+
+// Output without smoothing (K = 0): s on valid pixels.
+template <bool B>
+__global__ void hc_copy_kernel(PostPair one, const PostPair *__restrict__ many, int src, int use_delta) {
+  PAIR;
+  const int W = P.W, H = P.H;
+  (void)W;
+  (void)H;
+  for_pixels(P, [&](int x, int y, size_t k) {
+    const uint8_t mk = P.mb[src][k];
+    P.disparity[k] = mk ? (float)hc_s_at(P, k, mk, src, use_delta) : __builtin_nanf("");
+    if (P.valid_mask) P.valid_mask[k] = mk;
+  });
+}
+
 // a = A(s) = box(s m) / box(m) on valid pixels (Eq. 1)
 template <bool B>
 __global__ void hc_a_kernel(PostPair one, const PostPair *__restrict__ many, int src) {
@@ -931,6 +1059,20 @@ static void box2d(const PostLaunch &L, int R, int in, int out) {
 // Improved Laplacian smoothing of (ob[src], delta, mb[src]) or s_in; writes
 // disparity (NaN where invalid) and valid_mask.
 hipError_t post_hc(const PostLaunch &L, int src, int R, int K, float alpha, int use_delta) {
+  if (K == 0) {
+    LAUNCH(hc_copy_kernel, pixgrid(L), dim3(PIX_T), src, use_delta);
+    return hipGetLastError();
+  }
+  if (R <= HCF_RMAX) {
+    const dim3 g(ceil_div(L.maxW, HCF_T - 2 * R), ceil_div(L.maxH, HCF_SY), L.npairs);
+    LAUNCH(hc_mean_s_kernel, g, dim3(HCF_T), src, use_delta, R);
+    for (int it = 0; it < K; ++it) {
+      const int dp = it == 0 ? -1 : ((it & 1) ? F_D0 : F_D1), dn = (it & 1) ? F_D1 : F_D0;
+      LAUNCH(hc_iter_kernel, g, dim3(HCF_T), src, use_delta, R, (double)alpha, dp, dn,
+             it == K - 1 ? 1 : 0);
+    }
+    return hipGetLastError();
+  }
   LAUNCH(hc_init_kernel, pixgrid(L), dim3(PIX_T), src, use_delta);
   box2d(L, R, F_D, F_CNT);  // counts of valid pixels
   box2d(L, R, F_IN, F_IN);  // box(s m)
@@ -941,6 +1083,38 @@ hipError_t post_hc(const PostLaunch &L, int src, int R, int K, float alpha, int 
     LAUNCH(hc_d_kernel, pixgrid(L), dim3(PIX_T), src);
   }
   LAUNCH(hc_out_kernel, pixgrid(L), dim3(PIX_T), src, K > 0 ? (int)F_D : (int)F_S);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- reprojection
+// [X Y Z W] = Q [x y d 1], point (X/W, Y/W, Z/W); NaN for a NaN disparity or
+// W == 0.
+__global__ void reproject_kernel(const float *__restrict__ disp, int H, int W, Mat4 Q,
+                                 float *__restrict__ xyz) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+  if (x >= W || y >= H) return;
+  const size_t k = (size_t)y * W + x;
+  const float df = disp[k];
+  float px = __builtin_nanf(""), py = px, pz = px;
+  if (!__builtin_isnan(df)) {
+    const double v[4] = {(double)x, (double)y, (double)df, 1.0};
+    double r[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      r[i] = Q.q[4 * i] * v[0] + Q.q[4 * i + 1] * v[1] + Q.q[4 * i + 2] * v[2] + Q.q[4 * i + 3] * v[3];
+    if (r[3] != 0.0) {
+      px = (float)(r[0] / r[3]);
+      py = (float)(r[1] / r[3]);
+      pz = (float)(r[2] / r[3]);
+    }
+  }
+  xyz[3 * k] = px;
+  xyz[3 * k + 1] = py;
+  xyz[3 * k + 2] = pz;
+}
+
+hipError_t launch_reproject(const float *disp, int H, int W, const Mat4 &Q, float *xyz, hipStream_t s) {
+  hipLaunchKernelGGL(reproject_kernel, dim3(ceil_div(W, 256), H), dim3(256), 0, s, disp, H, W, Q, xyz);
   return hipGetLastError();
 }
 

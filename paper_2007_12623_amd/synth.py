@@ -47,6 +47,7 @@ SEED_C2 = 2002
 SEED_C3 = 3003
 SEED_C4 = 4004
 SEED_C5 = 5005
+SEED_PAPER = 6006
 
 C4_SHAPES = ((240, 320), (480, 640), (540, 960), (720, 1280))  # (H, W)
 
@@ -84,7 +85,7 @@ def _flat_patches(rng, canvas, H, W, oy, ox):
     return placed
 
 
-def _disparity_field(rng, Hc, Wc, H, W, dmax, oy, ox):
+def _disparity_field(rng, Hc, Wc, H, W, dmax, oy, ox, dmin=0):
     """Field over the whole canvas; image pixel (x, y) sits at (ox+x, oy+y)."""
     yy, xx = np.mgrid[0:Hc, 0:Wc].astype(np.float64)
     xi = xx - ox
@@ -98,12 +99,12 @@ def _disparity_field(rng, Hc, Wc, H, W, dmax, oy, ox):
     cx = rng.uniform(0.3, 0.7) * W
     r2 = (xi - cx) ** 2 + (yi - cy) ** 2
     f = f + 0.2 * dmax * np.sqrt(np.maximum(0.0, 1.0 - r2 / rho**2))
-    # affine map so that the image window spans [1, dmax-2]
+    # affine map so that the image window spans [dmin+1, dmax-2]
     win = f[oy:oy + H, ox:ox + W]
     lo, hi = win.min(), win.max()
     span = max(hi - lo, 1e-9)
-    d = 1.0 + (f - lo) / span * (dmax - 3.0)
-    return np.clip(d, 1.0, dmax - 2.0)
+    d = (dmin + 1.0) + (f - lo) / span * (dmax - dmin - 3.0)
+    return np.clip(d, dmin + 1.0, dmax - 2.0)
 
 
 def _lerp_rows(rows: np.ndarray, u: np.ndarray) -> np.ndarray:
@@ -120,8 +121,9 @@ def _lerp_rows(rows: np.ndarray, u: np.ndarray) -> np.ndarray:
 class Scene:
     """A seeded texture canvas plus disparity field; frames are crops."""
 
-    def __init__(self, H: int, W: int, dmax: int, seed: int):
-        self.H, self.W, self.dmax, self.seed = H, W, dmax, seed
+    def __init__(self, H: int, W: int, dmax: int, seed: int, dmin: int = 0):
+        assert -PAD < dmin < dmax
+        self.H, self.W, self.dmax, self.dmin, self.seed = H, W, dmax, dmin, seed
         self.rng = np.random.default_rng(seed)
         self.Hc = H + 2 * PAD
         self.Wc = W + 2 * PAD + dmax + 2
@@ -131,7 +133,7 @@ class Scene:
         self.patches = _flat_patches(self.rng, canvas, H, W, self.oy, self.ox)
         self.canvas = canvas
         self.field = _disparity_field(self.rng, self.Hc, self.Wc, H, W, dmax,
-                                      self.oy, self.ox)
+                                      self.oy, self.ox, dmin)
 
     def frame(self, ty: int = 0, tx: int = 0, noise_rng=None):
         """Left/right uint8 images and ground truth for a shift (ty, tx)."""
@@ -160,9 +162,9 @@ class Scene:
                 "gt_right": gt_right, "gt_left": gt_left}
 
 
-def make_pair(H: int, W: int, dmax: int, seed: int):
-    """One seeded pair (frame 0 of a scene)."""
-    return Scene(H, W, dmax, seed).frame(0, 0)
+def make_pair(H: int, W: int, dmax: int, seed: int, dmin: int = 0):
+    """One seeded pair (frame 0 of a scene); disparities in [dmin+1, dmax-2]."""
+    return Scene(H, W, dmax, seed, dmin).frame(0, 0)
 
 
 def make_sequence(H: int, W: int, dmax: int, seed: int, n_frames: int):
@@ -195,6 +197,12 @@ def c2_sequence(n_frames: int = 30):
 def c5_sequence(n_frames: int = 30):
     """1920x1080, disparities 0..255, 15x15 window, drifting sequence."""
     return make_sequence(1080, 1920, 255, SEED_C5, n_frames)
+
+
+def paper_pair():
+    """960x540 with the paper's candidate range -20..80 (101 values), 11x11
+    window (Section IV's recordings; Section II-A's window)."""
+    return make_pair(540, 960, 80, SEED_PAPER, dmin=-20)
 
 
 def c4_layout(seed: int = SEED_C4, n_pairs: int = 64):

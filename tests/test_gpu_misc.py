@@ -88,3 +88,18 @@ def test_debug_get_errors(B):
 def test_create_bad_device(B):
     h = C.c_void_p()
     assert B.lib().st_create(C.byref(h), 99) == B.ST_ENODEV
+
+
+def test_reproject_matches_oracle(B, orc):
+    r = np.random.default_rng(12)
+    H, Ww = 70, 130
+    d = r.uniform(-5.0, 90.0, size=(H, Ww)).astype(np.float32)
+    d[r.random((H, Ww)) < 0.1] = np.nan
+    d[0, :4] = 0.0
+    Q = r.normal(size=(4, 4))
+    Q[3, 2] = 0.2
+    g = np_(B.st_reproject(cu(d), Q))
+    ref = orc.reproject(d.astype(np.float64), Q)
+    assert np.array_equal(np.isnan(g), np.isnan(ref))
+    fin = ~np.isnan(ref)
+    np.testing.assert_allclose(g[fin], ref[fin].astype(np.float32), rtol=1e-6, atol=1e-6)

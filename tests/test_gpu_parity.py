@@ -107,6 +107,15 @@ def test_match_full_size_frame(B, orc):
     _check_wta(None, ref, oL, mL, oR, mR)
 
 
+def test_match_paper_range_frame(B, orc):
+    """The paper's candidate range -20..80 (101 values) at 960x540, 11x11."""
+    p = synth.paper_pair()
+    L, R = p["left"], p["right"]
+    oL, mL, oR, mR = (np_(t) for t in B.st_match_wta(cu(L), cu(R), -20, 80, 11))
+    ref = orc.match(L, R, -20, 80, 11)
+    _check_wta(None, ref, oL, mL, oR, mR)
+
+
 def test_subpixel_exact_z(B, orc):
     L, R = _pair(60, 250, 31, 31)
     ref = orc.match(L, R, 0, 31, 7)
@@ -254,6 +263,12 @@ def test_end_to_end_full_pipeline(B, orc):
     seq = synth.c2_sequence(1)
     _end_to_end(B, orc, seq[0]["left"], seq[0]["right"], 0, 127, 11, B.preset("full"),
                 orc.params_c2())
+
+
+def test_end_to_end_paper_range(B, orc):
+    """Signed range -20..80 through the whole pipeline."""
+    p = synth.make_pair(200, 420, 80, 6106, dmin=-20)
+    _end_to_end(B, orc, p["left"], p["right"], -20, 80, 11, B.preset("full"), orc.params_c2())
 
 
 def test_pipeline_options(B, orc):

@@ -344,3 +344,39 @@ def test_pipeline_recovers_synthetic_disparity(orc):
     v = mask > 0
     assert v.mean() > 0.8
     assert np.nanmedian(np.abs(disp[v & ~np.isnan(gt)] - gt[v & ~np.isnan(gt)])) < 0.5
+
+
+def _rig_q(f, B, cx, cy):
+    # reprojection matrix of a horizontal rectified rig: W = d / B
+    return np.array([[1, 0, 0, -cx], [0, 1, 0, -cy], [0, 0, 0, f], [0, 0, 1.0 / B, 0]], np.float64)
+
+
+def test_reproject_closed_form(orc):
+    """Section II's depth from disparity: Z = f B / d, X = (x - cx) Z / f,
+    Y = (y - cy) Z / f for a horizontal rig; NaN for invalid or zero
+    disparity (W = 0)."""
+    f, Bl, cx, cy = 800.0, 5.0, 31.5, 20.25
+    rng = np.random.default_rng(4)
+    H, W = 40, 64
+    d = rng.uniform(2.0, 90.0, size=(H, W))
+    d[3, 5] = np.nan
+    d[7, 9] = 0.0
+    xyz = orc.reproject(d, _rig_q(f, Bl, cx, cy))
+    yy, xx = np.mgrid[0:H, 0:W].astype(np.float64)
+    ok = np.isfinite(d) & (d != 0)
+    Z = f * Bl / np.where(ok, d, 1.0)
+    np.testing.assert_allclose(xyz[..., 2][ok], Z[ok], rtol=1e-12)
+    np.testing.assert_allclose(xyz[..., 0][ok], ((xx - cx) * Z / f)[ok], rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(xyz[..., 1][ok], ((yy - cy) * Z / f)[ok], rtol=1e-12, atol=1e-12)
+    assert np.isnan(xyz[3, 5]).all() and np.isnan(xyz[7, 9]).all()
+
+
+def test_reproject_fronto_parallel_plane(orc):
+    """A constant disparity is a plane at constant depth whose points are
+    evenly spaced by Z / f per pixel."""
+    f, Bl = 1000.0, 4.0
+    d = np.full((8, 12), 40.0)
+    xyz = orc.reproject(d, _rig_q(f, Bl, 0.0, 0.0))
+    assert np.allclose(xyz[..., 2], 100.0, rtol=0, atol=1e-12)
+    assert np.allclose(np.diff(xyz[..., 0], axis=1), 0.1, atol=1e-12)
+    assert np.allclose(np.diff(xyz[..., 1], axis=0), 0.1, atol=1e-12)

@@ -1,0 +1,93 @@
+"""Pins of the Eq. (4) re-search (Section II-C) in the oracle: limits where
+the cost reduces to a known answer, a brute-force textbook-ZNCC argmin, and
+the reduction of Eqs. (1)-(4) to the plain smoothing when no re-search runs."""
+import numpy as np
+
+from paper_2007_12623_amd import synth
+
+
+def _shift_pair(k, H=40, W=90, seed=3):
+    r = np.random.default_rng(seed)
+    wide = r.integers(0, 256, size=(H, W + k), dtype=np.uint8)
+    return wide[:, :W].copy(), wide[:, k:].copy()
+
+
+def test_large_eta_rounds_d(orc):
+    """eta -> infinity: the smoothing term decides; o = the integer nearest d."""
+    p = synth.make_pair(50, 120, 31, 21)
+    L, R = p["left"], p["right"]
+    r = np.random.default_rng(1)
+    d = r.uniform(8.0, 24.0, size=L.shape)
+    d = np.where(np.abs(d - np.floor(d) - 0.5) < 0.05, d + 0.2, d)  # keep off .5
+    m = np.zeros(L.shape, np.uint8)
+    m[10:40, 40:110] = 1
+    o0 = np.full(L.shape, 7, np.int32)
+    o = orc.research(L, R, 0, 31, 7, o0, m, d, 5, 1e9)
+    sel = m == 1
+    assert np.array_equal(o[sel], np.rint(d[sel]).astype(np.int32))
+    assert np.array_equal(o[~sel], o0[~sel])
+
+
+def test_zero_eta_finds_exact_shift(orc):
+    """eta = 0 on a noise-free integer shift: z = 1 only at the shift, and
+    1/z is smallest there."""
+    k = 6
+    L, R = _shift_pair(k)
+    H, W = L.shape
+    m = np.zeros((H, W), np.uint8)
+    m[5:35, 20:80] = 1
+    d = np.full((H, W), k + 3.3)
+    o = orc.research(L, R, 0, 20, 9, np.zeros((H, W), np.int32), m, d, 5, 0.0)
+    assert (o[m == 1] == k).all()
+
+
+def test_cost_argmin_brute_force(orc):
+    """The chosen candidate minimises 1/max(z, 1e-3) + eta (c - d)^2 with z
+    the textbook ZNCC of the two windows."""
+    p = synth.make_pair(40, 100, 31, 5)
+    L, R = p["left"].astype(np.float64), p["right"].astype(np.float64)
+    win, h, eta = 7, 3, 0.01
+    r = np.random.default_rng(9)
+    d = r.uniform(3.0, 28.0, size=L.shape)
+    m = np.ones(L.shape, np.uint8)
+    o = orc.research(p["left"], p["right"], 0, 31, win, np.zeros(L.shape, np.int32), m, d, 5, eta)
+    for (y, x) in [(10, 40), (20, 60), (30, 80), (15, 35), (25, 95)]:
+        best, arg = np.inf, None
+        for c in range(max(0, int(np.ceil(d[y, x] - 5))), min(31, int(np.floor(d[y, x] + 5))) + 1):
+            xr = x - c
+            if not (h <= x <= L.shape[1] - 1 - h and h <= xr <= L.shape[1] - 1 - h):
+                continue
+            a = L[y - h:y + h + 1, x - h:x + h + 1].ravel()
+            b = R[y - h:y + h + 1, xr - h:xr + h + 1].ravel()
+            z = np.corrcoef(a, b)[0, 1]
+            cost = 1.0 / max(z, 1e-3) + eta * (c - d[y, x]) ** 2
+            if cost < best - 1e-12:
+                best, arg = cost, c
+        assert o[y, x] == arg, (y, x)
+
+
+def test_one_iteration_is_plain_smoothing(orc):
+    """K = 1: no re-search runs before the output, so Eqs. (1)-(4) give the
+    improved Laplacian smoothing of o."""
+    p = synth.make_pair(40, 80, 31, 8)
+    r = np.random.default_rng(2)
+    o = r.integers(5, 25, size=(40, 80)).astype(np.int32)
+    m = (r.random((40, 80)) > 0.2).astype(np.uint8)
+    d, oo = orc.hc_research(p["left"], p["right"], 0, 31, 7, o, m, 3, 1, 0.1, 0.01, 5)
+    ref = orc.hc_smooth(o.astype(np.float64), m, 3, 1, 0.1)
+    v = m == 1
+    np.testing.assert_allclose(d[v], ref[v], rtol=0, atol=1e-12)
+    assert np.isnan(d[~v]).all() and np.array_equal(oo, o)
+
+
+def test_exact_shift_is_a_fixed_point(orc):
+    """A noise-free integer shift with o = k everywhere: smoothing keeps
+    d = k and the re-search keeps o = k."""
+    k = 4
+    L, R = _shift_pair(k, 50, 100, 11)
+    m = np.zeros(L.shape, np.uint8)
+    m[6:44, 12:94] = 1
+    o = np.where(m == 1, k, 0).astype(np.int32)
+    d, oo = orc.hc_research(L, R, 0, 15, 7, o, m, 4, 3, 0.1, 0.01, 5)
+    np.testing.assert_allclose(d[m == 1], k, atol=1e-12)
+    assert (oo[m == 1] == k).all()
