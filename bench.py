@@ -47,6 +47,29 @@ def parse():
     return ap.parse_args()
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "match_persistent_960x540x128_hbm.md")
+MATCH_SRC = os.path.join(ROOT, "paper_2007_12623_amd", "csrc", "match.hip")
+
+
+def recorded_traffic():
+    """HBM bytes per matcher launch from the committed FETCH_SIZE/WRITE_SIZE
+    summary, or None when the matcher source has changed since."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_FILE).read()
+        sha = hashlib.sha256(open(MATCH_SRC, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    vals = dict(line.split(":", 1) for line in text.splitlines()
+                if line.startswith(("match_hip_sha256:", "traffic_bytes_per_launch:")))
+    if vals.get("match_hip_sha256", "").strip() != sha:
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(seq, seconds):
     """The oracle as it stands, on the host cores, over whole frames of the
     same workload until about `seconds` have passed (at least one frame)."""
@@ -134,7 +157,7 @@ def main():
                    "win": WIN},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": VALU_PEAK_TOPS,
                      "unit": "TOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
-                     "traffic": None, "kernel": "match_persistent_kernel",
+                     "traffic": recorded_traffic(), "kernel": "match_persistent_kernel",
                      "kernel_ms": round(matcher_ms, 4), "ops_per_eval": OPS_PER_EVAL},
     }
     if not args.no_extras:
@@ -186,6 +209,10 @@ def extras(B, torch, np, synth, seq, pairs, h):
     ms_m = B.stereo_time_matcher(bp, params, reps=5, handle=h)
     res["uneven64_matcher_ms"] = round(ms_m, 3)
     res["uneven64_matcher_gevals"] = round(bev / ms_m / 1e6, 2)
+    # the Eq. (4) re-search inside the smoothing (K = 3, radius 15)
+    pr = B.preset("full", research=1)
+    res["research_ms_per_pair"] = round(
+        _time(lambda: B.stereo_match(L0, R0, DMIN, DMAX, WIN, pr, handle=h), torch), 4)
     # the paper's candidate range -20..80 (101 values), whole path, one pair
     pp = synth.paper_pair()
     Lp, Rp = torch.from_numpy(pp["left"]).cuda(), torch.from_numpy(pp["right"]).cuda()

@@ -69,6 +69,12 @@ typedef struct {
   float smooth_alpha;         /* Eq. (2) weight (0.1) */
   int32_t precision;          /* st_precision of image and cost storage */
   int32_t debug_outputs;      /* 1: keep intermediates for stereo_debug_get */
+  int32_t research;           /* 1: Eq. (4) - the discrete disparities o are
+                                 re-searched around d in every smoothing
+                                 iteration and Eqs. (1)-(2) use o (Section
+                                 II-C); 0: smoothing of s = o + delta */
+  int32_t research_range;     /* half width of the re-search window (5) */
+  float research_eta;         /* weight of (o* - d)^2 in Eq. (4) (0.01) */
 } st_params;
 
 /* Fill *p with the paper's constants (Section II, Appendix of constants):
@@ -207,6 +213,20 @@ st_status st_fill(st_handle h, const int16_t *o_in, const uint8_t *m_in, int H, 
  * out is NaN where m == 0. */
 st_status st_hc_smooth(st_handle h, const float *s, const uint8_t *m, int H, int W, int R, int K,
                        float alpha, float *out, void *stream);
+
+/* One Eq. (4) re-search (Section II-C) of every pixel with m != 0: among the
+ * integers c in [d - range, d + range] and [dmin, dmax] whose ZNCC is
+ * defined (both windows inside the image, non-zero variances), the c
+ * minimising 1/max(z, 1e-3) + eta (c - d)^2, ties to the smaller c (the
+ * paper's reciprocal ZNCC held finite where z <= 0); a pixel without a
+ * defined candidate keeps o_in.  z is exact (integer window sums, FP64
+ * normalisation).  left/right: device uint8 with pitch; o_in, o_out: device
+ * int16 H x W (must not alias); m: device uint8 H x W; d: device FP64 H x W.
+ * ST_EINVAL for bad shapes, range outside [0, 64], eta < 0 or NULL pointers. */
+st_status st_research(st_handle h, const uint8_t *left, const uint8_t *right, int H, int W,
+                      int pitch, int dmin, int dmax, int win, const int16_t *o_in,
+                      const uint8_t *m, const double *d, int range, float eta, int16_t *o_out,
+                      void *stream);
 
 /* ---- disparity to 3-D points ---- */
 

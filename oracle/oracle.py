@@ -51,14 +51,17 @@ class Params(C.Structure):
                 ("radial_thresh", C.c_double), ("fill_radial_r", C.c_int32),
                 ("fill_min_lines", C.c_int32), ("fill_disk_r", C.c_int32),
                 ("fill_disk_frac", C.c_double), ("smooth_radius", C.c_int32),
-                ("smooth_iters", C.c_int32), ("smooth_alpha", C.c_double)]
+                ("smooth_iters", C.c_int32), ("smooth_alpha", C.c_double),
+                ("research", C.c_int32), ("research_range", C.c_int32),
+                ("research_eta", C.c_double)]
 
 
 def params_c1(**kw):
     """320x240 setting: LR check, one fill pass, 5x5 (R=2) smoothing, K=1."""
     p = dict(subpixel=1, lr_check=1, lr_tol=1, radial_iters=0, radial_r0=10, radial_dr=10,
              radial_thresh=2.5, fill_radial_r=50, fill_min_lines=2, fill_disk_r=20,
-             fill_disk_frac=0.25, smooth_radius=2, smooth_iters=1, smooth_alpha=0.1)
+             fill_disk_frac=0.25, smooth_radius=2, smooth_iters=1, smooth_alpha=0.1, research=0,
+             research_range=5, research_eta=0.01)
     p.update(kw)
     return Params(**p)
 
@@ -67,7 +70,8 @@ def params_c2(**kw):
     """Full pipeline: 3 outlier/fill alternations r=10,20,30, R=15, K=3."""
     p = dict(subpixel=1, lr_check=1, lr_tol=1, radial_iters=3, radial_r0=10, radial_dr=10,
              radial_thresh=2.5, fill_radial_r=50, fill_min_lines=2, fill_disk_r=20,
-             fill_disk_frac=0.25, smooth_radius=15, smooth_iters=3, smooth_alpha=0.1)
+             fill_disk_frac=0.25, smooth_radius=15, smooth_iters=3, smooth_alpha=0.1, research=0,
+             research_range=5, research_eta=0.01)
     p.update(kw)
     return Params(**p)
 

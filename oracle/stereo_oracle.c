@@ -639,6 +639,9 @@ typedef struct {
   int32_t smooth_radius;  /* 15 px (Section II-C) */
   int32_t smooth_iters;   /* 3 */
   double smooth_alpha;    /* 0.1 */
+  int32_t research;       /* 1: Eq. (4) re-search inside the smoothing */
+  int32_t research_range; /* 5 px */
+  double research_eta;    /* 0.01 */
 } or_params;
 
 /*
@@ -688,7 +691,11 @@ int or_pipeline(const uint8_t *L, const uint8_t *R, int H, int W, int pitch, int
   }
   if (o_post) memcpy(o_post, oL, sizeof(int32_t) * (size_t)N);
   for (int64_t k = 0; k < N; ++k) s[k] = mm[k] == 1 ? (double)oL[k] + dl[k] : (double)oL[k];
-  if (p->smooth_iters > 0) {
+  if (p->research) {
+    rc = or_hc_research(L, R, H, W, pitch, win, dmin, dmax, oL, mm, p->smooth_radius,
+                        p->smooth_iters, p->smooth_alpha, p->research_eta, p->research_range, disp);
+    if (rc) goto done;
+  } else if (p->smooth_iters > 0) {
     rc = or_hc_smooth(H, W, s, mm, p->smooth_radius, p->smooth_iters, p->smooth_alpha, disp);
     if (rc) goto done;
   } else {

@@ -25,7 +25,7 @@ STATUS_NAMES = {0: "ST_OK", -1: "ST_EINVAL", -2: "ST_ENOMEM", -3: "ST_EHIP", -4:
 EXPORTS = ("st_default_params", "st_create", "st_destroy", "st_last_error", "stereo_match",
            "stereo_match_batched", "stereo_refine_forward", "stereo_refine_backward",
            "stereo_refine_step", "stereo_debug_get", "st_window_stats", "st_match_wta",
-           "st_subpixel", "st_lr_check", "st_radial_outlier", "st_fill", "st_hc_smooth", "st_reproject",
+           "st_subpixel", "st_lr_check", "st_radial_outlier", "st_fill", "st_hc_smooth", "st_reproject", "st_research",
            "st_autotune", "st_set_variant", "st_num_variants", "st_variant_name", "st_version",
            "stereo_time_matcher")
 
@@ -44,7 +44,8 @@ class st_params(C.Structure):
                 ("fill_disk_r", C.c_int32), ("fill_disk_min_frac", C.c_float),
                 ("smooth_radius", C.c_int32), ("smooth_iters", C.c_int32),
                 ("smooth_alpha", C.c_float), ("precision", C.c_int32),
-                ("debug_outputs", C.c_int32)]
+                ("debug_outputs", C.c_int32), ("research", C.c_int32),
+                ("research_range", C.c_int32), ("research_eta", C.c_float)]
 
 
 class st_pair(C.Structure):
@@ -86,6 +87,7 @@ def lib() -> C.CDLL:
             "st_fill": (i32, [vp, vp, vp, i32, i32, i32, i32, i32, f32, vp, vp, vp]),
             "st_hc_smooth": (i32, [vp, vp, vp, i32, i32, i32, i32, f32, vp, vp]),
             "st_reproject": (i32, [vp, vp, i32, i32, vp, vp, vp]),
+            "st_research": (i32, [vp, vp, vp] + [i32] * 6 + [vp, vp, vp, i32, f32, vp, vp]),
             "st_autotune": (i32, [vp, i32, i32, i32, i32, i32, i32, C.POINTER(i32), vp]),
             "st_set_variant": (i32, [vp, i32]),
             "stereo_time_matcher": (i32, [vp, C.POINTER(st_pair), i32, C.POINTER(st_params), i32,
@@ -348,6 +350,18 @@ def st_hc_smooth(s, m, R, K, alpha=0.1, handle=None, stream=None):
     out = torch.empty((H, W), dtype=torch.float32, device=s.device)
     _check(lib().st_hc_smooth(_h(handle), s.data_ptr(), m.data_ptr(), H, W, R, K, alpha,
                               out.data_ptr(), _stream(stream)))
+    return out
+
+
+def st_research(left, right, dmin, dmax, win, o, m, d, range_=5, eta=0.01, handle=None,
+                stream=None):
+    """One Eq. (4) re-search: new int16 disparities around d (float64)."""
+    import torch
+    H, W = left.shape
+    out = torch.empty_like(o)
+    _check(lib().st_research(_h(handle), left.data_ptr(), right.data_ptr(), H, W, left.stride(0),
+                             dmin, dmax, win, o.data_ptr(), m.data_ptr(), d.data_ptr(), range_,
+                             eta, out.data_ptr(), _stream(stream)))
     return out
 
 

@@ -160,6 +160,10 @@ static st_status check_params(const st_params *p) {
   ARG(p->fill_disk_min_frac >= 0.0f && p->fill_disk_min_frac <= 1.0f, "fill_disk_min_frac not in [0,1]");
   ARG(p->smooth_radius >= 0 && p->smooth_radius <= 2048, "smooth_radius out of range");
   ARG(p->smooth_iters >= 0 && p->smooth_iters <= 64, "smooth_iters out of range");
+  ARG(p->research == 0 || p->research == 1, "research must be 0 or 1");
+  ARG(p->research_range >= 0 && p->research_range <= 64, "research_range out of range");
+  ARG(p->research_eta >= 0.0f, "research_eta < 0");
+  ARG(!p->research || p->smooth_radius <= 64, "the Eq. (4) re-search needs smooth_radius <= 64");
   return ST_OK;
 }
 
@@ -384,7 +388,8 @@ static hipError_t post_stages(const PostLaunch &L, const st_params &p, const Deb
     ck(hipMemcpyAsync(dbg->o, L.one.ob[cur], 2 * dbg->N, hipMemcpyDeviceToDevice, L.s));
     ck(hipMemcpyAsync(dbg->m, L.one.mb[cur], dbg->N, hipMemcpyDeviceToDevice, L.s));
   }
-  ck(post_hc(L, cur, p.smooth_radius, p.smooth_iters, p.smooth_alpha, p.subpixel));
+  ck(post_hc(L, cur, p.smooth_radius, p.smooth_iters, p.smooth_alpha, p.subpixel, p.research,
+             p.research_range, p.research_eta));
   return e;
 }
 
@@ -414,6 +419,9 @@ void st_default_params(st_params *p) {
   p->smooth_alpha = 0.1f;
   p->precision = ST_FP32;
   p->debug_outputs = 0;
+  p->research = 0;
+  p->research_range = 5;
+  p->research_eta = 0.01f;
 }
 
 const char *st_last_error(void) { return g_err.c_str(); }
@@ -731,6 +739,44 @@ st_status st_fill(st_handle h, const int16_t *o_in, const uint8_t *m_in, int H, 
   return ST_OK;
 }
 
+st_status st_research(st_handle h, const uint8_t *left, const uint8_t *right, int H, int W,
+                      int pitch, int dmin, int dmax, int win, const int16_t *o_in,
+                      const uint8_t *m, const double *d, int range, float eta, int16_t *o_out,
+                      void *stream) {
+  st_status rc = check_shape(H, W, pitch, dmin, dmax, win);
+  if (rc) return rc;
+  ARG(range >= 0 && range <= 64 && eta >= 0.0f, "bad range or eta");
+  ARG(left && right && o_in && m && d && o_out, "NULL pointer");
+  ARG((const void *)o_in != (const void *)o_out, "o_out aliases o_in");
+  ARG(h, "NULL handle");
+  hipSetDevice(h->device);
+  hipStream_t s = (hipStream_t)stream;
+  const size_t N = (size_t)H * W;
+  HIPCK(grow(h, h->ws, 16 * N + 1024, false) == ST_OK ? hipSuccess : hipErrorOutOfMemory);
+  PostPair Q{};
+  Q.left = left;
+  Q.right = right;
+  Q.H = H;
+  Q.W = W;
+  Q.pitch = pitch;
+  Q.win = win;
+  Q.dmin = dmin;
+  Q.dmax = dmax;
+  int32_t *base = (int32_t *)h->ws.p;
+  Q.SL = base;
+  Q.SSL = base + N;
+  Q.SR = base + 2 * N;
+  Q.SSR = base + 3 * N;
+  HIPCK(launch_window_stats_dense(left, H, W, pitch, win, base, base + N, nullptr, s));
+  HIPCK(launch_window_stats_dense(right, H, W, pitch, win, base + 2 * N, base + 3 * N, nullptr, s));
+  Q.ob[0] = const_cast<int16_t *>(o_in);
+  Q.mb[0] = const_cast<uint8_t *>(m);
+  Q.ob[1] = o_out;
+  Q.f = const_cast<double *>(d);
+  HIPCK(post_research(single_launch(Q, s), 0, 0, 1, 0, range, eta));
+  return ST_OK;
+}
+
 st_status st_reproject(st_handle h, const float *disparity, int H, int W, const double *Q,
                        float *xyz, void *stream) {
   ARG(H >= 1 && W >= 1 && (long long)H * W <= (1LL << 28), "bad shape");
@@ -759,7 +805,7 @@ st_status st_hc_smooth(st_handle h, const float *s_in, const uint8_t *m, int H, 
   Q.f = (double *)h->ws.p;
   Q.disparity = out;
   Q.valid_mask = nullptr;
-  HIPCK(post_hc(single_launch(Q, (hipStream_t)stream), 0, R, K, alpha, 0));
+  HIPCK(post_hc(single_launch(Q, (hipStream_t)stream), 0, R, K, alpha, 0, 0, 0, 0.0f));
   return ST_OK;
 }
 

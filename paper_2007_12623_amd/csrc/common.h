@@ -131,7 +131,12 @@ hipError_t post_lr(const PostLaunch &L, int tol, int dst);
 hipError_t post_outlier(const PostLaunch &L, int r, float thresh, int src, int dst);
 hipError_t post_fill(const PostLaunch &L, int radial_r, int min_lines, int disk_r, float frac,
                      int src, int tmp, int dst);
-hipError_t post_hc(const PostLaunch &L, int src, int R, int K, float alpha, int use_delta);
+hipError_t post_hc(const PostLaunch &L, int src, int R, int K, float alpha, int use_delta,
+                   int research, int range, float eta);
+// one Eq. (4) re-search: o from ob[osrc], mask mb[msrc], d from FP64 plane
+// dplane of f; the new o goes to ob[odst]
+hipError_t post_research(const PostLaunch &L, int osrc, int msrc, int odst, int dplane, int range,
+                         float eta);
 int refine_planes();
 int refine_partials(int H, int W);
 hipError_t launch_refine_forward(const RefineArgs &A, hipStream_t s);

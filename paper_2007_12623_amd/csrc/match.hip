@@ -492,77 +492,102 @@ __global__ void prep_planes_kernel(PrepPair one, const PrepPair *many) {
   }
 }
 
-// Window sums S = sum I, SS = sum I^2 (exact ints) and 1/sqrt(n SS - S^2)
-// computed in FP64, for every pixel of one image; 0 / NaN where the window
-// leaves the image, NaN where it is flat.  side 0: left image (padded plane
-// holds 128 n - S), side 1: right image (padded plane holds S), side 2:
-// dense outputs only (PrepPair fields SL, SSL, invLd).
-constexpr int WS_BX = 32, WS_BY = 8, WS_HMAX = 7;
+// Window sums S = sum I, SS = sum I^2 and 1/sqrt(n SS - S^2) of every pixel
+// whose window lies inside the image (0 / NaN elsewhere).  side 0: left
+// image (dense and padded planes), 1: right image, 2: dense planes only.
+// A block of WS_T threads owns WS_T columns; each thread keeps the vertical
+// window sums of its column down a segment of WS_SY rows and the horizontal
+// sums are differences of a block prefix sum (wave scans plus wave totals in
+// LDS).  Output columns of a block are WS_T - 2 WS_HMAX wide for every window.
+constexpr int WS_T = 256, WS_SY = 64, WS_HMAX = 7, WS_NOUT = WS_T - 2 * WS_HMAX;
+
+__device__ __forceinline__ void block_prefix_i2(int &a, int &b, int (*wt)[4]) {
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int ua = __shfl_up(a, o, 64), ub = __shfl_up(b, o, 64);
+    if (lane >= o) {
+      a += ua;
+      b += ub;
+    }
+  }
+  if (lane == 63) {
+    wt[0][wave] = a;
+    wt[1][wave] = b;
+  }
+  __syncthreads();
+  for (int w = 0; w < wave; ++w) {
+    a += wt[0][w];
+    b += wt[1][w];
+  }
+}
+
 template <bool B>
-__global__ __launch_bounds__(256) void window_stats_kernel(PrepPair one, const PrepPair *many,
-                                                           int side) {
+__global__ __launch_bounds__(WS_T) void window_stats_kernel(PrepPair one, const PrepPair *many,
+                                                            int side) {
   const PrepPair &P = B ? many[blockIdx.z] : one;
-  __shared__ uint8_t tile[WS_BY + 2 * WS_HMAX][WS_BX + 2 * WS_HMAX];
-  __shared__ int cs[WS_BY][WS_BX + 2 * WS_HMAX];
-  __shared__ int css[WS_BY][WS_BX + 2 * WS_HMAX];
+  __shared__ int pa[2][WS_T], pb[2][WS_T], wt[2][2][4];
   const int H = P.H, W = P.W, win = P.win, h = win / 2;
-  const int bx = blockIdx.x * WS_BX, by = blockIdx.y * WS_BY;
-  if (bx >= W || by >= H) return;  // uniform per block
-  const uint8_t *img = side == 1 ? P.R : P.L;
-  const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * WS_BX + tx;
-  const int TW = WS_BX + 2 * h, TH = WS_BY + 2 * h;
-  for (int i = tid; i < TW * TH; i += 256) {
-    const int r = i / TW, c = i - r * TW;
-    const int gy = by - h + r, gx = bx - h + c;
-    tile[r][c] = (gy >= 0 && gy < H && gx >= 0 && gx < W) ? img[(size_t)gy * P.pitch + gx] : 0;
-  }
-  __syncthreads();
-  for (int i = tid; i < WS_BY * TW; i += 256) {
-    const int r = i / TW, c = i - r * TW;
-    int s = 0, ss = 0;
-    for (int v = 0; v < win; ++v) {
-      const int p = tile[r + v][c];
-      s += p;
-      ss += p * p;
-    }
-    cs[r][c] = s;
-    css[r][c] = ss;
-  }
-  __syncthreads();
-  const int x = bx + tx, y = by + ty;
-  if (x >= W || y >= H) return;
+  const int xo = blockIdx.x * WS_NOUT, y0 = blockIdx.y * WS_SY;
+  if (xo >= W || y0 >= H) return;  // uniform per block
+  const GLOBAL uint8_t *img = gro(side == 1 ? P.R : P.L);
+  const int t = threadIdx.x, c = xo - h + t;
+  const bool cin = c >= 0 && c < W;
+  auto px = [&](int r) -> int { return (cin && r >= 0 && r < H) ? (int)img[(size_t)r * P.pitch + c] : 0; };
   int s = 0, ss = 0;
-  for (int u = 0; u < win; ++u) {
-    s += cs[ty][tx + u];
-    ss += css[ty][tx + u];
+  for (int r = y0 - h; r < y0 + h; ++r) {
+    const int v = px(r);
+    s += v;
+    ss += v * v;
   }
-  const bool inside = x >= h && x <= W - 1 - h && y >= h && y <= H - 1 - h;
-  float iv = __builtin_nanf("");
-  if (!inside) {
-    s = 0;
-    ss = 0;
-  } else {
-    const long long n = (long long)win * win;
-    const long long varN = n * ss - (long long)s * s;
-    if (varN > 0) iv = (float)(1.0 / sqrt((double)varN));
-  }
-  const size_t k = (size_t)y * W + x;
-  if (side == 1) {
-    P.SR[k] = s;
-    P.SSR[k] = ss;
-    if (P.invRd) P.invRd[k] = iv;
-    const size_t kp = (size_t)y * P.strideR + x + P.padR;
-    P.SRp[kp] = s;
-    P.invR[kp] = iv;
-  } else {
-    P.SL[k] = s;
-    P.SSL[k] = ss;
-    if (P.invLd) P.invLd[k] = iv;
-    if (side == 0) {
-      const size_t kp = (size_t)y * P.strideL + x + P.padL;
-      P.negSL[kp] = 128 * win * win - s;
-      P.invL[kp] = iv;
+  const bool out_col = c >= xo && c < xo + WS_NOUT && c < W;  // then h <= t < WS_T - h
+  const int y1 = min(y0 + WS_SY, H);
+  for (int y = y0; y < y1; ++y) {
+    const int b = y & 1;
+    const int v = px(y + h);
+    s += v;
+    ss += v * v;
+    int ps = s, pss = ss;
+    block_prefix_i2(ps, pss, wt[b]);
+    pa[b][t] = ps;
+    pb[b][t] = pss;
+    __syncthreads();
+    if (out_col) {
+      const int x = c;
+      int S = pa[b][t + h] - (t - h - 1 >= 0 ? pa[b][t - h - 1] : 0);
+      int SS = pb[b][t + h] - (t - h - 1 >= 0 ? pb[b][t - h - 1] : 0);
+      const bool inside = x >= h && x <= W - 1 - h && y >= h && y <= H - 1 - h;
+      float iv = __builtin_nanf("");
+      if (!inside) {
+        S = 0;
+        SS = 0;
+      } else {
+        const long long n = (long long)win * win;
+        const long long varN = n * SS - (long long)S * S;
+        if (varN > 0) iv = (float)(1.0 / sqrt((double)varN));
+      }
+      const size_t k = (size_t)y * W + x;
+      if (side == 1) {
+        P.SR[k] = S;
+        P.SSR[k] = SS;
+        if (P.invRd) P.invRd[k] = iv;
+        const size_t kp = (size_t)y * P.strideR + x + P.padR;
+        P.SRp[kp] = S;
+        P.invR[kp] = iv;
+      } else {
+        P.SL[k] = S;
+        P.SSL[k] = SS;
+        if (P.invLd) P.invLd[k] = iv;
+        if (side == 0) {
+          const size_t kp = (size_t)y * P.strideL + x + P.padL;
+          P.negSL[kp] = 128 * win * win - S;
+          P.invL[kp] = iv;
+        }
+      }
     }
+    const int vl = px(y - h);
+    s -= vl;
+    ss -= vl * vl;
   }
 }
 
@@ -686,10 +711,10 @@ hipError_t launch_prep(const PrepPair &one, const PrepPair *many, int npairs, in
   } while (0)
   if (prec == P_I16) PP(P_I16); else if (prec == P_F16) PP(P_F16); else PP(P_BF16);
 #undef PP
-  const dim3 gs(ceil_div(maxW, WS_BX), ceil_div(maxH, WS_BY), npairs);
+  const dim3 gs(ceil_div(maxW, WS_NOUT), ceil_div(maxH, WS_SY), npairs);
   for (int side = 0; side < 2; ++side) {
-    if (many) hipLaunchKernelGGL(window_stats_kernel<true>, gs, dim3(WS_BX, WS_BY), 0, s, one, many, side);
-    else hipLaunchKernelGGL(window_stats_kernel<false>, gs, dim3(WS_BX, WS_BY), 0, s, one, many, side);
+    if (many) hipLaunchKernelGGL(window_stats_kernel<true>, gs, dim3(WS_T), 0, s, one, many, side);
+    else hipLaunchKernelGGL(window_stats_kernel<false>, gs, dim3(WS_T), 0, s, one, many, side);
   }
   return hipGetLastError();
 }
@@ -705,8 +730,8 @@ hipError_t launch_window_stats_dense(const uint8_t *img, int H, int W, int pitch
   P.SL = S;
   P.SSL = SS;
   P.invLd = inv;
-  const dim3 gs(ceil_div(W, WS_BX), ceil_div(H, WS_BY), 1);
-  hipLaunchKernelGGL(window_stats_kernel<false>, gs, dim3(WS_BX, WS_BY), 0, s, P, (const PrepPair *)nullptr, 2);
+  const dim3 gs(ceil_div(W, WS_NOUT), ceil_div(H, WS_SY), 1);
+  hipLaunchKernelGGL(window_stats_kernel<false>, gs, dim3(WS_T), 0, s, P, (const PrepPair *)nullptr, 2);
   return hipGetLastError();
 }
 

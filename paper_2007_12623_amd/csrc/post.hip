@@ -281,7 +281,7 @@ __global__ void lr_check_kernel(PostPair one, const PostPair *__restrict__ many,
 // diagonals: a thread scans SEG rows of one line (plus the look-ahead) and
 // the lanes of a wave are neighbouring lines, so each step reads
 // consecutive columns of one row.
-constexpr int SEG = 64;
+constexpr int SEG = 32;
 
 __device__ __forceinline__ uint64_t ballot64(bool p) { return __ballot(p); }
 __device__ __forceinline__ int ctz64(uint64_t v) { return __builtin_ctzll(v); }
@@ -562,82 +562,89 @@ __global__ void outlier_combine_kernel(PostPair one, const PostPair *__restrict_
 // (i) radial fill from the scanned hits: complete lines (both opposite
 // directions hit) give (va*sb + vb*sa)/(sa+sb); with >= min_lines complete
 // lines the hole takes their mean, an exact rational rounded half to even;
-// code 2.
+// code 2.  Fused with the row prefix sums of the result that the disk fill
+// reads: pc[y][x+1] = number of valid pixels x' <= x in row y, ps[y][x+1]
+// the sum of their disparities.  One block per row; the row goes in chunks
+// of 256 columns with a block scan (wave scans plus wave totals in LDS).
 template <bool B>
-__global__ void fill_radial_kernel(PostPair one, const PostPair *__restrict__ many, int min_lines, int src,
-                                   int dst) {
+__global__ __launch_bounds__(256) void fill_radial_kernel(PostPair one, const PostPair *__restrict__ many,
+                                                          int min_lines, int src, int dst) {
   PAIR;
-  const int W = P.W, H = P.H;
-  (void)W;
-  (void)H;
-  for_pixels(P, [&](int x, int y, size_t k) {
-    const int16_t *o = P.ob[src];
-    const uint8_t *m = P.mb[src];
-    P.ob[dst][k] = o[k];
-    P.mb[dst][k] = m[k];
-    if (m[k]) return;
-    const size_t N = (size_t)W * H;
-    long long num = 0, den = 1;
-    int lines = 0;
-    for (int ln = 0; ln < 4; ++ln) {
-      const uint32_t ha = P.hits[(size_t)(2 * ln) * N + k], hb = P.hits[(size_t)(2 * ln + 1) * N + k];
-      if (!ha || !hb) continue;
-      const long long sa = ha >> 16, sb = hb >> 16;
-      const long long va = (int16_t)(ha & 0xFFFFu), vb = (int16_t)(hb & 0xFFFFu);
-      const long long lnum = va * sb + vb * sa;
-      const long long ld = sa + sb;
-      num = num * ld + lnum * den;
-      den = den * ld;
-      ++lines;
+  __shared__ int wc[4], wsum[4];
+  const int y = blockIdx.x;
+  if (y >= P.H) return;  // uniform per block
+  const int W = P.W, H = P.H, t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const size_t N = (size_t)W * H;
+  const GLOBAL int16_t *o = gro(P.ob[src]);
+  const GLOBAL uint8_t *m = gro(P.mb[src]);
+  const GLOBAL uint32_t *hits = gro(P.hits);
+  GLOBAL int32_t *pcr = grw(P.pc) + (size_t)y * (W + 1);
+  GLOBAL int32_t *psr = grw(P.ps) + (size_t)y * (W + 1);
+  if (t == 0) {
+    pcr[0] = 0;
+    psr[0] = 0;
+  }
+  int carry_c = 0, carry_s = 0;
+  for (int x0 = 0; x0 < W; x0 += 256) {
+    const int x = x0 + t;
+    int ov = 0, mv = 0;
+    if (x < W) {
+      const size_t k = (size_t)y * W + x;
+      ov = o[k];
+      mv = m[k];
+      if (!mv) {
+        long long num = 0, den = 1;
+        int lines = 0;
+        for (int ln = 0; ln < 4; ++ln) {
+          const uint32_t ha = hits[(size_t)(2 * ln) * N + k], hb = hits[(size_t)(2 * ln + 1) * N + k];
+          if (!ha || !hb) continue;
+          const long long sa = ha >> 16, sb = hb >> 16;
+          const long long va = (int16_t)(ha & 0xFFFFu), vb = (int16_t)(hb & 0xFFFFu);
+          const long long lnum = va * sb + vb * sa;
+          const long long ld = sa + sb;
+          num = num * ld + lnum * den;
+          den = den * ld;
+          ++lines;
+        }
+        if (lines >= min_lines && lines > 0) {
+          ov = (int)round_half_even(num, den * lines);
+          mv = 2;
+        }
+      }
+      grw(P.ob[dst])[k] = (int16_t)ov;
+      grw(P.mb[dst])[k] = (uint8_t)mv;
     }
-    if (lines >= min_lines && lines > 0) {
-      P.ob[dst][k] = (int16_t)round_half_even(num, den * lines);
-      P.mb[dst][k] = 2;
+    int c = mv ? 1 : 0, sv = mv ? ov : 0;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int uc = __shfl_up(c, off, 64), us = __shfl_up(sv, off, 64);
+      if (lane >= off) {
+        c += uc;
+        sv += us;
+      }
     }
-  });
+    if (lane == 63) {
+      wc[wave] = c;
+      wsum[wave] = sv;
+    }
+    __syncthreads();
+    int bc = carry_c, bs = carry_s;
+    for (int w = 0; w < wave; ++w) {
+      bc += wc[w];
+      bs += wsum[w];
+    }
+    if (x < W) {
+      pcr[x + 1] = bc + c;
+      psr[x + 1] = bs + sv;
+    }
+    for (int w = 0; w < 4; ++w) {
+      carry_c += wc[w];
+      carry_s += wsum[w];
+    }
+    __syncthreads();  // wc / wsum are rewritten by the next chunk
+  }
 }
 
-// Row prefix sums of the valid count and of the valid disparities of
-// (ob[src], mb[src]): pc[y][x+1] = sum_{x' <= x} [m != 0]; pc[y][0] = 0.
-template <bool B>
-__global__ __launch_bounds__(256) void row_prefix_kernel(PostPair one, const PostPair *__restrict__ many,
-                                                         int src) {
-  PAIR;
-  __shared__ int sc[256], ss[256];
-  const int y = blockIdx.x;
-  if (y >= P.H) return;
-  const int W = P.W;
-  const int16_t *o = P.ob[src];
-  const uint8_t *m = P.mb[src];
-  const int t = threadIdx.x;
-  const int per = ceil_div(W, 256);
-  const int x0 = min(t * per, W), x1 = min(x0 + per, W);
-  int c = 0, s = 0;
-  for (int x = x0; x < x1; ++x) {
-    const size_t k = (size_t)y * W + x;
-    if (m[k]) { ++c; s += o[k]; }
-  }
-  sc[t] = c;
-  ss[t] = s;
-  __syncthreads();
-  for (int off = 1; off < 256; off <<= 1) {
-    int ac = 0, as = 0;
-    if (t >= off) { ac = sc[t - off]; as = ss[t - off]; }
-    __syncthreads();
-    sc[t] += ac;
-    ss[t] += as;
-    __syncthreads();
-  }
-  int bc = t ? sc[t - 1] : 0, bs = t ? ss[t - 1] : 0;
-  int32_t *pcr = P.pc + (size_t)y * (W + 1), *psr = P.ps + (size_t)y * (W + 1);
-  if (t == 0) { pcr[0] = 0; psr[0] = 0; }
-  for (int x = x0; x < x1; ++x) {
-    const size_t k = (size_t)y * W + x;
-    if (m[k]) { ++bc; bs += o[k]; }
-    pcr[x + 1] = bc;
-    psr[x + 1] = bs;
-  }
-}
 
 __device__ __forceinline__ int isqrt_floor(int v) {
   int w = (int)sqrt((double)v);
@@ -827,10 +834,10 @@ __global__ __launch_bounds__(256) void box_h_lds_kernel(PostPair one, const Post
 constexpr int HCF_T = 256, HCF_RMAX = 64, HCF_SY = 64;
 enum { F_C = 1, F_D0 = 2, F_D1 = 3 };  // planes of P.f used with F_A below
 
-__device__ __forceinline__ double hc_s_at(const PostPair &P, size_t k, uint8_t mk, int src,
+__device__ __forceinline__ double hc_s_at(const PostPair &P, size_t k, uint8_t mk, int osrc,
                                           int use_delta) {
   if (P.s_in) return (double)gro(P.s_in)[k];
-  const double o = (double)gro(P.ob[src])[k];
+  const double o = (double)gro(P.ob[osrc])[k];
   return (mk == 1 && use_delta) ? o + (double)gro(P.delta)[k] : o;
 }
 
@@ -853,8 +860,8 @@ __device__ __forceinline__ void block_prefix(double v, double *buf, double *wt) 
 
 template <bool B, int PASS>
 __device__ __forceinline__ void hc_box(PostPair one, const PostPair *__restrict__ many, int src,
-                                       int use_delta, int R, double alpha, int dprev, int dout,
-                                       int last) {
+                                       int osrc, int use_delta, int R, double alpha, int dprev,
+                                       int dout, int last) {
   PAIR;
   __shared__ double pre[2][HCF_T], prw[2][HCF_T], wt[2][4], wtw[2][4];
   const int H = P.H, W = P.W;
@@ -876,7 +883,7 @@ __device__ __forceinline__ void hc_box(PostPair one, const PostPair *__restrict_
     const uint8_t mk = m[k];
     if (!mk) return 0.0;
     w = 1.0;
-    const double sv = hc_s_at(P, k, mk, src, use_delta);
+    const double sv = hc_s_at(P, k, mk, osrc, use_delta);
     if (PASS == 0) return sv;
     const double dp = dprev < 0 ? sv : fD[k];
     return fA[k] - alpha * sv - (1.0 - alpha) * dp;
@@ -917,28 +924,145 @@ __device__ __forceinline__ void hc_box(PostPair one, const PostPair *__restrict_
   }
 }
 
+// src: mask plane; osrc: the plane of the discrete disparities o
 template <bool B>
 __global__ __launch_bounds__(HCF_T) void hc_mean_s_kernel(PostPair one, const PostPair *__restrict__ many,
-                                                          int src, int use_delta, int R) {
-  hc_box<B, 0>(one, many, src, use_delta, R, 0.0, -1, 0, 0);
+                                                          int src, int osrc, int use_delta, int R) {
+  hc_box<B, 0>(one, many, src, osrc, use_delta, R, 0.0, -1, 0, 0);
 }
 template <bool B>
 __global__ __launch_bounds__(HCF_T) void hc_iter_kernel(PostPair one, const PostPair *__restrict__ many,
-                                                        int src, int use_delta, int R, double alpha,
-                                                        int dprev, int dout, int last) {
-  hc_box<B, 1>(one, many, src, use_delta, R, alpha, dprev, dout, last);
+                                                        int src, int osrc, int use_delta, int R,
+                                                        double alpha, int dprev, int dout, int last) {
+  hc_box<B, 1>(one, many, src, osrc, use_delta, R, alpha, dprev, dout, last);
+}
+
+// ---- Eq. (4): re-search of the discrete disparities around d.  A block
+// covers 128 pixels of a row and stages, as the sub-pixel kernel does, the
+// L window rows and the R columns of every candidate of the block; each
+// candidate's window sum is exact (v_dot4_u32_u8), z and the cost in FP64.
+template <int ND>
+__device__ __forceinline__ int sp_sum1(const uint8_t (*Ls)[SP_LROW], const uint8_t (*Rs)[SP_RROW],
+                                       const int *misL, const int *misR, int win, int tx, int rs0) {
+  const uint32_t lmask = (win & 3) ? (1u << (8 * (win & 3))) - 1u : 0xFFFFFFFFu;
+  uint32_t acc = 0;
+  for (int v = 0; v < win; ++v) {
+    const int lb = tx + misL[v], rs = rs0 + misR[v];
+    const uint32_t *lw = (const uint32_t *)&Ls[v][lb & ~3];
+    const uint32_t *rw = (const uint32_t *)&Rs[v][rs & ~3];
+    uint32_t lt[ND + 1], rt[ND + 1];
+#pragma unroll
+    for (int i = 0; i <= ND; ++i) {
+      lt[i] = lw[i];
+      rt[i] = rw[i];
+    }
+#pragma unroll
+    for (int i = 0; i < ND; ++i) {
+      uint32_t l = __builtin_amdgcn_alignbyte(lt[i + 1], lt[i], lb & 3);
+      if (i == ND - 1) l &= lmask;
+      acc = __builtin_amdgcn_udot4(l, __builtin_amdgcn_alignbyte(rt[i + 1], rt[i], rs & 3), acc, false);
+    }
+  }
+  return (int)acc;
+}
+
+template <bool B>
+__global__ __launch_bounds__(SP_TX) void research_kernel(PostPair one, const PostPair *__restrict__ many,
+                                                         int osrc, int msrc, int odst, int dplane,
+                                                         int range, double eta) {
+  PAIR;
+  __shared__ __align__(16) uint8_t Ls[SP_MAXWIN][SP_LROW];
+  __shared__ __align__(16) uint8_t Rs[SP_MAXWIN][SP_RROW];
+  __shared__ int s_cmin, s_cmax, misL[SP_MAXWIN], misR[SP_MAXWIN];
+  const int tx = threadIdx.x;
+  const int x0 = blockIdx.x * SP_TX, y = blockIdx.y;
+  if (x0 >= P.W || y >= P.H) return;  // uniform per block
+  const int W = P.W, H = P.H, win = P.win, h = win / 2;
+  const int x = x0 + tx;
+  const size_t N = (size_t)W * H, k = (size_t)y * W + x;
+  // pixels whose own window is inside the image can have a defined candidate
+  const bool inside = x < W && x >= h && x <= W - 1 - h && y >= h && y <= H - 1 - h;
+  const uint8_t mk = x < W ? P.mb[msrc][k] : 0;
+  const double d = mk ? P.f[(size_t)dplane * N + k] : 0.0;
+  int lo = 0, hi = -1;
+  if (mk && inside) {
+    lo = max(max(P.dmin, (int)ceil(d - range)), x - (W - 1 - h));
+    hi = min(min(P.dmax, (int)floor(d + range)), x - h);
+  }
+  if (tx == 0) {
+    s_cmin = 1 << 30;
+    s_cmax = -(1 << 30);
+  }
+  __syncthreads();
+  if (lo <= hi) {
+    atomicMin(&s_cmin, lo);
+    atomicMax(&s_cmax, hi);
+  }
+  __syncthreads();
+  const int cmin = s_cmin, cmax = s_cmax;
+  if (cmin <= cmax) {
+    // Ls[r][misL[r] + c] = L(y-h+r, x0-h+c), Rs[r][misR[r] + c] = R(y-h+r, x0-cmax-h+c)
+    const int LW = SP_TX + 2 * h, RW = SP_TX + (cmax - cmin) + 2 * h;
+    const int lx0 = x0 - h, rx0 = x0 - cmax - h;
+    const GLOBAL uint8_t *Lg = gro(P.left), *Rg = gro(P.right);
+    const size_t span = (size_t)(H - 1) * P.pitch + W;
+    for (int r = 0; r < win; ++r) {  // rows inside: the block has an inside pixel
+      const size_t row = (size_t)(y - h + r) * P.pitch;
+      stage_row(Ls[r], Lg + row + lx0, LW, Lg, Lg + span, tx);
+      stage_row(Rs[r], Rg + row + rx0, RW, Rg, Rg + span, tx);
+      if (tx == 0) {
+        misL[r] = (int)((uintptr_t)(Lg + row + lx0) & 3);
+        misR[r] = (int)((uintptr_t)(Rg + row + rx0) & 3);
+      }
+    }
+  }
+  __syncthreads();
+  if (x >= W) return;
+  int onew = P.ob[osrc][k];
+  if (lo <= hi) {
+    const long long n = (long long)win * win;
+    const long long sl = P.SL[k];
+    const long long varL = n * (long long)P.SSL[k] - sl * sl;
+    if (varL > 0) {
+      double best = __builtin_inf();
+      const int nd = (win + 3) >> 2;
+      for (int c = lo; c <= hi; ++c) {
+        const size_t kr = (size_t)y * W + (x - c);
+        const long long sr = P.SR[kr];
+        const long long varR = n * (long long)P.SSR[kr] - sr * sr;
+        if (varR <= 0) continue;
+        const int rs0 = tx + cmax - c;  // window column 0 of candidate c in Rs
+        int slr;
+        switch (nd) {
+          case 1: slr = sp_sum1<1>(Ls, Rs, misL, misR, win, tx, rs0); break;
+          case 2: slr = sp_sum1<2>(Ls, Rs, misL, misR, win, tx, rs0); break;
+          case 3: slr = sp_sum1<3>(Ls, Rs, misL, misR, win, tx, rs0); break;
+          default: slr = sp_sum1<4>(Ls, Rs, misL, misR, win, tx, rs0); break;
+        }
+        const double z = (double)(n * (long long)slr - sl * sr) / sqrt((double)varL * (double)varR);
+        const double e = (double)c - d;
+        const double cost = 1.0 / (z > 1e-3 ? z : 1e-3) + eta * e * e;
+        if (cost < best) {
+          best = cost;
+          onew = c;
+        }
+      }
+    }
+  }
+  P.ob[odst][k] = (int16_t)onew;
 }
 
 // Output without smoothing (K = 0): s on valid pixels.
 template <bool B>
-__global__ void hc_copy_kernel(PostPair one, const PostPair *__restrict__ many, int src, int use_delta) {
+__global__ void hc_copy_kernel(PostPair one, const PostPair *__restrict__ many, int src, int osrc,
+                               int use_delta) {
   PAIR;
   const int W = P.W, H = P.H;
   (void)W;
   (void)H;
   for_pixels(P, [&](int x, int y, size_t k) {
     const uint8_t mk = P.mb[src][k];
-    P.disparity[k] = mk ? (float)hc_s_at(P, k, mk, src, use_delta) : __builtin_nanf("");
+    P.disparity[k] = mk ? (float)hc_s_at(P, k, mk, osrc, use_delta) : __builtin_nanf("");
     if (P.valid_mask) P.valid_mask[k] = mk;
   });
 }
@@ -1039,8 +1163,7 @@ hipError_t post_fill(const PostLaunch &L, int radial_r, int min_lines, int disk_
                      int src, int tmp, int dst) {
   LAUNCH(fill_rows_kernel, rowgrid(L), dim3(64), radial_r, src);
   LAUNCH(fill_vscan_kernel, vscangrid(L), dim3(64), radial_r, src);
-  LAUNCH(fill_radial_kernel, pixgrid(L), dim3(PIX_T), min_lines, src, tmp);
-  LAUNCH(row_prefix_kernel, dim3(L.maxH, 1, L.npairs), dim3(256), tmp);
+  LAUNCH(fill_radial_kernel, dim3(L.maxH, 1, L.npairs), dim3(256), min_lines, src, tmp);
   LAUNCH(fill_disk_kernel, pixgrid(L), dim3(PIX_T), disk_r, frac, tmp, dst);
   return hipGetLastError();
 }
@@ -1058,17 +1181,48 @@ static void box2d(const PostLaunch &L, int R, int in, int out) {
 
 // Improved Laplacian smoothing of (ob[src], delta, mb[src]) or s_in; writes
 // disparity (NaN where invalid) and valid_mask.
-hipError_t post_hc(const PostLaunch &L, int src, int R, int K, float alpha, int use_delta) {
+hipError_t post_research(const PostLaunch &L, int osrc, int msrc, int odst, int dplane, int range,
+                         float eta) {
+  LAUNCH(research_kernel, dim3(ceil_div(L.maxW, SP_TX), L.maxH, L.npairs), dim3(SP_TX), osrc, msrc,
+         odst, dplane, range, (double)eta);
+  return hipGetLastError();
+}
+
+hipError_t post_hc(const PostLaunch &L, int src, int R, int K, float alpha, int use_delta,
+                   int research, int range, float eta) {
+  if (research) {
+    // Eqs. (1)-(4): o itself is smoothed (no sub-pixel offset) and re-searched
+    // after every iteration but the last; o ping-pongs between the two fill
+    // planes (the final mask stays in plane src)
+    int ocur = src, oalt = src == 1 ? 2 : 1;
+    const dim3 g(ceil_div(L.maxW, HCF_T - 2 * R), ceil_div(L.maxH, HCF_SY), L.npairs);
+    if (K == 0) {
+      LAUNCH(hc_copy_kernel, pixgrid(L), dim3(PIX_T), src, ocur, 0);
+      return hipGetLastError();
+    }
+    for (int it = 0; it < K; ++it) {
+      const int dp = it == 0 ? -1 : ((it & 1) ? F_D0 : F_D1), dn = (it & 1) ? F_D1 : F_D0;
+      const int last = it == K - 1;
+      LAUNCH(hc_mean_s_kernel, g, dim3(HCF_T), src, ocur, 0, R);
+      LAUNCH(hc_iter_kernel, g, dim3(HCF_T), src, ocur, 0, R, (double)alpha, dp, dn, last);
+      if (!last) {
+        LAUNCH(research_kernel, dim3(ceil_div(L.maxW, SP_TX), L.maxH, L.npairs), dim3(SP_TX), ocur,
+               src, oalt, dn, range, (double)eta);
+        std::swap(ocur, oalt);
+      }
+    }
+    return hipGetLastError();
+  }
   if (K == 0) {
-    LAUNCH(hc_copy_kernel, pixgrid(L), dim3(PIX_T), src, use_delta);
+    LAUNCH(hc_copy_kernel, pixgrid(L), dim3(PIX_T), src, src, use_delta);
     return hipGetLastError();
   }
   if (R <= HCF_RMAX) {
     const dim3 g(ceil_div(L.maxW, HCF_T - 2 * R), ceil_div(L.maxH, HCF_SY), L.npairs);
-    LAUNCH(hc_mean_s_kernel, g, dim3(HCF_T), src, use_delta, R);
+    LAUNCH(hc_mean_s_kernel, g, dim3(HCF_T), src, src, use_delta, R);
     for (int it = 0; it < K; ++it) {
       const int dp = it == 0 ? -1 : ((it & 1) ? F_D0 : F_D1), dn = (it & 1) ? F_D1 : F_D0;
-      LAUNCH(hc_iter_kernel, g, dim3(HCF_T), src, use_delta, R, (double)alpha, dp, dn,
+      LAUNCH(hc_iter_kernel, g, dim3(HCF_T), src, src, use_delta, R, (double)alpha, dp, dn,
              it == K - 1 ? 1 : 0);
     }
     return hipGetLastError();
