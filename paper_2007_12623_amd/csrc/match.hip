@@ -499,7 +499,7 @@ __global__ void prep_planes_kernel(PrepPair one, const PrepPair *many) {
 // window sums of its column down a segment of WS_SY rows and the horizontal
 // sums are differences of a block prefix sum (wave scans plus wave totals in
 // LDS).  Output columns of a block are WS_T - 2 WS_HMAX wide for every window.
-constexpr int WS_T = 256, WS_SY = 64, WS_HMAX = 7, WS_NOUT = WS_T - 2 * WS_HMAX;
+constexpr int WS_T = 256, WS_SY = 16, WS_HMAX = 7, WS_NOUT = WS_T - 2 * WS_HMAX;
 
 __device__ __forceinline__ void block_prefix_i2(int &a, int &b, int (*wt)[4]) {
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;

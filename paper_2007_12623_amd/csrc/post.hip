@@ -75,24 +75,30 @@ __global__ void fill_u32_kernel(uint32_t *p, int N, uint32_t v) {
 constexpr int SP_TX = 128, SP_MAXWIN = 15;
 constexpr int SP_LROW = SP_TX + 24, SP_RROW = SP_TX + 256 + 32;
 
-// Copy the bytes [g, g + len) of one image row to an LDS row as whole
-// dwords starting at the dword-aligned address below g, one dword per thread
-// (len + 3 < 4 * SP_TX); the byte offset of g in the LDS row is g & 3.
-// Bytes outside [lo, hi), the image buffer, are not read (a dword that is not
-// wholly inside is assembled byte by byte) and come out as 0.
-__device__ __forceinline__ void stage_row(uint8_t *dst, const GLOBAL uint8_t *g, int len,
-                                          const GLOBAL uint8_t *lo, const GLOBAL uint8_t *hi,
-                                          int tid) {
-  const int mis = (int)((uintptr_t)g & 3);
-  if (tid >= ((mis + len + 3) >> 2)) return;
-  const GLOBAL uint8_t *p = g - mis + 4 * tid;
+// Copy the bytes [off, off + len) of the image buffer base[0, span) (byte
+// offsets relative to base; off may be negative) to an LDS row as whole
+// dwords starting at the dword-aligned address at or below base + off, one
+// dword per thread (len + 3 < 4 * SP_TX); the byte offset of base + off in
+// the LDS row is (base + off) & 3.  The range of dwords wholly inside the
+// buffer is worked out once per row (uniform); the at most two dwords that
+// straddle its ends are assembled byte by byte; bytes outside come out 0.
+__device__ __forceinline__ void stage_row(uint8_t *dst, const GLOBAL uint8_t *base, long long off,
+                                          int len, long long span, int tid) {
+  const int mis = (int)(((uintptr_t)base + (uintptr_t)off) & 3);
+  const long long a0 = off - mis;  // offset of dword 0
+  const int nd = (mis + len + 3) >> 2;
+  const int ilo = a0 >= 0 ? 0 : (int)((-a0 + 3) >> 2);
+  const int ihi = span - a0 >= 4 ? (int)min((span - a0) >> 2, (long long)nd) : 0;
+  if (tid >= nd) return;
+  const GLOBAL uint32_t *row = (const GLOBAL uint32_t *)(base + a0);
   uint32_t v;
-  if (p >= lo && p + 4 <= hi) {
-    v = *(const GLOBAL uint32_t *)p;
+  if (tid >= ilo && tid < ihi) {
+    v = row[(unsigned)tid];
   } else {
     v = 0;
+    const long long b = a0 + 4 * (long long)tid;
     for (int j = 0; j < 4; ++j)
-      if (p + j >= lo && p + j < hi) v |= (uint32_t)p[j] << (8 * j);
+      if (b + j >= 0 && b + j < span) v |= (uint32_t)base[b + j] << (8 * j);
   }
   ((uint32_t *)dst)[tid] = v;
 }
@@ -176,16 +182,16 @@ __global__ __launch_bounds__(SP_TX) void subpixel_kernel(PostPair one, const Pos
     const int LW = SP_TX + 2 * h, RW = SP_TX + (omax - omin) + 2 + 2 * h;
     const int lx0 = x0 - h, rx0 = x0 - omax - 1 - h;
     const GLOBAL uint8_t *Lg = gro(P.left), *Rg = gro(P.right);
-    const size_t span = (size_t)(H - 1) * P.pitch + W;
+    const long long span = (long long)(H - 1) * P.pitch + W;
 #pragma unroll
     for (int r = 0; r < SP_MAXWIN; ++r) {
       if (r < win) {
-        const size_t row = (size_t)(y - h + r) * P.pitch;  // inside: the block has a valid pixel
-        stage_row(Ls[r], Lg + row + lx0, LW, Lg, Lg + span, tx);
-        stage_row(Rs[r], Rg + row + rx0, RW, Rg, Rg + span, tx);
+        const long long row = (long long)(y - h + r) * P.pitch;  // inside: the block has a valid pixel
+        stage_row(Ls[r], Lg, row + lx0, LW, span, tx);
+        stage_row(Rs[r], Rg, row + rx0, RW, span, tx);
         if (tx == 0) {
-          misL[r] = (int)((uintptr_t)(Lg + row + lx0) & 3);
-          misR[r] = (int)((uintptr_t)(Rg + row + rx0) & 3);
+          misL[r] = (int)(((uintptr_t)Lg + (uintptr_t)(row + lx0)) & 3);
+          misR[r] = (int)(((uintptr_t)Rg + (uintptr_t)(row + rx0)) & 3);
         }
       }
     }
@@ -298,11 +304,12 @@ __device__ __forceinline__ bool step_breaks(const GLOBAL int16_t *o, const GLOBA
 }
 
 template <bool B>
-__global__ __launch_bounds__(64) void outlier_rows_kernel(PostPair one, const PostPair *__restrict__ many, int r,
+__global__ __launch_bounds__(256) void outlier_rows_kernel(PostPair one, const PostPair *__restrict__ many, int r,
                                                           float thresh, int src) {
   PAIR;
   const int H = P.H, W = P.W;
-  const int y = blockIdx.y, xb = blockIdx.x * 64, lane = threadIdx.x;
+  // a block holds 4 waves, one row each (no block-level synchronisation)
+  const int lane = threadIdx.x & 63, y = blockIdx.y * 4 + (threadIdx.x >> 6), xb = blockIdx.x * 64;
   if (y >= H || xb >= W) return;  // whole wave
   const GLOBAL int16_t *o = gro(P.ob[src]) + (size_t)y * W;
   const GLOBAL uint8_t *m = gro(P.mb[src]) + (size_t)y * W;
@@ -337,11 +344,12 @@ __global__ __launch_bounds__(64) void outlier_rows_kernel(PostPair one, const Po
 }
 
 template <bool B>
-__global__ __launch_bounds__(64) void fill_rows_kernel(PostPair one, const PostPair *__restrict__ many, int R,
+__global__ __launch_bounds__(256) void fill_rows_kernel(PostPair one, const PostPair *__restrict__ many, int R,
                                                        int src) {
   PAIR;
   const int H = P.H, W = P.W;
-  const int y = blockIdx.y, xb = blockIdx.x * 64, lane = threadIdx.x;
+  // a block holds 4 waves, one row each (no block-level synchronisation)
+  const int lane = threadIdx.x & 63, y = blockIdx.y * 4 + (threadIdx.x >> 6), xb = blockIdx.x * 64;
   if (y >= H || xb >= W) return;  // whole wave
   const GLOBAL int16_t *o = gro(P.ob[src]) + (size_t)y * W;
   const GLOBAL uint8_t *m = gro(P.mb[src]) + (size_t)y * W;
@@ -708,8 +716,16 @@ enum { F_S = 0, F_IN = 1, F_CNT = 2, F_TMP = 3, F_A = 4, F_D = 5 };
 
 // s = o + delta for matched pixels (code 1), o for filled ones (code 2), or
 // the given s_in; plane F_IN <- s*m, F_D <- m (ones, used for the counts).
+__device__ __forceinline__ double hc_s_at(const PostPair &P, size_t k, uint8_t mk, int osrc,
+                                          int use_delta) {
+  if (P.s_in) return (double)gro(P.s_in)[k];
+  const double o = (double)gro(P.ob[osrc])[k];
+  return (mk == 1 && use_delta) ? o + (double)gro(P.delta)[k] : o;
+}
+
 template <bool B>
-__global__ void hc_init_kernel(PostPair one, const PostPair *__restrict__ many, int src, int use_delta) {
+__global__ void hc_init_kernel(PostPair one, const PostPair *__restrict__ many, int src, int osrc,
+                               int use_delta, int counts) {
   PAIR;
   const int W = P.W, H = P.H;
   (void)W;
@@ -717,14 +733,10 @@ __global__ void hc_init_kernel(PostPair one, const PostPair *__restrict__ many, 
   for_pixels(P, [&](int x, int y, size_t k) {
     const size_t N = (size_t)W * H;
     const uint8_t mk = P.mb[src][k];
-    double v = 0.0;
-    if (mk) {
-      if (P.s_in) v = (double)P.s_in[k];
-      else v = (mk == 1 && use_delta) ? (double)P.ob[src][k] + (double)P.delta[k] : (double)P.ob[src][k];
-    }
+    const double v = mk ? hc_s_at(P, k, mk, osrc, use_delta) : 0.0;
     P.f[F_S * N + k] = v;
-    P.f[F_IN * N + k] = mk ? v : 0.0;
-    P.f[F_D * N + k] = mk ? 1.0 : 0.0;
+    P.f[F_IN * N + k] = v;
+    if (counts) P.f[F_D * N + k] = mk ? 1.0 : 0.0;
   });
 }
 
@@ -822,121 +834,6 @@ __global__ __launch_bounds__(256) void box_h_lds_kernel(PostPair one, const Post
   }
 }
 
-// ---- fused smoothing passes: one kernel per masked mean, for R <= HCF_RMAX.
-// A block of 256 threads owns 256 columns (output columns are the middle
-// 256 - 2R) and a segment of rows.  Each thread keeps the vertical window sum
-// of its column while stepping down the rows (adding the entering row,
-// subtracting the leaving one, both computed from the inputs on the fly); the
-// horizontal window sum is a difference of a block-wide prefix sum (wave scan
-// plus wave totals in LDS).  Pass 0 writes a = A(s) (Eq. 1) and the valid
-// counts; pass 1 takes b = a - alpha s - (1-alpha) d_prev (Eq. 2) and writes
-// d = a - A(b) (Eq. 3), in the last iteration straight to the outputs.
-constexpr int HCF_T = 256, HCF_RMAX = 64, HCF_SY = 64;
-enum { F_C = 1, F_D0 = 2, F_D1 = 3 };  // planes of P.f used with F_A below
-
-__device__ __forceinline__ double hc_s_at(const PostPair &P, size_t k, uint8_t mk, int osrc,
-                                          int use_delta) {
-  if (P.s_in) return (double)gro(P.s_in)[k];
-  const double o = (double)gro(P.ob[osrc])[k];
-  return (mk == 1 && use_delta) ? o + (double)gro(P.delta)[k] : o;
-}
-
-// Block-wide inclusive prefix sum of one double per thread; buf is a
-// 256-entry LDS row, wt 4 wave totals.  Returns after the row is in buf.
-__device__ __forceinline__ void block_prefix(double v, double *buf, double *wt) {
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const double u = __shfl_up(v, o, 64);
-    if (lane >= o) v += u;
-  }
-  if (lane == 63) wt[wave] = v;
-  __syncthreads();
-  double base = 0.0;
-  for (int w = 0; w < wave; ++w) base += wt[w];
-  buf[t] = v + base;
-  __syncthreads();
-}
-
-template <bool B, int PASS>
-__device__ __forceinline__ void hc_box(PostPair one, const PostPair *__restrict__ many, int src,
-                                       int osrc, int use_delta, int R, double alpha, int dprev,
-                                       int dout, int last) {
-  PAIR;
-  __shared__ double pre[2][HCF_T], prw[2][HCF_T], wt[2][4], wtw[2][4];
-  const int H = P.H, W = P.W;
-  const int nout = HCF_T - 2 * R;
-  const int xo = blockIdx.x * nout, y0 = blockIdx.y * HCF_SY;
-  if (xo >= W || y0 >= H) return;  // uniform per block
-  const size_t N = (size_t)W * H;
-  const int t = threadIdx.x;
-  const int c = xo - R + t;  // this thread's column
-  const bool cin = c >= 0 && c < W;
-  const GLOBAL uint8_t *m = gro(P.mb[src]);
-  const GLOBAL double *fA = gro(P.f) + (size_t)F_A * N;
-  const GLOBAL double *fD = gro(P.f) + (size_t)(dprev < 0 ? 0 : dprev) * N;
-  // window input of row r at this column: (value, count)
-  auto in = [&](int r, double &w) -> double {
-    w = 0.0;
-    if (!cin || r < 0 || r >= H) return 0.0;
-    const size_t k = (size_t)r * W + c;
-    const uint8_t mk = m[k];
-    if (!mk) return 0.0;
-    w = 1.0;
-    const double sv = hc_s_at(P, k, mk, osrc, use_delta);
-    if (PASS == 0) return sv;
-    const double dp = dprev < 0 ? sv : fD[k];
-    return fA[k] - alpha * sv - (1.0 - alpha) * dp;
-  };
-  double sv = 0.0, sw = 0.0, w;
-  for (int r = y0 - R; r < y0 + R; ++r) {
-    sv += in(r, w);
-    sw += w;
-  }
-  const int y1 = min(y0 + HCF_SY, H);
-  for (int y = y0; y < y1; ++y) {
-    const int b = y & 1;
-    sv += in(y + R, w);
-    sw += w;
-    block_prefix(sv, pre[b], wt[b]);
-    if (PASS == 0) block_prefix(sw, prw[b], wtw[b]);
-    const int x = c;  // output column of thread t when R <= t < HCF_T - R
-    if (t >= R && t < HCF_T - R && cin) {
-      const size_t k = (size_t)y * W + x;
-      const uint8_t mk = m[k];
-      const double bv = pre[b][t + R] - (t - R - 1 >= 0 ? pre[b][t - R - 1] : 0.0);
-      if (PASS == 0) {
-        const double bw = prw[b][t + R] - (t - R - 1 >= 0 ? prw[b][t - R - 1] : 0.0);
-        grw(P.f)[(size_t)F_A * N + k] = mk ? bv / bw : 0.0;
-        grw(P.f)[(size_t)F_C * N + k] = bw;
-      } else {
-        const double d = mk ? fA[k] - bv / gro(P.f)[(size_t)F_C * N + k] : 0.0;
-        if (last) {
-          grw(P.disparity)[k] = mk ? (float)d : __builtin_nanf("");
-          if (P.valid_mask) grw(P.valid_mask)[k] = mk;  // the smoothing stage entry has none
-        } else {
-          grw(P.f)[(size_t)dout * N + k] = d;
-        }
-      }
-    }
-    sv -= in(y - R, w);
-    sw -= w;
-  }
-}
-
-// src: mask plane; osrc: the plane of the discrete disparities o
-template <bool B>
-__global__ __launch_bounds__(HCF_T) void hc_mean_s_kernel(PostPair one, const PostPair *__restrict__ many,
-                                                          int src, int osrc, int use_delta, int R) {
-  hc_box<B, 0>(one, many, src, osrc, use_delta, R, 0.0, -1, 0, 0);
-}
-template <bool B>
-__global__ __launch_bounds__(HCF_T) void hc_iter_kernel(PostPair one, const PostPair *__restrict__ many,
-                                                        int src, int osrc, int use_delta, int R,
-                                                        double alpha, int dprev, int dout, int last) {
-  hc_box<B, 1>(one, many, src, osrc, use_delta, R, alpha, dprev, dout, last);
-}
-
 // ---- Eq. (4): re-search of the discrete disparities around d.  A block
 // covers 128 pixels of a row and stages, as the sub-pixel kernel does, the
 // L window rows and the R columns of every candidate of the block; each
@@ -1005,14 +902,17 @@ __global__ __launch_bounds__(SP_TX) void research_kernel(PostPair one, const Pos
     const int LW = SP_TX + 2 * h, RW = SP_TX + (cmax - cmin) + 2 * h;
     const int lx0 = x0 - h, rx0 = x0 - cmax - h;
     const GLOBAL uint8_t *Lg = gro(P.left), *Rg = gro(P.right);
-    const size_t span = (size_t)(H - 1) * P.pitch + W;
-    for (int r = 0; r < win; ++r) {  // rows inside: the block has an inside pixel
-      const size_t row = (size_t)(y - h + r) * P.pitch;
-      stage_row(Ls[r], Lg + row + lx0, LW, Lg, Lg + span, tx);
-      stage_row(Rs[r], Rg + row + rx0, RW, Rg, Rg + span, tx);
-      if (tx == 0) {
-        misL[r] = (int)((uintptr_t)(Lg + row + lx0) & 3);
-        misR[r] = (int)((uintptr_t)(Rg + row + rx0) & 3);
+    const long long span = (long long)(H - 1) * P.pitch + W;
+#pragma unroll
+    for (int r = 0; r < SP_MAXWIN; ++r) {
+      if (r < win) {  // rows inside: the block has an inside pixel
+        const long long row = (long long)(y - h + r) * P.pitch;
+        stage_row(Ls[r], Lg, row + lx0, LW, span, tx);
+        stage_row(Rs[r], Rg, row + rx0, RW, span, tx);
+        if (tx == 0) {
+          misL[r] = (int)(((uintptr_t)Lg + (uintptr_t)(row + lx0)) & 3);
+          misR[r] = (int)(((uintptr_t)Rg + (uintptr_t)(row + rx0)) & 3);
+        }
       }
     }
   }
@@ -1146,23 +1046,23 @@ hipError_t post_lr(const PostLaunch &L, int tol, int dst) {
   LAUNCH(lr_check_kernel, pixgrid(L), dim3(PIX_T), tol, dst);
   return hipGetLastError();
 }
-static dim3 rowgrid(const PostLaunch &L) { return dim3(ceil_div(L.maxW, 64), L.maxH, L.npairs); }
+static dim3 rowgrid(const PostLaunch &L) { return dim3(ceil_div(L.maxW, 64), ceil_div(L.maxH, 4), L.npairs); }
 static dim3 vscangrid(const PostLaunch &L) {
   const int n = (L.maxW + 2 * (L.maxW + L.maxH - 1)) * ceil_div(L.maxH, SEG);
-  return dim3(ceil_div(n, 64), 1, L.npairs);
+  return dim3(ceil_div(n, 256), 1, L.npairs);
 }
 
 hipError_t post_outlier(const PostLaunch &L, int r, float thresh, int src, int dst) {
-  LAUNCH(outlier_rows_kernel, rowgrid(L), dim3(64), r, thresh, src);
-  LAUNCH(outlier_vscan_kernel, vscangrid(L), dim3(64), r, thresh, src);
+  LAUNCH(outlier_rows_kernel, rowgrid(L), dim3(256), r, thresh, src);
+  LAUNCH(outlier_vscan_kernel, vscangrid(L), dim3(256), r, thresh, src);
   LAUNCH(outlier_combine_kernel, pixgrid(L), dim3(PIX_T), src, dst);
   return hipGetLastError();
 }
 // radial fill src -> tmp, disk fill tmp -> dst (dst may equal src)
 hipError_t post_fill(const PostLaunch &L, int radial_r, int min_lines, int disk_r, float frac,
                      int src, int tmp, int dst) {
-  LAUNCH(fill_rows_kernel, rowgrid(L), dim3(64), radial_r, src);
-  LAUNCH(fill_vscan_kernel, vscangrid(L), dim3(64), radial_r, src);
+  LAUNCH(fill_rows_kernel, rowgrid(L), dim3(256), radial_r, src);
+  LAUNCH(fill_vscan_kernel, vscangrid(L), dim3(256), radial_r, src);
   LAUNCH(fill_radial_kernel, dim3(L.maxH, 1, L.npairs), dim3(256), min_lines, src, tmp);
   LAUNCH(fill_disk_kernel, pixgrid(L), dim3(PIX_T), disk_r, frac, tmp, dst);
   return hipGetLastError();
@@ -1190,53 +1090,33 @@ hipError_t post_research(const PostLaunch &L, int osrc, int msrc, int odst, int 
 
 hipError_t post_hc(const PostLaunch &L, int src, int R, int K, float alpha, int use_delta,
                    int research, int range, float eta) {
-  if (research) {
-    // Eqs. (1)-(4): o itself is smoothed (no sub-pixel offset) and re-searched
-    // after every iteration but the last; o ping-pongs between the two fill
-    // planes (the final mask stays in plane src)
-    int ocur = src, oalt = src == 1 ? 2 : 1;
-    const dim3 g(ceil_div(L.maxW, HCF_T - 2 * R), ceil_div(L.maxH, HCF_SY), L.npairs);
-    if (K == 0) {
-      LAUNCH(hc_copy_kernel, pixgrid(L), dim3(PIX_T), src, ocur, 0);
-      return hipGetLastError();
-    }
-    for (int it = 0; it < K; ++it) {
-      const int dp = it == 0 ? -1 : ((it & 1) ? F_D0 : F_D1), dn = (it & 1) ? F_D1 : F_D0;
-      const int last = it == K - 1;
-      LAUNCH(hc_mean_s_kernel, g, dim3(HCF_T), src, ocur, 0, R);
-      LAUNCH(hc_iter_kernel, g, dim3(HCF_T), src, ocur, 0, R, (double)alpha, dp, dn, last);
-      if (!last) {
-        LAUNCH(research_kernel, dim3(ceil_div(L.maxW, SP_TX), L.maxH, L.npairs), dim3(SP_TX), ocur,
-               src, oalt, dn, range, (double)eta);
-        std::swap(ocur, oalt);
-      }
-    }
-    return hipGetLastError();
-  }
   if (K == 0) {
     LAUNCH(hc_copy_kernel, pixgrid(L), dim3(PIX_T), src, src, use_delta);
     return hipGetLastError();
   }
-  if (R <= HCF_RMAX) {
-    const dim3 g(ceil_div(L.maxW, HCF_T - 2 * R), ceil_div(L.maxH, HCF_SY), L.npairs);
-    LAUNCH(hc_mean_s_kernel, g, dim3(HCF_T), src, src, use_delta, R);
-    for (int it = 0; it < K; ++it) {
-      const int dp = it == 0 ? -1 : ((it & 1) ? F_D0 : F_D1), dn = (it & 1) ? F_D1 : F_D0;
-      LAUNCH(hc_iter_kernel, g, dim3(HCF_T), src, src, use_delta, R, (double)alpha, dp, dn,
-             it == K - 1 ? 1 : 0);
-    }
-    return hipGetLastError();
-  }
-  LAUNCH(hc_init_kernel, pixgrid(L), dim3(PIX_T), src, use_delta);
+  // research: Eqs. (1)-(4), the discrete o (no sub-pixel offset) is smoothed
+  // and re-searched after every iteration but the last; o ping-pongs between
+  // the two fill planes while the mask stays in plane src
+  int ocur = src, oalt = src == 1 ? 2 : 1;
+  if (research) use_delta = 0;
+  LAUNCH(hc_init_kernel, pixgrid(L), dim3(PIX_T), src, ocur, use_delta, 1);
   box2d(L, R, F_D, F_CNT);  // counts of valid pixels
-  box2d(L, R, F_IN, F_IN);  // box(s m)
-  LAUNCH(hc_a_kernel, pixgrid(L), dim3(PIX_T), src);
   for (int it = 0; it < K; ++it) {
+    if (it == 0 || research) {
+      if (it > 0) LAUNCH(hc_init_kernel, pixgrid(L), dim3(PIX_T), src, ocur, use_delta, 0);
+      box2d(L, R, F_IN, F_IN);  // box(o m) or box(s m)
+      LAUNCH(hc_a_kernel, pixgrid(L), dim3(PIX_T), src);
+    }
     LAUNCH(hc_b_kernel, pixgrid(L), dim3(PIX_T), src, (double)alpha, it == 0 ? 1 : 0);
     box2d(L, R, F_IN, F_IN);
     LAUNCH(hc_d_kernel, pixgrid(L), dim3(PIX_T), src);
+    if (research && it < K - 1) {
+      LAUNCH(research_kernel, dim3(ceil_div(L.maxW, SP_TX), L.maxH, L.npairs), dim3(SP_TX), ocur,
+             src, oalt, (int)F_D, range, (double)eta);
+      std::swap(ocur, oalt);
+    }
   }
-  LAUNCH(hc_out_kernel, pixgrid(L), dim3(PIX_T), src, K > 0 ? (int)F_D : (int)F_S);
+  LAUNCH(hc_out_kernel, pixgrid(L), dim3(PIX_T), src, (int)F_D);
   return hipGetLastError();
 }
 
