@@ -768,8 +768,34 @@ __global__ void box_v_kernel(PostPair one, const PostPair *__restrict__ many, in
   }
 }
 
+// Output stage of a row box pass: the plain box sum (mode 0), or the masked
+// mean steps fused into it: mode 1 a = box(s m)/box(m) (Eq. 1), mode 2
+// d = a - box(b m)/box(m) (Eq. 3), mode 3 the same d written as the final
+// disparity (NaN where invalid) and mask.
+__device__ __forceinline__ void box_store(const PostPair &P, int mode, int src, int out, size_t N,
+                                          size_t k, double v) {
+  if (mode == 0) {
+    P.f[(size_t)out * N + k] = v;
+    return;
+  }
+  const uint8_t mk = P.mb[src][k];
+  const double mean = v / P.f[(size_t)F_CNT * N + k];
+  if (mode == 1) {
+    P.f[(size_t)F_A * N + k] = mk ? mean : 0.0;
+  } else {
+    const double d = mk ? P.f[(size_t)F_A * N + k] - mean : 0.0;
+    if (mode == 2) {
+      P.f[(size_t)F_D * N + k] = d;
+    } else {
+      P.disparity[k] = mk ? (float)d : __builtin_nanf("");
+      if (P.valid_mask) P.valid_mask[k] = mk;
+    }
+  }
+}
+
 template <bool B>
-__global__ void box_h_kernel(PostPair one, const PostPair *__restrict__ many, int R, int seg, int in, int out) {
+__global__ void box_h_kernel(PostPair one, const PostPair *__restrict__ many, int R, int seg, int in, int out,
+                             int mode, int src) {
   PAIR;
   const int y = blockIdx.x * blockDim.x + threadIdx.x;
   const int x0 = blockIdx.y * seg;
@@ -777,13 +803,12 @@ __global__ void box_h_kernel(PostPair one, const PostPair *__restrict__ many, in
   if (y >= H || x0 >= W) return;
   const size_t N = (size_t)W * H;
   const double *row = P.f + in * N + (size_t)y * W;
-  double *fo = P.f + out * N + (size_t)y * W;
   double s = 0.0;
   for (int u = x0 - R; u <= x0 + R; ++u)
     if (u >= 0 && u < W) s += row[u];
   const int x1 = min(x0 + seg, W);
   for (int x = x0; x < x1; ++x) {
-    fo[x] = s;
+    box_store(P, mode, src, out, N, (size_t)y * W + x, s);
     const int a = x + R + 1, b = x - R;
     if (a < W) s += row[a];
     if (b >= 0) s -= row[b];
@@ -796,7 +821,7 @@ __global__ void box_h_kernel(PostPair one, const PostPair *__restrict__ many, in
 constexpr int BOXH_MAXW = 4096;
 template <bool B>
 __global__ __launch_bounds__(256) void box_h_lds_kernel(PostPair one, const PostPair *__restrict__ many, int R,
-                                                        int in, int out) {
+                                                        int in, int out, int mode, int src) {
   PAIR;
   __shared__ double row[BOXH_MAXW];
   __shared__ double part[256];
@@ -804,10 +829,9 @@ __global__ __launch_bounds__(256) void box_h_lds_kernel(PostPair one, const Post
   const int H = P.H, W = P.W;
   if (y >= H) return;
   const size_t N = (size_t)W * H;
-  const double *src = P.f + in * N + (size_t)y * W;
-  double *dst = P.f + out * N + (size_t)y * W;
+  const double *rin = P.f + in * N + (size_t)y * W;
   const int t = threadIdx.x;
-  for (int x = t; x < W; x += 256) row[x] = src[x];
+  for (int x = t; x < W; x += 256) row[x] = rin[x];
   __syncthreads();
   // each thread scans a contiguous segment, then the segment totals
   const int per = ceil_div(W, 256);
@@ -830,7 +854,7 @@ __global__ __launch_bounds__(256) void box_h_lds_kernel(PostPair one, const Post
   __syncthreads();
   for (int x = t; x < W; x += 256) {
     const int a = min(x + R, W - 1), b = x - R - 1;
-    dst[x] = row[a] - (b >= 0 ? row[b] : 0.0);
+    box_store(P, mode, src, out, N, (size_t)y * W + x, row[a] - (b >= 0 ? row[b] : 0.0));
   }
 }
 
@@ -967,18 +991,6 @@ __global__ void hc_copy_kernel(PostPair one, const PostPair *__restrict__ many, 
   });
 }
 
-// a = A(s) = box(s m) / box(m) on valid pixels (Eq. 1)
-template <bool B>
-__global__ void hc_a_kernel(PostPair one, const PostPair *__restrict__ many, int src) {
-  PAIR;
-  const int W = P.W, H = P.H;
-  (void)W;
-  (void)H;
-  for_pixels(P, [&](int x, int y, size_t k) {
-    const size_t N = (size_t)W * H;
-    P.f[F_A * N + k] = P.mb[src][k] ? P.f[F_IN * N + k] / P.f[F_CNT * N + k] : 0.0;
-  });
-}
 
 // b = a - alpha*s - (1-alpha)*d_prev on valid pixels, 0 elsewhere (Eq. 2);
 // d_prev is s in the first iteration.
@@ -996,32 +1008,7 @@ __global__ void hc_b_kernel(PostPair one, const PostPair *__restrict__ many, int
   });
 }
 
-// d = a - A(b) (Eq. 3)
-template <bool B>
-__global__ void hc_d_kernel(PostPair one, const PostPair *__restrict__ many, int src) {
-  PAIR;
-  const int W = P.W, H = P.H;
-  (void)W;
-  (void)H;
-  for_pixels(P, [&](int x, int y, size_t k) {
-    const size_t N = (size_t)W * H;
-    P.f[F_D * N + k] = P.mb[src][k] ? P.f[F_A * N + k] - P.f[F_IN * N + k] / P.f[F_CNT * N + k] : 0.0;
-  });
-}
 
-template <bool B>
-__global__ void hc_out_kernel(PostPair one, const PostPair *__restrict__ many, int src, int plane) {
-  PAIR;
-  const int W = P.W, H = P.H;
-  (void)W;
-  (void)H;
-  for_pixels(P, [&](int x, int y, size_t k) {
-    const size_t N = (size_t)W * H;
-    const uint8_t mk = P.mb[src][k];
-    P.disparity[k] = mk ? (float)P.f[plane * N + k] : __builtin_nanf("");
-    if (P.valid_mask) P.valid_mask[k] = mk;
-  });
-}
 
 // ---------------------------------------------------------------- host side
 static inline dim3 pixgrid(const PostLaunch &L) { return dim3(ceil_div(L.maxW, PIX_SEG), L.maxH, L.npairs); }
@@ -1068,15 +1055,16 @@ hipError_t post_fill(const PostLaunch &L, int radial_r, int min_lines, int disk_
   return hipGetLastError();
 }
 
-static void box2d(const PostLaunch &L, int R, int in, int out) {
+// Box sum over the (2R+1)^2 window of plane `in`, stored by box_store's mode.
+static void box2d(const PostLaunch &L, int R, int in, int out, int mode = 0, int src = 0) {
   const int seg = 32;
   LAUNCH(box_v_kernel, dim3(ceil_div(L.maxW, 64), ceil_div(L.maxH, seg), L.npairs), dim3(64), R,
          seg, in, F_TMP);
   if (L.maxW <= BOXH_MAXW)
-    LAUNCH(box_h_lds_kernel, dim3(L.maxH, 1, L.npairs), dim3(256), R, F_TMP, out);
+    LAUNCH(box_h_lds_kernel, dim3(L.maxH, 1, L.npairs), dim3(256), R, F_TMP, out, mode, src);
   else
     LAUNCH(box_h_kernel, dim3(ceil_div(L.maxH, 64), ceil_div(L.maxW, seg), L.npairs), dim3(64), R,
-           seg, F_TMP, out);
+           seg, F_TMP, out, mode, src);
 }
 
 // Improved Laplacian smoothing of (ob[src], delta, mb[src]) or s_in; writes
@@ -1104,19 +1092,16 @@ hipError_t post_hc(const PostLaunch &L, int src, int R, int K, float alpha, int 
   for (int it = 0; it < K; ++it) {
     if (it == 0 || research) {
       if (it > 0) LAUNCH(hc_init_kernel, pixgrid(L), dim3(PIX_T), src, ocur, use_delta, 0);
-      box2d(L, R, F_IN, F_IN);  // box(o m) or box(s m)
-      LAUNCH(hc_a_kernel, pixgrid(L), dim3(PIX_T), src);
+      box2d(L, R, F_IN, F_IN, 1, src);  // a = box(o m) / box(m) or box(s m) / box(m)
     }
     LAUNCH(hc_b_kernel, pixgrid(L), dim3(PIX_T), src, (double)alpha, it == 0 ? 1 : 0);
-    box2d(L, R, F_IN, F_IN);
-    LAUNCH(hc_d_kernel, pixgrid(L), dim3(PIX_T), src);
+    box2d(L, R, F_IN, F_IN, it == K - 1 ? 3 : 2, src);  // d = a - box(b m) / box(m)
     if (research && it < K - 1) {
       LAUNCH(research_kernel, dim3(ceil_div(L.maxW, SP_TX), L.maxH, L.npairs), dim3(SP_TX), ocur,
              src, oalt, (int)F_D, range, (double)eta);
       std::swap(ocur, oalt);
     }
   }
-  LAUNCH(hc_out_kernel, pixgrid(L), dim3(PIX_T), src, (int)F_D);
   return hipGetLastError();
 }
 
