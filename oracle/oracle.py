@@ -53,7 +53,7 @@ class Params(C.Structure):
                 ("fill_disk_frac", C.c_double), ("smooth_radius", C.c_int32),
                 ("smooth_iters", C.c_int32), ("smooth_alpha", C.c_double),
                 ("research", C.c_int32), ("research_range", C.c_int32),
-                ("research_eta", C.c_double)]
+                ("research_eta", C.c_double), ("chess", C.c_int32)]
 
 
 def params_c1(**kw):
@@ -61,7 +61,7 @@ def params_c1(**kw):
     p = dict(subpixel=1, lr_check=1, lr_tol=1, radial_iters=0, radial_r0=10, radial_dr=10,
              radial_thresh=2.5, fill_radial_r=50, fill_min_lines=2, fill_disk_r=20,
              fill_disk_frac=0.25, smooth_radius=2, smooth_iters=1, smooth_alpha=0.1, research=0,
-             research_range=5, research_eta=0.01)
+             research_range=5, research_eta=0.01, chess=0)
     p.update(kw)
     return Params(**p)
 
@@ -71,17 +71,17 @@ def params_c2(**kw):
     p = dict(subpixel=1, lr_check=1, lr_tol=1, radial_iters=3, radial_r0=10, radial_dr=10,
              radial_thresh=2.5, fill_radial_r=50, fill_min_lines=2, fill_disk_r=20,
              fill_disk_frac=0.25, smooth_radius=15, smooth_iters=3, smooth_alpha=0.1, research=0,
-             research_range=5, research_eta=0.01)
+             research_range=5, research_eta=0.01, chess=0)
     p.update(kw)
     return Params(**p)
 
 
 def _setup(L):
-    L.or_window_stats.argtypes = [u8, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, i64, i64, i64, u8]
+    L.or_window_stats.argtypes = [u8] + [C.c_int] * 6 + [i64, i64, i64, u8]
     L.or_window_stats.restype = C.c_int
     L.or_zncc_windows.argtypes = [u8, u8, C.c_int]
     L.or_zncc_windows.restype = C.c_double
-    L.or_match.argtypes = [u8, u8] + [C.c_int] * 9 + [i32, u8, f64, f64, f64, f64, i32, u8, f64, f64]
+    L.or_match.argtypes = [u8, u8] + [C.c_int] * 10 + [i32, u8, f64, f64, f64, f64, i32, u8, f64, f64]
     L.or_match.restype = C.c_int
     L.or_subpixel.argtypes = [C.c_int64, i32, u8, f64, f64, f64, C.c_int, C.c_int, f64]
     L.or_subpixel.restype = None
@@ -93,9 +93,9 @@ def _setup(L):
     L.or_fill.restype = C.c_int
     L.or_hc_smooth.argtypes = [C.c_int, C.c_int, f64, u8, C.c_int, C.c_int, C.c_double, f64]
     L.or_hc_smooth.restype = C.c_int
-    L.or_research.argtypes = [u8, u8] + [C.c_int] * 6 + [i32, u8, f64, C.c_int, C.c_double, i32]
+    L.or_research.argtypes = [u8, u8] + [C.c_int] * 7 + [i32, u8, f64, C.c_int, C.c_double, i32]
     L.or_research.restype = None
-    L.or_hc_research.argtypes = ([u8, u8] + [C.c_int] * 6 + [i32, u8, C.c_int, C.c_int, C.c_double,
+    L.or_hc_research.argtypes = ([u8, u8] + [C.c_int] * 7 + [i32, u8, C.c_int, C.c_int, C.c_double,
                                                              C.c_double, C.c_int, f64])
     L.or_hc_research.restype = C.c_int
     L.or_reproject.argtypes = [C.c_int, C.c_int, f64, f64, f64]
@@ -116,12 +116,12 @@ def _c(a, dt):
     return np.ascontiguousarray(a, dtype=dt)
 
 
-def window_stats(img, win, brute=False):
+def window_stats(img, win, brute=False, chess=False):
     img = _c(img, np.uint8)
     H, W = img.shape
     S = np.zeros((H, W), np.int64); SS = np.zeros_like(S); V = np.zeros_like(S)
     ins = np.zeros((H, W), np.uint8)
-    rc = lib().or_window_stats(img, H, W, W, win, int(brute), S, SS, V, ins)
+    rc = lib().or_window_stats(img, H, W, W, win, int(brute), int(chess), S, SS, V, ins)
     assert rc == 0, rc
     return S, SS, V, ins
 
@@ -132,7 +132,7 @@ def zncc_windows(a, b):
     return lib().or_zncc_windows(a, b, a.size)
 
 
-def match(left, right, dmin, dmax, win, rows=None, brute=False):
+def match(left, right, dmin, dmax, win, rows=None, brute=False, chess=False):
     """Cost volume + WTA for rows [y0, y1) (default all rows)."""
     L = _c(left, np.uint8); R = _c(right, np.uint8)
     H, W = L.shape
@@ -141,7 +141,7 @@ def match(left, right, dmin, dmax, win, rows=None, brute=False):
     out = dict(oL=np.zeros(n, np.int32), mL=np.zeros(n, np.uint8), zbest=np.zeros(n),
                gap=np.zeros(n), zm=np.zeros(n), zp=np.zeros(n), oR=np.zeros(n, np.int32),
                mR=np.zeros(n, np.uint8), zbestR=np.zeros(n), gapR=np.zeros(n))
-    rc = lib().or_match(L, R, H, W, W, dmin, dmax, win, y0, y1, int(brute), out["oL"],
+    rc = lib().or_match(L, R, H, W, W, dmin, dmax, win, y0, y1, int(brute), int(chess), out["oL"],
                         out["mL"], out["zbest"], out["gap"], out["zm"], out["zp"], out["oR"],
                         out["mR"], out["zbestR"], out["gapR"])
     assert rc == 0, rc
@@ -189,23 +189,24 @@ def hc_smooth(s, m, R, K, alpha=0.1):
     return out
 
 
-def research(left, right, dmin, dmax, win, o, m, d, range_=5, eta=0.01):
+def research(left, right, dmin, dmax, win, o, m, d, range_=5, eta=0.01, chess=False):
     """One Eq. (4) re-search of every valid pixel around d (float64 H x W)."""
     L = _c(left, np.uint8); R = _c(right, np.uint8)
     H, W = L.shape
     out = np.zeros((H, W), np.int32)
-    lib().or_research(L, R, H, W, W, win, dmin, dmax, _c(o, np.int32), _c(m, np.uint8),
+    lib().or_research(L, R, H, W, W, win, int(chess), dmin, dmax, _c(o, np.int32), _c(m, np.uint8),
                       _c(d, np.float64), range_, eta, out)
     return out
 
 
-def hc_research(left, right, dmin, dmax, win, o, m, R, K, alpha=0.1, eta=0.01, range_=5):
+def hc_research(left, right, dmin, dmax, win, o, m, R, K, alpha=0.1, eta=0.01, range_=5,
+                chess=False):
     """Eqs. (1)-(4): returns (d^K, final o)."""
     L = _c(left, np.uint8); Rr = _c(right, np.uint8)
     H, W = L.shape
     oo = _c(o, np.int32).copy()
     out = np.zeros((H, W), np.float64)
-    rc = lib().or_hc_research(L, Rr, H, W, W, win, dmin, dmax, oo, _c(m, np.uint8), R, K, alpha,
+    rc = lib().or_hc_research(L, Rr, H, W, W, win, int(chess), dmin, dmax, oo, _c(m, np.uint8), R, K, alpha,
                               eta, range_, out)
     assert rc == 0, rc
     return out, oo

@@ -70,12 +70,16 @@ static int inside(int H, int W, int h, int y, int x) {
  * paper).  For every pixel whose window lies inside the image:
  *   S = sum I, SS = sum I^2, varN = n*SS - S^2 (n = win^2), exactly.
  * brute != 0 sums the window directly instead of through integral images.
+ * chess != 0: the chessboard window of the paper's matching (every other
+ * pixel): only offsets (u, v) from the centre with u + v even, n =
+ * (win^2 + 1) / 2, summed directly.
  */
-int or_window_stats(const uint8_t *img, int H, int W, int pitch, int win, int brute,
+int or_window_stats(const uint8_t *img, int H, int W, int pitch, int win, int brute, int chess,
                     int64_t *S, int64_t *SS, int64_t *varN, uint8_t *ins) {
   if (win < 1 || (win & 1) == 0 || H < 1 || W < 1 || pitch < W) return OR_EINVAL;
   int h = win / 2;
-  int64_t n = (int64_t)win * win;
+  int64_t n = chess ? ((int64_t)win * win + 1) / 2 : (int64_t)win * win;
+  if (chess) brute = 1;
   int64_t *f1 = NULL, *f2 = NULL, *i1 = NULL, *i2 = NULL;
   if (!brute) {
     f1 = malloc(sizeof(int64_t) * (size_t)H * W);
@@ -102,6 +106,7 @@ int or_window_stats(const uint8_t *img, int H, int W, int pitch, int win, int br
       if (brute) {
         for (int v = -h; v <= h; ++v)
           for (int u = -h; u <= h; ++u) {
+            if (chess && ((u + v) & 1)) continue;
             int64_t p = img[(int64_t)(y + v) * pitch + x + u];
             s += p; ss += p * p;
           }
@@ -144,20 +149,24 @@ double or_zncc_windows(const uint8_t *a, const uint8_t *b, int n) {
  *   z(x,y,d) = (n*S_LR - S_L*S_R) / sqrt(varN_L * varN_R)
  * with S_LR = sum_W L(x+u,y+v) R(x+u-d,y+v) in int64 (integral image of the
  * product per d, or direct loops when brute != 0).  The whole cost volume is
- * kept in memory.
+ * kept in memory.  chess != 0: the window is the chessboard of the paper's
+ * matching (Section II-A: every other pixel of the window), the cells with
+ * u + v even, and n = (win^2 + 1) / 2; the sums then come from integral
+ * images of the product masked to one checker colour, picked by the colour
+ * of the centre (x + y).
  *   oL, mL      : argmax_d z (ties -> smallest d), mask 1 if any valid d
  *   zbest, gap  : best z and best - (max over other valid d) (inf if none)
  *   zm, zp      : z at oL-1 and oL+1 (NaN if out of range or invalid)
  *   oR, mR, ... : for right pixel xr, argmax_d z(xr+d, y, d)
  */
 int or_match(const uint8_t *L, const uint8_t *R, int H, int W, int pitch, int dmin, int dmax,
-             int win, int y0, int y1, int brute,
+             int win, int y0, int y1, int brute, int chess,
              int32_t *oL, uint8_t *mL, double *zbest, double *gap, double *zm, double *zp,
              int32_t *oR, uint8_t *mR, double *zbestR, double *gapR) {
   if (win < 1 || (win & 1) == 0 || dmax < dmin || y0 < 0 || y1 > H || y1 < y0 || pitch < W)
     return OR_EINVAL;
   int h = win / 2;
-  int64_t n = (int64_t)win * win;
+  int64_t n = chess ? ((int64_t)win * win + 1) / 2 : (int64_t)win * win;
   int D = dmax - dmin + 1;
   int rows = y1 - y0;
   size_t plane = (size_t)rows * W;
@@ -170,8 +179,8 @@ int or_match(const uint8_t *L, const uint8_t *R, int H, int W, int pitch, int dm
     free(SL); free(SSL); free(VL); free(SR); free(SSR); free(VR); free(IL); free(IR); free(vol);
     return OR_ENOMEM;
   }
-  or_window_stats(L, H, W, pitch, win, brute, SL, SSL, VL, IL);
-  or_window_stats(R, H, W, pitch, win, brute, SR, SSR, VR, IR);
+  or_window_stats(L, H, W, pitch, win, brute, chess, SL, SSL, VL, IL);
+  or_window_stats(R, H, W, pitch, win, brute, chess, SR, SSR, VR, IR);
 
   /* rows of the product image needed: [y0-h, y1+h) clipped to the image */
   int py0 = y0 - h < 0 ? 0 : y0 - h;
@@ -182,19 +191,23 @@ int or_match(const uint8_t *L, const uint8_t *R, int H, int W, int pitch, int dm
   {
     int64_t *prod = brute ? NULL : malloc(sizeof(int64_t) * (size_t)(PH > 0 ? PH : 1) * W);
     int64_t *ii = brute ? NULL : malloc(sizeof(int64_t) * (size_t)(PH + 1) * (W + 1));
+    int64_t *ii1 = (brute || !chess) ? NULL : malloc(sizeof(int64_t) * (size_t)(PH + 1) * (W + 1));
 #pragma omp for schedule(dynamic)
     for (int di = 0; di < D; ++di) {
       int d = dmin + di;
       if (!brute) {
-        for (int y = py0; y < py1; ++y)
-          for (int x = 0; x < W; ++x) {
-            int xr = x - d;
-            int64_t v = 0;
-            if (xr >= 0 && xr < W)
-              v = (int64_t)L[(int64_t)y * pitch + x] * (int64_t)R[(int64_t)y * pitch + xr];
-            prod[(int64_t)(y - py0) * W + x] = v;
-          }
-        integral(prod, PH, W, ii);
+        /* colour c of the chessboard: pass 0 keeps (x + y) even cells, pass 1 odd */
+        for (int pass = 0; pass < (chess ? 2 : 1); ++pass) {
+          for (int y = py0; y < py1; ++y)
+            for (int x = 0; x < W; ++x) {
+              int xr = x - d;
+              int64_t v = 0;
+              if (xr >= 0 && xr < W && (!chess || ((x + y) & 1) == pass))
+                v = (int64_t)L[(int64_t)y * pitch + x] * (int64_t)R[(int64_t)y * pitch + xr];
+              prod[(int64_t)(y - py0) * W + x] = v;
+            }
+          integral(prod, PH, W, pass ? ii1 : ii);
+        }
       }
       double *zd = vol + plane * (size_t)di;
       for (int y = y0; y < y1; ++y)
@@ -206,11 +219,13 @@ int or_match(const uint8_t *L, const uint8_t *R, int H, int W, int pitch, int dm
             int64_t slr = 0;
             if (brute) {
               for (int v = -h; v <= h; ++v)
-                for (int u = -h; u <= h; ++u)
+                for (int u = -h; u <= h; ++u) {
+                  if (chess && ((u + v) & 1)) continue;
                   slr += (int64_t)L[(int64_t)(y + v) * pitch + x + u] *
                          (int64_t)R[(int64_t)(y + v) * pitch + x + u - d];
+                }
             } else {
-              slr = box(ii, W, y - py0, x, h);
+              slr = box(chess && ((x + y) & 1) ? ii1 : ii, W, y - py0, x, h);
             }
             int64_t num = n * slr - SL[kl] * SR[kr];
             z = (double)num / sqrt((double)VL[kl] * (double)VR[kr]);
@@ -218,7 +233,7 @@ int or_match(const uint8_t *L, const uint8_t *R, int H, int W, int pitch, int dm
           zd[(size_t)(y - y0) * W + x] = z;
         }
     }
-    free(prod); free(ii);
+    free(prod); free(ii); free(ii1);
   }
 
   /* left reference WTA */
@@ -510,16 +525,19 @@ int or_hc_smooth(int H, int W, const double *s, const uint8_t *m, int R, int K, 
 /*
  * Exact ZNCC of the left window at (x, y) and the right window at (x - d, y)
  * by direct sums (Section II-A): (n*S_LR - S_L*S_R) / sqrt(varN_L * varN_R)
- * with int64 sums.  Returns NAN when either window leaves the image or has
- * zero variance (the candidate is not valid).
+ * with int64 sums (chess: the chessboard cells u + v even, n = (win^2+1)/2).
+ * Returns NAN when either window leaves the image or has zero variance (the
+ * candidate is not valid).
  */
-static double zncc_at(const uint8_t *L, const uint8_t *R, int H, int W, int pitch, int win, int y,
-                      int x, int d) {
+static double zncc_at(const uint8_t *L, const uint8_t *R, int H, int W, int pitch, int win,
+                      int chess, int y, int x, int d) {
   int h = win / 2, xr = x - d;
   if (!inside(H, W, h, y, x) || xr < h || xr > W - 1 - h) return NAN;
-  int64_t n = (int64_t)win * win, sl = 0, sll = 0, sr = 0, srr = 0, slr = 0;
+  int64_t n = chess ? ((int64_t)win * win + 1) / 2 : (int64_t)win * win;
+  int64_t sl = 0, sll = 0, sr = 0, srr = 0, slr = 0;
   for (int v = -h; v <= h; ++v)
     for (int u = -h; u <= h; ++u) {
+      if (chess && ((u + v) & 1)) continue;
       int64_t a = L[(int64_t)(y + v) * pitch + x + u], b = R[(int64_t)(y + v) * pitch + xr + u];
       sl += a; sll += a * a; sr += b; srr += b * b; slr += a * b;
     }
@@ -537,9 +555,9 @@ static double zncc_at(const uint8_t *L, const uint8_t *R, int H, int W, int pitc
  * smaller o*.  A pixel without any defined candidate keeps its o.
  * o_in / o_out: H*W int32 (may alias), m: mask, d: H*W.
  */
-void or_research(const uint8_t *L, const uint8_t *R, int H, int W, int pitch, int win, int dmin,
-                 int dmax, const int32_t *o_in, const uint8_t *m, const double *d, int range,
-                 double eta, int32_t *o_out) {
+void or_research(const uint8_t *L, const uint8_t *R, int H, int W, int pitch, int win, int chess,
+                 int dmin, int dmax, const int32_t *o_in, const uint8_t *m, const double *d,
+                 int range, double eta, int32_t *o_out) {
 #pragma omp parallel for
   for (int y = 0; y < H; ++y)
     for (int x = 0; x < W; ++x) {
@@ -551,7 +569,7 @@ void or_research(const uint8_t *L, const uint8_t *R, int H, int W, int pitch, in
         if (hi > dmax) hi = dmax;
         double best = INFINITY;
         for (int c = (int)lo; c <= (int)hi; ++c) {
-          double z = zncc_at(L, R, H, W, pitch, win, y, x, c);
+          double z = zncc_at(L, R, H, W, pitch, win, chess, y, x, c);
           if (isnan(z)) continue;
           double cost = 1.0 / (z > 1e-3 ? z : 1e-3) + eta * (c - d[k]) * (c - d[k]);
           if (cost < best) { best = cost; o = c; }
@@ -572,9 +590,9 @@ void or_research(const uint8_t *L, const uint8_t *R, int H, int W, int pitch, in
  * o (int32, in/out: the final discrete disparities), out = d^K (NaN where
  * invalid).
  */
-int or_hc_research(const uint8_t *L, const uint8_t *R, int H, int W, int pitch, int win, int dmin,
-                   int dmax, int32_t *o, const uint8_t *m, int Rs, int K, double alpha, double eta,
-                   int range, double *out) {
+int or_hc_research(const uint8_t *L, const uint8_t *R, int H, int W, int pitch, int win, int chess,
+                   int dmin, int dmax, int32_t *o, const uint8_t *m, int Rs, int K, double alpha,
+                   double eta, int range, double *out) {
   int64_t N = (int64_t)H * W;
   double *od = malloc(sizeof(double) * (size_t)N), *a = malloc(sizeof(double) * (size_t)N);
   double *b = malloc(sizeof(double) * (size_t)N), *ab = malloc(sizeof(double) * (size_t)N);
@@ -591,7 +609,8 @@ int or_hc_research(const uint8_t *L, const uint8_t *R, int H, int W, int pitch, 
       b[k] = m[k] ? a[k] - alpha * od[k] - (1.0 - alpha) * dprev[k] : 0.0;
     masked_mean(H, W, b, m, Rs, ab);
     for (int64_t k = 0; k < N; ++k) dprev[k] = m[k] ? a[k] - ab[k] : NAN;
-    if (it < K - 1) or_research(L, R, H, W, pitch, win, dmin, dmax, o, m, dprev, range, eta, o);
+    if (it < K - 1)
+      or_research(L, R, H, W, pitch, win, chess, dmin, dmax, o, m, dprev, range, eta, o);
   }
   if (K == 0)
     for (int64_t k = 0; k < N; ++k) dprev[k] = m[k] ? (double)o[k] : NAN;
@@ -642,6 +661,7 @@ typedef struct {
   int32_t research;       /* 1: Eq. (4) re-search inside the smoothing */
   int32_t research_range; /* 5 px */
   double research_eta;    /* 0.01 */
+  int32_t chess;          /* 1: chessboard window (Section II-A) */
 } or_params;
 
 /*
@@ -668,7 +688,8 @@ int or_pipeline(const uint8_t *L, const uint8_t *R, int H, int W, int pitch, int
   int rc = OR_ENOMEM;
   if (!oL || !oR || !mL || !mR || !mm || !m2 || !zb || !gp || !zm || !zp || !zbR || !gpR || !dl || !s)
     goto done;
-  rc = or_match(L, R, H, W, pitch, dmin, dmax, win, 0, H, 0, oL, mL, zb, gp, zm, zp, oR, mR, zbR, gpR);
+  rc = or_match(L, R, H, W, pitch, dmin, dmax, win, 0, H, 0, p->chess, oL, mL, zb, gp, zm, zp, oR,
+                mR, zbR, gpR);
   if (rc) goto done;
   if (o_wta) memcpy(o_wta, oL, sizeof(int32_t) * (size_t)N);
   if (m_wta) memcpy(m_wta, mL, (size_t)N);
@@ -692,7 +713,7 @@ int or_pipeline(const uint8_t *L, const uint8_t *R, int H, int W, int pitch, int
   if (o_post) memcpy(o_post, oL, sizeof(int32_t) * (size_t)N);
   for (int64_t k = 0; k < N; ++k) s[k] = mm[k] == 1 ? (double)oL[k] + dl[k] : (double)oL[k];
   if (p->research) {
-    rc = or_hc_research(L, R, H, W, pitch, win, dmin, dmax, oL, mm, p->smooth_radius,
+    rc = or_hc_research(L, R, H, W, pitch, win, p->chess, dmin, dmax, oL, mm, p->smooth_radius,
                         p->smooth_iters, p->smooth_alpha, p->research_eta, p->research_range, disp);
     if (rc) goto done;
   } else if (p->smooth_iters > 0) {
