@@ -219,6 +219,16 @@ def extras(B, torch, np, synth, seq, pairs, h):
     ms = _time(lambda: B.stereo_match(Lp, Rp, -20, 80, WIN, params, handle=h), torch)
     res["paper_range_ms_per_pair"] = round(ms, 4)
     res["paper_range_gevals"] = round(H * W * 101 / ms / 1e6, 2)
+    # the paper's own matching setting: 11x11 chessboard window over -20..80;
+    # the matcher alone on that one pair (the figure the paper times at about
+    # 5 ms) and the whole path, then the matcher on the 30-frame batch
+    pc = B.preset("full", chessboard=1)
+    one = [{"left": Lp, "right": Rp, "dmin": -20, "dmax": 80, "win": WIN}]
+    res["paper_chess_matcher_ms"] = round(B.stereo_time_matcher(one, pc, reps=10, handle=h), 4)
+    res["paper_chess_ms_per_pair"] = round(
+        _time(lambda: B.stereo_match(Lp, Rp, -20, 80, WIN, pc, handle=h), torch), 4)
+    res["matcher_chess_fp32_ms_per_pair"] = round(
+        B.stereo_time_matcher(pairs, pc, reps=5, handle=h) / len(pairs), 4)
     # disparity to 3-D points
     disp, _ = B.stereo_match(Lp, Rp, -20, 80, WIN, params, handle=h)
     Q = np.array([[1, 0, 0, -W / 2], [0, 1, 0, -H / 2], [0, 0, 0, 1000.0], [0, 0, 0.2, 0]])

@@ -75,6 +75,11 @@ typedef struct {
                                  II-C); 0: smoothing of s = o + delta */
   int32_t research_range;     /* half width of the re-search window (5) */
   float research_eta;         /* weight of (o* - d)^2 in Eq. (4) (0.01) */
+  int32_t chessboard;         /* 1: the chessboard window of Section II-A - only
+                                 the cells (u, v) around the centre with u + v
+                                 even (61 of 121 at 11x11) enter every ZNCC,
+                                 in matching, sub-pixel fit and re-search;
+                                 0: the full square window (default) */
 } st_params;
 
 /* Fill *p with the paper's constants (Section II, Appendix of constants):
@@ -170,10 +175,13 @@ st_status stereo_debug_get(st_handle h, const char *name, void **dev_ptr);
 
 /* Window statistics (Section II-A): S = sum I, SS = sum I^2 over the window
  * of every pixel whose window lies inside the image (0 elsewhere), and
- * inv = 1/sqrt(win^2*SS - S^2) computed in FP64 (NaN where the window leaves
- * the image or has zero variance). */
+ * inv = 1/sqrt(n*SS - S^2) computed in FP64 (NaN where the window leaves
+ * the image or has zero variance).  chess = 0: the square window, n = win^2;
+ * chess = 1: its chessboard cells (u + v even around the centre),
+ * n = (win^2 + 1) / 2.  The same flag has this meaning in st_match_wta,
+ * st_subpixel and st_research. */
 st_status st_window_stats(st_handle h, const uint8_t *img, int H, int W, int pitch, int win,
-                          int32_t *S, int32_t *SS, float *inv, void *stream);
+                          int chess, int32_t *S, int32_t *SS, float *inv, void *stream);
 
 /* ZNCC matching and winner-take-all in both references (Section II-A).
  *  oL, mL : argmax_d z(x, y, d) and 1 if any candidate is valid
@@ -182,14 +190,14 @@ st_status st_window_stats(st_handle h, const uint8_t *img, int H, int W, int pit
  * invalid; ties within 2^-18 of each other may resolve to either.
  * precision selects FP32 or FP16/BF16 image and cost storage. */
 st_status st_match_wta(st_handle h, const uint8_t *left, const uint8_t *right, int H, int W,
-                       int pitch, int dmin, int dmax, int win, int precision, int16_t *oL,
-                       uint8_t *mL, int16_t *oR, uint8_t *mR, void *stream);
+                       int pitch, int dmin, int dmax, int win, int chess, int precision,
+                       int16_t *oL, uint8_t *mL, int16_t *oR, uint8_t *mR, void *stream);
 
 /* Exact ZNCC at oL-1, oL, oL+1 (int32 sums, FP64 normalisation) and the
  * parabola offset delta; zm/zp NaN where the neighbour is not a valid
  * candidate.  Any of zbest/zm/zp may be NULL. */
 st_status st_subpixel(st_handle h, const uint8_t *left, const uint8_t *right, int H, int W,
-                      int pitch, int dmin, int dmax, int win, const int16_t *oL,
+                      int pitch, int dmin, int dmax, int win, int chess, const int16_t *oL,
                       const uint8_t *mL, double *zbest, double *zm, double *zp, float *delta,
                       void *stream);
 
@@ -224,7 +232,7 @@ st_status st_hc_smooth(st_handle h, const float *s, const uint8_t *m, int H, int
  * int16 H x W (must not alias); m: device uint8 H x W; d: device FP64 H x W.
  * ST_EINVAL for bad shapes, range outside [0, 64], eta < 0 or NULL pointers. */
 st_status st_research(st_handle h, const uint8_t *left, const uint8_t *right, int H, int W,
-                      int pitch, int dmin, int dmax, int win, const int16_t *o_in,
+                      int pitch, int dmin, int dmax, int win, int chess, const int16_t *o_in,
                       const uint8_t *m, const double *d, int range, float eta, int16_t *o_out,
                       void *stream);
 

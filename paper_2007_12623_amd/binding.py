@@ -45,7 +45,8 @@ class st_params(C.Structure):
                 ("smooth_radius", C.c_int32), ("smooth_iters", C.c_int32),
                 ("smooth_alpha", C.c_float), ("precision", C.c_int32),
                 ("debug_outputs", C.c_int32), ("research", C.c_int32),
-                ("research_range", C.c_int32), ("research_eta", C.c_float)]
+                ("research_range", C.c_int32), ("research_eta", C.c_float),
+                ("chessboard", C.c_int32)]
 
 
 class st_pair(C.Structure):
@@ -79,15 +80,15 @@ def lib() -> C.CDLL:
             "stereo_refine_backward": (i32, [vp, vp, vp, vp, vp, i32, i32, i32, i32, f32, vp, vp]),
             "stereo_refine_step": (i32, [vp, vp, vp, vp, i32, i32, f32, f32, vp]),
             "stereo_debug_get": (i32, [vp, C.c_char_p, C.POINTER(vp)]),
-            "st_window_stats": (i32, [vp, vp, i32, i32, i32, i32, vp, vp, vp, vp]),
-            "st_match_wta": (i32, [vp, vp, vp, i32, i32, i32, i32, i32, i32, i32, vp, vp, vp, vp, vp]),
-            "st_subpixel": (i32, [vp, vp, vp, i32, i32, i32, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp]),
+            "st_window_stats": (i32, [vp, vp, i32, i32, i32, i32, i32, vp, vp, vp, vp]),
+            "st_match_wta": (i32, [vp, vp, vp] + [i32] * 8 + [vp, vp, vp, vp, vp]),
+            "st_subpixel": (i32, [vp, vp, vp] + [i32] * 7 + [vp, vp, vp, vp, vp, vp, vp]),
             "st_lr_check": (i32, [vp, vp, vp, vp, vp, i32, i32, i32, vp, vp]),
             "st_radial_outlier": (i32, [vp, vp, vp, i32, i32, i32, f32, vp, vp]),
             "st_fill": (i32, [vp, vp, vp, i32, i32, i32, i32, i32, f32, vp, vp, vp]),
             "st_hc_smooth": (i32, [vp, vp, vp, i32, i32, i32, i32, f32, vp, vp]),
             "st_reproject": (i32, [vp, vp, i32, i32, vp, vp, vp]),
-            "st_research": (i32, [vp, vp, vp] + [i32] * 6 + [vp, vp, vp, i32, f32, vp, vp]),
+            "st_research": (i32, [vp, vp, vp] + [i32] * 7 + [vp, vp, vp, i32, f32, vp, vp]),
             "st_autotune": (i32, [vp, i32, i32, i32, i32, i32, i32, C.POINTER(i32), vp]),
             "st_set_variant": (i32, [vp, i32]),
             "stereo_time_matcher": (i32, [vp, C.POINTER(st_pair), i32, C.POINTER(st_params), i32,
@@ -277,18 +278,19 @@ def _hip_runtime():
 
 
 # ---------------------------------------------------------------- stages
-def st_window_stats(img, win, handle=None, stream=None):
+def st_window_stats(img, win, chess=False, handle=None, stream=None):
     import torch
     H, W = img.shape
     S = torch.empty((H, W), dtype=torch.int32, device=img.device)
     SS = torch.empty_like(S)
     inv = torch.empty((H, W), dtype=torch.float32, device=img.device)
-    _check(lib().st_window_stats(_h(handle), img.data_ptr(), H, W, img.stride(0), win,
+    _check(lib().st_window_stats(_h(handle), img.data_ptr(), H, W, img.stride(0), win, int(chess),
                                  S.data_ptr(), SS.data_ptr(), inv.data_ptr(), _stream(stream)))
     return S, SS, inv
 
 
-def st_match_wta(left, right, dmin, dmax, win, precision=ST_FP32, handle=None, stream=None):
+def st_match_wta(left, right, dmin, dmax, win, precision=ST_FP32, chess=False, handle=None,
+                 stream=None):
     import torch
     H, W = left.shape
     dev = left.device
@@ -297,12 +299,12 @@ def st_match_wta(left, right, dmin, dmax, win, precision=ST_FP32, handle=None, s
     mL = torch.empty((H, W), dtype=torch.uint8, device=dev)
     mR = torch.empty_like(mL)
     _check(lib().st_match_wta(_h(handle), left.data_ptr(), right.data_ptr(), H, W, left.stride(0),
-                              dmin, dmax, win, precision, oL.data_ptr(), mL.data_ptr(),
+                              dmin, dmax, win, int(chess), precision, oL.data_ptr(), mL.data_ptr(),
                               oR.data_ptr(), mR.data_ptr(), _stream(stream)))
     return oL, mL, oR, mR
 
 
-def st_subpixel(left, right, dmin, dmax, win, oL, mL, handle=None, stream=None):
+def st_subpixel(left, right, dmin, dmax, win, oL, mL, chess=False, handle=None, stream=None):
     import torch
     H, W = left.shape
     dev = left.device
@@ -311,7 +313,7 @@ def st_subpixel(left, right, dmin, dmax, win, oL, mL, handle=None, stream=None):
     zp = torch.empty_like(zb)
     dl = torch.empty((H, W), dtype=torch.float32, device=dev)
     _check(lib().st_subpixel(_h(handle), left.data_ptr(), right.data_ptr(), H, W, left.stride(0),
-                             dmin, dmax, win, oL.data_ptr(), mL.data_ptr(), zb.data_ptr(),
+                             dmin, dmax, win, int(chess), oL.data_ptr(), mL.data_ptr(), zb.data_ptr(),
                              zm.data_ptr(), zp.data_ptr(), dl.data_ptr(), _stream(stream)))
     return zb, zm, zp, dl
 
@@ -353,14 +355,14 @@ def st_hc_smooth(s, m, R, K, alpha=0.1, handle=None, stream=None):
     return out
 
 
-def st_research(left, right, dmin, dmax, win, o, m, d, range_=5, eta=0.01, handle=None,
-                stream=None):
+def st_research(left, right, dmin, dmax, win, o, m, d, range_=5, eta=0.01, chess=False,
+                handle=None, stream=None):
     """One Eq. (4) re-search: new int16 disparities around d (float64)."""
     import torch
     H, W = left.shape
     out = torch.empty_like(o)
     _check(lib().st_research(_h(handle), left.data_ptr(), right.data_ptr(), H, W, left.stride(0),
-                             dmin, dmax, win, o.data_ptr(), m.data_ptr(), d.data_ptr(), range_,
+                             dmin, dmax, win, int(chess), o.data_ptr(), m.data_ptr(), d.data_ptr(), range_,
                              eta, out.data_ptr(), _stream(stream)))
     return out
 

@@ -164,6 +164,7 @@ static st_status check_params(const st_params *p) {
   ARG(p->research_range >= 0 && p->research_range <= 64, "research_range out of range");
   ARG(p->research_eta >= 0.0f, "research_eta < 0");
   ARG(!p->research || p->smooth_radius <= 64, "the Eq. (4) re-search needs smooth_radius <= 64");
+  ARG(p->chessboard == 0 || p->chessboard == 1, "chessboard must be 0 or 1");
   return ST_OK;
 }
 
@@ -173,11 +174,14 @@ static int pmod(int a, int m) { return ((a % m) + m) % m; }
 
 // Spans, bands, chunks and plane padding of one pair for the matcher.
 static void make_geom(MatchPair &P, int H, int W, int win, int dmin, int dmax, int DC, int TY,
-                      int CG) {
+                      int CG, int chess) {
   const int h = win / 2, K = KC;
   P.H = H;
   P.W = W;
   P.win = win;
+  P.chess = chess;
+  P.nwin = chess ? (win * win + 1) / 2 : win * win;
+  P.lplane = 0;
   P.dmin = dmin;
   P.dmax = dmax;
   P.DC = DC;
@@ -237,8 +241,10 @@ static PairLayout layout(const MatchPair &P, int prec, bool debug) {
   const size_t N = (size_t)P.H * P.W;
   const size_t nl = (size_t)P.strideL * P.H, nr = (size_t)P.strideR * P.H;
   const int RB = prec == P_I16 ? 1 : 2;
-  Lo.Lp = c.take(2 * nl);
-  Lo.NLp = c.take(2 * nl);
+  // two colour copies of the L planes for the chessboard window
+  const size_t ncopy = P.chess ? 2 : 1;
+  Lo.Lp = c.take(2 * nl * ncopy);
+  Lo.NLp = c.take(2 * nl * ncopy);
   Lo.Rp = c.take(RB * nr + 64);
   Lo.negSL = c.take(4 * nl);
   Lo.invL = c.take(4 * nl);
@@ -282,6 +288,7 @@ static void fill_views(const PairLayout &Lo, void *base, uint32_t *keys, MatchPa
   const size_t N = (size_t)M.H * M.W;
   M.Lp = at<void>(base, Lo.Lp);
   M.NLp = at<void>(base, Lo.NLp);
+  M.lplane = M.chess ? (uint32_t)(2 * (size_t)M.strideL * M.H) : 0u;
   M.Rp = at<void>(base, Lo.Rp);
   M.negSL = at<int32_t>(base, Lo.negSL);
   M.invL = at<float>(base, Lo.invL);
@@ -297,6 +304,7 @@ static void fill_views(const PairLayout &Lo, void *base, uint32_t *keys, MatchPa
   Pp.W = M.W;
   Pp.pitch = pitch;
   Pp.win = M.win;
+  Pp.chess = M.chess;
   Pp.Lp = at<void>(base, Lo.Lp);
   Pp.NLp = at<void>(base, Lo.NLp);
   Pp.Rp = at<void>(base, Lo.Rp);
@@ -320,6 +328,7 @@ static void fill_views(const PairLayout &Lo, void *base, uint32_t *keys, MatchPa
   Q.W = M.W;
   Q.pitch = pitch;
   Q.win = M.win;
+  Q.chess = M.chess;
   Q.dmin = M.dmin;
   Q.dmax = M.dmax;
   Q.SL = Pp.SL;
@@ -422,6 +431,7 @@ void st_default_params(st_params *p) {
   p->research = 0;
   p->research_range = 5;
   p->research_eta = 0.01f;
+  p->chessboard = 0;
 }
 
 const char *st_last_error(void) { return g_err.c_str(); }
@@ -494,10 +504,10 @@ void st_destroy(st_handle h) {
 
 // Prepare scratch for one pair and fill the device views.
 static st_status setup_single(st_handle h, const uint8_t *left, const uint8_t *right, int H, int W,
-                              int pitch, int dmin, int dmax, int win, int prec, int variant,
-                              bool debug, MatchPair &M, PrepPair &Pp, PostPair &Q, PairLayout &Lo,
-                              hipStream_t s) {
-  make_geom(M, H, W, win, dmin, dmax, kDC, variant_TY(variant), variant_CG(variant));
+                              int pitch, int dmin, int dmax, int win, int chess, int prec,
+                              int variant, bool debug, MatchPair &M, PrepPair &Pp, PostPair &Q,
+                              PairLayout &Lo, hipStream_t s) {
+  make_geom(M, H, W, win, dmin, dmax, kDC, variant_TY(variant), variant_CG(variant), chess);
   Lo = layout(M, prec, debug);
   st_status rc = grow(h, h->ws, Lo.total, false);
   if (rc) return rc;
@@ -551,7 +561,8 @@ st_status stereo_match(st_handle h, const uint8_t *left, const uint8_t *right, i
   PrepPair Pp;
   PostPair Q;
   PairLayout Lo;
-  rc = setup_single(h, left, right, H, W, pitch, dmin, dmax, win, prec, v, debug, M, Pp, Q, Lo, s);
+  rc = setup_single(h, left, right, H, W, pitch, dmin, dmax, win, params->chessboard, prec, v,
+                    debug, M, Pp, Q, Lo, s);
   if (rc) return rc;
   h->dbg.clear();
   rc = run_front(h, M, Pp, prec, s);
@@ -588,21 +599,23 @@ st_status stereo_debug_get(st_handle h, const char *name, void **dev_ptr) {
 
 // ---------------------------------------------------------------- single stages
 st_status st_window_stats(st_handle h, const uint8_t *img, int H, int W, int pitch, int win,
-                          int32_t *S, int32_t *SS, float *inv, void *stream) {
+                          int chess, int32_t *S, int32_t *SS, float *inv, void *stream) {
   ARG(win >= 3 && win <= 15 && (win & 1), "win must be odd and in [3, 15]");
+  ARG(chess == 0 || chess == 1, "chess must be 0 or 1");
   ARG(H >= 1 && W >= 1 && pitch >= W, "bad image shape");
   ARG(img && S && SS && inv, "NULL pointer");
   ARG(h, "NULL handle");
   hipSetDevice(h->device);
-  HIPCK(launch_window_stats_dense(img, H, W, pitch, win, S, SS, inv, (hipStream_t)stream));
+  HIPCK(launch_window_stats_dense(img, H, W, pitch, win, chess, S, SS, inv, (hipStream_t)stream));
   return ST_OK;
 }
 
 st_status st_match_wta(st_handle h, const uint8_t *left, const uint8_t *right, int H, int W,
-                       int pitch, int dmin, int dmax, int win, int precision, int16_t *oL,
-                       uint8_t *mL, int16_t *oR, uint8_t *mR, void *stream) {
+                       int pitch, int dmin, int dmax, int win, int chess, int precision,
+                       int16_t *oL, uint8_t *mL, int16_t *oR, uint8_t *mR, void *stream) {
   st_status rc = check_shape(H, W, pitch, dmin, dmax, win);
   if (rc) return rc;
+  ARG(chess == 0 || chess == 1, "chess must be 0 or 1");
   ARG(precision >= 0 && precision <= 2, "unknown precision %d", precision);
   ARG(left && right && oL && mL && oR && mR, "NULL pointer");
   ARG(h, "NULL handle");
@@ -613,7 +626,8 @@ st_status st_match_wta(st_handle h, const uint8_t *left, const uint8_t *right, i
   PrepPair Pp;
   PostPair Q;
   PairLayout Lo;
-  rc = setup_single(h, left, right, H, W, pitch, dmin, dmax, win, precision, v, false, M, Pp, Q, Lo, s);
+  rc = setup_single(h, left, right, H, W, pitch, dmin, dmax, win, chess, precision, v, false, M, Pp,
+                    Q, Lo, s);
   if (rc) return rc;
   rc = run_front(h, M, Pp, precision, s);
   if (rc) return rc;
@@ -626,11 +640,12 @@ st_status st_match_wta(st_handle h, const uint8_t *left, const uint8_t *right, i
 }
 
 st_status st_subpixel(st_handle h, const uint8_t *left, const uint8_t *right, int H, int W,
-                      int pitch, int dmin, int dmax, int win, const int16_t *oL,
+                      int pitch, int dmin, int dmax, int win, int chess, const int16_t *oL,
                       const uint8_t *mL, double *zbest, double *zm, double *zp, float *delta,
                       void *stream) {
   st_status rc = check_shape(H, W, pitch, dmin, dmax, win);
   if (rc) return rc;
+  ARG(chess == 0 || chess == 1, "chess must be 0 or 1");
   ARG(left && right && oL && mL && delta, "NULL pointer");
   ARG(h, "NULL handle");
   hipSetDevice(h->device);
@@ -644,6 +659,7 @@ st_status st_subpixel(st_handle h, const uint8_t *left, const uint8_t *right, in
   Q.W = W;
   Q.pitch = pitch;
   Q.win = win;
+  Q.chess = chess;
   Q.dmin = dmin;
   Q.dmax = dmax;
   int32_t *base = (int32_t *)h->ws.p;
@@ -651,8 +667,8 @@ st_status st_subpixel(st_handle h, const uint8_t *left, const uint8_t *right, in
   Q.SSL = base + N;
   Q.SR = base + 2 * N;
   Q.SSR = base + 3 * N;
-  HIPCK(launch_window_stats_dense(left, H, W, pitch, win, base, base + N, nullptr, s));
-  HIPCK(launch_window_stats_dense(right, H, W, pitch, win, base + 2 * N, base + 3 * N, nullptr, s));
+  HIPCK(launch_window_stats_dense(left, H, W, pitch, win, chess, base, base + N, nullptr, s));
+  HIPCK(launch_window_stats_dense(right, H, W, pitch, win, chess, base + 2 * N, base + 3 * N, nullptr, s));
   Q.ob[0] = const_cast<int16_t *>(oL);
   Q.mb[0] = const_cast<uint8_t *>(mL);
   Q.zbest = zbest;
@@ -740,11 +756,12 @@ st_status st_fill(st_handle h, const int16_t *o_in, const uint8_t *m_in, int H, 
 }
 
 st_status st_research(st_handle h, const uint8_t *left, const uint8_t *right, int H, int W,
-                      int pitch, int dmin, int dmax, int win, const int16_t *o_in,
+                      int pitch, int dmin, int dmax, int win, int chess, const int16_t *o_in,
                       const uint8_t *m, const double *d, int range, float eta, int16_t *o_out,
                       void *stream) {
   st_status rc = check_shape(H, W, pitch, dmin, dmax, win);
   if (rc) return rc;
+  ARG(chess == 0 || chess == 1, "chess must be 0 or 1");
   ARG(range >= 0 && range <= 64 && eta >= 0.0f, "bad range or eta");
   ARG(left && right && o_in && m && d && o_out, "NULL pointer");
   ARG((const void *)o_in != (const void *)o_out, "o_out aliases o_in");
@@ -760,6 +777,7 @@ st_status st_research(st_handle h, const uint8_t *left, const uint8_t *right, in
   Q.W = W;
   Q.pitch = pitch;
   Q.win = win;
+  Q.chess = chess;
   Q.dmin = dmin;
   Q.dmax = dmax;
   int32_t *base = (int32_t *)h->ws.p;
@@ -767,8 +785,8 @@ st_status st_research(st_handle h, const uint8_t *left, const uint8_t *right, in
   Q.SSL = base + N;
   Q.SR = base + 2 * N;
   Q.SSR = base + 3 * N;
-  HIPCK(launch_window_stats_dense(left, H, W, pitch, win, base, base + N, nullptr, s));
-  HIPCK(launch_window_stats_dense(right, H, W, pitch, win, base + 2 * N, base + 3 * N, nullptr, s));
+  HIPCK(launch_window_stats_dense(left, H, W, pitch, win, chess, base, base + N, nullptr, s));
+  HIPCK(launch_window_stats_dense(right, H, W, pitch, win, chess, base + 2 * N, base + 3 * N, nullptr, s));
   Q.ob[0] = const_cast<int16_t *>(o_in);
   Q.mb[0] = const_cast<uint8_t *>(m);
   Q.ob[1] = o_out;
@@ -851,7 +869,8 @@ st_status stereo_match_batched(st_handle h, const st_pair *pairs, int n_pairs,
       auto it = h->tune.find("batched");
       if (it != h->tune.end()) v = it->second;
     }
-    make_geom(M[i], q.H, q.W, q.win, q.dmin, q.dmax, DC, variant_TY(v), variant_CG(v));
+    make_geom(M[i], q.H, q.W, q.win, q.dmin, q.dmax, DC, variant_TY(v), variant_CG(v),
+              params->chessboard);
     Lo[i] = layout(M[i], prec, false);
     total = (total + 255) & ~(size_t)255;
     base[i] = total;
@@ -1096,7 +1115,7 @@ static int pick_variant(st_handle h, int H, int W, int win, int dmin, int dmax, 
   long long best_n = -1;
   for (int v = 0; v < kNumVariants; ++v) {
     MatchPair P;
-    make_geom(P, H, W, win, dmin, dmax, kDC, variant_TY(v), variant_CG(v));
+    make_geom(P, H, W, win, dmin, dmax, kDC, variant_TY(v), variant_CG(v), 0);
     const long long n = (long long)P.nspan * P.nband * P.ncg;
     if (n >= 2LL * h->ncu) return v;
     if (n > best_n) {
@@ -1178,7 +1197,8 @@ extern "C" st_status st_autotune(st_handle h, int H, int W, int dmin, int dmax, 
     PrepPair Pp;
     PostPair Q;
     PairLayout Lo;
-    rc = setup_single(h, dimg, dimg + N, H, W, W, dmin, dmax, win, precision, v, false, M, Pp, Q, Lo, s);
+    rc = setup_single(h, dimg, dimg + N, H, W, W, dmin, dmax, win, 0, precision, v, false, M, Pp,
+                      Q, Lo, s);
     if (rc) break;
     launch_prep(Pp, nullptr, 1, H, std::max(M.strideL, M.strideR), W, precision, s);
     PostLaunch L = single_launch(Q, s);

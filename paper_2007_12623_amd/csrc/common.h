@@ -25,6 +25,8 @@ enum Prec { P_I16 = 0, P_F16 = 1, P_BF16 = 2 };
 
 // Geometry and device pointers of one prepared pair, as the matcher sees it.
 // Planes are padded row-major arrays: image column x lives at index x + pad.
+// With the chessboard window the L planes come twice, lplane bytes apart:
+// copy c keeps the pixels with (x + y) & 1 == c and holds 0 elsewhere.
 //   L planes / L stats: stride strideL, pad padL  (padL chosen so that the
 //                       first column of every lane is 16-byte aligned)
 //   R plane  / R stats: stride strideR, pad padR  (multiple of 4)
@@ -45,6 +47,9 @@ struct MatchPair {
   int32_t CG, ncg;      // chunks per workgroup task, chunk groups
   int32_t rp;           // slot stride of the right key tile (4 mod 8)
   int32_t first_task;   // index of this pair's first task in a batched queue
+  int32_t chess;        // 1: chessboard window (cells u + v even around the centre)
+  int32_t nwin;         // cells of the window: win^2, or (win^2 + 1) / 2 for the chessboard
+  uint32_t lplane;      // bytes from the colour-0 copy of Lp / NLp to the colour-1 copy
 };
 
 // Dense per-pair view used by the post-processing kernels.  A batched
@@ -53,6 +58,7 @@ struct MatchPair {
 struct PostPair {
   const uint8_t *left, *right;
   int32_t H, W, pitch, win, dmin, dmax;
+  int32_t chess;                       // 1: chessboard window
   const int32_t *SL, *SSL, *SR, *SSR;  // dense window sums (0 outside)
   uint32_t *keyL, *keyR;               // merged WTA keys (cleared by decode)
   int16_t *oR;
@@ -74,6 +80,7 @@ struct PostPair {
 struct PrepPair {
   const uint8_t *L, *R;
   int32_t H, W, pitch, win;
+  int32_t chess;                         // 1: chessboard window, two L plane copies
   void *Lp, *NLp, *Rp;                   // padded image planes
   int32_t *negSL, *SRp;                  // padded statistics planes
   float *invL, *invR;
@@ -119,7 +126,7 @@ hipError_t launch_match_persistent(const MatchPair *pairs_dev, const int4 *tasks
 int match_persistent_occupancy(int win, int prec, size_t lds);
 size_t match_lds_bytes(const MatchPair &P);  // key tiles of one workgroup
 hipError_t launch_window_stats_dense(const uint8_t *img, int H, int W, int pitch, int win,
-                                     int32_t *S, int32_t *SS, float *inv, hipStream_t s);
+                                     int chess, int32_t *S, int32_t *SS, float *inv, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, int N, uint32_t v, hipStream_t s);
 struct Mat4 {
   double q[16];

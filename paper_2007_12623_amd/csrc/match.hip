@@ -144,10 +144,13 @@ __device__ __forceinline__ void load_dw_shifted(uint32_t (&dst)[N], const GLOBAL
 
 // ---------------------------------------------------------------- one task
 // Rows [y0, y1) of the span starting at column xs, disparities d0 .. d0+DC-1;
-// keys go to the workgroup's tiles.
+// keys go to the workgroup's tiles.  With the chessboard window the pass
+// takes colour `par`: its L planes hold only the pixels with (x + y) & 1 ==
+// par, so the window sums of a pixel of that colour run over exactly its
+// chessboard cells, and the pixels of the other colour produce no keys.
 template <int WIN, int DC, int PREC>
 __device__ __forceinline__ void match_rows(const MatchPair &P, int y0, int y1, int xs, int d0,
-                                           int lane, const KeyTile &kt) {
+                                           int par, int lane, const KeyTile &kt) {
   constexpr int H = WIN / 2;
   constexpr int K = KC;
   constexpr int T = K + DC - 1;                 // R columns touched by a lane
@@ -156,7 +159,7 @@ __device__ __forceinline__ void match_rows(const MatchPair &P, int y0, int y1, i
   constexpr int RB = IM::RB;
   constexpr int NLD = K / 2;                    // dwords of one L row segment (int16/fp16)
   constexpr int NRD = (T * RB + 3) / 4;         // dwords of one R row segment
-  const int n = WIN * WIN;
+  const int n = P.nwin;
 
   const int x0 = xs + lane * K;
   const int colL = x0 + P.padL;                 // multiple of 8
@@ -164,8 +167,8 @@ __device__ __forceinline__ void match_rows(const MatchPair &P, int y0, int y1, i
   const int rsh = (RB * colR) & 3;              // byte misalignment (wave-uniform)
   const bool halo = (lane == 0) || (lane == WV - 1);
   // planes are under 4 GiB: byte offsets of the lane's segments fit 32 bits
-  const GLOBAL char *Lg = (const GLOBAL char *)P.Lp;
-  const GLOBAL char *NLg = (const GLOBAL char *)P.NLp;
+  const GLOBAL char *Lg = (const GLOBAL char *)P.Lp + par * P.lplane;
+  const GLOBAL char *NLg = (const GLOBAL char *)P.NLp + par * P.lplane;
   const GLOBAL char *Rg = (const GLOBAL char *)P.Rp;
   const uint32_t Lo = 2u * (uint32_t)colL, Ro = (uint32_t)(RB * colR - rsh);
   const uint32_t sL = 2u * (uint32_t)P.strideL, sR = (uint32_t)(RB * P.strideR);
@@ -236,10 +239,14 @@ __device__ __forceinline__ void match_rows(const MatchPair &P, int y0, int y1, i
       const uint32_t o = 4u * (uint32_t)(y * P.strideL + colL);
       const GLOBAL int32_t *ns = (const GLOBAL int32_t *)((const GLOBAL char *)P.negSL + o);
       const GLOBAL float *iv = (const GLOBAL float *)((const GLOBAL char *)P.invL + o);
+      // chessboard: column x0 + c has colour par when c & 1 == cpar (x0 has
+      // the parity of xs, so cpar is wave-uniform)
+      const int cpar = (xs + y + par) & 1;
 #pragma unroll
       for (int c = 0; c < K; ++c) {
         nsl[c] = ns[c];
-        il[c] = halo ? __builtin_nanf("") : iv[c];
+        const bool off = halo || (P.chess && (c & 1) != cpar);
+        il[c] = off ? __builtin_nanf("") : iv[c];
       }
     }
     int sr[T];
@@ -354,7 +361,9 @@ __device__ __forceinline__ void match_rows(const MatchPair &P, int y0, int y1, i
 // sub-bands so that every wave has work.
 template <int WIN, int DC, int PREC>
 __device__ __forceinline__ void wg_task(const MatchPair &P, int g, int cg, LDS uint32_t *lds) {
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & (WV - 1);
+  // the wave index is uniform: in a scalar register every quantity derived
+  // from it (chunk, colour, rows of the item) stays scalar as well
+  const int tid = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & (WV - 1);
   constexpr int NT = NWAVE * WV;
   const int h = WIN / 2;
   const int band = g / P.nspan, span = g - band * P.nspan;
@@ -377,13 +386,17 @@ __device__ __forceinline__ void wg_task(const MatchPair &P, int g, int cg, LDS u
   for (int i = tid; i < rows * 8 * kt.rp; i += NT) kt.rt[i] = 0u;
   __syncthreads();
 
-  const int SB = nc >= NWAVE ? 1 : NWAVE / nc;
+  // units: (chunk, colour) pairs, one colour unless the window is a chessboard
+  const int units = nc * (P.chess ? 2 : 1);
+  const int SB = units >= NWAVE ? 1 : NWAVE / units;
   const int TYs = ceil_div(rows, SB);
-  const int items = nc * SB;
+  const int items = units * SB;
   for (int it = wave; it < items; it += NWAVE) {
-    const int c = cf + it % nc, sb = it / nc;
+    const int u = it % units, sb = it / units;
+    const int c = cf + u % nc, par = u / nc;
     const int ya = y0 + sb * TYs, yb = min(ya + TYs, y1);
-    if (ya < yb) match_rows<WIN, DC, PREC>(P, ya, yb, xs, P.dmin + min(c * DC, D - DC), lane, kt);
+    if (ya < yb)
+      match_rows<WIN, DC, PREC>(P, ya, yb, xs, P.dmin + min(c * DC, D - DC), par, lane, kt);
   }
   __syncthreads();
 
@@ -457,13 +470,9 @@ __global__ void prep_planes_kernel(PrepPair one, const PrepPair *many) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (y >= P.H) return;
   const int W = P.W;
-  const int n = P.win * P.win;
+  const int n = P.chess ? (P.win * P.win + 1) / 2 : P.win * P.win;
   const float qnan = __builtin_nanf("");
-  if (c < P.strideL) {
-    const int x = c - P.padL;
-    const bool in = x >= 0 && x < W;
-    const int v = in ? (int)P.L[(size_t)y * P.pitch + x] - 128 : 0;
-    const size_t k = (size_t)y * P.strideL + c;
+  auto putL = [&](size_t k, int v) {
     if constexpr (PREC == P_I16) {
       ((int16_t *)P.Lp)[k] = (int16_t)(n * v);
       ((int16_t *)P.NLp)[k] = (int16_t)(-n * v);
@@ -473,6 +482,20 @@ __global__ void prep_planes_kernel(PrepPair one, const PrepPair *many) {
     } else {
       ((uint16_t *)P.Lp)[k] = (uint16_t)(__builtin_bit_cast(uint32_t, (float)v) >> 16);
       ((uint16_t *)P.NLp)[k] = (uint16_t)(__builtin_bit_cast(uint32_t, (float)(-v)) >> 16);
+    }
+  };
+  if (c < P.strideL) {
+    const int x = c - P.padL;
+    const bool in = x >= 0 && x < W;
+    const int v = in ? (int)P.L[(size_t)y * P.pitch + x] - 128 : 0;
+    const size_t k = (size_t)y * P.strideL + c;
+    if (!P.chess) {
+      putL(k, v);
+    } else {
+      // colour copies: (x + y) even in the first, odd in the second
+      const bool even = ((x + y) & 1) == 0;
+      putL(k, even ? v : 0);
+      putL(k + (size_t)P.strideL * P.H, even ? 0 : v);
     }
     if (!in) { P.negSL[k] = 0; P.invL[k] = qnan; }
   }
@@ -499,34 +522,42 @@ __global__ void prep_planes_kernel(PrepPair one, const PrepPair *many) {
 // window sums of its column down a segment of WS_SY rows and the horizontal
 // sums are differences of a block prefix sum (wave scans plus wave totals in
 // LDS).  Output columns of a block are WS_T - 2 WS_HMAX wide for every window.
+// CH (chessboard window): a column keeps separate sums of its cells with
+// x + y even and odd; a pixel takes the prefix sums of its own colour, since
+// the cells u + v even around (x, y) are exactly those of the colour of
+// (x, y).
 constexpr int WS_T = 256, WS_SY = 16, WS_HMAX = 7, WS_NOUT = WS_T - 2 * WS_HMAX;
 
-__device__ __forceinline__ void block_prefix_i2(int &a, int &b, int (*wt)[4]) {
+template <int N>
+__device__ __forceinline__ void block_prefix(int (&a)[N], int (*wt)[4]) {
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) {
-    const int ua = __shfl_up(a, o, 64), ub = __shfl_up(b, o, 64);
+    int u[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) u[i] = __shfl_up(a[i], o, 64);
     if (lane >= o) {
-      a += ua;
-      b += ub;
+#pragma unroll
+      for (int i = 0; i < N; ++i) a[i] += u[i];
     }
   }
   if (lane == 63) {
-    wt[0][wave] = a;
-    wt[1][wave] = b;
+#pragma unroll
+    for (int i = 0; i < N; ++i) wt[i][wave] = a[i];
   }
   __syncthreads();
   for (int w = 0; w < wave; ++w) {
-    a += wt[0][w];
-    b += wt[1][w];
+#pragma unroll
+    for (int i = 0; i < N; ++i) a[i] += wt[i][w];
   }
 }
 
-template <bool B>
+template <bool B, bool CH>
 __global__ __launch_bounds__(WS_T) void window_stats_kernel(PrepPair one, const PrepPair *many,
                                                             int side) {
   const PrepPair &P = B ? many[blockIdx.z] : one;
-  __shared__ int pa[2][WS_T], pb[2][WS_T], wt[2][2][4];
+  constexpr int NV = CH ? 4 : 2;  // (S, SS) of each colour
+  __shared__ int pf[2][NV][WS_T], wt[2][NV][4];
   const int H = P.H, W = P.W, win = P.win, h = win / 2;
   const int xo = blockIdx.x * WS_NOUT, y0 = blockIdx.y * WS_SY;
   if (xo >= W || y0 >= H) return;  // uniform per block
@@ -534,36 +565,49 @@ __global__ __launch_bounds__(WS_T) void window_stats_kernel(PrepPair one, const 
   const int t = threadIdx.x, c = xo - h + t;
   const bool cin = c >= 0 && c < W;
   auto px = [&](int r) -> int { return (cin && r >= 0 && r < H) ? (int)img[(size_t)r * P.pitch + c] : 0; };
-  int s = 0, ss = 0;
-  for (int r = y0 - h; r < y0 + h; ++r) {
-    const int v = px(r);
-    s += v;
-    ss += v * v;
-  }
+  int acc[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) acc[i] = 0;
+  // add (sgn = 1) or remove (sgn = -1) row r of the column
+  auto step = [&](int r, int sgn) {
+    const int v = sgn * px(r), vv = v * (sgn * v);
+    if constexpr (CH) {
+      const bool odd = ((c + r) & 1) != 0;
+      acc[0] += odd ? 0 : v;
+      acc[1] += odd ? 0 : vv;
+      acc[2] += odd ? v : 0;
+      acc[3] += odd ? vv : 0;
+    } else {
+      acc[0] += v;
+      acc[1] += vv;
+    }
+  };
+  for (int r = y0 - h; r < y0 + h; ++r) step(r, 1);
   const bool out_col = c >= xo && c < xo + WS_NOUT && c < W;  // then h <= t < WS_T - h
   const int y1 = min(y0 + WS_SY, H);
+  const int n = CH ? (win * win + 1) / 2 : win * win;
   for (int y = y0; y < y1; ++y) {
     const int b = y & 1;
-    const int v = px(y + h);
-    s += v;
-    ss += v * v;
-    int ps = s, pss = ss;
-    block_prefix_i2(ps, pss, wt[b]);
-    pa[b][t] = ps;
-    pb[b][t] = pss;
+    step(y + h, 1);
+    int pv[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) pv[i] = acc[i];
+    block_prefix<NV>(pv, wt[b]);
+#pragma unroll
+    for (int i = 0; i < NV; ++i) pf[b][i][t] = pv[i];
     __syncthreads();
     if (out_col) {
       const int x = c;
-      int S = pa[b][t + h] - (t - h - 1 >= 0 ? pa[b][t - h - 1] : 0);
-      int SS = pb[b][t + h] - (t - h - 1 >= 0 ? pb[b][t - h - 1] : 0);
+      const int q = CH ? 2 * ((x + y) & 1) : 0;
+      int S = pf[b][q][t + h] - (t - h - 1 >= 0 ? pf[b][q][t - h - 1] : 0);
+      int SS = pf[b][q + 1][t + h] - (t - h - 1 >= 0 ? pf[b][q + 1][t - h - 1] : 0);
       const bool inside = x >= h && x <= W - 1 - h && y >= h && y <= H - 1 - h;
       float iv = __builtin_nanf("");
       if (!inside) {
         S = 0;
         SS = 0;
       } else {
-        const long long n = (long long)win * win;
-        const long long varN = n * SS - (long long)S * S;
+        const long long varN = (long long)n * SS - (long long)S * S;
         if (varN > 0) iv = (float)(1.0 / sqrt((double)varN));
       }
       const size_t k = (size_t)y * W + x;
@@ -580,14 +624,12 @@ __global__ __launch_bounds__(WS_T) void window_stats_kernel(PrepPair one, const 
         if (P.invLd) P.invLd[k] = iv;
         if (side == 0) {
           const size_t kp = (size_t)y * P.strideL + x + P.padL;
-          P.negSL[kp] = 128 * win * win - S;
+          P.negSL[kp] = 128 * n - S;
           P.invL[kp] = iv;
         }
       }
     }
-    const int vl = px(y - h);
-    s -= vl;
-    ss -= vl * vl;
+    step(y - h, -1);
   }
 }
 
@@ -711,27 +753,37 @@ hipError_t launch_prep(const PrepPair &one, const PrepPair *many, int npairs, in
   } while (0)
   if (prec == P_I16) PP(P_I16); else if (prec == P_F16) PP(P_F16); else PP(P_BF16);
 #undef PP
+  // the window shape is shared by every pair of a batch (one parameter set)
   const dim3 gs(ceil_div(maxW, WS_NOUT), ceil_div(maxH, WS_SY), npairs);
+#define WS(b, ch) hipLaunchKernelGGL((window_stats_kernel<b, ch>), gs, dim3(WS_T), 0, s, one, many, side)
   for (int side = 0; side < 2; ++side) {
-    if (many) hipLaunchKernelGGL(window_stats_kernel<true>, gs, dim3(WS_T), 0, s, one, many, side);
-    else hipLaunchKernelGGL(window_stats_kernel<false>, gs, dim3(WS_T), 0, s, one, many, side);
+    if (many) {
+      if (one.chess) WS(true, true); else WS(true, false);
+    } else {
+      if (one.chess) WS(false, true); else WS(false, false);
+    }
   }
+#undef WS
   return hipGetLastError();
 }
 
 hipError_t launch_window_stats_dense(const uint8_t *img, int H, int W, int pitch, int win,
-                                     int32_t *S, int32_t *SS, float *inv, hipStream_t s) {
+                                     int chess, int32_t *S, int32_t *SS, float *inv, hipStream_t s) {
   PrepPair P = {};
   P.L = img;
   P.H = H;
   P.W = W;
   P.pitch = pitch;
   P.win = win;
+  P.chess = chess;
   P.SL = S;
   P.SSL = SS;
   P.invLd = inv;
   const dim3 gs(ceil_div(W, WS_NOUT), ceil_div(H, WS_SY), 1);
-  hipLaunchKernelGGL(window_stats_kernel<false>, gs, dim3(WS_T), 0, s, P, (const PrepPair *)nullptr, 2);
+  if (chess)
+    hipLaunchKernelGGL((window_stats_kernel<false, true>), gs, dim3(WS_T), 0, s, P, (const PrepPair *)nullptr, 2);
+  else
+    hipLaunchKernelGGL((window_stats_kernel<false, false>), gs, dim3(WS_T), 0, s, P, (const PrepPair *)nullptr, 2);
   return hipGetLastError();
 }
 

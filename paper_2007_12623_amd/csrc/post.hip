@@ -103,16 +103,25 @@ __device__ __forceinline__ void stage_row(uint8_t *dst, const GLOBAL uint8_t *ba
   ((uint32_t *)dst)[tid] = v;
 }
 
+// Byte mask of window row v for the chessboard window (cells u + v even,
+// counted from the window's corner, which has the parity of the centre):
+// bytes 0 and 2 of every dword in even rows, 1 and 3 in odd rows.
+__device__ __forceinline__ uint32_t chess_mask(int chess, int v) {
+  return chess ? ((v & 1) ? 0xFF00FF00u : 0x00FF00FFu) : 0xFFFFFFFFu;
+}
+
 // Sums over one staged window of L(u) R(u + e) for e = 0, 1, 2, i.e. at the
 // disparities o + 1, o, o - 1.  ND dwords hold the win bytes of an L row
-// (the bytes past win are masked to 0); the R row starts at byte rs.
+// (the bytes past win, and the other chessboard colour, are masked to 0);
+// the R row starts at byte rs.
 template <int ND>
 __device__ __forceinline__ void sp_sums(const uint8_t (*Ls)[SP_LROW], const uint8_t (*Rs)[SP_RROW],
-                                        const int *misL, const int *misR, int win, int tx, int rs0,
-                                        int &sp, int &s0, int &sm) {
+                                        const int *misL, const int *misR, int win, int chess,
+                                        int tx, int rs0, int &sp, int &s0, int &sm) {
   const uint32_t lmask = (win & 3) ? (1u << (8 * (win & 3))) - 1u : 0xFFFFFFFFu;
   uint32_t a0 = 0, a1 = 0, a2 = 0;
   for (int v = 0; v < win; ++v) {
+    const uint32_t cm = chess_mask(chess, v);
     const int lb = tx + misL[v], rs = rs0 + misR[v];
     const int la = lb & ~3, lsh = lb & 3, ra = rs & ~3, rsh = rs & 3;
     const bool up1 = rsh + 1 >= 4, up2 = rsh + 2 >= 4;
@@ -126,7 +135,7 @@ __device__ __forceinline__ void sp_sums(const uint8_t (*Ls)[SP_LROW], const uint
     for (int i = 0; i < ND + 2; ++i) rt[i] = rw[i];
     uint32_t l[ND];
 #pragma unroll
-    for (int i = 0; i < ND; ++i) l[i] = __builtin_amdgcn_alignbyte(lt[i + 1], lt[i], lsh);
+    for (int i = 0; i < ND; ++i) l[i] = __builtin_amdgcn_alignbyte(lt[i + 1], lt[i], lsh) & cm;
     l[ND - 1] &= lmask;
     // R windows shifted by e bytes: alignbyte within a dword pair, and the
     // next pair when rsh + e reaches 4
@@ -209,12 +218,12 @@ __global__ __launch_bounds__(SP_TX) void subpixel_kernel(PostPair one, const Pos
   const int rs = tx + omax - o;
   int sm = 0, s0 = 0, sp = 0;  // sums at d = o - 1, o, o + 1
   switch ((win + 3) >> 2) {
-    case 1: sp_sums<1>(Ls, Rs, misL, misR, win, tx, rs, sp, s0, sm); break;
-    case 2: sp_sums<2>(Ls, Rs, misL, misR, win, tx, rs, sp, s0, sm); break;
-    case 3: sp_sums<3>(Ls, Rs, misL, misR, win, tx, rs, sp, s0, sm); break;
-    default: sp_sums<4>(Ls, Rs, misL, misR, win, tx, rs, sp, s0, sm); break;
+    case 1: sp_sums<1>(Ls, Rs, misL, misR, win, P.chess, tx, rs, sp, s0, sm); break;
+    case 2: sp_sums<2>(Ls, Rs, misL, misR, win, P.chess, tx, rs, sp, s0, sm); break;
+    case 3: sp_sums<3>(Ls, Rs, misL, misR, win, P.chess, tx, rs, sp, s0, sm); break;
+    default: sp_sums<4>(Ls, Rs, misL, misR, win, P.chess, tx, rs, sp, s0, sm); break;
   }
-  const long long n = (long long)win * win;
+  const long long n = P.chess ? ((long long)win * win + 1) / 2 : (long long)win * win;
   const long long sl = P.SL[k];
   const long long varL = n * (long long)P.SSL[k] - sl * sl;
   const int slr[3] = {sm, s0, sp};
@@ -864,10 +873,12 @@ __global__ __launch_bounds__(256) void box_h_lds_kernel(PostPair one, const Post
 // candidate's window sum is exact (v_dot4_u32_u8), z and the cost in FP64.
 template <int ND>
 __device__ __forceinline__ int sp_sum1(const uint8_t (*Ls)[SP_LROW], const uint8_t (*Rs)[SP_RROW],
-                                       const int *misL, const int *misR, int win, int tx, int rs0) {
+                                       const int *misL, const int *misR, int win, int chess, int tx,
+                                       int rs0) {
   const uint32_t lmask = (win & 3) ? (1u << (8 * (win & 3))) - 1u : 0xFFFFFFFFu;
   uint32_t acc = 0;
   for (int v = 0; v < win; ++v) {
+    const uint32_t cm = chess_mask(chess, v);
     const int lb = tx + misL[v], rs = rs0 + misR[v];
     const uint32_t *lw = (const uint32_t *)&Ls[v][lb & ~3];
     const uint32_t *rw = (const uint32_t *)&Rs[v][rs & ~3];
@@ -879,7 +890,7 @@ __device__ __forceinline__ int sp_sum1(const uint8_t (*Ls)[SP_LROW], const uint8
     }
 #pragma unroll
     for (int i = 0; i < ND; ++i) {
-      uint32_t l = __builtin_amdgcn_alignbyte(lt[i + 1], lt[i], lb & 3);
+      uint32_t l = __builtin_amdgcn_alignbyte(lt[i + 1], lt[i], lb & 3) & cm;
       if (i == ND - 1) l &= lmask;
       acc = __builtin_amdgcn_udot4(l, __builtin_amdgcn_alignbyte(rt[i + 1], rt[i], rs & 3), acc, false);
     }
@@ -944,7 +955,7 @@ __global__ __launch_bounds__(SP_TX) void research_kernel(PostPair one, const Pos
   if (x >= W) return;
   int onew = P.ob[osrc][k];
   if (lo <= hi) {
-    const long long n = (long long)win * win;
+    const long long n = P.chess ? ((long long)win * win + 1) / 2 : (long long)win * win;
     const long long sl = P.SL[k];
     const long long varL = n * (long long)P.SSL[k] - sl * sl;
     if (varL > 0) {
@@ -958,10 +969,10 @@ __global__ __launch_bounds__(SP_TX) void research_kernel(PostPair one, const Pos
         const int rs0 = tx + cmax - c;  // window column 0 of candidate c in Rs
         int slr;
         switch (nd) {
-          case 1: slr = sp_sum1<1>(Ls, Rs, misL, misR, win, tx, rs0); break;
-          case 2: slr = sp_sum1<2>(Ls, Rs, misL, misR, win, tx, rs0); break;
-          case 3: slr = sp_sum1<3>(Ls, Rs, misL, misR, win, tx, rs0); break;
-          default: slr = sp_sum1<4>(Ls, Rs, misL, misR, win, tx, rs0); break;
+          case 1: slr = sp_sum1<1>(Ls, Rs, misL, misR, win, P.chess, tx, rs0); break;
+          case 2: slr = sp_sum1<2>(Ls, Rs, misL, misR, win, P.chess, tx, rs0); break;
+          case 3: slr = sp_sum1<3>(Ls, Rs, misL, misR, win, P.chess, tx, rs0); break;
+          default: slr = sp_sum1<4>(Ls, Rs, misL, misR, win, P.chess, tx, rs0); break;
         }
         const double z = (double)(n * (long long)slr - sl * sr) / sqrt((double)varL * (double)varR);
         const double e = (double)c - d;

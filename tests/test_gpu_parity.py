@@ -203,8 +203,9 @@ def _end_to_end(B, orc, L, R, dmin, dmax, win, params_gpu, params_orc):
     finally:
         h.close()
     po = params_orc
+    chess = bool(po.chess)
     # matching: validity exact, winners exact away from near-ties
-    ref = orc.match(L, R, dmin, dmax, win)
+    ref = orc.match(L, R, dmin, dmax, win, chess=chess)
     assert np.array_equal(m_wta, ref["mL"]) and np.array_equal(m_r, ref["mR"])
     sel = (ref["mL"] == 1) & ~tie_mask(ref["gap"])
     assert np.array_equal(o_wta[sel], ref["oL"][sel])
