@@ -195,7 +195,9 @@ st_status st_match_wta(st_handle h, const uint8_t *left, const uint8_t *right, i
 
 /* Exact ZNCC at oL-1, oL, oL+1 (int32 sums, FP64 normalisation) and the
  * parabola offset delta; zm/zp NaN where the neighbour is not a valid
- * candidate.  Any of zbest/zm/zp may be NULL. */
+ * candidate.  Any of zbest/zm/zp may be NULL.  A pixel with mL != 0 must
+ * have oL in [dmin, dmax]; one outside is treated as unmatched (NaN z,
+ * delta 0). */
 st_status st_subpixel(st_handle h, const uint8_t *left, const uint8_t *right, int H, int W,
                       int pitch, int dmin, int dmax, int win, int chess, const int16_t *oL,
                       const uint8_t *mL, double *zbest, double *zm, double *zp, float *delta,

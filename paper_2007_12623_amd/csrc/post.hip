@@ -68,12 +68,16 @@ __global__ void fill_u32_kernel(uint32_t *p, int N, uint32_t v) {
 // n*S_LR - S_L*S_R, FP64 normalisation), then the parabola offset
 // delta = (zm - zp) / (2 (zm - 2 z0 + zp)) clamped to [-1/2, 1/2]; 0 at the
 // ends of the range, when a neighbour is missing or the curvature is >= 0.
-// A block covers 128 pixels of one row: it stages the window rows of the left
-// image and the right columns its disparities reach in LDS once; every thread
-// then reads its window rows as packed bytes and forms the three sums with
-// v_dot4_u32_u8 (4 products per instruction, exact in 32 bits).
+// A block of 256 threads covers 128 columns x 4 rows: it stages the window
+// rows of the left image and the right columns its disparities reach in LDS
+// once, and each thread takes two pixels of its column.  The three window
+// sums sum_u L(u) R(u + e), e = 0, 1, 2, are formed as sum_w L(w - e) R(w):
+// the R bytes are aligned once per window row and the L row is shifted by e
+// bytes with a constant v_alignbyte, so no per-lane selects are needed;
+// v_dot4_u32_u8 adds 4 products per instruction, exact in 32 bits.
 constexpr int SP_TX = 128, SP_MAXWIN = 15;
 constexpr int SP_LROW = SP_TX + 24, SP_RROW = SP_TX + 256 + 32;
+constexpr int SPB_T = 256, SPB_TY = 4, SPB_ROWS = SP_MAXWIN + SPB_TY - 1;
 
 // Copy the bytes [off, off + len) of the image buffer base[0, span) (byte
 // offsets relative to base; off may be negative) to an LDS row as whole
@@ -110,46 +114,88 @@ __device__ __forceinline__ uint32_t chess_mask(int chess, int v) {
   return chess ? ((v & 1) ? 0xFF00FF00u : 0x00FF00FFu) : 0xFFFFFFFFu;
 }
 
-// Sums over one staged window of L(u) R(u + e) for e = 0, 1, 2, i.e. at the
-// disparities o + 1, o, o - 1.  ND dwords hold the win bytes of an L row
-// (the bytes past win, and the other chessboard colour, are masked to 0);
-// the R row starts at byte rs.
-template <int ND>
+// Dword i counted from the 4-aligned byte offset a0 of the buffer
+// base[0, span); bytes outside the buffer read as 0.
+__device__ __forceinline__ uint32_t fetch_dw(const GLOBAL uint8_t *base, long long a0, int i,
+                                             long long span) {
+  const long long b = a0 + 4 * (long long)i;
+  if (b >= 0 && b + 4 <= span) return *(const GLOBAL uint32_t *)(base + b);
+  uint32_t v = 0;
+  for (int j = 0; j < 4; ++j)
+    if (b + j >= 0 && b + j < span) v |= (uint32_t)base[b + j] << (8 * j);
+  return v;
+}
+
+// Stage image rows yr0 .. yr0 + nrows - 1 (rows outside the image are
+// skipped): LW bytes of L from column lx0 and RW bytes of R from column rx0
+// go to Ls[r] / Rs[r] as whole dwords from the dword-aligned address at or
+// below the first byte; mL[r] / mR[r] receive the offset of that byte in the
+// LDS row.  All threads of the block share the dwords of a row.
+__device__ __forceinline__ void stage_rows(uint8_t (*Ls)[SP_LROW], uint8_t (*Rs)[SP_RROW], int *mL,
+                                           int *mR, const GLOBAL uint8_t *Lg,
+                                           const GLOBAL uint8_t *Rg, int pitch, long long span,
+                                           int H, int yr0, int nrows, int lx0, int LW, int rx0,
+                                           int RW, int tid, int nthreads) {
+  for (int r = 0; r < nrows; ++r) {
+    const int yy = yr0 + r;
+    if (yy < 0 || yy >= H) continue;  // uniform
+    const long long row = (long long)yy * pitch;
+    const int misl = (int)(((uintptr_t)Lg + (uintptr_t)(row + lx0)) & 3);
+    const int misr = (int)(((uintptr_t)Rg + (uintptr_t)(row + rx0)) & 3);
+    const int nl = (misl + LW + 3) >> 2, nr = (misr + RW + 3) >> 2;
+    const long long al = row + lx0 - misl, ar = row + rx0 - misr;
+    for (int i = tid; i < nl + nr; i += nthreads) {
+      if (i < nl) ((uint32_t *)Ls[r])[i] = fetch_dw(Lg, al, i, span);
+      else ((uint32_t *)Rs[r])[i - nl] = fetch_dw(Rg, ar, i - nl, span);
+    }
+    if (tid == 0) {
+      mL[r] = misl;
+      mR[r] = misr;
+    }
+  }
+}
+
+// Window sums over stage rows r0 .. r0 + WIN - 1 of L(u) R(rs0 + u + e) for
+// e = 0, 1, 2 (the disparities o + 1, o, o - 1).  NL dwords hold the WIN
+// bytes of an L row (bytes past WIN, and the other chessboard colour, masked
+// to 0); NR dwords cover the WIN + 2 bytes of R that the shifted rows meet.
+template <int WIN>
 __device__ __forceinline__ void sp_sums(const uint8_t (*Ls)[SP_LROW], const uint8_t (*Rs)[SP_RROW],
-                                        const int *misL, const int *misR, int win, int chess,
-                                        int tx, int rs0, int &sp, int &s0, int &sm) {
-  const uint32_t lmask = (win & 3) ? (1u << (8 * (win & 3))) - 1u : 0xFFFFFFFFu;
+                                        const int *mL, const int *mR, int chess, int r0, int tx,
+                                        int rs0, int &sp, int &s0, int &sm) {
+  constexpr int NL = (WIN + 3) / 4, NR = (WIN + 5) / 4;
+  constexpr uint32_t lmask = (WIN & 3) ? (1u << (8 * (WIN & 3))) - 1u : 0xFFFFFFFFu;
   uint32_t a0 = 0, a1 = 0, a2 = 0;
-  for (int v = 0; v < win; ++v) {
+#pragma unroll 1
+  for (int v = 0; v < WIN; ++v) {
+    const int r = r0 + v;
+    const int lb = tx + mL[r], rb = rs0 + mR[r];
+    const uint32_t *lw = (const uint32_t *)&Ls[r][lb & ~3];
+    const uint32_t *rw = (const uint32_t *)&Rs[r][rb & ~3];
+    uint32_t lt[NL + 1], rt[NR + 1];
+#pragma unroll
+    for (int i = 0; i <= NL; ++i) lt[i] = lw[i];
+#pragma unroll
+    for (int i = 0; i <= NR; ++i) rt[i] = rw[i];
     const uint32_t cm = chess_mask(chess, v);
-    const int lb = tx + misL[v], rs = rs0 + misR[v];
-    const int la = lb & ~3, lsh = lb & 3, ra = rs & ~3, rsh = rs & 3;
-    const bool up1 = rsh + 1 >= 4, up2 = rsh + 2 >= 4;
-    const int sh1 = (rsh + 1) & 3, sh2 = (rsh + 2) & 3;
-    const uint32_t *lw = (const uint32_t *)&Ls[v][la];
-    const uint32_t *rw = (const uint32_t *)&Rs[v][ra];
-    uint32_t lt[ND + 1], rt[ND + 2];
+    // l[0] = 0 (before the window), l[1 + i] = window dword i (0 past NL)
+    uint32_t l[NR + 1];
+    l[0] = 0;
 #pragma unroll
-    for (int i = 0; i <= ND; ++i) lt[i] = lw[i];
-#pragma unroll
-    for (int i = 0; i < ND + 2; ++i) rt[i] = rw[i];
-    uint32_t l[ND];
-#pragma unroll
-    for (int i = 0; i < ND; ++i) l[i] = __builtin_amdgcn_alignbyte(lt[i + 1], lt[i], lsh) & cm;
-    l[ND - 1] &= lmask;
-    // R windows shifted by e bytes: alignbyte within a dword pair, and the
-    // next pair when rsh + e reaches 4
-    uint32_t A1[ND + 1], A2[ND + 1];
-#pragma unroll
-    for (int i = 0; i <= ND; ++i) {
-      A1[i] = __builtin_amdgcn_alignbyte(rt[i + 1], rt[i], sh1);
-      A2[i] = __builtin_amdgcn_alignbyte(rt[i + 1], rt[i], sh2);
+    for (int i = 0; i < NR; ++i) {
+      uint32_t t = 0;
+      if (i < NL) {
+        t = __builtin_amdgcn_alignbyte(lt[i + 1], lt[i], lb & 3) & cm;
+        if (i == NL - 1) t &= lmask;
+      }
+      l[i + 1] = t;
     }
 #pragma unroll
-    for (int i = 0; i < ND; ++i) {
-      a0 = __builtin_amdgcn_udot4(l[i], __builtin_amdgcn_alignbyte(rt[i + 1], rt[i], rsh), a0, false);
-      a1 = __builtin_amdgcn_udot4(l[i], up1 ? A1[i + 1] : A1[i], a1, false);
-      a2 = __builtin_amdgcn_udot4(l[i], up2 ? A2[i + 1] : A2[i], a2, false);
+    for (int i = 0; i < NR; ++i) {
+      const uint32_t rr = __builtin_amdgcn_alignbyte(rt[i + 1], rt[i], rb & 3);
+      if (i < NL) a0 = __builtin_amdgcn_udot4(l[i + 1], rr, a0, false);
+      a1 = __builtin_amdgcn_udot4(__builtin_amdgcn_alignbyte(l[i + 1], l[i], 3), rr, a1, false);
+      a2 = __builtin_amdgcn_udot4(__builtin_amdgcn_alignbyte(l[i + 1], l[i], 2), rr, a2, false);
     }
   }
   sp = (int)a0;
@@ -157,101 +203,126 @@ __device__ __forceinline__ void sp_sums(const uint8_t (*Ls)[SP_LROW], const uint
   sm = (int)a2;
 }
 
+__device__ __forceinline__ int wave_min(int v) {
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) v = min(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
 template <bool B>
-__global__ __launch_bounds__(SP_TX) void subpixel_kernel(PostPair one, const PostPair *__restrict__ many) {
+__global__ __launch_bounds__(SPB_T) void subpixel_kernel(PostPair one, const PostPair *__restrict__ many) {
   PAIR;
-  __shared__ __align__(16) uint8_t Ls[SP_MAXWIN][SP_LROW];
-  __shared__ __align__(16) uint8_t Rs[SP_MAXWIN][SP_RROW];
-  __shared__ int s_omin, s_omax, misL[SP_MAXWIN], misR[SP_MAXWIN];
-  const int tx = threadIdx.x;
-  const int x0 = blockIdx.x * SP_TX, y = blockIdx.y;
-  if (x0 >= P.W || y >= P.H) return;  // uniform per block
+  __shared__ __align__(16) uint8_t Ls[SPB_ROWS][SP_LROW];
+  __shared__ __align__(16) uint8_t Rs[SPB_ROWS][SP_RROW];
+  __shared__ int s_omin, s_omax, mL[SPB_ROWS], mR[SPB_ROWS];
+  const int tid = threadIdx.x, tx = tid & (SP_TX - 1), ty = tid / SP_TX;
+  const int x0 = blockIdx.x * SP_TX, y0 = blockIdx.y * SPB_TY;
+  if (x0 >= P.W || y0 >= P.H) return;  // uniform per block
   const int W = P.W, H = P.H, win = P.win, h = win / 2;
   const int x = x0 + tx;
-  const bool in = x < W;
-  const size_t k = (size_t)y * W + x;
-  const bool valid = in && P.mb[0][k];
-  const int o = valid ? (int)P.ob[0][k] : 0;
-  if (tx == 0) {
+  constexpr int NPT = SPB_TY * SP_TX / SPB_T;  // pixels per thread: rows y0 + ty + 2 j
+  int o[NPT];
+  bool valid[NPT];
+  int lo = 1 << 30, hi = -(1 << 30);
+#pragma unroll
+  for (int j = 0; j < NPT; ++j) {
+    const int y = y0 + ty + 2 * j;
+    const bool in = x < W && y < H;
+    const size_t k = (size_t)y * W + x;
+    o[j] = in ? (int)P.ob[0][k] : 0;
+    // a disparity outside [dmin, dmax] counts as unmatched: the staged R
+    // columns cover the range only
+    valid[j] = in && P.mb[0][k] && o[j] >= P.dmin && o[j] <= P.dmax;
+    if (!valid[j]) o[j] = 0;
+    if (valid[j]) {
+      lo = min(lo, o[j]);
+      hi = max(hi, o[j]);
+    }
+  }
+  if (tid == 0) {
     s_omin = 1 << 30;
     s_omax = -(1 << 30);
   }
   __syncthreads();
-  if (valid) {
-    atomicMin(&s_omin, o);
-    atomicMax(&s_omax, o);
+  lo = wave_min(lo);
+  hi = wave_max(hi);
+  if ((tid & (WV - 1)) == 0 && lo <= hi) {
+    atomicMin(&s_omin, lo);
+    atomicMax(&s_omax, hi);
   }
   __syncthreads();
   const int omin = s_omin, omax = s_omax;
   const double qn = __builtin_nan("");
   if (omin <= omax) {
-    // Ls[r][misL[r] + c] = L(y-h+r, x0-h+c), Rs[r][misR[r] + c] = R(y-h+r, x0-omax-1-h+c).
+    // Ls[r][mL[r] + c] = L(y0-h+r, x0-h+c), Rs[r][mR[r] + c] = R(y0-h+r, x0-omax-1-h+c).
     // Bytes of columns outside the image only enter sums whose z is
     // discarded (a valid pixel's windows at o lie inside the image).
     const int LW = SP_TX + 2 * h, RW = SP_TX + (omax - omin) + 2 + 2 * h;
-    const int lx0 = x0 - h, rx0 = x0 - omax - 1 - h;
-    const GLOBAL uint8_t *Lg = gro(P.left), *Rg = gro(P.right);
-    const long long span = (long long)(H - 1) * P.pitch + W;
-#pragma unroll
-    for (int r = 0; r < SP_MAXWIN; ++r) {
-      if (r < win) {
-        const long long row = (long long)(y - h + r) * P.pitch;  // inside: the block has a valid pixel
-        stage_row(Ls[r], Lg, row + lx0, LW, span, tx);
-        stage_row(Rs[r], Rg, row + rx0, RW, span, tx);
-        if (tx == 0) {
-          misL[r] = (int)(((uintptr_t)Lg + (uintptr_t)(row + lx0)) & 3);
-          misR[r] = (int)(((uintptr_t)Rg + (uintptr_t)(row + rx0)) & 3);
-        }
-      }
-    }
+    const int nrows = min(SPB_TY, H - y0) + 2 * h;
+    stage_rows(Ls, Rs, mL, mR, gro(P.left), gro(P.right), P.pitch,
+               (long long)(H - 1) * P.pitch + W, H, y0 - h, nrows, x0 - h, LW, x0 - omax - 1 - h,
+               RW, tid, SPB_T);
   }
   __syncthreads();
-  if (!in) return;
-  if (!valid) {
-    if (P.zbest) P.zbest[k] = qn;
-    if (P.zm) P.zm[k] = qn;
-    if (P.zp) P.zp[k] = qn;
-    P.delta[k] = 0.0f;
-    return;
-  }
-  // window column u of the thread at d = o + 1 - e is Rs[v][rs + e + u]
-  const int rs = tx + omax - o;
-  int sm = 0, s0 = 0, sp = 0;  // sums at d = o - 1, o, o + 1
-  switch ((win + 3) >> 2) {
-    case 1: sp_sums<1>(Ls, Rs, misL, misR, win, P.chess, tx, rs, sp, s0, sm); break;
-    case 2: sp_sums<2>(Ls, Rs, misL, misR, win, P.chess, tx, rs, sp, s0, sm); break;
-    case 3: sp_sums<3>(Ls, Rs, misL, misR, win, P.chess, tx, rs, sp, s0, sm); break;
-    default: sp_sums<4>(Ls, Rs, misL, misR, win, P.chess, tx, rs, sp, s0, sm); break;
-  }
   const long long n = P.chess ? ((long long)win * win + 1) / 2 : (long long)win * win;
-  const long long sl = P.SL[k];
-  const long long varL = n * (long long)P.SSL[k] - sl * sl;
-  const int slr[3] = {sm, s0, sp};
-  double z[3];
-  for (int q = 0; q < 3; ++q) {
-    const int d = o + q - 1;
-    const int xr = x - d;
-    z[q] = qn;
-    if (d < P.dmin || d > P.dmax || xr < h || xr > W - 1 - h) continue;
-    const size_t kr = (size_t)y * W + xr;
-    const long long sr = P.SR[kr];
-    const long long varR = n * (long long)P.SSR[kr] - sr * sr;
-    if (varR <= 0) continue;
-    const long long num = n * (long long)slr[q] - sl * sr;
-    z[q] = (double)num / sqrt((double)varL * (double)varR);
-  }
-  if (P.zbest) P.zbest[k] = z[1];
-  if (P.zm) P.zm[k] = z[0];
-  if (P.zp) P.zp[k] = z[2];
-  double dl = 0.0;
-  if (o > P.dmin && o < P.dmax && !__builtin_isnan(z[0]) && !__builtin_isnan(z[2])) {
-    const double den = 2.0 * (z[0] - 2.0 * z[1] + z[2]);
-    if (den < 0.0) {
-      dl = (z[0] - z[2]) / den;
-      dl = dl > 0.5 ? 0.5 : (dl < -0.5 ? -0.5 : dl);
+#pragma unroll
+  for (int j = 0; j < NPT; ++j) {
+    const int r0 = ty + 2 * j, y = y0 + r0;
+    if (x >= W || y >= H) continue;
+    const size_t k = (size_t)y * W + x;
+    if (!valid[j]) {
+      if (P.zbest) P.zbest[k] = qn;
+      if (P.zm) P.zm[k] = qn;
+      if (P.zp) P.zp[k] = qn;
+      P.delta[k] = 0.0f;
+      continue;
     }
+    // window column u of the thread at d = o + 1 - e is Rs[r][rs + e + u]
+    const int rs = tx + omax - o[j];
+    int sm = 0, s0 = 0, sp = 0;  // sums at d = o - 1, o, o + 1
+    switch (win) {
+      case 3: sp_sums<3>(Ls, Rs, mL, mR, P.chess, r0, tx, rs, sp, s0, sm); break;
+      case 5: sp_sums<5>(Ls, Rs, mL, mR, P.chess, r0, tx, rs, sp, s0, sm); break;
+      case 7: sp_sums<7>(Ls, Rs, mL, mR, P.chess, r0, tx, rs, sp, s0, sm); break;
+      case 9: sp_sums<9>(Ls, Rs, mL, mR, P.chess, r0, tx, rs, sp, s0, sm); break;
+      case 11: sp_sums<11>(Ls, Rs, mL, mR, P.chess, r0, tx, rs, sp, s0, sm); break;
+      case 13: sp_sums<13>(Ls, Rs, mL, mR, P.chess, r0, tx, rs, sp, s0, sm); break;
+      default: sp_sums<15>(Ls, Rs, mL, mR, P.chess, r0, tx, rs, sp, s0, sm); break;
+    }
+    const long long sl = P.SL[k];
+    const long long varL = n * (long long)P.SSL[k] - sl * sl;
+    const int slr[3] = {sm, s0, sp};
+    double z[3];
+    for (int q = 0; q < 3; ++q) {
+      const int d = o[j] + q - 1;
+      const int xr = x - d;
+      z[q] = qn;
+      if (d < P.dmin || d > P.dmax || xr < h || xr > W - 1 - h) continue;
+      const size_t kr = (size_t)y * W + xr;
+      const long long sr = P.SR[kr];
+      const long long varR = n * (long long)P.SSR[kr] - sr * sr;
+      if (varR <= 0) continue;
+      const long long num = n * (long long)slr[q] - sl * sr;
+      z[q] = (double)num / sqrt((double)varL * (double)varR);
+    }
+    if (P.zbest) P.zbest[k] = z[1];
+    if (P.zm) P.zm[k] = z[0];
+    if (P.zp) P.zp[k] = z[2];
+    double dl = 0.0;
+    if (o[j] > P.dmin && o[j] < P.dmax && !__builtin_isnan(z[0]) && !__builtin_isnan(z[2])) {
+      const double den = 2.0 * (z[0] - 2.0 * z[1] + z[2]);
+      if (den < 0.0) {
+        dl = (z[0] - z[2]) / den;
+        dl = dl > 0.5 ? 0.5 : (dl < -0.5 ? -0.5 : dl);
+      }
+    }
+    P.delta[k] = (float)dl;
   }
-  P.delta[k] = (float)dl;
 }
 
 // ---------------------------------------------------------------- LR check
@@ -290,9 +361,10 @@ __global__ void lr_check_kernel(PostPair one, const PostPair *__restrict__ many,
 //   fill:    the nearest valid pixel within R steps, as (steps << 16) |
 //            uint16 disparity, 0 when there is none (planes hits[2t],
 //            hits[2t+1]).
-// Rows: a wave covers 64 columns of a row, lanes are columns, and ballot
-// masks give the next break or valid pixel; the look-ahead runs over the
-// following 64-column blocks until every lane is settled.  Columns and
+// Rows: one wave per row sweeps its 64-column blocks left to right and then
+// right to left, lanes are columns, ballot masks give the breaks or valid
+// pixels of a block, and the position of the nearest one so far is carried
+// from block to block; each pixel is read once per sweep.  Columns and
 // diagonals: a thread scans SEG rows of one line (plus the look-ahead) and
 // the lanes of a wave are neighbouring lines, so each step reads
 // consecutive columns of one row.
@@ -301,95 +373,133 @@ constexpr int SEG = 32;
 __device__ __forceinline__ uint64_t ballot64(bool p) { return __ballot(p); }
 __device__ __forceinline__ int ctz64(uint64_t v) { return __builtin_ctzll(v); }
 __device__ __forceinline__ int top64(uint64_t v) { return 63 - __builtin_clzll(v); }
+// lanes strictly below / at or below / strictly above `lane`
+__device__ __forceinline__ uint64_t lanes_below(int lane) { return (1ull << lane) - 1; }
+__device__ __forceinline__ uint64_t lanes_upto(int lane) { return lane == 63 ? ~0ull : (2ull << lane) - 1; }
+__device__ __forceinline__ uint64_t lanes_above(int lane) { return lane == 63 ? 0ull : ~0ull << (lane + 1); }
 
-// forward / backward step failure of the outlier test at column p of a row:
-// the neighbour is outside, invalid or too far in disparity
-__device__ __forceinline__ bool step_breaks(const GLOBAL int16_t *o, const GLOBAL uint8_t *m, int p,
-                                            int q, int W, float thresh) {
-  if (q < 0 || q >= W || p < 0 || p >= W) return true;
-  if (!m[q]) return true;
-  const int dv = o[q] - o[p];
-  return !((float)(dv < 0 ? -dv : dv) < thresh);
+// A step between neighbouring pixels holds when the far one is valid and
+// within thresh in disparity.
+__device__ __forceinline__ bool step_holds(int o_near, int o_far, bool m_far, float thresh) {
+  const int dv = o_far - o_near;
+  return m_far && (float)(dv < 0 ? -dv : dv) < thresh;
 }
 
+// Outlier test along rows: db = distance from x back to the last break at or
+// before x (the step x -> x-1 fails, or x = 0), df = distance to the first
+// break at or after x (the step x -> x+1 fails, or x = W-1); bit 0 of pass
+// is df >= r, bit 1 db >= r.  The backward bits of the first sweep wait in a
+// register mask, one bit per block, when W <= 64 * 64; wider rows keep them
+// in pass itself.
 template <bool B>
 __global__ __launch_bounds__(256) void outlier_rows_kernel(PostPair one, const PostPair *__restrict__ many, int r,
                                                           float thresh, int src) {
   PAIR;
   const int H = P.H, W = P.W;
-  // a block holds 4 waves, one row each (no block-level synchronisation)
-  const int lane = threadIdx.x & 63, y = blockIdx.y * 4 + (threadIdx.x >> 6), xb = blockIdx.x * 64;
-  if (y >= H || xb >= W) return;  // whole wave
+  const int lane = threadIdx.x & 63, y = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (y >= H) return;  // whole wave
   const GLOBAL int16_t *o = gro(P.ob[src]) + (size_t)y * W;
   const GLOBAL uint8_t *m = gro(P.mb[src]) + (size_t)y * W;
-  const int x = xb + lane;
-  // forward: distance to the first break at or after x must reach r
-  int df = 0;
-  bool open = true;
-  for (int k = 0; ; ++k) {
-    const int p0 = xb + 64 * k;
-    const uint64_t bm = ballot64(step_breaks(o, m, p0 + lane, p0 + lane + 1, W, thresh));
-    if (open) {
-      const uint64_t rest = k == 0 ? bm >> lane << lane : bm;  // breaks at >= x
-      if (rest) { df = p0 + ctz64(rest) - x; open = false; }
-      else if (p0 + 64 - x >= r) { df = r; open = false; }
+  GLOBAL uint8_t *pass = grw(P.pass) + (size_t)y * W;
+  const int nb = ceil_div(W, 64);
+  const bool inreg = nb <= 64;
+  uint64_t dbits = 0;
+  int lastb = -(1 << 30), co = 0, cm = 0;  // carried: last break, o and m of column 64 b - 1
+  for (int b = 0; b < nb; ++b) {
+    const int x = 64 * b + lane;
+    const bool in = x < W;
+    const int ov = in ? o[x] : 0, mv = in && m[x] ? 1 : 0;
+    int on = __shfl_up(ov, 1, 64), mn = __shfl_up(mv, 1, 64);
+    if (lane == 0) {
+      on = co;
+      mn = cm;
     }
-    if (!__any(open)) break;
-  }
-  // backward: distance from the last break at or before x
-  int db = 0;
-  open = true;
-  for (int k = 0; ; ++k) {
-    const int p0 = xb - 64 * k;
-    const uint64_t bm = ballot64(step_breaks(o, m, p0 + lane, p0 + lane - 1, W, thresh));
-    if (open) {
-      const uint64_t low = k == 0 ? (lane == 63 ? bm : bm & ((2ull << lane) - 1)) : bm;  // <= x
-      if (low) { db = x - (p0 + top64(low)); open = false; }
-      else if (x - (p0 - 1) >= r) { db = r; open = false; }
+    const uint64_t bm = ballot64(in && (x == 0 || !step_holds(ov, on, mn, thresh)));
+    const uint64_t low = bm & lanes_upto(lane);
+    const int lb = low ? 64 * b + top64(low) : lastb;
+    if (inreg) {
+      if (x - lb >= r) dbits |= 1ull << b;
+    } else if (in && mv) {
+      pass[x] = x - lb >= r ? 2 : 0;
     }
-    if (!__any(open)) break;
+    if (bm) lastb = 64 * b + top64(bm);
+    co = __shfl(ov, 63, 64);
+    cm = __shfl(mv, 63, 64);
   }
-  if (x < W && m[x]) P.pass[(size_t)y * W + x] = (df >= r ? 1 : 0) | (db >= r ? 2 : 0);
+  int nextb = 1 << 30;
+  co = 0;
+  cm = 0;  // o and m of column 64 (b + 1)
+  for (int b = nb - 1; b >= 0; --b) {
+    const int x = 64 * b + lane;
+    const bool in = x < W;
+    const int ov = in ? o[x] : 0, mv = in && m[x] ? 1 : 0;
+    int on = __shfl_down(ov, 1, 64), mn = __shfl_down(mv, 1, 64);
+    if (lane == 63) {
+      on = co;
+      mn = cm;
+    }
+    const uint64_t bm = ballot64(in && (x + 1 >= W || !step_holds(ov, on, mn, thresh)));
+    const uint64_t rest = bm & ~lanes_below(lane);
+    const int fb = rest ? 64 * b + ctz64(rest) : nextb;
+    if (in && mv) {
+      const int bbit = inreg ? (((dbits >> b) & 1) ? 2 : 0) : pass[x];
+      pass[x] = (fb - x >= r ? 1 : 0) | bbit;
+    }
+    if (bm) nextb = 64 * b + ctz64(bm);
+    co = __shfl(ov, 0, 64);
+    cm = __shfl(mv, 0, 64);
+  }
 }
 
+// Nearest valid pixel along rows for the holes: hits[0] to the right
+// (forward), hits[1] to the left, within R.
 template <bool B>
 __global__ __launch_bounds__(256) void fill_rows_kernel(PostPair one, const PostPair *__restrict__ many, int R,
                                                        int src) {
   PAIR;
   const int H = P.H, W = P.W;
-  // a block holds 4 waves, one row each (no block-level synchronisation)
-  const int lane = threadIdx.x & 63, y = blockIdx.y * 4 + (threadIdx.x >> 6), xb = blockIdx.x * 64;
-  if (y >= H || xb >= W) return;  // whole wave
+  const int lane = threadIdx.x & 63, y = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (y >= H) return;  // whole wave
   const GLOBAL int16_t *o = gro(P.ob[src]) + (size_t)y * W;
   const GLOBAL uint8_t *m = gro(P.mb[src]) + (size_t)y * W;
-  const int x = xb + lane;
-  int qf = -1, qb = -1;
-  bool open = true;
-  for (int k = 0; ; ++k) {
-    const int p0 = xb + 64 * k, p = p0 + lane;
-    const uint64_t vm = ballot64(p < W && m[p]);
-    if (open) {
-      const uint64_t rest = k == 0 ? (lane == 63 ? 0ull : vm >> (lane + 1) << (lane + 1)) : vm;  // > x
-      if (rest) { qf = p0 + ctz64(rest); open = false; }
-      else if (p0 + 64 - x > R || p0 + 64 >= W) open = false;
+  const size_t N = (size_t)W * H;
+  GLOBAL uint32_t *hf = grw(P.hits) + (size_t)y * W;
+  GLOBAL uint32_t *hb = grw(P.hits) + N + (size_t)y * W;
+  const int nb = ceil_div(W, 64);
+  auto hit = [&](int q, int oq, int x) -> uint32_t {
+    const int dq = q > x ? q - x : x - q;
+    return (q >= 0 && dq <= R) ? ((uint32_t)dq << 16) | (uint16_t)oq : 0u;
+  };
+  int lastv = -1, lasto = 0;  // carried: last valid column left of the block
+  for (int b = 0; b < nb; ++b) {
+    const int x = 64 * b + lane;
+    const bool in = x < W;
+    const int ov = in ? o[x] : 0;
+    const bool mv = in && m[x];
+    const uint64_t vm = ballot64(mv);
+    const uint64_t low = vm & lanes_below(lane);
+    const int oq = __shfl(ov, low ? top64(low) : 0, 64);
+    if (in && !mv) hb[x] = low ? hit(64 * b + top64(low), oq, x) : hit(lastv, lasto, x);
+    if (vm) {
+      lastv = 64 * b + top64(vm);
+      lasto = __shfl(ov, top64(vm), 64);
     }
-    if (!__any(open)) break;
   }
-  open = true;
-  for (int k = 0; ; ++k) {
-    const int p0 = xb - 64 * k, p = p0 + lane;
-    const uint64_t vm = ballot64(p >= 0 && p < W && m[p]);
-    if (open) {
-      const uint64_t low = k == 0 ? vm & ((1ull << lane) - 1) : vm;  // < x
-      if (low) { qb = p0 + top64(low); open = false; }
-      else if (x - (p0 - 1) > R || p0 <= 0) open = false;
+  int nextv = -1, nexto = 0;  // carried: first valid column right of the block
+  for (int b = nb - 1; b >= 0; --b) {
+    const int x = 64 * b + lane;
+    const bool in = x < W;
+    const int ov = in ? o[x] : 0;
+    const bool mv = in && m[x];
+    const uint64_t vm = ballot64(mv);
+    const uint64_t rest = vm & lanes_above(lane);
+    const int oq = __shfl(ov, rest ? ctz64(rest) : 0, 64);
+    if (in && !mv) hf[x] = rest ? hit(64 * b + ctz64(rest), oq, x) : hit(nextv, nexto, x);
+    if (vm) {
+      nextv = 64 * b + ctz64(vm);
+      nexto = __shfl(ov, ctz64(vm), 64);
     }
-    if (!__any(open)) break;
   }
-  if (x >= W || m[x]) return;
-  const size_t N = (size_t)W * H, k = (size_t)y * W + x;
-  P.hits[k] = (qf >= 0 && qf - x <= R) ? ((uint32_t)(qf - x) << 16) | (uint16_t)o[qf] : 0u;
-  P.hits[N + k] = (qb >= 0 && x - qb <= R) ? ((uint32_t)(x - qb) << 16) | (uint16_t)o[qb] : 0u;
 }
 
 // Columns (t = 1), diagonals (t = 2, x = y + l - (H-1)) and anti-diagonals
@@ -777,34 +887,97 @@ __global__ void box_v_kernel(PostPair one, const PostPair *__restrict__ many, in
   }
 }
 
-// Output stage of a row box pass: the plain box sum (mode 0), or the masked
-// mean steps fused into it: mode 1 a = box(s m)/box(m) (Eq. 1), mode 2
-// d = a - box(b m)/box(m) (Eq. 3), mode 3 the same d written as the final
-// disparity (NaN where invalid) and mask.
+// Output stage of a box pass: the plain box sum (mode 0, to plane out), or
+// the masked mean steps fused into it:
+//   mode 1: a = box(s m)/box(m) (Eq. 1) -> F_A
+//   mode 2: d = a - box(b m)/box(m) (Eq. 3) -> F_D
+//   mode 3: the same d written as the final disparity (NaN where invalid)
+//           and mask
+//   mode 4: mode 1, and b = a - alpha s - (1 - alpha) s (Eq. 2 of the first
+//           iteration, d_prev = s) -> plane out
+//   mode 5: d as in mode 2, and the next iteration's b = a - alpha s -
+//           (1 - alpha) d (Eq. 2) -> plane out
+// (b and a are 0 on invalid pixels, as the masked sums need.)
 __device__ __forceinline__ void box_store(const PostPair &P, int mode, int src, int out, size_t N,
-                                          size_t k, double v) {
+                                          size_t k, double v, double alpha) {
   if (mode == 0) {
     P.f[(size_t)out * N + k] = v;
     return;
   }
   const uint8_t mk = P.mb[src][k];
   const double mean = v / P.f[(size_t)F_CNT * N + k];
-  if (mode == 1) {
+  if (mode == 1 || mode == 4) {
     P.f[(size_t)F_A * N + k] = mk ? mean : 0.0;
-  } else {
-    const double d = mk ? P.f[(size_t)F_A * N + k] - mean : 0.0;
-    if (mode == 2) {
-      P.f[(size_t)F_D * N + k] = d;
-    } else {
-      P.disparity[k] = mk ? (float)d : __builtin_nanf("");
-      if (P.valid_mask) P.valid_mask[k] = mk;
+    if (mode == 4) {
+      const double s = P.f[(size_t)F_S * N + k];
+      P.f[(size_t)out * N + k] = mk ? mean - alpha * s - (1.0 - alpha) * s : 0.0;
     }
+    return;
+  }
+  const double a = P.f[(size_t)F_A * N + k];
+  const double d = mk ? a - mean : 0.0;
+  if (mode == 2) {
+    P.f[(size_t)F_D * N + k] = d;
+  } else if (mode == 5) {
+    const double s = P.f[(size_t)F_S * N + k];
+    P.f[(size_t)out * N + k] = mk ? a - alpha * s - (1.0 - alpha) * d : 0.0;
+  } else {
+    P.disparity[k] = mk ? (float)d : __builtin_nanf("");
+    if (P.valid_mask) P.valid_mask[k] = mk;
+  }
+}
+
+// 2-D box sum over the (2R+1)^2 window of plane `in` (clipped at the image
+// border) in one pass, written through box_store.  A block of BX_T threads
+// owns BX_T columns, of which the middle BX_T - 2R are output, and a segment
+// of BX_SY rows: each thread keeps the vertical window sum of its column in a
+// register and slides it down the segment; per row the horizontal sums are
+// differences of a block prefix sum (wave scans plus wave totals in LDS).
+// `in` must differ from every plane the output stage writes.
+constexpr int BX_T = 256, BX_SY = 32, BX_RMAX = 96;
+template <bool B>
+__global__ __launch_bounds__(BX_T) void box2d_kernel(PostPair one, const PostPair *__restrict__ many, int R,
+                                                     int in, int out, int mode, int src, double alpha) {
+  PAIR;
+  __shared__ double pf[2][BX_T];
+  __shared__ double wt[2][BX_T / WV];
+  const int H = P.H, W = P.W;
+  const int nout = BX_T - 2 * R;
+  const int xo = blockIdx.x * nout, y0 = blockIdx.y * BX_SY;
+  if (xo >= W || y0 >= H) return;  // uniform per block
+  const size_t N = (size_t)W * H;
+  const int t = threadIdx.x, lane = t & (WV - 1), wave = t / WV, c = xo - R + t;
+  const bool cin = c >= 0 && c < W;
+  const GLOBAL double *fi = gro(P.f) + (size_t)in * N;
+  auto px = [&](int r) -> double { return (cin && r >= 0 && r < H) ? fi[(size_t)r * W + c] : 0.0; };
+  double s = 0.0;
+  for (int r = y0 - R; r < y0 + R; ++r) s += px(r);
+  const bool out_col = c >= xo && c < xo + nout && c < W;  // then R <= t < BX_T - R
+  const int y1 = min(y0 + BX_SY, H);
+  for (int y = y0; y < y1; ++y) {
+    const int b = y & 1;
+    s += px(y + R);
+    double p = s;
+#pragma unroll
+    for (int o = 1; o < WV; o <<= 1) {
+      const double u = __shfl_up(p, o, WV);
+      if (lane >= o) p += u;
+    }
+    if (lane == WV - 1) wt[b][wave] = p;
+    __syncthreads();
+    for (int w = 0; w < wave; ++w) p += wt[b][w];
+    pf[b][t] = p;
+    __syncthreads();
+    if (out_col)
+      box_store(P, mode, src, out, N, (size_t)y * W + c,
+                pf[b][t + R] - (t - R - 1 >= 0 ? pf[b][t - R - 1] : 0.0), alpha);
+    s -= px(y - R);
   }
 }
 
 template <bool B>
 __global__ void box_h_kernel(PostPair one, const PostPair *__restrict__ many, int R, int seg, int in, int out,
-                             int mode, int src) {
+                             int mode, int src, double alpha) {
   PAIR;
   const int y = blockIdx.x * blockDim.x + threadIdx.x;
   const int x0 = blockIdx.y * seg;
@@ -817,7 +990,7 @@ __global__ void box_h_kernel(PostPair one, const PostPair *__restrict__ many, in
     if (u >= 0 && u < W) s += row[u];
   const int x1 = min(x0 + seg, W);
   for (int x = x0; x < x1; ++x) {
-    box_store(P, mode, src, out, N, (size_t)y * W + x, s);
+    box_store(P, mode, src, out, N, (size_t)y * W + x, s, alpha);
     const int a = x + R + 1, b = x - R;
     if (a < W) s += row[a];
     if (b >= 0) s -= row[b];
@@ -830,7 +1003,7 @@ __global__ void box_h_kernel(PostPair one, const PostPair *__restrict__ many, in
 constexpr int BOXH_MAXW = 4096;
 template <bool B>
 __global__ __launch_bounds__(256) void box_h_lds_kernel(PostPair one, const PostPair *__restrict__ many, int R,
-                                                        int in, int out, int mode, int src) {
+                                                        int in, int out, int mode, int src, double alpha) {
   PAIR;
   __shared__ double row[BOXH_MAXW];
   __shared__ double part[256];
@@ -863,7 +1036,7 @@ __global__ __launch_bounds__(256) void box_h_lds_kernel(PostPair one, const Post
   __syncthreads();
   for (int x = t; x < W; x += 256) {
     const int a = min(x + R, W - 1), b = x - R - 1;
-    box_store(P, mode, src, out, N, (size_t)y * W + x, row[a] - (b >= 0 ? row[b] : 0.0));
+    box_store(P, mode, src, out, N, (size_t)y * W + x, row[a] - (b >= 0 ? row[b] : 0.0), alpha);
   }
 }
 
@@ -1037,14 +1210,14 @@ hipError_t post_decode(const PostLaunch &L) {
   return hipGetLastError();
 }
 hipError_t post_subpixel(const PostLaunch &L) {
-  LAUNCH(subpixel_kernel, dim3(ceil_div(L.maxW, SP_TX), L.maxH, L.npairs), dim3(SP_TX));
+  LAUNCH(subpixel_kernel, dim3(ceil_div(L.maxW, SP_TX), ceil_div(L.maxH, SPB_TY), L.npairs), dim3(SPB_T));
   return hipGetLastError();
 }
 hipError_t post_lr(const PostLaunch &L, int tol, int dst) {
   LAUNCH(lr_check_kernel, pixgrid(L), dim3(PIX_T), tol, dst);
   return hipGetLastError();
 }
-static dim3 rowgrid(const PostLaunch &L) { return dim3(ceil_div(L.maxW, 64), ceil_div(L.maxH, 4), L.npairs); }
+static dim3 rowgrid(const PostLaunch &L) { return dim3(ceil_div(L.maxH, 4), 1, L.npairs); }
 static dim3 vscangrid(const PostLaunch &L) {
   const int n = (L.maxW + 2 * (L.maxW + L.maxH - 1)) * ceil_div(L.maxH, SEG);
   return dim3(ceil_div(n, 256), 1, L.npairs);
@@ -1066,16 +1239,25 @@ hipError_t post_fill(const PostLaunch &L, int radial_r, int min_lines, int disk_
   return hipGetLastError();
 }
 
-// Box sum over the (2R+1)^2 window of plane `in`, stored by box_store's mode.
-static void box2d(const PostLaunch &L, int R, int in, int out, int mode = 0, int src = 0) {
+// Box sum over the (2R+1)^2 window of plane `in`, stored by box_store's
+// mode: one fused pass for R <= BX_RMAX, else a column pass into F_TMP and a
+// row pass (in and the written planes must then differ from F_TMP).
+static void box2d(const PostLaunch &L, int R, int in, int out, int mode = 0, int src = 0,
+                  double alpha = 0.0) {
+  if (R <= BX_RMAX) {
+    const int nout = BX_T - 2 * R;
+    LAUNCH(box2d_kernel, dim3(ceil_div(L.maxW, nout), ceil_div(L.maxH, BX_SY), L.npairs),
+           dim3(BX_T), R, in, out, mode, src, alpha);
+    return;
+  }
   const int seg = 32;
   LAUNCH(box_v_kernel, dim3(ceil_div(L.maxW, 64), ceil_div(L.maxH, seg), L.npairs), dim3(64), R,
          seg, in, F_TMP);
   if (L.maxW <= BOXH_MAXW)
-    LAUNCH(box_h_lds_kernel, dim3(L.maxH, 1, L.npairs), dim3(256), R, F_TMP, out, mode, src);
+    LAUNCH(box_h_lds_kernel, dim3(L.maxH, 1, L.npairs), dim3(256), R, F_TMP, out, mode, src, alpha);
   else
     LAUNCH(box_h_kernel, dim3(ceil_div(L.maxH, 64), ceil_div(L.maxW, seg), L.npairs), dim3(64), R,
-           seg, F_TMP, out, mode, src);
+           seg, F_TMP, out, mode, src, alpha);
 }
 
 // Improved Laplacian smoothing of (ob[src], delta, mb[src]) or s_in; writes
@@ -1100,6 +1282,18 @@ hipError_t post_hc(const PostLaunch &L, int src, int R, int K, float alpha, int 
   if (research) use_delta = 0;
   LAUNCH(hc_init_kernel, pixgrid(L), dim3(PIX_T), src, ocur, use_delta, 1);
   box2d(L, R, F_D, F_CNT);  // counts of valid pixels
+  if (!research) {
+    // a is fixed; every b (Eq. 2) is formed in the output stage of the box
+    // pass before it, alternating between the planes F_D and F_IN (the
+    // counts' input in F_D is no longer needed)
+    box2d(L, R, F_IN, F_D, 4, src, alpha);  // a = box(s m) / box(m), b_0 -> F_D
+    int bin = F_D, bout = F_IN;
+    for (int it = 0; it < K; ++it) {
+      box2d(L, R, bin, bout, it == K - 1 ? 3 : 5, src, alpha);  // d = a - box(b m) / box(m)
+      std::swap(bin, bout);
+    }
+    return hipGetLastError();
+  }
   for (int it = 0; it < K; ++it) {
     if (it == 0 || research) {
       if (it > 0) LAUNCH(hc_init_kernel, pixgrid(L), dim3(PIX_T), src, ocur, use_delta, 0);

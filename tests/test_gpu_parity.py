@@ -116,6 +116,26 @@ def test_match_paper_range_frame(B, orc):
     _check_wta(None, ref, oL, mL, oR, mR)
 
 
+@pytest.mark.parametrize("case", CASES, ids=[f"{c[0]}x{c[1]}_d{c[2]}..{c[3]}_w{c[4]}" for c in CASES])
+def test_subpixel_every_window(B, orc, case):
+    """Exact z at o-1, o, o+1 for every window size, ragged shapes (rows not
+    a multiple of the 4-row blocks, columns not of 128) and signed ranges."""
+    H, W, dmin, dmax, win, seed = case
+    L, R = _pair(H, W, max(dmax, 8), seed)
+    ref = orc.match(L, R, dmin, dmax, win)
+    zb, zm, zp, dl = (np_(t) for t in B.st_subpixel(cu(L), cu(R), dmin, dmax, win,
+                                                       cu(ref["oL"].astype(np.int16)), cu(ref["mL"])))
+    v = ref["mL"] == 1
+    np.testing.assert_allclose(zb[v], ref["zbest"][v], atol=1e-12)
+    for key, g in (("zm", zm), ("zp", zp)):
+        assert np.array_equal(np.isnan(g[v]), np.isnan(ref[key][v])), key
+        f = v & ~np.isnan(ref[key])
+        np.testing.assert_allclose(g[f], ref[key][f], atol=1e-12)
+    rd = orc.subpixel(ref["oL"], ref["mL"], ref["zm"], ref["zbest"], ref["zp"], dmin, dmax)
+    assert np.abs(dl[v] - rd[v]).max() <= 1e-5
+    assert (dl[~v] == 0).all() and np.isnan(zb[~v]).all()
+
+
 def test_subpixel_exact_z(B, orc):
     L, R = _pair(60, 250, 31, 31)
     ref = orc.match(L, R, 0, 31, 7)
@@ -163,7 +183,7 @@ def test_outlier_and_fill_stages(B, orc, H, W):
         assert np.array_equal(np_(go)[rm > 0], ro[rm > 0]), f"fill values {args}"
 
 
-@pytest.mark.parametrize("R,K", [(2, 1), (15, 3), (4, 2), (0, 1), (3, 0)])
+@pytest.mark.parametrize("R,K", [(2, 1), (15, 3), (4, 2), (0, 1), (3, 0), (96, 2), (100, 2)])
 def test_hc_smooth_stage(B, orc, R, K):
     r = np.random.default_rng(R * 10 + K)
     H, W = 90, 170
