@@ -113,6 +113,30 @@ struct RefineArgs {
 
 __host__ __device__ inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
+// Block coordinates (x, y, pair) of a launch with grid (X, Y, pairs).  The
+// launched blocks are spread over the 8 XCDs round-robin (block b runs on
+// XCD b % 8); they are renumbered so that each XCD takes one contiguous
+// eighth of the blocks in (pair, y, x) order.  An XCD then works through a
+// few neighbouring row bands of one or two pairs at a time, and data that
+// neighbouring blocks share (scan look-aheads, window halos, staged rows)
+// stays in its L2.
+struct BlockPos {
+  int x, y, pair;
+};
+__device__ __forceinline__ BlockPos block_pos() {
+  const int X = gridDim.x, Y = gridDim.y;
+  const int T = X * Y * gridDim.z;
+  const int b = blockIdx.x + X * (blockIdx.y + Y * blockIdx.z);
+  const int xcd = b & 7, s = b >> 3;
+  const int g = xcd * (T >> 3) + min(xcd, T & 7) + s;
+  BlockPos q;
+  q.x = g % X;
+  const int r = g / X;
+  q.y = r % Y;
+  q.pair = r / Y;
+  return q;
+}
+
 // ---- host launchers (one per stage); all return hipGetLastError()
 hipError_t launch_prep(const PrepPair &one, const PrepPair *many, int npairs, int maxH,
                        int maxCols, int maxW, int prec, hipStream_t s);

@@ -3,28 +3,41 @@
 // whole input maps and writes new ones, one thread per pixel, so results do
 // not depend on scheduling.  Integer results are exact; smoothing runs in
 // FP64.  Each kernel serves one pair (descriptor by value) or a batch (table
-// in device memory, pair = blockIdx.z).
+// in device memory; see block_pos for the block-to-pair mapping).
 #include <algorithm>
 
 #include "common.h"
 
 namespace st {
 
-#define PAIR const PostPair &P = B ? many[blockIdx.z] : one
+#define PAIR                          \
+  const BlockPos bp = block_pos();    \
+  const PostPair &P = B ? many[bp.pair] : one
 // Per-pixel kernels: a block of PIX_T threads covers PIX_SEG columns of one
 // row, PIX_SEG / PIX_T pixels per thread at stride PIX_T (coalesced).  Few,
 // fat blocks: with one short-lived block per 128 pixels these kernels were
 // limited by the rate at which waves are launched, not by work.
 constexpr int PIX_T = 256, PIX_SEG = 1024;
 template <class F>
-__device__ __forceinline__ void for_pixels(const PostPair &P, F f) {
-  const int y = blockIdx.y;
+__device__ __forceinline__ void for_pixels(const PostPair &P, const BlockPos &bp, F f) {
+  const int y = bp.y;
   if (y >= P.H) return;
-  const int x1 = min(P.W, (int)(blockIdx.x + 1) * PIX_SEG);
-  for (int x = blockIdx.x * PIX_SEG + threadIdx.x; x < x1; x += PIX_T) f(x, y, (size_t)y * P.W + x);
+  const int x1 = min(P.W, (bp.x + 1) * PIX_SEG);
+  for (int x = bp.x * PIX_SEG + threadIdx.x; x < x1; x += PIX_T) f(x, y, (size_t)y * P.W + x);
 }
 
+// floor(a / b) for b > 0.  With |a|, b < 2^52 (every case of the default
+// radii) a double estimate, off by at most one, is corrected with the exact
+// integer remainder, which avoids the long 64-bit integer division.
 __device__ __forceinline__ long long floordiv_ll(long long a, long long b) {
+  constexpr long long LIM = 1LL << 52;
+  if (a > -LIM && a < LIM && b < LIM) {
+    long long q = (long long)floor((double)a / (double)b);
+    const long long r = a - q * b;
+    if (r < 0) --q;
+    else if (r >= b) ++q;
+    return q;
+  }
   long long q = a / b, r = a % b;
   if (r != 0 && ((r < 0) != (b < 0))) --q;
   return q;
@@ -47,7 +60,7 @@ __global__ void decode_kernel(PostPair one, const PostPair *__restrict__ many) {
   const int W = P.W, H = P.H;
   (void)W;
   (void)H;
-  for_pixels(P, [&](int x, int y, size_t k) {
+  for_pixels(P, bp, [&](int x, int y, size_t k) {
     const uint32_t a = P.keyL[k], b = P.keyR[k];
     P.ob[0][k] = a ? (int16_t)(P.dmin + 255 - (int)(a & 255u)) : 0;
     P.mb[0][k] = a ? 1 : 0;
@@ -221,7 +234,7 @@ __global__ __launch_bounds__(SPB_T) void subpixel_kernel(PostPair one, const Pos
   __shared__ __align__(16) uint8_t Rs[SPB_ROWS][SP_RROW];
   __shared__ int s_omin, s_omax, mL[SPB_ROWS], mR[SPB_ROWS];
   const int tid = threadIdx.x, tx = tid & (SP_TX - 1), ty = tid / SP_TX;
-  const int x0 = blockIdx.x * SP_TX, y0 = blockIdx.y * SPB_TY;
+  const int x0 = bp.x * SP_TX, y0 = bp.y * SPB_TY;
   if (x0 >= P.W || y0 >= P.H) return;  // uniform per block
   const int W = P.W, H = P.H, win = P.win, h = win / 2;
   const int x = x0 + tx;
@@ -334,7 +347,7 @@ __global__ void lr_check_kernel(PostPair one, const PostPair *__restrict__ many,
   const int W = P.W, H = P.H;
   (void)W;
   (void)H;
-  for_pixels(P, [&](int x, int y, size_t k) {
+  for_pixels(P, bp, [&](int x, int y, size_t k) {
     const int16_t *oL = P.ob[0];
     uint8_t keep = 0;
     if (P.mb[0][k]) {
@@ -396,7 +409,7 @@ __global__ __launch_bounds__(256) void outlier_rows_kernel(PostPair one, const P
                                                           float thresh, int src) {
   PAIR;
   const int H = P.H, W = P.W;
-  const int lane = threadIdx.x & 63, y = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63, y = bp.x * 4 + (threadIdx.x >> 6);
   if (y >= H) return;  // whole wave
   const GLOBAL int16_t *o = gro(P.ob[src]) + (size_t)y * W;
   const GLOBAL uint8_t *m = gro(P.mb[src]) + (size_t)y * W;
@@ -458,7 +471,7 @@ __global__ __launch_bounds__(256) void fill_rows_kernel(PostPair one, const Post
                                                        int src) {
   PAIR;
   const int H = P.H, W = P.W;
-  const int lane = threadIdx.x & 63, y = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63, y = bp.x * 4 + (threadIdx.x >> 6);
   if (y >= H) return;  // whole wave
   const GLOBAL int16_t *o = gro(P.ob[src]) + (size_t)y * W;
   const GLOBAL uint8_t *m = gro(P.mb[src]) + (size_t)y * W;
@@ -546,7 +559,7 @@ __global__ void outlier_vscan_kernel(PostPair one, const PostPair *__restrict__ 
   PAIR;
   const int H = P.H, W = P.W;
   int t, l, sg;
-  if (!vscan_task(blockIdx.x * blockDim.x + threadIdx.x, H, W, t, l, sg)) return;
+  if (!vscan_task(bp.x * blockDim.x + threadIdx.x, H, W, t, l, sg)) return;
   const VLine L = vline(t, l, H, W);
   const int a = max(L.ylo, sg * SEG), b = min(L.yhi, sg * SEG + SEG);
   if (a >= b) return;
@@ -559,12 +572,15 @@ __global__ void outlier_vscan_kernel(PostPair one, const PostPair *__restrict__ 
     const bool good = vnb & ((float)(dv < 0 ? -dv : dv) < thresh);
     return good ? min(run + 1, r) : 0;
   };
-  {  // forward (+y), walked from the end of the look-ahead back to a
+  // forward results of the own rows wait in a bit mask (bit y - a) and are
+  // stored with the backward ones
+  uint32_t fbits = 0;
+  {  // forward (+y), walked from the end of the look-ahead back to a; the
+     // line's last pixel has no forward step (bit stays 0)
     const int e = min(L.yhi - 1, b - 1 + r);
     int k = e * L.st + L.c0;
     int on = o[k], run = 0;
     bool vn = m[k] != 0;
-    if (e < b && vn) pass[k] = 0;
     int y = e - 1;
     k -= L.st;
 #pragma unroll 8
@@ -582,7 +598,7 @@ __global__ void outlier_vscan_kernel(PostPair one, const PostPair *__restrict__ 
       run = step(op, on, vn, run);
       on = op;
       vn = v;
-      if (v) pass[k] = run >= r ? 1 : 0;
+      fbits |= (v && run >= r ? 1u : 0u) << (y - a);
     }
   }
   {  // backward (-y); when e == a the first row has no step (run 0 < r)
@@ -590,6 +606,7 @@ __global__ void outlier_vscan_kernel(PostPair one, const PostPair *__restrict__ 
     int k = e * L.st + L.c0;
     int on = o[k], run = 0;
     bool vn = m[k] != 0;
+    if (e == a && vn) pass[k] = (uint8_t)(fbits & 1u);
     int y = e + 1;
     k += L.st;
 #pragma unroll 8
@@ -607,7 +624,7 @@ __global__ void outlier_vscan_kernel(PostPair one, const PostPair *__restrict__ 
       run = step(op, on, vn, run);
       on = op;
       vn = v;
-      if (v && run >= r) pass[k] |= 2;
+      if (v) pass[k] = (uint8_t)(((fbits >> (y - a)) & 1u) | (run >= r ? 2u : 0u));
     }
   }
 }
@@ -617,7 +634,7 @@ __global__ void fill_vscan_kernel(PostPair one, const PostPair *__restrict__ man
   PAIR;
   const int H = P.H, W = P.W;
   int t, l, sg;
-  if (!vscan_task(blockIdx.x * blockDim.x + threadIdx.x, H, W, t, l, sg)) return;
+  if (!vscan_task(bp.x * blockDim.x + threadIdx.x, H, W, t, l, sg)) return;
   const VLine L = vline(t, l, H, W);
   const int a = max(L.ylo, sg * SEG), b = min(L.yhi, sg * SEG + SEG);
   if (a >= b) return;
@@ -677,7 +694,7 @@ __global__ void outlier_combine_kernel(PostPair one, const PostPair *__restrict_
   const int W = P.W, H = P.H;
   (void)W;
   (void)H;
-  for_pixels(P, [&](int x, int y, size_t k) {
+  for_pixels(P, bp, [&](int x, int y, size_t k) {
     const size_t N = (size_t)W * H;
     const uint8_t mk = P.mb[src][k];
     P.ob[dst][k] = P.ob[src][k];
@@ -698,7 +715,7 @@ __global__ __launch_bounds__(256) void fill_radial_kernel(PostPair one, const Po
                                                           int min_lines, int src, int dst) {
   PAIR;
   __shared__ int wc[4], wsum[4];
-  const int y = blockIdx.x;
+  const int y = bp.x;
   if (y >= P.H) return;  // uniform per block
   const int W = P.W, H = P.H, t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const size_t N = (size_t)W * H;
@@ -720,10 +737,15 @@ __global__ __launch_bounds__(256) void fill_radial_kernel(PostPair one, const Po
       ov = o[k];
       mv = m[k];
       if (!mv) {
+        // all eight hits in one round trip
+        uint32_t hv[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) hv[i] = hits[(size_t)i * N + k];
         long long num = 0, den = 1;
         int lines = 0;
+#pragma unroll
         for (int ln = 0; ln < 4; ++ln) {
-          const uint32_t ha = hits[(size_t)(2 * ln) * N + k], hb = hits[(size_t)(2 * ln + 1) * N + k];
+          const uint32_t ha = hv[2 * ln], hb = hv[2 * ln + 1];
           if (!ha || !hb) continue;
           const long long sa = ha >> 16, sb = hb >> 16;
           const long long va = (int16_t)(ha & 0xFFFFu), vb = (int16_t)(hb & 0xFFFFu);
@@ -801,7 +823,7 @@ __global__ __launch_bounds__(PIX_T) void fill_disk_kernel(PostPair one, const Po
   const int W = P.W, H = P.H;
   (void)W;
   (void)H;
-  for_pixels(P, [&](int x, int y, size_t k) {
+  for_pixels(P, bp, [&](int x, int y, size_t k) {
     const GLOBAL int16_t *o = gro(P.ob[src]);
     const GLOBAL uint8_t *m = gro(P.mb[src]);
     grw(P.ob[dst])[k] = o[k];
@@ -830,11 +852,12 @@ __global__ __launch_bounds__(PIX_T) void fill_disk_kernel(PostPair one, const Po
 }
 
 // ---------------------------------------------------------------- smoothing (FP64)
-// Planes of P.f: 0 s, 1 s*m / b, 2 box(m), 3 column pass, 4 a = A(s), 5 d.
+// Planes of P.f: 0 s, 1 s*m / b, 2 box(m) (as float), 3 column pass, 4 a =
+// A(s), 5 d / b.
 enum { F_S = 0, F_IN = 1, F_CNT = 2, F_TMP = 3, F_A = 4, F_D = 5 };
 
 // s = o + delta for matched pixels (code 1), o for filled ones (code 2), or
-// the given s_in; plane F_IN <- s*m, F_D <- m (ones, used for the counts).
+// the given s_in.
 __device__ __forceinline__ double hc_s_at(const PostPair &P, size_t k, uint8_t mk, int osrc,
                                           int use_delta) {
   if (P.s_in) return (double)gro(P.s_in)[k];
@@ -842,6 +865,26 @@ __device__ __forceinline__ double hc_s_at(const PostPair &P, size_t k, uint8_t m
   return (mk == 1 && use_delta) ? o + (double)gro(P.delta)[k] : o;
 }
 
+// One box pass: its input, output stage and the smoothing's inputs.
+//   in >= 0: plane in of P.f; BOX_IN_MASK: the mask (1 on valid pixels);
+//   BOX_IN_S: s on valid pixels, 0 elsewhere (formed on the fly).
+//   mode / out / alpha: see box_store; src: plane of the mask; osrc and
+//   use_delta: where s comes from (hc_s_at).
+enum { BOX_IN_MASK = -1, BOX_IN_S = -2 };
+struct BoxArgs {
+  int R, in, out, mode, src, osrc, use_delta;
+  double alpha;
+};
+
+__device__ __forceinline__ double box_in(const PostPair &P, const BoxArgs &A, size_t N, size_t k) {
+  if (A.in >= 0) return gro(P.f)[(size_t)A.in * N + k];
+  const uint8_t mk = gro(P.mb[A.src])[k];
+  if (A.in == BOX_IN_MASK) return mk ? 1.0 : 0.0;
+  return mk ? hc_s_at(P, k, mk, A.osrc, A.use_delta) : 0.0;
+}
+
+// Research mode: plane F_S <- s on valid pixels (0 elsewhere), F_IN <- the
+// same, and with `counts` F_D <- the mask.
 template <bool B>
 __global__ void hc_init_kernel(PostPair one, const PostPair *__restrict__ many, int src, int osrc,
                                int use_delta, int counts) {
@@ -849,7 +892,7 @@ __global__ void hc_init_kernel(PostPair one, const PostPair *__restrict__ many, 
   const int W = P.W, H = P.H;
   (void)W;
   (void)H;
-  for_pixels(P, [&](int x, int y, size_t k) {
+  for_pixels(P, bp, [&](int x, int y, size_t k) {
     const size_t N = (size_t)W * H;
     const uint8_t mk = P.mb[src][k];
     const double v = mk ? hc_s_at(P, k, mk, osrc, use_delta) : 0.0;
@@ -859,36 +902,37 @@ __global__ void hc_init_kernel(PostPair one, const PostPair *__restrict__ many, 
   });
 }
 
-// Box sums over a (2R+1) window along columns: a thread owns one column and
-// a segment of seg rows, seeds the window sum, then slides it.
+// Box sums over a (2R+1) window along columns into plane F_TMP: a thread
+// owns one column and a segment of seg rows, seeds the window sum, then
+// slides it.
 template <bool B>
-__global__ void box_v_kernel(PostPair one, const PostPair *__restrict__ many, int R, int seg, int in, int out) {
+__global__ void box_v_kernel(PostPair one, const PostPair *__restrict__ many, BoxArgs A, int seg) {
   PAIR;
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  const int y0 = blockIdx.y * seg;
-  const int H = P.H, W = P.W;
+  const int x = bp.x * blockDim.x + threadIdx.x;
+  const int y0 = bp.y * seg;
+  const int H = P.H, W = P.W, R = A.R;
   if (x >= W || y0 >= H) return;
   const size_t N = (size_t)W * H;
-  const GLOBAL double *__restrict__ fi = gro(P.f) + in * N;
-  GLOBAL double *__restrict__ fo = grw(P.f) + out * N;
+  GLOBAL double *__restrict__ fo = grw(P.f) + F_TMP * N;
   double s = 0.0;
   const int va = max(0, y0 - R), vb = min(H - 1, y0 + R);
 #pragma unroll 8
-  for (int v = va; v <= vb; ++v) s += fi[(size_t)v * W + x];
+  for (int v = va; v <= vb; ++v) s += box_in(P, A, N, (size_t)v * W + x);
   const int y1 = min(y0 + seg, H);
 #pragma unroll 4
   for (int y = y0; y < y1; ++y) {
     fo[(size_t)y * W + x] = s;
     const int a = y + R + 1, b = y - R;
-    const double ea = a < H ? fi[(size_t)a * W + x] : 0.0;
-    const double eb = b >= 0 ? fi[(size_t)b * W + x] : 0.0;
+    const double ea = a < H ? box_in(P, A, N, (size_t)a * W + x) : 0.0;
+    const double eb = b >= 0 ? box_in(P, A, N, (size_t)b * W + x) : 0.0;
     s += ea;
     s -= eb;
   }
 }
 
-// Output stage of a box pass: the plain box sum (mode 0, to plane out), or
-// the masked mean steps fused into it:
+// Output stage of a box pass with window sum v at pixel k: the counts of
+// valid pixels (mode 0: the box sum of the mask, stored as float - an exact
+// small integer - in plane F_CNT), or the masked mean steps fused into it:
 //   mode 1: a = box(s m)/box(m) (Eq. 1) -> F_A
 //   mode 2: d = a - box(b m)/box(m) (Eq. 3) -> F_D
 //   mode 3: the same d written as the final disparity (NaN where invalid)
@@ -898,61 +942,72 @@ __global__ void box_v_kernel(PostPair one, const PostPair *__restrict__ many, in
 //   mode 5: d as in mode 2, and the next iteration's b = a - alpha s -
 //           (1 - alpha) d (Eq. 2) -> plane out
 // (b and a are 0 on invalid pixels, as the masked sums need.)
-__device__ __forceinline__ void box_store(const PostPair &P, int mode, int src, int out, size_t N,
-                                          size_t k, double v, double alpha) {
-  if (mode == 0) {
-    P.f[(size_t)out * N + k] = v;
+__device__ __forceinline__ void box_store(const PostPair &P, const BoxArgs &A, size_t N, size_t k,
+                                          double v) {
+  GLOBAL float *cnt = (GLOBAL float *)(grw(P.f) + (size_t)F_CNT * N);
+  if (A.mode == 0) {
+    cnt[k] = (float)v;
     return;
   }
-  const uint8_t mk = P.mb[src][k];
-  const double mean = v / P.f[(size_t)F_CNT * N + k];
-  if (mode == 1 || mode == 4) {
+  const uint8_t mk = P.mb[A.src][k];
+  const double mean = v / (double)cnt[k];
+  if (A.mode == 1 || A.mode == 4) {
     P.f[(size_t)F_A * N + k] = mk ? mean : 0.0;
-    if (mode == 4) {
-      const double s = P.f[(size_t)F_S * N + k];
-      P.f[(size_t)out * N + k] = mk ? mean - alpha * s - (1.0 - alpha) * s : 0.0;
+    if (A.mode == 4) {
+      const double s = mk ? hc_s_at(P, k, mk, A.osrc, A.use_delta) : 0.0;
+      P.f[(size_t)A.out * N + k] = mk ? mean - A.alpha * s - (1.0 - A.alpha) * s : 0.0;
     }
     return;
   }
   const double a = P.f[(size_t)F_A * N + k];
   const double d = mk ? a - mean : 0.0;
-  if (mode == 2) {
+  if (A.mode == 2) {
     P.f[(size_t)F_D * N + k] = d;
-  } else if (mode == 5) {
-    const double s = P.f[(size_t)F_S * N + k];
-    P.f[(size_t)out * N + k] = mk ? a - alpha * s - (1.0 - alpha) * d : 0.0;
+  } else if (A.mode == 5) {
+    const double s = mk ? hc_s_at(P, k, mk, A.osrc, A.use_delta) : 0.0;
+    P.f[(size_t)A.out * N + k] = mk ? a - A.alpha * s - (1.0 - A.alpha) * d : 0.0;
   } else {
     P.disparity[k] = mk ? (float)d : __builtin_nanf("");
     if (P.valid_mask) P.valid_mask[k] = mk;
   }
 }
 
-// 2-D box sum over the (2R+1)^2 window of plane `in` (clipped at the image
-// border) in one pass, written through box_store.  A block of BX_T threads
-// owns BX_T columns, of which the middle BX_T - 2R are output, and a segment
-// of BX_SY rows: each thread keeps the vertical window sum of its column in a
-// register and slides it down the segment; per row the horizontal sums are
-// differences of a block prefix sum (wave scans plus wave totals in LDS).
-// `in` must differ from every plane the output stage writes.
+// 2-D box sum over the (2R+1)^2 window of the pass's input (clipped at the
+// image border) in one pass, written through box_store.  A block of BX_T
+// threads owns BX_T columns, of which the middle BX_T - 2R are output, and a
+// segment of BX_SY rows: each thread keeps the vertical window sum of its
+// column in a register and slides it down the segment.  Per row the
+// horizontal sums are differences of the block's prefix sum, with one block
+// barrier: every wave stores its own inclusive scan and its total in LDS,
+// and a thread forms the prefix at the two window ends from the scan value
+// there plus the totals of the waves before it.  The input plane must
+// differ from every plane the output stage writes.
 constexpr int BX_T = 256, BX_SY = 32, BX_RMAX = 96;
 template <bool B>
-__global__ __launch_bounds__(BX_T) void box2d_kernel(PostPair one, const PostPair *__restrict__ many, int R,
-                                                     int in, int out, int mode, int src, double alpha) {
+__global__ __launch_bounds__(BX_T) void box2d_kernel(PostPair one, const PostPair *__restrict__ many,
+                                                     BoxArgs A) {
   PAIR;
   __shared__ double pf[2][BX_T];
   __shared__ double wt[2][BX_T / WV];
-  const int H = P.H, W = P.W;
+  const int H = P.H, W = P.W, R = A.R;
   const int nout = BX_T - 2 * R;
-  const int xo = blockIdx.x * nout, y0 = blockIdx.y * BX_SY;
+  const int xo = bp.x * nout, y0 = bp.y * BX_SY;
   if (xo >= W || y0 >= H) return;  // uniform per block
   const size_t N = (size_t)W * H;
   const int t = threadIdx.x, lane = t & (WV - 1), wave = t / WV, c = xo - R + t;
   const bool cin = c >= 0 && c < W;
-  const GLOBAL double *fi = gro(P.f) + (size_t)in * N;
-  auto px = [&](int r) -> double { return (cin && r >= 0 && r < H) ? fi[(size_t)r * W + c] : 0.0; };
+  auto px = [&](int r) -> double {
+    return (cin && r >= 0 && r < H) ? box_in(P, A, N, (size_t)r * W + c) : 0.0;
+  };
   double s = 0.0;
   for (int r = y0 - R; r < y0 + R; ++r) s += px(r);
   const bool out_col = c >= xo && c < xo + nout && c < W;  // then R <= t < BX_T - R
+  // global prefix at column index i of the block from the stored wave scans
+  auto prefix = [&](int b, int i) -> double {
+    double v = pf[b][i];
+    for (int w = 0; w < i / WV; ++w) v += wt[b][w];
+    return v;
+  };
   const int y1 = min(y0 + BX_SY, H);
   for (int y = y0; y < y1; ++y) {
     const int b = y & 1;
@@ -963,55 +1018,54 @@ __global__ __launch_bounds__(BX_T) void box2d_kernel(PostPair one, const PostPai
       const double u = __shfl_up(p, o, WV);
       if (lane >= o) p += u;
     }
+    pf[b][t] = p;
     if (lane == WV - 1) wt[b][wave] = p;
     __syncthreads();
-    for (int w = 0; w < wave; ++w) p += wt[b][w];
-    pf[b][t] = p;
-    __syncthreads();
     if (out_col)
-      box_store(P, mode, src, out, N, (size_t)y * W + c,
-                pf[b][t + R] - (t - R - 1 >= 0 ? pf[b][t - R - 1] : 0.0), alpha);
+      box_store(P, A, N, (size_t)y * W + c,
+                prefix(b, t + R) - (t - R - 1 >= 0 ? prefix(b, t - R - 1) : 0.0));
     s -= px(y - R);
   }
 }
 
+// Row pass over the column sums in F_TMP (one thread per row segment).
 template <bool B>
-__global__ void box_h_kernel(PostPair one, const PostPair *__restrict__ many, int R, int seg, int in, int out,
-                             int mode, int src, double alpha) {
+__global__ void box_h_kernel(PostPair one, const PostPair *__restrict__ many, BoxArgs A, int seg) {
   PAIR;
-  const int y = blockIdx.x * blockDim.x + threadIdx.x;
-  const int x0 = blockIdx.y * seg;
-  const int H = P.H, W = P.W;
+  const int y = bp.x * blockDim.x + threadIdx.x;
+  const int x0 = bp.y * seg;
+  const int H = P.H, W = P.W, R = A.R;
   if (y >= H || x0 >= W) return;
   const size_t N = (size_t)W * H;
-  const double *row = P.f + in * N + (size_t)y * W;
+  const double *row = P.f + F_TMP * N + (size_t)y * W;
   double s = 0.0;
   for (int u = x0 - R; u <= x0 + R; ++u)
     if (u >= 0 && u < W) s += row[u];
   const int x1 = min(x0 + seg, W);
   for (int x = x0; x < x1; ++x) {
-    box_store(P, mode, src, out, N, (size_t)y * W + x, s, alpha);
+    box_store(P, A, N, (size_t)y * W + x, s);
     const int a = x + R + 1, b = x - R;
     if (a < W) s += row[a];
     if (b >= 0) s -= row[b];
   }
 }
 
-// Row box sums through LDS: one block per row stages the row, takes an
-// inclusive prefix sum and writes out(x) = P(min(x+R, W-1)) - P(x-R-1),
-// with coalesced loads and stores.  Rows up to BOXH_MAXW wide.
+// Row pass over the column sums in F_TMP through LDS: one block per row
+// stages the row, takes an inclusive prefix sum and writes out(x) =
+// P(min(x+R, W-1)) - P(x-R-1), with coalesced loads and stores.  Rows up to
+// BOXH_MAXW wide.
 constexpr int BOXH_MAXW = 4096;
 template <bool B>
-__global__ __launch_bounds__(256) void box_h_lds_kernel(PostPair one, const PostPair *__restrict__ many, int R,
-                                                        int in, int out, int mode, int src, double alpha) {
+__global__ __launch_bounds__(256) void box_h_lds_kernel(PostPair one, const PostPair *__restrict__ many,
+                                                        BoxArgs A) {
   PAIR;
   __shared__ double row[BOXH_MAXW];
   __shared__ double part[256];
-  const int y = blockIdx.x;
-  const int H = P.H, W = P.W;
+  const int y = bp.x;
+  const int H = P.H, W = P.W, R = A.R;
   if (y >= H) return;
   const size_t N = (size_t)W * H;
-  const double *rin = P.f + in * N + (size_t)y * W;
+  const double *rin = P.f + F_TMP * N + (size_t)y * W;
   const int t = threadIdx.x;
   for (int x = t; x < W; x += 256) row[x] = rin[x];
   __syncthreads();
@@ -1036,7 +1090,7 @@ __global__ __launch_bounds__(256) void box_h_lds_kernel(PostPair one, const Post
   __syncthreads();
   for (int x = t; x < W; x += 256) {
     const int a = min(x + R, W - 1), b = x - R - 1;
-    box_store(P, mode, src, out, N, (size_t)y * W + x, row[a] - (b >= 0 ? row[b] : 0.0), alpha);
+    box_store(P, A, N, (size_t)y * W + x, row[a] - (b >= 0 ? row[b] : 0.0));
   }
 }
 
@@ -1080,7 +1134,7 @@ __global__ __launch_bounds__(SP_TX) void research_kernel(PostPair one, const Pos
   __shared__ __align__(16) uint8_t Rs[SP_MAXWIN][SP_RROW];
   __shared__ int s_cmin, s_cmax, misL[SP_MAXWIN], misR[SP_MAXWIN];
   const int tx = threadIdx.x;
-  const int x0 = blockIdx.x * SP_TX, y = blockIdx.y;
+  const int x0 = bp.x * SP_TX, y = bp.y;
   if (x0 >= P.W || y >= P.H) return;  // uniform per block
   const int W = P.W, H = P.H, win = P.win, h = win / 2;
   const int x = x0 + tx;
@@ -1168,7 +1222,7 @@ __global__ void hc_copy_kernel(PostPair one, const PostPair *__restrict__ many, 
   const int W = P.W, H = P.H;
   (void)W;
   (void)H;
-  for_pixels(P, [&](int x, int y, size_t k) {
+  for_pixels(P, bp, [&](int x, int y, size_t k) {
     const uint8_t mk = P.mb[src][k];
     P.disparity[k] = mk ? (float)hc_s_at(P, k, mk, osrc, use_delta) : __builtin_nanf("");
     if (P.valid_mask) P.valid_mask[k] = mk;
@@ -1184,7 +1238,7 @@ __global__ void hc_b_kernel(PostPair one, const PostPair *__restrict__ many, int
   const int W = P.W, H = P.H;
   (void)W;
   (void)H;
-  for_pixels(P, [&](int x, int y, size_t k) {
+  for_pixels(P, bp, [&](int x, int y, size_t k) {
     const size_t N = (size_t)W * H;
     const double s = P.f[F_S * N + k];
     const double dp = first ? s : P.f[F_D * N + k];
@@ -1239,25 +1293,22 @@ hipError_t post_fill(const PostLaunch &L, int radial_r, int min_lines, int disk_
   return hipGetLastError();
 }
 
-// Box sum over the (2R+1)^2 window of plane `in`, stored by box_store's
-// mode: one fused pass for R <= BX_RMAX, else a column pass into F_TMP and a
-// row pass (in and the written planes must then differ from F_TMP).
-static void box2d(const PostLaunch &L, int R, int in, int out, int mode = 0, int src = 0,
-                  double alpha = 0.0) {
-  if (R <= BX_RMAX) {
-    const int nout = BX_T - 2 * R;
-    LAUNCH(box2d_kernel, dim3(ceil_div(L.maxW, nout), ceil_div(L.maxH, BX_SY), L.npairs),
-           dim3(BX_T), R, in, out, mode, src, alpha);
+// Box sum over the (2R+1)^2 window of the pass's input, stored by
+// box_store's mode: one fused pass for R <= BX_RMAX, else a column pass into
+// F_TMP and a row pass (the input and the written planes must then differ
+// from F_TMP).
+static void box2d(const PostLaunch &L, const BoxArgs &A) {
+  if (A.R <= BX_RMAX) {
+    const int nout = BX_T - 2 * A.R;
+    LAUNCH(box2d_kernel, dim3(ceil_div(L.maxW, nout), ceil_div(L.maxH, BX_SY), L.npairs), dim3(BX_T), A);
     return;
   }
   const int seg = 32;
-  LAUNCH(box_v_kernel, dim3(ceil_div(L.maxW, 64), ceil_div(L.maxH, seg), L.npairs), dim3(64), R,
-         seg, in, F_TMP);
+  LAUNCH(box_v_kernel, dim3(ceil_div(L.maxW, 64), ceil_div(L.maxH, seg), L.npairs), dim3(64), A, seg);
   if (L.maxW <= BOXH_MAXW)
-    LAUNCH(box_h_lds_kernel, dim3(L.maxH, 1, L.npairs), dim3(256), R, F_TMP, out, mode, src, alpha);
+    LAUNCH(box_h_lds_kernel, dim3(L.maxH, 1, L.npairs), dim3(256), A);
   else
-    LAUNCH(box_h_kernel, dim3(ceil_div(L.maxH, 64), ceil_div(L.maxW, seg), L.npairs), dim3(64), R,
-           seg, F_TMP, out, mode, src, alpha);
+    LAUNCH(box_h_kernel, dim3(ceil_div(L.maxH, 64), ceil_div(L.maxW, seg), L.npairs), dim3(64), A, seg);
 }
 
 // Improved Laplacian smoothing of (ob[src], delta, mb[src]) or s_in; writes
@@ -1280,28 +1331,37 @@ hipError_t post_hc(const PostLaunch &L, int src, int R, int K, float alpha, int 
   // the two fill planes while the mask stays in plane src
   int ocur = src, oalt = src == 1 ? 2 : 1;
   if (research) use_delta = 0;
-  LAUNCH(hc_init_kernel, pixgrid(L), dim3(PIX_T), src, ocur, use_delta, 1);
-  box2d(L, R, F_D, F_CNT);  // counts of valid pixels
+  auto args = [&](int in, int out, int mode) {
+    BoxArgs A;
+    A.R = R;
+    A.in = in;
+    A.out = out;
+    A.mode = mode;
+    A.src = src;
+    A.osrc = ocur;
+    A.use_delta = use_delta;
+    A.alpha = (double)alpha;
+    return A;
+  };
+  box2d(L, args(BOX_IN_MASK, F_CNT, 0));  // counts of valid pixels
   if (!research) {
-    // a is fixed; every b (Eq. 2) is formed in the output stage of the box
-    // pass before it, alternating between the planes F_D and F_IN (the
-    // counts' input in F_D is no longer needed)
-    box2d(L, R, F_IN, F_D, 4, src, alpha);  // a = box(s m) / box(m), b_0 -> F_D
+    // a is fixed and s is formed on the fly from the disparities; every b
+    // (Eq. 2) is formed in the output stage of the box pass before it,
+    // alternating between the planes F_D and F_IN
+    box2d(L, args(BOX_IN_S, F_D, 4));  // a = box(s m) / box(m), b_0 -> F_D
     int bin = F_D, bout = F_IN;
     for (int it = 0; it < K; ++it) {
-      box2d(L, R, bin, bout, it == K - 1 ? 3 : 5, src, alpha);  // d = a - box(b m) / box(m)
+      box2d(L, args(bin, bout, it == K - 1 ? 3 : 5));  // d = a - box(b m) / box(m)
       std::swap(bin, bout);
     }
     return hipGetLastError();
   }
   for (int it = 0; it < K; ++it) {
-    if (it == 0 || research) {
-      if (it > 0) LAUNCH(hc_init_kernel, pixgrid(L), dim3(PIX_T), src, ocur, use_delta, 0);
-      box2d(L, R, F_IN, F_IN, 1, src);  // a = box(o m) / box(m) or box(s m) / box(m)
-    }
+    LAUNCH(hc_init_kernel, pixgrid(L), dim3(PIX_T), src, ocur, use_delta, 0);
+    box2d(L, args(F_IN, F_IN, 1));  // a = box(o m) / box(m)
     LAUNCH(hc_b_kernel, pixgrid(L), dim3(PIX_T), src, (double)alpha, it == 0 ? 1 : 0);
-    box2d(L, R, F_IN, F_IN, it == K - 1 ? 3 : 2, src);  // d = a - box(b m) / box(m)
-    if (research && it < K - 1) {
+    box2d(L, args(F_IN, F_IN, it == K - 1 ? 3 : 2));  // d = a - box(b m) / box(m)
+    if (it < K - 1) {
       LAUNCH(research_kernel, dim3(ceil_div(L.maxW, SP_TX), L.maxH, L.npairs), dim3(SP_TX), ocur,
              src, oalt, (int)F_D, range, (double)eta);
       std::swap(ocur, oalt);
