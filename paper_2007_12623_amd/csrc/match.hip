@@ -91,11 +91,14 @@ template <> struct Img<P_BF16> {
 // so that ties prefer the smaller disparity.  With j = 15 - (b & 15) and
 // c = 0x80000000 + 240 - (d0 - dmin), the low part is (b & 15) + c and
 // q << 8 = ((b - 0x3F800000) << 4) & ~0xFF, where b is clamped to 1.0.
+// A lane key below 0.5 (no valid candidate: the running maxima start at 0)
+// gives 0, which leaves a merged maximum unchanged.
 __device__ __forceinline__ uint32_t key_base(int dd0) { return 0x80000000u + 240u - (uint32_t)dd0; }
 __device__ __forceinline__ uint32_t global_key(float k, uint32_t c) {
   const uint32_t b = __builtin_bit_cast(uint32_t, k);
   const uint32_t hi = (max(b, 0x3F800000u) << 4) + 0x08000000u;  // (b' - 0x3F800000) << 4
-  return (hi & 0xFFFFFF00u) | ((b & 15u) + c);
+  const uint32_t key = (hi & 0xFFFFFF00u) | ((b & 15u) + c);
+  return b >= 0x3F000000u ? key : 0u;
 }
 
 __device__ __forceinline__ void gmax(GLOBAL uint32_t *p, uint32_t v) {
@@ -236,17 +239,23 @@ __device__ __forceinline__ void match_rows(const MatchPair &P, int y0, int y1, i
     int nsl[K];
     float il[K];
     {
+      // 32-byte aligned: colL is a multiple of 8, strideL of 16
       const uint32_t o = 4u * (uint32_t)(y * P.strideL + colL);
-      const GLOBAL int32_t *ns = (const GLOBAL int32_t *)((const GLOBAL char *)P.negSL + o);
-      const GLOBAL float *iv = (const GLOBAL float *)((const GLOBAL char *)P.invL + o);
+      const GLOBAL uint32_t *ns = (const GLOBAL uint32_t *)((const GLOBAL char *)P.negSL + o);
+      const GLOBAL uint32_t *iv = (const GLOBAL uint32_t *)((const GLOBAL char *)P.invL + o);
+      uint32_t nsw[K], ivw[K];
+      load_dw(nsw, (const GLOBAL char *)ns, 0);
+      load_dw(ivw, (const GLOBAL char *)iv, 0);
       // chessboard: column x0 + c has colour par when c & 1 == cpar (x0 has
       // the parity of xs, so cpar is wave-uniform)
       const int cpar = (xs + y + par) & 1;
+      // bit c set: column c is of the other colour (uniform)
+      const int cm = P.chess ? (cpar ? 0x55 : 0xAA) : 0;
 #pragma unroll
       for (int c = 0; c < K; ++c) {
-        nsl[c] = ns[c];
-        const bool off = halo || (P.chess && (c & 1) != cpar);
-        il[c] = off ? __builtin_nanf("") : iv[c];
+        nsl[c] = (int)nsw[c];
+        const bool off = halo | (((cm >> c) & 1) != 0);
+        il[c] = off ? __builtin_nanf("") : __builtin_bit_cast(float, ivw[c]);
       }
     }
     int sr[T];
@@ -329,20 +338,18 @@ __device__ __forceinline__ void match_rows(const MatchPair &P, int y0, int y1, i
 
     // ---- emit into the tiles: left reference per pixel, right reference
     //      per home column (lane 0 also the 7 columns left of its home)
+    // (branch-free: a lane without a valid candidate merges the key 0; the
+    // halo lanes' left keys are 0 as well, their normalisers being NaN)
     LDS uint32_t *lrow = kt.lt + (y - kt.y0) * (8 * LTP) + lane;
-    if (!halo) {
 #pragma unroll
-      for (int c = 0; c < K; ++c)
-        if (bestL[c] >= 0.5f) lmax(lrow + c * LTP, global_key(bestL[c], kc));
-    }
+    for (int c = 0; c < K; ++c) lmax(lrow + c * LTP, global_key(bestL[c], kc));
     LDS uint32_t *rrow = kt.rt + (y - kt.y0) * (8 * kt.rp);
     const int q0 = x0 - d0 - kt.rbase;  // tile column of home diagonal 0; q0 & 7 is wave-uniform
 #pragma unroll
-    for (int m = 0; m < K; ++m)
-      if (Pd[m + DC - 1] >= 0.5f) {
-        const int q = q0 + m;
-        lmax(rrow + (q & 7) * kt.rp + (q >> 3), global_key(Pd[m + DC - 1], kc));
-      }
+    for (int m = 0; m < K; ++m) {
+      const int q = q0 + m;
+      lmax(rrow + (q & 7) * kt.rp + (q >> 3), global_key(Pd[m + DC - 1], kc));
+    }
     if (lane == 0) {
 #pragma unroll
       for (int m = -(DC - 1); m < 0; ++m)
@@ -462,12 +469,13 @@ __global__ void reset_counter_kernel(int *counter) { *counter = 0; }
 
 // ---------------------------------------------------------------- preparation
 // Padded image planes and the padding of the statistics planes of one pair
-// (descriptor by value) or of a batch (table, pair = blockIdx.z).
+// (descriptor by value) or of a batch (table, pair from block_pos).
 template <int PREC, bool B>
 __global__ void prep_planes_kernel(PrepPair one, const PrepPair *many) {
-  const PrepPair &P = B ? many[blockIdx.z] : one;
-  const int y = blockIdx.y;
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const BlockPos bp = block_pos();
+  const PrepPair &P = B ? many[bp.pair] : one;
+  const int y = bp.y;
+  const int c = bp.x * blockDim.x + threadIdx.x;
   if (y >= P.H) return;
   const int W = P.W;
   const int n = P.chess ? (P.win * P.win + 1) / 2 : P.win * P.win;
@@ -555,11 +563,12 @@ __device__ __forceinline__ void block_prefix(int (&a)[N], int (*wt)[4]) {
 template <bool B, bool CH>
 __global__ __launch_bounds__(WS_T) void window_stats_kernel(PrepPair one, const PrepPair *many,
                                                             int side) {
-  const PrepPair &P = B ? many[blockIdx.z] : one;
+  const BlockPos bp = block_pos();
+  const PrepPair &P = B ? many[bp.pair] : one;
   constexpr int NV = CH ? 4 : 2;  // (S, SS) of each colour
   __shared__ int pf[2][NV][WS_T], wt[2][NV][4];
   const int H = P.H, W = P.W, win = P.win, h = win / 2;
-  const int xo = blockIdx.x * WS_NOUT, y0 = blockIdx.y * WS_SY;
+  const int xo = bp.x * WS_NOUT, y0 = bp.y * WS_SY;
   if (xo >= W || y0 >= H) return;  // uniform per block
   const GLOBAL uint8_t *img = gro(side == 1 ? P.R : P.L);
   const int t = threadIdx.x, c = xo - h + t;
