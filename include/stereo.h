@@ -276,7 +276,7 @@ st_status stereo_time_matcher(st_handle h, const st_pair *pairs, int n_pairs,
  * Variant ids are 0..st_num_variants()-1. */
 st_status st_set_variant(st_handle h, int variant);
 int st_num_variants(void);
-/* Host string describing variant v ("TY=16,CG=8": band height, disparity
+/* Host string describing variant v ("TY=8,CG=16": band height, disparity
  * chunks of 8 per workgroup), "" if out of range. */
 const char *st_variant_name(int v);
 

@@ -47,15 +47,26 @@ static st_status fail(st_status s, const char *fmt, ...) {
     }                                                                                     \
   } while (0)
 
+// Make the handle's device current for the calling thread.
+#define SETDEV(h)                                                                  \
+  do {                                                                             \
+    const hipError_t e_ = hipSetDevice((h)->device);                               \
+    if (e_ != hipSuccess)                                                          \
+      return fail(ST_EHIP, "hipSetDevice(%d) failed: %s", (h)->device, hipGetErrorString(e_)); \
+  } while (0)
+
 // ---------------------------------------------------------------- variants
 // Matcher tilings: band height TY and chunks per workgroup task CG, in the
-// order the default choice prefers them (fewer key merges and fewer
-// vertical-sum restarts first).  Every disparity chunk is 8 wide.
+// order the default choice prefers them.  Bands of 8 rows come first: their
+// key tiles (about 37 KB) leave room for three workgroups per CU, which the
+// matcher's register budget (three waves per SIMD) is sized for; among them
+// fewer key merges and fewer vertical-sum restarts first.  Every disparity
+// chunk is 8 wide.
 struct Variant {
   int TY, CG;
 };
-static const Variant kVariants[] = {{16, 16}, {16, 8}, {8, 16}, {8, 8}, {16, 4},
-                                    {8, 4},   {16, 2}, {8, 2},  {4, 4}, {4, 2}};
+static const Variant kVariants[] = {{8, 16}, {8, 8},  {16, 16}, {16, 8}, {8, 4},
+                                    {16, 4}, {8, 2},  {16, 2},  {4, 4},  {4, 2}};
 static const int kNumVariants = (int)(sizeof kVariants / sizeof kVariants[0]);
 
 // ---------------------------------------------------------------- handle
@@ -106,18 +117,18 @@ static st_status grow(st_handle h, DevBuf &b, size_t need, bool zero) {
   if (b.n >= need && b.p) return ST_OK;
   if (fault_alloc()) return fail(ST_ENOMEM, "device allocation of %zu bytes failed (injected)", need);
   if (b.p) {
-    hipDeviceSynchronize();
-    hipFree(b.p);
+    (void)hipDeviceSynchronize();  // the buffer may still be in use by queued work
+    (void)hipFree(b.p);
     b.p = nullptr;
     b.n = 0;
   }
   void *p = nullptr;
   if (hipMalloc(&p, need) != hipSuccess || !p) {
-    hipGetLastError();
+    (void)hipGetLastError();
     return fail(ST_ENOMEM, "device allocation of %zu bytes failed", need);
   }
   if (zero && hipMemset(p, 0, need) != hipSuccess) {
-    hipFree(p);
+    (void)hipFree(p);
     return fail(ST_EHIP, "hipMemset of scratch failed");
   }
   b.p = p;
@@ -127,7 +138,7 @@ static st_status grow(st_handle h, DevBuf &b, size_t need, bool zero) {
 }
 
 static void release(DevBuf &b) {
-  if (b.p) hipFree(b.p);
+  if (b.p) (void)hipFree(b.p);
   b.p = nullptr;
   b.n = 0;
 }
@@ -454,7 +465,7 @@ st_status st_create(st_handle *out, int device) {
   *out = nullptr;
   int n = 0;
   if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) {
-    hipGetLastError();
+    (void)hipGetLastError();
     return fail(ST_ENODEV, "no HIP device");
   }
   ARG(device >= 0, "device < 0");
@@ -465,10 +476,10 @@ st_status st_create(st_handle *out, int device) {
   if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
     return fail(ST_ENODEV, "device %d is %s, this library is built for gfx950", device,
                 prop.gcnArchName);
+  if (hipSetDevice(device) != hipSuccess) return fail(ST_ENODEV, "cannot select device %d", device);
   st_handle h = new st_handle_s();
   h->device = device;
   h->ncu = prop.multiProcessorCount;
-  hipSetDevice(device);
   if (hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess) {
     delete h;
     return fail(ST_EHIP, "cannot create the capture stream");
@@ -479,8 +490,8 @@ st_status st_create(st_handle *out, int device) {
 }
 
 static void drop_batch(BatchCache &b) {
-  if (b.exec) hipGraphExecDestroy(b.exec);
-  if (b.graph) hipGraphDestroy(b.graph);
+  if (b.exec) (void)hipGraphExecDestroy(b.exec);
+  if (b.graph) (void)hipGraphDestroy(b.graph);
   b.exec = nullptr;
   b.graph = nullptr;
   b.pairs.clear();
@@ -489,8 +500,9 @@ static void drop_batch(BatchCache &b) {
 
 void st_destroy(st_handle h) {
   if (!h) return;
-  hipSetDevice(h->device);
-  hipDeviceSynchronize();
+  // teardown is best effort: a failing call cannot be reported from here
+  (void)hipSetDevice(h->device);
+  (void)hipDeviceSynchronize();
   drop_batch(h->batch);
   release(h->batch.ws);
   release(h->batch.keys);
@@ -498,7 +510,7 @@ void st_destroy(st_handle h) {
   release(h->ws);
   release(h->keys);
   release(h->rws);
-  if (h->cap_stream) hipStreamDestroy(h->cap_stream);
+  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   delete h;
 }
 
@@ -552,7 +564,7 @@ st_status stereo_match(st_handle h, const uint8_t *left, const uint8_t *right, i
   if (rc) return rc;
   ARG(left && right && disparity && valid_mask, "NULL image or output pointer");
   ARG(h, "NULL handle");
-  hipSetDevice(h->device);
+  SETDEV(h);
   hipStream_t s = (hipStream_t)stream;
   const int prec = params->precision;
   const bool debug = params->debug_outputs != 0;
@@ -605,7 +617,7 @@ st_status st_window_stats(st_handle h, const uint8_t *img, int H, int W, int pit
   ARG(H >= 1 && W >= 1 && pitch >= W, "bad image shape");
   ARG(img && S && SS && inv, "NULL pointer");
   ARG(h, "NULL handle");
-  hipSetDevice(h->device);
+  SETDEV(h);
   HIPCK(launch_window_stats_dense(img, H, W, pitch, win, chess, S, SS, inv, (hipStream_t)stream));
   return ST_OK;
 }
@@ -619,7 +631,7 @@ st_status st_match_wta(st_handle h, const uint8_t *left, const uint8_t *right, i
   ARG(precision >= 0 && precision <= 2, "unknown precision %d", precision);
   ARG(left && right && oL && mL && oR && mR, "NULL pointer");
   ARG(h, "NULL handle");
-  hipSetDevice(h->device);
+  SETDEV(h);
   hipStream_t s = (hipStream_t)stream;
   const int v = pick_variant(h, H, W, win, dmin, dmax, precision);
   MatchPair M;
@@ -648,7 +660,7 @@ st_status st_subpixel(st_handle h, const uint8_t *left, const uint8_t *right, in
   ARG(chess == 0 || chess == 1, "chess must be 0 or 1");
   ARG(left && right && oL && mL && delta, "NULL pointer");
   ARG(h, "NULL handle");
-  hipSetDevice(h->device);
+  SETDEV(h);
   hipStream_t s = (hipStream_t)stream;
   const size_t N = (size_t)H * W;
   HIPCK(grow(h, h->ws, 16 * N + 1024, false) == ST_OK ? hipSuccess : hipErrorOutOfMemory);
@@ -684,7 +696,7 @@ st_status st_lr_check(st_handle h, const int16_t *oL, const uint8_t *mL, const i
   ARG(H >= 1 && W >= 1 && tol >= 0, "bad shape or tolerance");
   ARG(oL && mL && oR && mR && mask_out, "NULL pointer");
   ARG(h, "NULL handle");
-  hipSetDevice(h->device);
+  SETDEV(h);
   const size_t N = (size_t)H * W;
   HIPCK(grow(h, h->ws, 2 * N + 256, false) == ST_OK ? hipSuccess : hipErrorOutOfMemory);
   PostPair Q{};
@@ -706,7 +718,7 @@ st_status st_radial_outlier(st_handle h, const int16_t *o, const uint8_t *m_in, 
   ARG(o && m_in && m_out, "NULL pointer");
   ARG(m_out != m_in, "m_out aliases m_in");
   ARG(h, "NULL handle");
-  hipSetDevice(h->device);
+  SETDEV(h);
   const size_t N = (size_t)H * W;
   Carve c;
   const size_t ot = c.take(2 * N), pt = c.take(4 * N), tot = c.take(0);
@@ -733,7 +745,7 @@ st_status st_fill(st_handle h, const int16_t *o_in, const uint8_t *m_in, int H, 
   ARG((const void *)o_out != (const void *)o_in && (const void *)m_out != (const void *)m_in,
       "outputs alias inputs");
   ARG(h, "NULL handle");
-  hipSetDevice(h->device);
+  SETDEV(h);
   const size_t N = (size_t)H * W;
   Carve c;
   const size_t ot = c.take(2 * N), mt = c.take(N), pc = c.take(4 * (size_t)H * (W + 1)),
@@ -766,7 +778,7 @@ st_status st_research(st_handle h, const uint8_t *left, const uint8_t *right, in
   ARG(left && right && o_in && m && d && o_out, "NULL pointer");
   ARG((const void *)o_in != (const void *)o_out, "o_out aliases o_in");
   ARG(h, "NULL handle");
-  hipSetDevice(h->device);
+  SETDEV(h);
   hipStream_t s = (hipStream_t)stream;
   const size_t N = (size_t)H * W;
   HIPCK(grow(h, h->ws, 16 * N + 1024, false) == ST_OK ? hipSuccess : hipErrorOutOfMemory);
@@ -800,7 +812,7 @@ st_status st_reproject(st_handle h, const float *disparity, int H, int W, const 
   ARG(H >= 1 && W >= 1 && (long long)H * W <= (1LL << 28), "bad shape");
   ARG(disparity && Q && xyz, "NULL pointer");
   ARG(h, "NULL handle");
-  hipSetDevice(h->device);
+  SETDEV(h);
   Mat4 M;
   for (int i = 0; i < 16; ++i) M.q[i] = Q[i];
   HIPCK(launch_reproject(disparity, H, W, M, xyz, (hipStream_t)stream));
@@ -812,7 +824,7 @@ st_status st_hc_smooth(st_handle h, const float *s_in, const uint8_t *m, int H, 
   ARG(H >= 1 && W >= 1 && R >= 0 && R <= 2048 && K >= 0 && K <= 64, "bad shape or parameters");
   ARG(s_in && m && out, "NULL pointer");
   ARG(h, "NULL handle");
-  hipSetDevice(h->device);
+  SETDEV(h);
   const size_t N = (size_t)H * W;
   HIPCK(grow(h, h->ws, 6 * 8 * N + 256, false) == ST_OK ? hipSuccess : hipErrorOutOfMemory);
   PostPair Q{};
@@ -840,7 +852,7 @@ st_status stereo_match_batched(st_handle h, const st_pair *pairs, int n_pairs,
     ARG(q.left && q.right && q.disparity && q.valid_mask, "pair %d: NULL pointer", i);
   }
   ARG(h, "NULL handle");
-  hipSetDevice(h->device);
+  SETDEV(h);
   hipStream_t s = (hipStream_t)stream;
   const int prec = params->precision;
   BatchCache &B = h->batch;
@@ -962,14 +974,14 @@ st_status stereo_match_batched(st_handle h, const st_pair *pairs, int n_pairs,
   hipGraph_t g = nullptr;
   hipError_t ee = hipStreamEndCapture(cs, &g);
   if (e != hipSuccess || ee != hipSuccess) {
-    if (g) hipGraphDestroy(g);
+    if (g) (void)hipGraphDestroy(g);
     h->keys_dirty = true;
     return fail(ST_EHIP, "capture of the batched launch failed: %s",
                 hipGetErrorString(e != hipSuccess ? e : ee));
   }
   hipGraphExec_t ex = nullptr;
   if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
-    hipGraphDestroy(g);
+    (void)hipGraphDestroy(g);
     return fail(ST_EHIP, "hipGraphInstantiate failed");
   }
   B.graph = g;
@@ -1012,8 +1024,8 @@ st_status stereo_time_matcher(st_handle h, const st_pair *pairs, int n_pairs,
       total += ms;
     }
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   HIPCK(e);
   // the keys now hold the merged maxima again; the next decode clears them,
   // so replay the batch once to leave every output consistent
@@ -1031,7 +1043,7 @@ static st_status refine_setup(st_handle h, const uint8_t *left, const uint8_t *r
   ARG(left && right && d && mask, "NULL pointer");
   ARG(lambda_tv >= 0.0f, "lambda_tv < 0");
   ARG(h, "NULL handle");
-  hipSetDevice(h->device);
+  SETDEV(h);
   const size_t N = (size_t)H * W;
   const size_t need = (size_t)refine_planes() * 8 * N + 8 * (size_t)refine_partials(H, W) + 512;
   st_status rc = grow(h, h->rws, need, false);
@@ -1082,7 +1094,7 @@ st_status stereo_refine_step(st_handle h, float *d, const float *grad_d, const u
   ARG(H >= 1 && W >= 1 && (long long)H * W <= (1LL << 28), "bad shape");
   ARG(tau >= 0.0f && max_step >= 0.0f, "negative step parameters");
   ARG(h, "NULL handle");
-  hipSetDevice(h->device);
+  SETDEV(h);
   HIPCK(launch_refine_step(d, grad_d, mask, H * W, tau, max_step, (hipStream_t)stream));
   return ST_OK;
 }
@@ -1167,7 +1179,7 @@ extern "C" st_status st_autotune(st_handle h, int H, int W, int dmin, int dmax, 
   if (rc) return rc;
   ARG(precision >= 0 && precision <= 2, "unknown precision");
   ARG(h, "NULL handle");
-  hipSetDevice(h->device);
+  SETDEV(h);
   hipStream_t s = (hipStream_t)stream;
   // seeded test pattern: a smooth texture and its shift by a quarter range
   const size_t N = (size_t)H * W;
@@ -1186,13 +1198,19 @@ extern "C" st_status st_autotune(st_handle h, int H, int W, int dmin, int dmax, 
   uint8_t *dimg = nullptr;
   HIPCK(hipMalloc(&dimg, 2 * N));
   hipError_t e = hipMemcpy(dimg, img.data(), 2 * N, hipMemcpyHostToDevice);
-  if (e != hipSuccess) { hipFree(dimg); HIPCK(e); }
+  if (e != hipSuccess) {
+    (void)hipFree(dimg);
+    HIPCK(e);
+  }
   int best = -1;
   double best_ms = 1e30;
-  hipEvent_t e0, e1;
-  hipEventCreate(&e0);
-  hipEventCreate(&e1);
-  for (int v = 0; v < kNumVariants; ++v) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  auto ck = [&](hipError_t x) {
+    if (x != hipSuccess && e == hipSuccess) e = x;
+  };
+  for (int v = 0; v < kNumVariants && e == hipSuccess; ++v) {
     MatchPair M;
     PrepPair Pp;
     PostPair Q;
@@ -1200,17 +1218,17 @@ extern "C" st_status st_autotune(st_handle h, int H, int W, int dmin, int dmax, 
     rc = setup_single(h, dimg, dimg + N, H, W, W, dmin, dmax, win, 0, precision, v, false, M, Pp,
                       Q, Lo, s);
     if (rc) break;
-    launch_prep(Pp, nullptr, 1, H, std::max(M.strideL, M.strideR), W, precision, s);
+    ck(launch_prep(Pp, nullptr, 1, H, std::max(M.strideL, M.strideR), W, precision, s));
     PostLaunch L = single_launch(Q, s);
     double ms_min = 1e30;
-    for (int rep = 0; rep < 4; ++rep) {
-      hipEventRecord(e0, s);
-      launch_match(M, precision, s);
-      hipEventRecord(e1, s);
-      post_decode(L);
-      hipEventSynchronize(e1);
+    for (int rep = 0; rep < 4 && e == hipSuccess; ++rep) {
+      ck(hipEventRecord(e0, s));
+      ck(launch_match(M, precision, s));
+      ck(hipEventRecord(e1, s));
+      ck(post_decode(L));
+      ck(hipEventSynchronize(e1));
       float ms = 0;
-      hipEventElapsedTime(&ms, e0, e1);
+      ck(hipEventElapsedTime(&ms, e0, e1));
       if (rep > 0) ms_min = std::min(ms_min, (double)ms);
     }
     if (ms_min < best_ms) {
@@ -1218,11 +1236,12 @@ extern "C" st_status st_autotune(st_handle h, int H, int W, int dmin, int dmax, 
       best = v;
     }
   }
-  hipStreamSynchronize(s);
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
-  hipFree(dimg);
+  ck(hipStreamSynchronize(s));
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipFree(dimg);
   if (rc) return rc;
+  HIPCK(e);
   if (best < 0) return fail(ST_EUNSUPPORTED, "no matcher variant fits this shape");
   h->tune[tune_key(H, W, win, dmin, dmax, precision)] = best;
   save_tune(h);

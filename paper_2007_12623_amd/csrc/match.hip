@@ -432,7 +432,7 @@ __device__ __forceinline__ void wg_task(const MatchPair &P, int g, int cg, LDS u
 // One workgroup per task.  Blocks b with equal b % 8 run on one XCD; each
 // XCD gets whole (band, span) groups so that their chunk groups share its L2.
 template <int WIN, int DC, int PREC>
-__global__ __launch_bounds__(NWAVE * WV) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ __launch_bounds__(NWAVE * WV) __attribute__((amdgpu_waves_per_eu(3)))
 void match_kernel(MatchPair P, int ngroups) {
   extern __shared__ uint32_t lds_dyn[];
   const int b = blockIdx.x;
@@ -448,7 +448,7 @@ void match_kernel(MatchPair P, int ngroups) {
 // window size from a queue until it is empty.  Every workgroup reaches the
 // exit once the counter passes ntasks.
 template <int WIN, int DC, int PREC>
-__global__ __launch_bounds__(NWAVE * WV) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ __launch_bounds__(NWAVE * WV) __attribute__((amdgpu_waves_per_eu(3)))
 void match_persistent_kernel(const MatchPair *__restrict__ pairs, const int4 *__restrict__ tasks,
                              int ntasks, int *__restrict__ counter) {
   extern __shared__ uint32_t lds_dyn[];

@@ -141,29 +141,31 @@ __device__ __forceinline__ uint32_t fetch_dw(const GLOBAL uint8_t *base, long lo
 
 // Stage image rows yr0 .. yr0 + nrows - 1 (rows outside the image are
 // skipped): LW bytes of L from column lx0 and RW bytes of R from column rx0
-// go to Ls[r] / Rs[r] as whole dwords from the dword-aligned address at or
-// below the first byte; mL[r] / mR[r] receive the offset of that byte in the
-// LDS row.  All threads of the block share the dwords of a row.
-__device__ __forceinline__ void stage_rows(uint8_t (*Ls)[SP_LROW], uint8_t (*Rs)[SP_RROW], int *mL,
-                                           int *mR, const GLOBAL uint8_t *Lg,
-                                           const GLOBAL uint8_t *Rg, int pitch, long long span,
-                                           int H, int yr0, int nrows, int lx0, int LW, int rx0,
-                                           int RW, int tid, int nthreads) {
+// go to Ls[r] / Rs[r] starting at byte 0, realigned from the whole dwords of
+// the image (v_alignbyte of two neighbouring dwords), so that every staged
+// row has the same layout whatever the pitch.  All threads of the block
+// share the dwords of a row.
+__device__ __forceinline__ void stage_rows(uint8_t (*Ls)[SP_LROW], uint8_t (*Rs)[SP_RROW],
+                                           const GLOBAL uint8_t *Lg, const GLOBAL uint8_t *Rg,
+                                           int pitch, long long span, int H, int yr0, int nrows,
+                                           int lx0, int LW, int rx0, int RW, int tid, int nthreads) {
   for (int r = 0; r < nrows; ++r) {
     const int yy = yr0 + r;
     if (yy < 0 || yy >= H) continue;  // uniform
     const long long row = (long long)yy * pitch;
     const int misl = (int)(((uintptr_t)Lg + (uintptr_t)(row + lx0)) & 3);
     const int misr = (int)(((uintptr_t)Rg + (uintptr_t)(row + rx0)) & 3);
-    const int nl = (misl + LW + 3) >> 2, nr = (misr + RW + 3) >> 2;
+    const int nl = (LW + 3) >> 2, nr = (RW + 3) >> 2;
     const long long al = row + lx0 - misl, ar = row + rx0 - misr;
     for (int i = tid; i < nl + nr; i += nthreads) {
-      if (i < nl) ((uint32_t *)Ls[r])[i] = fetch_dw(Lg, al, i, span);
-      else ((uint32_t *)Rs[r])[i - nl] = fetch_dw(Rg, ar, i - nl, span);
-    }
-    if (tid == 0) {
-      mL[r] = misl;
-      mR[r] = misr;
+      const bool isl = i < nl;
+      const int j = isl ? i : i - nl;
+      const GLOBAL uint8_t *g = isl ? Lg : Rg;
+      const long long a = isl ? al : ar;
+      const uint32_t v = __builtin_amdgcn_alignbyte(fetch_dw(g, a, j + 1, span), fetch_dw(g, a, j, span),
+                                                    isl ? misl : misr);
+      if (isl) ((uint32_t *)Ls[r])[j] = v;
+      else ((uint32_t *)Rs[r])[j] = v;
     }
   }
 }
@@ -174,15 +176,16 @@ __device__ __forceinline__ void stage_rows(uint8_t (*Ls)[SP_LROW], uint8_t (*Rs)
 // to 0); NR dwords cover the WIN + 2 bytes of R that the shifted rows meet.
 template <int WIN>
 __device__ __forceinline__ void sp_sums(const uint8_t (*Ls)[SP_LROW], const uint8_t (*Rs)[SP_RROW],
-                                        const int *mL, const int *mR, int chess, int r0, int tx,
-                                        int rs0, int &sp, int &s0, int &sm) {
+                                        int chess, int r0, int tx, int rs0, int &sp, int &s0,
+                                        int &sm) {
   constexpr int NL = (WIN + 3) / 4, NR = (WIN + 5) / 4;
   constexpr uint32_t lmask = (WIN & 3) ? (1u << (8 * (WIN & 3))) - 1u : 0xFFFFFFFFu;
   uint32_t a0 = 0, a1 = 0, a2 = 0;
-#pragma unroll 1
+  // the window starts at byte tx of every L row and byte rs0 of every R row
+  const int lb = tx, rb = rs0;
+#pragma unroll 2
   for (int v = 0; v < WIN; ++v) {
     const int r = r0 + v;
-    const int lb = tx + mL[r], rb = rs0 + mR[r];
     const uint32_t *lw = (const uint32_t *)&Ls[r][lb & ~3];
     const uint32_t *rw = (const uint32_t *)&Rs[r][rb & ~3];
     uint32_t lt[NL + 1], rt[NR + 1];
@@ -232,7 +235,7 @@ __global__ __launch_bounds__(SPB_T) void subpixel_kernel(PostPair one, const Pos
   PAIR;
   __shared__ __align__(16) uint8_t Ls[SPB_ROWS][SP_LROW];
   __shared__ __align__(16) uint8_t Rs[SPB_ROWS][SP_RROW];
-  __shared__ int s_omin, s_omax, mL[SPB_ROWS], mR[SPB_ROWS];
+  __shared__ int s_omin, s_omax;
   const int tid = threadIdx.x, tx = tid & (SP_TX - 1), ty = tid / SP_TX;
   const int x0 = bp.x * SP_TX, y0 = bp.y * SPB_TY;
   if (x0 >= P.W || y0 >= P.H) return;  // uniform per block
@@ -272,12 +275,12 @@ __global__ __launch_bounds__(SPB_T) void subpixel_kernel(PostPair one, const Pos
   const int omin = s_omin, omax = s_omax;
   const double qn = __builtin_nan("");
   if (omin <= omax) {
-    // Ls[r][mL[r] + c] = L(y0-h+r, x0-h+c), Rs[r][mR[r] + c] = R(y0-h+r, x0-omax-1-h+c).
+    // Ls[r][c] = L(y0-h+r, x0-h+c), Rs[r][c] = R(y0-h+r, x0-omax-1-h+c).
     // Bytes of columns outside the image only enter sums whose z is
     // discarded (a valid pixel's windows at o lie inside the image).
     const int LW = SP_TX + 2 * h, RW = SP_TX + (omax - omin) + 2 + 2 * h;
     const int nrows = min(SPB_TY, H - y0) + 2 * h;
-    stage_rows(Ls, Rs, mL, mR, gro(P.left), gro(P.right), P.pitch,
+    stage_rows(Ls, Rs, gro(P.left), gro(P.right), P.pitch,
                (long long)(H - 1) * P.pitch + W, H, y0 - h, nrows, x0 - h, LW, x0 - omax - 1 - h,
                RW, tid, SPB_T);
   }
@@ -299,13 +302,13 @@ __global__ __launch_bounds__(SPB_T) void subpixel_kernel(PostPair one, const Pos
     const int rs = tx + omax - o[j];
     int sm = 0, s0 = 0, sp = 0;  // sums at d = o - 1, o, o + 1
     switch (win) {
-      case 3: sp_sums<3>(Ls, Rs, mL, mR, P.chess, r0, tx, rs, sp, s0, sm); break;
-      case 5: sp_sums<5>(Ls, Rs, mL, mR, P.chess, r0, tx, rs, sp, s0, sm); break;
-      case 7: sp_sums<7>(Ls, Rs, mL, mR, P.chess, r0, tx, rs, sp, s0, sm); break;
-      case 9: sp_sums<9>(Ls, Rs, mL, mR, P.chess, r0, tx, rs, sp, s0, sm); break;
-      case 11: sp_sums<11>(Ls, Rs, mL, mR, P.chess, r0, tx, rs, sp, s0, sm); break;
-      case 13: sp_sums<13>(Ls, Rs, mL, mR, P.chess, r0, tx, rs, sp, s0, sm); break;
-      default: sp_sums<15>(Ls, Rs, mL, mR, P.chess, r0, tx, rs, sp, s0, sm); break;
+      case 3: sp_sums<3>(Ls, Rs, P.chess, r0, tx, rs, sp, s0, sm); break;
+      case 5: sp_sums<5>(Ls, Rs, P.chess, r0, tx, rs, sp, s0, sm); break;
+      case 7: sp_sums<7>(Ls, Rs, P.chess, r0, tx, rs, sp, s0, sm); break;
+      case 9: sp_sums<9>(Ls, Rs, P.chess, r0, tx, rs, sp, s0, sm); break;
+      case 11: sp_sums<11>(Ls, Rs, P.chess, r0, tx, rs, sp, s0, sm); break;
+      case 13: sp_sums<13>(Ls, Rs, P.chess, r0, tx, rs, sp, s0, sm); break;
+      default: sp_sums<15>(Ls, Rs, P.chess, r0, tx, rs, sp, s0, sm); break;
     }
     const long long sl = P.SL[k];
     const long long varL = n * (long long)P.SSL[k] - sl * sl;
@@ -941,35 +944,67 @@ __global__ void box_v_kernel(PostPair one, const PostPair *__restrict__ many, Bo
 //           iteration, d_prev = s) -> plane out
 //   mode 5: d as in mode 2, and the next iteration's b = a - alpha s -
 //           (1 - alpha) d (Eq. 2) -> plane out
-// (b and a are 0 on invalid pixels, as the masked sums need.)
+// (b and a are 0 on invalid pixels, as the masked sums need.)  The inputs
+// the stage reads are gathered first (box_store_in), so that a caller can
+// load them ahead of time.
+struct BoxStoreIn {
+  uint8_t mk;
+  float cnt;
+  double a, s;
+};
+__device__ __forceinline__ BoxStoreIn box_store_in(const PostPair &P, const BoxArgs &A, size_t N,
+                                                   size_t k) {
+  BoxStoreIn q;
+  q.mk = 0;
+  q.cnt = 1.0f;
+  q.a = 0.0;
+  q.s = 0.0;
+  if (A.mode == 0) return q;
+  q.mk = gro(P.mb[A.src])[k];
+  q.cnt = ((const GLOBAL float *)(gro(P.f) + (size_t)F_CNT * N))[k];
+  if (A.mode == 2 || A.mode == 3 || A.mode == 5) q.a = gro(P.f)[(size_t)F_A * N + k];
+  if (A.mode == 4 || A.mode == 5) {
+    // s without a branch on the mask: both loads issue at once
+    if (P.s_in) {
+      q.s = (double)gro(P.s_in)[k];
+    } else {
+      const double o = (double)gro(P.ob[A.osrc])[k];
+      const double dl = A.use_delta ? (double)gro(P.delta)[k] : 0.0;
+      q.s = q.mk == 1 ? o + dl : o;
+    }
+  }
+  return q;
+}
 __device__ __forceinline__ void box_store(const PostPair &P, const BoxArgs &A, size_t N, size_t k,
-                                          double v) {
-  GLOBAL float *cnt = (GLOBAL float *)(grw(P.f) + (size_t)F_CNT * N);
+                                          double v, const BoxStoreIn &q) {
   if (A.mode == 0) {
-    cnt[k] = (float)v;
+    ((GLOBAL float *)(grw(P.f) + (size_t)F_CNT * N))[k] = (float)v;
     return;
   }
-  const uint8_t mk = P.mb[A.src][k];
-  const double mean = v / (double)cnt[k];
+  const uint8_t mk = q.mk;
+  const double mean = v / (double)q.cnt;
   if (A.mode == 1 || A.mode == 4) {
     P.f[(size_t)F_A * N + k] = mk ? mean : 0.0;
     if (A.mode == 4) {
-      const double s = mk ? hc_s_at(P, k, mk, A.osrc, A.use_delta) : 0.0;
+      const double s = mk ? q.s : 0.0;
       P.f[(size_t)A.out * N + k] = mk ? mean - A.alpha * s - (1.0 - A.alpha) * s : 0.0;
     }
     return;
   }
-  const double a = P.f[(size_t)F_A * N + k];
-  const double d = mk ? a - mean : 0.0;
+  const double d = mk ? q.a - mean : 0.0;
   if (A.mode == 2) {
     P.f[(size_t)F_D * N + k] = d;
   } else if (A.mode == 5) {
-    const double s = mk ? hc_s_at(P, k, mk, A.osrc, A.use_delta) : 0.0;
-    P.f[(size_t)A.out * N + k] = mk ? a - A.alpha * s - (1.0 - A.alpha) * d : 0.0;
+    const double s = mk ? q.s : 0.0;
+    P.f[(size_t)A.out * N + k] = mk ? q.a - A.alpha * s - (1.0 - A.alpha) * d : 0.0;
   } else {
     P.disparity[k] = mk ? (float)d : __builtin_nanf("");
     if (P.valid_mask) P.valid_mask[k] = mk;
   }
+}
+__device__ __forceinline__ void box_store(const PostPair &P, const BoxArgs &A, size_t N, size_t k,
+                                          double v) {
+  box_store(P, A, N, k, v, box_store_in(P, A, N, k));
 }
 
 // 2-D box sum over the (2R+1)^2 window of the pass's input (clipped at the
@@ -1000,6 +1035,7 @@ __global__ __launch_bounds__(BX_T) void box2d_kernel(PostPair one, const PostPai
     return (cin && r >= 0 && r < H) ? box_in(P, A, N, (size_t)r * W + c) : 0.0;
   };
   double s = 0.0;
+#pragma unroll 8
   for (int r = y0 - R; r < y0 + R; ++r) s += px(r);
   const bool out_col = c >= xo && c < xo + nout && c < W;  // then R <= t < BX_T - R
   // global prefix at column index i of the block from the stored wave scans
@@ -1009,9 +1045,19 @@ __global__ __launch_bounds__(BX_T) void box2d_kernel(PostPair one, const PostPai
     return v;
   };
   const int y1 = min(y0 + BX_SY, H);
+  // the next row's inputs are loaded one row ahead
+  double add_n = px(y0 + R), sub_n = px(y0 - R);
+  BoxStoreIn in_n = out_col ? box_store_in(P, A, N, (size_t)y0 * W + c) : BoxStoreIn{};
   for (int y = y0; y < y1; ++y) {
     const int b = y & 1;
-    s += px(y + R);
+    s += add_n;
+    const double sub = sub_n;
+    const BoxStoreIn in = in_n;
+    if (y + 1 < y1) {
+      add_n = px(y + 1 + R);
+      sub_n = px(y + 1 - R);
+      if (out_col) in_n = box_store_in(P, A, N, (size_t)(y + 1) * W + c);
+    }
     double p = s;
 #pragma unroll
     for (int o = 1; o < WV; o <<= 1) {
@@ -1023,8 +1069,8 @@ __global__ __launch_bounds__(BX_T) void box2d_kernel(PostPair one, const PostPai
     __syncthreads();
     if (out_col)
       box_store(P, A, N, (size_t)y * W + c,
-                prefix(b, t + R) - (t - R - 1 >= 0 ? prefix(b, t - R - 1) : 0.0));
-    s -= px(y - R);
+                prefix(b, t + R) - (t - R - 1 >= 0 ? prefix(b, t - R - 1) : 0.0), in);
+    s -= sub;
   }
 }
 
