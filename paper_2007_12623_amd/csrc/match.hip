@@ -470,56 +470,89 @@ __global__ void reset_counter_kernel(int *counter) { *counter = 0; }
 // ---------------------------------------------------------------- preparation
 // Padded image planes and the padding of the statistics planes of one pair
 // (descriptor by value) or of a batch (table, pair from block_pos).
+// A thread fills 4 consecutive plane columns (the strides are multiples of
+// 16, so a group never straddles a row end) with one 8-byte store per L plane
+// and one 4- or 8-byte store for R.
+template <int PREC>
+__device__ __forceinline__ uint16_t enc16(int v, int n) {
+  if constexpr (PREC == P_I16) return (uint16_t)(int16_t)(n * v);
+  else if constexpr (PREC == P_F16) return __builtin_bit_cast(uint16_t, (_Float16)(float)v);
+  else return (uint16_t)(__builtin_bit_cast(uint32_t, (float)v) >> 16);
+}
 template <int PREC, bool B>
 __global__ void prep_planes_kernel(PrepPair one, const PrepPair *many) {
   const BlockPos bp = block_pos();
   const PrepPair &P = B ? many[bp.pair] : one;
   const int y = bp.y;
-  const int c = bp.x * blockDim.x + threadIdx.x;
+  const int c0 = 4 * (bp.x * blockDim.x + threadIdx.x);
   if (y >= P.H) return;
   const int W = P.W;
   const int n = P.chess ? (P.win * P.win + 1) / 2 : P.win * P.win;
   const float qnan = __builtin_nanf("");
-  auto putL = [&](size_t k, int v) {
-    if constexpr (PREC == P_I16) {
-      ((int16_t *)P.Lp)[k] = (int16_t)(n * v);
-      ((int16_t *)P.NLp)[k] = (int16_t)(-n * v);
-    } else if constexpr (PREC == P_F16) {
-      ((_Float16 *)P.Lp)[k] = (_Float16)(float)v;
-      ((_Float16 *)P.NLp)[k] = (_Float16)(float)(-v);
-    } else {
-      ((uint16_t *)P.Lp)[k] = (uint16_t)(__builtin_bit_cast(uint32_t, (float)v) >> 16);
-      ((uint16_t *)P.NLp)[k] = (uint16_t)(__builtin_bit_cast(uint32_t, (float)(-v)) >> 16);
+  const GLOBAL uint8_t *Lrow = gro(P.L) + (size_t)y * P.pitch;
+  const GLOBAL uint8_t *Rrow = gro(P.R) + (size_t)y * P.pitch;
+  if (c0 < P.strideL) {
+    int v[4];
+    bool in[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int x = c0 + j - P.padL;
+      in[j] = x >= 0 && x < W;
+      v[j] = in[j] ? (int)Lrow[x] - 128 : 0;
     }
-  };
-  if (c < P.strideL) {
-    const int x = c - P.padL;
-    const bool in = x >= 0 && x < W;
-    const int v = in ? (int)P.L[(size_t)y * P.pitch + x] - 128 : 0;
-    const size_t k = (size_t)y * P.strideL + c;
+    const size_t k = (size_t)y * P.strideL + c0;
+    // mask: bit j keeps column j (all, or one chessboard colour)
+    auto put = [&](size_t kk, int keep) {
+      uint64_t a = 0, b = 0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int vj = (keep >> j) & 1 ? v[j] : 0;
+        a |= (uint64_t)enc16<PREC>(vj, n) << (16 * j);
+        b |= (uint64_t)enc16<PREC>(-vj, n) << (16 * j);
+      }
+      *(GLOBAL uint64_t *)((GLOBAL uint16_t *)P.Lp + kk) = a;
+      *(GLOBAL uint64_t *)((GLOBAL uint16_t *)P.NLp + kk) = b;
+    };
     if (!P.chess) {
-      putL(k, v);
+      put(k, 15);
     } else {
       // colour copies: (x + y) even in the first, odd in the second
-      const bool even = ((x + y) & 1) == 0;
-      putL(k, even ? v : 0);
-      putL(k + (size_t)P.strideL * P.H, even ? 0 : v);
+      const int even = ((c0 - P.padL + y) & 1) == 0 ? 0x5 : 0xA;
+      put(k, even);
+      put(k + (size_t)P.strideL * P.H, even ^ 0xF);
     }
-    if (!in) { P.negSL[k] = 0; P.invL[k] = qnan; }
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (!in[j]) {
+        P.negSL[k + j] = 0;
+        P.invL[k + j] = qnan;
+      }
   }
-  if (c < P.strideR) {
-    const int x = c - P.padR;
-    const bool in = x >= 0 && x < W;
-    const int v = in ? (int)P.R[(size_t)y * P.pitch + x] : 0;
-    const size_t k = (size_t)y * P.strideR + c;
-    if constexpr (PREC == P_I16) {
-      ((uint8_t *)P.Rp)[k] = (uint8_t)v;
-    } else if constexpr (PREC == P_F16) {
-      ((_Float16 *)P.Rp)[k] = (_Float16)(float)v;
-    } else {
-      ((uint16_t *)P.Rp)[k] = (uint16_t)(__builtin_bit_cast(uint32_t, (float)v) >> 16);
+  if (c0 < P.strideR) {
+    int v[4];
+    bool in[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int x = c0 + j - P.padR;
+      in[j] = x >= 0 && x < W;
+      v[j] = in[j] ? (int)Rrow[x] : 0;
     }
-    if (!in) { P.SRp[k] = 0; P.invR[k] = qnan; }
+    const size_t k = (size_t)y * P.strideR + c0;
+    if constexpr (PREC == P_I16) {
+      *(GLOBAL uint32_t *)((GLOBAL uint8_t *)P.Rp + k) =
+          (uint32_t)v[0] | ((uint32_t)v[1] << 8) | ((uint32_t)v[2] << 16) | ((uint32_t)v[3] << 24);
+    } else {
+      uint64_t a = 0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) a |= (uint64_t)enc16<PREC>(v[j], 1) << (16 * j);
+      *(GLOBAL uint64_t *)((GLOBAL uint16_t *)P.Rp + k) = a;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (!in[j]) {
+        P.SRp[k + j] = 0;
+        P.invR[k + j] = qnan;
+      }
   }
 }
 
@@ -528,37 +561,14 @@ __global__ void prep_planes_kernel(PrepPair one, const PrepPair *many) {
 // image (dense and padded planes), 1: right image, 2: dense planes only.
 // A block of WS_T threads owns WS_T columns; each thread keeps the vertical
 // window sums of its column down a segment of WS_SY rows and the horizontal
-// sums are differences of a block prefix sum (wave scans plus wave totals in
-// LDS).  Output columns of a block are WS_T - 2 WS_HMAX wide for every window.
+// sums are differences of a block prefix sum (wave scans and wave totals in
+// LDS, one barrier per row).  Output columns of a block are WS_T - 2 WS_HMAX
+// wide for every window.
 // CH (chessboard window): a column keeps separate sums of its cells with
 // x + y even and odd; a pixel takes the prefix sums of its own colour, since
 // the cells u + v even around (x, y) are exactly those of the colour of
 // (x, y).
 constexpr int WS_T = 256, WS_SY = 16, WS_HMAX = 7, WS_NOUT = WS_T - 2 * WS_HMAX;
-
-template <int N>
-__device__ __forceinline__ void block_prefix(int (&a)[N], int (*wt)[4]) {
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    int u[N];
-#pragma unroll
-    for (int i = 0; i < N; ++i) u[i] = __shfl_up(a[i], o, 64);
-    if (lane >= o) {
-#pragma unroll
-      for (int i = 0; i < N; ++i) a[i] += u[i];
-    }
-  }
-  if (lane == 63) {
-#pragma unroll
-    for (int i = 0; i < N; ++i) wt[i][wave] = a[i];
-  }
-  __syncthreads();
-  for (int w = 0; w < wave; ++w) {
-#pragma unroll
-    for (int i = 0; i < N; ++i) a[i] += wt[i][w];
-  }
-}
 
 template <bool B, bool CH>
 __global__ __launch_bounds__(WS_T) void window_stats_kernel(PrepPair one, const PrepPair *many,
@@ -595,21 +605,39 @@ __global__ __launch_bounds__(WS_T) void window_stats_kernel(PrepPair one, const 
   const bool out_col = c >= xo && c < xo + WS_NOUT && c < W;  // then h <= t < WS_T - h
   const int y1 = min(y0 + WS_SY, H);
   const int n = CH ? (win * win + 1) / 2 : win * win;
+  const int lane = t & (WV - 1), wave = t / WV;
+  // block prefix at column index i from the stored wave scans and totals
+  auto prefix = [&](int b, int q, int i) -> int {
+    int v = pf[b][q][i];
+    for (int w = 0; w < i / WV; ++w) v += wt[b][q][w];
+    return v;
+  };
   for (int y = y0; y < y1; ++y) {
     const int b = y & 1;
     step(y + h, 1);
+    // wave scans and wave totals to LDS, one barrier per row
     int pv[NV];
 #pragma unroll
     for (int i = 0; i < NV; ++i) pv[i] = acc[i];
-    block_prefix<NV>(pv, wt[b]);
 #pragma unroll
-    for (int i = 0; i < NV; ++i) pf[b][i][t] = pv[i];
+    for (int o = 1; o < WV; o <<= 1) {
+#pragma unroll
+      for (int i = 0; i < NV; ++i) {
+        const int u = __shfl_up(pv[i], o, WV);
+        if (lane >= o) pv[i] += u;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      pf[b][i][t] = pv[i];
+      if (lane == WV - 1) wt[b][i][wave] = pv[i];
+    }
     __syncthreads();
     if (out_col) {
       const int x = c;
       const int q = CH ? 2 * ((x + y) & 1) : 0;
-      int S = pf[b][q][t + h] - (t - h - 1 >= 0 ? pf[b][q][t - h - 1] : 0);
-      int SS = pf[b][q + 1][t + h] - (t - h - 1 >= 0 ? pf[b][q + 1][t - h - 1] : 0);
+      int S = prefix(b, q, t + h) - (t - h - 1 >= 0 ? prefix(b, q, t - h - 1) : 0);
+      int SS = prefix(b, q + 1, t + h) - (t - h - 1 >= 0 ? prefix(b, q + 1, t - h - 1) : 0);
       const bool inside = x >= h && x <= W - 1 - h && y >= h && y <= H - 1 - h;
       float iv = __builtin_nanf("");
       if (!inside) {
@@ -754,7 +782,7 @@ int match_persistent_occupancy(int win, int prec, size_t lds) {
 
 hipError_t launch_prep(const PrepPair &one, const PrepPair *many, int npairs, int maxH,
                        int maxCols, int maxW, int prec, hipStream_t s) {
-  const dim3 grid(ceil_div(maxCols, 256), maxH, npairs);
+  const dim3 grid(ceil_div(maxCols, 4 * 256), maxH, npairs);
 #define PP(pr)                                                                                \
   do {                                                                                        \
     if (many) hipLaunchKernelGGL((prep_planes_kernel<pr, true>), grid, dim3(256), 0, s, one, many); \

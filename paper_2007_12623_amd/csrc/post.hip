@@ -157,6 +157,23 @@ __device__ __forceinline__ void stage_rows(uint8_t (*Ls)[SP_LROW], uint8_t (*Rs)
     const int misr = (int)(((uintptr_t)Rg + (uintptr_t)(row + rx0)) & 3);
     const int nl = (LW + 3) >> 2, nr = (RW + 3) >> 2;
     const long long al = row + lx0 - misl, ar = row + rx0 - misr;
+    // dwords 0 .. nl (nr) of both ranges inside the buffer: plain loads with
+    // 32-bit offsets from a uniform base (every row but the image's first
+    // and last ones, at most)
+    const bool fast = al >= 0 && ar >= 0 && al + 4LL * (nl + 1) <= span && ar + 4LL * (nr + 1) <= span;
+    if (fast) {
+      const GLOBAL uint32_t *gl = (const GLOBAL uint32_t *)(Lg + al);
+      const GLOBAL uint32_t *gr = (const GLOBAL uint32_t *)(Rg + ar);
+      for (int i = tid; i < nl + nr; i += nthreads) {
+        const bool isl = i < nl;
+        const int j = isl ? i : i - nl;
+        const GLOBAL uint32_t *g = isl ? gl : gr;
+        const uint32_t v = __builtin_amdgcn_alignbyte(g[j + 1], g[j], isl ? misl : misr);
+        if (isl) ((uint32_t *)Ls[r])[j] = v;
+        else ((uint32_t *)Rs[r])[j] = v;
+      }
+      continue;
+    }
     for (int i = tid; i < nl + nr; i += nthreads) {
       const bool isl = i < nl;
       const int j = isl ? i : i - nl;
@@ -312,6 +329,9 @@ __global__ __launch_bounds__(SPB_T) void subpixel_kernel(PostPair one, const Pos
     }
     const long long sl = P.SL[k];
     const long long varL = n * (long long)P.SSL[k] - sl * sl;
+    // z = num / sqrt(varN_L varN_R) as num * rsqrt(varN_L) * rsqrt(varN_R):
+    // within a few ulp of the quotient, without the FP64 division
+    const double rl = rsqrt((double)varL);
     const int slr[3] = {sm, s0, sp};
     double z[3];
     for (int q = 0; q < 3; ++q) {
@@ -324,7 +344,7 @@ __global__ __launch_bounds__(SPB_T) void subpixel_kernel(PostPair one, const Pos
       const long long varR = n * (long long)P.SSR[kr] - sr * sr;
       if (varR <= 0) continue;
       const long long num = n * (long long)slr[q] - sl * sr;
-      z[q] = (double)num / sqrt((double)varL * (double)varR);
+      z[q] = (double)num * rl * rsqrt((double)varR);
     }
     if (P.zbest) P.zbest[k] = z[1];
     if (P.zm) P.zm[k] = z[0];
@@ -876,6 +896,7 @@ __device__ __forceinline__ double hc_s_at(const PostPair &P, size_t k, uint8_t m
 enum { BOX_IN_MASK = -1, BOX_IN_S = -2 };
 struct BoxArgs {
   int R, in, out, mode, src, osrc, use_delta;
+  int sy;  // rows per block of the fused pass
   double alpha;
 };
 
@@ -1010,14 +1031,14 @@ __device__ __forceinline__ void box_store(const PostPair &P, const BoxArgs &A, s
 // 2-D box sum over the (2R+1)^2 window of the pass's input (clipped at the
 // image border) in one pass, written through box_store.  A block of BX_T
 // threads owns BX_T columns, of which the middle BX_T - 2R are output, and a
-// segment of BX_SY rows: each thread keeps the vertical window sum of its
+// segment of A.sy rows: each thread keeps the vertical window sum of its
 // column in a register and slides it down the segment.  Per row the
 // horizontal sums are differences of the block's prefix sum, with one block
 // barrier: every wave stores its own inclusive scan and its total in LDS,
 // and a thread forms the prefix at the two window ends from the scan value
 // there plus the totals of the waves before it.  The input plane must
 // differ from every plane the output stage writes.
-constexpr int BX_T = 256, BX_SY = 32, BX_RMAX = 96;
+constexpr int BX_T = 256, BX_RMAX = 96;
 template <bool B>
 __global__ __launch_bounds__(BX_T) void box2d_kernel(PostPair one, const PostPair *__restrict__ many,
                                                      BoxArgs A) {
@@ -1026,7 +1047,7 @@ __global__ __launch_bounds__(BX_T) void box2d_kernel(PostPair one, const PostPai
   __shared__ double wt[2][BX_T / WV];
   const int H = P.H, W = P.W, R = A.R;
   const int nout = BX_T - 2 * R;
-  const int xo = bp.x * nout, y0 = bp.y * BX_SY;
+  const int xo = bp.x * nout, y0 = bp.y * A.sy;
   if (xo >= W || y0 >= H) return;  // uniform per block
   const size_t N = (size_t)W * H;
   const int t = threadIdx.x, lane = t & (WV - 1), wave = t / WV, c = xo - R + t;
@@ -1044,20 +1065,23 @@ __global__ __launch_bounds__(BX_T) void box2d_kernel(PostPair one, const PostPai
     for (int w = 0; w < i / WV; ++w) v += wt[b][w];
     return v;
   };
-  const int y1 = min(y0 + BX_SY, H);
-  // the next row's inputs are loaded one row ahead
-  double add_n = px(y0 + R), sub_n = px(y0 - R);
-  BoxStoreIn in_n = out_col ? box_store_in(P, A, N, (size_t)y0 * W + c) : BoxStoreIn{};
-  for (int y = y0; y < y1; ++y) {
+  const int y1 = min(y0 + A.sy, H);
+  // a row's inputs (entering and leaving rows, output-stage operands) are
+  // loaded two rows ahead
+  struct RowIn {
+    double add, sub;
+    BoxStoreIn st;
+  };
+  auto fetch = [&](int y) -> RowIn {
+    RowIn q;
+    q.add = px(y + R);
+    q.sub = px(y - R);
+    q.st = out_col ? box_store_in(P, A, N, (size_t)y * W + c) : BoxStoreIn{};
+    return q;
+  };
+  auto process = [&](int y, const RowIn &q) {
     const int b = y & 1;
-    s += add_n;
-    const double sub = sub_n;
-    const BoxStoreIn in = in_n;
-    if (y + 1 < y1) {
-      add_n = px(y + 1 + R);
-      sub_n = px(y + 1 - R);
-      if (out_col) in_n = box_store_in(P, A, N, (size_t)(y + 1) * W + c);
-    }
+    s += q.add;
     double p = s;
 #pragma unroll
     for (int o = 1; o < WV; o <<= 1) {
@@ -1069,8 +1093,19 @@ __global__ __launch_bounds__(BX_T) void box2d_kernel(PostPair one, const PostPai
     __syncthreads();
     if (out_col)
       box_store(P, A, N, (size_t)y * W + c,
-                prefix(b, t + R) - (t - R - 1 >= 0 ? prefix(b, t - R - 1) : 0.0), in);
-    s -= sub;
+                prefix(b, t + R) - (t - R - 1 >= 0 ? prefix(b, t - R - 1) : 0.0), q.st);
+    s -= q.sub;
+  };
+  RowIn q0 = fetch(y0), q1 = y0 + 1 < y1 ? fetch(y0 + 1) : RowIn{};
+  for (int y = y0; y < y1; y += 2) {  // y1 - y0 is uniform: every thread takes the same rows
+    const RowIn c0 = q0;
+    if (y + 2 < y1) q0 = fetch(y + 2);
+    process(y, c0);
+    if (y + 1 < y1) {
+      const RowIn c1 = q1;
+      if (y + 3 < y1) q1 = fetch(y + 3);
+      process(y + 1, c1);
+    }
   }
 }
 
@@ -1343,10 +1378,15 @@ hipError_t post_fill(const PostLaunch &L, int radial_r, int min_lines, int disk_
 // box_store's mode: one fused pass for R <= BX_RMAX, else a column pass into
 // F_TMP and a row pass (the input and the written planes must then differ
 // from F_TMP).
-static void box2d(const PostLaunch &L, const BoxArgs &A) {
+static void box2d(const PostLaunch &L, BoxArgs A) {
   if (A.R <= BX_RMAX) {
-    const int nout = BX_T - 2 * A.R;
-    LAUNCH(box2d_kernel, dim3(ceil_div(L.maxW, nout), ceil_div(L.maxH, BX_SY), L.npairs), dim3(BX_T), A);
+    // 32-row segments, shorter when that leaves fewer than about 1024
+    // blocks (a single pair): the seed of 2R rows per segment is the price
+    // of more blocks in flight
+    const int nout = BX_T - 2 * A.R, nx = ceil_div(L.maxW, nout);
+    A.sy = 32;
+    while (A.sy > 8 && (long long)nx * ceil_div(L.maxH, A.sy) * L.npairs < 1024) A.sy /= 2;
+    LAUNCH(box2d_kernel, dim3(nx, ceil_div(L.maxH, A.sy), L.npairs), dim3(BX_T), A);
     return;
   }
   const int seg = 32;
@@ -1386,6 +1426,7 @@ hipError_t post_hc(const PostLaunch &L, int src, int R, int K, float alpha, int 
     A.src = src;
     A.osrc = ocur;
     A.use_delta = use_delta;
+    A.sy = 32;
     A.alpha = (double)alpha;
     return A;
   };
