@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libstereo_mi355x.so")
-SOURCES = ["match.hip", "post.hip", "refine.hip", "api.hip"]
+SOURCES = ["match.hip", "prep.hip", "post.hip", "refine.hip", "api.hip"]
 ARCH = "gfx950"
 
 

@@ -1,0 +1,262 @@
+// Per-pair preparation for the matcher and the sub-pixel stages (Section
+// II-A: ZNCC needs the window means and deviations of both images): the
+// padded image planes the matcher streams, and the exact window sums with
+// the inverse deviations, for the square or the chessboard window.
+#include "common.h"
+
+namespace st {
+
+// ---------------------------------------------------------------- preparation
+// Padded image planes and the padding of the statistics planes of one pair
+// (descriptor by value) or of a batch (table, pair from block_pos).
+// A thread fills 4 consecutive plane columns (the strides are multiples of
+// 16, so a group never straddles a row end) with one 8-byte store per L plane
+// and one 4- or 8-byte store for R.
+template <int PREC>
+__device__ __forceinline__ uint16_t enc16(int v, int n) {
+  if constexpr (PREC == P_I16) return (uint16_t)(int16_t)(n * v);
+  else if constexpr (PREC == P_F16) return __builtin_bit_cast(uint16_t, (_Float16)(float)v);
+  else return (uint16_t)(__builtin_bit_cast(uint32_t, (float)v) >> 16);
+}
+template <int PREC, bool B>
+__global__ void prep_planes_kernel(PrepPair one, const PrepPair *many) {
+  const BlockPos bp = block_pos();
+  const PrepPair &P = B ? many[bp.pair] : one;
+  const int y = bp.y;
+  const int c0 = 4 * (bp.x * blockDim.x + threadIdx.x);
+  if (y >= P.H) return;
+  const int W = P.W;
+  const int n = P.chess ? (P.win * P.win + 1) / 2 : P.win * P.win;
+  const float qnan = __builtin_nanf("");
+  const GLOBAL uint8_t *Lrow = gro(P.L) + (size_t)y * P.pitch;
+  const GLOBAL uint8_t *Rrow = gro(P.R) + (size_t)y * P.pitch;
+  if (c0 < P.strideL) {
+    int v[4];
+    bool in[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int x = c0 + j - P.padL;
+      in[j] = x >= 0 && x < W;
+      v[j] = in[j] ? (int)Lrow[x] - 128 : 0;
+    }
+    const size_t k = (size_t)y * P.strideL + c0;
+    // mask: bit j keeps column j (all, or one chessboard colour)
+    auto put = [&](size_t kk, int keep) {
+      uint64_t a = 0, b = 0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int vj = (keep >> j) & 1 ? v[j] : 0;
+        a |= (uint64_t)enc16<PREC>(vj, n) << (16 * j);
+        b |= (uint64_t)enc16<PREC>(-vj, n) << (16 * j);
+      }
+      *(GLOBAL uint64_t *)((GLOBAL uint16_t *)P.Lp + kk) = a;
+      *(GLOBAL uint64_t *)((GLOBAL uint16_t *)P.NLp + kk) = b;
+    };
+    if (!P.chess) {
+      put(k, 15);
+    } else {
+      // colour copies: (x + y) even in the first, odd in the second
+      const int even = ((c0 - P.padL + y) & 1) == 0 ? 0x5 : 0xA;
+      put(k, even);
+      put(k + (size_t)P.strideL * P.H, even ^ 0xF);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (!in[j]) {
+        P.negSL[k + j] = 0;
+        P.invL[k + j] = qnan;
+      }
+  }
+  if (c0 < P.strideR) {
+    int v[4];
+    bool in[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int x = c0 + j - P.padR;
+      in[j] = x >= 0 && x < W;
+      v[j] = in[j] ? (int)Rrow[x] : 0;
+    }
+    const size_t k = (size_t)y * P.strideR + c0;
+    if constexpr (PREC == P_I16) {
+      *(GLOBAL uint32_t *)((GLOBAL uint8_t *)P.Rp + k) =
+          (uint32_t)v[0] | ((uint32_t)v[1] << 8) | ((uint32_t)v[2] << 16) | ((uint32_t)v[3] << 24);
+    } else {
+      uint64_t a = 0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) a |= (uint64_t)enc16<PREC>(v[j], 1) << (16 * j);
+      *(GLOBAL uint64_t *)((GLOBAL uint16_t *)P.Rp + k) = a;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (!in[j]) {
+        P.SRp[k + j] = 0;
+        P.invR[k + j] = qnan;
+      }
+  }
+}
+
+// Window sums S = sum I, SS = sum I^2 and 1/sqrt(n SS - S^2) of every pixel
+// whose window lies inside the image (0 / NaN elsewhere).  side 0: left
+// image (dense and padded planes), 1: right image, 2: dense planes only.
+// A block of WS_T threads owns WS_T columns; each thread keeps the vertical
+// window sums of its column down a segment of WS_SY rows and the horizontal
+// sums are differences of a block prefix sum (wave scans plus wave totals in
+// LDS).  Output columns of a block are WS_T - 2 WS_HMAX wide for every window.
+// CH (chessboard window): a column keeps separate sums of its cells with
+// x + y even and odd; a pixel takes the prefix sums of its own colour, since
+// the cells u + v even around (x, y) are exactly those of the colour of
+// (x, y).
+constexpr int WS_T = 256, WS_SY = 16, WS_HMAX = 7, WS_NOUT = WS_T - 2 * WS_HMAX;
+
+template <int N>
+__device__ __forceinline__ void block_prefix(int (&a)[N], int (*wt)[4]) {
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    int u[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) u[i] = __shfl_up(a[i], o, 64);
+    if (lane >= o) {
+#pragma unroll
+      for (int i = 0; i < N; ++i) a[i] += u[i];
+    }
+  }
+  if (lane == 63) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) wt[i][wave] = a[i];
+  }
+  __syncthreads();
+  for (int w = 0; w < wave; ++w) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) a[i] += wt[i][w];
+  }
+}
+
+template <bool B, bool CH>
+__global__ __launch_bounds__(WS_T) void window_stats_kernel(PrepPair one, const PrepPair *many,
+                                                            int side) {
+  const BlockPos bp = block_pos();
+  const PrepPair &P = B ? many[bp.pair] : one;
+  constexpr int NV = CH ? 4 : 2;  // (S, SS) of each colour
+  __shared__ int pf[2][NV][WS_T], wt[2][NV][4];
+  const int H = P.H, W = P.W, win = P.win, h = win / 2;
+  const int xo = bp.x * WS_NOUT, y0 = bp.y * WS_SY;
+  if (xo >= W || y0 >= H) return;  // uniform per block
+  const GLOBAL uint8_t *img = gro(side == 1 ? P.R : P.L);
+  const int t = threadIdx.x, c = xo - h + t;
+  const bool cin = c >= 0 && c < W;
+  auto px = [&](int r) -> int { return (cin && r >= 0 && r < H) ? (int)img[(size_t)r * P.pitch + c] : 0; };
+  int acc[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) acc[i] = 0;
+  // add (sgn = 1) or remove (sgn = -1) row r of the column
+  auto step = [&](int r, int sgn) {
+    const int v = sgn * px(r), vv = v * (sgn * v);
+    if constexpr (CH) {
+      const bool odd = ((c + r) & 1) != 0;
+      acc[0] += odd ? 0 : v;
+      acc[1] += odd ? 0 : vv;
+      acc[2] += odd ? v : 0;
+      acc[3] += odd ? vv : 0;
+    } else {
+      acc[0] += v;
+      acc[1] += vv;
+    }
+  };
+  for (int r = y0 - h; r < y0 + h; ++r) step(r, 1);
+  const bool out_col = c >= xo && c < xo + WS_NOUT && c < W;  // then h <= t < WS_T - h
+  const int y1 = min(y0 + WS_SY, H);
+  const int n = CH ? (win * win + 1) / 2 : win * win;
+  for (int y = y0; y < y1; ++y) {
+    const int b = y & 1;
+    step(y + h, 1);
+    int pv[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) pv[i] = acc[i];
+    block_prefix<NV>(pv, wt[b]);
+#pragma unroll
+    for (int i = 0; i < NV; ++i) pf[b][i][t] = pv[i];
+    __syncthreads();
+    if (out_col) {
+      const int x = c;
+      const int q = CH ? 2 * ((x + y) & 1) : 0;
+      int S = pf[b][q][t + h] - (t - h - 1 >= 0 ? pf[b][q][t - h - 1] : 0);
+      int SS = pf[b][q + 1][t + h] - (t - h - 1 >= 0 ? pf[b][q + 1][t - h - 1] : 0);
+      const bool inside = x >= h && x <= W - 1 - h && y >= h && y <= H - 1 - h;
+      float iv = __builtin_nanf("");
+      if (!inside) {
+        S = 0;
+        SS = 0;
+      } else {
+        const long long varN = (long long)n * SS - (long long)S * S;
+        if (varN > 0) iv = (float)(1.0 / sqrt((double)varN));
+      }
+      const size_t k = (size_t)y * W + x;
+      if (side == 1) {
+        P.SR[k] = S;
+        P.SSR[k] = SS;
+        if (P.invRd) P.invRd[k] = iv;
+        const size_t kp = (size_t)y * P.strideR + x + P.padR;
+        P.SRp[kp] = S;
+        P.invR[kp] = iv;
+      } else {
+        P.SL[k] = S;
+        P.SSL[k] = SS;
+        if (P.invLd) P.invLd[k] = iv;
+        if (side == 0) {
+          const size_t kp = (size_t)y * P.strideL + x + P.padL;
+          P.negSL[kp] = 128 * n - S;
+          P.invL[kp] = iv;
+        }
+      }
+    }
+    step(y - h, -1);
+  }
+}
+
+// ---------------------------------------------------------------- host launchers
+hipError_t launch_prep(const PrepPair &one, const PrepPair *many, int npairs, int maxH,
+                       int maxCols, int maxW, int prec, hipStream_t s) {
+  const dim3 grid(ceil_div(maxCols, 4 * 256), maxH, npairs);
+#define PP(pr)                                                                                \
+  do {                                                                                        \
+    if (many) hipLaunchKernelGGL((prep_planes_kernel<pr, true>), grid, dim3(256), 0, s, one, many); \
+    else hipLaunchKernelGGL((prep_planes_kernel<pr, false>), grid, dim3(256), 0, s, one, many);     \
+  } while (0)
+  if (prec == P_I16) PP(P_I16); else if (prec == P_F16) PP(P_F16); else PP(P_BF16);
+#undef PP
+  // the window shape is shared by every pair of a batch (one parameter set)
+  const dim3 gs(ceil_div(maxW, WS_NOUT), ceil_div(maxH, WS_SY), npairs);
+#define WS(b, ch) hipLaunchKernelGGL((window_stats_kernel<b, ch>), gs, dim3(WS_T), 0, s, one, many, side)
+  for (int side = 0; side < 2; ++side) {
+    if (many) {
+      if (one.chess) WS(true, true); else WS(true, false);
+    } else {
+      if (one.chess) WS(false, true); else WS(false, false);
+    }
+  }
+#undef WS
+  return hipGetLastError();
+}
+
+hipError_t launch_window_stats_dense(const uint8_t *img, int H, int W, int pitch, int win,
+                                     int chess, int32_t *S, int32_t *SS, float *inv, hipStream_t s) {
+  PrepPair P = {};
+  P.L = img;
+  P.H = H;
+  P.W = W;
+  P.pitch = pitch;
+  P.win = win;
+  P.chess = chess;
+  P.SL = S;
+  P.SSL = SS;
+  P.invLd = inv;
+  const dim3 gs(ceil_div(W, WS_NOUT), ceil_div(H, WS_SY), 1);
+  if (chess)
+    hipLaunchKernelGGL((window_stats_kernel<false, true>), gs, dim3(WS_T), 0, s, P, (const PrepPair *)nullptr, 2);
+  else
+    hipLaunchKernelGGL((window_stats_kernel<false, false>), gs, dim3(WS_T), 0, s, P, (const PrepPair *)nullptr, 2);
+  return hipGetLastError();
+}
+
+}  // namespace st
