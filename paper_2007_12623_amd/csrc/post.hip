@@ -962,16 +962,18 @@ __global__ void box_v_kernel(PostPair one, const PostPair *__restrict__ many, Bo
 //   mode 3: the same d written as the final disparity (NaN where invalid)
 //           and mask
 //   mode 4: mode 1, and b = a - alpha s - (1 - alpha) s (Eq. 2 of the first
-//           iteration, d_prev = s) -> plane out
-//   mode 5: d as in mode 2, and the next iteration's b = a - alpha s -
-//           (1 - alpha) d (Eq. 2) -> plane out
+//           iteration, d_prev = s) -> plane out, and c = alpha (a - s) ->
+//           plane F_S
+//   mode 5: the next iteration's b = a - alpha s - (1 - alpha) d (Eq. 2)
+//           with d = a - box(b m)/box(m) (Eq. 3), formed as
+//           c + (1 - alpha) box(b m)/box(m) -> plane out
 // (b and a are 0 on invalid pixels, as the masked sums need.)  The inputs
 // the stage reads are gathered first (box_store_in), so that a caller can
 // load them ahead of time.
 struct BoxStoreIn {
   uint8_t mk;
   float cnt;
-  double a, s;
+  double a, s;  // a; s (mode 4) or c (mode 5)
 };
 __device__ __forceinline__ BoxStoreIn box_store_in(const PostPair &P, const BoxArgs &A, size_t N,
                                                    size_t k) {
@@ -983,8 +985,9 @@ __device__ __forceinline__ BoxStoreIn box_store_in(const PostPair &P, const BoxA
   if (A.mode == 0) return q;
   q.mk = gro(P.mb[A.src])[k];
   q.cnt = ((const GLOBAL float *)(gro(P.f) + (size_t)F_CNT * N))[k];
-  if (A.mode == 2 || A.mode == 3 || A.mode == 5) q.a = gro(P.f)[(size_t)F_A * N + k];
-  if (A.mode == 4 || A.mode == 5) {
+  if (A.mode == 2 || A.mode == 3) q.a = gro(P.f)[(size_t)F_A * N + k];
+  if (A.mode == 5) q.s = gro(P.f)[(size_t)F_S * N + k];
+  if (A.mode == 4) {
     // s without a branch on the mask: both loads issue at once
     if (P.s_in) {
       q.s = (double)gro(P.s_in)[k];
@@ -1009,15 +1012,17 @@ __device__ __forceinline__ void box_store(const PostPair &P, const BoxArgs &A, s
     if (A.mode == 4) {
       const double s = mk ? q.s : 0.0;
       P.f[(size_t)A.out * N + k] = mk ? mean - A.alpha * s - (1.0 - A.alpha) * s : 0.0;
+      P.f[(size_t)F_S * N + k] = mk ? A.alpha * (mean - s) : 0.0;
     }
+    return;
+  }
+  if (A.mode == 5) {
+    P.f[(size_t)A.out * N + k] = mk ? q.s + (1.0 - A.alpha) * mean : 0.0;
     return;
   }
   const double d = mk ? q.a - mean : 0.0;
   if (A.mode == 2) {
     P.f[(size_t)F_D * N + k] = d;
-  } else if (A.mode == 5) {
-    const double s = mk ? q.s : 0.0;
-    P.f[(size_t)A.out * N + k] = mk ? q.a - A.alpha * s - (1.0 - A.alpha) * d : 0.0;
   } else {
     P.disparity[k] = mk ? (float)d : __builtin_nanf("");
     if (P.valid_mask) P.valid_mask[k] = mk;
@@ -1434,7 +1439,9 @@ hipError_t post_hc(const PostLaunch &L, int src, int R, int K, float alpha, int 
   if (!research) {
     // a is fixed and s is formed on the fly from the disparities; every b
     // (Eq. 2) is formed in the output stage of the box pass before it,
-    // alternating between the planes F_D and F_IN
+    // alternating between the planes F_D and F_IN; with c = alpha (a - s)
+    // (plane F_S), b_{k+1} = c + (1 - alpha) box(b_k m)/box(m), and only the
+    // last pass forms d = a - box(b m)/box(m)
     box2d(L, args(BOX_IN_S, F_D, 4));  // a = box(s m) / box(m), b_0 -> F_D
     int bin = F_D, bout = F_IN;
     for (int it = 0; it < K; ++it) {
