@@ -167,6 +167,7 @@ st_status stereo_refine_step(st_handle h, float *d, const float *grad_d, const u
  *  "delta" float         parabola offset
  *  "m_lr"  uint8         mask after the left-right check
  *  "o_post" int16, "m_post" uint8   disparity and mask after outlier removal/fills
+ * (integer disparities are -32768 where their mask is 0)
  * ST_EINVAL for an unknown name or when no debug run is held.
  */
 st_status stereo_debug_get(st_handle h, const char *name, void **dev_ptr);
@@ -185,7 +186,9 @@ st_status st_window_stats(st_handle h, const uint8_t *img, int H, int W, int pit
 
 /* ZNCC matching and winner-take-all in both references (Section II-A).
  *  oL, mL : argmax_d z(x, y, d) and 1 if any candidate is valid
- *  oR, mR : for right pixel xr, argmax_d z(xr + d, y, d)
+ *           (oL = -32768 where mL = 0)
+ *  oR, mR : for right pixel xr, argmax_d z(xr + d, y, d) (-32768 where
+ *           mR = 0)
  * Candidates whose windows leave the image or have zero variance are
  * invalid; ties within 2^-18 of each other may resolve to either.
  * precision selects FP32 or FP16/BF16 image and cost storage. */
@@ -213,7 +216,7 @@ st_status st_radial_outlier(st_handle h, const int16_t *o, const uint8_t *m_in, 
                             int r, float thresh, uint8_t *m_out, void *stream);
 
 /* Hole filling (Section II-B): radial then disk; filled pixels get code 2.
- * o_out/m_out must not alias the inputs. */
+ * o_out/m_out must not alias the inputs; o_out is -32768 where m_out = 0. */
 st_status st_fill(st_handle h, const int16_t *o_in, const uint8_t *m_in, int H, int W,
                   int radial_r, int min_lines, int disk_r, float min_frac, int16_t *o_out,
                   uint8_t *m_out, void *stream);

@@ -721,17 +721,20 @@ st_status st_radial_outlier(st_handle h, const int16_t *o, const uint8_t *m_in, 
   SETDEV(h);
   const size_t N = (size_t)H * W;
   Carve c;
-  const size_t ot = c.take(2 * N), pt = c.take(4 * N), tot = c.take(0);
+  const size_t ot = c.take(2 * N), it = c.take(2 * N), pt = c.take(4 * N), tot = c.take(0);
   HIPCK(grow(h, h->ws, tot, false) == ST_OK ? hipSuccess : hipErrorOutOfMemory);
+  hipStream_t s = (hipStream_t)stream;
+  // the scans read validity from the disparity: O_NONE where m_in == 0
+  HIPCK(launch_mark_invalid(o, m_in, at<int16_t>(h->ws.p, it), N, s));
   PostPair Q{};
   Q.H = H;
   Q.W = W;
-  Q.ob[1] = const_cast<int16_t *>(o);
+  Q.ob[1] = at<int16_t>(h->ws.p, it);
   Q.mb[1] = const_cast<uint8_t *>(m_in);
   Q.ob[2] = at<int16_t>(h->ws.p, ot);
   Q.pass = at<uint8_t>(h->ws.p, pt);
   Q.mb[2] = m_out;
-  HIPCK(post_outlier(single_launch(Q, (hipStream_t)stream), r, thresh, 1, 2));
+  HIPCK(post_outlier(single_launch(Q, s), r, thresh, 1, 2));
   return ST_OK;
 }
 
@@ -749,12 +752,16 @@ st_status st_fill(st_handle h, const int16_t *o_in, const uint8_t *m_in, int H, 
   const size_t N = (size_t)H * W;
   Carve c;
   const size_t ot = c.take(2 * N), mt = c.take(N), pc = c.take(4 * (size_t)H * (W + 1)),
-               ps = c.take(4 * (size_t)H * (W + 1)), ht = c.take(32 * N), tot = c.take(0);
+               ps = c.take(4 * (size_t)H * (W + 1)), ht = c.take(32 * N), it = c.take(2 * N),
+               tot = c.take(0);
   HIPCK(grow(h, h->ws, tot, false) == ST_OK ? hipSuccess : hipErrorOutOfMemory);
+  hipStream_t s = (hipStream_t)stream;
+  // the scans read validity from the disparity: O_NONE where m_in == 0
+  HIPCK(launch_mark_invalid(o_in, m_in, at<int16_t>(h->ws.p, it), N, s));
   PostPair Q{};
   Q.H = H;
   Q.W = W;
-  Q.ob[0] = const_cast<int16_t *>(o_in);
+  Q.ob[0] = at<int16_t>(h->ws.p, it);
   Q.mb[0] = const_cast<uint8_t *>(m_in);
   Q.ob[1] = at<int16_t>(h->ws.p, ot);
   Q.mb[1] = at<uint8_t>(h->ws.p, mt);
@@ -763,7 +770,7 @@ st_status st_fill(st_handle h, const int16_t *o_in, const uint8_t *m_in, int H, 
   Q.pc = at<int32_t>(h->ws.p, pc);
   Q.ps = at<int32_t>(h->ws.p, ps);
   Q.hits = at<uint32_t>(h->ws.p, ht);
-  HIPCK(post_fill(single_launch(Q, (hipStream_t)stream), radial_r, min_lines, disk_r, min_frac, 0, 1, 2));
+  HIPCK(post_fill(single_launch(Q, s), radial_r, min_lines, disk_r, min_frac, 0, 1, 2));
   return ST_OK;
 }
 

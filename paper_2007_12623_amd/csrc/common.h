@@ -23,6 +23,12 @@ constexpr int NWAVE = 4;      // waves of a matcher workgroup
 
 enum Prec { P_I16 = 0, P_F16 = 1, P_BF16 = 2 };
 
+// Disparity stored at pixels without a valid one in the integer disparity
+// maps of the post-processing (decode, left-right check, outlier removal,
+// fills): the radial scans then tell validity from the disparity alone and
+// read one 2-byte value per step.  Disparities lie within +-4096.
+constexpr int16_t O_NONE = -32768;
+
 // Geometry and device pointers of one prepared pair, as the matcher sees it.
 // Planes are padded row-major arrays: image column x lives at index x + pad.
 // With the chessboard window the L planes come twice, lplane bytes apart:
@@ -67,7 +73,7 @@ struct PostPair {
   uint8_t *mb[3];                      // masks, same roles
   double *zbest, *zm, *zp;             // may be null
   float *delta;
-  int32_t *pc, *ps;                    // row prefix sums, H x (W+1)
+  int32_t *pc, *ps;                    // row prefix sums (count, sum), H x (W+1)
   uint32_t *hits;                      // 8 planes: nearest valid pixel per direction
   uint8_t *pass;                       // 4 planes: outlier runs per line type
   double *f;                           // 6 smoothing planes of H x W
@@ -152,6 +158,10 @@ size_t match_lds_bytes(const MatchPair &P);  // key tiles of one workgroup
 hipError_t launch_window_stats_dense(const uint8_t *img, int H, int W, int pitch, int win,
                                      int chess, int32_t *S, int32_t *SS, float *inv, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, int N, uint32_t v, hipStream_t s);
+// out = m ? o : O_NONE over N pixels (a caller's map in the form the radial
+// scans read)
+hipError_t launch_mark_invalid(const int16_t *o, const uint8_t *m, int16_t *out, size_t N,
+                               hipStream_t s);
 struct Mat4 {
   double q[16];
 };

@@ -62,9 +62,9 @@ __global__ void decode_kernel(PostPair one, const PostPair *__restrict__ many) {
   (void)H;
   for_pixels(P, bp, [&](int x, int y, size_t k) {
     const uint32_t a = P.keyL[k], b = P.keyR[k];
-    P.ob[0][k] = a ? (int16_t)(P.dmin + 255 - (int)(a & 255u)) : 0;
+    P.ob[0][k] = a ? (int16_t)(P.dmin + 255 - (int)(a & 255u)) : O_NONE;
     P.mb[0][k] = a ? 1 : 0;
-    P.oR[k] = b ? (int16_t)(P.dmin + 255 - (int)(b & 255u)) : 0;
+    P.oR[k] = b ? (int16_t)(P.dmin + 255 - (int)(b & 255u)) : O_NONE;
     P.mR[k] = b ? 1 : 0;
     P.keyL[k] = 0;
     P.keyR[k] = 0;
@@ -74,6 +74,12 @@ __global__ void decode_kernel(PostPair one, const PostPair *__restrict__ many) {
 __global__ void fill_u32_kernel(uint32_t *p, int N, uint32_t v) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k < N) p[k] = v;
+}
+
+__global__ void mark_invalid_kernel(const int16_t *__restrict__ o, const uint8_t *__restrict__ m,
+                                    int16_t *__restrict__ out, size_t N) {
+  const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < N) out[k] = m[k] ? o[k] : O_NONE;
 }
 
 // ---------------------------------------------------------------- sub-pixel
@@ -381,7 +387,7 @@ __global__ void lr_check_kernel(PostPair one, const PostPair *__restrict__ many,
         if (P.mR[kr] && (diff < 0 ? -diff : diff) <= tol) keep = 1;
       }
     }
-    P.ob[dst][k] = oL[k];
+    P.ob[dst][k] = keep ? oL[k] : O_NONE;
     P.mb[dst][k] = keep;
   });
 }
@@ -427,15 +433,11 @@ __device__ __forceinline__ bool step_holds(int o_near, int o_far, bool m_far, fl
 // is df >= r, bit 1 db >= r.  The backward bits of the first sweep wait in a
 // register mask, one bit per block, when W <= 64 * 64; wider rows keep them
 // in pass itself.
-template <bool B>
-__global__ __launch_bounds__(256) void outlier_rows_kernel(PostPair one, const PostPair *__restrict__ many, int r,
-                                                          float thresh, int src) {
-  PAIR;
+__device__ __forceinline__ void outlier_rows(const PostPair &P, int bx, int r, float thresh, int src) {
   const int H = P.H, W = P.W;
-  const int lane = threadIdx.x & 63, y = bp.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63, y = bx * 4 + (threadIdx.x >> 6);
   if (y >= H) return;  // whole wave
-  const GLOBAL int16_t *o = gro(P.ob[src]) + (size_t)y * W;
-  const GLOBAL uint8_t *m = gro(P.mb[src]) + (size_t)y * W;
+  const GLOBAL int16_t *o = gro(P.ob[src]) + (size_t)y * W;  // O_NONE where invalid
   GLOBAL uint8_t *pass = grw(P.pass) + (size_t)y * W;
   const int nb = ceil_div(W, 64);
   const bool inreg = nb <= 64;
@@ -444,7 +446,7 @@ __global__ __launch_bounds__(256) void outlier_rows_kernel(PostPair one, const P
   for (int b = 0; b < nb; ++b) {
     const int x = 64 * b + lane;
     const bool in = x < W;
-    const int ov = in ? o[x] : 0, mv = in && m[x] ? 1 : 0;
+    const int ov = in ? o[x] : O_NONE, mv = ov != O_NONE ? 1 : 0;
     int on = __shfl_up(ov, 1, 64), mn = __shfl_up(mv, 1, 64);
     if (lane == 0) {
       on = co;
@@ -468,7 +470,7 @@ __global__ __launch_bounds__(256) void outlier_rows_kernel(PostPair one, const P
   for (int b = nb - 1; b >= 0; --b) {
     const int x = 64 * b + lane;
     const bool in = x < W;
-    const int ov = in ? o[x] : 0, mv = in && m[x] ? 1 : 0;
+    const int ov = in ? o[x] : O_NONE, mv = ov != O_NONE ? 1 : 0;
     int on = __shfl_down(ov, 1, 64), mn = __shfl_down(mv, 1, 64);
     if (lane == 63) {
       on = co;
@@ -489,15 +491,11 @@ __global__ __launch_bounds__(256) void outlier_rows_kernel(PostPair one, const P
 
 // Nearest valid pixel along rows for the holes: hits[0] to the right
 // (forward), hits[1] to the left, within R.
-template <bool B>
-__global__ __launch_bounds__(256) void fill_rows_kernel(PostPair one, const PostPair *__restrict__ many, int R,
-                                                       int src) {
-  PAIR;
+__device__ __forceinline__ void fill_rows(const PostPair &P, int bx, int R, int src) {
   const int H = P.H, W = P.W;
-  const int lane = threadIdx.x & 63, y = bp.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63, y = bx * 4 + (threadIdx.x >> 6);
   if (y >= H) return;  // whole wave
-  const GLOBAL int16_t *o = gro(P.ob[src]) + (size_t)y * W;
-  const GLOBAL uint8_t *m = gro(P.mb[src]) + (size_t)y * W;
+  const GLOBAL int16_t *o = gro(P.ob[src]) + (size_t)y * W;  // O_NONE where invalid
   const size_t N = (size_t)W * H;
   GLOBAL uint32_t *hf = grw(P.hits) + (size_t)y * W;
   GLOBAL uint32_t *hb = grw(P.hits) + N + (size_t)y * W;
@@ -510,8 +508,8 @@ __global__ __launch_bounds__(256) void fill_rows_kernel(PostPair one, const Post
   for (int b = 0; b < nb; ++b) {
     const int x = 64 * b + lane;
     const bool in = x < W;
-    const int ov = in ? o[x] : 0;
-    const bool mv = in && m[x];
+    const int ov = in ? o[x] : O_NONE;
+    const bool mv = ov != O_NONE;
     const uint64_t vm = ballot64(mv);
     const uint64_t low = vm & lanes_below(lane);
     const int oq = __shfl(ov, low ? top64(low) : 0, 64);
@@ -525,8 +523,8 @@ __global__ __launch_bounds__(256) void fill_rows_kernel(PostPair one, const Post
   for (int b = nb - 1; b >= 0; --b) {
     const int x = 64 * b + lane;
     const bool in = x < W;
-    const int ov = in ? o[x] : 0;
-    const bool mv = in && m[x];
+    const int ov = in ? o[x] : O_NONE;
+    const bool mv = ov != O_NONE;
     const uint64_t vm = ballot64(mv);
     const uint64_t rest = vm & lanes_above(lane);
     const int oq = __shfl(ov, rest ? ctz64(rest) : 0, 64);
@@ -576,18 +574,14 @@ __device__ __forceinline__ bool vscan_task(int idx, int H, int W, int &t, int &l
 // its own rows, writing results only where a later kernel reads them: pass
 // for valid pixels, hits for holes.  The loops are branch-free so that the
 // loads of an unrolled group issue together.
-template <bool B>
-__global__ void outlier_vscan_kernel(PostPair one, const PostPair *__restrict__ many, int r,
-                                     float thresh, int src) {
-  PAIR;
+__device__ __forceinline__ void outlier_vscan(const PostPair &P, int bx, int r, float thresh, int src) {
   const int H = P.H, W = P.W;
   int t, l, sg;
-  if (!vscan_task(bp.x * blockDim.x + threadIdx.x, H, W, t, l, sg)) return;
+  if (!vscan_task(bx * blockDim.x + threadIdx.x, H, W, t, l, sg)) return;
   const VLine L = vline(t, l, H, W);
   const int a = max(L.ylo, sg * SEG), b = min(L.yhi, sg * SEG + SEG);
   if (a >= b) return;
-  const GLOBAL int16_t *__restrict__ o = gro(P.ob[src]);
-  const GLOBAL uint8_t *__restrict__ m = gro(P.mb[src]);
+  const GLOBAL int16_t *__restrict__ o = gro(P.ob[src]);  // O_NONE where invalid
   GLOBAL uint8_t *__restrict__ pass = grw(P.pass) + (size_t)t * W * H;
   // run = consecutive good steps from y along the scan direction, capped at r
   auto step = [&](int op, int onb, bool vnb, int run) {
@@ -603,13 +597,13 @@ __global__ void outlier_vscan_kernel(PostPair one, const PostPair *__restrict__ 
     const int e = min(L.yhi - 1, b - 1 + r);
     int k = e * L.st + L.c0;
     int on = o[k], run = 0;
-    bool vn = m[k] != 0;
+    bool vn = on != O_NONE;
     int y = e - 1;
     k -= L.st;
 #pragma unroll 8
     for (; y >= b; --y, k -= L.st) {
       const int op = o[k];
-      const bool v = m[k] != 0;
+      const bool v = op != O_NONE;
       run = step(op, on, vn, run);
       on = op;
       vn = v;
@@ -617,7 +611,7 @@ __global__ void outlier_vscan_kernel(PostPair one, const PostPair *__restrict__ 
 #pragma unroll 8
     for (; y >= a; --y, k -= L.st) {
       const int op = o[k];
-      const bool v = m[k] != 0;
+      const bool v = op != O_NONE;
       run = step(op, on, vn, run);
       on = op;
       vn = v;
@@ -628,14 +622,14 @@ __global__ void outlier_vscan_kernel(PostPair one, const PostPair *__restrict__ 
     const int e = max(L.ylo, a - r);
     int k = e * L.st + L.c0;
     int on = o[k], run = 0;
-    bool vn = m[k] != 0;
+    bool vn = on != O_NONE;
     if (e == a && vn) pass[k] = (uint8_t)(fbits & 1u);
     int y = e + 1;
     k += L.st;
 #pragma unroll 8
     for (; y < a; ++y, k += L.st) {
       const int op = o[k];
-      const bool v = m[k] != 0;
+      const bool v = op != O_NONE;
       run = step(op, on, vn, run);
       on = op;
       vn = v;
@@ -643,7 +637,7 @@ __global__ void outlier_vscan_kernel(PostPair one, const PostPair *__restrict__ 
 #pragma unroll 8
     for (; y < b; ++y, k += L.st) {
       const int op = o[k];
-      const bool v = m[k] != 0;
+      const bool v = op != O_NONE;
       run = step(op, on, vn, run);
       on = op;
       vn = v;
@@ -652,17 +646,14 @@ __global__ void outlier_vscan_kernel(PostPair one, const PostPair *__restrict__ 
   }
 }
 
-template <bool B>
-__global__ void fill_vscan_kernel(PostPair one, const PostPair *__restrict__ many, int R, int src) {
-  PAIR;
+__device__ __forceinline__ void fill_vscan(const PostPair &P, int bx, int R, int src) {
   const int H = P.H, W = P.W;
   int t, l, sg;
-  if (!vscan_task(bp.x * blockDim.x + threadIdx.x, H, W, t, l, sg)) return;
+  if (!vscan_task(bx * blockDim.x + threadIdx.x, H, W, t, l, sg)) return;
   const VLine L = vline(t, l, H, W);
   const int a = max(L.ylo, sg * SEG), b = min(L.yhi, sg * SEG + SEG);
   if (a >= b) return;
-  const GLOBAL int16_t *__restrict__ o = gro(P.ob[src]);
-  const GLOBAL uint8_t *__restrict__ m = gro(P.mb[src]);
+  const GLOBAL int16_t *__restrict__ o = gro(P.ob[src]);  // O_NONE where invalid
   const size_t N = (size_t)W * H;
   GLOBAL uint32_t *__restrict__ hf = grw(P.hits) + (size_t)(2 * t) * N;
   GLOBAL uint32_t *__restrict__ hb = grw(P.hits) + (size_t)(2 * t + 1) * N;
@@ -673,15 +664,17 @@ __global__ void fill_vscan_kernel(PostPair one, const PostPair *__restrict__ man
     int y = e, k = e * L.st + L.c0;
 #pragma unroll 8
     for (; y >= b; --y, k -= L.st) {
-      const bool v = m[k] != 0;
-      const uint32_t ov = (uint16_t)o[k];
+      const int16_t oo = o[k];
+      const bool v = oo != O_NONE;
+      const uint32_t ov = (uint16_t)oo;
       q = v ? y : q;
       vq = v ? ov : vq;
     }
 #pragma unroll 8
     for (; y >= a; --y, k -= L.st) {
-      const bool v = m[k] != 0;
-      const uint32_t ov = (uint16_t)o[k];
+      const int16_t oo = o[k];
+      const bool v = oo != O_NONE;
+      const uint32_t ov = (uint16_t)oo;
       if (!v) hf[k] = (q >= 0 && q - y <= R) ? ((uint32_t)(q - y) << 16) | vq : 0u;
       q = v ? y : q;
       vq = v ? ov : vq;
@@ -694,20 +687,40 @@ __global__ void fill_vscan_kernel(PostPair one, const PostPair *__restrict__ man
     int y = e, k = e * L.st + L.c0;
 #pragma unroll 8
     for (; y < a; ++y, k += L.st) {
-      const bool v = m[k] != 0;
-      const uint32_t ov = (uint16_t)o[k];
+      const int16_t oo = o[k];
+      const bool v = oo != O_NONE;
+      const uint32_t ov = (uint16_t)oo;
       q = v ? y : q;
       vq = v ? ov : vq;
     }
 #pragma unroll 8
     for (; y < b; ++y, k += L.st) {
-      const bool v = m[k] != 0;
-      const uint32_t ov = (uint16_t)o[k];
+      const int16_t oo = o[k];
+      const bool v = oo != O_NONE;
+      const uint32_t ov = (uint16_t)oo;
       if (!v) hb[k] = (q >= 0 && y - q <= R) ? ((uint32_t)(y - q) << 16) | vq : 0u;
       q = v ? y : q;
       vq = v ? ov : vq;
     }
   }
+}
+
+// The four line types of a scan in one launch: the first nrow blocks of a
+// pair take rows (a wave per row), the others columns and diagonals; the
+// two kinds of work are independent and overlap on the GPU.
+template <bool B>
+__global__ __launch_bounds__(256) void outlier_scan_kernel(PostPair one, const PostPair *__restrict__ many,
+                                                          int r, float thresh, int src, int nrow) {
+  PAIR;
+  if (bp.x < nrow) outlier_rows(P, bp.x, r, thresh, src);
+  else outlier_vscan(P, bp.x - nrow, r, thresh, src);
+}
+template <bool B>
+__global__ __launch_bounds__(256) void fill_scan_kernel(PostPair one, const PostPair *__restrict__ many,
+                                                       int R, int src, int nrow) {
+  PAIR;
+  if (bp.x < nrow) fill_rows(P, bp.x, R, src);
+  else fill_vscan(P, bp.x - nrow, R, src);
 }
 
 // A valid pixel stays when some direction passes (Section II-B).
@@ -720,9 +733,10 @@ __global__ void outlier_combine_kernel(PostPair one, const PostPair *__restrict_
   for_pixels(P, bp, [&](int x, int y, size_t k) {
     const size_t N = (size_t)W * H;
     const uint8_t mk = P.mb[src][k];
-    P.ob[dst][k] = P.ob[src][k];
     const bool any = (P.pass[k] | P.pass[N + k] | P.pass[2 * N + k] | P.pass[3 * N + k]) != 0;
-    P.mb[dst][k] = (mk && any) ? mk : 0;
+    const bool keep = mk && any;
+    P.ob[dst][k] = keep ? P.ob[src][k] : O_NONE;
+    P.mb[dst][k] = keep ? mk : 0;
   });
 }
 
@@ -1345,6 +1359,11 @@ static inline dim3 pixgrid(const PostLaunch &L) { return dim3(ceil_div(L.maxW, P
       hipLaunchKernelGGL(kern<false>, grid, block, 0, L.s, L.one, L.many, ##__VA_ARGS__); \
   } while (0)
 
+hipError_t launch_mark_invalid(const int16_t *o, const uint8_t *m, int16_t *out, size_t N,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(mark_invalid_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, o, m, out, N);
+  return hipGetLastError();
+}
 hipError_t post_decode(const PostLaunch &L) {
   LAUNCH(decode_kernel, pixgrid(L), dim3(PIX_T));
   return hipGetLastError();
@@ -1357,23 +1376,24 @@ hipError_t post_lr(const PostLaunch &L, int tol, int dst) {
   LAUNCH(lr_check_kernel, pixgrid(L), dim3(PIX_T), tol, dst);
   return hipGetLastError();
 }
-static dim3 rowgrid(const PostLaunch &L) { return dim3(ceil_div(L.maxH, 4), 1, L.npairs); }
-static dim3 vscangrid(const PostLaunch &L) {
+// blocks of the row scans (4 rows each) and of the column / diagonal scans
+static int rowblocks(const PostLaunch &L) { return ceil_div(L.maxH, 4); }
+static int vscanblocks(const PostLaunch &L) {
   const int n = (L.maxW + 2 * (L.maxW + L.maxH - 1)) * ceil_div(L.maxH, SEG);
-  return dim3(ceil_div(n, 256), 1, L.npairs);
+  return ceil_div(n, 256);
 }
 
 hipError_t post_outlier(const PostLaunch &L, int r, float thresh, int src, int dst) {
-  LAUNCH(outlier_rows_kernel, rowgrid(L), dim3(256), r, thresh, src);
-  LAUNCH(outlier_vscan_kernel, vscangrid(L), dim3(256), r, thresh, src);
+  const int nrow = rowblocks(L);
+  LAUNCH(outlier_scan_kernel, dim3(nrow + vscanblocks(L), 1, L.npairs), dim3(256), r, thresh, src, nrow);
   LAUNCH(outlier_combine_kernel, pixgrid(L), dim3(PIX_T), src, dst);
   return hipGetLastError();
 }
 // radial fill src -> tmp, disk fill tmp -> dst (dst may equal src)
 hipError_t post_fill(const PostLaunch &L, int radial_r, int min_lines, int disk_r, float frac,
                      int src, int tmp, int dst) {
-  LAUNCH(fill_rows_kernel, rowgrid(L), dim3(256), radial_r, src);
-  LAUNCH(fill_vscan_kernel, vscangrid(L), dim3(256), radial_r, src);
+  const int nrow = rowblocks(L);
+  LAUNCH(fill_scan_kernel, dim3(nrow + vscanblocks(L), 1, L.npairs), dim3(256), radial_r, src, nrow);
   LAUNCH(fill_radial_kernel, dim3(L.maxH, 1, L.npairs), dim3(256), min_lines, src, tmp);
   LAUNCH(fill_disk_kernel, pixgrid(L), dim3(PIX_T), disk_r, frac, tmp, dst);
   return hipGetLastError();
