@@ -381,11 +381,16 @@ static hipError_t post_stages(const PostLaunch &L, const st_params &p, const Deb
     if (x != hipSuccess && e == hipSuccess) e = x;
   };
   ck(post_decode(L));
-  if (p.subpixel) ck(post_subpixel(L));
   int cur = 0;
-  if (p.lr_check) {
-    ck(post_lr(L, p.lr_tol, 1));
+  if (p.subpixel && p.lr_check) {
+    ck(post_subpixel_lr(L, p.lr_tol, 1));
     cur = 1;
+  } else {
+    if (p.subpixel) ck(post_subpixel(L));
+    if (p.lr_check) {
+      ck(post_lr(L, p.lr_tol, 1));
+      cur = 1;
+    }
   }
   if (dbg) ck(hipMemcpyAsync(dbg->mlr, L.one.mb[cur], dbg->N, hipMemcpyDeviceToDevice, L.s));
   if (p.radial_iters <= 0) {

@@ -169,6 +169,8 @@ hipError_t launch_reproject(const float *disp, int H, int W, const Mat4 &Q, floa
 hipError_t post_decode(const PostLaunch &L);
 hipError_t post_subpixel(const PostLaunch &L);
 hipError_t post_lr(const PostLaunch &L, int tol, int dst);
+// post_subpixel and post_lr in one launch
+hipError_t post_subpixel_lr(const PostLaunch &L, int tol, int dst);
 hipError_t post_outlier(const PostLaunch &L, int r, float thresh, int src, int dst);
 hipError_t post_fill(const PostLaunch &L, int radial_r, int min_lines, int disk_r, float frac,
                      int src, int tmp, int dst);

@@ -253,9 +253,7 @@ __device__ __forceinline__ int wave_max(int v) {
   return v;
 }
 
-template <bool B>
-__global__ __launch_bounds__(SPB_T) void subpixel_kernel(PostPair one, const PostPair *__restrict__ many) {
-  PAIR;
+__device__ __forceinline__ void subpixel_block(const PostPair &P, const BlockPos &bp) {
   __shared__ __align__(16) uint8_t Ls[SPB_ROWS][SP_LROW];
   __shared__ __align__(16) uint8_t Rs[SPB_ROWS][SP_RROW];
   __shared__ int s_omin, s_omax;
@@ -367,12 +365,16 @@ __global__ __launch_bounds__(SPB_T) void subpixel_kernel(PostPair one, const Pos
   }
 }
 
+template <bool B>
+__global__ __launch_bounds__(SPB_T) void subpixel_kernel(PostPair one, const PostPair *__restrict__ many) {
+  PAIR;
+  subpixel_block(P, bp);
+}
+
 // ---------------------------------------------------------------- LR check
 // (ob[0], mb[0]) and (oR, mR) -> (ob[dst], mb[dst]): kept when the right
 // pixel x - oL points back within tol.
-template <bool B>
-__global__ void lr_check_kernel(PostPair one, const PostPair *__restrict__ many, int tol, int dst) {
-  PAIR;
+__device__ __forceinline__ void lr_check_block(const PostPair &P, const BlockPos &bp, int tol, int dst) {
   const int W = P.W, H = P.H;
   (void)W;
   (void)H;
@@ -390,6 +392,31 @@ __global__ void lr_check_kernel(PostPair one, const PostPair *__restrict__ many,
     P.ob[dst][k] = keep ? oL[k] : O_NONE;
     P.mb[dst][k] = keep;
   });
+}
+template <bool B>
+__global__ void lr_check_kernel(PostPair one, const PostPair *__restrict__ many, int tol, int dst) {
+  PAIR;
+  lr_check_block(P, bp, tol, dst);
+}
+
+// Sub-pixel fit and left-right check in one launch (independent work on the
+// same maps): the first nsp blocks of a pair run the sub-pixel blocks (nspx
+// of them per row band), the rest the check (nlrx per row).
+template <bool B>
+__global__ __launch_bounds__(SPB_T) void subpixel_lr_kernel(PostPair one, const PostPair *__restrict__ many,
+                                                           int nspx, int nsp, int nlrx, int tol, int dst) {
+  PAIR;
+  BlockPos q = bp;
+  if (bp.x < nsp) {
+    q.x = bp.x % nspx;
+    q.y = bp.x / nspx;
+    subpixel_block(P, q);
+  } else {
+    const int i = bp.x - nsp;
+    q.x = i % nlrx;
+    q.y = i / nlrx;
+    lr_check_block(P, q, tol, dst);
+  }
 }
 
 
@@ -910,7 +937,9 @@ __device__ __forceinline__ double hc_s_at(const PostPair &P, size_t k, uint8_t m
 enum { BOX_IN_MASK = -1, BOX_IN_S = -2 };
 struct BoxArgs {
   int R, in, out, mode, src, osrc, use_delta;
-  int sy;  // rows per block of the fused pass
+  int sy;      // rows per block of the fused pass
+  int counts;  // 1: the pass also boxes the mask (mode 4, input BOX_IN_S) and
+               // stores the counts, instead of reading them
   double alpha;
 };
 
@@ -998,7 +1027,7 @@ __device__ __forceinline__ BoxStoreIn box_store_in(const PostPair &P, const BoxA
   q.s = 0.0;
   if (A.mode == 0) return q;
   q.mk = gro(P.mb[A.src])[k];
-  q.cnt = ((const GLOBAL float *)(gro(P.f) + (size_t)F_CNT * N))[k];
+  if (!A.counts) q.cnt = ((const GLOBAL float *)(gro(P.f) + (size_t)F_CNT * N))[k];
   if (A.mode == 2 || A.mode == 3) q.a = gro(P.f)[(size_t)F_A * N + k];
   if (A.mode == 5) q.s = gro(P.f)[(size_t)F_S * N + k];
   if (A.mode == 4) {
@@ -1056,14 +1085,18 @@ __device__ __forceinline__ void box_store(const PostPair &P, const BoxArgs &A, s
 // barrier: every wave stores its own inclusive scan and its total in LDS,
 // and a thread forms the prefix at the two window ends from the scan value
 // there plus the totals of the waves before it.  The input plane must
-// differ from every plane the output stage writes.
+// differ from every plane the output stage writes.  CNT: the same pass
+// boxes the mask as well (an integer sum beside the FP64 one) and stores the
+// counts, so that the first smoothing pass needs no counts pass before it.
 constexpr int BX_T = 256, BX_RMAX = 96;
-template <bool B>
+template <bool B, bool CNT>
 __global__ __launch_bounds__(BX_T) void box2d_kernel(PostPair one, const PostPair *__restrict__ many,
                                                      BoxArgs A) {
   PAIR;
   __shared__ double pf[2][BX_T];
   __shared__ double wt[2][BX_T / WV];
+  __shared__ int pfc[CNT ? 2 : 1][CNT ? BX_T : 1];
+  __shared__ int wtc[CNT ? 2 : 1][BX_T / WV];
   const int H = P.H, W = P.W, R = A.R;
   const int nout = BX_T - 2 * R;
   const int xo = bp.x * nout, y0 = bp.y * A.sy;
@@ -1071,12 +1104,36 @@ __global__ __launch_bounds__(BX_T) void box2d_kernel(PostPair one, const PostPai
   const size_t N = (size_t)W * H;
   const int t = threadIdx.x, lane = t & (WV - 1), wave = t / WV, c = xo - R + t;
   const bool cin = c >= 0 && c < W;
-  auto px = [&](int r) -> double {
-    return (cin && r >= 0 && r < H) ? box_in(P, A, N, (size_t)r * W + c) : 0.0;
+  // input at row r of the column, and (CNT) whether it is a valid pixel
+  auto px = [&](int r, int &cm) -> double {
+    cm = 0;
+    if (!(cin && r >= 0 && r < H)) return 0.0;
+    const size_t k = (size_t)r * W + c;
+    if constexpr (CNT) {
+      // mask, disparity and offset loaded together (no load behind the mask)
+      const uint8_t mk = gro(P.mb[A.src])[k];
+      double sv;
+      if (P.s_in) {
+        sv = (double)gro(P.s_in)[k];
+      } else {
+        const double o = (double)gro(P.ob[A.osrc])[k];
+        const double dl = A.use_delta ? (double)gro(P.delta)[k] : 0.0;
+        sv = mk == 1 ? o + dl : o;
+      }
+      cm = mk ? 1 : 0;
+      return mk ? sv : 0.0;
+    } else {
+      return box_in(P, A, N, k);
+    }
   };
   double s = 0.0;
+  int sc = 0;
 #pragma unroll 8
-  for (int r = y0 - R; r < y0 + R; ++r) s += px(r);
+  for (int r = y0 - R; r < y0 + R; ++r) {
+    int cm;
+    s += px(r, cm);
+    sc += cm;
+  }
   const bool out_col = c >= xo && c < xo + nout && c < W;  // then R <= t < BX_T - R
   // global prefix at column index i of the block from the stored wave scans
   auto prefix = [&](int b, int i) -> double {
@@ -1084,17 +1141,23 @@ __global__ __launch_bounds__(BX_T) void box2d_kernel(PostPair one, const PostPai
     for (int w = 0; w < i / WV; ++w) v += wt[b][w];
     return v;
   };
+  auto prefixc = [&](int b, int i) -> int {
+    int v = pfc[b][i];
+    for (int w = 0; w < i / WV; ++w) v += wtc[b][w];
+    return v;
+  };
   const int y1 = min(y0 + A.sy, H);
   // a row's inputs (entering and leaving rows, output-stage operands) are
   // loaded two rows ahead
   struct RowIn {
     double add, sub;
+    int addc, subc;
     BoxStoreIn st;
   };
   auto fetch = [&](int y) -> RowIn {
     RowIn q;
-    q.add = px(y + R);
-    q.sub = px(y - R);
+    q.add = px(y + R, q.addc);
+    q.sub = px(y - R, q.subc);
     q.st = out_col ? box_store_in(P, A, N, (size_t)y * W + c) : BoxStoreIn{};
     return q;
   };
@@ -1102,18 +1165,39 @@ __global__ __launch_bounds__(BX_T) void box2d_kernel(PostPair one, const PostPai
     const int b = y & 1;
     s += q.add;
     double p = s;
+    int pc = 0;
+    if constexpr (CNT) {
+      sc += q.addc;
+      pc = sc;
+    }
 #pragma unroll
     for (int o = 1; o < WV; o <<= 1) {
       const double u = __shfl_up(p, o, WV);
       if (lane >= o) p += u;
+      if constexpr (CNT) {
+        const int uc = __shfl_up(pc, o, WV);
+        if (lane >= o) pc += uc;
+      }
     }
     pf[b][t] = p;
     if (lane == WV - 1) wt[b][wave] = p;
+    if constexpr (CNT) {
+      pfc[b][t] = pc;
+      if (lane == WV - 1) wtc[b][wave] = pc;
+    }
     __syncthreads();
-    if (out_col)
-      box_store(P, A, N, (size_t)y * W + c,
-                prefix(b, t + R) - (t - R - 1 >= 0 ? prefix(b, t - R - 1) : 0.0), q.st);
+    if (out_col) {
+      BoxStoreIn st = q.st;
+      const size_t k = (size_t)y * W + c;
+      if constexpr (CNT) {
+        const int cnt = prefixc(b, t + R) - (t - R - 1 >= 0 ? prefixc(b, t - R - 1) : 0);
+        st.cnt = (float)cnt;
+        ((GLOBAL float *)(grw(P.f) + (size_t)F_CNT * N))[k] = st.cnt;
+      }
+      box_store(P, A, N, k, prefix(b, t + R) - (t - R - 1 >= 0 ? prefix(b, t - R - 1) : 0.0), st);
+    }
     s -= q.sub;
+    if constexpr (CNT) sc -= q.subc;
   };
   RowIn q0 = fetch(y0), q1 = y0 + 1 < y1 ? fetch(y0 + 1) : RowIn{};
   for (int y = y0; y < y1; y += 2) {  // y1 - y0 is uniform: every thread takes the same rows
@@ -1358,6 +1442,14 @@ static inline dim3 pixgrid(const PostLaunch &L) { return dim3(ceil_div(L.maxW, P
     else                                                                                 \
       hipLaunchKernelGGL(kern<false>, grid, block, 0, L.s, L.one, L.many, ##__VA_ARGS__); \
   } while (0)
+// the same with the batched and single-pair instantiations named
+#define LAUNCH_K(kbatch, kone, grid, block, ...)                                         \
+  do {                                                                                   \
+    if (L.many)                                                                          \
+      hipLaunchKernelGGL(kbatch, grid, block, 0, L.s, L.one, L.many, ##__VA_ARGS__);     \
+    else                                                                                 \
+      hipLaunchKernelGGL(kone, grid, block, 0, L.s, L.one, L.many, ##__VA_ARGS__);       \
+  } while (0)
 
 hipError_t launch_mark_invalid(const int16_t *o, const uint8_t *m, int16_t *out, size_t N,
                                hipStream_t s) {
@@ -1370,6 +1462,12 @@ hipError_t post_decode(const PostLaunch &L) {
 }
 hipError_t post_subpixel(const PostLaunch &L) {
   LAUNCH(subpixel_kernel, dim3(ceil_div(L.maxW, SP_TX), ceil_div(L.maxH, SPB_TY), L.npairs), dim3(SPB_T));
+  return hipGetLastError();
+}
+hipError_t post_subpixel_lr(const PostLaunch &L, int tol, int dst) {
+  const int nspx = ceil_div(L.maxW, SP_TX), nsp = nspx * ceil_div(L.maxH, SPB_TY);
+  const int nlrx = ceil_div(L.maxW, PIX_SEG), nlr = nlrx * L.maxH;
+  LAUNCH(subpixel_lr_kernel, dim3(nsp + nlr, 1, L.npairs), dim3(SPB_T), nspx, nsp, nlrx, tol, dst);
   return hipGetLastError();
 }
 hipError_t post_lr(const PostLaunch &L, int tol, int dst) {
@@ -1411,8 +1509,21 @@ static void box2d(const PostLaunch &L, BoxArgs A) {
     const int nout = BX_T - 2 * A.R, nx = ceil_div(L.maxW, nout);
     A.sy = 32;
     while (A.sy > 8 && (long long)nx * ceil_div(L.maxH, A.sy) * L.npairs < 1024) A.sy /= 2;
-    LAUNCH(box2d_kernel, dim3(nx, ceil_div(L.maxH, A.sy), L.npairs), dim3(BX_T), A);
+    const dim3 grid(nx, ceil_div(L.maxH, A.sy), L.npairs);
+    if (A.counts) {
+      LAUNCH_K((box2d_kernel<true, true>), (box2d_kernel<false, true>), grid, dim3(BX_T), A);
+    } else {
+      LAUNCH_K((box2d_kernel<true, false>), (box2d_kernel<false, false>), grid, dim3(BX_T), A);
+    }
     return;
+  }
+  if (A.counts) {  // column and row passes: the counts first
+    BoxArgs C = A;
+    C.in = BOX_IN_MASK;
+    C.mode = 0;
+    C.counts = 0;
+    box2d(L, C);
+    A.counts = 0;
   }
   const int seg = 32;
   LAUNCH(box_v_kernel, dim3(ceil_div(L.maxW, 64), ceil_div(L.maxH, seg), L.npairs), dim3(64), A, seg);
@@ -1452,17 +1563,19 @@ hipError_t post_hc(const PostLaunch &L, int src, int R, int K, float alpha, int 
     A.osrc = ocur;
     A.use_delta = use_delta;
     A.sy = 32;
+    A.counts = 0;
     A.alpha = (double)alpha;
     return A;
   };
-  box2d(L, args(BOX_IN_MASK, F_CNT, 0));  // counts of valid pixels
   if (!research) {
     // a is fixed and s is formed on the fly from the disparities; every b
     // (Eq. 2) is formed in the output stage of the box pass before it,
     // alternating between the planes F_D and F_IN; with c = alpha (a - s)
     // (plane F_S), b_{k+1} = c + (1 - alpha) box(b_k m)/box(m), and only the
     // last pass forms d = a - box(b m)/box(m)
-    box2d(L, args(BOX_IN_S, F_D, 4));  // a = box(s m) / box(m), b_0 -> F_D
+    BoxArgs first = args(BOX_IN_S, F_D, 4);  // a = box(s m) / box(m), b_0 -> F_D,
+    first.counts = 1;                         // and the counts box(m) in the same pass
+    box2d(L, first);
     int bin = F_D, bout = F_IN;
     for (int it = 0; it < K; ++it) {
       box2d(L, args(bin, bout, it == K - 1 ? 3 : 5));  // d = a - box(b m) / box(m)
@@ -1470,6 +1583,7 @@ hipError_t post_hc(const PostLaunch &L, int src, int R, int K, float alpha, int 
     }
     return hipGetLastError();
   }
+  box2d(L, args(BOX_IN_MASK, F_CNT, 0));  // counts of valid pixels
   for (int it = 0; it < K; ++it) {
     LAUNCH(hc_init_kernel, pixgrid(L), dim3(PIX_T), src, ocur, use_delta, 0);
     box2d(L, args(F_IN, F_IN, 1));  // a = box(o m) / box(m)
