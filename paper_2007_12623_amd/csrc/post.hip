@@ -792,63 +792,95 @@ __global__ __launch_bounds__(256) void fill_radial_kernel(PostPair one, const Po
     pcr[0] = 0;
     psr[0] = 0;
   }
+  // each thread takes 4 consecutive pixels of a 1024-column chunk: the hits
+  // of all its holes are loaded together, and one block scan of the thread
+  // totals serves the chunk
+  constexpr int PER = 4;
   int carry_c = 0, carry_s = 0;
-  for (int x0 = 0; x0 < W; x0 += 256) {
-    const int x = x0 + t;
-    int ov = 0, mv = 0;
-    if (x < W) {
-      const size_t k = (size_t)y * W + x;
-      ov = o[k];
-      mv = m[k];
-      if (!mv) {
-        // all eight hits in one round trip
-        uint32_t hv[8];
+  for (int x0 = 0; x0 < W; x0 += 256 * PER) {
+    const int xb = x0 + PER * t;
+    int ov[PER], mv[PER];
+    bool hole[PER];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) hv[i] = hits[(size_t)i * N + k];
-        long long num = 0, den = 1;
-        int lines = 0;
-#pragma unroll
-        for (int ln = 0; ln < 4; ++ln) {
-          const uint32_t ha = hv[2 * ln], hb = hv[2 * ln + 1];
-          if (!ha || !hb) continue;
-          const long long sa = ha >> 16, sb = hb >> 16;
-          const long long va = (int16_t)(ha & 0xFFFFu), vb = (int16_t)(hb & 0xFFFFu);
-          const long long lnum = va * sb + vb * sa;
-          const long long ld = sa + sb;
-          num = num * ld + lnum * den;
-          den = den * ld;
-          ++lines;
-        }
-        if (lines >= min_lines && lines > 0) {
-          ov = (int)round_half_even(num, den * lines);
-          mv = 2;
-        }
+    for (int j = 0; j < PER; ++j) {
+      const int x = xb + j;
+      ov[j] = 0;
+      mv[j] = 0;
+      if (x < W) {
+        const size_t k = (size_t)y * W + x;
+        ov[j] = o[k];
+        mv[j] = m[k];
       }
-      grw(P.ob[dst])[k] = (int16_t)ov;
-      grw(P.mb[dst])[k] = (uint8_t)mv;
+      hole[j] = x < W && mv[j] == 0;
     }
-    int c = mv ? 1 : 0, sv = mv ? ov : 0;
+    uint32_t hv[PER][8];
+#pragma unroll
+    for (int j = 0; j < PER; ++j)
+#pragma unroll
+      for (int i = 0; i < 8; ++i) hv[j][i] = hole[j] ? hits[(size_t)i * N + (size_t)y * W + xb + j] : 0u;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      if (!hole[j]) continue;
+      long long num = 0, den = 1;
+      int lines = 0;
+#pragma unroll
+      for (int ln = 0; ln < 4; ++ln) {
+        const uint32_t ha = hv[j][2 * ln], hb = hv[j][2 * ln + 1];
+        if (!ha || !hb) continue;
+        const long long sa = ha >> 16, sb = hb >> 16;
+        const long long va = (int16_t)(ha & 0xFFFFu), vb = (int16_t)(hb & 0xFFFFu);
+        const long long lnum = va * sb + vb * sa;
+        const long long ld = sa + sb;
+        num = num * ld + lnum * den;
+        den = den * ld;
+        ++lines;
+      }
+      if (lines >= min_lines && lines > 0) {
+        ov[j] = (int)round_half_even(num, den * lines);
+        mv[j] = 2;
+      }
+    }
+    int cl[PER], sl[PER], c = 0, sv = 0;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const int x = xb + j;
+      if (x < W) {
+        const size_t k = (size_t)y * W + x;
+        grw(P.ob[dst])[k] = (int16_t)ov[j];
+        grw(P.mb[dst])[k] = (uint8_t)mv[j];
+      }
+      c += mv[j] ? 1 : 0;
+      sv += mv[j] ? ov[j] : 0;
+      cl[j] = c;
+      sl[j] = sv;
+    }
+    // inclusive scan of the thread totals over the wave, then the block
+    int ic = c, is = sv;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
-      const int uc = __shfl_up(c, off, 64), us = __shfl_up(sv, off, 64);
+      const int uc = __shfl_up(ic, off, 64), us = __shfl_up(is, off, 64);
       if (lane >= off) {
-        c += uc;
-        sv += us;
+        ic += uc;
+        is += us;
       }
     }
     if (lane == 63) {
-      wc[wave] = c;
-      wsum[wave] = sv;
+      wc[wave] = ic;
+      wsum[wave] = is;
     }
     __syncthreads();
-    int bc = carry_c, bs = carry_s;
+    int bc = carry_c + ic - c, bs = carry_s + is - sv;  // totals before this thread
     for (int w = 0; w < wave; ++w) {
       bc += wc[w];
       bs += wsum[w];
     }
-    if (x < W) {
-      pcr[x + 1] = bc + c;
-      psr[x + 1] = bs + sv;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const int x = xb + j;
+      if (x < W) {
+        pcr[x + 1] = bc + cl[j];
+        psr[x + 1] = bs + sl[j];
+      }
     }
     for (int w = 0; w < 4; ++w) {
       carry_c += wc[w];
@@ -878,25 +910,52 @@ __global__ __launch_bounds__(PIX_T) void fill_disk_kernel(PostPair one, const Po
                                                         float frac, int src, int dst) {
   PAIR;
   __shared__ int hw[2 * DISK_TAB + 1];
+  __shared__ int holes[PIX_SEG];
+  __shared__ int nholes;
   const int RT = min(R, DISK_TAB);
   for (int i = threadIdx.x; i <= 2 * RT; i += blockDim.x) {
     const int dy = i - RT;
     hw[i] = isqrt_floor(R * R - dy * dy);
   }
+  if (threadIdx.x == 0) nholes = 0;
   __syncthreads();
-  const int W = P.W, H = P.H;
-  (void)W;
-  (void)H;
-  for_pixels(P, bp, [&](int x, int y, size_t k) {
-    const GLOBAL int16_t *o = gro(P.ob[src]);
-    const GLOBAL uint8_t *m = gro(P.mb[src]);
-    grw(P.ob[dst])[k] = o[k];
-    grw(P.mb[dst])[k] = m[k];
-    if (m[k]) return;
+  const int W = P.W, H = P.H, y = bp.y;
+  const GLOBAL int16_t *o = gro(P.ob[src]);
+  const GLOBAL uint8_t *m = gro(P.mb[src]);
+  // copy the segment, and list its holes in LDS (one slot reservation per
+  // wave and pass: ballot, then each hole lane at its rank)
+  const int lane = threadIdx.x & (WV - 1);
+  if (y < H) {
+    const int x1 = min(W, (bp.x + 1) * PIX_SEG);
+    for (int x0 = bp.x * PIX_SEG; x0 < x1; x0 += PIX_T) {  // uniform trip count
+      const int x = x0 + threadIdx.x;
+      bool hole = false;
+      if (x < x1) {
+        const size_t k = (size_t)y * W + x;
+        const int16_t ov = o[k];
+        const uint8_t mv = m[k];
+        grw(P.ob[dst])[k] = ov;
+        grw(P.mb[dst])[k] = mv;
+        hole = mv == 0;
+      }
+      const uint64_t hm = ballot64(hole);
+      int base = 0;
+      if (lane == 0 && hm) base = atomicAdd(&nholes, __builtin_popcountll(hm));
+      base = __shfl(base, 0, WV);
+      if (hole) holes[base + __builtin_popcountll(hm & lanes_below(lane))] = x;
+    }
+  }
+  __syncthreads();
+  if (y >= H) return;  // uniform per block
+  // the disk sums, one hole per thread
+  const int nh = nholes;
+  const GLOBAL int32_t *__restrict__ pc = gro(P.pc);
+  const GLOBAL int32_t *__restrict__ ps = gro(P.ps);
+  for (int i = threadIdx.x; i < nh; i += PIX_T) {
+    const int x = holes[i];
+    const size_t k = (size_t)y * W + x;
     long long cells = 0, cnt = 0, sum = 0;
     const int ya = max(-R, -y), yb = min(R, H - 1 - y);
-    const GLOBAL int32_t *__restrict__ pc = gro(P.pc);
-    const GLOBAL int32_t *__restrict__ ps = gro(P.ps);
 #pragma unroll 8
     for (int dy = ya; dy <= yb; ++dy) {
       const int qy = y + dy;
@@ -912,7 +971,7 @@ __global__ __launch_bounds__(PIX_T) void fill_disk_kernel(PostPair one, const Po
       grw(P.ob[dst])[k] = (int16_t)round_half_even(sum, cnt);
       grw(P.mb[dst])[k] = 2;
     }
-  });
+  }
 }
 
 // ---------------------------------------------------------------- smoothing (FP64)

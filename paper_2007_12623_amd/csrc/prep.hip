@@ -189,7 +189,9 @@ __global__ __launch_bounds__(WS_T) void window_stats_kernel(PrepPair one, const 
         SS = 0;
       } else {
         const long long varN = (long long)n * SS - (long long)S * S;
-        if (varN > 0) iv = (float)(1.0 / sqrt((double)varN));
+        // FP64 reciprocal square root (within an ulp of 1/sqrt in FP64),
+        // rounded once to float
+        if (varN > 0) iv = (float)rsqrt((double)varN);
       }
       const size_t k = (size_t)y * W + x;
       if (side == 1) {
