@@ -792,95 +792,63 @@ __global__ __launch_bounds__(256) void fill_radial_kernel(PostPair one, const Po
     pcr[0] = 0;
     psr[0] = 0;
   }
-  // each thread takes 4 consecutive pixels of a 1024-column chunk: the hits
-  // of all its holes are loaded together, and one block scan of the thread
-  // totals serves the chunk
-  constexpr int PER = 4;
   int carry_c = 0, carry_s = 0;
-  for (int x0 = 0; x0 < W; x0 += 256 * PER) {
-    const int xb = x0 + PER * t;
-    int ov[PER], mv[PER];
-    bool hole[PER];
+  for (int x0 = 0; x0 < W; x0 += 256) {
+    const int x = x0 + t;
+    int ov = 0, mv = 0;
+    if (x < W) {
+      const size_t k = (size_t)y * W + x;
+      ov = o[k];
+      mv = m[k];
+      if (!mv) {
+        // all eight hits in one round trip
+        uint32_t hv[8];
 #pragma unroll
-    for (int j = 0; j < PER; ++j) {
-      const int x = xb + j;
-      ov[j] = 0;
-      mv[j] = 0;
-      if (x < W) {
-        const size_t k = (size_t)y * W + x;
-        ov[j] = o[k];
-        mv[j] = m[k];
+        for (int i = 0; i < 8; ++i) hv[i] = hits[(size_t)i * N + k];
+        long long num = 0, den = 1;
+        int lines = 0;
+#pragma unroll
+        for (int ln = 0; ln < 4; ++ln) {
+          const uint32_t ha = hv[2 * ln], hb = hv[2 * ln + 1];
+          if (!ha || !hb) continue;
+          const long long sa = ha >> 16, sb = hb >> 16;
+          const long long va = (int16_t)(ha & 0xFFFFu), vb = (int16_t)(hb & 0xFFFFu);
+          const long long lnum = va * sb + vb * sa;
+          const long long ld = sa + sb;
+          num = num * ld + lnum * den;
+          den = den * ld;
+          ++lines;
+        }
+        if (lines >= min_lines && lines > 0) {
+          ov = (int)round_half_even(num, den * lines);
+          mv = 2;
+        }
       }
-      hole[j] = x < W && mv[j] == 0;
+      grw(P.ob[dst])[k] = (int16_t)ov;
+      grw(P.mb[dst])[k] = (uint8_t)mv;
     }
-    uint32_t hv[PER][8];
-#pragma unroll
-    for (int j = 0; j < PER; ++j)
-#pragma unroll
-      for (int i = 0; i < 8; ++i) hv[j][i] = hole[j] ? hits[(size_t)i * N + (size_t)y * W + xb + j] : 0u;
-#pragma unroll
-    for (int j = 0; j < PER; ++j) {
-      if (!hole[j]) continue;
-      long long num = 0, den = 1;
-      int lines = 0;
-#pragma unroll
-      for (int ln = 0; ln < 4; ++ln) {
-        const uint32_t ha = hv[j][2 * ln], hb = hv[j][2 * ln + 1];
-        if (!ha || !hb) continue;
-        const long long sa = ha >> 16, sb = hb >> 16;
-        const long long va = (int16_t)(ha & 0xFFFFu), vb = (int16_t)(hb & 0xFFFFu);
-        const long long lnum = va * sb + vb * sa;
-        const long long ld = sa + sb;
-        num = num * ld + lnum * den;
-        den = den * ld;
-        ++lines;
-      }
-      if (lines >= min_lines && lines > 0) {
-        ov[j] = (int)round_half_even(num, den * lines);
-        mv[j] = 2;
-      }
-    }
-    int cl[PER], sl[PER], c = 0, sv = 0;
-#pragma unroll
-    for (int j = 0; j < PER; ++j) {
-      const int x = xb + j;
-      if (x < W) {
-        const size_t k = (size_t)y * W + x;
-        grw(P.ob[dst])[k] = (int16_t)ov[j];
-        grw(P.mb[dst])[k] = (uint8_t)mv[j];
-      }
-      c += mv[j] ? 1 : 0;
-      sv += mv[j] ? ov[j] : 0;
-      cl[j] = c;
-      sl[j] = sv;
-    }
-    // inclusive scan of the thread totals over the wave, then the block
-    int ic = c, is = sv;
+    int c = mv ? 1 : 0, sv = mv ? ov : 0;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
-      const int uc = __shfl_up(ic, off, 64), us = __shfl_up(is, off, 64);
+      const int uc = __shfl_up(c, off, 64), us = __shfl_up(sv, off, 64);
       if (lane >= off) {
-        ic += uc;
-        is += us;
+        c += uc;
+        sv += us;
       }
     }
     if (lane == 63) {
-      wc[wave] = ic;
-      wsum[wave] = is;
+      wc[wave] = c;
+      wsum[wave] = sv;
     }
     __syncthreads();
-    int bc = carry_c + ic - c, bs = carry_s + is - sv;  // totals before this thread
+    int bc = carry_c, bs = carry_s;
     for (int w = 0; w < wave; ++w) {
       bc += wc[w];
       bs += wsum[w];
     }
-#pragma unroll
-    for (int j = 0; j < PER; ++j) {
-      const int x = xb + j;
-      if (x < W) {
-        pcr[x + 1] = bc + cl[j];
-        psr[x + 1] = bs + sl[j];
-      }
+    if (x < W) {
+      pcr[x + 1] = bc + c;
+      psr[x + 1] = bs + sv;
     }
     for (int w = 0; w < 4; ++w) {
       carry_c += wc[w];
