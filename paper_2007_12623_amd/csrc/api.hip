@@ -271,9 +271,6 @@ static PairLayout layout(const MatchPair &P, int prec, bool debug) {
     Lo.ob[i] = c.take(2 * N);
     Lo.mb[i] = c.take(N);
   }
-  Lo.zbest = c.take(8 * N);
-  Lo.zm = c.take(8 * N);
-  Lo.zp = c.take(8 * N);
   Lo.delta = c.take(4 * N);
   Lo.pc = c.take(4 * (size_t)P.H * (P.W + 1));
   Lo.ps = c.take(4 * (size_t)P.H * (P.W + 1));
@@ -281,6 +278,11 @@ static PairLayout layout(const MatchPair &P, int prec, bool debug) {
   // hold the radial scans (8 x 4 bytes of nearest hits, 4 x 1 byte of runs)
   Lo.f = c.take(6 * 8 * N);
   if (debug) {
+    // the FP64 scores of the sub-pixel step are written for the debug
+    // readout only
+    Lo.zbest = c.take(8 * N);
+    Lo.zm = c.take(8 * N);
+    Lo.zp = c.take(8 * N);
     Lo.dbg_mlr = c.take(N);
     Lo.dbg_o = c.take(2 * N);
     Lo.dbg_m = c.take(N);
@@ -354,9 +356,10 @@ static void fill_views(const PairLayout &Lo, void *base, uint32_t *keys, MatchPa
     Q.ob[i] = at<int16_t>(base, Lo.ob[i]);
     Q.mb[i] = at<uint8_t>(base, Lo.mb[i]);
   }
-  Q.zbest = at<double>(base, Lo.zbest);
-  Q.zm = at<double>(base, Lo.zm);
-  Q.zp = at<double>(base, Lo.zp);
+  // offset 0 is the first L plane, so 0 marks a buffer left out
+  Q.zbest = Lo.zbest ? at<double>(base, Lo.zbest) : nullptr;
+  Q.zm = Lo.zm ? at<double>(base, Lo.zm) : nullptr;
+  Q.zp = Lo.zp ? at<double>(base, Lo.zp) : nullptr;
   Q.delta = at<float>(base, Lo.delta);
   Q.pc = at<int32_t>(base, Lo.pc);
   Q.ps = at<int32_t>(base, Lo.ps);
@@ -556,6 +559,8 @@ static PostLaunch single_launch(const PostPair &Q, hipStream_t s) {
   L.npairs = 1;
   L.maxH = Q.H;
   L.maxW = Q.W;
+  L.maxWin = Q.win;
+  L.maxD = Q.dmax - Q.dmin + 1;
   L.s = s;
   return L;
 }
@@ -981,6 +986,12 @@ st_status stereo_match_batched(st_handle h, const st_pair *pairs, int n_pairs,
   L.npairs = n_pairs;
   L.maxH = maxH;
   L.maxW = maxW;
+  L.maxWin = 0;
+  L.maxD = 0;
+  for (int i = 0; i < n_pairs; ++i) {
+    L.maxWin = std::max(L.maxWin, Q[i].win);
+    L.maxD = std::max(L.maxD, Q[i].dmax - Q[i].dmin + 1);
+  }
   L.s = cs;
   ck(post_stages(L, *params, nullptr));
   hipGraph_t g = nullptr;

@@ -101,6 +101,7 @@ struct PostLaunch {
   PostPair one;
   const PostPair *many;  // null for a single pair
   int npairs, maxH, maxW;
+  int maxWin, maxD;  // largest window and disparity count over the pairs
   hipStream_t s;
 };
 

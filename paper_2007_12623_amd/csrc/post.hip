@@ -87,16 +87,29 @@ __global__ void mark_invalid_kernel(const int16_t *__restrict__ o, const uint8_t
 // n*S_LR - S_L*S_R, FP64 normalisation), then the parabola offset
 // delta = (zm - zp) / (2 (zm - 2 z0 + zp)) clamped to [-1/2, 1/2]; 0 at the
 // ends of the range, when a neighbour is missing or the curvature is >= 0.
-// A block of 256 threads covers 128 columns x 4 rows: it stages the window
-// rows of the left image and the right columns its disparities reach in LDS
-// once, and each thread takes two pixels of its column.  The three window
-// sums sum_u L(u) R(u + e), e = 0, 1, 2, are formed as sum_w L(w - e) R(w):
-// the R bytes are aligned once per window row and the L row is shifted by e
-// bytes with a constant v_alignbyte, so no per-lane selects are needed;
-// v_dot4_u32_u8 adds 4 products per instruction, exact in 32 bits.
+//
+// A block of 256 threads covers 128 columns x 8 rows; each thread takes
+// four pixels of its column (rows ty, ty + 2, ty + 4, ty + 6 of the band).
+// The block stages the image rows its windows meet in LDS, column-packed:
+// dword (p, c) holds the bytes of stage rows p .. p + 3 of stage column c,
+// byte 0 from row p.  A window is then NG = ceil(win / 4) packed rows of win
+// dwords, and sum_u L(u) R(u + e) over four window rows is one v_dot4_u32_u8
+// of aligned dwords, for any column and any shift e: no byte realignment per
+// lane.  Stage columns 0 .. 4 QL - 1 are L(., x0 - h + c); the next 4 QR
+// are R(., x0 - omax - 1 - h + c), omax the largest disparity of the block.
 constexpr int SP_TX = 128, SP_MAXWIN = 15;
+constexpr int SPB_T = 256, SPB_TY = 8, SP_NPT = SPB_TY * SP_TX / SPB_T;
+// row-major LDS rows of the Eq. (4) re-search
 constexpr int SP_LROW = SP_TX + 24, SP_RROW = SP_TX + 256 + 32;
-constexpr int SPB_T = 256, SPB_TY = 4, SPB_ROWS = SP_MAXWIN + SPB_TY - 1;
+
+__host__ __device__ inline int sp_groups(int win) { return (win + 3) / 4; }
+__host__ __device__ inline int sp_quads_l(int win) { return (SP_TX + win - 1 + 3) / 4; }
+__host__ __device__ inline int sp_quads_r(int win, int range) { return (SP_TX + range + 2 + win - 1 + 3) / 4; }
+// LDS bytes of the packed stage for windows up to maxWin and maxD disparities
+static size_t sp_lds_bytes(int maxWin, int maxD) {
+  const size_t S = 4 * (size_t)(sp_quads_l(maxWin) + sp_quads_r(maxWin, maxD - 1));
+  return (size_t)(SPB_TY + 4 * (sp_groups(maxWin) - 1)) * S * 4;
+}
 
 // Copy the bytes [off, off + len) of the image buffer base[0, span) (byte
 // offsets relative to base; off may be negative) to an LDS row as whole
@@ -133,109 +146,107 @@ __device__ __forceinline__ uint32_t chess_mask(int chess, int v) {
   return chess ? ((v & 1) ? 0xFF00FF00u : 0x00FF00FFu) : 0xFFFFFFFFu;
 }
 
-// Dword i counted from the 4-aligned byte offset a0 of the buffer
-// base[0, span); bytes outside the buffer read as 0.
-__device__ __forceinline__ uint32_t fetch_dw(const GLOBAL uint8_t *base, long long a0, int i,
-                                             long long span) {
-  const long long b = a0 + 4 * (long long)i;
-  if (b >= 0 && b + 4 <= span) return *(const GLOBAL uint32_t *)(base + b);
-  uint32_t v = 0;
-  for (int j = 0; j < 4; ++j)
-    if (b + j >= 0 && b + j < span) v |= (uint32_t)base[b + j] << (8 * j);
-  return v;
+// The dword-aligned dword at byte offset a of base[0, span) (base + a is
+// 4-aligned), its bytes outside the buffer 0.  A dword that straddles an end
+// of the buffer lies in the page of a byte inside and is read whole; one
+// wholly outside is not read (the aligned dword holding base[0] is read in
+// its place and dropped).
+__device__ __forceinline__ uint32_t sp_dword(const GLOBAL uint8_t *base, long long a, long long span) {
+  const bool ok = a > -4 && a < span;
+  const uint32_t x = *(const GLOBAL uint32_t *)(base + (ok ? a : -(long long)((uintptr_t)base & 3)));
+  const int lo = a < 0 ? (int)(-a) : 0, hi = a + 4 > span ? (int)(a + 4 - span) : 0;
+  return ok ? x & ((0xFFFFFFFFu << (8 * (lo & 3))) & (0xFFFFFFFFu >> (8 * (hi & 3)))) : 0u;
 }
 
-// Stage image rows yr0 .. yr0 + nrows - 1 (rows outside the image are
-// skipped): LW bytes of L from column lx0 and RW bytes of R from column rx0
-// go to Ls[r] / Rs[r] starting at byte 0, realigned from the whole dwords of
-// the image (v_alignbyte of two neighbouring dwords), so that every staged
-// row has the same layout whatever the pitch.  All threads of the block
-// share the dwords of a row.
-__device__ __forceinline__ void stage_rows(uint8_t (*Ls)[SP_LROW], uint8_t (*Rs)[SP_RROW],
-                                           const GLOBAL uint8_t *Lg, const GLOBAL uint8_t *Rg,
-                                           int pitch, long long span, int H, int yr0, int nrows,
-                                           int lx0, int LW, int rx0, int RW, int tid, int nthreads) {
-  for (int r = 0; r < nrows; ++r) {
-    const int yy = yr0 + r;
-    if (yy < 0 || yy >= H) continue;  // uniform
-    const long long row = (long long)yy * pitch;
-    const int misl = (int)(((uintptr_t)Lg + (uintptr_t)(row + lx0)) & 3);
-    const int misr = (int)(((uintptr_t)Rg + (uintptr_t)(row + rx0)) & 3);
-    const int nl = (LW + 3) >> 2, nr = (RW + 3) >> 2;
-    const long long al = row + lx0 - misl, ar = row + rx0 - misr;
-    // dwords 0 .. nl (nr) of both ranges inside the buffer: plain loads with
-    // 32-bit offsets from a uniform base (every row but the image's first
-    // and last ones, at most)
-    const bool fast = al >= 0 && ar >= 0 && al + 4LL * (nl + 1) <= span && ar + 4LL * (nr + 1) <= span;
-    if (fast) {
-      const GLOBAL uint32_t *gl = (const GLOBAL uint32_t *)(Lg + al);
-      const GLOBAL uint32_t *gr = (const GLOBAL uint32_t *)(Rg + ar);
-      for (int i = tid; i < nl + nr; i += nthreads) {
-        const bool isl = i < nl;
-        const int j = isl ? i : i - nl;
-        const GLOBAL uint32_t *g = isl ? gl : gr;
-        const uint32_t v = __builtin_amdgcn_alignbyte(g[j + 1], g[j], isl ? misl : misr);
-        if (isl) ((uint32_t *)Ls[r])[j] = v;
-        else ((uint32_t *)Rs[r])[j] = v;
+// Build packed rows 0 .. PR - 1 of the stage (row stride S dwords).  Work
+// item (chunk k, quad q): packed rows 4k .. 4k + 3 of stage columns
+// 4q .. 4q + 3, from image rows yr0 + 4k .. yr0 + 4k + 6 (one 4-byte load
+// each, realigned from two aligned dwords), shifting each row's bytes in at
+// the top of the four column dwords.  Bytes outside the buffer are 0; bytes
+// of columns outside the image only reach sums whose z is discarded.  When
+// every byte the block reads lies inside the buffer (all bands but the
+// image's first and last ones), the loads take no bounds checks.
+__device__ __forceinline__ void sp_pack(uint32_t *Pk, int S, int PR, const GLOBAL uint8_t *Lg,
+                                        const GLOBAL uint8_t *Rg, int pitch, long long span, int yr0,
+                                        int lx0, int QL, int rx0, int QR, int tid) {
+  const int nq = QL + QR, nk = (PR + 3) >> 2, items = nq * nk;
+  // bytes read: rows yr0 .. yr0 + 4 nk + 2, columns from 3 before the first
+  // staged one to 7 past the last one's start (two dwords per load)
+  const long long first = (long long)yr0 * pitch + min(lx0, rx0) - 3;
+  const long long last = (long long)(yr0 + 4 * nk + 2) * pitch + max(lx0 + 4 * QL, rx0 + 4 * QR) + 8;
+  const bool inside = first >= 0 && last <= span;
+  const int pm = pitch & 3;
+  for (int it = tid; it < items; it += SPB_T) {
+    const int k = it / nq, q = it - k * nq;
+    const bool isl = q < QL;
+    const GLOBAL uint8_t *g = isl ? Lg : Rg;
+    const int col = isl ? lx0 + 4 * q : rx0 + 4 * (q - QL);
+    const long long off0 = (long long)(yr0 + 4 * k) * pitch + col;
+    uint32_t raw[7];
+    if (inside) {
+      const GLOBAL uint8_t *p0 = g + off0;
+      const int m0 = (int)((uintptr_t)p0 & 3);
+#pragma unroll
+      for (int t = 0; t < 7; ++t) {
+        const int mis = (m0 + t * pm) & 3;
+        const GLOBAL uint32_t *a = (const GLOBAL uint32_t *)(p0 + (long long)t * pitch - mis);
+        raw[t] = __builtin_amdgcn_alignbyte(a[1], a[0], mis);
       }
-      continue;
+    } else {
+#pragma unroll
+      for (int t = 0; t < 7; ++t) {
+        const long long off = off0 + (long long)t * pitch;
+        const int mis = (int)(((uintptr_t)g + (uintptr_t)off) & 3);
+        const long long a = off - mis;
+        raw[t] = __builtin_amdgcn_alignbyte(sp_dword(g, a + 4, span), sp_dword(g, a, span), mis);
+      }
     }
-    for (int i = tid; i < nl + nr; i += nthreads) {
-      const bool isl = i < nl;
-      const int j = isl ? i : i - nl;
-      const GLOBAL uint8_t *g = isl ? Lg : Rg;
-      const long long a = isl ? al : ar;
-      const uint32_t v = __builtin_amdgcn_alignbyte(fetch_dw(g, a, j + 1, span), fetch_dw(g, a, j, span),
-                                                    isl ? misl : misr);
-      if (isl) ((uint32_t *)Ls[r])[j] = v;
-      else ((uint32_t *)Rs[r])[j] = v;
+    uint32_t c0 = 0, c1 = 0, c2 = 0, c3 = 0;
+    uint32_t *dst = Pk + 4 * q;
+#pragma unroll
+    for (int t = 0; t < 7; ++t) {
+      const uint32_t v = raw[t];
+      c0 = (c0 >> 8) | (v << 24);
+      c1 = (c1 >> 8) | ((v >> 8) << 24);
+      c2 = (c2 >> 8) | ((v >> 16) << 24);
+      c3 = (c3 >> 8) | ((v >> 24) << 24);
+      const int p = 4 * k + t - 3;
+      if (t >= 3 && p < PR) *(uint4 *)(dst + (size_t)p * S) = make_uint4(c0, c1, c2, c3);
     }
   }
 }
 
-// Window sums over stage rows r0 .. r0 + WIN - 1 of L(u) R(rs0 + u + e) for
-// e = 0, 1, 2 (the disparities o + 1, o, o - 1).  NL dwords hold the WIN
-// bytes of an L row (bytes past WIN, and the other chessboard colour, masked
-// to 0); NR dwords cover the WIN + 2 bytes of R that the shifted rows meet.
-template <int WIN>
-__device__ __forceinline__ void sp_sums(const uint8_t (*Ls)[SP_LROW], const uint8_t (*Rs)[SP_RROW],
-                                        int chess, int r0, int tx, int rs0, int &sp, int &s0,
-                                        int &sm) {
-  constexpr int NL = (WIN + 3) / 4, NR = (WIN + 5) / 4;
-  constexpr uint32_t lmask = (WIN & 3) ? (1u << (8 * (WIN & 3))) - 1u : 0xFFFFFFFFu;
+// Window sums at the disparities o + 1, o, o - 1 (sp, s0, sm) of a pixel
+// whose window starts at packed row r0, stage column tx of L and column rs
+// of the R part: sum over the packed rows and columns u of
+// L(u) . R(rs + u + e), e = 0, 1, 2.  The last packed row keeps the
+// win - 4 (NG - 1) rows inside the window; the chessboard window keeps the
+// bytes whose row and column have the parity of the window's corner.
+template <int WIN, bool CH>
+__device__ __forceinline__ void sp_sums(const uint32_t *Pk, int S, int QL, int r0, int tx, int rs,
+                                        int &sp, int &s0, int &sm) {
+  constexpr int NG = (WIN + 3) / 4, LAST = WIN - 4 * (NG - 1);
+  constexpr uint32_t lastmask = LAST == 4 ? 0xFFFFFFFFu : (1u << (8 * LAST)) - 1u;
   uint32_t a0 = 0, a1 = 0, a2 = 0;
-  // the window starts at byte tx of every L row and byte rs0 of every R row
-  const int lb = tx, rb = rs0;
-#pragma unroll 2
-  for (int v = 0; v < WIN; ++v) {
-    const int r = r0 + v;
-    const uint32_t *lw = (const uint32_t *)&Ls[r][lb & ~3];
-    const uint32_t *rw = (const uint32_t *)&Rs[r][rb & ~3];
-    uint32_t lt[NL + 1], rt[NR + 1];
 #pragma unroll
-    for (int i = 0; i <= NL; ++i) lt[i] = lw[i];
+  for (int g = 0; g < NG; ++g) {
+    const uint32_t *lrow = Pk + (r0 + 4 * g) * S + tx;
+    const uint32_t *rrow = Pk + (r0 + 4 * g) * S + 4 * QL + rs;
+    uint32_t rv[WIN + 2];
 #pragma unroll
-    for (int i = 0; i <= NR; ++i) rt[i] = rw[i];
-    const uint32_t cm = chess_mask(chess, v);
-    // l[0] = 0 (before the window), l[1 + i] = window dword i (0 past NL)
-    uint32_t l[NR + 1];
-    l[0] = 0;
+    for (int u = 0; u < WIN + 2; ++u) rv[u] = rrow[u];
 #pragma unroll
-    for (int i = 0; i < NR; ++i) {
-      uint32_t t = 0;
-      if (i < NL) {
-        t = __builtin_amdgcn_alignbyte(lt[i + 1], lt[i], lb & 3) & cm;
-        if (i == NL - 1) t &= lmask;
-      }
-      l[i + 1] = t;
+    for (int u = 0; u < WIN; ++u) {
+      uint32_t m = g == NG - 1 ? lastmask : 0xFFFFFFFFu;
+      if (CH) m &= (u & 1) ? 0xFF00FF00u : 0x00FF00FFu;
+      const uint32_t l = m == 0xFFFFFFFFu ? lrow[u] : lrow[u] & m;
+      a0 = __builtin_amdgcn_udot4(l, rv[u], a0, false);
+      a1 = __builtin_amdgcn_udot4(l, rv[u + 1], a1, false);
+      a2 = __builtin_amdgcn_udot4(l, rv[u + 2], a2, false);
     }
-#pragma unroll
-    for (int i = 0; i < NR; ++i) {
-      const uint32_t rr = __builtin_amdgcn_alignbyte(rt[i + 1], rt[i], rb & 3);
-      if (i < NL) a0 = __builtin_amdgcn_udot4(l[i + 1], rr, a0, false);
-      a1 = __builtin_amdgcn_udot4(__builtin_amdgcn_alignbyte(l[i + 1], l[i], 3), rr, a1, false);
-      a2 = __builtin_amdgcn_udot4(__builtin_amdgcn_alignbyte(l[i + 1], l[i], 2), rr, a2, false);
-    }
+    // one packed row at a time (2 win + 2 registers live): the products
+    // are formed here rather than sunk to the end of the window
+    asm volatile("" : "+v"(a0), "+v"(a1), "+v"(a2));
   }
   sp = (int)a0;
   s0 = (int)a1;
@@ -253,32 +264,113 @@ __device__ __forceinline__ int wave_max(int v) {
   return v;
 }
 
-__device__ __forceinline__ void subpixel_block(const PostPair &P, const BlockPos &bp) {
-  __shared__ __align__(16) uint8_t Ls[SPB_ROWS][SP_LROW];
-  __shared__ __align__(16) uint8_t Rs[SPB_ROWS][SP_RROW];
+// Per-pixel state of the sub-pixel block: the WTA disparity and whether it
+// is a valid candidate.
+struct SpPix {
+  int o[SP_NPT];
+  bool valid[SP_NPT];
+};
+
+template <int WIN, bool CH>
+__device__ __forceinline__ void sp_finish(const PostPair &P, const uint32_t *Pk, int S, int QL,
+                                          const SpPix &X, int tx, int ty, int x, int y0, int omax) {
+  const long long n = CH ? ((long long)WIN * WIN + 1) / 2 : (long long)WIN * WIN;
+  const double qn = __builtin_nan("");
+  const int W = P.W, H = P.H;
+#pragma unroll
+  for (int j = 0; j < SP_NPT; ++j) {
+    const int r0 = ty + 2 * j, y = y0 + r0;
+    if (x >= W || y >= H) continue;
+    const size_t k = (size_t)y * W + x;
+    if (!X.valid[j]) {
+      if (P.zbest) P.zbest[k] = qn;
+      if (P.zm) P.zm[k] = qn;
+      if (P.zp) P.zp[k] = qn;
+      P.delta[k] = 0.0f;
+      continue;
+    }
+    // window statistics: left at (x, y), right at x - d for d = o - 1, o,
+    // o + 1 (bit q of rok: d = o - 1 + q is a candidate whose right window
+    // is inside the image); issued before the sums, which hide their latency
+    const int o = X.o[j];
+    const int sli = P.SL[k], ssli = P.SSL[k];
+    int sri[3], ssri[3], rok = 0;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const int d = o + q - 1, xr = x - d;
+      const bool ok = d >= P.dmin && d <= P.dmax && xr >= WIN / 2 && xr <= W - 1 - WIN / 2;
+      const size_t kr = ok ? (size_t)y * W + xr : k;
+      sri[q] = P.SR[kr];
+      ssri[q] = P.SSR[kr];
+      rok |= ok ? 1 << q : 0;
+    }
+    // window column u at d = o + 1 - e is R stage column rs + e + u
+    int sm = 0, s0 = 0, sp = 0;  // sums at d = o - 1, o, o + 1
+    sp_sums<WIN, CH>(Pk, S, QL, r0, tx, tx + omax - o, sp, s0, sm);
+    // the sums are formed here, interleaved, not sunk into the branches
+    // below that use them (which would keep every LDS value live)
+    asm volatile("" ::"v"(sp), "v"(s0), "v"(sm));
+    // varN = n S2 - S1^2 and num = n S_LR - S_L S_R in FP64: every product
+    // and difference is an integer below 2^40, so exact.  z = num /
+    // sqrt(varN_L varN_R) as num * rsqrt(varN_L varN_R): within a few ulp of
+    // the quotient, without the FP64 division.
+    const double nd = (double)n, sl = (double)sli;
+    const double varL = fma(nd, (double)ssli, -(sl * sl));
+    const int slr[3] = {sm, s0, sp};
+    double z[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      z[q] = qn;
+      if (!((rok >> q) & 1)) continue;
+      const double sr = (double)sri[q];
+      const double varR = fma(nd, (double)ssri[q], -(sr * sr));
+      if (varR <= 0.0) continue;
+      const double num = fma(nd, (double)slr[q], -(sl * sr));
+      z[q] = num * rsqrt(varL * varR);
+    }
+    if (P.zbest) P.zbest[k] = z[1];
+    if (P.zm) P.zm[k] = z[0];
+    if (P.zp) P.zp[k] = z[2];
+    double dl = 0.0;
+    if (o > P.dmin && o < P.dmax && !__builtin_isnan(z[0]) && !__builtin_isnan(z[2])) {
+      const double den = 2.0 * (z[0] - 2.0 * z[1] + z[2]);
+      if (den < 0.0) {
+        dl = (z[0] - z[2]) / den;
+        dl = dl > 0.5 ? 0.5 : (dl < -0.5 ? -0.5 : dl);
+      }
+    }
+    P.delta[k] = (float)dl;
+    // one pixel's LDS reads at a time: hoisting the next pixel's reads
+    // above this one's sums would hold them all in registers
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+// Pk: the packed stage in dynamic LDS, sp_lds_bytes(win, dmax - dmin + 1)
+// bytes at least.
+__device__ __forceinline__ void subpixel_block(const PostPair &P, const BlockPos &bp, uint32_t *Pk) {
   __shared__ int s_omin, s_omax;
   const int tid = threadIdx.x, tx = tid & (SP_TX - 1), ty = tid / SP_TX;
   const int x0 = bp.x * SP_TX, y0 = bp.y * SPB_TY;
   if (x0 >= P.W || y0 >= P.H) return;  // uniform per block
   const int W = P.W, H = P.H, win = P.win, h = win / 2;
   const int x = x0 + tx;
-  constexpr int NPT = SPB_TY * SP_TX / SPB_T;  // pixels per thread: rows y0 + ty + 2 j
-  int o[NPT];
-  bool valid[NPT];
+  SpPix X;
   int lo = 1 << 30, hi = -(1 << 30);
 #pragma unroll
-  for (int j = 0; j < NPT; ++j) {
+  for (int j = 0; j < SP_NPT; ++j) {
     const int y = y0 + ty + 2 * j;
     const bool in = x < W && y < H;
     const size_t k = (size_t)y * W + x;
-    o[j] = in ? (int)P.ob[0][k] : 0;
+    X.o[j] = in ? (int)P.ob[0][k] : 0;
+    const bool mk = in && P.mb[0][k];
     // a disparity outside [dmin, dmax] counts as unmatched: the staged R
     // columns cover the range only
-    valid[j] = in && P.mb[0][k] && o[j] >= P.dmin && o[j] <= P.dmax;
-    if (!valid[j]) o[j] = 0;
-    if (valid[j]) {
-      lo = min(lo, o[j]);
-      hi = max(hi, o[j]);
+    X.valid[j] = mk && X.o[j] >= P.dmin && X.o[j] <= P.dmax;
+    if (!X.valid[j]) X.o[j] = 0;
+    if (X.valid[j]) {
+      lo = min(lo, X.o[j]);
+      hi = max(hi, X.o[j]);
     }
   }
   if (tid == 0) {
@@ -294,104 +386,79 @@ __device__ __forceinline__ void subpixel_block(const PostPair &P, const BlockPos
   }
   __syncthreads();
   const int omin = s_omin, omax = s_omax;
-  const double qn = __builtin_nan("");
+  const int QL = sp_quads_l(win), QR = omin <= omax ? sp_quads_r(win, omax - omin) : 0;
+  const int S = 4 * (QL + QR);
   if (omin <= omax) {
-    // Ls[r][c] = L(y0-h+r, x0-h+c), Rs[r][c] = R(y0-h+r, x0-omax-1-h+c).
-    // Bytes of columns outside the image only enter sums whose z is
-    // discarded (a valid pixel's windows at o lie inside the image).
-    const int LW = SP_TX + 2 * h, RW = SP_TX + (omax - omin) + 2 + 2 * h;
-    const int nrows = min(SPB_TY, H - y0) + 2 * h;
-    stage_rows(Ls, Rs, gro(P.left), gro(P.right), P.pitch,
-               (long long)(H - 1) * P.pitch + W, H, y0 - h, nrows, x0 - h, LW, x0 - omax - 1 - h,
-               RW, tid, SPB_T);
+    // a valid pixel's window rows lie inside the band's rows plus the halo
+    const int PR = min(SPB_TY, H - y0) + 4 * (sp_groups(win) - 1);
+    sp_pack(Pk, S, PR, gro(P.left), gro(P.right), P.pitch, (long long)(H - 1) * P.pitch + W, y0 - h,
+            x0 - h, QL, x0 - omax - 1 - h, QR, tid);
   }
   __syncthreads();
-  const long long n = P.chess ? ((long long)win * win + 1) / 2 : (long long)win * win;
-#pragma unroll
-  for (int j = 0; j < NPT; ++j) {
-    const int r0 = ty + 2 * j, y = y0 + r0;
-    if (x >= W || y >= H) continue;
-    const size_t k = (size_t)y * W + x;
-    if (!valid[j]) {
-      if (P.zbest) P.zbest[k] = qn;
-      if (P.zm) P.zm[k] = qn;
-      if (P.zp) P.zp[k] = qn;
-      P.delta[k] = 0.0f;
-      continue;
-    }
-    // window column u of the thread at d = o + 1 - e is Rs[r][rs + e + u]
-    const int rs = tx + omax - o[j];
-    int sm = 0, s0 = 0, sp = 0;  // sums at d = o - 1, o, o + 1
-    switch (win) {
-      case 3: sp_sums<3>(Ls, Rs, P.chess, r0, tx, rs, sp, s0, sm); break;
-      case 5: sp_sums<5>(Ls, Rs, P.chess, r0, tx, rs, sp, s0, sm); break;
-      case 7: sp_sums<7>(Ls, Rs, P.chess, r0, tx, rs, sp, s0, sm); break;
-      case 9: sp_sums<9>(Ls, Rs, P.chess, r0, tx, rs, sp, s0, sm); break;
-      case 11: sp_sums<11>(Ls, Rs, P.chess, r0, tx, rs, sp, s0, sm); break;
-      case 13: sp_sums<13>(Ls, Rs, P.chess, r0, tx, rs, sp, s0, sm); break;
-      default: sp_sums<15>(Ls, Rs, P.chess, r0, tx, rs, sp, s0, sm); break;
-    }
-    const long long sl = P.SL[k];
-    const long long varL = n * (long long)P.SSL[k] - sl * sl;
-    // z = num / sqrt(varN_L varN_R) as num * rsqrt(varN_L) * rsqrt(varN_R):
-    // within a few ulp of the quotient, without the FP64 division
-    const double rl = rsqrt((double)varL);
-    const int slr[3] = {sm, s0, sp};
-    double z[3];
-    for (int q = 0; q < 3; ++q) {
-      const int d = o[j] + q - 1;
-      const int xr = x - d;
-      z[q] = qn;
-      if (d < P.dmin || d > P.dmax || xr < h || xr > W - 1 - h) continue;
-      const size_t kr = (size_t)y * W + xr;
-      const long long sr = P.SR[kr];
-      const long long varR = n * (long long)P.SSR[kr] - sr * sr;
-      if (varR <= 0) continue;
-      const long long num = n * (long long)slr[q] - sl * sr;
-      z[q] = (double)num * rl * rsqrt((double)varR);
-    }
-    if (P.zbest) P.zbest[k] = z[1];
-    if (P.zm) P.zm[k] = z[0];
-    if (P.zp) P.zp[k] = z[2];
-    double dl = 0.0;
-    if (o[j] > P.dmin && o[j] < P.dmax && !__builtin_isnan(z[0]) && !__builtin_isnan(z[2])) {
-      const double den = 2.0 * (z[0] - 2.0 * z[1] + z[2]);
-      if (den < 0.0) {
-        dl = (z[0] - z[2]) / den;
-        dl = dl > 0.5 ? 0.5 : (dl < -0.5 ? -0.5 : dl);
-      }
-    }
-    P.delta[k] = (float)dl;
+#define SPF(w)                                                               \
+  case w:                                                                    \
+    if (P.chess) sp_finish<w, true>(P, Pk, S, QL, X, tx, ty, x, y0, omax);   \
+    else sp_finish<w, false>(P, Pk, S, QL, X, tx, ty, x, y0, omax);          \
+    break
+  switch (win) {
+    SPF(3);
+    SPF(5);
+    SPF(7);
+    SPF(9);
+    SPF(11);
+    SPF(13);
+    default:
+      if (P.chess) sp_finish<15, true>(P, Pk, S, QL, X, tx, ty, x, y0, omax);
+      else sp_finish<15, false>(P, Pk, S, QL, X, tx, ty, x, y0, omax);
+      break;
   }
+#undef SPF
 }
+
+extern __shared__ __align__(16) uint32_t sp_dyn[];
 
 template <bool B>
 __global__ __launch_bounds__(SPB_T) void subpixel_kernel(PostPair one, const PostPair *__restrict__ many) {
   PAIR;
-  subpixel_block(P, bp);
+  subpixel_block(P, bp, sp_dyn);
 }
 
 // ---------------------------------------------------------------- LR check
 // (ob[0], mb[0]) and (oR, mR) -> (ob[dst], mb[dst]): kept when the right
 // pixel x - oL points back within tol.
 __device__ __forceinline__ void lr_check_block(const PostPair &P, const BlockPos &bp, int tol, int dst) {
-  const int W = P.W, H = P.H;
-  (void)W;
-  (void)H;
-  for_pixels(P, bp, [&](int x, int y, size_t k) {
-    const int16_t *oL = P.ob[0];
-    uint8_t keep = 0;
-    if (P.mb[0][k]) {
-      const int xr = x - oL[k];
-      if (xr >= 0 && xr < W) {
-        const size_t kr = (size_t)y * W + xr;
-        const int diff = (int)oL[k] - (int)P.oR[kr];
-        if (P.mR[kr] && (diff < 0 ? -diff : diff) <= tol) keep = 1;
-      }
-    }
-    P.ob[dst][k] = keep ? oL[k] : O_NONE;
-    P.mb[dst][k] = keep;
-  });
+  // four consecutive pixels per thread (PIX_SEG = 4 PIX_T columns per
+  // block): the left maps of all four are read together, then the four right
+  // pixels they point at, so a thread waits for two round trips
+  const int W = P.W, y = bp.y;
+  if (y >= P.H) return;
+  const int xb = bp.x * PIX_SEG + 4 * (int)threadIdx.x;
+  const size_t row = (size_t)y * W;
+  int o[4], m[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int x = xb + i;
+    o[i] = x < W ? (int)P.ob[0][row + x] : 0;
+    m[i] = x < W ? (int)P.mb[0][row + x] : 0;
+  }
+  int orr[4], mrr[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int xr = xb + i - o[i];
+    const bool in = m[i] && xr >= 0 && xr < W;
+    const size_t kr = row + (in ? xr : 0);
+    orr[i] = in ? (int)P.oR[kr] : 0;
+    mrr[i] = in ? (int)P.mR[kr] : 0;
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int x = xb + i;
+    if (x >= W) break;
+    const int diff = o[i] - orr[i];
+    const bool keep = m[i] && mrr[i] && (diff < 0 ? -diff : diff) <= tol;
+    P.ob[dst][row + x] = keep ? (int16_t)o[i] : O_NONE;
+    P.mb[dst][row + x] = keep ? 1 : 0;
+  }
 }
 template <bool B>
 __global__ void lr_check_kernel(PostPair one, const PostPair *__restrict__ many, int tol, int dst) {
@@ -410,7 +477,7 @@ __global__ __launch_bounds__(SPB_T) void subpixel_lr_kernel(PostPair one, const 
   if (bp.x < nsp) {
     q.x = bp.x % nspx;
     q.y = bp.x / nspx;
-    subpixel_block(P, q);
+    subpixel_block(P, q, sp_dyn);
   } else {
     const int i = bp.x - nsp;
     q.x = i % nlrx;
@@ -1488,13 +1555,25 @@ hipError_t post_decode(const PostLaunch &L) {
   return hipGetLastError();
 }
 hipError_t post_subpixel(const PostLaunch &L) {
-  LAUNCH(subpixel_kernel, dim3(ceil_div(L.maxW, SP_TX), ceil_div(L.maxH, SPB_TY), L.npairs), dim3(SPB_T));
+  const dim3 grid(ceil_div(L.maxW, SP_TX), ceil_div(L.maxH, SPB_TY), L.npairs);
+  const size_t lds = sp_lds_bytes(L.maxWin, L.maxD);
+  if (L.many)
+    hipLaunchKernelGGL(subpixel_kernel<true>, grid, dim3(SPB_T), lds, L.s, L.one, L.many);
+  else
+    hipLaunchKernelGGL(subpixel_kernel<false>, grid, dim3(SPB_T), lds, L.s, L.one, L.many);
   return hipGetLastError();
 }
 hipError_t post_subpixel_lr(const PostLaunch &L, int tol, int dst) {
   const int nspx = ceil_div(L.maxW, SP_TX), nsp = nspx * ceil_div(L.maxH, SPB_TY);
   const int nlrx = ceil_div(L.maxW, PIX_SEG), nlr = nlrx * L.maxH;
-  LAUNCH(subpixel_lr_kernel, dim3(nsp + nlr, 1, L.npairs), dim3(SPB_T), nspx, nsp, nlrx, tol, dst);
+  const dim3 grid(nsp + nlr, 1, L.npairs);
+  const size_t lds = sp_lds_bytes(L.maxWin, L.maxD);
+  if (L.many)
+    hipLaunchKernelGGL(subpixel_lr_kernel<true>, grid, dim3(SPB_T), lds, L.s, L.one, L.many, nspx, nsp,
+                       nlrx, tol, dst);
+  else
+    hipLaunchKernelGGL(subpixel_lr_kernel<false>, grid, dim3(SPB_T), lds, L.s, L.one, L.many, nspx, nsp,
+                       nlrx, tol, dst);
   return hipGetLastError();
 }
 hipError_t post_lr(const PostLaunch &L, int tol, int dst) {
