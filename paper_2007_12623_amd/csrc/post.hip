@@ -521,70 +521,98 @@ __device__ __forceinline__ bool step_holds(int o_near, int o_far, bool m_far, fl
   return m_far && (float)(dv < 0 ? -dv : dv) < thresh;
 }
 
+// The 64-column blocks b0 .. b0 + RCH - 1 of a row, one int16 disparity per
+// lane and block (O_NONE outside the row): the loads of a whole chunk issue
+// together, so a sweep over a row of up to 64 RCH columns waits for one
+// memory round trip rather than one per block.
+constexpr int RCH = 16;
+__device__ __forceinline__ void row_chunk(const GLOBAL int16_t *o, int W, int b0, int lane, int (&ov)[RCH]) {
+#pragma unroll
+  for (int i = 0; i < RCH; ++i) {
+    const int x = 64 * (b0 + i) + lane;
+    ov[i] = x < W ? (int)o[x] : (int)O_NONE;
+  }
+}
+
 // Outlier test along rows: db = distance from x back to the last break at or
 // before x (the step x -> x-1 fails, or x = 0), df = distance to the first
 // break at or after x (the step x -> x+1 fails, or x = W-1); bit 0 of pass
 // is df >= r, bit 1 db >= r.  The backward bits of the first sweep wait in a
 // register mask, one bit per block, when W <= 64 * 64; wider rows keep them
-// in pass itself.
+// in pass itself.  Chunks of RCH blocks are swept from registers; a row of
+// one chunk is loaded once for both sweeps.
 __device__ __forceinline__ void outlier_rows(const PostPair &P, int bx, int r, float thresh, int src) {
   const int H = P.H, W = P.W;
   const int lane = threadIdx.x & 63, y = bx * 4 + (threadIdx.x >> 6);
   if (y >= H) return;  // whole wave
   const GLOBAL int16_t *o = gro(P.ob[src]) + (size_t)y * W;  // O_NONE where invalid
   GLOBAL uint8_t *pass = grw(P.pass) + (size_t)y * W;
-  const int nb = ceil_div(W, 64);
+  const int nb = ceil_div(W, 64), last = (nb - 1) / RCH * RCH;
   const bool inreg = nb <= 64;
   uint64_t dbits = 0;
+  int ov[RCH];
   int lastb = -(1 << 30), co = 0, cm = 0;  // carried: last break, o and m of column 64 b - 1
-  for (int b = 0; b < nb; ++b) {
-    const int x = 64 * b + lane;
-    const bool in = x < W;
-    const int ov = in ? o[x] : O_NONE, mv = ov != O_NONE ? 1 : 0;
-    int on = __shfl_up(ov, 1, 64), mn = __shfl_up(mv, 1, 64);
-    if (lane == 0) {
-      on = co;
-      mn = cm;
+  for (int c0 = 0; c0 < nb; c0 += RCH) {
+    row_chunk(o, W, c0, lane, ov);
+#pragma unroll
+    for (int i = 0; i < RCH; ++i) {
+      const int b = c0 + i;
+      if (b >= nb) break;  // uniform
+      const int x = 64 * b + lane;
+      const bool in = x < W;
+      const int mv = ov[i] != O_NONE ? 1 : 0;
+      int on = __shfl_up(ov[i], 1, 64), mn = __shfl_up(mv, 1, 64);
+      if (lane == 0) {
+        on = co;
+        mn = cm;
+      }
+      const uint64_t bm = ballot64(in && (x == 0 || !step_holds(ov[i], on, mn, thresh)));
+      const uint64_t low = bm & lanes_upto(lane);
+      const int lb = low ? 64 * b + top64(low) : lastb;
+      if (inreg) {
+        if (x - lb >= r) dbits |= 1ull << b;
+      } else if (in && mv) {
+        pass[x] = x - lb >= r ? 2 : 0;
+      }
+      if (bm) lastb = 64 * b + top64(bm);
+      co = __shfl(ov[i], 63, 64);
+      cm = __shfl(mv, 63, 64);
     }
-    const uint64_t bm = ballot64(in && (x == 0 || !step_holds(ov, on, mn, thresh)));
-    const uint64_t low = bm & lanes_upto(lane);
-    const int lb = low ? 64 * b + top64(low) : lastb;
-    if (inreg) {
-      if (x - lb >= r) dbits |= 1ull << b;
-    } else if (in && mv) {
-      pass[x] = x - lb >= r ? 2 : 0;
-    }
-    if (bm) lastb = 64 * b + top64(bm);
-    co = __shfl(ov, 63, 64);
-    cm = __shfl(mv, 63, 64);
   }
   int nextb = 1 << 30;
   co = 0;
   cm = 0;  // o and m of column 64 (b + 1)
-  for (int b = nb - 1; b >= 0; --b) {
-    const int x = 64 * b + lane;
-    const bool in = x < W;
-    const int ov = in ? o[x] : O_NONE, mv = ov != O_NONE ? 1 : 0;
-    int on = __shfl_down(ov, 1, 64), mn = __shfl_down(mv, 1, 64);
-    if (lane == 63) {
-      on = co;
-      mn = cm;
+  for (int c0 = last; c0 >= 0; c0 -= RCH) {
+    if (nb > RCH) row_chunk(o, W, c0, lane, ov);
+#pragma unroll
+    for (int i = RCH - 1; i >= 0; --i) {
+      const int b = c0 + i;
+      if (b >= nb) continue;  // uniform
+      const int x = 64 * b + lane;
+      const bool in = x < W;
+      const int mv = ov[i] != O_NONE ? 1 : 0;
+      int on = __shfl_down(ov[i], 1, 64), mn = __shfl_down(mv, 1, 64);
+      if (lane == 63) {
+        on = co;
+        mn = cm;
+      }
+      const uint64_t bm = ballot64(in && (x + 1 >= W || !step_holds(ov[i], on, mn, thresh)));
+      const uint64_t rest = bm & ~lanes_below(lane);
+      const int fb = rest ? 64 * b + ctz64(rest) : nextb;
+      if (in && mv) {
+        const int bbit = inreg ? (((dbits >> b) & 1) ? 2 : 0) : pass[x];
+        pass[x] = (fb - x >= r ? 1 : 0) | bbit;
+      }
+      if (bm) nextb = 64 * b + ctz64(bm);
+      co = __shfl(ov[i], 0, 64);
+      cm = __shfl(mv, 0, 64);
     }
-    const uint64_t bm = ballot64(in && (x + 1 >= W || !step_holds(ov, on, mn, thresh)));
-    const uint64_t rest = bm & ~lanes_below(lane);
-    const int fb = rest ? 64 * b + ctz64(rest) : nextb;
-    if (in && mv) {
-      const int bbit = inreg ? (((dbits >> b) & 1) ? 2 : 0) : pass[x];
-      pass[x] = (fb - x >= r ? 1 : 0) | bbit;
-    }
-    if (bm) nextb = 64 * b + ctz64(bm);
-    co = __shfl(ov, 0, 64);
-    cm = __shfl(mv, 0, 64);
   }
 }
 
 // Nearest valid pixel along rows for the holes: hits[0] to the right
-// (forward), hits[1] to the left, within R.
+// (forward), hits[1] to the left, within R.  Swept from registers in chunks
+// of RCH blocks, as the outlier rows are.
 __device__ __forceinline__ void fill_rows(const PostPair &P, int bx, int R, int src) {
   const int H = P.H, W = P.W;
   const int lane = threadIdx.x & 63, y = bx * 4 + (threadIdx.x >> 6);
@@ -593,39 +621,50 @@ __device__ __forceinline__ void fill_rows(const PostPair &P, int bx, int R, int 
   const size_t N = (size_t)W * H;
   GLOBAL uint32_t *hf = grw(P.hits) + (size_t)y * W;
   GLOBAL uint32_t *hb = grw(P.hits) + N + (size_t)y * W;
-  const int nb = ceil_div(W, 64);
+  const int nb = ceil_div(W, 64), last = (nb - 1) / RCH * RCH;
   auto hit = [&](int q, int oq, int x) -> uint32_t {
     const int dq = q > x ? q - x : x - q;
     return (q >= 0 && dq <= R) ? ((uint32_t)dq << 16) | (uint16_t)oq : 0u;
   };
+  int ov[RCH];
   int lastv = -1, lasto = 0;  // carried: last valid column left of the block
-  for (int b = 0; b < nb; ++b) {
-    const int x = 64 * b + lane;
-    const bool in = x < W;
-    const int ov = in ? o[x] : O_NONE;
-    const bool mv = ov != O_NONE;
-    const uint64_t vm = ballot64(mv);
-    const uint64_t low = vm & lanes_below(lane);
-    const int oq = __shfl(ov, low ? top64(low) : 0, 64);
-    if (in && !mv) hb[x] = low ? hit(64 * b + top64(low), oq, x) : hit(lastv, lasto, x);
-    if (vm) {
-      lastv = 64 * b + top64(vm);
-      lasto = __shfl(ov, top64(vm), 64);
+  for (int c0 = 0; c0 < nb; c0 += RCH) {
+    row_chunk(o, W, c0, lane, ov);
+#pragma unroll
+    for (int i = 0; i < RCH; ++i) {
+      const int b = c0 + i;
+      if (b >= nb) break;  // uniform
+      const int x = 64 * b + lane;
+      const bool in = x < W;
+      const bool mv = ov[i] != O_NONE;
+      const uint64_t vm = ballot64(mv);
+      const uint64_t low = vm & lanes_below(lane);
+      const int oq = __shfl(ov[i], low ? top64(low) : 0, 64);
+      if (in && !mv) hb[x] = low ? hit(64 * b + top64(low), oq, x) : hit(lastv, lasto, x);
+      if (vm) {
+        lastv = 64 * b + top64(vm);
+        lasto = __shfl(ov[i], top64(vm), 64);
+      }
     }
   }
   int nextv = -1, nexto = 0;  // carried: first valid column right of the block
-  for (int b = nb - 1; b >= 0; --b) {
-    const int x = 64 * b + lane;
-    const bool in = x < W;
-    const int ov = in ? o[x] : O_NONE;
-    const bool mv = ov != O_NONE;
-    const uint64_t vm = ballot64(mv);
-    const uint64_t rest = vm & lanes_above(lane);
-    const int oq = __shfl(ov, rest ? ctz64(rest) : 0, 64);
-    if (in && !mv) hf[x] = rest ? hit(64 * b + ctz64(rest), oq, x) : hit(nextv, nexto, x);
-    if (vm) {
-      nextv = 64 * b + ctz64(vm);
-      nexto = __shfl(ov, ctz64(vm), 64);
+  for (int c0 = last; c0 >= 0; c0 -= RCH) {
+    if (nb > RCH) row_chunk(o, W, c0, lane, ov);
+#pragma unroll
+    for (int i = RCH - 1; i >= 0; --i) {
+      const int b = c0 + i;
+      if (b >= nb) continue;  // uniform
+      const int x = 64 * b + lane;
+      const bool in = x < W;
+      const bool mv = ov[i] != O_NONE;
+      const uint64_t vm = ballot64(mv);
+      const uint64_t rest = vm & lanes_above(lane);
+      const int oq = __shfl(ov[i], rest ? ctz64(rest) : 0, 64);
+      if (in && !mv) hf[x] = rest ? hit(64 * b + ctz64(rest), oq, x) : hit(nextv, nexto, x);
+      if (vm) {
+        nextv = 64 * b + ctz64(vm);
+        nexto = __shfl(ov[i], ctz64(vm), 64);
+      }
     }
   }
 }

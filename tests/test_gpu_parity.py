@@ -164,10 +164,12 @@ def test_lr_check_stage(B, orc):
         assert np.array_equal(g, orc.lr_check(ref["oL"], ref["mL"], ref["oR"], ref["mR"], tol))
 
 
-@pytest.mark.parametrize("H,W", [(140, 330), (300, 70), (23, 700)])
+@pytest.mark.parametrize("H,W", [(140, 330), (300, 70), (23, 700), (19, 1100), (12, 2100), (7, 4200)])
 def test_outlier_and_fill_stages(B, orc, H, W):
-    """Rows, columns and both diagonals cut into 64-pixel scan segments:
-    shapes with lines shorter and longer than one segment."""
+    """Rows, columns and both diagonals cut into scan segments: shapes with
+    lines shorter and longer than one segment, and rows of one, two and
+    several register chunks of 16 x 64 columns (the last past 64 blocks,
+    where the outlier rows keep their backward bits in memory)."""
     L, R = _pair(H, W, 31, 42)
     ref = orc.match(L, R, 0, 31, 7)
     m = orc.lr_check(ref["oL"], ref["mL"], ref["oR"], ref["mR"], 1)
