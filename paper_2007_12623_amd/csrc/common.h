@@ -21,6 +21,34 @@ constexpr int KC = 8;         // image columns owned by one lane of the matcher
 constexpr int OUT_LANES = 62; // lanes 1..62 of a wave produce output; 0 and 63 are halos
 constexpr int NWAVE = 4;      // waves of a matcher workgroup
 
+// Inclusive prefix sum over the 64 lanes of a wave through DPP moves, with
+// no LDS round trip: Hillis-Steele over each row of 16 lanes with row shifts
+// of 1, 2, 4 and 8 (lanes shifted in from outside the row read 0), then the
+// total of row 0 added to row 1 and of row 2 to row 3 (row_bcast:15), and
+// the total of rows 0-1 to rows 2 and 3 (row_bcast:31).  Lanes a step does
+// not write keep 0, so the step adds 0 there.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int dpp_take(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, ROWS, 0xF, true);
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_take(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)dpp_take<CTRL, ROWS>((int)(unsigned)b);
+  const unsigned hi = (unsigned)dpp_take<CTRL, ROWS>((int)(unsigned)(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+template <class T>
+__device__ __forceinline__ T wave_scan_incl(T v) {
+  v += dpp_take<0x111, 0xF>(v);  // row_shr:1
+  v += dpp_take<0x112, 0xF>(v);  // row_shr:2
+  v += dpp_take<0x114, 0xF>(v);  // row_shr:4
+  v += dpp_take<0x118, 0xF>(v);  // row_shr:8
+  v += dpp_take<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp_take<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+  return v;
+}
+
 enum Prec { P_I16 = 0, P_F16 = 1, P_BF16 = 2 };
 
 // Disparity stored at pixels without a valid one in the integer disparity

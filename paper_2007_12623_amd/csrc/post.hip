@@ -521,6 +521,15 @@ __device__ __forceinline__ bool step_holds(int o_near, int o_far, bool m_far, fl
   return m_far && (float)(dv < 0 ? -dv : dv) < thresh;
 }
 
+// The same test against an integer bound: for an integer dv, |dv| < thresh
+// exactly when |dv| <= ceil(thresh) - 1; a bound below 0 lets no step hold.
+__device__ __forceinline__ int step_bound(float thresh) {
+  return thresh >= 1048576.0f ? 1048576 : thresh > 0.0f ? (int)ceilf(thresh) - 1 : -1;
+}
+__device__ __forceinline__ bool step_ok(int o_near, int o_far, bool m_far, int ti) {
+  return m_far && ti >= 0 && (unsigned)(o_far - o_near + ti) <= (unsigned)(2 * ti);
+}
+
 // The 64-column blocks b0 .. b0 + RCH - 1 of a row, one int16 disparity per
 // lane and block (O_NONE outside the row): the loads of a whole chunk issue
 // together, so a sweep over a row of up to 64 RCH columns waits for one
@@ -606,6 +615,64 @@ __device__ __forceinline__ void outlier_rows(const PostPair &P, int bx, int r, f
       if (bm) nextb = 64 * b + ctz64(bm);
       co = __shfl(ov[i], 0, 64);
       cm = __shfl(mv, 0, 64);
+    }
+  }
+}
+
+// Outlier rows for r <= 63, bit-parallel: per 64-column block, ballots give
+// the masks of forward breaks (the step x -> x+1 fails, or x = W-1) and of
+// backward breaks (x -> x-1 fails, or x = 0).  Bit 0 of pass (df >= r) is
+// that bits x .. x + r - 1 of the forward mask are clear, bit 1 (db >= r)
+// that bits x - r + 1 .. x of the backward mask are; each window is one
+// 64-bit funnel shift of the masks of two neighbouring blocks.  A chunk of
+// RCB blocks is loaded with one block more on either side; the outermost
+// lanes of those two, whose masks would need a third block, are never read
+// (r <= 63).
+constexpr int RCB = 8;  // blocks per chunk of the bit-parallel rows (register budget)
+__device__ __forceinline__ void outlier_rows_bits(const PostPair &P, int bx, int r, int ti, int src) {
+  const int H = P.H, W = P.W;
+  const int lane = threadIdx.x & 63, y = bx * 4 + (threadIdx.x >> 6);
+  if (y >= H) return;  // whole wave
+  const GLOBAL int16_t *o = gro(P.ob[src]) + (size_t)y * W;  // O_NONE where invalid
+  GLOBAL uint8_t *pass = grw(P.pass) + (size_t)y * W;
+  const int nb = ceil_div(W, 64);
+  const uint64_t rmask = (1ull << r) - 1;
+  for (int c0 = 0; c0 < nb; c0 += RCB) {
+    int ov[RCB + 2];  // blocks c0 - 1 .. c0 + RCB
+#pragma unroll
+    for (int i = 0; i < RCB + 2; ++i) {
+      const int x = 64 * (c0 - 1 + i) + lane;
+      ov[i] = x >= 0 && x < W ? (int)o[x] : (int)O_NONE;
+    }
+    auto masks = [&](int i, uint64_t &fm, uint64_t &bm) {
+      const int x = 64 * (c0 - 1 + i) + lane;
+      const bool in = x >= 0 && x < W;
+      // every shuffle with all lanes active: a lane reading an inactive one
+      // gets 0
+      int nx = __shfl_down(ov[i], 1, 64), pv = __shfl_up(ov[i], 1, 64);
+      const int n0 = i + 1 < RCB + 2 ? __shfl(ov[i + 1], 0, 64) : (int)O_NONE;
+      const int p63 = i > 0 ? __shfl(ov[i - 1], 63, 64) : (int)O_NONE;
+      if (lane == 63) nx = n0;
+      if (lane == 0) pv = p63;
+      fm = ballot64(in && (x == W - 1 || !step_ok(ov[i], nx, nx != O_NONE, ti)));
+      bm = ballot64(in && (x == 0 || !step_ok(ov[i], pv, pv != O_NONE, ti)));
+    };
+    uint64_t fA, bA, fB, bB, fC, bC;  // masks of blocks i - 1, i, i + 1
+    masks(0, fA, bA);
+    masks(1, fB, bB);
+#pragma unroll
+    for (int i = 1; i <= RCB; ++i) {
+      masks(i + 1, fC, bC);
+      const int x = 64 * (c0 - 1 + i) + lane;
+      if (x < W && ov[i] != O_NONE) {
+        const uint64_t wf = lane ? (fB >> lane) | (fC << (64 - lane)) : fB;
+        const uint64_t wb = lane < 63 ? (bB << (63 - lane)) | (bA >> (lane + 1)) : bB;
+        pass[x] = ((wf & rmask) == 0 ? 1 : 0) | ((wb >> (64 - r)) == 0 ? 2 : 0);
+      }
+      fA = fB;
+      bA = bB;
+      fB = fC;
+      bB = bC;
     }
   }
 }
@@ -717,10 +784,9 @@ __device__ __forceinline__ void outlier_vscan(const PostPair &P, int bx, int r, 
   const GLOBAL int16_t *__restrict__ o = gro(P.ob[src]);  // O_NONE where invalid
   GLOBAL uint8_t *__restrict__ pass = grw(P.pass) + (size_t)t * W * H;
   // run = consecutive good steps from y along the scan direction, capped at r
+  const int ti = step_bound(thresh);
   auto step = [&](int op, int onb, bool vnb, int run) {
-    const int dv = onb - op;
-    const bool good = vnb & ((float)(dv < 0 ? -dv : dv) < thresh);
-    return good ? min(run + 1, r) : 0;
+    return step_ok(op, onb, vnb, ti) ? min(run + 1, r) : 0;
   };
   // forward results of the own rows wait in a bit mask (bit y - a) and are
   // stored with the backward ones
@@ -845,8 +911,12 @@ template <bool B>
 __global__ __launch_bounds__(256) void outlier_scan_kernel(PostPair one, const PostPair *__restrict__ many,
                                                           int r, float thresh, int src, int nrow) {
   PAIR;
-  if (bp.x < nrow) outlier_rows(P, bp.x, r, thresh, src);
-  else outlier_vscan(P, bp.x - nrow, r, thresh, src);
+  if (bp.x < nrow) {
+    if (r <= 63) outlier_rows_bits(P, bp.x, r, step_bound(thresh), src);
+    else outlier_rows(P, bp.x, r, thresh, src);
+  } else {
+    outlier_vscan(P, bp.x - nrow, r, thresh, src);
+  }
 }
 template <bool B>
 __global__ __launch_bounds__(256) void fill_scan_kernel(PostPair one, const PostPair *__restrict__ many,
@@ -933,15 +1003,7 @@ __global__ __launch_bounds__(256) void fill_radial_kernel(PostPair one, const Po
       grw(P.ob[dst])[k] = (int16_t)ov;
       grw(P.mb[dst])[k] = (uint8_t)mv;
     }
-    int c = mv ? 1 : 0, sv = mv ? ov : 0;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-      const int uc = __shfl_up(c, off, 64), us = __shfl_up(sv, off, 64);
-      if (lane >= off) {
-        c += uc;
-        sv += us;
-      }
-    }
+    const int c = wave_scan_incl(mv ? 1 : 0), sv = wave_scan_incl(mv ? ov : 0);
     if (lane == 63) {
       wc[wave] = c;
       wsum[wave] = sv;
@@ -1303,15 +1365,8 @@ __global__ __launch_bounds__(BX_T) void box2d_kernel(PostPair one, const PostPai
       sc += q.addc;
       pc = sc;
     }
-#pragma unroll
-    for (int o = 1; o < WV; o <<= 1) {
-      const double u = __shfl_up(p, o, WV);
-      if (lane >= o) p += u;
-      if constexpr (CNT) {
-        const int uc = __shfl_up(pc, o, WV);
-        if (lane >= o) pc += uc;
-      }
-    }
+    p = wave_scan_incl(p);
+    if constexpr (CNT) pc = wave_scan_incl(pc);
     pf[b][t] = p;
     if (lane == WV - 1) wt[b][wave] = p;
     if constexpr (CNT) {

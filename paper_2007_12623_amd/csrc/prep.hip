@@ -112,15 +112,7 @@ template <int N>
 __device__ __forceinline__ void block_prefix(int (&a)[N], int (*wt)[4]) {
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
 #pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    int u[N];
-#pragma unroll
-    for (int i = 0; i < N; ++i) u[i] = __shfl_up(a[i], o, 64);
-    if (lane >= o) {
-#pragma unroll
-      for (int i = 0; i < N; ++i) a[i] += u[i];
-    }
-  }
+  for (int i = 0; i < N; ++i) a[i] = wave_scan_incl(a[i]);
   if (lane == 63) {
 #pragma unroll
     for (int i = 0; i < N; ++i) wt[i][wave] = a[i];

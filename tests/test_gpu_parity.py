@@ -174,7 +174,8 @@ def test_outlier_and_fill_stages(B, orc, H, W):
     ref = orc.match(L, R, 0, 31, 7)
     m = orc.lr_check(ref["oL"], ref["mL"], ref["oR"], ref["mR"], 1)
     o = ref["oL"]
-    for r in (1, 10, 20, 30):
+    # r <= 63 takes the bit-parallel row test, larger r the carried sweep
+    for r in (1, 10, 20, 30, 63, 64, 100):
         g = np_(B.st_radial_outlier(cu(o.astype(np.int16)), cu(m), r, 2.5))
         assert np.array_equal(g, orc.radial_outlier(o, m, r, 2.5)), f"outlier r={r}"
     m2 = orc.radial_outlier(o, m, 10, 2.5)
