@@ -1039,7 +1039,7 @@ __device__ __forceinline__ int isqrt_floor(int v) {
 // Disk sums come from the row prefix sums, one segment per disk row; the
 // half-widths floor(sqrt(R^2 - dy^2)) of the disk rows are tabulated once
 // per block (for |dy| <= DISK_TAB) instead of per pixel and row.
-constexpr int DISK_TAB = 512;
+constexpr int DISK_TAB = 512, DISK_R32 = 256;
 
 template <bool B>
 __global__ __launch_bounds__(PIX_T) void fill_disk_kernel(PostPair one, const PostPair *__restrict__ many, int R,
@@ -1087,6 +1087,31 @@ __global__ __launch_bounds__(PIX_T) void fill_disk_kernel(PostPair one, const Po
   const int nh = nholes;
   const GLOBAL int32_t *__restrict__ pc = gro(P.pc);
   const GLOBAL int32_t *__restrict__ ps = gro(P.ps);
+  if (R <= DISK_R32) {
+    // every sum fits 32 bits: (2R+1)^2 cells of |o| <= 4096 stay below 2^31
+    for (int i = threadIdx.x; i < nh; i += PIX_T) {
+      const int x = holes[i];
+      const size_t k = (size_t)y * W + x;
+      int cells = 0, cnt = 0, sum = 0;
+      const int ya = max(-R, -y), yb = min(R, H - 1 - y);
+      const GLOBAL int32_t *pcr = pc + (size_t)(y + ya) * (W + 1);
+      const GLOBAL int32_t *psr = ps + (size_t)(y + ya) * (W + 1);
+#pragma unroll 8
+      for (int dy = ya; dy <= yb; ++dy, pcr += W + 1, psr += W + 1) {
+        const int w = hw[dy + RT];
+        const int xl = max(0, x - w), xh = min(W - 1, x + w);
+        cells += xh - xl + 1;
+        cnt += pcr[xh + 1] - pcr[xl];
+        sum += psr[xh + 1] - psr[xl];
+      }
+      const double need = ceil((double)frac * (double)cells);
+      if (cnt > 0 && (double)cnt >= need) {
+        grw(P.ob[dst])[k] = (int16_t)round_half_even(sum, cnt);
+        grw(P.mb[dst])[k] = 2;
+      }
+    }
+    return;
+  }
   for (int i = threadIdx.x; i < nh; i += PIX_T) {
     const int x = holes[i];
     const size_t k = (size_t)y * W + x;

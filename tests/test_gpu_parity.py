@@ -186,6 +186,22 @@ def test_outlier_and_fill_stages(B, orc, H, W):
         assert np.array_equal(np_(go)[rm > 0], ro[rm > 0]), f"fill values {args}"
 
 
+def test_fill_disk_radius_paths(B, orc):
+    """Disk radii up to 256 sum in 32 bits, larger ones in 64: both paths on
+    the same holes."""
+    L, R = _pair(60, 320, 31, 43)
+    ref = orc.match(L, R, 0, 31, 7)
+    m = orc.lr_check(ref["oL"], ref["mL"], ref["oR"], ref["mR"], 1)
+    o = ref["oL"]
+    m2 = orc.radial_outlier(o, m, 10, 2.5)
+    # fractions near the valid share of the disks leave some holes unfilled
+    for args in ((0, 2, 256, 0.8), (0, 2, 257, 0.8), (0, 2, 300, 0.81), (0, 2, 256, 0.81)):
+        go, gm = B.st_fill(cu(o.astype(np.int16)), cu(m2), *args)
+        ro, rm = orc.fill(o, m2, *args)
+        assert np.array_equal(np_(gm), rm), f"fill mask {args}"
+        assert np.array_equal(np_(go)[rm > 0], ro[rm > 0]), f"fill values {args}"
+
+
 @pytest.mark.parametrize("R,K", [(2, 1), (15, 3), (4, 2), (0, 1), (3, 0), (96, 2), (100, 2)])
 def test_hc_smooth_stage(B, orc, R, K):
     r = np.random.default_rng(R * 10 + K)
