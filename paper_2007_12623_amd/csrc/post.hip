@@ -770,6 +770,14 @@ __device__ __forceinline__ bool vscan_task(int idx, int H, int W, int &t, int &l
   return false;
 }
 
+// Element k (>= 0) of a 16-bit plane: planes hold at most 2^28 pixels, so
+// the byte offset fits 32 bits and the load takes the plane's base in
+// scalar registers plus one 32-bit lane offset (no 64-bit address per
+// step).
+__device__ __forceinline__ int16_t ld16(const GLOBAL int16_t *p, int k) {
+  return *(const GLOBAL int16_t *)((const GLOBAL char *)p + 2u * (uint32_t)k);
+}
+
 // Each scan first runs through the look-ahead rows (state only), then through
 // its own rows, writing results only where a later kernel reads them: pass
 // for valid pixels, hits for holes.  The loops are branch-free so that the
@@ -795,13 +803,13 @@ __device__ __forceinline__ void outlier_vscan(const PostPair &P, int bx, int r, 
      // line's last pixel has no forward step (bit stays 0)
     const int e = min(L.yhi - 1, b - 1 + r);
     int k = e * L.st + L.c0;
-    int on = o[k], run = 0;
+    int on = ld16(o, k), run = 0;
     bool vn = on != O_NONE;
     int y = e - 1;
     k -= L.st;
 #pragma unroll 8
     for (; y >= b; --y, k -= L.st) {
-      const int op = o[k];
+      const int op = ld16(o, k);
       const bool v = op != O_NONE;
       run = step(op, on, vn, run);
       on = op;
@@ -809,7 +817,7 @@ __device__ __forceinline__ void outlier_vscan(const PostPair &P, int bx, int r, 
     }
 #pragma unroll 8
     for (; y >= a; --y, k -= L.st) {
-      const int op = o[k];
+      const int op = ld16(o, k);
       const bool v = op != O_NONE;
       run = step(op, on, vn, run);
       on = op;
@@ -820,14 +828,14 @@ __device__ __forceinline__ void outlier_vscan(const PostPair &P, int bx, int r, 
   {  // backward (-y); when e == a the first row has no step (run 0 < r)
     const int e = max(L.ylo, a - r);
     int k = e * L.st + L.c0;
-    int on = o[k], run = 0;
+    int on = ld16(o, k), run = 0;
     bool vn = on != O_NONE;
     if (e == a && vn) pass[k] = (uint8_t)(fbits & 1u);
     int y = e + 1;
     k += L.st;
 #pragma unroll 8
     for (; y < a; ++y, k += L.st) {
-      const int op = o[k];
+      const int op = ld16(o, k);
       const bool v = op != O_NONE;
       run = step(op, on, vn, run);
       on = op;
@@ -835,7 +843,7 @@ __device__ __forceinline__ void outlier_vscan(const PostPair &P, int bx, int r, 
     }
 #pragma unroll 8
     for (; y < b; ++y, k += L.st) {
-      const int op = o[k];
+      const int op = ld16(o, k);
       const bool v = op != O_NONE;
       run = step(op, on, vn, run);
       on = op;
@@ -863,7 +871,7 @@ __device__ __forceinline__ void fill_vscan(const PostPair &P, int bx, int R, int
     int y = e, k = e * L.st + L.c0;
 #pragma unroll 8
     for (; y >= b; --y, k -= L.st) {
-      const int16_t oo = o[k];
+      const int16_t oo = ld16(o, k);
       const bool v = oo != O_NONE;
       const uint32_t ov = (uint16_t)oo;
       q = v ? y : q;
@@ -871,7 +879,7 @@ __device__ __forceinline__ void fill_vscan(const PostPair &P, int bx, int R, int
     }
 #pragma unroll 8
     for (; y >= a; --y, k -= L.st) {
-      const int16_t oo = o[k];
+      const int16_t oo = ld16(o, k);
       const bool v = oo != O_NONE;
       const uint32_t ov = (uint16_t)oo;
       if (!v) hf[k] = (q >= 0 && q - y <= R) ? ((uint32_t)(q - y) << 16) | vq : 0u;
@@ -886,7 +894,7 @@ __device__ __forceinline__ void fill_vscan(const PostPair &P, int bx, int R, int
     int y = e, k = e * L.st + L.c0;
 #pragma unroll 8
     for (; y < a; ++y, k += L.st) {
-      const int16_t oo = o[k];
+      const int16_t oo = ld16(o, k);
       const bool v = oo != O_NONE;
       const uint32_t ov = (uint16_t)oo;
       q = v ? y : q;
@@ -894,7 +902,7 @@ __device__ __forceinline__ void fill_vscan(const PostPair &P, int bx, int R, int
     }
 #pragma unroll 8
     for (; y < b; ++y, k += L.st) {
-      const int16_t oo = o[k];
+      const int16_t oo = ld16(o, k);
       const bool v = oo != O_NONE;
       const uint32_t ov = (uint16_t)oo;
       if (!v) hb[k] = (q >= 0 && y - q <= R) ? ((uint32_t)(y - q) << 16) | vq : 0u;
