@@ -264,6 +264,12 @@ __device__ __forceinline__ int wave_max(int v) {
   return v;
 }
 
+// The int32 at byte offset off of a plane (offsets of planes under 4 GiB):
+// the base stays scalar, the lane keeps a 32-bit offset.
+__device__ __forceinline__ int ld32(const int32_t *p, uint32_t off) {
+  return *(const GLOBAL int32_t *)((const GLOBAL char *)p + off);
+}
+
 // Per-pixel state of the sub-pixel block: the WTA disparity and whether it
 // is a valid candidate.
 struct SpPix {
@@ -293,15 +299,17 @@ __device__ __forceinline__ void sp_finish(const PostPair &P, const uint32_t *Pk,
     // o + 1 (bit q of rok: d = o - 1 + q is a candidate whose right window
     // is inside the image); issued before the sums, which hide their latency
     const int o = X.o[j];
-    const int sli = P.SL[k], ssli = P.SSL[k];
+    // statistics planes hold under 2^28 int32 values: 32-bit byte offsets
+    const uint32_t k4 = 4u * (uint32_t)k;
+    const int sli = ld32(P.SL, k4), ssli = ld32(P.SSL, k4);
     int sri[3], ssri[3], rok = 0;
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
       const int d = o + q - 1, xr = x - d;
       const bool ok = d >= P.dmin && d <= P.dmax && xr >= WIN / 2 && xr <= W - 1 - WIN / 2;
-      const size_t kr = ok ? (size_t)y * W + xr : k;
-      sri[q] = P.SR[kr];
-      ssri[q] = P.SSR[kr];
+      const uint32_t kr4 = ok ? k4 + 4u * (uint32_t)(xr - x) : k4;
+      sri[q] = ld32(P.SR, kr4);
+      ssri[q] = ld32(P.SSR, kr4);
       rok |= ok ? 1 << q : 0;
     }
     // window column u at d = o + 1 - e is R stage column rs + e + u
@@ -1102,15 +1110,18 @@ __global__ __launch_bounds__(PIX_T) void fill_disk_kernel(PostPair one, const Po
       const size_t k = (size_t)y * W + x;
       int cells = 0, cnt = 0, sum = 0;
       const int ya = max(-R, -y), yb = min(R, H - 1 - y);
-      const GLOBAL int32_t *pcr = pc + (size_t)(y + ya) * (W + 1);
-      const GLOBAL int32_t *psr = ps + (size_t)(y + ya) * (W + 1);
+      // byte offsets into the prefix planes (under 4 GiB): the row part is
+      // the same for every lane, the column part a 32-bit lane offset
+      const GLOBAL char *pcb = (const GLOBAL char *)pc, *psb = (const GLOBAL char *)ps;
+      uint32_t ro = 4u * (uint32_t)(y + ya) * (uint32_t)(W + 1);
 #pragma unroll 8
-      for (int dy = ya; dy <= yb; ++dy, pcr += W + 1, psr += W + 1) {
+      for (int dy = ya; dy <= yb; ++dy, ro += 4u * (uint32_t)(W + 1)) {
         const int w = hw[dy + RT];
         const int xl = max(0, x - w), xh = min(W - 1, x + w);
         cells += xh - xl + 1;
-        cnt += pcr[xh + 1] - pcr[xl];
-        sum += psr[xh + 1] - psr[xl];
+        const uint32_t oh = ro + 4u * (uint32_t)(xh + 1), ol = ro + 4u * (uint32_t)xl;
+        cnt += *(const GLOBAL int32_t *)(pcb + oh) - *(const GLOBAL int32_t *)(pcb + ol);
+        sum += *(const GLOBAL int32_t *)(psb + oh) - *(const GLOBAL int32_t *)(psb + ol);
       }
       const double need = ceil((double)frac * (double)cells);
       if (cnt > 0 && (double)cnt >= need) {
