@@ -798,11 +798,16 @@ __device__ __forceinline__ void outlier_vscan(const PostPair &P, int bx, int r, 
   const int a = max(L.ylo, sg * SEG), b = min(L.yhi, sg * SEG + SEG);
   if (a >= b) return;
   const GLOBAL int16_t *__restrict__ o = gro(P.ob[src]);  // O_NONE where invalid
-  GLOBAL uint8_t *__restrict__ pass = grw(P.pass) + (size_t)t * W * H;
-  // run = consecutive good steps from y along the scan direction, capped at r
+  // pass byte of flat index k of this line type: the four planes hold at
+  // most 2^30 bytes, so the offset is 32-bit from the scalar base
+  GLOBAL uint8_t *const pbase = grw(P.pass);
+  const uint32_t poff = (uint32_t)t * (uint32_t)W * (uint32_t)H;
+  auto pass_at = [&](int k) -> GLOBAL uint8_t & { return pbase[poff + (uint32_t)k]; };
+  // run = consecutive good steps from y along the scan direction (not
+  // capped: only run >= r is asked)
   const int ti = step_bound(thresh);
   auto step = [&](int op, int onb, bool vnb, int run) {
-    return step_ok(op, onb, vnb, ti) ? min(run + 1, r) : 0;
+    return step_ok(op, onb, vnb, ti) ? run + 1 : 0;
   };
   // forward results of the own rows wait in a bit mask (bit y - a) and are
   // stored with the backward ones
@@ -838,7 +843,7 @@ __device__ __forceinline__ void outlier_vscan(const PostPair &P, int bx, int r, 
     int k = e * L.st + L.c0;
     int on = ld16(o, k), run = 0;
     bool vn = on != O_NONE;
-    if (e == a && vn) pass[k] = (uint8_t)(fbits & 1u);
+    if (e == a && vn) pass_at(k) = (uint8_t)(fbits & 1u);
     int y = e + 1;
     k += L.st;
 #pragma unroll 8
@@ -856,7 +861,7 @@ __device__ __forceinline__ void outlier_vscan(const PostPair &P, int bx, int r, 
       run = step(op, on, vn, run);
       on = op;
       vn = v;
-      if (v) pass[k] = (uint8_t)(((fbits >> (y - a)) & 1u) | (run >= r ? 2u : 0u));
+      if (v) pass_at(k) = (uint8_t)(((fbits >> (y - a)) & 1u) | (run >= r ? 2u : 0u));
     }
   }
 }
