@@ -166,31 +166,27 @@ __device__ __forceinline__ uint32_t sp_dword(const GLOBAL uint8_t *base, long lo
 // of columns outside the image only reach sums whose z is discarded.  When
 // every byte the block reads lies inside the buffer (all bands but the
 // image's first and last ones), the loads take no bounds checks.
-__device__ __forceinline__ void sp_pack(uint32_t *Pk, int S, int PR, const GLOBAL uint8_t *Lg,
-                                        const GLOBAL uint8_t *Rg, int pitch, long long span, int yr0,
-                                        int lx0, int QL, int rx0, int QR, int tid) {
-  const int nq = QL + QR, nk = (PR + 3) >> 2, items = nq * nk;
-  // bytes read: rows yr0 .. yr0 + 4 nk + 2, columns from 3 before the first
-  // staged one to 7 past the last one's start (two dwords per load)
-  const long long first = (long long)yr0 * pitch + min(lx0, rx0) - 3;
-  const long long last = (long long)(yr0 + 4 * nk + 2) * pitch + max(lx0 + 4 * QL, rx0 + 4 * QR) + 8;
-  const bool inside = first >= 0 && last <= span;
-  const int pm = pitch & 3;
+// One side of the stage: nq quads from image column col0, stage columns
+// from cbase.  g is the same for every lane, so a load takes the plane's
+// base in scalar registers and a 32-bit lane offset (the fast path, taken
+// when every offset of the block is below 2^31).
+__device__ __forceinline__ void sp_pack_side(uint32_t *Pk, int S, int PR, const GLOBAL uint8_t *g,
+                                             int pitch, long long span, int yr0, int col0, int nq,
+                                             int cbase, bool inside, int tid) {
+  const int items = nq * ((PR + 3) >> 2), pm = pitch & 3;
   for (int it = tid; it < items; it += SPB_T) {
     const int k = it / nq, q = it - k * nq;
-    const bool isl = q < QL;
-    const GLOBAL uint8_t *g = isl ? Lg : Rg;
-    const int col = isl ? lx0 + 4 * q : rx0 + 4 * (q - QL);
-    const long long off0 = (long long)(yr0 + 4 * k) * pitch + col;
+    const long long off0 = (long long)(yr0 + 4 * k) * pitch + col0 + 4 * q;
     uint32_t raw[7];
     if (inside) {
-      const GLOBAL uint8_t *p0 = g + off0;
-      const int m0 = (int)((uintptr_t)p0 & 3);
+      const uint32_t o0 = (uint32_t)off0;
+      const int m0 = (int)(((uintptr_t)g + o0) & 3);
 #pragma unroll
       for (int t = 0; t < 7; ++t) {
         const int mis = (m0 + t * pm) & 3;
-        const GLOBAL uint32_t *a = (const GLOBAL uint32_t *)(p0 + (long long)t * pitch - mis);
-        raw[t] = __builtin_amdgcn_alignbyte(a[1], a[0], mis);
+        const uint32_t a = o0 + (uint32_t)(t * pitch) - (uint32_t)mis;
+        const GLOBAL uint32_t *w = (const GLOBAL uint32_t *)(g + a);
+        raw[t] = __builtin_amdgcn_alignbyte(w[1], w[0], mis);
       }
     } else {
 #pragma unroll
@@ -202,7 +198,7 @@ __device__ __forceinline__ void sp_pack(uint32_t *Pk, int S, int PR, const GLOBA
       }
     }
     uint32_t c0 = 0, c1 = 0, c2 = 0, c3 = 0;
-    uint32_t *dst = Pk + 4 * q;
+    uint32_t *dst = Pk + (cbase + 4 * q);
 #pragma unroll
     for (int t = 0; t < 7; ++t) {
       const uint32_t v = raw[t];
@@ -211,9 +207,31 @@ __device__ __forceinline__ void sp_pack(uint32_t *Pk, int S, int PR, const GLOBA
       c2 = (c2 >> 8) | ((v >> 16) << 24);
       c3 = (c3 >> 8) | ((v >> 24) << 24);
       const int p = 4 * k + t - 3;
-      if (t >= 3 && p < PR) *(uint4 *)(dst + (size_t)p * S) = make_uint4(c0, c1, c2, c3);
+      if (t >= 3 && p < PR) *(uint4 *)(dst + p * S) = make_uint4(c0, c1, c2, c3);
     }
   }
+}
+
+// Build packed rows 0 .. PR - 1 of the stage (row stride S dwords).  Work
+// item (chunk k, quad q): packed rows 4k .. 4k + 3 of stage columns
+// 4q .. 4q + 3, from image rows yr0 + 4k .. yr0 + 4k + 6 (one 4-byte load
+// each, realigned from two aligned dwords), shifting each row's bytes in at
+// the top of the four column dwords.  Bytes outside the buffer are 0; bytes
+// of columns outside the image only reach sums whose z is discarded.  When
+// every byte the block reads lies inside the buffer (all bands but the
+// image's first and last ones), the loads take no bounds checks.
+__device__ __forceinline__ void sp_pack(uint32_t *Pk, int S, int PR, const GLOBAL uint8_t *Lg,
+                                        const GLOBAL uint8_t *Rg, int pitch, long long span, int yr0,
+                                        int lx0, int QL, int rx0, int QR, int tid) {
+  const int nk = (PR + 3) >> 2;
+  // bytes read: rows yr0 .. yr0 + 4 nk + 2, columns from 3 before the first
+  // staged one to 7 past the last one's start (two dwords per load)
+  const long long first = (long long)yr0 * pitch + min(lx0, rx0) - 3;
+  const long long last = (long long)(yr0 + 4 * nk + 2) * pitch + max(lx0 + 4 * QL, rx0 + 4 * QR) + 8;
+  // (and the offsets fit 31 bits: the pitch is the caller's, not bounded)
+  const bool inside = first >= 0 && last <= span && last < (1LL << 31);
+  sp_pack_side(Pk, S, PR, Lg, pitch, span, yr0, lx0, QL, 0, inside, tid);
+  sp_pack_side(Pk, S, PR, Rg, pitch, span, yr0, rx0, QR, 4 * QL, inside, tid);
 }
 
 // Window sums at the disparities o + 1, o, o - 1 (sp, s0, sm) of a pixel
