@@ -1178,8 +1178,8 @@ __global__ __launch_bounds__(PIX_T) void fill_disk_kernel(PostPair one, const Po
 }
 
 // ---------------------------------------------------------------- smoothing (FP64)
-// Planes of P.f: 0 s, 1 s*m / b, 2 box(m) (as float), 3 column pass, 4 a =
-// A(s), 5 d / b.
+// Planes of P.f: 0 s (re-search) / b_1 = a - s, 1 s*m / b, 2 box(m) (as
+// float), 3 column pass, 4 a = A(s), 5 d / b.
 enum { F_S = 0, F_IN = 1, F_CNT = 2, F_TMP = 3, F_A = 4, F_D = 5 };
 
 // s = o + delta for matched pixels (code 1), o for filled ones (code 2), or
@@ -1266,19 +1266,19 @@ __global__ void box_v_kernel(PostPair one, const PostPair *__restrict__ many, Bo
 //   mode 2: d = a - box(b m)/box(m) (Eq. 3) -> F_D
 //   mode 3: the same d written as the final disparity (NaN where invalid)
 //           and mask
-//   mode 4: mode 1, and b = a - alpha s - (1 - alpha) s (Eq. 2 of the first
-//           iteration, d_prev = s) -> plane out, and c = alpha (a - s) ->
-//           plane F_S
+//   mode 4: mode 1, and b_1 = a - alpha s - (1 - alpha) s (Eq. 2 of the
+//           first iteration, d_prev = s) -> plane out (F_S)
 //   mode 5: the next iteration's b = a - alpha s - (1 - alpha) d (Eq. 2)
 //           with d = a - box(b m)/box(m) (Eq. 3), formed as
-//           c + (1 - alpha) box(b m)/box(m) -> plane out
+//           c + (1 - alpha) box(b m)/box(m) with c = alpha (a - s) =
+//           alpha b_1 (plane F_S) -> plane out
 // (b and a are 0 on invalid pixels, as the masked sums need.)  The inputs
 // the stage reads are gathered first (box_store_in), so that a caller can
 // load them ahead of time.
 struct BoxStoreIn {
   uint8_t mk;
   float cnt;
-  double a, s;  // a; s (mode 4) or c (mode 5)
+  double a, s;  // a; s (mode 4) or b_1 (mode 5)
 };
 __device__ __forceinline__ BoxStoreIn box_store_in(const PostPair &P, const BoxArgs &A, size_t N,
                                                    size_t k) {
@@ -1315,14 +1315,16 @@ __device__ __forceinline__ void box_store(const PostPair &P, const BoxArgs &A, s
   if (A.mode == 1 || A.mode == 4) {
     P.f[(size_t)F_A * N + k] = mk ? mean : 0.0;
     if (A.mode == 4) {
+      // b_1 = a - alpha s - (1 - alpha) d_0 with d_0 = s; the later passes
+      // take c = alpha (a - s) = alpha b_1 from this plane
       const double s = mk ? q.s : 0.0;
       P.f[(size_t)A.out * N + k] = mk ? mean - A.alpha * s - (1.0 - A.alpha) * s : 0.0;
-      P.f[(size_t)F_S * N + k] = mk ? A.alpha * (mean - s) : 0.0;
     }
     return;
   }
   if (A.mode == 5) {
-    P.f[(size_t)A.out * N + k] = mk ? q.s + (1.0 - A.alpha) * mean : 0.0;
+    // b_{k+1} = c + (1 - alpha) box(b_k m) / box(m), c = alpha b_1 (q.s)
+    P.f[(size_t)A.out * N + k] = mk ? A.alpha * q.s + (1.0 - A.alpha) * mean : 0.0;
     return;
   }
   const double d = mk ? q.a - mean : 0.0;
@@ -1838,17 +1840,19 @@ hipError_t post_hc(const PostLaunch &L, int src, int R, int K, float alpha, int 
   };
   if (!research) {
     // a is fixed and s is formed on the fly from the disparities; every b
-    // (Eq. 2) is formed in the output stage of the box pass before it,
-    // alternating between the planes F_D and F_IN; with c = alpha (a - s)
-    // (plane F_S), b_{k+1} = c + (1 - alpha) box(b_k m)/box(m), and only the
-    // last pass forms d = a - box(b m)/box(m)
-    BoxArgs first = args(BOX_IN_S, F_D, 4);  // a = box(s m) / box(m), b_0 -> F_D,
+    // (Eq. 2) is formed in the output stage of the box pass before it.  b_1
+    // = a - s stays in plane F_S: with c = alpha (a - s) = alpha b_1,
+    // b_{k+1} = c + (1 - alpha) box(b_k m)/box(m), the later b alternating
+    // between the planes F_D and F_IN, and only the last pass forms
+    // d = a - box(b m)/box(m)
+    BoxArgs first = args(BOX_IN_S, F_S, 4);  // a = box(s m) / box(m), b_1 -> F_S,
     first.counts = 1;                         // and the counts box(m) in the same pass
     box2d(L, first);
-    int bin = F_D, bout = F_IN;
+    int bin = F_S, bout = F_D;
     for (int it = 0; it < K; ++it) {
       box2d(L, args(bin, bout, it == K - 1 ? 3 : 5));  // d = a - box(b m) / box(m)
-      std::swap(bin, bout);
+      bin = bout;
+      bout = bout == F_D ? F_IN : F_D;
     }
     return hipGetLastError();
   }
