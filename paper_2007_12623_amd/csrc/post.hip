@@ -987,44 +987,64 @@ __global__ void outlier_combine_kernel(PostPair one, const PostPair *__restrict_
 // lines the hole takes their mean, an exact rational rounded half to even;
 // code 2.  Fused with the row prefix sums of the result that the disk fill
 // reads: pc[y][x+1] = number of valid pixels x' <= x in row y, ps[y][x+1]
-// the sum of their disparities.  One block per row; the row goes in chunks
-// of 256 columns with a block scan (wave scans plus wave totals in LDS).
+// the sum of their disparities.  One block per row; a thread takes the
+// columns t, t + 256, t + 512, t + 768 of each 1024-column piece, so that
+// the maps of all four, then the hits of all their holes, are loaded
+// together (two round trips per piece), and the piece's prefix sums take
+// one block barrier (wave scans, then the wave totals of the four chunks
+// in LDS).
+constexpr int RF_CPT = 4;
 template <bool B>
 __global__ __launch_bounds__(256) void fill_radial_kernel(PostPair one, const PostPair *__restrict__ many,
                                                           int min_lines, int src, int dst) {
   PAIR;
-  __shared__ int wc[4], wsum[4];
+  __shared__ int wc[RF_CPT][4], wsum[RF_CPT][4];
   const int y = bp.x;
   if (y >= P.H) return;  // uniform per block
   const int W = P.W, H = P.H, t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const size_t N = (size_t)W * H;
   const GLOBAL int16_t *o = gro(P.ob[src]);
   const GLOBAL uint8_t *m = gro(P.mb[src]);
-  const GLOBAL uint32_t *hits = gro(P.hits);
   GLOBAL int32_t *pcr = grw(P.pc) + (size_t)y * (W + 1);
   GLOBAL int32_t *psr = grw(P.ps) + (size_t)y * (W + 1);
   if (t == 0) {
     pcr[0] = 0;
     psr[0] = 0;
   }
+  const uint32_t row = (uint32_t)y * (uint32_t)W;  // flat index of (0, y): below 2^28
   int carry_c = 0, carry_s = 0;
-  for (int x0 = 0; x0 < W; x0 += 256) {
-    const int x = x0 + t;
-    int ov = 0, mv = 0;
-    if (x < W) {
-      const size_t k = (size_t)y * W + x;
-      ov = o[k];
-      mv = m[k];
-      if (!mv) {
-        // all eight hits in one round trip
-        uint32_t hv[8];
+  for (int x0 = 0; x0 < W; x0 += 256 * RF_CPT) {
+    int ov[RF_CPT], mv[RF_CPT];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) hv[i] = hits[(size_t)i * N + k];
+    for (int j = 0; j < RF_CPT; ++j) {
+      const int x = x0 + 256 * j + t;
+      const bool in = x < W;
+      ov[j] = in ? (int)ld16(o, (int)(row + x)) : 0;
+      mv[j] = in ? (int)m[row + x] : 0;
+    }
+    // the eight hits of every hole of the thread, all in flight together
+    // (plane i from its own base, 32-bit lane offsets)
+    uint32_t hv[RF_CPT][8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const GLOBAL char *hp = (const GLOBAL char *)(gro(P.hits) + (size_t)i * N);
+#pragma unroll
+      for (int j = 0; j < RF_CPT; ++j) {
+        const int x = x0 + 256 * j + t;
+        const bool hole = x < W && mv[j] == 0;
+        hv[j][i] = hole ? *(const GLOBAL uint32_t *)(hp + 4u * (row + (uint32_t)x)) : 0u;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < RF_CPT; ++j) {
+      const int x = x0 + 256 * j + t;
+      if (x >= W) continue;
+      if (mv[j] == 0) {
         long long num = 0, den = 1;
         int lines = 0;
 #pragma unroll
         for (int ln = 0; ln < 4; ++ln) {
-          const uint32_t ha = hv[2 * ln], hb = hv[2 * ln + 1];
+          const uint32_t ha = hv[j][2 * ln], hb = hv[j][2 * ln + 1];
           if (!ha || !hb) continue;
           const long long sa = ha >> 16, sb = hb >> 16;
           const long long va = (int16_t)(ha & 0xFFFFu), vb = (int16_t)(hb & 0xFFFFu);
@@ -1035,33 +1055,48 @@ __global__ __launch_bounds__(256) void fill_radial_kernel(PostPair one, const Po
           ++lines;
         }
         if (lines >= min_lines && lines > 0) {
-          ov = (int)round_half_even(num, den * lines);
-          mv = 2;
+          ov[j] = (int)round_half_even(num, den * lines);
+          mv[j] = 2;
         }
       }
-      grw(P.ob[dst])[k] = (int16_t)ov;
-      grw(P.mb[dst])[k] = (uint8_t)mv;
+      grw(P.ob[dst])[row + x] = (int16_t)ov[j];
+      grw(P.mb[dst])[row + x] = (uint8_t)mv[j];
     }
-    const int c = wave_scan_incl(mv ? 1 : 0), sv = wave_scan_incl(mv ? ov : 0);
+    int c[RF_CPT], sv[RF_CPT];
+#pragma unroll
+    for (int j = 0; j < RF_CPT; ++j) {
+      c[j] = wave_scan_incl(mv[j] ? 1 : 0);
+      sv[j] = wave_scan_incl(mv[j] ? ov[j] : 0);
+    }
     if (lane == 63) {
-      wc[wave] = c;
-      wsum[wave] = sv;
+#pragma unroll
+      for (int j = 0; j < RF_CPT; ++j) {
+        wc[j][wave] = c[j];
+        wsum[j][wave] = sv[j];
+      }
     }
     __syncthreads();
-    int bc = carry_c, bs = carry_s;
-    for (int w = 0; w < wave; ++w) {
-      bc += wc[w];
-      bs += wsum[w];
+    // chunk j, wave w starts after the whole chunks before j and the waves
+    // of chunk j before w
+#pragma unroll
+    for (int j = 0; j < RF_CPT; ++j) {
+      int bc = carry_c, bs = carry_s;
+      for (int w = 0; w < wave; ++w) {
+        bc += wc[j][w];
+        bs += wsum[j][w];
+      }
+      const int x = x0 + 256 * j + t;
+      if (x < W) {
+        pcr[x + 1] = bc + c[j];
+        psr[x + 1] = bs + sv[j];
+      }
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        carry_c += wc[j][w];
+        carry_s += wsum[j][w];
+      }
     }
-    if (x < W) {
-      pcr[x + 1] = bc + c;
-      psr[x + 1] = bs + sv;
-    }
-    for (int w = 0; w < 4; ++w) {
-      carry_c += wc[w];
-      carry_s += wsum[w];
-    }
-    __syncthreads();  // wc / wsum are rewritten by the next chunk
+    __syncthreads();  // wc / wsum are rewritten by the next piece
   }
 }
 
