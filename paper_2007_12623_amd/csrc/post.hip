@@ -26,6 +26,30 @@ __device__ __forceinline__ void for_pixels(const PostPair &P, const BlockPos &bp
   for (int x = bp.x * PIX_SEG + threadIdx.x; x < x1; x += PIX_T) f(x, y, (size_t)y * P.W + x);
 }
 
+// The same with a thread's pixels loaded (ld) before any is finished (st):
+// the loads of one pixel would otherwise wait behind the stores of the
+// previous one, which the compiler may not move them past, and a thread
+// would wait for one memory round trip per pixel.
+template <class LD, class ST>
+__device__ __forceinline__ void for_pixels_ls(const PostPair &P, const BlockPos &bp, LD ld, ST st) {
+  constexpr int NP = PIX_SEG / PIX_T;
+  const int y = bp.y;
+  if (y >= P.H) return;
+  const int xb = bp.x * PIX_SEG + (int)threadIdx.x, x1 = min(P.W, (bp.x + 1) * PIX_SEG);
+  using T = decltype(ld((size_t)0));
+  T v[NP];
+#pragma unroll
+  for (int i = 0; i < NP; ++i) {
+    const int x = xb + i * PIX_T;
+    if (x < x1) v[i] = ld((size_t)y * P.W + x);
+  }
+#pragma unroll
+  for (int i = 0; i < NP; ++i) {
+    const int x = xb + i * PIX_T;
+    if (x < x1) st((size_t)y * P.W + x, v[i]);
+  }
+}
+
 // floor(a / b) for b > 0.  With |a|, b < 2^52 (every case of the default
 // radii) a double estimate, off by at most one, is corrected with the exact
 // integer remainder, which avoids the long 64-bit integer division.
@@ -60,15 +84,17 @@ __global__ void decode_kernel(PostPair one, const PostPair *__restrict__ many) {
   const int W = P.W, H = P.H;
   (void)W;
   (void)H;
-  for_pixels(P, bp, [&](int x, int y, size_t k) {
-    const uint32_t a = P.keyL[k], b = P.keyR[k];
-    P.ob[0][k] = a ? (int16_t)(P.dmin + 255 - (int)(a & 255u)) : O_NONE;
-    P.mb[0][k] = a ? 1 : 0;
-    P.oR[k] = b ? (int16_t)(P.dmin + 255 - (int)(b & 255u)) : O_NONE;
-    P.mR[k] = b ? 1 : 0;
-    P.keyL[k] = 0;
-    P.keyR[k] = 0;
-  });
+  for_pixels_ls(
+      P, bp, [&](size_t k) { return make_uint2(P.keyL[k], P.keyR[k]); },
+      [&](size_t k, uint2 ab) {
+        const uint32_t a = ab.x, b = ab.y;
+        P.ob[0][k] = a ? (int16_t)(P.dmin + 255 - (int)(a & 255u)) : O_NONE;
+        P.mb[0][k] = a ? 1 : 0;
+        P.oR[k] = b ? (int16_t)(P.dmin + 255 - (int)(b & 255u)) : O_NONE;
+        P.mR[k] = b ? 1 : 0;
+        P.keyL[k] = 0;
+        P.keyR[k] = 0;
+      });
 }
 
 __global__ void fill_u32_kernel(uint32_t *p, int N, uint32_t v) {
@@ -972,14 +998,19 @@ __global__ void outlier_combine_kernel(PostPair one, const PostPair *__restrict_
   const int W = P.W, H = P.H;
   (void)W;
   (void)H;
-  for_pixels(P, bp, [&](int x, int y, size_t k) {
-    const size_t N = (size_t)W * H;
-    const uint8_t mk = P.mb[src][k];
-    const bool any = (P.pass[k] | P.pass[N + k] | P.pass[2 * N + k] | P.pass[3 * N + k]) != 0;
-    const bool keep = mk && any;
-    P.ob[dst][k] = keep ? P.ob[src][k] : O_NONE;
-    P.mb[dst][k] = keep ? mk : 0;
-  });
+  const size_t N = (size_t)W * H;
+  for_pixels_ls(
+      P, bp,
+      [&](size_t k) {
+        const uint8_t mk = P.mb[src][k];
+        const bool any = (P.pass[k] | P.pass[N + k] | P.pass[2 * N + k] | P.pass[3 * N + k]) != 0;
+        // (mask code if kept, 0 otherwise) and the disparity
+        return make_int2(mk && any ? (int)mk : 0, (int)P.ob[src][k]);
+      },
+      [&](size_t k, int2 v) {
+        P.ob[dst][k] = v.x ? (int16_t)v.y : O_NONE;
+        P.mb[dst][k] = (uint8_t)v.x;
+      });
 }
 
 // (i) radial fill from the scanned hits: complete lines (both opposite
@@ -1136,18 +1167,26 @@ __global__ __launch_bounds__(PIX_T) void fill_disk_kernel(PostPair one, const Po
   // wave and pass: ballot, then each hole lane at its rank)
   const int lane = threadIdx.x & (WV - 1);
   if (y < H) {
-    const int x1 = min(W, (bp.x + 1) * PIX_SEG);
-    for (int x0 = bp.x * PIX_SEG; x0 < x1; x0 += PIX_T) {  // uniform trip count
-      const int x = x0 + threadIdx.x;
-      bool hole = false;
+    // the segment's maps are loaded together, then copied and listed
+    constexpr int NP = PIX_SEG / PIX_T;
+    const int x1 = min(W, (bp.x + 1) * PIX_SEG), xb = bp.x * PIX_SEG + (int)threadIdx.x;
+    int16_t ov[NP];
+    uint8_t mv[NP];
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+      const int x = xb + i * PIX_T;
+      ov[i] = x < x1 ? o[(size_t)y * W + x] : (int16_t)0;
+      mv[i] = x < x1 ? m[(size_t)y * W + x] : (uint8_t)1;
+    }
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+      const int x = xb + i * PIX_T;
       if (x < x1) {
         const size_t k = (size_t)y * W + x;
-        const int16_t ov = o[k];
-        const uint8_t mv = m[k];
-        grw(P.ob[dst])[k] = ov;
-        grw(P.mb[dst])[k] = mv;
-        hole = mv == 0;
+        grw(P.ob[dst])[k] = ov[i];
+        grw(P.mb[dst])[k] = mv[i];
       }
+      const bool hole = x < x1 && mv[i] == 0;
       const uint64_t hm = ballot64(hole);
       int base = 0;
       if (lane == 0 && hm) base = atomicAdd(&nholes, __builtin_popcountll(hm));
