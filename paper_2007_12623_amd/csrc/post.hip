@@ -1427,6 +1427,7 @@ __device__ __forceinline__ void box_store(const PostPair &P, const BoxArgs &A, s
 // boxes the mask as well (an integer sum beside the FP64 one) and stores the
 // counts, so that the first smoothing pass needs no counts pass before it.
 constexpr int BX_T = 256, BX_RMAX = 96, BX_PF = 2;  // rows loaded ahead (4 measured slower: 4 waves per SIMD)
+constexpr int BX_SY = 32;  // rows per segment (64 measured slower: half the blocks)
 template <bool B, bool CNT>
 __global__ __launch_bounds__(BX_T) void box2d_kernel(PostPair one, const PostPair *__restrict__ many,
                                                      BoxArgs A) {
@@ -1852,7 +1853,7 @@ static void box2d(const PostLaunch &L, BoxArgs A) {
     // blocks (a single pair): the seed of 2R rows per segment is the price
     // of more blocks in flight
     const int nout = BX_T - 2 * A.R, nx = ceil_div(L.maxW, nout);
-    A.sy = 32;
+    A.sy = BX_SY;
     while (A.sy > 8 && (long long)nx * ceil_div(L.maxH, A.sy) * L.npairs < 1024) A.sy /= 2;
     const dim3 grid(nx, ceil_div(L.maxH, A.sy), L.npairs);
     if (A.counts) {
