@@ -946,10 +946,28 @@ st_status stereo_match_batched(st_handle h, const st_pair *pairs, int n_pairs,
     BatchCache::Group gr;
     gr.win = w;
     gr.off = (int)sorted.size();
-    gr.ntasks = (int)v.size();
     gr.lds = wlds[w];
     gr.nblocks = h->ncu * match_persistent_occupancy(w, prec, gr.lds);
-    for (auto &e : v) sorted.push_back(e.second);
+    // the queue's last round: its tasks (the cheapest, at the end) go in
+    // two halves of their band's rows, so that the workgroups run out of
+    // work at most half a task apart (tk.w = first row | end row << 16)
+    const int nsplit = std::min((int)v.size(), gr.nblocks);
+    const int nfull = (int)v.size() - nsplit;
+    for (int i = 0; i < nfull; ++i) sorted.push_back(v[i].second);
+    for (int i = nfull; i < (int)v.size(); ++i) {
+      const int4 tk = v[i].second;
+      const MatchPair &P = M[tk.x];
+      const int hh = P.win / 2, band = tk.y / P.nspan;
+      const int rows = std::min(P.TY, P.H - 2 * hh - band * P.TY);
+      if (rows < 2) {
+        sorted.push_back(tk);
+        continue;
+      }
+      const int mid = rows / 2;
+      sorted.push_back(make_int4(tk.x, tk.y, tk.z, mid << 16));
+      sorted.push_back(make_int4(tk.x, tk.y, tk.z, mid | (rows << 16)));
+    }
+    gr.ntasks = (int)sorted.size() - gr.off;
     groups.push_back(gr);
   }
   // device tables

@@ -363,19 +363,28 @@ __device__ __forceinline__ void match_rows(const MatchPair &P, int y0, int y1, i
 
 // ---------------------------------------------------------------- workgroup task
 // Band `g` (band * nspan + span) of a pair, chunk group `cg`: the chunks
-// cg*CG .. min((cg+1)*CG, nchunk)-1.  The 4 waves take (chunk, sub-band)
-// items in turn; with fewer chunks than waves the band is cut into
-// sub-bands so that every wave has work.
+// cg*CG .. min((cg+1)*CG, nchunk)-1, rows rlo .. rhi-1 of the band (all of
+// it, or one half of it for the tasks that end a queue).  The 4 waves take
+// (chunk, sub-band) items in turn; with fewer chunks than waves the rows
+// are cut into sub-bands so that every wave has work.
 template <int WIN, int DC, int PREC>
-__device__ __forceinline__ void wg_task(const MatchPair &P, int g, int cg, LDS uint32_t *lds) {
+__device__ __forceinline__ void wg_task(const MatchPair &P, int g, int cg, int rlo, int rhi,
+                                        LDS uint32_t *lds) {
   // the wave index is uniform: in a scalar register every quantity derived
   // from it (chunk, colour, rows of the item) stays scalar as well
   const int tid = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & (WV - 1);
   constexpr int NT = NWAVE * WV;
   const int h = WIN / 2;
   const int band = g / P.nspan, span = g - band * P.nspan;
-  const int y0 = h + band * P.TY;
-  const int y1 = min(y0 + P.TY, P.H - h);
+  const int y0 = h + band * P.TY + rlo;
+  const int y1 = min(h + band * P.TY + rhi, P.H - h);
+  if (y0 >= y1) {
+    // uniform over the workgroup (no half band past the image is queued):
+    // still one barrier, which the persistent loop's reuse of its task
+    // index relies on
+    __syncthreads();
+    return;
+  }
   const int rows = y1 - y0;
   const int xs = P.xs0 + span * (OUT_LANES * KC);
   const int D = P.dmax - P.dmin + 1;
@@ -441,11 +450,11 @@ void match_kernel(MatchPair P, int ngroups) {
   const int cg = r % P.ncg;
   const int g = (r / P.ncg) * 8 + xcd;
   if (g >= ngroups) return;
-  wg_task<WIN, DC, PREC>(P, g, cg, (LDS uint32_t *)lds_dyn);
+  wg_task<WIN, DC, PREC>(P, g, cg, 0, P.TY, (LDS uint32_t *)lds_dyn);
 }
 
-// Persistent form: workgroups pull tasks (pair, group, chunk group) of one
-// window size from a queue until it is empty.  Every workgroup reaches the
+// Persistent form: workgroups pull tasks (pair, group, chunk group, rows) of
+// one window size from a queue until it is empty.  Every workgroup reaches the
 // exit once the counter passes ntasks.
 template <int WIN, int DC, int PREC>
 __global__ __launch_bounds__(NWAVE * WV) __attribute__((amdgpu_waves_per_eu(3)))
@@ -461,7 +470,9 @@ void match_persistent_kernel(const MatchPair *__restrict__ pairs, const int4 *__
     if (t >= ntasks) break;
     const int4 tk = tasks[t];
     const MatchPair P = pairs[tk.x];
-    wg_task<WIN, DC, PREC>(P, tk.y, tk.z, (LDS uint32_t *)lds_dyn);
+    // tk.w: 0 for the whole band, else rows (w & 0xFFFF) .. (w >> 16) - 1
+    const int rlo = tk.w ? (tk.w & 0xFFFF) : 0, rhi = tk.w ? (tk.w >> 16) : P.TY;
+    wg_task<WIN, DC, PREC>(P, tk.y, tk.z, rlo, rhi, (LDS uint32_t *)lds_dyn);
   }
 }
 
