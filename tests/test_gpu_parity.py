@@ -179,7 +179,9 @@ def test_outlier_and_fill_stages(B, orc, H, W):
         g = np_(B.st_radial_outlier(cu(o.astype(np.int16)), cu(m), r, 2.5))
         assert np.array_equal(g, orc.radial_outlier(o, m, r, 2.5)), f"outlier r={r}"
     m2 = orc.radial_outlier(o, m, 10, 2.5)
-    for args in ((50, 2, 20, 0.25), (5, 1, 3, 0.5), (0, 2, 20, 0.25), (50, 4, 0, 0.0)):
+    # radial radii on either side of 64 (one 64-column block of look-ahead)
+    for args in ((50, 2, 20, 0.25), (5, 1, 3, 0.5), (0, 2, 20, 0.25), (50, 4, 0, 0.0),
+                 (63, 2, 0, 0.0), (64, 2, 0, 0.0), (100, 1, 0, 0.0)):
         go, gm = B.st_fill(cu(o.astype(np.int16)), cu(m2), *args)
         ro, rm = orc.fill(o, m2, *args)
         assert np.array_equal(np_(gm), rm), f"fill mask {args}"
