@@ -89,17 +89,23 @@ template <> struct Img<P_BF16> {
 // Global key of a lane-local key: 0x80000000 | q << 8 | 255 - (d - dmin),
 // q = quantised z (the bits of z+2 above the index field, counted from 1.0),
 // so that ties prefer the smaller disparity.  With j = 15 - (b & 15) and
-// c = 0x80000000 + 240 - (d0 - dmin), the low part is (b & 15) + c and
-// q << 8 = ((b - 0x3F800000) << 4) & ~0xFF, where b is clamped to 1.0.
-// A lane key below 0.5 (no valid candidate: the running maxima start at 0)
-// gives 0, which leaves a merged maximum unchanged.
-__device__ __forceinline__ uint32_t key_base(int dd0) { return 0x80000000u + 240u - (uint32_t)dd0; }
+// c = 0x88000000 + 240 - (d0 - dmin), the key is
+// ((m & ~15) << 4) + c + (b & 15), where m is b clamped to [1.0, KEY_NONE]:
+// the shift takes 1.0 to 0xF8000000, which c's 0x08000000 carries out.  A
+// lane without a valid candidate holds the start value KEY_START (a
+// negative float: below every z+2 as a float, above KEY_NONE as unsigned),
+// clamped to KEY_NONE, whose shifted part cancels c's high bits; its low
+// nibble 15 (as the index field of a valid key, at least 8) keeps the rest,
+// 255 - (d0 - dmin), non-negative.  So bit 31 marks a valid key, and a key
+// without it never wins a merge.
+constexpr uint32_t KEY_NONE = 0x47800000u, KEY_START = 0xBF80000Fu;
+__device__ __forceinline__ uint32_t key_base(int dd0) { return 0x88000000u + 240u - (uint32_t)dd0; }
 __device__ __forceinline__ uint32_t global_key(float k, uint32_t c) {
   const uint32_t b = __builtin_bit_cast(uint32_t, k);
-  const uint32_t hi = (max(b, 0x3F800000u) << 4) + 0x08000000u;  // (b' - 0x3F800000) << 4
-  const uint32_t key = (hi & 0xFFFFFF00u) | ((b & 15u) + c);
-  return b >= 0x3F000000u ? key : 0u;
+  const uint32_t m = min(max(b, 0x3F800000u), KEY_NONE);  // v_med3_u32
+  return ((m & ~15u) << 4) + c + (b & 15u);
 }
+__device__ __forceinline__ bool key_valid(uint32_t v) { return (int)v < 0; }
 
 __device__ __forceinline__ void gmax(GLOBAL uint32_t *p, uint32_t v) {
   __hip_atomic_fetch_max(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -274,9 +280,9 @@ __device__ __forceinline__ void match_rows(const MatchPair &P, int y0, int y1, i
     float bestL[K];
     float Pd[T];
 #pragma unroll
-    for (int c = 0; c < K; ++c) bestL[c] = 0.0f;
+    for (int c = 0; c < K; ++c) bestL[c] = __builtin_bit_cast(float, KEY_START);
 #pragma unroll
-    for (int t = 0; t < T; ++t) Pd[t] = 0.0f;
+    for (int t = 0; t < T; ++t) Pd[t] = __builtin_bit_cast(float, KEY_START);
 
     // ---- per chunk disparity j: horizontal window sums of the lane's
     //      columns (own columns through prefix sums; the h columns beyond each
@@ -337,9 +343,10 @@ __device__ __forceinline__ void match_rows(const MatchPair &P, int y0, int y1, i
     for (int t = 0; t < DC - 1; ++t) Pd[t + K] = kmax(Pd[t + K], from_right(Pd[t]));
 
     // ---- emit into the tiles: left reference per pixel, right reference
-    //      per home column (lane 0 also the 7 columns left of its home)
-    // (branch-free: a lane without a valid candidate merges the key 0; the
-    // halo lanes' left keys are 0 as well, their normalisers being NaN)
+    //      per home column.  Branch-free: a lane without a valid candidate
+    //      merges a key below 0x80000000.  The halo lanes' keys are all of
+    //      that kind, their normalisers being NaN; so are lane 0's diagonals
+    //      left of its home, the columns that the previous span covers.
     LDS uint32_t *lrow = kt.lt + (y - kt.y0) * (8 * LTP) + lane;
 #pragma unroll
     for (int c = 0; c < K; ++c) lmax(lrow + c * LTP, global_key(bestL[c], kc));
@@ -349,14 +356,6 @@ __device__ __forceinline__ void match_rows(const MatchPair &P, int y0, int y1, i
     for (int m = 0; m < K; ++m) {
       const int q = q0 + m;
       lmax(rrow + (q & 7) * kt.rp + (q >> 3), global_key(Pd[m + DC - 1], kc));
-    }
-    if (lane == 0) {
-#pragma unroll
-      for (int m = -(DC - 1); m < 0; ++m)
-        if (Pd[m + DC - 1] >= 0.5f) {
-          const int q = q0 + m;
-          lmax(rrow + (q & 7) * kt.rp + (q >> 3), global_key(Pd[m + DC - 1], kc));
-        }
     }
   }
 }
@@ -428,12 +427,12 @@ __device__ __forceinline__ void wg_task(const MatchPair &P, int g, int cg, int r
       if (x < 0 || x >= P.W) continue;
       const uint32_t v = kt.lt[r * 8 * LTP + (xr & 7) * LTP + (xr >> 3)];
       if (whole) kl[rowoff + x] = v;
-      else if (v) gmax(kl + rowoff + x, v);
+      else if (key_valid(v)) gmax(kl + rowoff + x, v);
     }
     for (int q = tid; q < RW; q += NT) {
       const uint32_t v = kt.rt[r * 8 * kt.rp + (q & 7) * kt.rp + (q >> 3)];
       const int x = kt.rbase + q;
-      if (v && x >= 0 && x < P.W) gmax(kr + rowoff + x, v);
+      if (key_valid(v) && x >= 0 && x < P.W) gmax(kr + rowoff + x, v);
     }
   }
 }

@@ -87,11 +87,12 @@ __global__ void decode_kernel(PostPair one, const PostPair *__restrict__ many) {
   for_pixels_ls(
       P, bp, [&](size_t k) { return make_uint2(P.keyL[k], P.keyR[k]); },
       [&](size_t k, uint2 ab) {
-        const uint32_t a = ab.x, b = ab.y;
-        P.ob[0][k] = a ? (int16_t)(P.dmin + 255 - (int)(a & 255u)) : O_NONE;
-        P.mb[0][k] = a ? 1 : 0;
-        P.oR[k] = b ? (int16_t)(P.dmin + 255 - (int)(b & 255u)) : O_NONE;
-        P.mR[k] = b ? 1 : 0;
+        // bit 31 marks a key with a valid candidate
+        const bool va = (int)ab.x < 0, vb = (int)ab.y < 0;
+        P.ob[0][k] = va ? (int16_t)(P.dmin + 255 - (int)(ab.x & 255u)) : O_NONE;
+        P.mb[0][k] = va ? 1 : 0;
+        P.oR[k] = vb ? (int16_t)(P.dmin + 255 - (int)(ab.y & 255u)) : O_NONE;
+        P.mR[k] = vb ? 1 : 0;
         P.keyL[k] = 0;
         P.keyR[k] = 0;
       });
