@@ -1427,16 +1427,18 @@ __device__ __forceinline__ void box_store(const PostPair &P, const BoxArgs &A, s
 // differ from every plane the output stage writes.  CNT: the same pass
 // boxes the mask as well (an integer sum beside the FP64 one) and stores the
 // counts, so that the first smoothing pass needs no counts pass before it.
-constexpr int BX_T = 256, BX_RMAX = 96, BX_PF = 2;  // rows loaded ahead (4 measured slower: 4 waves per SIMD)
+constexpr int BX_T = 256, BX_RMAX = 96;
 constexpr int BX_SY = 32;  // rows per segment (64 measured slower: half the blocks)
 template <bool B, bool CNT>
 __global__ __launch_bounds__(BX_T) void box2d_kernel(PostPair one, const PostPair *__restrict__ many,
                                                      BoxArgs A) {
   PAIR;
-  __shared__ double pf[2][BX_T];
-  __shared__ double wt[2][BX_T / WV];
-  __shared__ int pfc[CNT ? 2 : 1][CNT ? BX_T : 1];
-  __shared__ int wtc[CNT ? 2 : 1][BX_T / WV];
+  // scans of two rows per barrier, in slots 0-1 and 2-3 alternately: a
+  // pair's slots are written again only after the next pair's barrier
+  __shared__ double pf[4][BX_T];
+  __shared__ double wt[4][BX_T / WV];
+  __shared__ int pfc[CNT ? 4 : 1][CNT ? BX_T : 1];
+  __shared__ int wtc[CNT ? 4 : 1][BX_T / WV];
   const int H = P.H, W = P.W, R = A.R;
   const int nout = BX_T - 2 * R;
   const int xo = bp.x * nout, y0 = bp.y * A.sy;
@@ -1488,7 +1490,7 @@ __global__ __launch_bounds__(BX_T) void box2d_kernel(PostPair one, const PostPai
   };
   const int y1 = min(y0 + A.sy, H);
   // a row's inputs (entering and leaving rows, output-stage operands) are
-  // loaded BX_PF rows ahead
+  // loaded two rows ahead
   struct RowIn {
     double add, sub;
     int addc, subc;
@@ -1501,14 +1503,16 @@ __global__ __launch_bounds__(BX_T) void box2d_kernel(PostPair one, const PostPai
     q.st = out_col ? box_store_in(P, A, N, (size_t)y * W + c) : BoxStoreIn{};
     return q;
   };
-  auto process = [&](int y, const RowIn &q) {
-    const int b = y & 1;
+  // the column sums of a row, scanned along the block into slot b
+  auto stage = [&](int b, const RowIn &q) {
     s += q.add;
     double p = s;
+    s -= q.sub;
     int pc = 0;
     if constexpr (CNT) {
       sc += q.addc;
       pc = sc;
+      sc -= q.subc;
     }
     p = wave_scan_incl(p);
     if constexpr (CNT) pc = wave_scan_incl(pc);
@@ -1518,32 +1522,31 @@ __global__ __launch_bounds__(BX_T) void box2d_kernel(PostPair one, const PostPai
       pfc[b][t] = pc;
       if (lane == WV - 1) wtc[b][wave] = pc;
     }
-    __syncthreads();
-    if (out_col) {
-      BoxStoreIn st = q.st;
-      const size_t k = (size_t)y * W + c;
-      if constexpr (CNT) {
-        const int cnt = prefixc(b, t + R) - (t - R - 1 >= 0 ? prefixc(b, t - R - 1) : 0);
-        st.cnt = (float)cnt;
-        ((GLOBAL float *)(grw(P.f) + (size_t)F_CNT * N))[k] = st.cnt;
-      }
-      box_store(P, A, N, k, prefix(b, t + R) - (t - R - 1 >= 0 ? prefix(b, t - R - 1) : 0.0), st);
-    }
-    s -= q.sub;
-    if constexpr (CNT) sc -= q.subc;
   };
-  RowIn q[BX_PF];
-#pragma unroll
-  for (int j = 0; j < BX_PF; ++j) q[j] = y0 + j < y1 ? fetch(y0 + j) : RowIn{};
-  for (int y = y0; y < y1; y += BX_PF) {  // y1 - y0 is uniform: every thread takes the same rows
-#pragma unroll
-    for (int j = 0; j < BX_PF; ++j) {
-      if (y + j < y1) {
-        const RowIn cj = q[j];
-        if (y + j + BX_PF < y1) q[j] = fetch(y + j + BX_PF);
-        process(y + j, cj);
-      }
+  auto emit = [&](int b, int y, const RowIn &q) {
+    if (!out_col) return;
+    BoxStoreIn st = q.st;
+    const size_t k = (size_t)y * W + c;
+    if constexpr (CNT) {
+      const int cnt = prefixc(b, t + R) - (t - R - 1 >= 0 ? prefixc(b, t - R - 1) : 0);
+      st.cnt = (float)cnt;
+      ((GLOBAL float *)(grw(P.f) + (size_t)F_CNT * N))[k] = st.cnt;
     }
+    box_store(P, A, N, k, prefix(b, t + R) - (t - R - 1 >= 0 ? prefix(b, t - R - 1) : 0.0), st);
+  };
+  RowIn q0 = y0 < y1 ? fetch(y0) : RowIn{};
+  RowIn q1 = y0 + 1 < y1 ? fetch(y0 + 1) : RowIn{};
+  // y1 - y0 is uniform: every thread takes the same rows and barriers
+  for (int y = y0, b = 0; y < y1; y += 2, b ^= 2) {
+    const RowIn c0 = q0, c1 = q1;
+    const bool two = y + 1 < y1;
+    if (y + 2 < y1) q0 = fetch(y + 2);
+    if (y + 3 < y1) q1 = fetch(y + 3);
+    stage(b, c0);
+    if (two) stage(b + 1, c1);
+    __syncthreads();
+    emit(b, y, c0);
+    if (two) emit(b + 1, y + 1, c1);
   }
 }
 
