@@ -211,11 +211,14 @@ __global__ __launch_bounds__(WS_T) void window_stats_kernel(PrepPair one, const 
 // ---------------------------------------------------------------- host launchers
 hipError_t launch_prep(const PrepPair &one, const PrepPair *many, int npairs, int maxH,
                        int maxCols, int maxW, int prec, hipStream_t s) {
-  const dim3 grid(ceil_div(maxCols, 4 * 256), maxH, npairs);
+  // one block per row (4 columns a thread) up to 4096 columns: a second,
+  // mostly idle block per row costs more than the wider block
+  const int nt = std::min(1024, (ceil_div(maxCols, 4) + WV - 1) / WV * WV);
+  const dim3 grid(ceil_div(maxCols, 4 * nt), maxH, npairs);
 #define PP(pr)                                                                                \
   do {                                                                                        \
-    if (many) hipLaunchKernelGGL((prep_planes_kernel<pr, true>), grid, dim3(256), 0, s, one, many); \
-    else hipLaunchKernelGGL((prep_planes_kernel<pr, false>), grid, dim3(256), 0, s, one, many);     \
+    if (many) hipLaunchKernelGGL((prep_planes_kernel<pr, true>), grid, dim3(nt), 0, s, one, many); \
+    else hipLaunchKernelGGL((prep_planes_kernel<pr, false>), grid, dim3(nt), 0, s, one, many);     \
   } while (0)
   if (prec == P_I16) PP(P_I16); else if (prec == P_F16) PP(P_F16); else PP(P_BF16);
 #undef PP
