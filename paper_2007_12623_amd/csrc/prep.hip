@@ -100,29 +100,15 @@ __global__ void prep_planes_kernel(PrepPair one, const PrepPair *many) {
 // image (dense and padded planes), 1: right image, 2: dense planes only.
 // A block of WS_T threads owns WS_T columns; each thread keeps the vertical
 // window sums of its column down a segment of WS_SY rows and the horizontal
-// sums are differences of a block prefix sum (wave scans plus wave totals in
-// LDS).  Output columns of a block are WS_T - 2 WS_HMAX wide for every window.
+// sums are differences of a block prefix sum (wave scans, then the wave
+// totals before each wave added through LDS).  Two rows share each of the
+// two barriers this takes.  Output columns of a block are WS_T - 2 WS_HMAX
+// wide for every window.
 // CH (chessboard window): a column keeps separate sums of its cells with
 // x + y even and odd; a pixel takes the prefix sums of its own colour, since
 // the cells u + v even around (x, y) are exactly those of the colour of
 // (x, y).
 constexpr int WS_T = 256, WS_SY = 16, WS_HMAX = 7, WS_NOUT = WS_T - 2 * WS_HMAX;
-
-template <int N>
-__device__ __forceinline__ void block_prefix(int (&a)[N], int (*wt)[4]) {
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-#pragma unroll
-  for (int i = 0; i < N; ++i) a[i] = wave_scan_incl(a[i]);
-  if (lane == 63) {
-#pragma unroll
-    for (int i = 0; i < N; ++i) wt[i][wave] = a[i];
-  }
-  __syncthreads();
-  for (int w = 0; w < wave; ++w) {
-#pragma unroll
-    for (int i = 0; i < N; ++i) a[i] += wt[i][w];
-  }
-}
 
 template <bool B, bool CH>
 __global__ __launch_bounds__(WS_T) void window_stats_kernel(PrepPair one, const PrepPair *many,
@@ -130,7 +116,7 @@ __global__ __launch_bounds__(WS_T) void window_stats_kernel(PrepPair one, const 
   const BlockPos bp = block_pos();
   const PrepPair &P = B ? many[bp.pair] : one;
   constexpr int NV = CH ? 4 : 2;  // (S, SS) of each colour
-  __shared__ int pf[2][NV][WS_T], wt[2][NV][4];
+  __shared__ int pf[2][NV][WS_T], wt[2][NV][WS_T / 64];
   const int H = P.H, W = P.W, win = P.win, h = win / 2;
   const int xo = bp.x * WS_NOUT, y0 = bp.y * WS_SY;
   if (xo >= W || y0 >= H) return;  // uniform per block
@@ -159,16 +145,30 @@ __global__ __launch_bounds__(WS_T) void window_stats_kernel(PrepPair one, const 
   const bool out_col = c >= xo && c < xo + WS_NOUT && c < W;  // then h <= t < WS_T - h
   const int y1 = min(y0 + WS_SY, H);
   const int n = CH ? (win * win + 1) / 2 : win * win;
-  for (int y = y0; y < y1; ++y) {
-    const int b = y & 1;
+  const int lane = t & 63, wave = t >> 6;
+  // the window sums of row y (add row y + h, then drop row y - h for the
+  // next), scanned along each wave; the wave totals go to slot b
+  auto stage = [&](int b, int y, int (&pv)[NV]) {
     step(y + h, 1);
-    int pv[NV];
 #pragma unroll
     for (int i = 0; i < NV; ++i) pv[i] = acc[i];
-    block_prefix<NV>(pv, wt[b]);
+    step(y - h, -1);
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      pv[i] = wave_scan_incl(pv[i]);
+      if (lane == 63) wt[b][i][wave] = pv[i];
+    }
+  };
+  // the block prefix: the totals of the waves before this one added
+  auto finish = [&](int b, int (&pv)[NV]) {
+    for (int w = 0; w < wave; ++w) {
+#pragma unroll
+      for (int i = 0; i < NV; ++i) pv[i] += wt[b][i][w];
+    }
 #pragma unroll
     for (int i = 0; i < NV; ++i) pf[b][i][t] = pv[i];
-    __syncthreads();
+  };
+  auto emit = [&](int b, int y) {
     if (out_col) {
       const int x = c;
       const int q = CH ? 2 * ((x + y) & 1) : 0;
@@ -204,7 +204,24 @@ __global__ __launch_bounds__(WS_T) void window_stats_kernel(PrepPair one, const 
         }
       }
     }
-    step(y - h, -1);
+  };
+  // y1 - y0 is uniform: every thread takes the same rows and barriers
+  // slot 0 row y, slot 1 row y + 1.  The first barrier: the wave totals are
+  // written before they are read, and the previous pair's outputs have read
+  // the prefix sums before they are written again.  The second: the prefix
+  // sums are complete before the outputs read them, and the totals read
+  // before the next pair writes them.
+  for (int y = y0; y < y1; y += 2) {
+    const bool two = y + 1 < y1;
+    int p0[NV], p1[NV];
+    stage(0, y, p0);
+    if (two) stage(1, y + 1, p1);
+    __syncthreads();
+    finish(0, p0);
+    if (two) finish(1, p1);
+    __syncthreads();
+    emit(0, y);
+    if (two) emit(1, y + 1);
   }
 }
 
