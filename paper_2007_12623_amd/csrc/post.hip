@@ -1433,12 +1433,11 @@ template <bool B, bool CNT>
 __global__ __launch_bounds__(BX_T) void box2d_kernel(PostPair one, const PostPair *__restrict__ many,
                                                      BoxArgs A) {
   PAIR;
-  // scans of two rows per barrier, in slots 0-1 and 2-3 alternately: a
-  // pair's slots are written again only after the next pair's barrier
-  __shared__ double pf[4][BX_T];
-  __shared__ double wt[4][BX_T / WV];
-  __shared__ int pfc[CNT ? 4 : 1][CNT ? BX_T : 1];
-  __shared__ int wtc[CNT ? 4 : 1][BX_T / WV];
+  // block prefix sums of two rows (slots 0 and 1) and their wave totals
+  __shared__ double pf[2][BX_T];
+  __shared__ double wt[2][BX_T / WV];
+  __shared__ int pfc[CNT ? 2 : 1][CNT ? BX_T : 1];
+  __shared__ int wtc[CNT ? 2 : 1][BX_T / WV];
   const int H = P.H, W = P.W, R = A.R;
   const int nout = BX_T - 2 * R;
   const int xo = bp.x * nout, y0 = bp.y * A.sy;
@@ -1477,17 +1476,6 @@ __global__ __launch_bounds__(BX_T) void box2d_kernel(PostPair one, const PostPai
     sc += cm;
   }
   const bool out_col = c >= xo && c < xo + nout && c < W;  // then R <= t < BX_T - R
-  // global prefix at column index i of the block from the stored wave scans
-  auto prefix = [&](int b, int i) -> double {
-    double v = pf[b][i];
-    for (int w = 0; w < i / WV; ++w) v += wt[b][w];
-    return v;
-  };
-  auto prefixc = [&](int b, int i) -> int {
-    int v = pfc[b][i];
-    for (int w = 0; w < i / WV; ++w) v += wtc[b][w];
-    return v;
-  };
   const int y1 = min(y0 + A.sy, H);
   // a row's inputs (entering and leaving rows, output-stage operands) are
   // loaded two rows ahead
@@ -1503,12 +1491,13 @@ __global__ __launch_bounds__(BX_T) void box2d_kernel(PostPair one, const PostPai
     q.st = out_col ? box_store_in(P, A, N, (size_t)y * W + c) : BoxStoreIn{};
     return q;
   };
-  // the column sums of a row, scanned along the block into slot b
-  auto stage = [&](int b, const RowIn &q) {
+  // the column sums of a row, scanned along each wave; the wave totals go
+  // to slot b
+  auto stage = [&](int b, const RowIn &q, double &p, int &pc) {
     s += q.add;
-    double p = s;
+    p = s;
     s -= q.sub;
-    int pc = 0;
+    pc = 0;
     if constexpr (CNT) {
       sc += q.addc;
       pc = sc;
@@ -1516,37 +1505,54 @@ __global__ __launch_bounds__(BX_T) void box2d_kernel(PostPair one, const PostPai
     }
     p = wave_scan_incl(p);
     if constexpr (CNT) pc = wave_scan_incl(pc);
-    pf[b][t] = p;
-    if (lane == WV - 1) wt[b][wave] = p;
-    if constexpr (CNT) {
-      pfc[b][t] = pc;
-      if (lane == WV - 1) wtc[b][wave] = pc;
+    if (lane == WV - 1) {
+      wt[b][wave] = p;
+      if constexpr (CNT) wtc[b][wave] = pc;
     }
+  };
+  // the block prefix: the totals of the waves before this one added
+  auto finish = [&](int b, double p, int pc) {
+    for (int w = 0; w < wave; ++w) {
+      p += wt[b][w];
+      if constexpr (CNT) pc += wtc[b][w];
+    }
+    pf[b][t] = p;
+    if constexpr (CNT) pfc[b][t] = pc;
   };
   auto emit = [&](int b, int y, const RowIn &q) {
     if (!out_col) return;
     BoxStoreIn st = q.st;
     const size_t k = (size_t)y * W + c;
     if constexpr (CNT) {
-      const int cnt = prefixc(b, t + R) - (t - R - 1 >= 0 ? prefixc(b, t - R - 1) : 0);
+      const int cnt = pfc[b][t + R] - (t - R - 1 >= 0 ? pfc[b][t - R - 1] : 0);
       st.cnt = (float)cnt;
       ((GLOBAL float *)(grw(P.f) + (size_t)F_CNT * N))[k] = st.cnt;
     }
-    box_store(P, A, N, k, prefix(b, t + R) - (t - R - 1 >= 0 ? prefix(b, t - R - 1) : 0.0), st);
+    box_store(P, A, N, k, pf[b][t + R] - (t - R - 1 >= 0 ? pf[b][t - R - 1] : 0.0), st);
   };
   RowIn q0 = y0 < y1 ? fetch(y0) : RowIn{};
   RowIn q1 = y0 + 1 < y1 ? fetch(y0 + 1) : RowIn{};
-  // y1 - y0 is uniform: every thread takes the same rows and barriers
-  for (int y = y0, b = 0; y < y1; y += 2, b ^= 2) {
+  // y1 - y0 is uniform: every thread takes the same rows and barriers.  Slot
+  // 0 row y, slot 1 row y + 1.  The first barrier: the wave totals are
+  // written before they are read, and the previous pair's outputs have read
+  // the prefix sums before they are written again.  The second: the prefix
+  // sums are complete before the outputs read them, and the totals read
+  // before the next pair writes them.
+  for (int y = y0; y < y1; y += 2) {
     const RowIn c0 = q0, c1 = q1;
     const bool two = y + 1 < y1;
     if (y + 2 < y1) q0 = fetch(y + 2);
     if (y + 3 < y1) q1 = fetch(y + 3);
-    stage(b, c0);
-    if (two) stage(b + 1, c1);
+    double p0, p1 = 0.0;
+    int pc0, pc1 = 0;
+    stage(0, c0, p0, pc0);
+    if (two) stage(1, c1, p1, pc1);
     __syncthreads();
-    emit(b, y, c0);
-    if (two) emit(b + 1, y + 1, c1);
+    finish(0, p0, pc0);
+    if (two) finish(1, p1, pc1);
+    __syncthreads();
+    emit(0, y, c0);
+    if (two) emit(1, y + 1, c1);
   }
 }
 
