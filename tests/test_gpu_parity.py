@@ -35,6 +35,8 @@ CASES = [
     (50, 190, -12, -5, 11, 14),     # D = 8, all negative
     (40, 260, 0, 40, 13, 15),
     (48, 300, 10, 60, 15, 16),
+    (30, 600, 0, 255, 7, 17),       # D = 256, the largest range
+    (30, 560, -3, 246, 5, 18),      # D = 250: last chunk shifted to d0 - dmin = 242
 ]
 
 
