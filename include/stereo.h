@@ -99,7 +99,9 @@ const char *st_last_error(void);
 /*
  * Whole stereo path of Section II for one rectified pair.
  *  left, right : H x W uint8 with row pitch `pitch` bytes
- *  dmin..dmax  : candidate disparities, 8 <= dmax - dmin + 1 <= 256
+ *  dmin..dmax  : candidate disparities within +-4096, 8 <= dmax - dmin + 1
+ *                <= 256; a range of 1..7 disparities is valid but not
+ *                implemented here (ST_EUNSUPPORTED)
  *  win         : odd window size, 3..15 (15 keeps every window sum exact in
  *                24 bits and the ZNCC numerator inside int32)
  *  disparity   : H x W float out; NaN where invalid
@@ -167,6 +169,9 @@ st_status stereo_refine_step(st_handle h, float *d, const float *grad_d, const u
  *  "delta" float         parabola offset
  *  "m_lr"  uint8         mask after the left-right check
  *  "o_post" int16, "m_post" uint8   disparity and mask after outlier removal/fills
+ *  with research = 1 and K = smooth_iters >= 2, for j = 1 .. K-1:
+ *  "o_rs<j>" int16  the discrete disparities after the j-th Eq. (4) re-search
+ *  "d_rs<j>" double the smoothed d^j that re-search was centred on
  * (integer disparities are -32768 where their mask is 0)
  * ST_EINVAL for an unknown name or when no debug run is held.
  */

@@ -96,7 +96,7 @@ def _setup(L):
     L.or_research.argtypes = [u8, u8] + [C.c_int] * 7 + [i32, u8, f64, C.c_int, C.c_double, i32]
     L.or_research.restype = None
     L.or_hc_research.argtypes = ([u8, u8] + [C.c_int] * 7 + [i32, u8, C.c_int, C.c_int, C.c_double,
-                                                             C.c_double, C.c_int, f64])
+                                                             C.c_double, C.c_int, C.c_void_p, f64])
     L.or_hc_research.restype = C.c_int
     L.or_reproject.argtypes = [C.c_int, C.c_int, f64, f64, f64]
     L.or_reproject.restype = None
@@ -200,14 +200,15 @@ def research(left, right, dmin, dmax, win, o, m, d, range_=5, eta=0.01, chess=Fa
 
 
 def hc_research(left, right, dmin, dmax, win, o, m, R, K, alpha=0.1, eta=0.01, range_=5,
-                chess=False):
-    """Eqs. (1)-(4): returns (d^K, final o)."""
+                chess=False, d_init=None):
+    """Eqs. (1)-(4): returns (d^K, final o).  d_init: d^0 (default o)."""
     L = _c(left, np.uint8); Rr = _c(right, np.uint8)
     H, W = L.shape
     oo = _c(o, np.int32).copy()
     out = np.zeros((H, W), np.float64)
+    di = None if d_init is None else _c(d_init, np.float64)
     rc = lib().or_hc_research(L, Rr, H, W, W, win, int(chess), dmin, dmax, oo, _c(m, np.uint8), R, K, alpha,
-                              eta, range_, out)
+                              eta, range_, None if di is None else di.ctypes.data, out)
     assert rc == 0, rc
     return out, oo
 

@@ -588,11 +588,12 @@ void or_research(const uint8_t *L, const uint8_t *R, int H, int W, int pitch, in
  *     o   = re-search around d^k                            (Eq. 4; k < K,
  *           the last update could not change d^K)
  * o (int32, in/out: the final discrete disparities), out = d^K (NaN where
- * invalid).
+ * invalid).  d_init (may be NULL): d^0 instead of o, so that the loop can be
+ * resumed from any iteration's state (o, d).
  */
 int or_hc_research(const uint8_t *L, const uint8_t *R, int H, int W, int pitch, int win, int chess,
                    int dmin, int dmax, int32_t *o, const uint8_t *m, int Rs, int K, double alpha,
-                   double eta, int range, double *out) {
+                   double eta, int range, const double *d_init, double *out) {
   int64_t N = (int64_t)H * W;
   double *od = malloc(sizeof(double) * (size_t)N), *a = malloc(sizeof(double) * (size_t)N);
   double *b = malloc(sizeof(double) * (size_t)N), *ab = malloc(sizeof(double) * (size_t)N);
@@ -601,7 +602,7 @@ int or_hc_research(const uint8_t *L, const uint8_t *R, int H, int W, int pitch, 
     free(od); free(a); free(b); free(ab); free(dprev);
     return OR_ENOMEM;
   }
-  for (int64_t k = 0; k < N; ++k) dprev[k] = m[k] ? (double)o[k] : NAN;
+  for (int64_t k = 0; k < N; ++k) dprev[k] = m[k] ? (d_init ? d_init[k] : (double)o[k]) : NAN;
   for (int it = 0; it < K; ++it) {
     for (int64_t k = 0; k < N; ++k) od[k] = (double)o[k];
     masked_mean(H, W, od, m, Rs, a);
@@ -714,7 +715,8 @@ int or_pipeline(const uint8_t *L, const uint8_t *R, int H, int W, int pitch, int
   for (int64_t k = 0; k < N; ++k) s[k] = mm[k] == 1 ? (double)oL[k] + dl[k] : (double)oL[k];
   if (p->research) {
     rc = or_hc_research(L, R, H, W, pitch, win, p->chess, dmin, dmax, oL, mm, p->smooth_radius,
-                        p->smooth_iters, p->smooth_alpha, p->research_eta, p->research_range, disp);
+                        p->smooth_iters, p->smooth_alpha, p->research_eta, p->research_range, NULL,
+                        disp);
     if (rc) goto done;
   } else if (p->smooth_iters > 0) {
     rc = or_hc_smooth(H, W, s, mm, p->smooth_radius, p->smooth_iters, p->smooth_alpha, disp);

@@ -99,7 +99,7 @@ struct st_handle_s {
   int device = 0;
   int ncu = 256;
   hipStream_t cap_stream = nullptr;
-  DevBuf ws, keys, rws;
+  DevBuf ws, keys, rws, dbgrs;
   bool keys_dirty = false;
   int variant = -1;
   std::map<std::string, int> tune;
@@ -146,10 +146,14 @@ static void release(DevBuf &b) {
 // ---------------------------------------------------------------- checks
 static st_status check_shape(int H, int W, int pitch, int dmin, int dmax, int win) {
   ARG(win >= 3 && win <= 15 && (win & 1), "win must be odd and in [3, 15] (got %d)", win);
-  ARG(dmax >= dmin, "dmax < dmin (%d < %d)", dmax, dmin);
-  ARG(dmax - dmin + 1 >= 8 && dmax - dmin + 1 <= 256,
-      "dmax - dmin + 1 must be in [8, 256] (got %d)", dmax - dmin + 1);
+  // bounds first, so that the range below is computed without overflow
   ARG(dmin >= -4096 && dmax <= 4096, "disparities beyond +-4096 are not supported");
+  ARG(dmax >= dmin, "dmax < dmin (%d < %d)", dmax, dmin);
+  const int D = dmax - dmin + 1;
+  ARG(D <= 256, "dmax - dmin + 1 must be at most 256 (got %d)", D);
+  // a valid request: the matcher's disparity chunks are 8 wide
+  if (D < 8)
+    return fail(ST_EUNSUPPORTED, "ranges of fewer than 8 disparities are not implemented (got %d)", D);
   ARG(H >= win && W >= win, "image %dx%d smaller than the window %d", W, H, win);
   ARG((long long)H * W <= (1LL << 28), "image too large");
   ARG(pitch >= W, "pitch %d < width %d", pitch, W);
@@ -373,6 +377,7 @@ static void fill_views(const PairLayout &Lo, void *base, uint32_t *keys, MatchPa
 struct DebugSink {
   void *mlr, *o, *m;
   size_t N;
+  HcTrace trace;  // the Eq. (4) loop's states (trace.n = 0: none kept)
 };
 
 // Every stage after the matcher, identical for the single and the batched
@@ -417,7 +422,7 @@ static hipError_t post_stages(const PostLaunch &L, const st_params &p, const Deb
     ck(hipMemcpyAsync(dbg->m, L.one.mb[cur], dbg->N, hipMemcpyDeviceToDevice, L.s));
   }
   ck(post_hc(L, cur, p.smooth_radius, p.smooth_iters, p.smooth_alpha, p.subpixel, p.research,
-             p.research_range, p.research_eta));
+             p.research_range, p.research_eta, dbg && dbg->trace.n > 0 ? &dbg->trace : nullptr));
   return e;
 }
 
@@ -518,6 +523,7 @@ void st_destroy(st_handle h) {
   release(h->ws);
   release(h->keys);
   release(h->rws);
+  release(h->dbgrs);
   if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   delete h;
 }
@@ -592,8 +598,18 @@ st_status stereo_match(st_handle h, const uint8_t *left, const uint8_t *right, i
   Q.disparity = disparity;
   Q.valid_mask = valid_mask;
   PostLaunch L = single_launch(Q, s);
+  const size_t N = (size_t)H * W;
   DebugSink sink{at<void>(h->ws.p, Lo.dbg_mlr), at<void>(h->ws.p, Lo.dbg_o),
-                 at<void>(h->ws.p, Lo.dbg_m), (size_t)H * W};
+                 at<void>(h->ws.p, Lo.dbg_m), N, HcTrace{nullptr, nullptr, 0}};
+  const int nrs = debug && params->research ? std::max(0, params->smooth_iters - 1) : 0;
+  if (nrs > 0) {
+    // the state after every re-search: o (int16) and the d it was centred on
+    rc = grow(h, h->dbgrs, (size_t)nrs * 10 * N + 256, false);
+    if (rc) return rc;
+    sink.trace.d = (double *)h->dbgrs.p;
+    sink.trace.o = (int16_t *)((double *)h->dbgrs.p + (size_t)nrs * N);
+    sink.trace.n = nrs;
+  }
   HIPCK(post_stages(L, *params, debug ? &sink : nullptr));
   if (debug) {
     h->dbg["o_wta"] = Q.ob[0];
@@ -607,6 +623,10 @@ st_status stereo_match(st_handle h, const uint8_t *left, const uint8_t *right, i
     h->dbg["m_lr"] = at<void>(h->ws.p, Lo.dbg_mlr);
     h->dbg["o_post"] = at<void>(h->ws.p, Lo.dbg_o);
     h->dbg["m_post"] = at<void>(h->ws.p, Lo.dbg_m);
+    for (int j = 0; j < nrs; ++j) {
+      h->dbg["o_rs" + std::to_string(j + 1)] = sink.trace.o + (size_t)j * N;
+      h->dbg["d_rs" + std::to_string(j + 1)] = sink.trace.d + (size_t)j * N;
+    }
   }
   return ST_OK;
 }
@@ -865,7 +885,10 @@ st_status stereo_match_batched(st_handle h, const st_pair *pairs, int n_pairs,
   for (int i = 0; i < n_pairs; ++i) {
     const st_pair &q = pairs[i];
     rc = check_shape(q.H, q.W, q.pitch, q.dmin, q.dmax, q.win);
-    if (rc) return fail(ST_EINVAL, "pair %d: %s", i, g_err.c_str());
+    if (rc) {
+      const std::string why = g_err;
+      return fail(rc, "pair %d: %s", i, why.c_str());
+    }
     ARG(q.left && q.right && q.disparity && q.valid_mask, "pair %d: NULL pointer", i);
   }
   ARG(h, "NULL handle");
@@ -881,6 +904,9 @@ st_status stereo_match_batched(st_handle h, const st_pair *pairs, int n_pairs,
     HIPCK(hipGraphLaunch(B.exec, s));
     return ST_OK;
   }
+  // a replay of the previous layout may still be queued (on this or another
+  // stream): its graph and the device tables it reads are replaced below
+  HIPCK(hipDeviceSynchronize());
   drop_batch(B);
   // one disparity chunk size for the whole launch, band height per pair
   const int DC = 8;

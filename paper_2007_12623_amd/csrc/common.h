@@ -203,8 +203,16 @@ hipError_t post_subpixel_lr(const PostLaunch &L, int tol, int dst);
 hipError_t post_outlier(const PostLaunch &L, int r, float thresh, int src, int dst);
 hipError_t post_fill(const PostLaunch &L, int radial_r, int min_lines, int disk_r, float frac,
                      int src, int tmp, int dst);
+// Per-iteration state of the Eq. (4) loop kept for a debug readout (single
+// pair): after re-search j (j = 0 .. n-1) the new o goes to o + j N and the
+// d it was centred on to d + j N.
+struct HcTrace {
+  int16_t *o;
+  double *d;
+  int n;
+};
 hipError_t post_hc(const PostLaunch &L, int src, int R, int K, float alpha, int use_delta,
-                   int research, int range, float eta);
+                   int research, int range, float eta, const HcTrace *trace = nullptr);
 // one Eq. (4) re-search: o from ob[osrc], mask mb[msrc], d from FP64 plane
 // dplane of f; the new o goes to ob[odst]
 hipError_t post_research(const PostLaunch &L, int osrc, int msrc, int odst, int dplane, int range,

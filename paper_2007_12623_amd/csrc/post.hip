@@ -1899,7 +1899,7 @@ hipError_t post_research(const PostLaunch &L, int osrc, int msrc, int odst, int 
 }
 
 hipError_t post_hc(const PostLaunch &L, int src, int R, int K, float alpha, int use_delta,
-                   int research, int range, float eta) {
+                   int research, int range, float eta, const HcTrace *trace) {
   if (K == 0) {
     LAUNCH(hc_copy_kernel, pixgrid(L), dim3(PIX_T), src, src, use_delta);
     return hipGetLastError();
@@ -1950,6 +1950,15 @@ hipError_t post_hc(const PostLaunch &L, int src, int R, int K, float alpha, int 
     if (it < K - 1) {
       LAUNCH(research_kernel, dim3(ceil_div(L.maxW, SP_TX), L.maxH, L.npairs), dim3(SP_TX), ocur,
              src, oalt, (int)F_D, range, (double)eta);
+      if (trace && !L.many && it < trace->n) {
+        const size_t N = (size_t)L.one.H * L.one.W;
+        hipError_t e = hipMemcpyAsync(trace->o + it * N, L.one.ob[oalt], 2 * N,
+                                      hipMemcpyDeviceToDevice, L.s);
+        if (e == hipSuccess)
+          e = hipMemcpyAsync(trace->d + it * N, L.one.f + (size_t)F_D * N, 8 * N,
+                             hipMemcpyDeviceToDevice, L.s);
+        if (e != hipSuccess) return e;
+      }
       std::swap(ocur, oalt);
     }
   }

@@ -54,14 +54,29 @@ def _match(**kw):
 
 @pytest.mark.parametrize("kw,msg", [
     (dict(win=4), "odd"), (dict(win=17), "odd"), (dict(win=1), "odd"),
-    (dict(dmin=5, dmax=4), "dmax < dmin"), (dict(dmin=0, dmax=3), "[8, 256]"),
-    (dict(dmin=0, dmax=256), "[8, 256]"), (dict(H=5), "smaller"), (dict(W=6), "smaller"),
+    (dict(dmin=5, dmax=4), "dmax < dmin"), (dict(dmin=0, dmax=256), "at most 256"),
+    (dict(dmin=-2 ** 31, dmax=2 ** 31 - 1), "4096"), (dict(dmin=-5000, dmax=-4990), "4096"),
+    (dict(H=5), "smaller"), (dict(W=6), "smaller"),
     (dict(pitch=99), "pitch"), (dict(left=None), "NULL"), (dict(mask=None), "NULL"),
     (dict(), "NULL handle"),
 ])
 def test_stereo_match_argument_errors(kw, msg):
     assert _match(**kw) == B.ST_EINVAL
     assert msg in B.st_last_error()
+
+
+@pytest.mark.parametrize("dmax", [0, 3, 6])
+def test_short_ranges_are_unsupported(dmax):
+    """Fewer than 8 candidates is a valid request that this build does not
+    implement: ST_EUNSUPPORTED, before any device call, also in a batch."""
+    assert _match(dmin=0, dmax=dmax) == B.ST_EUNSUPPORTED
+    assert "fewer than 8" in B.st_last_error()
+    arr = (B.st_pair * 2)()
+    arr[0] = B.st_pair(1, 1, 50, 60, 60, 0, 31, 7, 1, 1)
+    arr[1] = B.st_pair(1, 1, 50, 60, 60, 0, dmax, 7, 1, 1)
+    p = B.st_default_params()
+    assert B.lib().stereo_match_batched(None, arr, 2, C.byref(p), None) == B.ST_EUNSUPPORTED
+    assert "pair 1" in B.st_last_error()
 
 
 def test_params_struct_guard():

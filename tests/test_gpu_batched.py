@@ -3,6 +3,7 @@ across graph replays, and independent of the matcher's tile variant."""
 import numpy as np
 import pytest
 
+import e2e
 from gpu_util import cu, np_
 from paper_2007_12623_amd import synth
 
@@ -85,23 +86,77 @@ def test_matcher_variants_bit_identical(B):
         h.close()
 
 
-def test_uneven_batch_of_64(B):
-    """The 64-pair batch of four shapes, 32..192 candidates, 7x7 and 11x11:
-    spot-check 8 pairs against the per-pair path."""
+@pytest.fixture(scope="module")
+def c4(B):
+    """The 64-pair batch of four shapes, 32..192 candidates, 7x7 and 11x11,
+    run once through the batched launch."""
     import torch
     batch = synth.c4_batch()
     pairs = [{"left": cu(q["left"]), "right": cu(q["right"]), "dmin": q["dmin"], "dmax": q["dmax"],
               "win": q["win"]} for q in batch]
-    params = B.preset("full")
     h = B.Handle(0)
     try:
-        outs = B.stereo_match_batched(pairs, params, handle=h)
+        outs = B.stereo_match_batched(pairs, B.preset("full"), handle=h)
         torch.cuda.synchronize()
-        for i in range(0, 64, 8):
-            q = pairs[i]
-            ds, ms = B.stereo_match(q["left"], q["right"], q["dmin"], q["dmax"], q["win"], params,
-                                    handle=h)
-            assert np.array_equal(np_(outs[i][1]), np_(ms)), i
-            assert np.array_equal(np_(outs[i][0]), np_(ds), equal_nan=True), i
+        res = [(np_(d), np_(m)) for d, m in outs]
+        single = []
+        for q in pairs:
+            ds, ms = B.stereo_match(q["left"], q["right"], q["dmin"], q["dmax"], q["win"],
+                                    B.preset("full"), handle=h)
+            single.append((np_(ds), np_(ms)))
+    finally:
+        h.close()
+    return batch, res, single
+
+
+def test_uneven_batch_of_64_equals_single(c4):
+    """Every pair of the batch equals the per-pair path bit for bit."""
+    batch, res, single = c4
+    for i, ((d, m), (ds, ms)) in enumerate(zip(res, single)):
+        assert np.array_equal(m, ms), i
+        assert np.array_equal(d, ds, equal_nan=True), i
+
+
+@pytest.mark.parametrize("part", range(4))
+def test_uneven_batch_of_64_against_oracle(orc, c4, part):
+    """Every pair of the batch against the oracle's pipeline from its
+    images: masks exact and disparities within the smoothing bar outside
+    the reach of the matcher's near-ties (16 pairs per part)."""
+    batch, res, _ = c4
+    po = orc.params_c2()
+    for i in range(16 * part, 16 * part + 16):
+        q = batch[i]
+        ref = orc.match(q["left"], q["right"], q["dmin"], q["dmax"], q["win"])
+        n_cmp, n_excl = e2e.against_pipeline(orc, q["left"], q["right"], q["dmin"], q["dmax"],
+                                             q["win"], res[i][0], res[i][1], po, ref)
+        print(f"pair {i} {q['W']}x{q['H']} D={q['dmax'] + 1} win={q['win']}: "
+              f"compared {n_cmp} px, {n_excl} px within near-tie reach")
+
+
+def test_rebuild_on_a_side_stream_without_host_sync(B):
+    """Two batch layouts in a row on one non-default stream, no host
+    synchronisation between them: the second call replaces the graph and
+    the device tables that the first call's replay reads, so it must order
+    itself after that replay.  Both outputs equal the per-pair path."""
+    import torch
+    a = _mini_batch()
+    b = _mini_batch()[1:4]
+    params = B.preset("full", radial_r0=5, radial_dr=5, smooth_radius=4)
+    h = B.Handle(0)
+    s = torch.cuda.Stream()
+    try:
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            oa = B.stereo_match_batched(a, params, handle=h)
+            oa2 = B.stereo_match_batched(a, params, handle=h)   # graph replay
+            ob = B.stereo_match_batched(b, params, handle=h)    # rebuild
+        s.synchronize()
+        for batch, outs in ((a, oa2), (b, ob)):
+            for q, (d, m) in zip(batch, outs):
+                ds, ms = B.stereo_match(q["left"], q["right"], q["dmin"], q["dmax"], q["win"],
+                                        params, handle=h)
+                torch.cuda.synchronize()
+                assert np.array_equal(np_(m), np_(ms))
+                assert np.array_equal(np_(d), np_(ds), equal_nan=True)
     finally:
         h.close()

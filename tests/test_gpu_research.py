@@ -4,6 +4,7 @@ re-search mode."""
 import numpy as np
 import pytest
 
+import e2e
 from gpu_util import cu, np_
 from paper_2007_12623_amd import synth
 
@@ -49,29 +50,54 @@ def test_research_step_matches_oracle(B, orc, win, rng_, eta):
     assert np.array_equal(g[m == 0], o[m == 0])
 
 
-def test_research_pipeline(B, orc):
-    """The whole path with Eqs. (1)-(4) (K = 3, radius 15): masks exact,
-    disparities within the smoothing bar on all but near-tie re-search
-    decisions (several results can be correct there)."""
+@pytest.mark.parametrize("K", [3, 4])
+def test_research_pipeline(B, orc, K):
+    """The whole path with Eqs. (1)-(4) (radius 15), checked iteration by
+    iteration on the GPU's own state: each smoothing step from the GPU's
+    (o, d) must give the GPU's next d (FP64 on both sides), each re-search
+    around that d the GPU's next o (a differing pixel only where both
+    choices cost the same up to rounding), and the last step the output
+    within the smoothing bar.  Before the loop, every stage is checked as
+    in the plain pipeline."""
     import torch
     p = synth.make_pair(160, 400, 63, 77)
     L, R = p["left"], p["right"]
     Hh, Ww = L.shape
+    prm = B.preset("full", research=1, smooth_iters=K)
+    po = orc.params_c2(research=1, smooth_iters=K)
     h = B.Handle(0)
     try:
-        prm = B.preset("full", research=1, debug_outputs=1)
-        disp, mask = B.stereo_match(cu(L), cu(R), 0, 63, 11, prm, handle=h)
-        disp, mask = np_(disp), np_(mask)
-        o_post = np_(B.stereo_debug_get("o_post", (Hh, Ww), torch.int16, handle=h)).astype(np.int32)
-        m_post = np_(B.stereo_debug_get("m_post", (Hh, Ww), torch.uint8, handle=h))
+        g = e2e.run_debug(B, L, R, 0, 63, 11, prm, handle=h)
+        o_rs = [np_(B.stereo_debug_get(f"o_rs{j}", (Hh, Ww), torch.int16, handle=h)).astype(np.int32)
+                for j in range(1, K)]
+        d_rs = [np_(B.stereo_debug_get(f"d_rs{j}", (Hh, Ww), torch.float64, handle=h))
+                for j in range(1, K)]
     finally:
         h.close()
-    assert np.array_equal(mask, m_post)
-    dref, _ = orc.hc_research(L, R, 0, 63, 11, o_post, m_post, 15, 3,
-                              float(np.float32(0.1)), float(np.float32(0.01)), 5)
-    v = m_post > 0
-    assert np.isnan(disp[~v]).all()
-    tol = np.maximum(1e-5, np.spacing(np.abs(dref[v]).astype(np.float32)).astype(np.float64))
-    ok = np.abs(disp[v] - dref[v]) <= tol
-    print(f"re-search pipeline: {ok.mean():.6f} of valid pixels within the bar")
-    assert ok.mean() > 0.995
+    ref = orc.match(L, R, 0, 63, 11)
+    e2e.stagewise(orc, L, R, 0, 63, 11, g, po, ref)
+    m = g["m_post"]
+    v = m > 0
+    assert np.array_equal(g["mask"], m)
+    assert np.isnan(g["disp"][~v]).all()
+    alpha, eta = float(np.float32(0.1)), float(np.float32(0.01))
+    o, d = g["o_post"], np.where(v, g["o_post"], 0).astype(np.float64)
+    ties = 0
+    for j in range(1, K + 1):
+        dref, _ = orc.hc_research(L, R, 0, 63, 11, o, m, 15, 1, alpha, eta, 5, d_init=d)
+        if j == K:
+            err = np.abs(g["disp"][v] - dref[v])
+            assert (err <= e2e.smooth_bar(dref[v])).all(), err.max()
+            break
+        dg = d_rs[j - 1]
+        np.testing.assert_allclose(dg[v], dref[v], rtol=0, atol=1e-9)
+        og = o_rs[j - 1]
+        want = orc.research(L, R, 0, 63, 11, o, m, dg, 5, eta)
+        assert np.array_equal(og[~v], o[~v])
+        for (y, x) in np.argwhere(og != want):
+            cg = _cost(L, R, y, x, int(og[y, x]), dg[y, x], 11, eta)
+            cw = _cost(L, R, y, x, int(want[y, x]), dg[y, x], 11, eta)
+            assert abs(cg - cw) < 1e-9, (j, y, x, og[y, x], want[y, x], cg, cw)
+            ties += 1
+        o, d = og, dg
+    print(f"re-search pipeline K={K}: {ties} re-search decisions were cost ties")

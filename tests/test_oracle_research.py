@@ -165,3 +165,23 @@ def test_no_candidate_keeps_o(orc):
     d = np.full((30, 80), 7.5)
     o = orc.research(p["left"], p["right"], 0, 15, 5, o0, m, d, 0, 0.01)
     assert (o == 6).all()
+
+
+def test_resume_from_a_state(orc):
+    """d_init resumes the loop from a state (o, d): one iteration gives
+    d = a - A(a - alpha o - (1 - alpha) d_init), a = A(o) (Eqs. (1)-(3) by
+    hand with scipy box means), and no re-search runs (K = 1)."""
+    p = synth.make_pair(40, 90, 31, 12)
+    r = np.random.default_rng(5)
+    o = r.integers(5, 25, size=(40, 90)).astype(np.int32)
+    m = (r.random((40, 90)) > 0.25).astype(np.uint8)
+    d0 = o + r.uniform(-1.5, 1.5, size=(40, 90))
+    Rs, alpha = 3, 0.1
+    v = m == 1
+    a = _masked_mean(o.astype(np.float64), m, Rs)
+    b = a - alpha * o - (1 - alpha) * d0
+    want = a - _masked_mean(np.where(v, b, 0.0), m, Rs)
+    got, oo = orc.hc_research(p["left"], p["right"], 0, 31, 7, o, m, Rs, 1, alpha, 0.01, 5,
+                              d_init=d0)
+    np.testing.assert_allclose(got[v], want[v], rtol=0, atol=1e-11)
+    assert np.array_equal(oo, o)
