@@ -65,6 +65,11 @@ def lib() -> C.CDLL:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with "
                               "`python -c 'import __graft_entry__ as g; g.build()'`")
+        # torch ships its own HIP runtime under the same soname as the ROCm
+        # one the library was linked against: loading torch first makes the
+        # library bind to that runtime, so the process holds one HIP runtime
+        # (with the ROCm copy loaded first, torch then finds no GPU)
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         vp, i32, f32 = C.c_void_p, C.c_int, C.c_float
         sig = {

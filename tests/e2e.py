@@ -75,17 +75,18 @@ def stagewise(orc, L, R, dmin, dmax, win, g, po, ref, tie_bar=1e-5):
     rep["int_disagree_frac"] = float(dis.sum() / max(1, vl.sum()))
     rep["int_disagree_above_bar_px"] = bad
     rep["right_int_disagree_px"] = int(disr.sum())
-    # the exact z at the GPU's winner: equal to the oracle's where the
-    # winners agree, and below it by less than the tie bar where they do not
     agree = vl & ~dis
-    dz = np.abs(g["zbest"][vl] - ref["zbest"][vl])
-    np.testing.assert_allclose(g["zbest"][agree], ref["zbest"][agree], rtol=0, atol=1e-12)
-    assert (dz <= tie_bar + 1e-12).all()
-    rep["max_abs_dz"] = float(dz.max()) if dz.size else 0.0
-    rep["mean_abs_dz"] = float(dz.mean()) if dz.size else 0.0
-    # sub-pixel offsets where the winners agree
     dl = g["delta"]
     if po.subpixel:
+        # the exact z at the GPU's winner (computed by the sub-pixel step):
+        # equal to the oracle's where the winners agree, and below it by less
+        # than the tie bar where they do not
+        dz = np.abs(g["zbest"][vl] - ref["zbest"][vl])
+        np.testing.assert_allclose(g["zbest"][agree], ref["zbest"][agree], rtol=0, atol=1e-12)
+        assert (dz <= tie_bar + 1e-12).all()
+        rep["max_abs_dz"] = float(dz.max()) if dz.size else 0.0
+        rep["mean_abs_dz"] = float(dz.mean()) if dz.size else 0.0
+        # sub-pixel offsets where the winners agree
         dref = orc.subpixel(ref["oL"], ref["mL"], ref["zm"], ref["zbest"], ref["zp"], dmin, dmax)
         dd = np.abs(dl[agree] - dref[agree])
         assert dd.size == 0 or dd.max() <= 1e-5

@@ -1,5 +1,6 @@
 """Batched persistent launch: equal to the per-pair path bit for bit, stable
-across graph replays, and independent of the matcher's tile variant."""
+across graph replays, and independent of the matcher's tile variant; every
+pair of the 64-pair uneven batch checked against the oracle stage by stage."""
 import numpy as np
 import pytest
 
@@ -118,19 +119,28 @@ def test_uneven_batch_of_64_equals_single(c4):
 
 
 @pytest.mark.parametrize("part", range(4))
-def test_uneven_batch_of_64_against_oracle(orc, c4, part):
-    """Every pair of the batch against the oracle's pipeline from its
-    images: masks exact and disparities within the smoothing bar outside
-    the reach of the matcher's near-ties (16 pairs per part)."""
+def test_uneven_batch_of_64_against_oracle(B, orc, c4, part):
+    """Every pair of the batch against the oracle (16 pairs per part): the
+    pair's debug run through the per-pair path gives the batched output bit
+    for bit, and every stage of it equals the oracle's stage run on the same
+    input (matching exact away from near-ties, later stages exact or within
+    the smoothing bar)."""
     batch, res, _ = c4
     po = orc.params_c2()
-    for i in range(16 * part, 16 * part + 16):
-        q = batch[i]
-        ref = orc.match(q["left"], q["right"], q["dmin"], q["dmax"], q["win"])
-        n_cmp, n_excl = e2e.against_pipeline(orc, q["left"], q["right"], q["dmin"], q["dmax"],
-                                             q["win"], res[i][0], res[i][1], po, ref)
-        print(f"pair {i} {q['W']}x{q['H']} D={q['dmax'] + 1} win={q['win']}: "
-              f"compared {n_cmp} px, {n_excl} px within near-tie reach")
+    h = B.Handle(0)
+    try:
+        for i in range(16 * part, 16 * part + 16):
+            q = batch[i]
+            L, R, dmin, dmax, win = q["left"], q["right"], q["dmin"], q["dmax"], q["win"]
+            g = e2e.run_debug(B, L, R, dmin, dmax, win, B.preset("full"), handle=h)
+            assert np.array_equal(g["mask"], res[i][1]), i
+            assert np.array_equal(g["disp"], res[i][0], equal_nan=True), i
+            ref = orc.match(L, R, dmin, dmax, win)
+            rep = e2e.stagewise(orc, L, R, dmin, dmax, win, g, po, ref)
+            print(f"pair {i} {q['W']}x{q['H']} D={dmax - dmin + 1} win={win}: stage-wise exact; "
+                  f"{rep['int_disagree_px']} near-tie winners differ", flush=True)
+    finally:
+        h.close()
 
 
 def test_rebuild_on_a_side_stream_without_host_sync(B):
