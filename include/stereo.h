@@ -112,6 +112,33 @@ st_status stereo_match(st_handle h, const uint8_t *left, const uint8_t *right, i
                        int pitch, int dmin, int dmax, int win, const st_params *params,
                        float *disparity, uint8_t *valid_mask, void *stream);
 
+/* Bytes of the fixed per-GPU scratch array behind stereo_match_noalloc. */
+#define ST_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/*
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The same
+ * computation and result as stereo_match (same arguments, same kernels),
+ * but every intermediate lives in one static device array of
+ * ST_NOALLOC_SCRATCH_BYTES (64 MiB) that each GPU the library runs on holds
+ * until the process ends; the call allocates and frees nothing.  The caller
+ * still owns the images and the outputs.
+ *  - Enough for a 960x540 pair at up to 256 disparities and any window, the
+ *    chessboard window included, and for every smaller pair.  A pair whose
+ *    planes, maps and keys need more returns ST_EUNSUPPORTED before any
+ *    device call, with the bytes needed in st_last_error().
+ *  - params->debug_outputs must be 0 (the debug buffers belong to the
+ *    handle): ST_EINVAL otherwise.
+ *  - Every call on one GPU shares that GPU's array and it keeps the last
+ *    call's contents (the call clears what must start at zero itself).
+ *    Calls that overlap on one GPU - from several handles, host threads or
+ *    streams without ordering between them - race on it.
+ */
+st_status stereo_match_noalloc(st_handle h, const uint8_t *left, const uint8_t *right, int H,
+                               int W, int pitch, int dmin, int dmax, int win,
+                               const st_params *params, float *disparity, uint8_t *valid_mask,
+                               void *stream);
+
 /* One pair of a batch: same meaning as the stereo_match arguments. */
 typedef struct {
   const uint8_t *left, *right;

@@ -27,7 +27,7 @@ EXPORTS = ("st_default_params", "st_create", "st_destroy", "st_last_error", "ste
            "stereo_refine_step", "stereo_debug_get", "st_window_stats", "st_match_wta",
            "st_subpixel", "st_lr_check", "st_radial_outlier", "st_fill", "st_hc_smooth", "st_reproject", "st_research",
            "st_autotune", "st_set_variant", "st_num_variants", "st_variant_name", "st_version",
-           "stereo_time_matcher")
+           "stereo_time_matcher", "stereo_match_noalloc")
 
 
 class StereoError(RuntimeError):
@@ -80,6 +80,8 @@ def lib() -> C.CDLL:
             "st_version": (C.c_char_p, []),
             "stereo_match": (i32, [vp, vp, vp, i32, i32, i32, i32, i32, i32,
                                    C.POINTER(st_params), vp, vp, vp]),
+            "stereo_match_noalloc": (i32, [vp, vp, vp, i32, i32, i32, i32, i32, i32,
+                                           C.POINTER(st_params), vp, vp, vp]),
             "stereo_match_batched": (i32, [vp, C.POINTER(st_pair), i32, C.POINTER(st_params), vp]),
             "stereo_refine_forward": (i32, [vp, vp, vp, vp, vp, i32, i32, i32, i32, f32, vp, vp, vp]),
             "stereo_refine_backward": (i32, [vp, vp, vp, vp, vp, i32, i32, i32, i32, f32, vp, vp]),
@@ -207,6 +209,21 @@ def stereo_match(left, right, dmin, dmax, win, params=None, disparity=None, vali
     _check(lib().stereo_match(_h(handle), left.data_ptr(), right.data_ptr(), H, W, left.stride(0),
                               dmin, dmax, win, C.byref(params), disparity.data_ptr(),
                               valid_mask.data_ptr(), _stream(stream)))
+    return disparity, valid_mask
+
+
+def stereo_match_noalloc(left, right, dmin, dmax, win, params, disparity, valid_mask,
+                         handle=None, stream=None):
+    """stereo_match with every intermediate in the library's fixed per-GPU
+    scratch array (no device allocation); the outputs must be given."""
+    import torch
+    assert left.dtype == torch.uint8 and right.dtype == torch.uint8 and left.is_cuda
+    assert left.shape == right.shape and left.stride() == right.stride() and left.stride(1) == 1
+    H, W = left.shape
+    _check(lib().stereo_match_noalloc(_h(handle), left.data_ptr(), right.data_ptr(), H, W,
+                                      left.stride(0), dmin, dmax, win, C.byref(params),
+                                      disparity.data_ptr(), valid_mask.data_ptr(),
+                                      _stream(stream)))
     return disparity, valid_mask
 
 

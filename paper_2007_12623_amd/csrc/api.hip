@@ -11,6 +11,7 @@
 #include <cstring>
 #include <fstream>
 #include <map>
+#include <mutex>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -106,6 +107,33 @@ struct st_handle_s {
   std::map<std::string, void *> dbg;
   BatchCache batch;
 };
+
+// ---------------------------------------------------------------- fixed scratch
+// The scratch of stereo_match_noalloc: a file-scope device array, of which
+// every GPU the library runs on holds its own copy until the process ends.
+// In host code the array's name is only a host-side stand-in: kernels get the
+// device address that hipGetSymbolAddress returns for the current device,
+// looked up once per device when the first handle on it is created.
+static __device__ __align__(256) unsigned char scratch[ST_NOALLOC_SCRATCH_BYTES];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch[kMaxDevices];
+
+// This device's copy of `scratch` (the device must be current).
+static st_status scratch_lookup(int device) {
+  if (device >= kMaxDevices) return fail(ST_EUNSUPPORTED, "device %d: at most %d devices", device, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch[device]) return ST_OK;
+  void *p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p) {
+    (void)hipGetLastError();
+    return fail(ST_EHIP, "hipGetSymbolAddress(scratch) on device %d failed: %s", device,
+                hipGetErrorString(e));
+  }
+  g_scratch[device] = p;
+  return ST_OK;
+}
 
 static bool fault_alloc() {
   const char *e = getenv("STEREO_FAULT");
@@ -493,6 +521,11 @@ st_status st_create(st_handle *out, int device) {
   st_handle h = new st_handle_s();
   h->device = device;
   h->ncu = prop.multiProcessorCount;
+  const st_status rs = scratch_lookup(device);
+  if (rs != ST_OK) {
+    delete h;
+    return rs;
+  }
   if (hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess) {
     delete h;
     return fail(ST_EHIP, "cannot create the capture stream");
@@ -628,6 +661,49 @@ st_status stereo_match(st_handle h, const uint8_t *left, const uint8_t *right, i
       h->dbg["d_rs" + std::to_string(j + 1)] = sink.trace.d + (size_t)j * N;
     }
   }
+  return ST_OK;
+}
+
+st_status stereo_match_noalloc(st_handle h, const uint8_t *left, const uint8_t *right, int H,
+                               int W, int pitch, int dmin, int dmax, int win,
+                               const st_params *params, float *disparity, uint8_t *valid_mask,
+                               void *stream) {
+  st_status rc = check_shape(H, W, pitch, dmin, dmax, win);
+  if (rc) return rc;
+  rc = check_params(params);
+  if (rc) return rc;
+  ARG(left && right && disparity && valid_mask, "NULL image or output pointer");
+  ARG(h, "NULL handle");
+  ARG(!params->debug_outputs,
+      "debug_outputs needs handle-owned buffers: use stereo_match for a debug run");
+  void *base = h->device < kMaxDevices ? g_scratch[h->device] : nullptr;
+  if (!base) return fail(ST_EHIP, "no scratch address for device %d", h->device);
+  const int prec = params->precision;
+  const int v = pick_variant(h, H, W, win, dmin, dmax, prec);
+  MatchPair M;
+  PrepPair Pp;
+  PostPair Q;
+  make_geom(M, H, W, win, dmin, dmax, kDC, variant_TY(v), variant_CG(v), params->chessboard);
+  const PairLayout Lo = layout(M, prec, false);
+  const size_t N = (size_t)H * W;
+  const size_t koff = (Lo.total + 255) & ~(size_t)255, need = koff + 8 * N;
+  if (need > (size_t)ST_NOALLOC_SCRATCH_BYTES)
+    return fail(ST_EUNSUPPORTED,
+                "a %dx%d pair with %d disparities needs %zu bytes of scratch; the fixed scratch "
+                "of stereo_match_noalloc holds %zu",
+                W, H, dmax - dmin + 1, need, (size_t)ST_NOALLOC_SCRATCH_BYTES);
+  SETDEV(h);
+  hipStream_t s = (hipStream_t)stream;
+  uint32_t *keys = at<uint32_t>(base, koff);
+  // the merged keys must start at zero whatever the last call left: cleared
+  // by a kernel (no memset node if the caller captures the stream)
+  HIPCK(launch_fill_u32(keys, (int)(2 * N), 0u, s));
+  fill_views(Lo, base, keys, M, Pp, Q, left, right, pitch);
+  rc = run_front(h, M, Pp, prec, s);
+  if (rc) return rc;
+  Q.disparity = disparity;
+  Q.valid_mask = valid_mask;
+  HIPCK(post_stages(single_launch(Q, s), *params, nullptr));
   return ST_OK;
 }
 
