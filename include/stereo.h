@@ -292,13 +292,37 @@ st_status st_reproject(st_handle h, const float *disparity, int H, int W, const 
 /* ---- tuning ---- */
 
 /* Time the matcher's tile variants (band height, disparity chunks per
- * workgroup) for one problem shape on the handle's device and remember the
+ * workgroup, disparities per lane) for one problem shape on the handle's
+ * device (a seeded texture and its shift: the matcher's work does not
+ * depend on the image content) and remember the
  * fastest for that (win, disparity-count bucket, width bucket, precision).  The table
  * is saved to / loaded from the JSON file named by the environment variable
  * STEREO_TUNE_CACHE when it is set.  *best_cfg (host, may be NULL) receives
  * the chosen variant id. */
 st_status st_autotune(st_handle h, int H, int W, int dmin, int dmax, int win, int precision,
                       int *best_cfg, void *stream);
+
+/*
+ * Autotuner of the batched launch: for every window size in the batch, the
+ * persistent matcher launch of that window's pairs is timed (reps launches,
+ * HIP events on `stream`) under each matcher variant - band height, chunks
+ * per workgroup task and disparities per lane, st_variant_name() - and the
+ * fastest is kept in the handle's tuning table under a key of the batch
+ * layout (the window, precision, window shape and every pair's size and
+ * range), which stereo_match_batched reads when it builds the graph of a
+ * batch with that layout (and the STEREO_TUNE_CACHE file keeps).  Runs the
+ * whole batch once per variant, so it writes the pairs' outputs; they end
+ * as stereo_match_batched leaves them with the tuned choice.
+ *  best_cfg : host array of n_pairs ints (may be NULL): the variant chosen
+ *             for each pair's window size
+ * Same argument errors as stereo_match_batched; reps outside [1, 1000]
+ * gives ST_EINVAL.
+ */
+st_status st_autotune_batched(st_handle h, const st_pair *pairs, int n_pairs,
+                              const st_params *params, int reps, int *best_cfg, void *stream);
+/* The variant the handle's current batched graph uses for window size win
+ * (-1 if no batch is held or none of its pairs has that window). */
+int st_batch_variant(st_handle h, int win);
 
 /* Average duration in milliseconds (*ms_out, host) of the batched matcher
  * kernel alone, timed with HIP events on `stream` around each of `reps`

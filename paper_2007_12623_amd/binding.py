@@ -27,7 +27,8 @@ EXPORTS = ("st_default_params", "st_create", "st_destroy", "st_last_error", "ste
            "stereo_refine_step", "stereo_debug_get", "st_window_stats", "st_match_wta",
            "st_subpixel", "st_lr_check", "st_radial_outlier", "st_fill", "st_hc_smooth", "st_reproject", "st_research",
            "st_autotune", "st_set_variant", "st_num_variants", "st_variant_name", "st_version",
-           "stereo_time_matcher", "stereo_match_noalloc")
+           "stereo_time_matcher", "stereo_match_noalloc", "st_autotune_batched",
+           "st_batch_variant")
 
 
 class StereoError(RuntimeError):
@@ -98,6 +99,9 @@ def lib() -> C.CDLL:
             "st_research": (i32, [vp, vp, vp] + [i32] * 7 + [vp, vp, vp, i32, f32, vp, vp]),
             "st_autotune": (i32, [vp, i32, i32, i32, i32, i32, i32, C.POINTER(i32), vp]),
             "st_set_variant": (i32, [vp, i32]),
+            "st_autotune_batched": (i32, [vp, C.POINTER(st_pair), i32, C.POINTER(st_params), i32,
+                                          C.POINTER(i32), vp]),
+            "st_batch_variant": (i32, [vp, i32]),
             "stereo_time_matcher": (i32, [vp, C.POINTER(st_pair), i32, C.POINTER(st_params), i32,
                                           C.POINTER(C.c_float), vp]),
             "st_num_variants": (i32, []),
@@ -409,6 +413,22 @@ def st_autotune(H, W, dmin, dmax, win, precision=ST_FP32, handle=None, stream=No
     _check(lib().st_autotune(_h(handle), H, W, dmin, dmax, win, precision, C.byref(best),
                              _stream(stream)))
     return best.value
+
+
+def st_autotune_batched(pairs, params=None, reps=3, handle=None, stream=None) -> list:
+    """Tune the persistent launch of every window size of this batch layout;
+    returns the variant chosen for each pair."""
+    if params is None:
+        params = st_default_params()
+    arr, _ = _pair_array(pairs)
+    best = (C.c_int * len(pairs))()
+    _check(lib().st_autotune_batched(_h(handle), arr, len(pairs), C.byref(params), reps, best,
+                                     _stream(stream)))
+    return list(best)
+
+
+def st_batch_variant(win: int, handle=None) -> int:
+    return lib().st_batch_variant(_h(handle), win)
 
 
 def st_set_variant(variant: int, handle=None) -> None:

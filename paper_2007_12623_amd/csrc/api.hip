@@ -57,17 +57,20 @@ static st_status fail(st_status s, const char *fmt, ...) {
   } while (0)
 
 // ---------------------------------------------------------------- variants
-// Matcher tilings: band height TY and chunks per workgroup task CG, in the
-// order the default choice prefers them.  Bands of 8 rows come first: their
-// key tiles (about 37 KB) leave room for three workgroups per CU, which the
-// matcher's register budget (three waves per SIMD) is sized for; among them
-// fewer key merges and fewer vertical-sum restarts first.  Every disparity
-// chunk is 8 wide.
+// Matcher tilings: band height TY, chunks per workgroup task CG and
+// disparities per lane DC (the chunk width), in the order the default
+// choice prefers them.  Bands of 8 rows come first: their key tiles (about
+// 37 KB) leave room for three workgroups per CU, which the matcher's
+// register budget (three waves per SIMD) is sized for; among them fewer key
+// merges and fewer vertical-sum restarts first.  Chunks of 4 disparities
+// halve the registers of the running sums but convert and merge twice as
+// many keys per evaluation; the autotuners try them like any other tiling.
 struct Variant {
-  int TY, CG;
+  int TY, CG, DC;
 };
-static const Variant kVariants[] = {{8, 16}, {8, 8},  {16, 16}, {16, 8}, {8, 4},
-                                    {16, 4}, {8, 2},  {16, 2},  {4, 4},  {4, 2}};
+static const Variant kVariants[] = {{8, 16, 8}, {8, 8, 8},  {16, 16, 8}, {16, 8, 8}, {8, 4, 8},
+                                    {16, 4, 8}, {8, 2, 8},  {16, 2, 8},  {4, 4, 8},  {4, 2, 8},
+                                    {8, 32, 4}, {8, 16, 4}, {16, 32, 4}, {8, 8, 4}};
 static const int kNumVariants = (int)(sizeof kVariants / sizeof kVariants[0]);
 
 // ---------------------------------------------------------------- handle
@@ -80,10 +83,11 @@ struct BatchCache {
   std::vector<st_pair> pairs;
   st_params params{};
   int variant = -2;
+  unsigned tune_gen = 0;  // the tuning table's generation the graph was built with
   // what the matcher launches of this batch need, for stereo_time_matcher:
   // one persistent launch per window size present in the batch
   struct Group {
-    int win, off, ntasks, nblocks;
+    int win, dc, variant, off, ntasks, nblocks;
     size_t lds;
   };
   std::vector<Group> groups;
@@ -100,10 +104,15 @@ struct st_handle_s {
   int device = 0;
   int ncu = 256;
   hipStream_t cap_stream = nullptr;
+  // a second capture stream and its fork / join events: the persistent
+  // launches of a batch's window sizes after the first run beside it
+  hipStream_t side_stream = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   DevBuf ws, keys, rws, dbgrs;
   bool keys_dirty = false;
   int variant = -1;
   std::map<std::string, int> tune;
+  unsigned tune_gen = 0;  // bumped whenever the tuning table changes
   std::map<std::string, void *> dbg;
   BatchCache batch;
 };
@@ -456,7 +465,7 @@ static hipError_t post_stages(const PostLaunch &L, const st_params &p, const Deb
 
 static int variant_TY(int v) { return kVariants[v].TY; }
 static int variant_CG(int v) { return kVariants[v].CG; }
-static constexpr int kDC = 8;
+static int variant_DC(int v) { return kVariants[v].DC; }
 
 extern "C" {
 
@@ -495,11 +504,13 @@ int st_num_variants(void) { return kNumVariants; }
 const char *st_variant_name(int v) {
   static thread_local char buf[64];
   if (v < 0 || v >= kNumVariants) return "";
-  snprintf(buf, sizeof buf, "TY=%d,CG=%d", kVariants[v].TY, kVariants[v].CG);
+  snprintf(buf, sizeof buf, "TY=%d,CG=%d,DC=%d", kVariants[v].TY, kVariants[v].CG,
+           kVariants[v].DC);
   return buf;
 }
 
 static void load_tune(st_handle h);
+static void save_tune(st_handle h);
 
 st_status st_create(st_handle *out, int device) {
   ARG(out, "out is NULL");
@@ -526,9 +537,15 @@ st_status st_create(st_handle *out, int device) {
     delete h;
     return rs;
   }
-  if (hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+  if (hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&h->side_stream, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&h->fork_ev, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&h->join_ev, hipEventDisableTiming) != hipSuccess) {
+    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+    if (h->side_stream) (void)hipStreamDestroy(h->side_stream);
+    if (h->fork_ev) (void)hipEventDestroy(h->fork_ev);
     delete h;
-    return fail(ST_EHIP, "cannot create the capture stream");
+    return fail(ST_EHIP, "cannot create the capture streams");
   }
   load_tune(h);
   *out = h;
@@ -558,6 +575,9 @@ void st_destroy(st_handle h) {
   release(h->rws);
   release(h->dbgrs);
   if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+  if (h->side_stream) (void)hipStreamDestroy(h->side_stream);
+  if (h->fork_ev) (void)hipEventDestroy(h->fork_ev);
+  if (h->join_ev) (void)hipEventDestroy(h->join_ev);
   delete h;
 }
 
@@ -566,7 +586,8 @@ static st_status setup_single(st_handle h, const uint8_t *left, const uint8_t *r
                               int pitch, int dmin, int dmax, int win, int chess, int prec,
                               int variant, bool debug, MatchPair &M, PrepPair &Pp, PostPair &Q,
                               PairLayout &Lo, hipStream_t s) {
-  make_geom(M, H, W, win, dmin, dmax, kDC, variant_TY(variant), variant_CG(variant), chess);
+  make_geom(M, H, W, win, dmin, dmax, variant_DC(variant), variant_TY(variant), variant_CG(variant),
+            chess);
   Lo = layout(M, prec, debug);
   st_status rc = grow(h, h->ws, Lo.total, false);
   if (rc) return rc;
@@ -683,7 +704,8 @@ st_status stereo_match_noalloc(st_handle h, const uint8_t *left, const uint8_t *
   MatchPair M;
   PrepPair Pp;
   PostPair Q;
-  make_geom(M, H, W, win, dmin, dmax, kDC, variant_TY(v), variant_CG(v), params->chessboard);
+  make_geom(M, H, W, win, dmin, dmax, variant_DC(v), variant_TY(v), variant_CG(v),
+            params->chessboard);
   const PairLayout Lo = layout(M, prec, false);
   const size_t N = (size_t)H * W;
   const size_t koff = (Lo.total + 255) & ~(size_t)255, need = koff + 8 * N;
@@ -953,6 +975,58 @@ st_status st_hc_smooth(st_handle h, const float *s_in, const uint8_t *m, int H, 
 }
 
 // ---------------------------------------------------------------- batched
+// Tuning-table key of the persistent launch of one window size of a batch:
+// window, precision, window shape and the size and range of each of that
+// window's pairs in order (64-bit FNV-1a).
+static std::string batch_key(const st_pair *pairs, int n, int win, int prec, int chess) {
+  uint64_t x = 1469598103934665603ull;
+  auto mix = [&](int v) {
+    for (int b = 0; b < 4; ++b) {
+      x ^= (uint8_t)((uint32_t)v >> (8 * b));
+      x *= 1099511628211ull;
+    }
+  };
+  for (int i = 0; i < n; ++i)
+    if (pairs[i].win == win) {
+      mix(pairs[i].H);
+      mix(pairs[i].W);
+      mix(pairs[i].dmin);
+      mix(pairs[i].dmax);
+    }
+  char b[96];
+  snprintf(b, sizeof b, "b_w%d_p%d_c%d_%016llx", win, prec, chess, (unsigned long long)x);
+  return b;
+}
+
+// The persistent matcher launches of the current batch on stream s, one per
+// window size: the first on s, the others one after another on the side
+// stream, forked from s after the work already on it and joined back into
+// it, so that each launch's workgroups take the CUs that the launch beside
+// it frees at its tail.  ev0 / ev1 (may be null) bracket all of them on s.
+static hipError_t launch_groups(st_handle h, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+  BatchCache &B = h->batch;
+  hipError_t e = hipSuccess;
+  auto ck = [&](hipError_t x) {
+    if (x != hipSuccess && e == hipSuccess) e = x;
+  };
+  if (ev0) ck(hipEventRecord(ev0, s));
+  if (B.groups.size() > 1) {
+    ck(hipEventRecord(h->fork_ev, s));
+    ck(hipStreamWaitEvent(h->side_stream, h->fork_ev, 0));
+  }
+  for (size_t gi = 0; gi < B.groups.size(); ++gi) {
+    const BatchCache::Group &g = B.groups[gi];
+    ck(launch_match_persistent(B.tM, B.tT + g.off, g.ntasks, B.tC + gi, g.win, g.dc, B.prec,
+                               g.nblocks, g.lds, gi == 0 ? s : h->side_stream, nullptr, nullptr));
+  }
+  if (B.groups.size() > 1) {
+    ck(hipEventRecord(h->join_ev, h->side_stream));
+    ck(hipStreamWaitEvent(s, h->join_ev, 0));
+  }
+  if (ev1) ck(hipEventRecord(ev1, s));
+  return e;
+}
+
 st_status stereo_match_batched(st_handle h, const st_pair *pairs, int n_pairs,
                                const st_params *params, void *stream) {
   ARG(pairs && n_pairs >= 1 && n_pairs <= 65535, "bad pair list");
@@ -974,6 +1048,7 @@ st_status stereo_match_batched(st_handle h, const st_pair *pairs, int n_pairs,
   BatchCache &B = h->batch;
   const int vforce = h->variant;
   bool same = B.exec && (int)B.pairs.size() == n_pairs && B.variant == vforce &&
+              B.tune_gen == h->tune_gen &&
               memcmp(&B.params, params, sizeof(st_params)) == 0 &&
               memcmp(B.pairs.data(), pairs, sizeof(st_pair) * n_pairs) == 0;
   if (same) {
@@ -984,8 +1059,19 @@ st_status stereo_match_batched(st_handle h, const st_pair *pairs, int n_pairs,
   // stream): its graph and the device tables it reads are replaced below
   HIPCK(hipDeviceSynchronize());
   drop_batch(B);
-  // one disparity chunk size for the whole launch, band height per pair
-  const int DC = 8;
+  // the matcher variant of each window size: forced, tuned for this batch
+  // layout, or the first in preference order
+  std::map<int, int> wvar;
+  for (int i = 0; i < n_pairs; ++i) {
+    const int w = pairs[i].win;
+    if (wvar.count(w)) continue;
+    int v = vforce >= 0 ? vforce : 0;
+    if (vforce < 0) {
+      auto it = h->tune.find(batch_key(pairs, n_pairs, w, prec, params->chessboard));
+      if (it != h->tune.end()) v = it->second;
+    }
+    wvar[w] = v;
+  }
   std::vector<MatchPair> M(n_pairs);
   std::vector<PrepPair> Pp(n_pairs);
   std::vector<PostPair> Q(n_pairs);
@@ -995,12 +1081,8 @@ st_status stereo_match_batched(st_handle h, const st_pair *pairs, int n_pairs,
   int maxH = 0, maxW = 0, maxCols = 0;
   for (int i = 0; i < n_pairs; ++i) {
     const st_pair &q = pairs[i];
-    int v = vforce >= 0 ? vforce : 0;
-    if (vforce < 0) {
-      auto it = h->tune.find("batched");
-      if (it != h->tune.end()) v = it->second;
-    }
-    make_geom(M[i], q.H, q.W, q.win, q.dmin, q.dmax, DC, variant_TY(v), variant_CG(v),
+    const int v = wvar[q.win];
+    make_geom(M[i], q.H, q.W, q.win, q.dmin, q.dmax, variant_DC(v), variant_TY(v), variant_CG(v),
               params->chessboard);
     Lo[i] = layout(M[i], prec, false);
     total = (total + 255) & ~(size_t)255;
@@ -1047,9 +1129,11 @@ st_status stereo_match_batched(st_handle h, const st_pair *pairs, int n_pairs,
                                             const std::pair<int, int4> &b) { return a.first > b.first; });
     BatchCache::Group gr;
     gr.win = w;
+    gr.variant = wvar[w];
+    gr.dc = variant_DC(gr.variant);
     gr.off = (int)sorted.size();
     gr.lds = wlds[w];
-    gr.nblocks = h->ncu * match_persistent_occupancy(w, prec, gr.lds);
+    gr.nblocks = h->ncu * match_persistent_occupancy(w, gr.dc, prec, gr.lds);
     // the queue's last round: its tasks (the cheapest, at the end) go in
     // two halves of their band's rows, so that the workgroups run out of
     // work at most half a task apart (tk.w = first row | end row << 16)
@@ -1096,10 +1180,12 @@ st_status stereo_match_batched(st_handle h, const st_pair *pairs, int n_pairs,
   hipError_t e = hipSuccess;
   auto ck = [&](hipError_t x) { if (x != hipSuccess && e == hipSuccess) e = x; };
   ck(launch_prep(Pp[0], at<PrepPair>(B.tables.p, tP), n_pairs, maxH, maxCols, maxW, prec, cs));
-  for (size_t gi = 0; gi < groups.size(); ++gi)
-    ck(launch_match_persistent(at<MatchPair>(B.tables.p, tM), at<int4>(B.tables.p, tT) + groups[gi].off,
-                               groups[gi].ntasks, at<int>(B.tables.p, tC) + gi, groups[gi].win, prec,
-                               groups[gi].nblocks, groups[gi].lds, cs, nullptr, nullptr));
+  B.tM = at<MatchPair>(B.tables.p, tM);
+  B.tT = at<int4>(B.tables.p, tT);
+  B.tC = at<int>(B.tables.p, tC);
+  B.groups = groups;
+  B.prec = prec;
+  ck(launch_groups(h, cs, nullptr, nullptr));
   PostLaunch L;
   L.one = Q[0];
   L.many = at<PostPair>(B.tables.p, tQ);
@@ -1129,16 +1215,36 @@ st_status stereo_match_batched(st_handle h, const st_pair *pairs, int n_pairs,
   }
   B.graph = g;
   B.exec = ex;
-  B.tM = at<MatchPair>(B.tables.p, tM);
-  B.tT = at<int4>(B.tables.p, tT);
-  B.tC = at<int>(B.tables.p, tC);
-  B.groups = groups;
-  B.prec = prec;
   B.pairs.assign(pairs, pairs + n_pairs);
   B.params = *params;
   B.variant = vforce;
+  B.tune_gen = h->tune_gen;
   HIPCK(hipGraphLaunch(B.exec, s));
   return ST_OK;
+}
+
+// Mean ms of each window size's persistent launch alone (reps launches each,
+// HIP events on s); the batch must have been built and run.
+static hipError_t time_each_group(st_handle h, int reps, hipStream_t s, std::vector<double> &ms) {
+  BatchCache &B = h->batch;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  ms.assign(B.groups.size(), 0.0);
+  for (size_t gi = 0; gi < B.groups.size() && e == hipSuccess; ++gi) {
+    const BatchCache::Group &g = B.groups[gi];
+    for (int r = 0; r < reps && e == hipSuccess; ++r) {
+      e = launch_match_persistent(B.tM, B.tT + g.off, g.ntasks, B.tC + gi, g.win, g.dc, B.prec,
+                                  g.nblocks, g.lds, s, e0, e1);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float t = 0.0f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+      ms[gi] += t / reps;
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  return e;
 }
 
 st_status stereo_time_matcher(st_handle h, const st_pair *pairs, int n_pairs,
@@ -1155,17 +1261,14 @@ st_status stereo_time_matcher(st_handle h, const st_pair *pairs, int n_pairs,
   HIPCK(hipEventCreate(&e1));
   double total = 0.0;
   hipError_t e = hipSuccess;
+  // the matcher phase as the graph runs it: every window size's launch,
+  // side by side, between two events on the stream
   for (int r = 0; r < reps && e == hipSuccess; ++r) {
-    // each counter reset is a one-lane kernel ahead of its timed launch
-    for (size_t gi = 0; gi < B.groups.size() && e == hipSuccess; ++gi) {
-      const BatchCache::Group &g = B.groups[gi];
-      e = launch_match_persistent(B.tM, B.tT + g.off, g.ntasks, B.tC + gi, g.win, B.prec,
-                                  g.nblocks, g.lds, s, e0, e1);
-      if (e == hipSuccess) e = hipEventSynchronize(e1);
-      float ms = 0.0f;
-      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-      total += ms;
-    }
+    e = launch_groups(h, s, e0, e1);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    total += ms;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -1175,6 +1278,54 @@ st_status stereo_time_matcher(st_handle h, const st_pair *pairs, int n_pairs,
   HIPCK(hipGraphLaunch(B.exec, s));
   *ms_out = (float)(total / reps);
   return ST_OK;
+}
+
+st_status st_autotune_batched(st_handle h, const st_pair *pairs, int n_pairs,
+                              const st_params *params, int reps, int *best_cfg, void *stream) {
+  ARG(h, "NULL handle");
+  ARG(reps >= 1 && reps <= 1000, "reps must be in [1, 1000]");
+  ARG(pairs && n_pairs >= 1, "bad pair list");
+  hipStream_t s = (hipStream_t)stream;
+  const int saved = h->variant;
+  std::map<int, std::pair<double, int>> best;  // window -> (ms, variant)
+  st_status rc = ST_OK;
+  for (int v = 0; v < kNumVariants && rc == ST_OK; ++v) {
+    h->variant = v;
+    rc = stereo_match_batched(h, pairs, n_pairs, params, stream);  // builds and runs it
+    if (rc) break;
+    std::vector<double> ms;
+    const hipError_t e = time_each_group(h, reps, s, ms);
+    if (e != hipSuccess) {
+      rc = fail(ST_EHIP, "timing the persistent launches failed: %s", hipGetErrorString(e));
+      break;
+    }
+    const BatchCache &B = h->batch;
+    for (size_t gi = 0; gi < B.groups.size(); ++gi) {
+      auto it = best.find(B.groups[gi].win);
+      if (it == best.end() || ms[gi] < it->second.first) best[B.groups[gi].win] = {ms[gi], v};
+    }
+  }
+  h->variant = saved;
+  if (rc) {
+    h->keys_dirty = true;
+    drop_batch(h->batch);
+    return rc;
+  }
+  const int prec = params->precision;
+  for (auto &kv : best) h->tune[batch_key(pairs, n_pairs, kv.first, prec, params->chessboard)] = kv.second.second;
+  ++h->tune_gen;
+  save_tune(h);
+  if (best_cfg)
+    for (int i = 0; i < n_pairs; ++i) best_cfg[i] = best[pairs[i].win].second;
+  // rebuild with the tuned variants; the outputs come from them
+  return stereo_match_batched(h, pairs, n_pairs, params, stream);
+}
+
+int st_batch_variant(st_handle h, int win) {
+  if (!h || !h->batch.exec) return -1;
+  for (const BatchCache::Group &g : h->batch.groups)
+    if (g.win == win) return g.variant;
+  return -1;
 }
 
 // ---------------------------------------------------------------- refinement
@@ -1270,7 +1421,7 @@ static int pick_variant(st_handle h, int H, int W, int win, int dmin, int dmax, 
   long long best_n = -1;
   for (int v = 0; v < kNumVariants; ++v) {
     MatchPair P;
-    make_geom(P, H, W, win, dmin, dmax, kDC, variant_TY(v), variant_CG(v), 0);
+    make_geom(P, H, W, win, dmin, dmax, variant_DC(v), variant_TY(v), variant_CG(v), 0);
     const long long n = (long long)P.nspan * P.nband * P.ncg;
     if (n >= 2LL * h->ncu) return v;
     if (n > best_n) {
@@ -1387,6 +1538,7 @@ extern "C" st_status st_autotune(st_handle h, int H, int W, int dmin, int dmax, 
   HIPCK(e);
   if (best < 0) return fail(ST_EUNSUPPORTED, "no matcher variant fits this shape");
   h->tune[tune_key(H, W, win, dmin, dmax, precision)] = best;
+  ++h->tune_gen;
   save_tune(h);
   if (best_cfg) *best_cfg = best;
   return ST_OK;

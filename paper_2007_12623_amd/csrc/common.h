@@ -176,13 +176,14 @@ __device__ __forceinline__ BlockPos block_pos() {
 hipError_t launch_prep(const PrepPair &one, const PrepPair *many, int npairs, int maxH,
                        int maxCols, int maxW, int prec, hipStream_t s);
 hipError_t launch_match(const MatchPair &P, int prec, hipStream_t s);
-// One persistent matcher launch over the tasks of one window size; ev0/ev1
-// (may be null) are recorded on s just before and after it.
+// One persistent matcher launch over the tasks of one window size and one
+// chunk width dc (4 or 8 disparities per lane); ev0/ev1 (may be null) are
+// recorded on s just before and after it.
 hipError_t launch_match_persistent(const MatchPair *pairs_dev, const int4 *tasks_dev, int ntasks,
-                                   int *counter_dev, int win, int prec, int nblocks, size_t lds,
-                                   hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
+                                   int *counter_dev, int win, int dc, int prec, int nblocks,
+                                   size_t lds, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
 // resident matcher workgroups per CU with `lds` bytes of key tiles each
-int match_persistent_occupancy(int win, int prec, size_t lds);
+int match_persistent_occupancy(int win, int dc, int prec, size_t lds);
 size_t match_lds_bytes(const MatchPair &P);  // key tiles of one workgroup
 hipError_t launch_window_stats_dense(const uint8_t *img, int H, int W, int pitch, int win,
                                      int chess, int32_t *S, int32_t *SS, float *inv, hipStream_t s);

@@ -24,30 +24,69 @@
 //    memory once per band: plain stores for the left keys when the group
 //    holds every chunk, one atomic max per right column otherwise.
 #include <algorithm>
+#include <type_traits>
 
 #include "common.h"
 
 namespace st {
 
 // ---------------------------------------------------------------- helpers
-// Neighbour-lane values through the LDS crossbar (ds_bpermute): the LDS pipe
-// is otherwise idle in this kernel, so the exchange costs no VALU issue slots.
-// Lane 0 reads lane 63 and back; both are halo lanes whose outputs are unused.
-__device__ __forceinline__ int from_left(int v) {   // lane i receives lane i-1
-  return __builtin_amdgcn_ds_bpermute(((int)__lane_id() - 1) << 2, v);
+// Neighbour-lane terms through DPP wave shifts, an operand modifier of the
+// add (or max) that consumes the value: no LDS round trip and no wait.
+// add_left(a, v) = a + v of lane i-1 (wave_shr:1), add_right(a, v) = a + v
+// of lane i+1 (wave_shl:1).  Lane 0 (left) and lane 63 (right) read 0;
+// both are halo lanes whose outputs are unused.  The instructions are
+// written out (the compiler folds only some of its DPP moves into the adds,
+// and keeps the rest as separate moves); a DPP read of a VGPR needs two
+// wait states after the VALU write of it, hence the s_nop 1 in front.
+__device__ __forceinline__ int add_left(int a, int v) {
+  int r;
+  asm("s_nop 1\n\tv_add_u32_dpp %0, %1, %2 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1"
+      : "=v"(r) : "v"(v), "v"(a));
+  return r;
 }
-__device__ __forceinline__ int from_right(int v) {  // lane i receives lane i+1
-  return __builtin_amdgcn_ds_bpermute(((int)__lane_id() + 1) << 2, v);
+__device__ __forceinline__ int add_right(int a, int v) {
+  int r;
+  asm("s_nop 1\n\tv_add_u32_dpp %0, %1, %2 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1"
+      : "=v"(r) : "v"(v), "v"(a));
+  return r;
 }
-__device__ __forceinline__ float from_left(float v) {
-  return __builtin_bit_cast(float, from_left(__builtin_bit_cast(int, v)));
+__device__ __forceinline__ float add_left(float a, float v) {
+  float r;
+  asm("s_nop 1\n\tv_add_f32_dpp %0, %1, %2 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1"
+      : "=v"(r) : "v"(v), "v"(a));
+  return r;
 }
-__device__ __forceinline__ float from_right(float v) {
-  return __builtin_bit_cast(float, from_right(__builtin_bit_cast(int, v)));
+__device__ __forceinline__ float add_right(float a, float v) {
+  float r;
+  asm("s_nop 1\n\tv_add_f32_dpp %0, %1, %2 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1"
+      : "=v"(r) : "v"(v), "v"(a));
+  return r;
 }
-// max that ignores a quiet-NaN operand (lowers to v_max_f32 / v_max3_f32)
+// max(a, v of lane i+1), ignoring quiet NaNs like kmax below.  Lane 63 has
+// no right neighbour and keeps a: without bound_ctrl the shift leaves that
+// lane unwritten, and the result is a's own register.  (A zero read there
+// would be the key of z + 3 = 0, a valid key, for columns no lane covers.)
+__device__ __forceinline__ float max_right(float a, float v) {
+  asm("s_nop 1\n\tv_max_f32_dpp %0, %1, %0 wave_shl:1 row_mask:0xf bank_mask:0xf"
+      : "+v"(a) : "v"(v));
+  return a;
+}
+// Maxima of keys that ignore quiet-NaN operands (the keys of invalid
+// candidates), as single v_max_f32 / v_max3_f32 instructions: written as
+// builtins the compiler first canonicalises every operand that comes out of
+// integer bit operations (one more v_max_f32 per key).  The keys are normal
+// floats or quiet NaNs, for which the instruction returns an operand's bits
+// unchanged.
 __device__ __forceinline__ float kmax(float a, float b) {
-  return __builtin_amdgcn_fmed3f(a, b, __builtin_inff());
+  float r;
+  asm("v_max_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+__device__ __forceinline__ float kmax3(float a, float b, float c) {
+  float r;
+  asm("v_max3_f32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+  return r;
 }
 __device__ __forceinline__ int s24(int v) { return __builtin_amdgcn_sbfe(v, 0, 24); }
 
@@ -86,24 +125,31 @@ template <> struct Img<P_BF16> {
   }
 };
 
-// Global key of a lane-local key: 0x80000000 | q << 8 | 255 - (d - dmin),
-// q = quantised z (the bits of z+2 above the index field, counted from 1.0),
-// so that ties prefer the smaller disparity.  With j = 15 - (b & 15) and
-// c = 0x88000000 + 240 - (d0 - dmin), the key is
-// ((m & ~15) << 4) + c + (b & 15), where m is b clamped to [1.0, KEY_NONE]:
-// the shift takes 1.0 to 0xF8000000, which c's 0x08000000 carries out.  A
-// lane without a valid candidate holds the start value KEY_START (a
-// negative float: below every z+2 as a float, above KEY_NONE as unsigned),
-// clamped to KEY_NONE, whose shifted part cancels c's high bits; its low
-// nibble 15 (as the index field of a valid key, at least 8) keeps the rest,
-// 255 - (d0 - dmin), non-negative.  So bit 31 marks a valid key, and a key
-// without it never wins a merge.
-constexpr uint32_t KEY_NONE = 0x47800000u, KEY_START = 0xBF80000Fu;
-__device__ __forceinline__ uint32_t key_base(int dd0) { return 0x88000000u + 240u - (uint32_t)dd0; }
+// Lane keys are the bits of z + 3 (in [2, 4] up to rounding: non-negative
+// floats compare like unsigned integers, and one binade keeps the
+// quantisation uniform) with the low nibble replaced by 15 - j, j the
+// disparity's index in its chunk.  The global key of a lane key b with
+// nibble m is 0x80000000 | q << 8 | 255 - (d - dmin), q the bits of z + 3
+// above the nibble, so that ties prefer the smaller disparity.  With
+// c = 0x80001000 + 240 - (d0 - dmin) it is ((b & ~15) << 4) + c + m,
+// computed as ((b << 4) + c) - 15 m: for b in [2, 4] the 32-bit shift gives
+// a signed value in [-4096, 0x08001000], so the key has bit 31 set and
+// keeps the order of z.  A lane without a valid candidate keeps the start
+// value KEY_START, a negative float (below every z + 3 and ignored by none
+// of the maxima) whose shifted bits are 0x80000000: its key, 0x1000 +
+// 240 - (d0 - dmin), has bit 31 clear.  So bit 31 marks a valid key, and a
+// key without it never wins a merge.
+constexpr float KEY_OFFSET = 3.0f;
+constexpr uint32_t KEY_START = 0xB8000000u;
+__device__ __forceinline__ uint32_t key_base(int dd0) { return 0x80001000u + 240u - (uint32_t)dd0; }
 __device__ __forceinline__ uint32_t global_key(float k, uint32_t c) {
   const uint32_t b = __builtin_bit_cast(uint32_t, k);
-  const uint32_t m = min(max(b, 0x3F800000u), KEY_NONE);  // v_med3_u32
-  return ((m & ~15u) << 4) + c + (b & 15u);
+  // three instructions; left to itself the compiler takes four (a separate
+  // shift, the product -15 m, then a three-way add)
+  uint32_t t, key;
+  asm("v_lshl_add_u32 %0, %1, 4, %2" : "=v"(t) : "v"(b), "v"(c));
+  asm("v_mad_i32_i24 %0, %1, -15, %2" : "=v"(key) : "v"(b & 15u), "v"(t));
+  return key;
 }
 __device__ __forceinline__ bool key_valid(uint32_t v) { return (int)v < 0; }
 
@@ -140,9 +186,13 @@ __device__ __forceinline__ void load_dw(uint32_t (&dst)[N], const GLOBAL char *b
 
 // Load N dwords starting `sh` bytes (0..3, uniform) after byte offset `off`
 // (a multiple of 4): one extra dword, then v_alignbyte per dword.
-template <int N>
+template <int N, bool SH>
 __device__ __forceinline__ void load_dw_shifted(uint32_t (&dst)[N], const GLOBAL char *base,
                                                 uint32_t off, int sh) {
+  if constexpr (!SH) {
+    load_dw(dst, base, off);
+    return;
+  }
   const GLOBAL uint32_t *q = (const GLOBAL uint32_t *)(base + off);
   uint32_t t[N + 1];
 #pragma unroll
@@ -157,7 +207,7 @@ __device__ __forceinline__ void load_dw_shifted(uint32_t (&dst)[N], const GLOBAL
 // takes colour `par`: its L planes hold only the pixels with (x + y) & 1 ==
 // par, so the window sums of a pixel of that colour run over exactly its
 // chessboard cells, and the pixels of the other colour produce no keys.
-template <int WIN, int DC, int PREC>
+template <int WIN, int DC, int PREC, bool SH>
 __device__ __forceinline__ void match_rows(const MatchPair &P, int y0, int y1, int xs, int d0,
                                            int par, int lane, const KeyTile &kt) {
   constexpr int H = WIN / 2;
@@ -173,7 +223,9 @@ __device__ __forceinline__ void match_rows(const MatchPair &P, int y0, int y1, i
   const int x0 = xs + lane * K;
   const int colL = x0 + P.padL;                 // multiple of 8
   const int colR = x0 - d0 - (DC - 1) + P.padR;
-  const int rsh = (RB * colR) & 3;              // byte misalignment (wave-uniform)
+  // byte misalignment of the right segments (wave-uniform; 0 unless SH, the
+  // shifted last chunk of some ranges)
+  const int rsh = SH ? (RB * colR) & 3 : 0;
   const bool halo = (lane == 0) || (lane == WV - 1);
   // planes are under 4 GiB: byte offsets of the lane's segments fit 32 bits
   const GLOBAL char *Lg = (const GLOBAL char *)P.Lp + par * P.lplane;
@@ -193,10 +245,10 @@ __device__ __forceinline__ void match_rows(const MatchPair &P, int y0, int y1, i
     const bool two = r + 1 <= y0 + H;
     uint32_t la[NLD], lb[NLD], ra[NRD], rb[NRD];
     load_dw(la, Lg, Lo + sL * r);
-    load_dw_shifted(ra, Rg, Ro + sR * r, rsh);
+    load_dw_shifted<NRD, SH>(ra, Rg, Ro + sR * r, rsh);
     if (two) {
       load_dw(lb, Lg, Lo + sL * (r + 1));
-      load_dw_shifted(rb, Rg, Ro + sR * (r + 1), rsh);
+      load_dw_shifted<NRD, SH>(rb, Rg, Ro + sR * (r + 1), rsh);
     } else {
 #pragma unroll
       for (int i = 0; i < NLD; ++i) lb[i] = 0;
@@ -225,8 +277,8 @@ __device__ __forceinline__ void match_rows(const MatchPair &P, int y0, int y1, i
       uint32_t la[NLD], lo[NLD], ra[NRD], ro[NRD];
       load_dw(la, Lg, Lo + sL * ra_);
       load_dw(lo, NLg, Lo + sL * rl_);
-      load_dw_shifted(ra, Rg, Ro + sR * ra_, rsh);
-      load_dw_shifted(ro, Rg, Ro + sR * rl_, rsh);
+      load_dw_shifted<NRD, SH>(ra, Rg, Ro + sR * ra_, rsh);
+      load_dw_shifted<NRD, SH>(ro, Rg, Ro + sR * rl_, rsh);
       uint32_t lp[K], rp[T];
 #pragma unroll
       for (int c = 0; c < K; ++c) lp[c] = __builtin_amdgcn_perm(lo[c / 2], la[c / 2], sel16(c & 1));
@@ -288,59 +340,77 @@ __device__ __forceinline__ void match_rows(const MatchPair &P, int y0, int y1, i
     //      columns (own columns through prefix sums; the h columns beyond each
     //      side as one partial sum from the neighbouring lane: suffix sums of
     //      the left lane, prefix sums of the right lane), then the keys.
-    //      Evaluation (i, j) uses right column t = i - j + DC - 1.
+    //      Evaluation (i, j) uses right column t = i - j + DC - 1.  The
+    //      disparities go in pairs (j, j + 1): key (i, j) and key (i, j + 1)
+    //      meet in the left maximum of pixel i, keys (i, j) and (i + 1, j + 1)
+    //      on diagonal t, so every merge takes two keys (v_max3).
+    const int nn = s24(n);
 #pragma unroll
-    for (int j = 0; j < DC; ++j) {
-      Acc Pf[K + 1];
-      Pf[0] = 0;
+    for (int j0 = 0; j0 < DC; j0 += 2) {
+      float kp[2][K];
 #pragma unroll
-      for (int c = 0; c < K; ++c) Pf[c + 1] = c == 0 ? V[j][0] : Pf[c] + V[j][c];
-      Acc Sf[H + 1];
-      Sf[0] = 0;
+      for (int jj = 0; jj < 2; ++jj) {
+        const int j = j0 + jj;
+        Acc Pf[K + 1];
+        Pf[0] = 0;
 #pragma unroll
-      for (int k = 1; k <= H; ++k) Sf[k] = k == 1 ? V[j][K - 1] : Sf[k - 1] + V[j][K - k];
-      Acc hl[H + 1], hr[H + 1];
+        for (int c = 0; c < K; ++c) Pf[c + 1] = c == 0 ? V[j][0] : Pf[c] + V[j][c];
+        Acc Sf[H + 1];
+        Sf[0] = 0;
 #pragma unroll
-      for (int k = 1; k <= H; ++k) {
-        hl[k] = from_left(Sf[k]);
-        hr[k] = from_right(Pf[k]);
+        for (int k = 1; k <= H; ++k) Sf[k] = k == 1 ? V[j][K - 1] : Sf[k - 1] + V[j][K - k];
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+          const int lo = i - H, hi = i + H + 1;   // own columns [max(lo,0), min(hi,K))
+          Acc Sij = (lo > 0) ? Pf[hi < K ? hi : K] - Pf[lo] : Pf[hi < K ? hi : K];
+          if (lo < 0) Sij = add_left(Sij, Sf[-lo]);    // suffix sums of the left lane
+          if (hi > K) Sij = add_right(Sij, Pf[hi - K]);  // prefix sums of the right lane
+          const int t = i - j + DC - 1;
+          int num;
+          if constexpr (PREC == P_I16) {
+            num = s24(nsl[i]) * s24(sr[t]) + Sij;
+          } else {
+            // Sij is an exact integer below 2^23 in fp32
+            num = s24((int)Sij) * nn + s24(nsl[i]) * s24(sr[t]);
+          }
+          const float zl = (float)num * ir[t];
+          float zq;
+          if constexpr (PREC == P_I16) {
+            zq = __builtin_fmaf(zl, il[i], KEY_OFFSET);
+          } else if constexpr (PREC == P_F16) {
+            // the cost slice: z rounded to fp16 (v_fma_mixlo_f16), widened
+            // and offset in one v_fma_mix_f32
+            const _Float16 zh = (_Float16)(zl * il[i]);
+            asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel_hi:[1,0,0]" : "=v"(zq) : "v"(zh), "v"(KEY_OFFSET));
+          } else {
+            // the cost slice: z rounded to bf16 (to nearest even) into the
+            // high half of a dword whose low half is 0, which is then that
+            // value as an fp32 (one v_cvt_pk_bf16_f32)
+            float zb;
+            asm("v_cvt_pk_bf16_f32 %0, 0, %1" : "=v"(zb) : "v"(zl * il[i]));
+            zq = zb + KEY_OFFSET;
+          }
+          kp[jj][i] = __builtin_bit_cast(
+              float, (__builtin_bit_cast(uint32_t, zq) & ~15u) | (uint32_t)(15 - j));
+        }
       }
 #pragma unroll
-      for (int i = 0; i < K; ++i) {
-        const int lo = i - H, hi = i + H + 1;   // own columns [max(lo,0), min(hi,K))
-        Acc Sij = (lo > 0) ? Pf[hi < K ? hi : K] - Pf[lo] : Pf[hi < K ? hi : K];
-        if (lo < 0) Sij = Sij + hl[-lo];
-        if (hi > K) Sij = Sij + hr[hi - K];
-        const int t = i - j + DC - 1;
-        int num;
-        if constexpr (PREC == P_I16) {
-          num = s24(nsl[i]) * s24(sr[t]) + Sij;
-        } else {
-          num = s24((int)Sij) * n + s24(nsl[i]) * s24(sr[t]);
-        }
-        const float zl = (float)num * ir[t];
-        float zq;
-        if constexpr (PREC == P_I16) {
-          zq = __builtin_fmaf(zl, il[i], 2.0f);
-        } else if constexpr (PREC == P_F16) {
-          zq = (float)(_Float16)(zl * il[i]) + 2.0f;
-        } else {
-          uint32_t u = __builtin_bit_cast(uint32_t, zl * il[i]);
-          u = (u + 0x7FFFu + ((u >> 16) & 1u)) & 0xFFFF0000u;
-          zq = __builtin_bit_cast(float, u) + 2.0f;
-        }
-        const float key = __builtin_bit_cast(
-            float, (__builtin_bit_cast(uint32_t, zq) & ~15u) | (uint32_t)(15 - j));
-        bestL[i] = kmax(bestL[i], key);
-        Pd[t] = kmax(Pd[t], key);
+      for (int i = 0; i < K; ++i) bestL[i] = kmax3(bestL[i], kp[0][i], kp[1][i]);
+      // diagonal t = i - j0 + DC - 1 holds (i, j0) and (i + 1, j0 + 1)
+#pragma unroll
+      for (int i = 0; i < K - 1; ++i) {
+        const int t = i - j0 + DC - 1;
+        Pd[t] = kmax3(Pd[t], kp[0][i], kp[1][i + 1]);
       }
+      Pd[K - 1 - j0 + DC - 1] = kmax(Pd[K - 1 - j0 + DC - 1], kp[0][K - 1]);
+      Pd[DC - 2 - j0] = kmax(Pd[DC - 2 - j0], kp[1][0]);
     }
 
     // ---- right reference: fold diagonals of higher lanes into this lane's
     //      home diagonals t in [DC-1, T).  Increasing t order chains the
     //      contributions of several lanes in one pass.
 #pragma unroll
-    for (int t = 0; t < DC - 1; ++t) Pd[t + K] = kmax(Pd[t + K], from_right(Pd[t]));
+    for (int t = 0; t < DC - 1; ++t) Pd[t + K] = max_right(Pd[t + K], Pd[t]);
 
     // ---- emit into the tiles: left reference per pixel, right reference
     //      per home column.  Branch-free: a lane without a valid candidate
@@ -410,8 +480,14 @@ __device__ __forceinline__ void wg_task(const MatchPair &P, int g, int cg, int r
     const int u = it % units, sb = it / units;
     const int c = cf + u % nc, par = u / nc;
     const int ya = y0 + sb * TYs, yb = min(ya + TYs, y1);
-    if (ya < yb)
-      match_rows<WIN, DC, PREC>(P, ya, yb, xs, P.dmin + min(c * DC, D - DC), par, lane, kt);
+    if (ya < yb) {
+      const int d0 = P.dmin + min(c * DC, D - DC);
+      // right segments start on a dword unless the chunk was shifted
+      if (((Img<PREC>::RB * (xs - d0 - (DC - 1) + P.padR)) & 3) != 0)
+        match_rows<WIN, DC, PREC, true>(P, ya, yb, xs, d0, par, lane, kt);
+      else
+        match_rows<WIN, DC, PREC, false>(P, ya, yb, xs, d0, par, lane, kt);
+    }
   }
   __syncthreads();
 
@@ -496,95 +572,73 @@ static hipError_t launch_match_t(const MatchPair &P, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int DC, int PREC>
-static hipError_t launch_match_w(const MatchPair &P, hipStream_t s) {
-  switch (P.win) {
-    case 3: return launch_match_t<3, DC, PREC>(P, s);
-    case 5: return launch_match_t<5, DC, PREC>(P, s);
-    case 7: return launch_match_t<7, DC, PREC>(P, s);
-    case 9: return launch_match_t<9, DC, PREC>(P, s);
-    case 11: return launch_match_t<11, DC, PREC>(P, s);
-    case 13: return launch_match_t<13, DC, PREC>(P, s);
-    case 15: return launch_match_t<15, DC, PREC>(P, s);
+// Calls f(window, disparities per thread, precision) with the three as
+// compile-time constants: windows 3..15 (odd), chunks of 4 or 8
+// disparities, the three image precisions.
+template <class F>
+static auto with_config(int win, int dc, int prec, F &&f) {
+  auto by_prec = [&](auto W, auto D) {
+    if (prec == P_I16) return f(W, D, std::integral_constant<int, P_I16>{});
+    if (prec == P_F16) return f(W, D, std::integral_constant<int, P_F16>{});
+    return f(W, D, std::integral_constant<int, P_BF16>{});
+  };
+  auto by_dc = [&](auto W) {
+    if (dc == 4) return by_prec(W, std::integral_constant<int, 4>{});
+    return by_prec(W, std::integral_constant<int, 8>{});
+  };
+  switch (win) {
+    case 3: return by_dc(std::integral_constant<int, 3>{});
+    case 5: return by_dc(std::integral_constant<int, 5>{});
+    case 7: return by_dc(std::integral_constant<int, 7>{});
+    case 9: return by_dc(std::integral_constant<int, 9>{});
+    case 11: return by_dc(std::integral_constant<int, 11>{});
+    case 13: return by_dc(std::integral_constant<int, 13>{});
+    default: return by_dc(std::integral_constant<int, 15>{});
   }
-  return hipErrorInvalidValue;
 }
+
+static bool config_ok(int win, int dc) { return win >= 3 && win <= 15 && (win & 1) && (dc == 4 || dc == 8); }
 
 hipError_t launch_match(const MatchPair &P, int prec, hipStream_t s) {
-  if (P.DC != 8) return hipErrorInvalidValue;
-  if (prec == P_I16) return launch_match_w<8, P_I16>(P, s);
-  if (prec == P_F16) return launch_match_w<8, P_F16>(P, s);
-  return launch_match_w<8, P_BF16>(P, s);
-}
-
-template <int WIN, int PREC>
-static hipError_t launch_pwp(const MatchPair *pairs_dev, const int4 *tasks_dev, int ntasks,
-                             int *counter, int nblocks, size_t lds, hipStream_t s) {
-  hipError_t e = allow_lds(match_persistent_kernel<WIN, 8, PREC>, lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((match_persistent_kernel<WIN, 8, PREC>), dim3(nblocks), dim3(NWAVE * WV), lds, s,
-                     pairs_dev, tasks_dev, ntasks, counter);
-  return hipGetLastError();
-}
-
-template <int WIN>
-static hipError_t launch_pw(const MatchPair *pairs_dev, const int4 *tasks_dev, int ntasks,
-                            int *counter, int prec, int nblocks, size_t lds, hipStream_t s) {
-  if (prec == P_I16) return launch_pwp<WIN, P_I16>(pairs_dev, tasks_dev, ntasks, counter, nblocks, lds, s);
-  if (prec == P_F16) return launch_pwp<WIN, P_F16>(pairs_dev, tasks_dev, ntasks, counter, nblocks, lds, s);
-  return launch_pwp<WIN, P_BF16>(pairs_dev, tasks_dev, ntasks, counter, nblocks, lds, s);
+  if (!config_ok(P.win, P.DC)) return hipErrorInvalidValue;
+  return with_config(P.win, P.DC, prec, [&](auto W, auto D, auto Pr) {
+    return launch_match_t<decltype(W)::value, decltype(D)::value, decltype(Pr)::value>(P, s);
+  });
 }
 
 // One persistent launch over the tasks of one window size.
 hipError_t launch_match_persistent(const MatchPair *pairs_dev, const int4 *tasks_dev, int ntasks,
-                                   int *counter_dev, int win, int prec, int nblocks, size_t lds,
-                                   hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+                                   int *counter_dev, int win, int dc, int prec, int nblocks,
+                                   size_t lds, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+  if (!config_ok(win, dc)) return hipErrorInvalidValue;
   hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, counter_dev);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (ev0) (void)hipEventRecord(ev0, s);
-  switch (win) {
-    case 3: e = launch_pw<3>(pairs_dev, tasks_dev, ntasks, counter_dev, prec, nblocks, lds, s); break;
-    case 5: e = launch_pw<5>(pairs_dev, tasks_dev, ntasks, counter_dev, prec, nblocks, lds, s); break;
-    case 7: e = launch_pw<7>(pairs_dev, tasks_dev, ntasks, counter_dev, prec, nblocks, lds, s); break;
-    case 9: e = launch_pw<9>(pairs_dev, tasks_dev, ntasks, counter_dev, prec, nblocks, lds, s); break;
-    case 11: e = launch_pw<11>(pairs_dev, tasks_dev, ntasks, counter_dev, prec, nblocks, lds, s); break;
-    case 13: e = launch_pw<13>(pairs_dev, tasks_dev, ntasks, counter_dev, prec, nblocks, lds, s); break;
-    default: e = launch_pw<15>(pairs_dev, tasks_dev, ntasks, counter_dev, prec, nblocks, lds, s); break;
-  }
+  e = with_config(win, dc, prec, [&](auto W, auto D, auto Pr) {
+    auto *k = match_persistent_kernel<decltype(W)::value, decltype(D)::value, decltype(Pr)::value>;
+    hipError_t x = allow_lds(k, lds);
+    if (x != hipSuccess) return x;
+    hipLaunchKernelGGL(k, dim3(nblocks), dim3(NWAVE * WV), lds, s, pairs_dev, tasks_dev, ntasks,
+                       counter_dev);
+    return hipGetLastError();
+  });
   if (ev1) (void)hipEventRecord(ev1, s);
   return e;
 }
 
-template <int WIN, int PREC>
-static int occ_wp(size_t lds) {
-  int n = 0;
-  if (allow_lds(match_persistent_kernel<WIN, 8, PREC>, lds) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, match_persistent_kernel<WIN, 8, PREC>,
-                                                   NWAVE * WV, lds) != hipSuccess) {
-    (void)hipGetLastError();
-    return 1;
-  }
-  return std::max(1, n);
-}
-
-template <int WIN>
-static int occ_w(int prec, size_t lds) {
-  if (prec == P_I16) return occ_wp<WIN, P_I16>(lds);
-  if (prec == P_F16) return occ_wp<WIN, P_F16>(lds);
-  return occ_wp<WIN, P_BF16>(lds);
-}
-
-int match_persistent_occupancy(int win, int prec, size_t lds) {
-  switch (win) {
-    case 3: return occ_w<3>(prec, lds);
-    case 5: return occ_w<5>(prec, lds);
-    case 7: return occ_w<7>(prec, lds);
-    case 9: return occ_w<9>(prec, lds);
-    case 11: return occ_w<11>(prec, lds);
-    case 13: return occ_w<13>(prec, lds);
-    default: return occ_w<15>(prec, lds);
-  }
+int match_persistent_occupancy(int win, int dc, int prec, size_t lds) {
+  if (!config_ok(win, dc)) return 1;
+  return with_config(win, dc, prec, [&](auto W, auto D, auto Pr) {
+    auto *k = match_persistent_kernel<decltype(W)::value, decltype(D)::value, decltype(Pr)::value>;
+    int n = 0;
+    if (allow_lds(k, lds) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, NWAVE * WV, lds) != hipSuccess) {
+      (void)hipGetLastError();
+      return 1;
+    }
+    return std::max(1, n);
+  });
 }
 
 }  // namespace st
