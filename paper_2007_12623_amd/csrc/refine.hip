@@ -15,164 +15,198 @@
 
 namespace st {
 
-enum {
-  RF_RW = 0, RF_SLOPE, RF_V, RF_W, RF_WW, RF_LW, RF_L, RF_LL,   // inputs of the box sums
-  RF_BV, RF_BW, RF_BWW, RF_BLW, RF_BL, RF_BLL,                  // their box sums
-  RF_TMP, RF_A1, RF_A2, RF_A3, RF_A4, RF_B1, RF_B2, RF_B3, RF_B4,
-  RF_NPLANES
-};
+// Per-pixel planes kept between the passes: the backward fields of Omega's
+// pixels (0 elsewhere).
+enum { RF_A1 = 0, RF_A2, RF_A3, RF_A4, RF_NPLANES };
 
-__global__ void refine_warp_kernel(RefineArgs A) {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  const int y = blockIdx.y;
-  if (x >= A.W) return;
-  const size_t N = (size_t)A.W * A.H, k = (size_t)y * A.W + x;
-  const double dd = (double)A.d[k];
+// Both passes are fused box-sum kernels: a block of RT_T threads owns RT_T
+// consecutive columns (RT_T - 2h of them outputs) and RT_SY rows.  Each
+// thread keeps the vertical window sums of its column in registers (the
+// entering row added, the leaving row removed, every input computed where
+// it is needed: R_w from d and the right image, or a plane read); per row
+// the block stores them in LDS and every output thread adds the 2h + 1 of
+// its window.  Two LDS buffers alternate between rows, so one barrier per
+// row orders the stores of a row after the reads of the row before.
+constexpr int RT_T = 256, RT_SY = 32, RT_HMAX = 7;
+
+// R_w(x, y): the right row interpolated at u = x - d(x, y) clamped to
+// [0, W-1] (segment [floor(u), floor(u) + 1]: at an integer u the segment
+// to the right), and its slope dR_w/du (0 where u is clamped).
+__device__ __forceinline__ void warp_px(const RefineArgs &A, int x, int y, double &rw,
+                                        double &slope) {
+  const double dd = (double)A.d[(size_t)y * A.W + x];
   const double u0 = (double)x - dd;
-  double u = u0 < 0.0 ? 0.0 : (u0 > A.W - 1.0 ? A.W - 1.0 : u0);
+  const double u = u0 < 0.0 ? 0.0 : (u0 > A.W - 1.0 ? A.W - 1.0 : u0);
   int i0 = (int)floor(u);
   if (i0 > A.W - 1) i0 = A.W - 1;
   const int i1 = i0 + 1 < A.W ? i0 + 1 : A.W - 1;
   const double t = u - i0;
   const uint8_t *rr = A.R + (size_t)y * A.pitch;
   const double r0 = rr[i0], r1 = rr[i1];
-  const double rw = r0 * (1.0 - t) + r1 * t;
-  const double l = A.L[(size_t)y * A.pitch + x];
-  A.f[RF_RW * N + k] = rw;
-  A.f[RF_SLOPE * N + k] = (u0 >= 0.0 && u0 <= A.W - 1.0) ? (r1 - r0) : 0.0;
-  A.f[RF_V * N + k] = A.mask[k] ? 1.0 : 0.0;
-  A.f[RF_W * N + k] = rw;
-  A.f[RF_WW * N + k] = rw * rw;
-  A.f[RF_LW * N + k] = l * rw;
-  A.f[RF_L * N + k] = l;
-  A.f[RF_LL * N + k] = l * l;
+  rw = r0 * (1.0 - t) + r1 * t;
+  slope = (u0 >= 0.0 && u0 <= A.W - 1.0) ? (r1 - r0) : 0.0;
 }
 
-__global__ void rbox_v_kernel(const double *__restrict__ in, double *out, int H, int W, int R,
-                              int seg) {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  const int y0 = blockIdx.y * seg;
-  if (x >= W || y0 >= H) return;
-  double s = 0.0;
-  for (int v = y0 - R; v <= y0 + R; ++v)
-    if (v >= 0 && v < H) s += in[(size_t)v * W + x];
-  const int y1 = min(y0 + seg, H);
-  for (int y = y0; y < y1; ++y) {
-    out[(size_t)y * W + x] = s;
-    const int a = y + R + 1, b = y - R;
-    if (a < H) s += in[(size_t)a * W + x];
-    if (b >= 0) s -= in[(size_t)b * W + x];
-  }
-}
+// Anisotropic TV terms of pixel k: lambda |d(q+e) - d(q)| over the right and
+// down neighbours (energy), and the subgradient with sign(0) = 0.
+__device__ __forceinline__ double sgn(double v) { return v > 0.0 ? 1.0 : (v < 0.0 ? -1.0 : 0.0); }
 
-__global__ void rbox_h_kernel(const double *__restrict__ in, double *out, int H, int W, int R,
-                              int seg) {
-  const int y = blockIdx.x * blockDim.x + threadIdx.x;
-  const int x0 = blockIdx.y * seg;
-  if (y >= H || x0 >= W) return;
-  const double *row = in + (size_t)y * W;
-  double s = 0.0;
-  for (int u = x0 - R; u <= x0 + R; ++u)
-    if (u >= 0 && u < W) s += row[u];
-  const int x1 = min(x0 + seg, W);
-  for (int x = x0; x < x1; ++x) {
-    out[(size_t)y * W + x] = s;
-    const int a = x + R + 1, b = x - R;
-    if (a < W) s += row[a];
-    if (b >= 0) s -= row[b];
-  }
-}
-
-// Omega, Z, the energy terms and the backward fields A1..A4.
-__global__ __launch_bounds__(256) void refine_z_kernel(RefineArgs A) {
-  __shared__ double red[256];
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  const int y = blockIdx.y;
-  const size_t N = (size_t)A.W * A.H;
-  double e = 0.0;
-  if (x < A.W) {
-    const size_t k = (size_t)y * A.W + x;
-    const int h = A.win / 2;
-    const double n = (double)A.win * A.win;
-    const double *f = A.f;
-    double z = __builtin_nan(""), a1 = 0, a2 = 0, a3 = 0, a4 = 0;
-    const bool inside = x >= h && x <= A.W - 1 - h && y >= h && y <= A.H - 1 - h;
-    if (A.mask[k] && inside && f[RF_BV * N + k] > n - 0.5) {
-      const double sl = f[RF_BL * N + k], sll = f[RF_BLL * N + k];
-      const double sw = f[RF_BW * N + k], sww = f[RF_BWW * N + k], slw = f[RF_BLW * N + k];
-      const double saa = sll - sl * sl / n;
-      if (saa > 0.0 && n * sll - sl * sl > 0.5) {
-        const double sbb = sww - sw * sw / n;
-        const double sab = slw - sl * sw / n;
-        z = 0.0;
-        if (sbb > 1e-6 * n) {  // numerically constant R_w window: Z = 0
-          const double al = 1.0 / sqrt(saa * sbb);
-          const double be = 1.0 / sbb;
-          z = sab * al;
-          a1 = al;
-          a2 = (sl / n) * al;
-          a3 = z * be;
-          a4 = z * (sw / n) * be;
-        }
-        e += 1.0 - z;
-      }
-    }
-    if (A.Z) A.Z[k] = (float)z;
-    A.f[RF_A1 * N + k] = a1;
-    A.f[RF_A2 * N + k] = a2;
-    A.f[RF_A3 * N + k] = a3;
-    A.f[RF_A4 * N + k] = a4;
-    if (A.mask[k]) {
-      const double dk = A.d[k];
-      if (x + 1 < A.W && A.mask[k + 1]) e += A.lambda * fabs((double)A.d[k + 1] - dk);
-      if (y + 1 < A.H && A.mask[k + A.W]) e += A.lambda * fabs((double)A.d[k + A.W] - dk);
-    }
-  }
-  red[threadIdx.x] = e;
+// Block sum of one double per thread in a fixed order (deterministic).
+__device__ __forceinline__ double block_sum(double v, double *red) {
+  const int t = threadIdx.x;
+  red[t] = v;
   __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
-    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+  for (int off = RT_T / 2; off > 0; off >>= 1) {
+    if (t < off) red[t] += red[t + off];
     __syncthreads();
   }
-  if (threadIdx.x == 0) A.partial[blockIdx.y * gridDim.x + blockIdx.x] = red[0];
+  return red[0];
+}
+
+// Forward: the six window sums (valid count, R_w, R_w^2, L R_w, L, L^2),
+// Omega, Z, the energy of the block's pixels (to one partial per block)
+// and the backward fields a1..a4 = alpha, mu_L alpha, Z beta, Z mu_w beta.
+__global__ __launch_bounds__(RT_T) void refine_fwd_kernel(RefineArgs A) {
+  __shared__ double sv[2][6][RT_T];
+  const int h = A.win / 2, W = A.W, H = A.H, nout = RT_T - 2 * h;
+  const int xo = blockIdx.x * nout, y0 = blockIdx.y * RT_SY;
+  const int t = threadIdx.x, c = xo - h + t;
+  const bool cin = c >= 0 && c < W;
+  const size_t N = (size_t)W * H;
+  const double n = (double)A.win * A.win;
+  double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  auto add_row = [&](int r, double sg) {
+    if (!cin || r < 0 || r >= H) return;
+    double rw, sl;
+    warp_px(A, c, r, rw, sl);
+    const double l = A.L[(size_t)r * A.pitch + c];
+    acc[0] += A.mask[(size_t)r * W + c] ? sg : 0.0;
+    acc[1] += sg * rw;
+    acc[2] += sg * (rw * rw);
+    acc[3] += sg * (l * rw);
+    acc[4] += sg * l;
+    acc[5] += sg * (l * l);
+  };
+  for (int r = y0 - h; r < y0 + h; ++r) add_row(r, 1.0);
+  const int y1 = min(y0 + RT_SY, H);
+  const bool out_col = t >= h && t < RT_T - h && c < W;
+  double e = 0.0;
+  for (int y = y0; y < y1; ++y) {  // the same rows for every thread
+    add_row(y + h, 1.0);
+    const int b = y & 1;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) sv[b][q][t] = acc[q];
+    add_row(y - h, -1.0);
+    __syncthreads();
+    if (out_col) {
+      double sb[6];
+#pragma unroll
+      for (int q = 0; q < 6; ++q) {
+        double v = 0.0;
+        for (int j = -h; j <= h; ++j) v += sv[b][q][t + j];
+        sb[q] = v;
+      }
+      const size_t k = (size_t)y * W + c;
+      double z = __builtin_nan(""), a1 = 0, a2 = 0, a3 = 0, a4 = 0;
+      const bool inside = c >= h && c <= W - 1 - h && y >= h && y <= H - 1 - h;
+      if (A.mask[k] && inside && sb[0] > n - 0.5) {
+        const double sw = sb[1], sww = sb[2], slw = sb[3], sl = sb[4], sll = sb[5];
+        const double saa = sll - sl * sl / n;
+        if (saa > 0.0 && n * sll - sl * sl > 0.5) {
+          const double sbb = sww - sw * sw / n;
+          const double sab = slw - sl * sw / n;
+          z = 0.0;
+          if (sbb > 1e-6 * n) {  // numerically constant R_w window: Z = 0
+            const double al = 1.0 / sqrt(saa * sbb);
+            const double be = 1.0 / sbb;
+            z = sab * al;
+            a1 = al;
+            a2 = (sl / n) * al;
+            a3 = z * be;
+            a4 = z * (sw / n) * be;
+          }
+          e += 1.0 - z;
+        }
+      }
+      if (A.Z) A.Z[k] = (float)z;
+      A.f[RF_A1 * N + k] = a1;
+      A.f[RF_A2 * N + k] = a2;
+      A.f[RF_A3 * N + k] = a3;
+      A.f[RF_A4 * N + k] = a4;
+      if (A.mask[k]) {
+        const double dk = A.d[k];
+        if (c + 1 < W && A.mask[k + 1]) e += A.lambda * fabs((double)A.d[k + 1] - dk);
+        if (y + 1 < H && A.mask[k + W]) e += A.lambda * fabs((double)A.d[k + W] - dk);
+      }
+    }
+  }
+  __syncthreads();  // the last row's window reads are done before sv is reused
+  const double tot = block_sum(e, &sv[0][0][0]);
+  if (t == 0) A.partial[blockIdx.y * gridDim.x + blockIdx.x] = tot;
 }
 
 // Fixed-order sum of the block partials (deterministic).
-__global__ __launch_bounds__(256) void refine_sum_kernel(const double *partial, int n, double *E) {
-  __shared__ double red[256];
+__global__ __launch_bounds__(RT_T) void refine_sum_kernel(const double *partial, int n, double *E) {
+  __shared__ double red[RT_T];
   double s = 0.0;
-  for (int i = threadIdx.x; i < n; i += 256) s += partial[i];
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
-    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) *E = red[0];
+  for (int i = threadIdx.x; i < n; i += RT_T) s += partial[i];
+  const double tot = block_sum(s, red);
+  if (threadIdx.x == 0) *E = tot;
 }
 
-__device__ __forceinline__ double sgn(double v) { return v > 0.0 ? 1.0 : (v < 0.0 ? -1.0 : 0.0); }
-
-__global__ void refine_grad_kernel(RefineArgs A) {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  const int y = blockIdx.y;
-  if (x >= A.W) return;
-  const size_t N = (size_t)A.W * A.H, k = (size_t)y * A.W + x;
-  const double *f = A.f;
-  const double l = f[RF_L * N + k], rw = f[RF_RW * N + k];
-  const double gR = -(l * f[RF_B1 * N + k] - f[RF_B2 * N + k] - rw * f[RF_B3 * N + k] +
-                      f[RF_B4 * N + k]);
-  double g = gR * (-f[RF_SLOPE * N + k]);
-  if (A.mask[k]) {
-    const double dk = A.d[k];
-    double tv = 0.0;
-    if (x + 1 < A.W && A.mask[k + 1]) tv -= sgn((double)A.d[k + 1] - dk);
-    if (y + 1 < A.H && A.mask[k + A.W]) tv -= sgn((double)A.d[k + A.W] - dk);
-    if (x > 0 && A.mask[k - 1]) tv += sgn(dk - (double)A.d[k - 1]);
-    if (y > 0 && A.mask[k - A.W]) tv += sgn(dk - (double)A.d[k - A.W]);
-    g += A.lambda * tv;
+// Backward: B(a1..a4), the sums of the fields over the windows that contain
+// q, then dE/dd(q) = dE/dR_w(q) (-slope(q)) + lambda dTV/dd(q) with
+// dE/dR_w(q) = -[L(q) B(a1) - B(a2) - R_w(q) B(a3) + B(a4)].
+__global__ __launch_bounds__(RT_T) void refine_bwd_kernel(RefineArgs A) {
+  __shared__ double sv[2][4][RT_T];
+  const int h = A.win / 2, W = A.W, H = A.H, nout = RT_T - 2 * h;
+  const int xo = blockIdx.x * nout, y0 = blockIdx.y * RT_SY;
+  const int t = threadIdx.x, c = xo - h + t;
+  const bool cin = c >= 0 && c < W;
+  const size_t N = (size_t)W * H;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  auto add_row = [&](int r, double sg) {
+    if (!cin || r < 0 || r >= H) return;
+    const size_t k = (size_t)r * W + c;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] += sg * A.f[q * N + k];
+  };
+  for (int r = y0 - h; r < y0 + h; ++r) add_row(r, 1.0);
+  const int y1 = min(y0 + RT_SY, H);
+  const bool out_col = t >= h && t < RT_T - h && c < W;
+  for (int y = y0; y < y1; ++y) {
+    add_row(y + h, 1.0);
+    const int b = y & 1;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) sv[b][q][t] = acc[q];
+    add_row(y - h, -1.0);
+    __syncthreads();
+    if (out_col) {
+      double bs[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        double v = 0.0;
+        for (int j = -h; j <= h; ++j) v += sv[b][q][t + j];
+        bs[q] = v;
+      }
+      const size_t k = (size_t)y * W + c;
+      double rw, slope;
+      warp_px(A, c, y, rw, slope);
+      const double l = A.L[(size_t)y * A.pitch + c];
+      const double gR = -(l * bs[0] - bs[1] - rw * bs[2] + bs[3]);
+      double g = gR * (-slope);
+      if (A.mask[k]) {
+        const double dk = A.d[k];
+        double tv = 0.0;
+        if (c + 1 < W && A.mask[k + 1]) tv -= sgn((double)A.d[k + 1] - dk);
+        if (y + 1 < H && A.mask[k + W]) tv -= sgn((double)A.d[k + W] - dk);
+        if (c > 0 && A.mask[k - 1]) tv += sgn(dk - (double)A.d[k - 1]);
+        if (y > 0 && A.mask[k - W]) tv += sgn(dk - (double)A.d[k - W]);
+        g += A.lambda * tv;
+      }
+      A.grad[k] = (float)g;
+    }
   }
-  A.grad[k] = (float)g;
 }
 
 __global__ void refine_step_kernel(float *d, const float *g, const uint8_t *mask, int N, float tau,
@@ -184,36 +218,25 @@ __global__ void refine_step_kernel(float *d, const float *g, const uint8_t *mask
   d[k] -= s;
 }
 
-static void rbox(const RefineArgs &A, int in, int out, hipStream_t s) {
-  const size_t N = (size_t)A.W * A.H;
-  const int R = A.win / 2, seg = 32;
-  hipLaunchKernelGGL(rbox_v_kernel, dim3(ceil_div(A.W, 64), ceil_div(A.H, seg)), dim3(64), 0, s,
-                     A.f + in * N, A.f + RF_TMP * N, A.H, A.W, R, seg);
-  hipLaunchKernelGGL(rbox_h_kernel, dim3(ceil_div(A.H, 64), ceil_div(A.W, seg)), dim3(64), 0, s,
-                     A.f + RF_TMP * N, A.f + out * N, A.H, A.W, R, seg);
+static dim3 rgrid(const RefineArgs &A) {
+  return dim3(ceil_div(A.W, RT_T - 2 * (A.win / 2)), ceil_div(A.H, RT_SY));
 }
 
 int refine_planes() { return RF_NPLANES; }
-int refine_partials(int H, int W) { return ceil_div(W, 256) * H; }
-
-static void refine_common(const RefineArgs &A, hipStream_t s) {
-  const dim3 g(ceil_div(A.W, 256), A.H);
-  hipLaunchKernelGGL(refine_warp_kernel, g, dim3(256), 0, s, A);
-  for (int p = 0; p < 6; ++p) rbox(A, RF_V + p, RF_BV + p, s);
-  hipLaunchKernelGGL(refine_z_kernel, g, dim3(256), 0, s, A);
-}
+// partials of the forward pass at the largest window (the most blocks)
+int refine_partials(int H, int W) { return ceil_div(W, RT_T - 2 * RT_HMAX) * ceil_div(H, RT_SY); }
 
 hipError_t launch_refine_forward(const RefineArgs &A, hipStream_t s) {
-  refine_common(A, s);
-  hipLaunchKernelGGL(refine_sum_kernel, dim3(1), dim3(256), 0, s, A.partial,
-                     refine_partials(A.H, A.W), A.E);
+  const dim3 g = rgrid(A);
+  hipLaunchKernelGGL(refine_fwd_kernel, g, dim3(RT_T), 0, s, A);
+  hipLaunchKernelGGL(refine_sum_kernel, dim3(1), dim3(RT_T), 0, s, A.partial, (int)(g.x * g.y), A.E);
   return hipGetLastError();
 }
 
 hipError_t launch_refine_backward(const RefineArgs &A, hipStream_t s) {
-  refine_common(A, s);
-  for (int p = 0; p < 4; ++p) rbox(A, RF_A1 + p, RF_B1 + p, s);
-  hipLaunchKernelGGL(refine_grad_kernel, dim3(ceil_div(A.W, 256), A.H), dim3(256), 0, s, A);
+  const dim3 g = rgrid(A);
+  hipLaunchKernelGGL(refine_fwd_kernel, g, dim3(RT_T), 0, s, A);
+  hipLaunchKernelGGL(refine_bwd_kernel, g, dim3(RT_T), 0, s, A);
   return hipGetLastError();
 }
 
