@@ -16,6 +16,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libstereo_mi355x.so")
 SOURCES = ["match.hip", "prep.hip", "post.hip", "refine.hip", "api.hip"]
 ARCH = "gfx950"
+# the profiler-range markers (roctx of rocprofiler-sdk)
+LIBS = ["-lrocprofiler-sdk-roctx"]
 
 
 def hipcc() -> str:
@@ -60,7 +62,8 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
         msg = "\n".join(f"--- {s}\n{o}" for s, o in failed)
         raise RuntimeError("hipcc failed:\n" + msg)
     tmp = LIB + ".tmp"
-    subprocess.check_call([cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp])
+    subprocess.check_call([cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp,
+                           *LIBS])
     os.replace(tmp, LIB)
     return LIB
 

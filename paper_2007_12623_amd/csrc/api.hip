@@ -16,10 +16,22 @@
 #include <string>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "common.h"
 #include "stereo.h"
 
 using namespace st;
+
+// ---------------------------------------------------------------- profiler ranges
+// A named range of the host timeline (the enqueueing of a stage, shown by
+// rocprofv3 --marker-trace); without a profiler attached it is a no-op.
+struct Range {
+  explicit Range(const char *name) { roctxRangePushA(name); }
+  ~Range() { roctxRangePop(); }
+  Range(const Range &) = delete;
+  Range &operator=(const Range &) = delete;
+};
 
 // ---------------------------------------------------------------- errors
 static thread_local std::string g_err;
@@ -647,7 +659,11 @@ st_status stereo_match(st_handle h, const uint8_t *left, const uint8_t *right, i
                     debug, M, Pp, Q, Lo, s);
   if (rc) return rc;
   h->dbg.clear();
-  rc = run_front(h, M, Pp, prec, s);
+  Range whole("stereo_match");
+  {
+    Range r("stereo_match: planes, statistics, matcher");
+    rc = run_front(h, M, Pp, prec, s);
+  }
   if (rc) return rc;
   Q.disparity = disparity;
   Q.valid_mask = valid_mask;
@@ -664,7 +680,10 @@ st_status stereo_match(st_handle h, const uint8_t *left, const uint8_t *right, i
     sink.trace.o = (int16_t *)((double *)h->dbgrs.p + (size_t)nrs * N);
     sink.trace.n = nrs;
   }
-  HIPCK(post_stages(L, *params, debug ? &sink : nullptr));
+  {
+    Range r("stereo_match: decode, sub-pixel, left-right, outliers, fills, smoothing");
+    HIPCK(post_stages(L, *params, debug ? &sink : nullptr));
+  }
   if (debug) {
     h->dbg["o_wta"] = Q.ob[0];
     h->dbg["m_wta"] = Q.mb[0];
@@ -721,6 +740,7 @@ st_status stereo_match_noalloc(st_handle h, const uint8_t *left, const uint8_t *
   // by a kernel (no memset node if the caller captures the stream)
   HIPCK(launch_fill_u32(keys, (int)(2 * N), 0u, s));
   fill_views(Lo, base, keys, M, Pp, Q, left, right, pitch);
+  Range whole("stereo_match_noalloc");
   rc = run_front(h, M, Pp, prec, s);
   if (rc) return rc;
   Q.disparity = disparity;
@@ -1052,9 +1072,11 @@ st_status stereo_match_batched(st_handle h, const st_pair *pairs, int n_pairs,
               memcmp(&B.params, params, sizeof(st_params)) == 0 &&
               memcmp(B.pairs.data(), pairs, sizeof(st_pair) * n_pairs) == 0;
   if (same) {
+    Range r("stereo_match_batched: graph replay");
     HIPCK(hipGraphLaunch(B.exec, s));
     return ST_OK;
   }
+  Range build("stereo_match_batched: layout, tables, capture");
   // a replay of the previous layout may still be queued (on this or another
   // stream): its graph and the device tables it reads are replaced below
   HIPCK(hipDeviceSynchronize());
@@ -1366,6 +1388,7 @@ st_status stereo_refine_forward(st_handle h, const uint8_t *left, const uint8_t 
   if (rc) return rc;
   A.Z = Z;
   A.E = E;
+  Range r("stereo_refine_forward");
   HIPCK(launch_refine_forward(A, (hipStream_t)stream));
   return ST_OK;
 }
@@ -1378,6 +1401,7 @@ st_status stereo_refine_backward(st_handle h, const uint8_t *left, const uint8_t
   st_status rc = refine_setup(h, left, right, d, mask, H, W, pitch, win, lambda_tv, A);
   if (rc) return rc;
   A.grad = grad_d;
+  Range r("stereo_refine_backward");
   HIPCK(launch_refine_backward(A, (hipStream_t)stream));
   return ST_OK;
 }

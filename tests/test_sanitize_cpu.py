@@ -151,5 +151,5 @@ def test_library_host_code_under_sanitizers(tmp_path):
     lib = str(tmp_path / "libstereo_san.so")
     subprocess.check_call([hb.hipcc(), f"--offload-arch={hb.ARCH}", "-shared", "-fPIC",
                            "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
-                           "-shared-libsan", *objs, "-o", lib])
+                           "-shared-libsan", *objs, "-o", lib, *hb.LIBS])
     assert "library ok" in _run(LIB_RUN.format(root=ROOT, lib=lib), _clang_asan_runtime())
