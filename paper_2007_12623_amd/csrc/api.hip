@@ -119,7 +119,11 @@ struct st_handle_s {
   // a second capture stream and its fork / join events: the persistent
   // launches of a batch's window sizes after the first run beside it
   hipStream_t side_stream = nullptr;
-  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr, post_fork = nullptr;
+  // capture streams of the post-processing of a batch's image sizes after
+  // the first (created when a batch first needs them), their join events
+  std::vector<hipStream_t> post_streams;
+  std::vector<hipEvent_t> post_done;
   DevBuf ws, keys, rws, dbgrs;
   bool keys_dirty = false;
   int variant = -1;
@@ -552,10 +556,12 @@ st_status st_create(st_handle *out, int device) {
   if (hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess ||
       hipStreamCreateWithFlags(&h->side_stream, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&h->fork_ev, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&h->join_ev, hipEventDisableTiming) != hipSuccess) {
+      hipEventCreateWithFlags(&h->join_ev, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&h->post_fork, hipEventDisableTiming) != hipSuccess) {
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
     if (h->side_stream) (void)hipStreamDestroy(h->side_stream);
     if (h->fork_ev) (void)hipEventDestroy(h->fork_ev);
+    if (h->join_ev) (void)hipEventDestroy(h->join_ev);
     delete h;
     return fail(ST_EHIP, "cannot create the capture streams");
   }
@@ -590,6 +596,9 @@ void st_destroy(st_handle h) {
   if (h->side_stream) (void)hipStreamDestroy(h->side_stream);
   if (h->fork_ev) (void)hipEventDestroy(h->fork_ev);
   if (h->join_ev) (void)hipEventDestroy(h->join_ev);
+  if (h->post_fork) (void)hipEventDestroy(h->post_fork);
+  for (hipStream_t ps : h->post_streams) (void)hipStreamDestroy(ps);
+  for (hipEvent_t pe : h->post_done) (void)hipEventDestroy(pe);
   delete h;
 }
 
@@ -1193,7 +1202,36 @@ st_status stereo_match_batched(st_handle h, const st_pair *pairs, int n_pairs,
   }
   HIPCK(hipMemcpy(at<void>(B.tables.p, tM), M.data(), sizeof(MatchPair) * n_pairs, hipMemcpyHostToDevice));
   HIPCK(hipMemcpy(at<void>(B.tables.p, tP), Pp.data(), sizeof(PrepPair) * n_pairs, hipMemcpyHostToDevice));
-  HIPCK(hipMemcpy(at<void>(B.tables.p, tQ), Q.data(), sizeof(PostPair) * n_pairs, hipMemcpyHostToDevice));
+  // post-processing by image size: the pairs of one size are consecutive in
+  // the table and run each stage as one launch whose grid fits that size
+  // (one grid for the largest pair would leave most blocks of a small pair
+  // empty); sizes by pixel count, largest first
+  std::map<std::pair<int, int>, std::vector<int>> byshape;
+  for (int i = 0; i < n_pairs; ++i) byshape[{pairs[i].H, pairs[i].W}].push_back(i);
+  std::vector<std::vector<int>> shapes;
+  for (auto &kv : byshape) shapes.push_back(kv.second);
+  std::stable_sort(shapes.begin(), shapes.end(), [&](const std::vector<int> &a, const std::vector<int> &b) {
+    return (long long)pairs[a[0]].H * pairs[a[0]].W > (long long)pairs[b[0]].H * pairs[b[0]].W;
+  });
+  std::vector<PostPair> Qs;
+  for (auto &g : shapes)
+    for (int i : g) Qs.push_back(Q[i]);
+  HIPCK(hipMemcpy(at<void>(B.tables.p, tQ), Qs.data(), sizeof(PostPair) * n_pairs, hipMemcpyHostToDevice));
+  // streams for the sizes after the first (at most kPostStreams, shared
+  // round robin beyond that)
+  constexpr int kPostStreams = 7;
+  const int nps = std::min((int)shapes.size() - 1, kPostStreams);
+  while ((int)h->post_streams.size() < nps) {
+    hipStream_t ps = nullptr;
+    hipEvent_t pe = nullptr;
+    HIPCK(hipStreamCreateWithFlags(&ps, hipStreamNonBlocking));
+    if (hipEventCreateWithFlags(&pe, hipEventDisableTiming) != hipSuccess) {
+      (void)hipStreamDestroy(ps);
+      return fail(ST_EHIP, "cannot create a post-processing event");
+    }
+    h->post_streams.push_back(ps);
+    h->post_done.push_back(pe);
+  }
   HIPCK(hipMemcpy(at<void>(B.tables.p, tT), sorted.data(), sizeof(int4) * sorted.size(), hipMemcpyHostToDevice));
   // resident waves of the persistent matcher
   // capture the whole sequence once, replay it on later calls
@@ -1208,20 +1246,35 @@ st_status stereo_match_batched(st_handle h, const st_pair *pairs, int n_pairs,
   B.groups = groups;
   B.prec = prec;
   ck(launch_groups(h, cs, nullptr, nullptr));
-  PostLaunch L;
-  L.one = Q[0];
-  L.many = at<PostPair>(B.tables.p, tQ);
-  L.npairs = n_pairs;
-  L.maxH = maxH;
-  L.maxW = maxW;
-  L.maxWin = 0;
-  L.maxD = 0;
-  for (int i = 0; i < n_pairs; ++i) {
-    L.maxWin = std::max(L.maxWin, Q[i].win);
-    L.maxD = std::max(L.maxD, Q[i].dmax - Q[i].dmin + 1);
+  // the post-processing of each image size; sizes after the first on
+  // streams forked after the matcher and joined back at the end
+  if (nps > 0) {
+    ck(hipEventRecord(h->post_fork, cs));
+    for (int k = 0; k < nps; ++k) ck(hipStreamWaitEvent(h->post_streams[k], h->post_fork, 0));
   }
-  L.s = cs;
-  ck(post_stages(L, *params, nullptr));
+  int first = 0;
+  for (size_t g = 0; g < shapes.size(); ++g) {
+    const std::vector<int> &ids = shapes[g];
+    PostLaunch L;
+    L.one = Qs[first];
+    L.many = at<PostPair>(B.tables.p, tQ) + first;
+    L.npairs = (int)ids.size();
+    L.maxH = pairs[ids[0]].H;
+    L.maxW = pairs[ids[0]].W;
+    L.maxWin = 0;
+    L.maxD = 0;
+    for (int i : ids) {
+      L.maxWin = std::max(L.maxWin, Q[i].win);
+      L.maxD = std::max(L.maxD, Q[i].dmax - Q[i].dmin + 1);
+    }
+    L.s = g == 0 ? cs : h->post_streams[(g - 1) % kPostStreams];
+    ck(post_stages(L, *params, nullptr));
+    first += (int)ids.size();
+  }
+  for (int k = 0; k < nps; ++k) {
+    ck(hipEventRecord(h->post_done[k], h->post_streams[k]));
+    ck(hipStreamWaitEvent(cs, h->post_done[k], 0));
+  }
   hipGraph_t g = nullptr;
   hipError_t ee = hipStreamEndCapture(cs, &g);
   if (e != hipSuccess || ee != hipSuccess) {
