@@ -82,7 +82,8 @@ struct Variant {
 };
 static const Variant kVariants[] = {{8, 16, 8}, {8, 8, 8},  {16, 16, 8}, {16, 8, 8}, {8, 4, 8},
                                     {16, 4, 8}, {8, 2, 8},  {16, 2, 8},  {4, 4, 8},  {4, 2, 8},
-                                    {8, 32, 4}, {8, 16, 4}, {16, 32, 4}, {8, 8, 4}};
+                                    {8, 32, 4}, {8, 16, 4}, {16, 32, 4}, {8, 8, 4}, {10, 16, 8},
+                                    {6, 16, 8}};
 static const int kNumVariants = (int)(sizeof kVariants / sizeof kVariants[0]);
 
 // ---------------------------------------------------------------- handle

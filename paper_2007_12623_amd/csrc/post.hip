@@ -831,10 +831,28 @@ __device__ __forceinline__ int16_t ld16(const GLOBAL int16_t *p, int k) {
   return *(const GLOBAL int16_t *)((const GLOBAL char *)p + 2u * (uint32_t)k);
 }
 
+// Visit the n pixels k0, k0 + ks, ... of a line in order.  Whole groups of
+// LW pixels are loaded before any of them is visited, so that a visit's
+// conditional store never stands between a load and the next one: each
+// group waits for one memory round trip; the last n % LW pixels go one by
+// one.
+constexpr int LW = 8;
+template <class F>
+__device__ __forceinline__ void line_walk(const GLOBAL int16_t *o, int k0, int ks, int n, F f) {
+  int j = 0, k = k0;
+  for (; j + LW <= n; j += LW, k += LW * ks) {
+    int16_t v[LW];
+#pragma unroll
+    for (int i = 0; i < LW; ++i) v[i] = ld16(o, k + i * ks);
+#pragma unroll
+    for (int i = 0; i < LW; ++i) f(j + i, k + i * ks, v[i]);
+  }
+  for (; j < n; ++j, k += ks) f(j, k, ld16(o, k));
+}
+
 // Each scan first runs through the look-ahead rows (state only), then through
 // its own rows, writing results only where a later kernel reads them: pass
-// for valid pixels, hits for holes.  The loops are branch-free so that the
-// loads of an unrolled group issue together.
+// for valid pixels, hits for holes.
 __device__ __forceinline__ void outlier_vscan(const PostPair &P, int bx, int r, float thresh, int src) {
   const int H = P.H, W = P.W;
   int t, l, sg;
@@ -851,63 +869,48 @@ __device__ __forceinline__ void outlier_vscan(const PostPair &P, int bx, int r, 
   // run = consecutive good steps from y along the scan direction (not
   // capped: only run >= r is asked)
   const int ti = step_bound(thresh);
-  auto step = [&](int op, int onb, bool vnb, int run) {
-    return step_ok(op, onb, vnb, ti) ? run + 1 : 0;
-  };
   // forward results of the own rows wait in a bit mask (bit y - a) and are
   // stored with the backward ones
   uint32_t fbits = 0;
   {  // forward (+y), walked from the end of the look-ahead back to a; the
      // line's last pixel has no forward step (bit stays 0)
     const int e = min(L.yhi - 1, b - 1 + r);
-    int k = e * L.st + L.c0;
-    int on = ld16(o, k), run = 0;
+    int on = ld16(o, e * L.st + L.c0), run = 0;
     bool vn = on != O_NONE;
-    int y = e - 1;
-    k -= L.st;
-#pragma unroll 8
-    for (; y >= b; --y, k -= L.st) {
-      const int op = ld16(o, k);
+    auto step = [&](int op) {
       const bool v = op != O_NONE;
-      run = step(op, on, vn, run);
+      run = step_ok(op, on, vn, ti) ? run + 1 : 0;
       on = op;
       vn = v;
-    }
-#pragma unroll 8
-    for (; y >= a; --y, k -= L.st) {
-      const int op = ld16(o, k);
-      const bool v = op != O_NONE;
-      run = step(op, on, vn, run);
-      on = op;
-      vn = v;
-      fbits |= (v && run >= r ? 1u : 0u) << (y - a);
-    }
+      return v;
+    };
+    // look-ahead rows e-1 .. b, then own rows min(e-1, b-1) .. a
+    line_walk(o, (e - 1) * L.st + L.c0, -L.st, e - b, [&](int, int, int16_t op) { step(op); });
+    const int y0 = min(e - 1, b - 1);
+    line_walk(o, y0 * L.st + L.c0, -L.st, y0 - a + 1, [&](int i, int, int16_t op) {
+      const bool v = step(op);
+      fbits |= (v && run >= r ? 1u : 0u) << (y0 - i - a);
+    });
   }
   {  // backward (-y); when e == a the first row has no step (run 0 < r)
     const int e = max(L.ylo, a - r);
-    int k = e * L.st + L.c0;
-    int on = ld16(o, k), run = 0;
+    const int ke = e * L.st + L.c0;
+    int on = ld16(o, ke), run = 0;
     bool vn = on != O_NONE;
-    if (e == a && vn) pass_at(k) = (uint8_t)(fbits & 1u);
-    int y = e + 1;
-    k += L.st;
-#pragma unroll 8
-    for (; y < a; ++y, k += L.st) {
-      const int op = ld16(o, k);
+    if (e == a && vn) pass_at(ke) = (uint8_t)(fbits & 1u);
+    auto step = [&](int op) {
       const bool v = op != O_NONE;
-      run = step(op, on, vn, run);
+      run = step_ok(op, on, vn, ti) ? run + 1 : 0;
       on = op;
       vn = v;
-    }
-#pragma unroll 8
-    for (; y < b; ++y, k += L.st) {
-      const int op = ld16(o, k);
-      const bool v = op != O_NONE;
-      run = step(op, on, vn, run);
-      on = op;
-      vn = v;
-      if (v) pass_at(k) = (uint8_t)(((fbits >> (y - a)) & 1u) | (run >= r ? 2u : 0u));
-    }
+      return v;
+    };
+    // look-ahead rows e+1 .. a-1, then own rows max(e+1, a) .. b-1
+    line_walk(o, (e + 1) * L.st + L.c0, L.st, a - 1 - e, [&](int, int, int16_t op) { step(op); });
+    const int y0 = max(e + 1, a);
+    line_walk(o, y0 * L.st + L.c0, L.st, b - y0, [&](int i, int k, int16_t op) {
+      if (step(op)) pass_at(k) = (uint8_t)(((fbits >> (y0 + i - a)) & 1u) | (run >= r ? 2u : 0u));
+    });
   }
 }
 
@@ -922,51 +925,39 @@ __device__ __forceinline__ void fill_vscan(const PostPair &P, int bx, int R, int
   const size_t N = (size_t)W * H;
   GLOBAL uint32_t *__restrict__ hf = grw(P.hits) + (size_t)(2 * t) * N;
   GLOBAL uint32_t *__restrict__ hb = grw(P.hits) + (size_t)(2 * t + 1) * N;
-  {  // nearest valid pixel in +y
+  {  // nearest valid pixel in +y: look-ahead rows e .. b, own rows b-1 .. a
     const int e = min(L.yhi - 1, b - 1 + R);
     int q = -1;
     uint32_t vq = 0;
-    int y = e, k = e * L.st + L.c0;
-#pragma unroll 8
-    for (; y >= b; --y, k -= L.st) {
-      const int16_t oo = ld16(o, k);
+    line_walk(o, e * L.st + L.c0, -L.st, e - b + 1, [&](int i, int, int16_t oo) {
       const bool v = oo != O_NONE;
-      const uint32_t ov = (uint16_t)oo;
-      q = v ? y : q;
-      vq = v ? ov : vq;
-    }
-#pragma unroll 8
-    for (; y >= a; --y, k -= L.st) {
-      const int16_t oo = ld16(o, k);
+      q = v ? e - i : q;
+      vq = v ? (uint32_t)(uint16_t)oo : vq;
+    });
+    line_walk(o, (b - 1) * L.st + L.c0, -L.st, b - a, [&](int i, int k, int16_t oo) {
+      const int y = b - 1 - i;
       const bool v = oo != O_NONE;
-      const uint32_t ov = (uint16_t)oo;
       if (!v) hf[k] = (q >= 0 && q - y <= R) ? ((uint32_t)(q - y) << 16) | vq : 0u;
       q = v ? y : q;
-      vq = v ? ov : vq;
-    }
+      vq = v ? (uint32_t)(uint16_t)oo : vq;
+    });
   }
-  {  // nearest valid pixel in -y
+  {  // nearest valid pixel in -y: look-ahead rows e .. a-1, own rows a .. b-1
     const int e = max(L.ylo, a - R);
     int q = -1;
     uint32_t vq = 0;
-    int y = e, k = e * L.st + L.c0;
-#pragma unroll 8
-    for (; y < a; ++y, k += L.st) {
-      const int16_t oo = ld16(o, k);
+    line_walk(o, e * L.st + L.c0, L.st, a - e, [&](int i, int, int16_t oo) {
       const bool v = oo != O_NONE;
-      const uint32_t ov = (uint16_t)oo;
-      q = v ? y : q;
-      vq = v ? ov : vq;
-    }
-#pragma unroll 8
-    for (; y < b; ++y, k += L.st) {
-      const int16_t oo = ld16(o, k);
+      q = v ? e + i : q;
+      vq = v ? (uint32_t)(uint16_t)oo : vq;
+    });
+    line_walk(o, a * L.st + L.c0, L.st, b - a, [&](int i, int k, int16_t oo) {
+      const int y = a + i;
       const bool v = oo != O_NONE;
-      const uint32_t ov = (uint16_t)oo;
       if (!v) hb[k] = (q >= 0 && y - q <= R) ? ((uint32_t)(y - q) << 16) | vq : 0u;
       q = v ? y : q;
-      vq = v ? ov : vq;
-    }
+      vq = v ? (uint32_t)(uint16_t)oo : vq;
+    });
   }
 }
 
