@@ -127,9 +127,10 @@ __global__ __launch_bounds__(WS_T) void window_stats_kernel(PrepPair one, const 
   int acc[NV];
 #pragma unroll
   for (int i = 0; i < NV; ++i) acc[i] = 0;
-  // add (sgn = 1) or remove (sgn = -1) row r of the column
-  auto step = [&](int r, int sgn) {
-    const int v = sgn * px(r), vv = v * (sgn * v);
+  // add (sgn = 1) or remove (sgn = -1) row r of the column, whose pixel
+  // value is p
+  auto step_v = [&](int r, int sgn, int p) {
+    const int v = sgn * p, vv = v * (sgn * v);
     if constexpr (CH) {
       const bool odd = ((c + r) & 1) != 0;
       acc[0] += odd ? 0 : v;
@@ -141,18 +142,20 @@ __global__ __launch_bounds__(WS_T) void window_stats_kernel(PrepPair one, const 
       acc[1] += vv;
     }
   };
+  auto step = [&](int r, int sgn) { step_v(r, sgn, px(r)); };
   for (int r = y0 - h; r < y0 + h; ++r) step(r, 1);
   const bool out_col = c >= xo && c < xo + WS_NOUT && c < W;  // then h <= t < WS_T - h
   const int y1 = min(y0 + WS_SY, H);
   const int n = CH ? (win * win + 1) / 2 : win * win;
   const int lane = t & 63, wave = t >> 6;
   // the window sums of row y (add row y + h, then drop row y - h for the
-  // next), scanned along each wave; the wave totals go to slot b
-  auto stage = [&](int b, int y, int (&pv)[NV]) {
-    step(y + h, 1);
+  // next; q: their pixel values), scanned along each wave; the wave totals
+  // go to slot b
+  auto stage = [&](int b, int y, int2 q, int (&pv)[NV]) {
+    step_v(y + h, 1, q.x);
 #pragma unroll
     for (int i = 0; i < NV; ++i) pv[i] = acc[i];
-    step(y - h, -1);
+    step_v(y - h, -1, q.y);
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
       pv[i] = wave_scan_incl(pv[i]);
@@ -211,11 +214,17 @@ __global__ __launch_bounds__(WS_T) void window_stats_kernel(PrepPair one, const 
   // the prefix sums before they are written again.  The second: the prefix
   // sums are complete before the outputs read them, and the totals read
   // before the next pair writes them.
+  // the pixels a row's stage adds and drops are loaded two rows ahead
+  auto fetch = [&](int y) { return make_int2(px(y + h), px(y - h)); };
+  int2 q0 = fetch(y0), q1 = y0 + 1 < y1 ? fetch(y0 + 1) : make_int2(0, 0);
   for (int y = y0; y < y1; y += 2) {
     const bool two = y + 1 < y1;
+    const int2 c0 = q0, c1 = q1;
+    if (y + 2 < y1) q0 = fetch(y + 2);
+    if (y + 3 < y1) q1 = fetch(y + 3);
     int p0[NV], p1[NV];
-    stage(0, y, p0);
-    if (two) stage(1, y + 1, p1);
+    stage(0, y, c0, p0);
+    if (two) stage(1, y + 1, c1, p1);
     __syncthreads();
     finish(0, p0);
     if (two) finish(1, p1);
