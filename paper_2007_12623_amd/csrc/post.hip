@@ -914,6 +914,28 @@ __device__ __forceinline__ void outlier_vscan(const PostPair &P, int bx, int r, 
   }
 }
 
+// The first valid pixel of a line walking from k0 in steps of ks, at most n
+// pixels (its index along the walk in i, its disparity in vq; i = -1 when
+// there is none).  Groups of LW loads, stopping after the first group that
+// holds a valid pixel: where most pixels are valid that is the first.
+__device__ __forceinline__ int first_valid(const GLOBAL int16_t *o, int k0, int ks, int n,
+                                           uint32_t &vq) {
+  for (int j = 0; j < n; j += LW) {
+    int16_t v[LW];
+#pragma unroll
+    for (int i = 0; i < LW; ++i) v[i] = ld16(o, k0 + min(j + i, n - 1) * ks);
+    int f = -1;
+#pragma unroll
+    for (int i = LW - 1; i >= 0; --i)
+      if (j + i < n && v[i] != O_NONE) {
+        f = j + i;
+        vq = (uint32_t)(uint16_t)v[i];
+      }
+    if (f >= 0) return f;
+  }
+  return -1;
+}
+
 __device__ __forceinline__ void fill_vscan(const PostPair &P, int bx, int R, int src) {
   const int H = P.H, W = P.W;
   int t, l, sg;
@@ -925,15 +947,12 @@ __device__ __forceinline__ void fill_vscan(const PostPair &P, int bx, int R, int
   const size_t N = (size_t)W * H;
   GLOBAL uint32_t *__restrict__ hf = grw(P.hits) + (size_t)(2 * t) * N;
   GLOBAL uint32_t *__restrict__ hb = grw(P.hits) + (size_t)(2 * t + 1) * N;
-  {  // nearest valid pixel in +y: look-ahead rows e .. b, own rows b-1 .. a
+  {  // nearest valid pixel in +y: the first one at or after b (at most up to
+     // b - 1 + R), then own rows b-1 .. a
     const int e = min(L.yhi - 1, b - 1 + R);
-    int q = -1;
     uint32_t vq = 0;
-    line_walk(o, e * L.st + L.c0, -L.st, e - b + 1, [&](int i, int, int16_t oo) {
-      const bool v = oo != O_NONE;
-      q = v ? e - i : q;
-      vq = v ? (uint32_t)(uint16_t)oo : vq;
-    });
+    const int f = first_valid(o, b * L.st + L.c0, L.st, e - b + 1, vq);
+    int q = f >= 0 ? b + f : -1;
     line_walk(o, (b - 1) * L.st + L.c0, -L.st, b - a, [&](int i, int k, int16_t oo) {
       const int y = b - 1 - i;
       const bool v = oo != O_NONE;
@@ -942,15 +961,12 @@ __device__ __forceinline__ void fill_vscan(const PostPair &P, int bx, int R, int
       vq = v ? (uint32_t)(uint16_t)oo : vq;
     });
   }
-  {  // nearest valid pixel in -y: look-ahead rows e .. a-1, own rows a .. b-1
+  {  // nearest valid pixel in -y: the first one at or before a - 1 (at most
+     // down to a - R), then own rows a .. b-1
     const int e = max(L.ylo, a - R);
-    int q = -1;
     uint32_t vq = 0;
-    line_walk(o, e * L.st + L.c0, L.st, a - e, [&](int i, int, int16_t oo) {
-      const bool v = oo != O_NONE;
-      q = v ? e + i : q;
-      vq = v ? (uint32_t)(uint16_t)oo : vq;
-    });
+    const int f = first_valid(o, (a - 1) * L.st + L.c0, -L.st, a - e, vq);
+    int q = f >= 0 ? a - 1 - f : -1;
     line_walk(o, a * L.st + L.c0, L.st, b - a, [&](int i, int k, int16_t oo) {
       const int y = a + i;
       const bool v = oo != O_NONE;
