@@ -1209,8 +1209,15 @@ st_status stereo_match_batched(st_handle h, const st_pair *pairs, int n_pairs,
   // empty); sizes by pixel count, largest first
   std::map<std::pair<int, int>, std::vector<int>> byshape;
   for (int i = 0; i < n_pairs; ++i) byshape[{pairs[i].H, pairs[i].W}].push_back(i);
+  // a size with many pairs is cut in two halves on two streams, so that the
+  // tail of one half's launch overlaps the other's (each stage is a chain
+  // of short launches whose last blocks leave most of the chip idle)
   std::vector<std::vector<int>> shapes;
-  for (auto &kv : byshape) shapes.push_back(kv.second);
+  for (auto &kv : byshape) {
+    const size_t n = kv.second.size(), cut = n >= 8 ? n / 2 : n;
+    shapes.emplace_back(kv.second.begin(), kv.second.begin() + cut);
+    if (cut < n) shapes.emplace_back(kv.second.begin() + cut, kv.second.end());
+  }
   std::stable_sort(shapes.begin(), shapes.end(), [&](const std::vector<int> &a, const std::vector<int> &b) {
     return (long long)pairs[a[0]].H * pairs[a[0]].W > (long long)pairs[b[0]].H * pairs[b[0]].W;
   });
@@ -1218,7 +1225,7 @@ st_status stereo_match_batched(st_handle h, const st_pair *pairs, int n_pairs,
   for (auto &g : shapes)
     for (int i : g) Qs.push_back(Q[i]);
   HIPCK(hipMemcpy(at<void>(B.tables.p, tQ), Qs.data(), sizeof(PostPair) * n_pairs, hipMemcpyHostToDevice));
-  // streams for the sizes after the first (at most kPostStreams, shared
+  // streams for the groups after the first (at most kPostStreams, shared
   // round robin beyond that)
   constexpr int kPostStreams = 7;
   const int nps = std::min((int)shapes.size() - 1, kPostStreams);
@@ -1247,8 +1254,8 @@ st_status stereo_match_batched(st_handle h, const st_pair *pairs, int n_pairs,
   B.groups = groups;
   B.prec = prec;
   ck(launch_groups(h, cs, nullptr, nullptr));
-  // the post-processing of each image size; sizes after the first on
-  // streams forked after the matcher and joined back at the end
+  // the post-processing of each group; groups after the first on streams
+  // forked after the matcher and joined back at the end
   if (nps > 0) {
     ck(hipEventRecord(h->post_fork, cs));
     for (int k = 0; k < nps; ++k) ck(hipStreamWaitEvent(h->post_streams[k], h->post_fork, 0));
