@@ -2,6 +2,8 @@
 // II-A: ZNCC needs the window means and deviations of both images): the
 // padded image planes the matcher streams, and the exact window sums with
 // the inverse deviations, for the square or the chessboard window.
+#include <type_traits>
+
 #include "common.h"
 
 namespace st {
@@ -97,87 +99,116 @@ __global__ void prep_planes_kernel(PrepPair one, const PrepPair *many) {
 
 // Window sums S = sum I, SS = sum I^2 and 1/sqrt(n SS - S^2) of every pixel
 // whose window lies inside the image (0 / NaN elsewhere).  side 0: left
-// image (dense and padded planes), 1: right image, 2: dense planes only.
-// A block of WS_T threads owns WS_T columns; each thread keeps the vertical
-// window sums of its column down a segment of WS_SY rows and the horizontal
-// sums are differences of a block prefix sum (wave scans, then the wave
-// totals before each wave added through LDS).  Two rows share each of the
-// two barriers this takes.  Output columns of a block are WS_T - 2 WS_HMAX
-// wide for every window.
+// image (dense and padded planes), 1: right image, 2: dense planes only;
+// NS = 2: both images of the pair in one pass (sides 0 and 1), so that the
+// two share every barrier.  A block of WS_T threads owns WS_T columns; each
+// thread keeps the vertical window sums of its column down a segment of
+// WS_SY rows and the horizontal sums are differences of a block prefix sum
+// (wave scans, then the wave totals before each wave added through LDS).
+// Two rows share each of the two barriers this takes.  Output columns of a
+// block are WS_T - 2 WS_HMAX wide for every window.
 // CH (chessboard window): a column keeps separate sums of its cells with
 // x + y even and odd; a pixel takes the prefix sums of its own colour, since
 // the cells u + v even around (x, y) are exactly those of the colour of
 // (x, y).
 constexpr int WS_T = 256, WS_SY = 16, WS_HMAX = 7, WS_NOUT = WS_T - 2 * WS_HMAX;
 
-template <bool B, bool CH>
+template <bool B, bool CH, int NS>
 __global__ __launch_bounds__(WS_T) void window_stats_kernel(PrepPair one, const PrepPair *many,
                                                             int side) {
   const BlockPos bp = block_pos();
   const PrepPair &P = B ? many[bp.pair] : one;
   constexpr int NV = CH ? 4 : 2;  // (S, SS) of each colour
-  __shared__ int pf[2][NV][WS_T], wt[2][NV][WS_T / 64];
+  constexpr int NA = NS * NV;     // sums of a column: per image, per colour
+  __shared__ int pf[2][NA][WS_T], wt[2][NA][WS_T / 64];
   const int H = P.H, W = P.W, win = P.win, h = win / 2;
   const int xo = bp.x * WS_NOUT, y0 = bp.y * WS_SY;
   if (xo >= W || y0 >= H) return;  // uniform per block
-  const GLOBAL uint8_t *img = gro(side == 1 ? P.R : P.L);
+  // the images of the pass and their sides
+  const GLOBAL uint8_t *img[NS];
+  int sd[NS];
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    sd[i] = NS == 2 ? i : side;
+    img[i] = gro(sd[i] == 1 ? P.R : P.L);
+  }
   const int t = threadIdx.x, c = xo - h + t;
   const bool cin = c >= 0 && c < W;
-  auto px = [&](int r) -> int { return (cin && r >= 0 && r < H) ? (int)img[(size_t)r * P.pitch + c] : 0; };
-  int acc[NV];
-#pragma unroll
-  for (int i = 0; i < NV; ++i) acc[i] = 0;
-  // add (sgn = 1) or remove (sgn = -1) row r of the column, whose pixel
-  // value is p
-  auto step_v = [&](int r, int sgn, int p) {
-    const int v = sgn * p, vv = v * (sgn * v);
-    if constexpr (CH) {
-      const bool odd = ((c + r) & 1) != 0;
-      acc[0] += odd ? 0 : v;
-      acc[1] += odd ? 0 : vv;
-      acc[2] += odd ? v : 0;
-      acc[3] += odd ? vv : 0;
+  using Px = typename std::conditional<NS == 2, int2, int>::type;
+  // the pixel values of row r of the column (0 outside the image)
+  auto px = [&](int r) -> Px {
+    const bool in = cin && r >= 0 && r < H;
+    const size_t k = (size_t)r * P.pitch + c;
+    if constexpr (NS == 2) {
+      return make_int2(in ? (int)img[0][k] : 0, in ? (int)img[1][k] : 0);
     } else {
-      acc[0] += v;
-      acc[1] += vv;
+      return in ? (int)img[0][k] : 0;
     }
   };
-  auto step = [&](int r, int sgn) { step_v(r, sgn, px(r)); };
-  for (int r = y0 - h; r < y0 + h; ++r) step(r, 1);
+  auto val = [](const Px &p, int i) -> int {
+    if constexpr (NS == 2) return i ? p.y : p.x;
+    else return p;
+  };
+  int acc[NA];
+#pragma unroll
+  for (int i = 0; i < NA; ++i) acc[i] = 0;
+  // add (sgn = 1) or remove (sgn = -1) row r of the column, whose pixel
+  // values are p
+  auto step_v = [&](int r, int sgn, const Px &p) {
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+      const int v = sgn * val(p, i), vv = v * (sgn * v);
+      int *a = acc + NV * i;
+      if constexpr (CH) {
+        const bool odd = ((c + r) & 1) != 0;
+        a[0] += odd ? 0 : v;
+        a[1] += odd ? 0 : vv;
+        a[2] += odd ? v : 0;
+        a[3] += odd ? vv : 0;
+      } else {
+        a[0] += v;
+        a[1] += vv;
+      }
+    }
+  };
+  for (int r = y0 - h; r < y0 + h; ++r) step_v(r, 1, px(r));
   const bool out_col = c >= xo && c < xo + WS_NOUT && c < W;  // then h <= t < WS_T - h
   const int y1 = min(y0 + WS_SY, H);
   const int n = CH ? (win * win + 1) / 2 : win * win;
   const int lane = t & 63, wave = t >> 6;
   // the window sums of row y (add row y + h, then drop row y - h for the
-  // next; q: their pixel values), scanned along each wave; the wave totals
-  // go to slot b
-  auto stage = [&](int b, int y, int2 q, int (&pv)[NV]) {
-    step_v(y + h, 1, q.x);
+  // next; qa, qd: their pixel values), scanned along each wave; the wave
+  // totals go to slot b
+  auto stage = [&](int b, int y, const Px &qa, const Px &qd, int (&pv)[NA]) {
+    step_v(y + h, 1, qa);
 #pragma unroll
-    for (int i = 0; i < NV; ++i) pv[i] = acc[i];
-    step_v(y - h, -1, q.y);
+    for (int i = 0; i < NA; ++i) pv[i] = acc[i];
+    step_v(y - h, -1, qd);
 #pragma unroll
-    for (int i = 0; i < NV; ++i) {
+    for (int i = 0; i < NA; ++i) {
       pv[i] = wave_scan_incl(pv[i]);
       if (lane == 63) wt[b][i][wave] = pv[i];
     }
   };
   // the block prefix: the totals of the waves before this one added
-  auto finish = [&](int b, int (&pv)[NV]) {
+  auto finish = [&](int b, int (&pv)[NA]) {
     for (int w = 0; w < wave; ++w) {
 #pragma unroll
-      for (int i = 0; i < NV; ++i) pv[i] += wt[b][i][w];
+      for (int i = 0; i < NA; ++i) pv[i] += wt[b][i][w];
     }
 #pragma unroll
-    for (int i = 0; i < NV; ++i) pf[b][i][t] = pv[i];
+    for (int i = 0; i < NA; ++i) pf[b][i][t] = pv[i];
   };
   auto emit = [&](int b, int y) {
-    if (out_col) {
-      const int x = c;
-      const int q = CH ? 2 * ((x + y) & 1) : 0;
+    if (!out_col) return;
+    const int x = c;
+    const bool inside = x >= h && x <= W - 1 - h && y >= h && y <= H - 1 - h;
+    const size_t k = (size_t)y * W + x;
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+      const int q = NV * i + (CH ? 2 * ((x + y) & 1) : 0);
       int S = pf[b][q][t + h] - (t - h - 1 >= 0 ? pf[b][q][t - h - 1] : 0);
       int SS = pf[b][q + 1][t + h] - (t - h - 1 >= 0 ? pf[b][q + 1][t - h - 1] : 0);
-      const bool inside = x >= h && x <= W - 1 - h && y >= h && y <= H - 1 - h;
       float iv = __builtin_nanf("");
       if (!inside) {
         S = 0;
@@ -188,8 +219,7 @@ __global__ __launch_bounds__(WS_T) void window_stats_kernel(PrepPair one, const 
         // rounded once to float
         if (varN > 0) iv = (float)rsqrt((double)varN);
       }
-      const size_t k = (size_t)y * W + x;
-      if (side == 1) {
+      if (sd[i] == 1) {
         P.SR[k] = S;
         P.SSR[k] = SS;
         if (P.invRd) P.invRd[k] = iv;
@@ -200,7 +230,7 @@ __global__ __launch_bounds__(WS_T) void window_stats_kernel(PrepPair one, const 
         P.SL[k] = S;
         P.SSL[k] = SS;
         if (P.invLd) P.invLd[k] = iv;
-        if (side == 0) {
+        if (sd[i] == 0) {
           const size_t kp = (size_t)y * P.strideL + x + P.padL;
           P.negSL[kp] = 128 * n - S;
           P.invL[kp] = iv;
@@ -215,16 +245,22 @@ __global__ __launch_bounds__(WS_T) void window_stats_kernel(PrepPair one, const 
   // sums are complete before the outputs read them, and the totals read
   // before the next pair writes them.
   // the pixels a row's stage adds and drops are loaded two rows ahead
-  auto fetch = [&](int y) { return make_int2(px(y + h), px(y - h)); };
-  int2 q0 = fetch(y0), q1 = y0 + 1 < y1 ? fetch(y0 + 1) : make_int2(0, 0);
+  Px a0 = px(y0 + h), d0 = px(y0 - h);
+  Px a1 = px(y0 + 1 + h), d1 = px(y0 + 1 - h);
   for (int y = y0; y < y1; y += 2) {
     const bool two = y + 1 < y1;
-    const int2 c0 = q0, c1 = q1;
-    if (y + 2 < y1) q0 = fetch(y + 2);
-    if (y + 3 < y1) q1 = fetch(y + 3);
-    int p0[NV], p1[NV];
-    stage(0, y, c0, p0);
-    if (two) stage(1, y + 1, c1, p1);
+    const Px ca0 = a0, cd0 = d0, ca1 = a1, cd1 = d1;
+    if (y + 2 < y1) {
+      a0 = px(y + 2 + h);
+      d0 = px(y + 2 - h);
+    }
+    if (y + 3 < y1) {
+      a1 = px(y + 3 + h);
+      d1 = px(y + 3 - h);
+    }
+    int p0[NA], p1[NA];
+    stage(0, y, ca0, cd0, p0);
+    if (two) stage(1, y + 1, ca1, cd1, p1);
     __syncthreads();
     finish(0, p0);
     if (two) finish(1, p1);
@@ -248,15 +284,14 @@ hipError_t launch_prep(const PrepPair &one, const PrepPair *many, int npairs, in
   } while (0)
   if (prec == P_I16) PP(P_I16); else if (prec == P_F16) PP(P_F16); else PP(P_BF16);
 #undef PP
-  // the window shape is shared by every pair of a batch (one parameter set)
+  // the window shape is shared by every pair of a batch (one parameter set);
+  // both images in one pass
   const dim3 gs(ceil_div(maxW, WS_NOUT), ceil_div(maxH, WS_SY), npairs);
-#define WS(b, ch) hipLaunchKernelGGL((window_stats_kernel<b, ch>), gs, dim3(WS_T), 0, s, one, many, side)
-  for (int side = 0; side < 2; ++side) {
-    if (many) {
-      if (one.chess) WS(true, true); else WS(true, false);
-    } else {
-      if (one.chess) WS(false, true); else WS(false, false);
-    }
+#define WS(b, ch) hipLaunchKernelGGL((window_stats_kernel<b, ch, 2>), gs, dim3(WS_T), 0, s, one, many, 0)
+  if (many) {
+    if (one.chess) WS(true, true); else WS(true, false);
+  } else {
+    if (one.chess) WS(false, true); else WS(false, false);
   }
 #undef WS
   return hipGetLastError();
@@ -276,9 +311,9 @@ hipError_t launch_window_stats_dense(const uint8_t *img, int H, int W, int pitch
   P.invLd = inv;
   const dim3 gs(ceil_div(W, WS_NOUT), ceil_div(H, WS_SY), 1);
   if (chess)
-    hipLaunchKernelGGL((window_stats_kernel<false, true>), gs, dim3(WS_T), 0, s, P, (const PrepPair *)nullptr, 2);
+    hipLaunchKernelGGL((window_stats_kernel<false, true, 1>), gs, dim3(WS_T), 0, s, P, (const PrepPair *)nullptr, 2);
   else
-    hipLaunchKernelGGL((window_stats_kernel<false, false>), gs, dim3(WS_T), 0, s, P, (const PrepPair *)nullptr, 2);
+    hipLaunchKernelGGL((window_stats_kernel<false, false, 1>), gs, dim3(WS_T), 0, s, P, (const PrepPair *)nullptr, 2);
   return hipGetLastError();
 }
 
