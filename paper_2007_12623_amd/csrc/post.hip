@@ -806,19 +806,37 @@ __device__ __forceinline__ VLine vline(int t, int l, int H, int W) {
   }
   return v;
 }
-__device__ __forceinline__ int vlines(int t, int H, int W) { return t == 1 ? W : W + H - 1; }
-
-// Thread index -> (line type 1..3, line, row segment); false past the end.
+// Thread index -> (line type 1..3, line, row segment); false for an idle
+// thread.  The rows [a0, a1) of a segment meet W columns and W + (a1 - a0) -
+// 1 lines of either diagonal direction: a line type gives each segment
+// W + SEG - 1 threads (W for columns), and its range of thread indices is
+// rounded up to whole waves, so that the lanes of a wave share one line type
+// and with it the step between a line's pixels in the plane.
+__host__ __device__ inline int vscan_slots(int t, int W) { return t == 1 ? W : W + SEG - 1; }
+__host__ __device__ inline int vscan_span(int t, int H, int W) {
+  return (ceil_div(H, SEG) * vscan_slots(t, W) + WV - 1) / WV * WV;
+}
 __device__ __forceinline__ bool vscan_task(int idx, int H, int W, int &t, int &l, int &sg) {
   const int ns = ceil_div(H, SEG);
   for (t = 1; t < 4; ++t) {
-    const int nl = vlines(t, H, W);
-    if (idx < nl * ns) {
-      sg = idx / nl;
-      l = idx - sg * nl;
+    const int span = vscan_span(t, H, W);
+    if (idx < span) {
+      const int nper = vscan_slots(t, W);
+      sg = idx / nper;
+      if (sg >= ns) return false;  // rounding to whole waves
+      const int i = idx - sg * nper;
+      if (t == 1) {
+        l = i;
+        return true;
+      }
+      const int a0 = sg * SEG, a1 = min(H, a0 + SEG);
+      if (i >= W + (a1 - a0) - 1) return false;  // a short last segment
+      // the first line through the segment: through (0, a1 - 1) for the
+      // diagonals, through (0, a0) for the anti-diagonals
+      l = (t == 2 ? H - a1 : a0) + i;
       return true;
     }
-    idx -= nl * ns;
+    idx -= span;
   }
   return false;
 }
@@ -831,23 +849,32 @@ __device__ __forceinline__ int16_t ld16(const GLOBAL int16_t *p, int k) {
   return *(const GLOBAL int16_t *)((const GLOBAL char *)p + 2u * (uint32_t)k);
 }
 
-// Visit the n pixels k0, k0 + ks, ... of a line in order.  Whole groups of
-// LW pixels are loaded before any of them is visited, so that a visit's
-// conditional store never stands between a load and the next one: each
-// group waits for one memory round trip; the last n % LW pixels go one by
-// one.
+// Visit the n pixels k0, k0 + ks, ... of a line in order (ks the same for
+// every lane of the wave).  Whole groups of LW pixels are loaded before any
+// of them is visited, so that a visit's conditional store never stands
+// between a load and the next one: each group waits for one memory round
+// trip; the last n % LW pixels go one by one.  Load i of a group takes the
+// scalar base o + i ks (below o for a negative step: the sum with the lane's
+// offset, the byte offset of the group's first pixel, is a pixel of the
+// line) and the one lane offset of the group.
 constexpr int LW = 8;
 template <class F>
 __device__ __forceinline__ void line_walk(const GLOBAL int16_t *o, int k0, int ks, int n, F f) {
+  const int ksu = __builtin_amdgcn_readfirstlane(ks);
+  const GLOBAL char *bs[LW];
+#pragma unroll
+  for (int i = 0; i < LW; ++i)
+    bs[i] = (const GLOBAL char *)((uintptr_t)o + (uintptr_t)(2 * (intptr_t)i * ksu));
   int j = 0, k = k0;
-  for (; j + LW <= n; j += LW, k += LW * ks) {
+  for (; j + LW <= n; j += LW, k += LW * ksu) {
+    const uint32_t kb = 2u * (uint32_t)k;
     int16_t v[LW];
 #pragma unroll
-    for (int i = 0; i < LW; ++i) v[i] = ld16(o, k + i * ks);
+    for (int i = 0; i < LW; ++i) v[i] = *(const GLOBAL int16_t *)(bs[i] + kb);
 #pragma unroll
-    for (int i = 0; i < LW; ++i) f(j + i, k + i * ks, v[i]);
+    for (int i = 0; i < LW; ++i) f(j + i, k + i * ksu, v[i]);
   }
-  for (; j < n; ++j, k += ks) f(j, k, ld16(o, k));
+  for (; j < n; ++j, k += ksu) f(j, k, ld16(o, k));
 }
 
 // Each scan first runs through the look-ahead rows (state only), then through
@@ -1840,7 +1867,8 @@ hipError_t post_lr(const PostLaunch &L, int tol, int dst) {
 // blocks of the row scans (4 rows each) and of the column / diagonal scans
 static int rowblocks(const PostLaunch &L) { return ceil_div(L.maxH, 4); }
 static int vscanblocks(const PostLaunch &L) {
-  const int n = (L.maxW + 2 * (L.maxW + L.maxH - 1)) * ceil_div(L.maxH, SEG);
+  int n = 0;
+  for (int t = 1; t < 4; ++t) n += vscan_span(t, L.maxH, L.maxW);
   return ceil_div(n, 256);
 }
 
