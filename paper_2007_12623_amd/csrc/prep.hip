@@ -20,6 +20,27 @@ __device__ __forceinline__ uint16_t enc16(int v, int n) {
   else if constexpr (PREC == P_F16) return __builtin_bit_cast(uint16_t, (_Float16)(float)v);
   else return (uint16_t)(__builtin_bit_cast(uint32_t, (float)v) >> 16);
 }
+// Bytes x0 .. x0 + 3 of an image row of W bytes, byte j of the result (0
+// outside the row).  Inside the row the bytes come from one aligned dword,
+// or two realigned with v_alignbyte (the misalignment is that of the row
+// base, the same for every thread of the row when x0 is a multiple of 4);
+// near the row's ends byte by byte, so that no load leaves the row.
+__device__ __forceinline__ uint32_t row4(const GLOBAL uint8_t *row, int x0, int W) {
+  const int mis = (int)(((uintptr_t)row + (uintptr_t)(intptr_t)x0) & 3);
+  const int lo = x0 - mis;
+  if (lo >= 0 && lo + (mis ? 8 : 4) <= W) {
+    const GLOBAL uint32_t *q = (const GLOBAL uint32_t *)(row + lo);
+    return mis ? __builtin_amdgcn_alignbyte(q[1], q[0], mis) : q[0];
+  }
+  uint32_t v = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int x = x0 + j;
+    if (x >= 0 && x < W) v |= (uint32_t)row[x] << (8 * j);
+  }
+  return v;
+}
+
 template <int PREC, bool B>
 __global__ void prep_planes_kernel(PrepPair one, const PrepPair *many) {
   const BlockPos bp = block_pos();
@@ -35,11 +56,12 @@ __global__ void prep_planes_kernel(PrepPair one, const PrepPair *many) {
   if (c0 < P.strideL) {
     int v[4];
     bool in[4];
+    const uint32_t w4 = row4(Lrow, c0 - P.padL, W);
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int x = c0 + j - P.padL;
       in[j] = x >= 0 && x < W;
-      v[j] = in[j] ? (int)Lrow[x] - 128 : 0;
+      v[j] = in[j] ? (int)((w4 >> (8 * j)) & 255u) - 128 : 0;
     }
     const size_t k = (size_t)y * P.strideL + c0;
     // mask: bit j keeps column j (all, or one chessboard colour)
@@ -72,11 +94,12 @@ __global__ void prep_planes_kernel(PrepPair one, const PrepPair *many) {
   if (c0 < P.strideR) {
     int v[4];
     bool in[4];
+    const uint32_t w4 = row4(Rrow, c0 - P.padR, W);
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int x = c0 + j - P.padR;
       in[j] = x >= 0 && x < W;
-      v[j] = in[j] ? (int)Rrow[x] : 0;
+      v[j] = in[j] ? (int)((w4 >> (8 * j)) & 255u) : 0;
     }
     const size_t k = (size_t)y * P.strideR + c0;
     if constexpr (PREC == P_I16) {
