@@ -1059,10 +1059,13 @@ __global__ void outlier_combine_kernel(PostPair one, const PostPair *__restrict_
 // together (two round trips per piece), and the piece's prefix sums take
 // one block barrier (wave scans, then the wave totals of the four chunks
 // in LDS).
+// packed (the disk fill's radius up to DISK_RPK and rows narrower than 4096):
+// one 32-bit word per prefix, count | sum << 12 (the sum modulo 2^20; see
+// fill_disk_kernel), in plane pc alone.
 constexpr int RF_CPT = 4;
 template <bool B>
 __global__ __launch_bounds__(256) void fill_radial_kernel(PostPair one, const PostPair *__restrict__ many,
-                                                          int min_lines, int src, int dst) {
+                                                          int min_lines, int src, int dst, int packed) {
   PAIR;
   __shared__ int wc[RF_CPT][4], wsum[RF_CPT][4];
   const int y = bp.x;
@@ -1075,7 +1078,7 @@ __global__ __launch_bounds__(256) void fill_radial_kernel(PostPair one, const Po
   GLOBAL int32_t *psr = grw(P.ps) + (size_t)y * (W + 1);
   if (t == 0) {
     pcr[0] = 0;
-    psr[0] = 0;
+    if (!packed) psr[0] = 0;
   }
   const uint32_t row = (uint32_t)y * (uint32_t)W;  // flat index of (0, y): below 2^28
   int carry_c = 0, carry_s = 0;
@@ -1153,8 +1156,12 @@ __global__ __launch_bounds__(256) void fill_radial_kernel(PostPair one, const Po
       }
       const int x = x0 + 256 * j + t;
       if (x < W) {
-        pcr[x + 1] = bc + c[j];
-        psr[x + 1] = bs + sv[j];
+        if (packed) {
+          pcr[x + 1] = (int32_t)((uint32_t)(bc + c[j]) | ((uint32_t)(bs + sv[j]) << 12));
+        } else {
+          pcr[x + 1] = bc + c[j];
+          psr[x + 1] = bs + sv[j];
+        }
       }
 #pragma unroll
       for (int w = 0; w < 4; ++w) {
@@ -1179,11 +1186,11 @@ __device__ __forceinline__ int isqrt_floor(int v) {
 // Disk sums come from the row prefix sums, one segment per disk row; the
 // half-widths floor(sqrt(R^2 - dy^2)) of the disk rows are tabulated once
 // per block (for |dy| <= DISK_TAB) instead of per pixel and row.
-constexpr int DISK_TAB = 512, DISK_R32 = 256;
+constexpr int DISK_TAB = 512, DISK_R32 = 256, DISK_RPK = 63;
 
 template <bool B>
 __global__ __launch_bounds__(PIX_T) void fill_disk_kernel(PostPair one, const PostPair *__restrict__ many, int R,
-                                                        float frac, int src, int dst) {
+                                                        float frac, int src, int dst, int packed) {
   PAIR;
   __shared__ int hw[2 * DISK_TAB + 1];
   __shared__ int holes[PIX_SEG];
@@ -1235,6 +1242,37 @@ __global__ __launch_bounds__(PIX_T) void fill_disk_kernel(PostPair one, const Po
   const int nh = nholes;
   const GLOBAL int32_t *__restrict__ pc = gro(P.pc);
   const GLOBAL int32_t *__restrict__ ps = gro(P.ps);
+  if (packed) {
+    // one load at either end of a disk row (the address unit, not the bytes,
+    // bounds this loop): the difference of two packed prefixes is cnt +
+    // sum * 4096 exactly as an int32, since a row segment holds at most
+    // 2 DISK_RPK + 1 = 127 cells (cnt in [0, 127]) of |o| <= 4096 (|sum| <
+    // 2^19), and the counts below 4096 never wrap
+    for (int i = threadIdx.x; i < nh; i += PIX_T) {
+      const int x = holes[i];
+      const size_t k = (size_t)y * W + x;
+      int cells = 0, cnt = 0, sum = 0;
+      const int ya = max(-R, -y), yb = min(R, H - 1 - y);
+      const GLOBAL char *pcb = (const GLOBAL char *)pc;
+      uint32_t ro = 4u * (uint32_t)(y + ya) * (uint32_t)(W + 1);
+#pragma unroll 8
+      for (int dy = ya; dy <= yb; ++dy, ro += 4u * (uint32_t)(W + 1)) {
+        const int w = hw[dy + RT];
+        const int xl = max(0, x - w), xh = min(W - 1, x + w);
+        cells += xh - xl + 1;
+        const int d = (int)(*(const GLOBAL uint32_t *)(pcb + ro + 4u * (uint32_t)(xh + 1)) -
+                            *(const GLOBAL uint32_t *)(pcb + ro + 4u * (uint32_t)xl));
+        cnt += d & 0xFFF;
+        sum += d >> 12;
+      }
+      const double need = ceil((double)frac * (double)cells);
+      if (cnt > 0 && (double)cnt >= need) {
+        grw(P.ob[dst])[k] = (int16_t)round_half_even(sum, cnt);
+        grw(P.mb[dst])[k] = 2;
+      }
+    }
+    return;
+  }
   if (R <= DISK_R32) {
     // every sum fits 32 bits: (2R+1)^2 cells of |o| <= 4096 stay below 2^31
     for (int i = threadIdx.x; i < nh; i += PIX_T) {
@@ -1883,8 +1921,10 @@ hipError_t post_fill(const PostLaunch &L, int radial_r, int min_lines, int disk_
                      int src, int tmp, int dst) {
   const int nrow = rowblocks(L);
   LAUNCH(fill_scan_kernel, dim3(nrow + vscanblocks(L), 1, L.npairs), dim3(256), radial_r, src, nrow);
-  LAUNCH(fill_radial_kernel, dim3(L.maxH, 1, L.npairs), dim3(256), min_lines, src, tmp);
-  LAUNCH(fill_disk_kernel, pixgrid(L), dim3(PIX_T), disk_r, frac, tmp, dst);
+  // packed row prefixes when every pair of the launch allows them
+  const int packed = disk_r <= DISK_RPK && L.maxW < 4096 ? 1 : 0;
+  LAUNCH(fill_radial_kernel, dim3(L.maxH, 1, L.npairs), dim3(256), min_lines, src, tmp, packed);
+  LAUNCH(fill_disk_kernel, pixgrid(L), dim3(PIX_T), disk_r, frac, tmp, dst, packed);
   return hipGetLastError();
 }
 

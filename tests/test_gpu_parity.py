@@ -195,19 +195,42 @@ def test_outlier_and_fill_stages(B, orc, H, W):
 
 
 def test_fill_disk_radius_paths(B, orc):
-    """Disk radii up to 256 sum in 32 bits, larger ones in 64: both paths on
-    the same holes."""
+    """Disk radii up to 63 in rows narrower than 4096 take packed row prefixes
+    (count and sum modulo 2^20 in one word), up to 256 they sum in 32 bits,
+    larger ones in 64: every path on the same holes, and the packed path's
+    neighbours on either side of its radius limit."""
     L, R = _pair(60, 320, 31, 43)
     ref = orc.match(L, R, 0, 31, 7)
     m = orc.lr_check(ref["oL"], ref["mL"], ref["oR"], ref["mR"], 1)
     o = ref["oL"]
     m2 = orc.radial_outlier(o, m, 10, 2.5)
     # fractions near the valid share of the disks leave some holes unfilled
-    for args in ((0, 2, 256, 0.8), (0, 2, 257, 0.8), (0, 2, 300, 0.81), (0, 2, 256, 0.81)):
+    for args in ((0, 2, 20, 0.25), (0, 2, 20, 0.8), (0, 2, 63, 0.8), (0, 2, 64, 0.8),
+                 (0, 2, 256, 0.8), (0, 2, 257, 0.8), (0, 2, 300, 0.81), (0, 2, 256, 0.81)):
         go, gm = B.st_fill(cu(o.astype(np.int16)), cu(m2), *args)
         ro, rm = orc.fill(o, m2, *args)
         assert np.array_equal(np_(gm), rm), f"fill mask {args}"
         assert np.array_equal(np_(go)[rm > 0], ro[rm > 0]), f"fill values {args}"
+
+
+def test_fill_disk_packed_extremes(B, orc):
+    """The packed row prefixes at their limits: disparities of +-4096 over a
+    radius-63 disk (a row segment sum near 2^19 in magnitude), a row of 4095
+    pixels (row counts up to 4095 in the 12-bit field) and one of 4096, which
+    takes the unpacked prefixes."""
+    r = np.random.default_rng(77)
+    # (shape, disparity range, valid share): 99 % valid at +-4090..4096 puts
+    # row segments of ~126 valid cells, sums of ~5.2e5 < 2^19, next to holes
+    for H, W, lo, hi, pv in ((140, 300, 4000, 4097, 0.4), (140, 300, -4096, -3999, 0.4),
+                             (140, 300, 4090, 4097, 0.99), (140, 300, -4096, -4089, 0.99),
+                             (40, 4095, -4096, 4097, 0.4), (40, 4096, -4096, 4097, 0.4)):
+        o = r.integers(lo, hi, size=(H, W)).astype(np.int16)
+        m = (r.random((H, W)) < pv).astype(np.uint8)
+        for args in ((0, 2, 63, 0.05), (0, 2, 20, 0.25)):
+            go, gm = B.st_fill(cu(o), cu(m), *args)
+            ro, rm = orc.fill(o.astype(np.int32), m, *args)
+            assert np.array_equal(np_(gm), rm), f"fill mask {H}x{W} {args}"
+            assert np.array_equal(np_(go)[rm > 0], ro[rm > 0]), f"fill values {H}x{W} {args}"
 
 
 @pytest.mark.parametrize("R,K", [(2, 1), (15, 3), (4, 2), (0, 1), (3, 0), (96, 2), (100, 2)])
