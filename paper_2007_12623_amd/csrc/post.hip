@@ -50,6 +50,39 @@ __device__ __forceinline__ void for_pixels_ls(const PostPair &P, const BlockPos 
   }
 }
 
+// Four consecutive pixels per thread (PIX_SEG = 4 PIX_T columns per block),
+// for the kernels whose per-pixel work is a few loads and stores: when the
+// width is a multiple of 4 every quad starts 4-aligned in the flat planes and
+// lies inside its row, and, if the caller's planes are aligned for it
+// (`aligned`: a stage entry point may hand in any pointer), `quad` moves it
+// with one wide load or store per plane (a quarter of the address work of a
+// pixel per lane, which bounded these kernels); otherwise `one` takes the
+// pixels one by one.
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+template <class Q, class S>
+__device__ __forceinline__ void for_quads(const PostPair &P, const BlockPos &bp, bool aligned, Q quad,
+                                          S one) {
+  const int y = bp.y, W = P.W;
+  if (y >= P.H) return;
+  const int x = bp.x * PIX_SEG + 4 * (int)threadIdx.x;
+  if (x >= W) return;
+  const size_t k = (size_t)y * W + x;
+  if ((W & 3) == 0 && aligned) {
+    quad(k);
+  } else {
+    for (int i = 0; i < 4 && x + i < W; ++i) one(k + i);
+  }
+}
+template <class T>
+__device__ __forceinline__ T ldq(const void *p, size_t byte_off) {
+  return *(const GLOBAL T *)((const GLOBAL char *)p + byte_off);
+}
+template <class T>
+__device__ __forceinline__ void stq(void *p, size_t byte_off, T v) {
+  *(GLOBAL T *)((GLOBAL char *)p + byte_off) = v;
+}
+
 // floor(a / b) for b > 0.  With |a|, b < 2^52 (every case of the default
 // radii) a double estimate, off by at most one, is corrected with the exact
 // integer remainder, which avoids the long 64-bit integer division.
@@ -81,18 +114,35 @@ __device__ __forceinline__ long long round_half_even(long long num, long long de
 template <bool B>
 __global__ void decode_kernel(PostPair one, const PostPair *__restrict__ many) {
   PAIR;
-  const int W = P.W, H = P.H;
-  (void)W;
-  (void)H;
-  for_pixels_ls(
-      P, bp, [&](size_t k) { return make_uint2(P.keyL[k], P.keyR[k]); },
-      [&](size_t k, uint2 ab) {
-        // bit 31 marks a key with a valid candidate
-        const bool va = (int)ab.x < 0, vb = (int)ab.y < 0;
-        P.ob[0][k] = va ? (int16_t)(P.dmin + 255 - (int)(ab.x & 255u)) : O_NONE;
-        P.mb[0][k] = va ? 1 : 0;
-        P.oR[k] = vb ? (int16_t)(P.dmin + 255 - (int)(ab.y & 255u)) : O_NONE;
-        P.mR[k] = vb ? 1 : 0;
+  // bit 31 marks a key with a valid candidate
+  auto dis = [&](uint32_t key) -> uint32_t {
+    return (int)key < 0 ? (uint32_t)(uint16_t)(int16_t)(P.dmin + 255 - (int)(key & 255u)) : 0x8000u;
+  };
+  // quads: keys 16-byte, disparity maps 8-byte, masks 4-byte aligned
+  const bool al = (((uintptr_t)P.keyL | (uintptr_t)P.keyR) & 15) == 0 &&
+                  (((uintptr_t)P.ob[0] | (uintptr_t)P.oR) & 7) == 0 &&
+                  (((uintptr_t)P.mb[0] | (uintptr_t)P.mR) & 3) == 0;
+  for_quads(
+      P, bp, al,
+      [&](size_t k) {
+        const u32x4 a = ldq<u32x4>(P.keyL, 4 * k), b = ldq<u32x4>(P.keyR, 4 * k);
+        const u32x2 oa = {dis(a.x) | dis(a.y) << 16, dis(a.z) | dis(a.w) << 16};
+        const u32x2 ob = {dis(b.x) | dis(b.y) << 16, dis(b.z) | dis(b.w) << 16};
+        const uint32_t ma = (a.x >> 31) | (a.y >> 31) << 8 | (a.z >> 31) << 16 | (a.w >> 31) << 24;
+        const uint32_t mb = (b.x >> 31) | (b.y >> 31) << 8 | (b.z >> 31) << 16 | (b.w >> 31) << 24;
+        stq(P.ob[0], 2 * k, oa);
+        stq(P.mb[0], k, ma);
+        stq(P.oR, 2 * k, ob);
+        stq(P.mR, k, mb);
+        stq(P.keyL, 4 * k, u32x4{0u, 0u, 0u, 0u});
+        stq(P.keyR, 4 * k, u32x4{0u, 0u, 0u, 0u});
+      },
+      [&](size_t k) {
+        const uint32_t a = P.keyL[k], b = P.keyR[k];
+        P.ob[0][k] = (int16_t)dis(a);
+        P.mb[0][k] = (uint8_t)(a >> 31);
+        P.oR[k] = (int16_t)dis(b);
+        P.mR[k] = (uint8_t)(b >> 31);
         P.keyL[k] = 0;
         P.keyR[k] = 0;
       });
@@ -1034,17 +1084,36 @@ __global__ void outlier_combine_kernel(PostPair one, const PostPair *__restrict_
   (void)W;
   (void)H;
   const size_t N = (size_t)W * H;
-  for_pixels_ls(
-      P, bp,
+  const bool al = (((uintptr_t)P.mb[src] | (uintptr_t)P.mb[dst] | (uintptr_t)P.pass) & 3) == 0 &&
+                  (((uintptr_t)P.ob[src] | (uintptr_t)P.ob[dst]) & 7) == 0;
+  for_quads(
+      P, bp, al,
+      [&](size_t k) {
+        const uint32_t mk = ldq<uint32_t>(P.mb[src], k);
+        const uint32_t any = ldq<uint32_t>(P.pass, k) | ldq<uint32_t>(P.pass, N + k) |
+                             ldq<uint32_t>(P.pass, 2 * N + k) | ldq<uint32_t>(P.pass, 3 * N + k);
+        const u32x2 o = ldq<u32x2>(P.ob[src], 2 * k);
+        // per byte i: the mask code if the pixel stays (valid, some
+        // direction passes), else 0; its disparity, or O_NONE
+        uint32_t mo = 0, oo[2] = {0u, 0u};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const uint32_t m = (mk >> (8 * i)) & 255u;
+          const bool keep = m != 0 && ((any >> (8 * i)) & 255u) != 0;
+          mo |= (keep ? m : 0u) << (8 * i);
+          const uint32_t oi = ((i < 2 ? o.x : o.y) >> (16 * (i & 1))) & 0xFFFFu;
+          oo[i >> 1] |= (keep ? oi : 0x8000u) << (16 * (i & 1));
+        }
+        stq(P.ob[dst], 2 * k, u32x2{oo[0], oo[1]});
+        stq(P.mb[dst], k, mo);
+      },
       [&](size_t k) {
         const uint8_t mk = P.mb[src][k];
         const bool any = (P.pass[k] | P.pass[N + k] | P.pass[2 * N + k] | P.pass[3 * N + k]) != 0;
-        // (mask code if kept, 0 otherwise) and the disparity
-        return make_int2(mk && any ? (int)mk : 0, (int)P.ob[src][k]);
-      },
-      [&](size_t k, int2 v) {
-        P.ob[dst][k] = v.x ? (int16_t)v.y : O_NONE;
-        P.mb[dst][k] = (uint8_t)v.x;
+        const bool keep = mk && any;
+        const int16_t o = P.ob[src][k];
+        P.ob[dst][k] = keep ? o : O_NONE;
+        P.mb[dst][k] = keep ? mk : 0;
       });
 }
 

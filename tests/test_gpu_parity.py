@@ -170,6 +170,32 @@ def test_lr_check_stage(B, orc):
         assert np.array_equal(g, orc.lr_check(ref["oL"], ref["mL"], ref["oR"], ref["mR"], tol))
 
 
+def test_outlier_stage_unaligned_masks(B, orc):
+    """Mask buffers that start off a dword boundary (views one byte into a
+    larger buffer) at a width that is a multiple of 4: the per-pixel kernels
+    then take their pixels one by one instead of four per wide load, with
+    the same result."""
+    import torch
+    H, W = 64, 400
+    L, R = _pair(H, W, 31, 44)
+    ref = orc.match(L, R, 0, 31, 7)
+    m = orc.lr_check(ref["oL"], ref["mL"], ref["oR"], ref["mR"], 1)
+    o = cu(ref["oL"].astype(np.int16))
+    want = orc.radial_outlier(ref["oL"], m, 20, 2.5)
+    buf = torch.zeros(H * W + 1, dtype=torch.uint8, device="cuda")
+    m_in = buf[1:].view(H, W)
+    m_in.copy_(cu(m))
+    assert m_in.data_ptr() % 4 == 1
+    out = torch.zeros(H * W + 3, dtype=torch.uint8, device="cuda")
+    m_out = out[3:].view(H, W)
+    from paper_2007_12623_amd import binding
+    binding._check(binding.lib().st_radial_outlier(binding._h(None), o.data_ptr(), m_in.data_ptr(), H, W,
+                                                   20, 2.5, m_out.data_ptr(), binding._stream(None)))
+    torch.cuda.synchronize()
+    assert np.array_equal(np_(m_out), want)
+    assert np.array_equal(np_(B.st_radial_outlier(o, cu(m), 20, 2.5)), want)
+
+
 @pytest.mark.parametrize("H,W", [(140, 330), (300, 70), (23, 700), (19, 1100), (12, 2100), (7, 4200)])
 def test_outlier_and_fill_stages(B, orc, H, W):
     """Rows, columns and both diagonals cut into scan segments: shapes with
