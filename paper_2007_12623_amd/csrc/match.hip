@@ -471,15 +471,21 @@ __device__ __forceinline__ void wg_task(const MatchPair &P, int g, int cg, int r
   for (int i = tid; i < rows * 8 * kt.rp; i += NT) kt.rt[i] = 0u;
   __syncthreads();
 
-  // units: (chunk, colour) pairs, one colour unless the window is a chessboard
+  // units: (chunk, colour) pairs, one colour unless the window is a
+  // chessboard.  Items: the units in whole rounds of NWAVE over the band's
+  // rows, then those of an incomplete last round (one or two) cut into
+  // sub-bands, NWAVE / rem each, so that every wave has work there too
+  // (three keep whole rows: a quarter band costs its own restart)
   const int units = nc * (P.chess ? 2 : 1);
-  const int SB = units >= NWAVE ? 1 : NWAVE / units;
+  const int full = units / NWAVE * NWAVE, rem = units - full;
+  const int SB = rem == 0 ? 1 : NWAVE / rem;
   const int TYs = ceil_div(rows, SB);
-  const int items = units * SB;
+  const int items = full + rem * SB;
   for (int it = wave; it < items; it += NWAVE) {
-    const int u = it % units, sb = it / units;
+    const int r = it - full;
+    const int u = r < 0 ? it : full + r % rem, sb = r < 0 ? 0 : r / rem;
     const int c = cf + u % nc, par = u / nc;
-    const int ya = y0 + sb * TYs, yb = min(ya + TYs, y1);
+    const int ya = r < 0 ? y0 : y0 + sb * TYs, yb = r < 0 ? y1 : min(ya + TYs, y1);
     if (ya < yb) {
       const int d0 = P.dmin + min(c * DC, D - DC);
       // right segments start on a dword unless the chunk was shifted
