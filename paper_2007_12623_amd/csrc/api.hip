@@ -121,6 +121,8 @@ struct st_handle_s {
   // launches of a batch's window sizes after the first run beside it
   hipStream_t side_stream = nullptr;
   hipEvent_t fork_ev = nullptr, join_ev = nullptr, post_fork = nullptr;
+  // the window statistics of a batch beside its plane preparation
+  hipEvent_t prep_fork = nullptr, prep_join = nullptr;
   // capture streams of the post-processing of a batch's image sizes after
   // the first (created when a batch first needs them), their join events
   std::vector<hipStream_t> post_streams;
@@ -558,11 +560,15 @@ st_status st_create(st_handle *out, int device) {
       hipStreamCreateWithFlags(&h->side_stream, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&h->fork_ev, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&h->join_ev, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&h->post_fork, hipEventDisableTiming) != hipSuccess) {
+      hipEventCreateWithFlags(&h->post_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&h->prep_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&h->prep_join, hipEventDisableTiming) != hipSuccess) {
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
     if (h->side_stream) (void)hipStreamDestroy(h->side_stream);
     if (h->fork_ev) (void)hipEventDestroy(h->fork_ev);
     if (h->join_ev) (void)hipEventDestroy(h->join_ev);
+    if (h->post_fork) (void)hipEventDestroy(h->post_fork);
+    if (h->prep_fork) (void)hipEventDestroy(h->prep_fork);
     delete h;
     return fail(ST_EHIP, "cannot create the capture streams");
   }
@@ -598,6 +604,8 @@ void st_destroy(st_handle h) {
   if (h->fork_ev) (void)hipEventDestroy(h->fork_ev);
   if (h->join_ev) (void)hipEventDestroy(h->join_ev);
   if (h->post_fork) (void)hipEventDestroy(h->post_fork);
+  if (h->prep_fork) (void)hipEventDestroy(h->prep_fork);
+  if (h->prep_join) (void)hipEventDestroy(h->prep_join);
   for (hipStream_t ps : h->post_streams) (void)hipStreamDestroy(ps);
   for (hipEvent_t pe : h->post_done) (void)hipEventDestroy(pe);
   delete h;
@@ -1247,7 +1255,14 @@ st_status stereo_match_batched(st_handle h, const st_pair *pairs, int n_pairs,
   HIPCK(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
   hipError_t e = hipSuccess;
   auto ck = [&](hipError_t x) { if (x != hipSuccess && e == hipSuccess) e = x; };
-  ck(launch_prep(Pp[0], at<PrepPair>(B.tables.p, tP), n_pairs, maxH, maxCols, maxW, prec, cs));
+  // the window statistics on the side stream beside the plane preparation
+  // (disjoint parts of the planes), joined before the matcher
+  ck(hipEventRecord(h->prep_fork, cs));
+  ck(hipStreamWaitEvent(h->side_stream, h->prep_fork, 0));
+  ck(launch_prep(Pp[0], at<PrepPair>(B.tables.p, tP), n_pairs, maxH, maxCols, maxW, prec, cs,
+                 h->side_stream));
+  ck(hipEventRecord(h->prep_join, h->side_stream));
+  ck(hipStreamWaitEvent(cs, h->prep_join, 0));
   B.tM = at<MatchPair>(B.tables.p, tM);
   B.tT = at<int4>(B.tables.p, tT);
   B.tC = at<int>(B.tables.p, tC);

@@ -173,8 +173,11 @@ __device__ __forceinline__ BlockPos block_pos() {
 }
 
 // ---- host launchers (one per stage); all return hipGetLastError()
+// The padded planes on s, the window statistics on s_stats (s when null; the
+// two write disjoint parts of the planes and may run side by side).
 hipError_t launch_prep(const PrepPair &one, const PrepPair *many, int npairs, int maxH,
-                       int maxCols, int maxW, int prec, hipStream_t s);
+                       int maxCols, int maxW, int prec, hipStream_t s,
+                       hipStream_t s_stats = nullptr);
 hipError_t launch_match(const MatchPair &P, int prec, hipStream_t s);
 // One persistent matcher launch over the tasks of one window size and one
 // chunk width dc (4 or 8 disparities per lane); ev0/ev1 (may be null) are

@@ -295,7 +295,7 @@ __global__ __launch_bounds__(WS_T) void window_stats_kernel(PrepPair one, const 
 
 // ---------------------------------------------------------------- host launchers
 hipError_t launch_prep(const PrepPair &one, const PrepPair *many, int npairs, int maxH,
-                       int maxCols, int maxW, int prec, hipStream_t s) {
+                       int maxCols, int maxW, int prec, hipStream_t s, hipStream_t s_stats) {
   // one block per row (4 columns a thread) up to 4096 columns: a second,
   // mostly idle block per row costs more than the wider block
   const int nt = std::min(1024, (ceil_div(maxCols, 4) + WV - 1) / WV * WV);
@@ -310,7 +310,8 @@ hipError_t launch_prep(const PrepPair &one, const PrepPair *many, int npairs, in
   // the window shape is shared by every pair of a batch (one parameter set);
   // both images in one pass
   const dim3 gs(ceil_div(maxW, WS_NOUT), ceil_div(maxH, WS_SY), npairs);
-#define WS(b, ch) hipLaunchKernelGGL((window_stats_kernel<b, ch, 2>), gs, dim3(WS_T), 0, s, one, many, 0)
+  hipStream_t ss = s_stats ? s_stats : s;
+#define WS(b, ch) hipLaunchKernelGGL((window_stats_kernel<b, ch, 2>), gs, dim3(WS_T), 0, ss, one, many, 0)
   if (many) {
     if (one.chess) WS(true, true); else WS(true, false);
   } else {
