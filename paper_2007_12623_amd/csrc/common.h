@@ -138,6 +138,7 @@ struct RefineArgs {
   const float *d;
   const uint8_t *mask;
   int H, W, pitch, win;
+  int sy;           // rows per block of the fused passes (set by the launchers)
   double lambda;
   double *f;        // planes of H*W doubles
   double *partial;  // one double per block of the energy kernel

@@ -20,14 +20,18 @@ namespace st {
 enum { RF_A1 = 0, RF_A2, RF_A3, RF_A4, RF_NPLANES };
 
 // Both passes are fused box-sum kernels: a block of RT_T threads owns RT_T
-// consecutive columns (RT_T - 2h of them outputs) and RT_SY rows.  Each
+// consecutive columns (RT_T - 2h of them outputs) and A.sy rows.  Each
 // thread keeps the vertical window sums of its column in registers (the
 // entering row added, the leaving row removed, every input computed where
 // it is needed: R_w from d and the right image, or a plane read); per row
 // the block stores them in LDS and every output thread adds the 2h + 1 of
 // its window.  Two LDS buffers alternate between rows, so one barrier per
 // row orders the stores of a row after the reads of the row before.
-constexpr int RT_T = 256, RT_SY = 32, RT_HMAX = 7;
+// Rows per block: 32, halved down to 1 while a launch has fewer than
+// RT_MINB blocks (a 960x540 pair: 2 rows, 1080 blocks).  The seed of 2h rows
+// per block is the price of the blocks that fill the chip: 68 blocks of 32
+// rows took 0.309 ms per refinement step at 960x540, 1080 of 2 rows 0.071.
+constexpr int RT_T = 256, RT_SY = 32, RT_HMAX = 7, RT_MINB = 1024;
 
 // R_w(x, y): the right row interpolated at u = x - d(x, y) clamped to
 // [0, W-1] (segment [floor(u), floor(u) + 1]: at an integer u the segment
@@ -69,7 +73,7 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
 __global__ __launch_bounds__(RT_T) void refine_fwd_kernel(RefineArgs A) {
   __shared__ double sv[2][6][RT_T];
   const int h = A.win / 2, W = A.W, H = A.H, nout = RT_T - 2 * h;
-  const int xo = blockIdx.x * nout, y0 = blockIdx.y * RT_SY;
+  const int xo = blockIdx.x * nout, y0 = blockIdx.y * A.sy;
   const int t = threadIdx.x, c = xo - h + t;
   const bool cin = c >= 0 && c < W;
   const size_t N = (size_t)W * H;
@@ -88,7 +92,7 @@ __global__ __launch_bounds__(RT_T) void refine_fwd_kernel(RefineArgs A) {
     acc[5] += sg * (l * l);
   };
   for (int r = y0 - h; r < y0 + h; ++r) add_row(r, 1.0);
-  const int y1 = min(y0 + RT_SY, H);
+  const int y1 = min(y0 + A.sy, H);
   const bool out_col = t >= h && t < RT_T - h && c < W;
   double e = 0.0;
   for (int y = y0; y < y1; ++y) {  // the same rows for every thread
@@ -160,7 +164,7 @@ __global__ __launch_bounds__(RT_T) void refine_sum_kernel(const double *partial,
 __global__ __launch_bounds__(RT_T) void refine_bwd_kernel(RefineArgs A) {
   __shared__ double sv[2][4][RT_T];
   const int h = A.win / 2, W = A.W, H = A.H, nout = RT_T - 2 * h;
-  const int xo = blockIdx.x * nout, y0 = blockIdx.y * RT_SY;
+  const int xo = blockIdx.x * nout, y0 = blockIdx.y * A.sy;
   const int t = threadIdx.x, c = xo - h + t;
   const bool cin = c >= 0 && c < W;
   const size_t N = (size_t)W * H;
@@ -172,7 +176,7 @@ __global__ __launch_bounds__(RT_T) void refine_bwd_kernel(RefineArgs A) {
     for (int q = 0; q < 4; ++q) acc[q] += sg * A.f[q * N + k];
   };
   for (int r = y0 - h; r < y0 + h; ++r) add_row(r, 1.0);
-  const int y1 = min(y0 + RT_SY, H);
+  const int y1 = min(y0 + A.sy, H);
   const bool out_col = t >= h && t < RT_T - h && c < W;
   for (int y = y0; y < y1; ++y) {
     add_row(y + h, 1.0);
@@ -218,22 +222,29 @@ __global__ void refine_step_kernel(float *d, const float *g, const uint8_t *mask
   d[k] -= s;
 }
 
-static dim3 rgrid(const RefineArgs &A) {
-  return dim3(ceil_div(A.W, RT_T - 2 * (A.win / 2)), ceil_div(A.H, RT_SY));
+// The launch's rows per block (A.sy) and grid.
+static dim3 rgrid(RefineArgs &A) {
+  const int gx = ceil_div(A.W, RT_T - 2 * (A.win / 2));
+  A.sy = RT_SY;
+  while (A.sy > 1 && (long long)gx * ceil_div(A.H, A.sy) < RT_MINB) A.sy /= 2;
+  return dim3(gx, ceil_div(A.H, A.sy));
 }
 
 int refine_planes() { return RF_NPLANES; }
-// partials of the forward pass at the largest window (the most blocks)
-int refine_partials(int H, int W) { return ceil_div(W, RT_T - 2 * RT_HMAX) * ceil_div(H, RT_SY); }
+// partials of the forward pass: at most one block per row and column
+// segment of the largest window
+int refine_partials(int H, int W) { return ceil_div(W, RT_T - 2 * RT_HMAX) * H; }
 
-hipError_t launch_refine_forward(const RefineArgs &A, hipStream_t s) {
+hipError_t launch_refine_forward(const RefineArgs &A0, hipStream_t s) {
+  RefineArgs A = A0;
   const dim3 g = rgrid(A);
   hipLaunchKernelGGL(refine_fwd_kernel, g, dim3(RT_T), 0, s, A);
   hipLaunchKernelGGL(refine_sum_kernel, dim3(1), dim3(RT_T), 0, s, A.partial, (int)(g.x * g.y), A.E);
   return hipGetLastError();
 }
 
-hipError_t launch_refine_backward(const RefineArgs &A, hipStream_t s) {
+hipError_t launch_refine_backward(const RefineArgs &A0, hipStream_t s) {
+  RefineArgs A = A0;
   const dim3 g = rgrid(A);
   hipLaunchKernelGGL(refine_fwd_kernel, g, dim3(RT_T), 0, s, A);
   hipLaunchKernelGGL(refine_bwd_kernel, g, dim3(RT_T), 0, s, A);
