@@ -1570,6 +1570,7 @@ __device__ __forceinline__ void box_store(const PostPair &P, const BoxArgs &A, s
 // counts, so that the first smoothing pass needs no counts pass before it.
 constexpr int BX_T = 256, BX_RMAX = 96;
 constexpr int BX_SY = 32;  // rows per segment (64 measured slower: half the blocks)
+constexpr int BX_SYMIN = 4;  // one 960x540 pair: 4 rows (2 measured slower)
 template <bool B, bool CNT>
 __global__ __launch_bounds__(BX_T) void box2d_kernel(PostPair one, const PostPair *__restrict__ many,
                                                      BoxArgs A) {
@@ -2003,12 +2004,12 @@ hipError_t post_fill(const PostLaunch &L, int radial_r, int min_lines, int disk_
 // from F_TMP).
 static void box2d(const PostLaunch &L, BoxArgs A) {
   if (A.R <= BX_RMAX) {
-    // 32-row segments, shorter when that leaves fewer than about 1024
-    // blocks (a single pair): the seed of 2R rows per segment is the price
-    // of more blocks in flight
+    // 32-row segments, shorter (down to BX_SYMIN rows) when that leaves
+    // fewer than about 1024 blocks (a single pair): the seed of 2R rows per
+    // segment is the price of more blocks in flight
     const int nout = BX_T - 2 * A.R, nx = ceil_div(L.maxW, nout);
     A.sy = BX_SY;
-    while (A.sy > 8 && (long long)nx * ceil_div(L.maxH, A.sy) * L.npairs < 1024) A.sy /= 2;
+    while (A.sy > BX_SYMIN && (long long)nx * ceil_div(L.maxH, A.sy) * L.npairs < 1024) A.sy /= 2;
     const dim3 grid(nx, ceil_div(L.maxH, A.sy), L.npairs);
     if (A.counts) {
       LAUNCH_K((box2d_kernel<true, true>), (box2d_kernel<false, true>), grid, dim3(BX_T), A);

@@ -126,7 +126,7 @@ __global__ void prep_planes_kernel(PrepPair one, const PrepPair *many) {
 // NS = 2: both images of the pair in one pass (sides 0 and 1), so that the
 // two share every barrier.  A block of WS_T threads owns WS_T columns; each
 // thread keeps the vertical window sums of its column down a segment of
-// WS_SY rows and the horizontal sums are differences of a block prefix sum
+// sy rows and the horizontal sums are differences of a block prefix sum
 // (wave scans, then the wave totals before each wave added through LDS).
 // Two rows share each of the two barriers this takes.  Output columns of a
 // block are WS_T - 2 WS_HMAX wide for every window.
@@ -134,18 +134,26 @@ __global__ void prep_planes_kernel(PrepPair one, const PrepPair *many) {
 // x + y even and odd; a pixel takes the prefix sums of its own colour, since
 // the cells u + v even around (x, y) are exactly those of the colour of
 // (x, y).
+// sy: 16 rows, halved down to 4 while a launch has fewer than 1024 blocks
+// (one 960x540 pair: 4 rows, 544 blocks instead of 136).
 constexpr int WS_T = 256, WS_SY = 16, WS_HMAX = 7, WS_NOUT = WS_T - 2 * WS_HMAX;
+static dim3 ws_grid(int maxW, int maxH, int npairs, int &sy) {
+  const int gx = ceil_div(maxW, WS_NOUT);
+  sy = WS_SY;
+  while (sy > 4 && (long long)gx * ceil_div(maxH, sy) * npairs < 1024) sy /= 2;
+  return dim3(gx, ceil_div(maxH, sy), npairs);
+}
 
 template <bool B, bool CH, int NS>
 __global__ __launch_bounds__(WS_T) void window_stats_kernel(PrepPair one, const PrepPair *many,
-                                                            int side) {
+                                                            int side, int sy) {
   const BlockPos bp = block_pos();
   const PrepPair &P = B ? many[bp.pair] : one;
   constexpr int NV = CH ? 4 : 2;  // (S, SS) of each colour
   constexpr int NA = NS * NV;     // sums of a column: per image, per colour
   __shared__ int pf[2][NA][WS_T], wt[2][NA][WS_T / 64];
   const int H = P.H, W = P.W, win = P.win, h = win / 2;
-  const int xo = bp.x * WS_NOUT, y0 = bp.y * WS_SY;
+  const int xo = bp.x * WS_NOUT, y0 = bp.y * sy;
   if (xo >= W || y0 >= H) return;  // uniform per block
   // the images of the pass and their sides
   const GLOBAL uint8_t *img[NS];
@@ -196,7 +204,7 @@ __global__ __launch_bounds__(WS_T) void window_stats_kernel(PrepPair one, const 
   };
   for (int r = y0 - h; r < y0 + h; ++r) step_v(r, 1, px(r));
   const bool out_col = c >= xo && c < xo + WS_NOUT && c < W;  // then h <= t < WS_T - h
-  const int y1 = min(y0 + WS_SY, H);
+  const int y1 = min(y0 + sy, H);
   const int n = CH ? (win * win + 1) / 2 : win * win;
   const int lane = t & 63, wave = t >> 6;
   // the window sums of row y (add row y + h, then drop row y - h for the
@@ -309,9 +317,10 @@ hipError_t launch_prep(const PrepPair &one, const PrepPair *many, int npairs, in
 #undef PP
   // the window shape is shared by every pair of a batch (one parameter set);
   // both images in one pass
-  const dim3 gs(ceil_div(maxW, WS_NOUT), ceil_div(maxH, WS_SY), npairs);
+  int sy;
+  const dim3 gs = ws_grid(maxW, maxH, npairs, sy);
   hipStream_t ss = s_stats ? s_stats : s;
-#define WS(b, ch) hipLaunchKernelGGL((window_stats_kernel<b, ch, 2>), gs, dim3(WS_T), 0, ss, one, many, 0)
+#define WS(b, ch) hipLaunchKernelGGL((window_stats_kernel<b, ch, 2>), gs, dim3(WS_T), 0, ss, one, many, 0, sy)
   if (many) {
     if (one.chess) WS(true, true); else WS(true, false);
   } else {
@@ -333,11 +342,12 @@ hipError_t launch_window_stats_dense(const uint8_t *img, int H, int W, int pitch
   P.SL = S;
   P.SSL = SS;
   P.invLd = inv;
-  const dim3 gs(ceil_div(W, WS_NOUT), ceil_div(H, WS_SY), 1);
+  int sy;
+  const dim3 gs = ws_grid(W, H, 1, sy);
   if (chess)
-    hipLaunchKernelGGL((window_stats_kernel<false, true, 1>), gs, dim3(WS_T), 0, s, P, (const PrepPair *)nullptr, 2);
+    hipLaunchKernelGGL((window_stats_kernel<false, true, 1>), gs, dim3(WS_T), 0, s, P, (const PrepPair *)nullptr, 2, sy);
   else
-    hipLaunchKernelGGL((window_stats_kernel<false, false, 1>), gs, dim3(WS_T), 0, s, P, (const PrepPair *)nullptr, 2);
+    hipLaunchKernelGGL((window_stats_kernel<false, false, 1>), gs, dim3(WS_T), 0, s, P, (const PrepPair *)nullptr, 2, sy);
   return hipGetLastError();
 }
 
