@@ -862,16 +862,20 @@ __device__ __forceinline__ VLine vline(int t, int l, int H, int W) {
 // W + SEG - 1 threads (W for columns), and its range of thread indices is
 // rounded up to whole waves, so that the lanes of a wave share one line type
 // and with it the step between a line's pixels in the plane.
-__host__ __device__ inline int vscan_slots(int t, int W) { return t == 1 ? W : W + SEG - 1; }
+// SG: rows per segment (SEG, or SEG / 2 for launches with few blocks).
+template <int SG>
+__host__ __device__ inline int vscan_slots(int t, int W) { return t == 1 ? W : W + SG - 1; }
+template <int SG>
 __host__ __device__ inline int vscan_span(int t, int H, int W) {
-  return (ceil_div(H, SEG) * vscan_slots(t, W) + WV - 1) / WV * WV;
+  return (ceil_div(H, SG) * vscan_slots<SG>(t, W) + WV - 1) / WV * WV;
 }
+template <int SG>
 __device__ __forceinline__ bool vscan_task(int idx, int H, int W, int &t, int &l, int &sg) {
-  const int ns = ceil_div(H, SEG);
+  const int ns = ceil_div(H, SG);
   for (t = 1; t < 4; ++t) {
-    const int span = vscan_span(t, H, W);
+    const int span = vscan_span<SG>(t, H, W);
     if (idx < span) {
-      const int nper = vscan_slots(t, W);
+      const int nper = vscan_slots<SG>(t, W);
       sg = idx / nper;
       if (sg >= ns) return false;  // rounding to whole waves
       const int i = idx - sg * nper;
@@ -879,7 +883,7 @@ __device__ __forceinline__ bool vscan_task(int idx, int H, int W, int &t, int &l
         l = i;
         return true;
       }
-      const int a0 = sg * SEG, a1 = min(H, a0 + SEG);
+      const int a0 = sg * SG, a1 = min(H, a0 + SG);
       if (i >= W + (a1 - a0) - 1) return false;  // a short last segment
       // the first line through the segment: through (0, a1 - 1) for the
       // diagonals, through (0, a0) for the anti-diagonals
@@ -930,12 +934,14 @@ __device__ __forceinline__ void line_walk(const GLOBAL int16_t *o, int k0, int k
 // Each scan first runs through the look-ahead rows (state only), then through
 // its own rows, writing results only where a later kernel reads them: pass
 // for valid pixels, hits for holes.
+template <int SG>
 __device__ __forceinline__ void outlier_vscan(const PostPair &P, int bx, int r, float thresh, int src) {
+  static_assert(SG <= 32, "the forward results of a segment wait in a 32-bit mask");
   const int H = P.H, W = P.W;
   int t, l, sg;
-  if (!vscan_task(bx * blockDim.x + threadIdx.x, H, W, t, l, sg)) return;
+  if (!vscan_task<SG>(bx * blockDim.x + threadIdx.x, H, W, t, l, sg)) return;
   const VLine L = vline(t, l, H, W);
-  const int a = max(L.ylo, sg * SEG), b = min(L.yhi, sg * SEG + SEG);
+  const int a = max(L.ylo, sg * SG), b = min(L.yhi, sg * SG + SG);
   if (a >= b) return;
   const GLOBAL int16_t *__restrict__ o = gro(P.ob[src]);  // O_NONE where invalid
   // pass byte of flat index k of this line type: the four planes hold at
@@ -1013,12 +1019,13 @@ __device__ __forceinline__ int first_valid(const GLOBAL int16_t *o, int k0, int 
   return -1;
 }
 
+template <int SG>
 __device__ __forceinline__ void fill_vscan(const PostPair &P, int bx, int R, int src) {
   const int H = P.H, W = P.W;
   int t, l, sg;
-  if (!vscan_task(bx * blockDim.x + threadIdx.x, H, W, t, l, sg)) return;
+  if (!vscan_task<SG>(bx * blockDim.x + threadIdx.x, H, W, t, l, sg)) return;
   const VLine L = vline(t, l, H, W);
-  const int a = max(L.ylo, sg * SEG), b = min(L.yhi, sg * SEG + SEG);
+  const int a = max(L.ylo, sg * SG), b = min(L.yhi, sg * SG + SG);
   if (a >= b) return;
   const GLOBAL int16_t *__restrict__ o = gro(P.ob[src]);  // O_NONE where invalid
   const size_t N = (size_t)W * H;
@@ -1057,7 +1064,7 @@ __device__ __forceinline__ void fill_vscan(const PostPair &P, int bx, int R, int
 // The four line types of a scan in one launch: the first nrow blocks of a
 // pair take rows (a wave per row), the others columns and diagonals; the
 // two kinds of work are independent and overlap on the GPU.
-template <bool B>
+template <bool B, int SG>
 __global__ __launch_bounds__(256) void outlier_scan_kernel(PostPair one, const PostPair *__restrict__ many,
                                                           int r, float thresh, int src, int nrow) {
   PAIR;
@@ -1065,15 +1072,15 @@ __global__ __launch_bounds__(256) void outlier_scan_kernel(PostPair one, const P
     if (r <= 63) outlier_rows_bits(P, bp.x, r, step_bound(thresh), src);
     else outlier_rows(P, bp.x, r, thresh, src);
   } else {
-    outlier_vscan(P, bp.x - nrow, r, thresh, src);
+    outlier_vscan<SG>(P, bp.x - nrow, r, thresh, src);
   }
 }
-template <bool B>
+template <bool B, int SG>
 __global__ __launch_bounds__(256) void fill_scan_kernel(PostPair one, const PostPair *__restrict__ many,
                                                        int R, int src, int nrow) {
   PAIR;
   if (bp.x < nrow) fill_rows(P, bp.x, R, src);
-  else fill_vscan(P, bp.x - nrow, R, src);
+  else fill_vscan<SG>(P, bp.x - nrow, R, src);
 }
 
 // A valid pixel stays when some direction passes (Section II-B).
@@ -1974,15 +1981,27 @@ hipError_t post_lr(const PostLaunch &L, int tol, int dst) {
 }
 // blocks of the row scans (4 rows each) and of the column / diagonal scans
 static int rowblocks(const PostLaunch &L) { return ceil_div(L.maxH, 4); }
+template <int SG>
 static int vscanblocks(const PostLaunch &L) {
   int n = 0;
-  for (int t = 1; t < 4; ++t) n += vscan_span(t, L.maxH, L.maxW);
+  for (int t = 1; t < 4; ++t) n += vscan_span<SG>(t, L.maxH, L.maxW);
   return ceil_div(n, 256);
+}
+// Segments of SEG rows, or SEG / 2 when a launch would have fewer than 1024
+// blocks (a single pair): the shorter segments' longer relative look-ahead
+// costs less than the idle CUs.
+static bool short_segments(const PostLaunch &L) {
+  return (long long)(rowblocks(L) + vscanblocks<SEG>(L)) * L.npairs < 1024;
 }
 
 hipError_t post_outlier(const PostLaunch &L, int r, float thresh, int src, int dst) {
   const int nrow = rowblocks(L);
-  LAUNCH(outlier_scan_kernel, dim3(nrow + vscanblocks(L), 1, L.npairs), dim3(256), r, thresh, src, nrow);
+  if (short_segments(L))
+    LAUNCH_K((outlier_scan_kernel<true, SEG / 2>), (outlier_scan_kernel<false, SEG / 2>),
+             dim3(nrow + vscanblocks<SEG / 2>(L), 1, L.npairs), dim3(256), r, thresh, src, nrow);
+  else
+    LAUNCH_K((outlier_scan_kernel<true, SEG>), (outlier_scan_kernel<false, SEG>),
+             dim3(nrow + vscanblocks<SEG>(L), 1, L.npairs), dim3(256), r, thresh, src, nrow);
   LAUNCH(outlier_combine_kernel, pixgrid(L), dim3(PIX_T), src, dst);
   return hipGetLastError();
 }
@@ -1990,7 +2009,12 @@ hipError_t post_outlier(const PostLaunch &L, int r, float thresh, int src, int d
 hipError_t post_fill(const PostLaunch &L, int radial_r, int min_lines, int disk_r, float frac,
                      int src, int tmp, int dst) {
   const int nrow = rowblocks(L);
-  LAUNCH(fill_scan_kernel, dim3(nrow + vscanblocks(L), 1, L.npairs), dim3(256), radial_r, src, nrow);
+  if (short_segments(L))
+    LAUNCH_K((fill_scan_kernel<true, SEG / 2>), (fill_scan_kernel<false, SEG / 2>),
+             dim3(nrow + vscanblocks<SEG / 2>(L), 1, L.npairs), dim3(256), radial_r, src, nrow);
+  else
+    LAUNCH_K((fill_scan_kernel<true, SEG>), (fill_scan_kernel<false, SEG>),
+             dim3(nrow + vscanblocks<SEG>(L), 1, L.npairs), dim3(256), radial_r, src, nrow);
   // packed row prefixes when every pair of the launch allows them
   const int packed = disk_r <= DISK_RPK && L.maxW < 4096 ? 1 : 0;
   LAUNCH(fill_radial_kernel, dim3(L.maxH, 1, L.npairs), dim3(256), min_lines, src, tmp, packed);
