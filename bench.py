@@ -376,6 +376,16 @@ def extras(B, torch, synth, pairs, h, want_c5_debug):
     res["uneven64_matcher_ms"] = round(ms_m, 3)
     res["uneven64_matcher_gevals"] = round(bev / ms_m / 1e6, 2)
     res["uneven64_matcher_frac"] = round(bev * OPS_PER_EVAL / (ms_m / 1e3) / 1e12 / VALU_PEAK_TOPS, 4)
+    # the same batch with the matcher tiling the batched autotuner picks for
+    # this layout (every variant timed on the batch itself, per window size)
+    B.st_autotune_batched(bp, params, reps=3, handle=h)
+    res["uneven64_tuned_variants"] = {str(w): B.st_variant_name(B.st_batch_variant(w, handle=h))
+                                      for w in sorted({q["win"] for q in batch})}
+    med, q1, q3 = _time(lambda: B.stereo_match_batched(bp, params, handle=h), torch, 10)
+    res["uneven64_tuned_ms_per_batch"] = round(med, 3)
+    ms_m = B.stereo_time_matcher(bp, params, reps=5, handle=h)
+    res["uneven64_tuned_matcher_ms"] = round(ms_m, 3)
+    res["uneven64_tuned_matcher_frac"] = round(bev * OPS_PER_EVAL / (ms_m / 1e3) / 1e12 / VALU_PEAK_TOPS, 4)
     del bp
     # the Eq. (4) re-search inside the smoothing (K = 3, radius 15)
     pr = B.preset("full", research=1)
