@@ -26,30 +26,6 @@ __device__ __forceinline__ void for_pixels(const PostPair &P, const BlockPos &bp
   for (int x = bp.x * PIX_SEG + threadIdx.x; x < x1; x += PIX_T) f(x, y, (size_t)y * P.W + x);
 }
 
-// The same with a thread's pixels loaded (ld) before any is finished (st):
-// the loads of one pixel would otherwise wait behind the stores of the
-// previous one, which the compiler may not move them past, and a thread
-// would wait for one memory round trip per pixel.
-template <class LD, class ST>
-__device__ __forceinline__ void for_pixels_ls(const PostPair &P, const BlockPos &bp, LD ld, ST st) {
-  constexpr int NP = PIX_SEG / PIX_T;
-  const int y = bp.y;
-  if (y >= P.H) return;
-  const int xb = bp.x * PIX_SEG + (int)threadIdx.x, x1 = min(P.W, (bp.x + 1) * PIX_SEG);
-  using T = decltype(ld((size_t)0));
-  T v[NP];
-#pragma unroll
-  for (int i = 0; i < NP; ++i) {
-    const int x = xb + i * PIX_T;
-    if (x < x1) v[i] = ld((size_t)y * P.W + x);
-  }
-#pragma unroll
-  for (int i = 0; i < NP; ++i) {
-    const int x = xb + i * PIX_T;
-    if (x < x1) st((size_t)y * P.W + x, v[i]);
-  }
-}
-
 // Four consecutive pixels per thread (PIX_SEG = 4 PIX_T columns per block),
 // for the kernels whose per-pixel work is a few loads and stores: when the
 // width is a multiple of 4 every quad starts 4-aligned in the flat planes and
@@ -604,7 +580,8 @@ __global__ __launch_bounds__(SPB_T) void subpixel_lr_kernel(PostPair one, const 
 // right to left, lanes are columns, ballot masks give the breaks or valid
 // pixels of a block, and the position of the nearest one so far is carried
 // from block to block; each pixel is read once per sweep.  Columns and
-// diagonals: a thread scans SEG rows of one line (plus the look-ahead) and
+// diagonals: a thread scans SEG rows of one line (SEG / 2 in launches of
+// few blocks; plus the look-ahead) and
 // the lanes of a wave are neighbouring lines, so each step reads
 // consecutive columns of one row.
 constexpr int SEG = 32;
