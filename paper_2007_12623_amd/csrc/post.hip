@@ -152,8 +152,6 @@ __global__ void mark_invalid_kernel(const int16_t *__restrict__ o, const uint8_t
 // are R(., x0 - omax - 1 - h + c), omax the largest disparity of the block.
 constexpr int SP_TX = 128, SP_MAXWIN = 15;
 constexpr int SPB_T = 256, SPB_TY = 8, SP_NPT = SPB_TY * SP_TX / SPB_T;
-// row-major LDS rows of the Eq. (4) re-search
-constexpr int SP_LROW = SP_TX + 24, SP_RROW = SP_TX + 256 + 32;
 
 __host__ __device__ inline int sp_groups(int win) { return (win + 3) / 4; }
 __host__ __device__ inline int sp_quads_l(int win) { return (SP_TX + win - 1 + 3) / 4; }
@@ -162,41 +160,6 @@ __host__ __device__ inline int sp_quads_r(int win, int range) { return (SP_TX + 
 static size_t sp_lds_bytes(int maxWin, int maxD) {
   const size_t S = 4 * (size_t)(sp_quads_l(maxWin) + sp_quads_r(maxWin, maxD - 1));
   return (size_t)(SPB_TY + 4 * (sp_groups(maxWin) - 1)) * S * 4;
-}
-
-// Copy the bytes [off, off + len) of the image buffer base[0, span) (byte
-// offsets relative to base; off may be negative) to an LDS row as whole
-// dwords starting at the dword-aligned address at or below base + off, one
-// dword per thread (len + 3 < 4 * SP_TX); the byte offset of base + off in
-// the LDS row is (base + off) & 3.  The range of dwords wholly inside the
-// buffer is worked out once per row (uniform); the at most two dwords that
-// straddle its ends are assembled byte by byte; bytes outside come out 0.
-__device__ __forceinline__ void stage_row(uint8_t *dst, const GLOBAL uint8_t *base, long long off,
-                                          int len, long long span, int tid) {
-  const int mis = (int)(((uintptr_t)base + (uintptr_t)off) & 3);
-  const long long a0 = off - mis;  // offset of dword 0
-  const int nd = (mis + len + 3) >> 2;
-  const int ilo = a0 >= 0 ? 0 : (int)((-a0 + 3) >> 2);
-  const int ihi = span - a0 >= 4 ? (int)min((span - a0) >> 2, (long long)nd) : 0;
-  if (tid >= nd) return;
-  const GLOBAL uint32_t *row = (const GLOBAL uint32_t *)(base + a0);
-  uint32_t v;
-  if (tid >= ilo && tid < ihi) {
-    v = row[(unsigned)tid];
-  } else {
-    v = 0;
-    const long long b = a0 + 4 * (long long)tid;
-    for (int j = 0; j < 4; ++j)
-      if (b + j >= 0 && b + j < span) v |= (uint32_t)base[b + j] << (8 * j);
-  }
-  ((uint32_t *)dst)[tid] = v;
-}
-
-// Byte mask of window row v for the chessboard window (cells u + v even,
-// counted from the window's corner, which has the parity of the centre):
-// bytes 0 and 2 of every dword in even rows, 1 and 3 in odd rows.
-__device__ __forceinline__ uint32_t chess_mask(int chess, int v) {
-  return chess ? ((v & 1) ? 0xFF00FF00u : 0x00FF00FFu) : 0xFFFFFFFFu;
 }
 
 // The dword-aligned dword at byte offset a of base[0, span) (base + a is
@@ -1749,123 +1712,171 @@ __global__ __launch_bounds__(256) void box_h_lds_kernel(PostPair one, const Post
 }
 
 // ---- Eq. (4): re-search of the discrete disparities around d.  A block
-// covers 128 pixels of a row and stages, as the sub-pixel kernel does, the
-// L window rows and the R columns of every candidate of the block; each
-// candidate's window sum is exact (v_dot4_u32_u8), z and the cost in FP64.
-template <int ND>
-__device__ __forceinline__ int sp_sum1(const uint8_t (*Ls)[SP_LROW], const uint8_t (*Rs)[SP_RROW],
-                                       const int *misL, const int *misR, int win, int chess, int tx,
-                                       int rs0) {
-  const uint32_t lmask = (win & 3) ? (1u << (8 * (win & 3))) - 1u : 0xFFFFFFFFu;
-  uint32_t acc = 0;
-  for (int v = 0; v < win; ++v) {
-    const uint32_t cm = chess_mask(chess, v);
-    const int lb = tx + misL[v], rs = rs0 + misR[v];
-    const uint32_t *lw = (const uint32_t *)&Ls[v][lb & ~3];
-    const uint32_t *rw = (const uint32_t *)&Rs[v][rs & ~3];
-    uint32_t lt[ND + 1], rt[ND + 1];
+// covers the sub-pixel kernel's band (SP_TX columns, SPB_TY rows) and builds
+// the same packed stage: the L columns of the band's windows and the R
+// columns from the block's largest candidate down to its smallest.  A lane
+// takes a pixel's candidates four at a time; each window sum is exact
+// (v_dot4_u32_u8 on aligned dwords), z and the cost in FP64, in ascending
+// candidate order so that the first of equal costs is kept.
+
+// Window sums of the candidates c0 .. c0 + 3 of a pixel whose window starts
+// at packed row r0 and L stage column tx; rs is the R stage column of window
+// column 0 at candidate c0 + 3 (candidate c0 + e at rs + 3 - e).  Reads
+// stage columns rs .. rs + WIN + 2 of the R part: in the row even where a
+// candidate past the pixel's last one reaches below column 0 (its sum is
+// not used).
+template <int WIN, bool CH>
+__device__ __forceinline__ void rs_sums4(const uint32_t *Pk, int S, int QL, int r0, int tx, int rs,
+                                         uint32_t (&acc)[4]) {
+  constexpr int NG = (WIN + 3) / 4, LAST = WIN - 4 * (NG - 1);
+  constexpr uint32_t lastmask = LAST == 4 ? 0xFFFFFFFFu : (1u << (8 * LAST)) - 1u;
 #pragma unroll
-    for (int i = 0; i <= ND; ++i) {
-      lt[i] = lw[i];
-      rt[i] = rw[i];
-    }
+  for (int e = 0; e < 4; ++e) acc[e] = 0;
 #pragma unroll
-    for (int i = 0; i < ND; ++i) {
-      uint32_t l = __builtin_amdgcn_alignbyte(lt[i + 1], lt[i], lb & 3) & cm;
-      if (i == ND - 1) l &= lmask;
-      acc = __builtin_amdgcn_udot4(l, __builtin_amdgcn_alignbyte(rt[i + 1], rt[i], rs & 3), acc, false);
+  for (int g = 0; g < NG; ++g) {
+    const uint32_t *lrow = Pk + (r0 + 4 * g) * S + tx;
+    const uint32_t *rrow = Pk + (r0 + 4 * g) * S + 4 * QL + rs;
+    uint32_t rv[WIN + 3];
+#pragma unroll
+    for (int u = 0; u < WIN + 3; ++u) rv[u] = rrow[u];
+#pragma unroll
+    for (int u = 0; u < WIN; ++u) {
+      uint32_t m = g == NG - 1 ? lastmask : 0xFFFFFFFFu;
+      if (CH) m &= (u & 1) ? 0xFF00FF00u : 0x00FF00FFu;
+      const uint32_t l = m == 0xFFFFFFFFu ? lrow[u] : lrow[u] & m;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc[e] = __builtin_amdgcn_udot4(l, rv[u + 3 - e], acc[e], false);
     }
+    asm volatile("" : "+v"(acc[0]), "+v"(acc[1]), "+v"(acc[2]), "+v"(acc[3]));
   }
-  return (int)acc;
 }
 
+// The re-searched disparity of pixel k (band row r0, L stage column tx):
+// the candidate c in [lo, hi] of least cost 1 / max(z, 1e-3) + eta (c - d)^2,
+// candidates whose right window has no variance skipped; o when none is left
+// or the left window has no variance.
+template <int WIN, bool CH>
+__device__ __forceinline__ int rs_best(const PostPair &P, const uint32_t *Pk, int S, int QL, int r0,
+                                       int tx, size_t k, int lo, int hi, double d, int cmax,
+                                       double eta, int o) {
+  const long long n = CH ? ((long long)WIN * WIN + 1) / 2 : (long long)WIN * WIN;
+  const long long sl = P.SL[k];
+  const long long varL = n * (long long)P.SSL[k] - sl * sl;
+  if (varL <= 0) return o;
+  double best = __builtin_inf();
+  int onew = o;
+  for (int c0 = lo; c0 <= hi; c0 += 4) {
+    uint32_t acc[4];
+    rs_sums4<WIN, CH>(Pk, S, QL, r0, tx, tx + cmax - (c0 + 3), acc);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int c = c0 + e;
+      if (c > hi) break;
+      const size_t kr = k - c;
+      const long long sr = P.SR[kr];
+      const long long varR = n * (long long)P.SSR[kr] - sr * sr;
+      if (varR <= 0) continue;
+      const double z = (double)(n * (long long)acc[e] - sl * sr) / sqrt((double)varL * (double)varR);
+      const double ec = (double)c - d;
+      const double cost = 1.0 / (z > 1e-3 ? z : 1e-3) + eta * ec * ec;
+      if (cost < best) {
+        best = cost;
+        onew = c;
+      }
+    }
+  }
+  return onew;
+}
+
+// Pk: the packed stage in dynamic LDS, sp_lds_bytes(win, dmax - dmin + 1)
+// bytes at least (the block's candidates lie in [dmin, dmax]).
 template <bool B>
-__global__ __launch_bounds__(SP_TX) void research_kernel(PostPair one, const PostPair *__restrict__ many,
+__global__ __launch_bounds__(SPB_T) void research_kernel(PostPair one, const PostPair *__restrict__ many,
                                                          int osrc, int msrc, int odst, int dplane,
                                                          int range, double eta) {
   PAIR;
-  __shared__ __align__(16) uint8_t Ls[SP_MAXWIN][SP_LROW];
-  __shared__ __align__(16) uint8_t Rs[SP_MAXWIN][SP_RROW];
-  __shared__ int s_cmin, s_cmax, misL[SP_MAXWIN], misR[SP_MAXWIN];
-  const int tx = threadIdx.x;
-  const int x0 = bp.x * SP_TX, y = bp.y;
-  if (x0 >= P.W || y >= P.H) return;  // uniform per block
+  uint32_t *Pk = sp_dyn;
+  __shared__ int s_cmin, s_cmax;
+  const int tid = threadIdx.x, tx = tid & (SP_TX - 1), ty = tid / SP_TX;
+  const int x0 = bp.x * SP_TX, y0 = bp.y * SPB_TY;
+  if (x0 >= P.W || y0 >= P.H) return;  // uniform per block
   const int W = P.W, H = P.H, win = P.win, h = win / 2;
   const int x = x0 + tx;
-  const size_t N = (size_t)W * H, k = (size_t)y * W + x;
-  // pixels whose own window is inside the image can have a defined candidate
-  const bool inside = x < W && x >= h && x <= W - 1 - h && y >= h && y <= H - 1 - h;
-  const uint8_t mk = x < W ? P.mb[msrc][k] : 0;
-  const double d = mk ? P.f[(size_t)dplane * N + k] : 0.0;
-  int lo = 0, hi = -1;
-  if (mk && inside) {
-    lo = max(max(P.dmin, (int)ceil(d - range)), x - (W - 1 - h));
-    hi = min(min(P.dmax, (int)floor(d + range)), x - h);
+  const size_t N = (size_t)W * H;
+  int lo[SP_NPT], hi[SP_NPT];
+  double dd[SP_NPT];
+  int cl = 1 << 30, chi = -(1 << 30);
+#pragma unroll
+  for (int j = 0; j < SP_NPT; ++j) {
+    const int y = y0 + ty + 2 * j;
+    const size_t k = (size_t)y * W + x;
+    // pixels whose own window is inside the image can have a defined
+    // candidate; a candidate's right window must be inside as well
+    const bool inside = x < W && y < H && x >= h && x <= W - 1 - h && y >= h && y <= H - 1 - h;
+    const uint8_t mk = inside ? P.mb[msrc][k] : 0;
+    dd[j] = mk ? P.f[(size_t)dplane * N + k] : 0.0;
+    lo[j] = 0;
+    hi[j] = -1;
+    if (mk) {
+      lo[j] = max(max(P.dmin, (int)ceil(dd[j] - range)), x - (W - 1 - h));
+      hi[j] = min(min(P.dmax, (int)floor(dd[j] + range)), x - h);
+    }
+    if (lo[j] <= hi[j]) {
+      cl = min(cl, lo[j]);
+      chi = max(chi, hi[j]);
+    }
   }
-  if (tx == 0) {
+  if (tid == 0) {
     s_cmin = 1 << 30;
     s_cmax = -(1 << 30);
   }
   __syncthreads();
-  if (lo <= hi) {
-    atomicMin(&s_cmin, lo);
-    atomicMax(&s_cmax, hi);
+  cl = wave_min(cl);
+  chi = wave_max(chi);
+  if ((tid & (WV - 1)) == 0 && cl <= chi) {
+    atomicMin(&s_cmin, cl);
+    atomicMax(&s_cmax, chi);
   }
   __syncthreads();
   const int cmin = s_cmin, cmax = s_cmax;
+  // stage column c of the R part is R(., x0 - cmax - h + c): window column u
+  // of candidate c at pixel x is column tx + cmax - c + u
+  const int QL = sp_quads_l(win), QR = cmin <= cmax ? sp_quads_r(win, cmax - cmin) : 0;
+  const int S = 4 * (QL + QR);
   if (cmin <= cmax) {
-    // Ls[r][misL[r] + c] = L(y-h+r, x0-h+c), Rs[r][misR[r] + c] = R(y-h+r, x0-cmax-h+c)
-    const int LW = SP_TX + 2 * h, RW = SP_TX + (cmax - cmin) + 2 * h;
-    const int lx0 = x0 - h, rx0 = x0 - cmax - h;
-    const GLOBAL uint8_t *Lg = gro(P.left), *Rg = gro(P.right);
-    const long long span = (long long)(H - 1) * P.pitch + W;
-#pragma unroll
-    for (int r = 0; r < SP_MAXWIN; ++r) {
-      if (r < win) {  // rows inside: the block has an inside pixel
-        const long long row = (long long)(y - h + r) * P.pitch;
-        stage_row(Ls[r], Lg, row + lx0, LW, span, tx);
-        stage_row(Rs[r], Rg, row + rx0, RW, span, tx);
-        if (tx == 0) {
-          misL[r] = (int)(((uintptr_t)Lg + (uintptr_t)(row + lx0)) & 3);
-          misR[r] = (int)(((uintptr_t)Rg + (uintptr_t)(row + rx0)) & 3);
-        }
-      }
-    }
+    const int PR = min(SPB_TY, H - y0) + 4 * (sp_groups(win) - 1);
+    sp_pack(Pk, S, PR, gro(P.left), gro(P.right), P.pitch, (long long)(H - 1) * P.pitch + W, y0 - h,
+            x0 - h, QL, x0 - cmax - h, QR, tid);
   }
   __syncthreads();
-  if (x >= W) return;
-  int onew = P.ob[osrc][k];
-  if (lo <= hi) {
-    const long long n = P.chess ? ((long long)win * win + 1) / 2 : (long long)win * win;
-    const long long sl = P.SL[k];
-    const long long varL = n * (long long)P.SSL[k] - sl * sl;
-    if (varL > 0) {
-      double best = __builtin_inf();
-      const int nd = (win + 3) >> 2;
-      for (int c = lo; c <= hi; ++c) {
-        const size_t kr = (size_t)y * W + (x - c);
-        const long long sr = P.SR[kr];
-        const long long varR = n * (long long)P.SSR[kr] - sr * sr;
-        if (varR <= 0) continue;
-        const int rs0 = tx + cmax - c;  // window column 0 of candidate c in Rs
-        int slr;
-        switch (nd) {
-          case 1: slr = sp_sum1<1>(Ls, Rs, misL, misR, win, P.chess, tx, rs0); break;
-          case 2: slr = sp_sum1<2>(Ls, Rs, misL, misR, win, P.chess, tx, rs0); break;
-          case 3: slr = sp_sum1<3>(Ls, Rs, misL, misR, win, P.chess, tx, rs0); break;
-          default: slr = sp_sum1<4>(Ls, Rs, misL, misR, win, P.chess, tx, rs0); break;
-        }
-        const double z = (double)(n * (long long)slr - sl * sr) / sqrt((double)varL * (double)varR);
-        const double e = (double)c - d;
-        const double cost = 1.0 / (z > 1e-3 ? z : 1e-3) + eta * e * e;
-        if (cost < best) {
-          best = cost;
-          onew = c;
-        }
+#pragma unroll
+  for (int j = 0; j < SP_NPT; ++j) {
+    const int r0 = ty + 2 * j, y = y0 + r0;
+    if (x >= W || y >= H) continue;
+    const size_t k = (size_t)y * W + x;
+    int onew = P.ob[osrc][k];
+    if (lo[j] <= hi[j]) {
+#define RSB(w)                                                                                    \
+  case w:                                                                                         \
+    onew = P.chess ? rs_best<w, true>(P, Pk, S, QL, r0, tx, k, lo[j], hi[j], dd[j], cmax, eta, onew) \
+                   : rs_best<w, false>(P, Pk, S, QL, r0, tx, k, lo[j], hi[j], dd[j], cmax, eta, onew); \
+    break
+      switch (win) {
+        RSB(3);
+        RSB(5);
+        RSB(7);
+        RSB(9);
+        RSB(11);
+        RSB(13);
+        default:
+          onew = P.chess ? rs_best<15, true>(P, Pk, S, QL, r0, tx, k, lo[j], hi[j], dd[j], cmax, eta, onew)
+                         : rs_best<15, false>(P, Pk, S, QL, r0, tx, k, lo[j], hi[j], dd[j], cmax, eta, onew);
+          break;
       }
+#undef RSB
     }
+    P.ob[odst][k] = (int16_t)onew;
   }
-  P.ob[odst][k] = (int16_t)onew;
 }
 
 // Output without smoothing (K = 0): s on valid pixels.
@@ -2037,10 +2048,20 @@ static void box2d(const PostLaunch &L, BoxArgs A) {
 
 // Improved Laplacian smoothing of (ob[src], delta, mb[src]) or s_in; writes
 // disparity (NaN where invalid) and valid_mask.
+static void launch_research(const PostLaunch &L, int osrc, int msrc, int odst, int dplane, int range,
+                            double eta) {
+  const dim3 grid(ceil_div(L.maxW, SP_TX), ceil_div(L.maxH, SPB_TY), L.npairs);
+  const size_t lds = sp_lds_bytes(L.maxWin, L.maxD);
+  if (L.many)
+    hipLaunchKernelGGL(research_kernel<true>, grid, dim3(SPB_T), lds, L.s, L.one, L.many, osrc, msrc,
+                       odst, dplane, range, eta);
+  else
+    hipLaunchKernelGGL(research_kernel<false>, grid, dim3(SPB_T), lds, L.s, L.one, L.many, osrc, msrc,
+                       odst, dplane, range, eta);
+}
 hipError_t post_research(const PostLaunch &L, int osrc, int msrc, int odst, int dplane, int range,
                          float eta) {
-  LAUNCH(research_kernel, dim3(ceil_div(L.maxW, SP_TX), L.maxH, L.npairs), dim3(SP_TX), osrc, msrc,
-         odst, dplane, range, (double)eta);
+  launch_research(L, osrc, msrc, odst, dplane, range, (double)eta);
   return hipGetLastError();
 }
 
@@ -2094,8 +2115,7 @@ hipError_t post_hc(const PostLaunch &L, int src, int R, int K, float alpha, int 
     LAUNCH(hc_b_kernel, pixgrid(L), dim3(PIX_T), src, (double)alpha, it == 0 ? 1 : 0);
     box2d(L, args(F_IN, F_IN, it == K - 1 ? 3 : 2));  // d = a - box(b m) / box(m)
     if (it < K - 1) {
-      LAUNCH(research_kernel, dim3(ceil_div(L.maxW, SP_TX), L.maxH, L.npairs), dim3(SP_TX), ocur,
-             src, oalt, (int)F_D, range, (double)eta);
+      launch_research(L, ocur, src, oalt, (int)F_D, range, (double)eta);
       if (trace && !L.many && it < trace->n) {
         const size_t N = (size_t)L.one.H * L.one.W;
         hipError_t e = hipMemcpyAsync(trace->o + it * N, L.one.ob[oalt], 2 * N,

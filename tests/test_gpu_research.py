@@ -17,37 +17,78 @@ def B():
     return binding
 
 
-def _cost(L, R, y, x, c, d, win, eta):
+def _cost(L, R, y, x, c, d, win, eta, chess=False):
     h = win // 2
-    a = L[y - h:y + h + 1, x - h:x + h + 1].astype(np.float64).ravel()
-    b = R[y - h:y + h + 1, x - c - h:x - c + h + 1].astype(np.float64).ravel()
-    z = np.corrcoef(a, b)[0, 1]
+    a = L[y - h:y + h + 1, x - h:x + h + 1].astype(np.float64)
+    b = R[y - h:y + h + 1, x - c - h:x - c + h + 1].astype(np.float64)
+    if chess:  # the cells of the window's corner parity
+        keep = (np.add.outer(np.arange(win), np.arange(win)) % 2) == 0
+        a, b = a[keep], b[keep]
+    z = np.corrcoef(a.ravel(), b.ravel())[0, 1]
     return 1.0 / max(z, 1e-3) + eta * (c - d) ** 2
 
 
-@pytest.mark.parametrize("win,rng_,eta", [(11, 5, 0.01), (7, 3, 0.05), (15, 8, 0.0)])
-def test_research_step_matches_oracle(B, orc, win, rng_, eta):
+# spread: d drawn over the whole range, so that a block's candidates span
+# most of it (the widest R stage)
+@pytest.mark.parametrize("win,rng_,eta,chess,spread", [
+    (11, 5, 0.01, False, False), (7, 3, 0.05, False, False), (15, 8, 0.0, False, False),
+    (11, 5, 0.01, True, False), (3, 1, 0.2, True, False), (13, 64, 0.02, False, True),
+    (9, 6, 0.01, True, True)])
+def test_research_step_matches_oracle(B, orc, win, rng_, eta, chess, spread):
     import torch
     p = synth.make_pair(90, 260, 47, 31 + win)
     L, R = p["left"], p["right"]
-    ref = orc.match(L, R, 0, 47, win)
+    ref = orc.match(L, R, 0, 47, win, chess=chess)
     o = ref["oL"].astype(np.int16)
     m = ref["mL"].copy()
     r = np.random.default_rng(win)
-    d = np.where(np.isnan(p["gt_left"]), o, p["gt_left"]) + r.uniform(-1.5, 1.5, size=L.shape)
+    if spread:
+        d = r.uniform(-3.0, 50.0, size=L.shape)
+    else:
+        d = np.where(np.isnan(p["gt_left"]), o, p["gt_left"]) + r.uniform(-1.5, 1.5, size=L.shape)
     m[r.random(L.shape) < 0.05] = 0
     g = np_(B.st_research(cu(L), cu(R), 0, 47, win, cu(o), cu(m),
-                          torch.tensor(d, dtype=torch.float64, device="cuda"), rng_, eta))
+                          torch.tensor(d, dtype=torch.float64, device="cuda"), rng_, eta,
+                          chess=chess))
     eta32 = float(np.float32(eta))  # the library takes eta as a float
-    want = orc.research(L, R, 0, 47, win, o.astype(np.int32), m, d, rng_, eta32)
+    want = orc.research(L, R, 0, 47, win, o.astype(np.int32), m, d, rng_, eta32, chess=chess)
     bad = np.argwhere(g != want)
     # only exact floating-point ties may differ
     for (y, x) in bad:
-        cg = _cost(L, R, y, x, int(g[y, x]), d[y, x], win, eta32)
-        cw = _cost(L, R, y, x, int(want[y, x]), d[y, x], win, eta32)
+        cg = _cost(L, R, y, x, int(g[y, x]), d[y, x], win, eta32, chess)
+        cw = _cost(L, R, y, x, int(want[y, x]), d[y, x], win, eta32, chess)
         assert abs(cg - cw) < 1e-9, (y, x, g[y, x], want[y, x], cg, cw)
     assert len(bad) <= 3
     assert np.array_equal(g[m == 0], o[m == 0])
+    assert (g != o).any()  # the step moved some pixels
+
+
+def test_research_step_pitched(B, orc):
+    """Rows at an odd pitch (every row at another byte alignment), a ragged
+    band and block at both ends."""
+    import torch
+    p = synth.make_pair(61, 203, 31, 5)
+    L, R = p["left"], p["right"]
+    ref = orc.match(L, R, 0, 31, 9)
+    o = ref["oL"].astype(np.int16)
+    m = ref["mL"].copy()
+    r = np.random.default_rng(3)
+    d = np.where(np.isnan(p["gt_left"]), o, p["gt_left"]) + r.uniform(-2.0, 2.0, size=L.shape)
+    pitch = 211
+    Lp = torch.zeros((61, pitch), dtype=torch.uint8, device="cuda")
+    Rp = torch.zeros((61, pitch), dtype=torch.uint8, device="cuda")
+    Lp[:, :203] = cu(L)
+    Rp[:, :203] = cu(R)
+    g = np_(B.st_research(Lp[:, :203], Rp[:, :203], 0, 31, 9, cu(o), cu(m),
+                          torch.tensor(d, dtype=torch.float64, device="cuda"), 4, 0.03))
+    eta32 = float(np.float32(0.03))
+    want = orc.research(L, R, 0, 31, 9, o.astype(np.int32), m, d, 4, eta32)
+    bad = np.argwhere(g != want)
+    for (y, x) in bad:
+        cg = _cost(L, R, y, x, int(g[y, x]), d[y, x], 9, eta32)
+        cw = _cost(L, R, y, x, int(want[y, x]), d[y, x], 9, eta32)
+        assert abs(cg - cw) < 1e-9, (y, x, g[y, x], want[y, x], cg, cw)
+    assert len(bad) <= 3
 
 
 @pytest.mark.parametrize("K", [3, 4])
