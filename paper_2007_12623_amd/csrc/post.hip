@@ -1341,8 +1341,8 @@ __global__ __launch_bounds__(PIX_T) void fill_disk_kernel(PostPair one, const Po
 }
 
 // ---------------------------------------------------------------- smoothing (FP64)
-// Planes of P.f: 0 s (re-search) / b_1 = a - s, 1 s*m / b, 2 box(m) (as
-// float), 3 column pass, 4 a = A(s), 5 d / b.
+// Planes of P.f: 0 b_1 = a - s, 1 b, 2 box(m) (as float), 3 column pass,
+// 4 a = A(s), 5 d / b.
 enum { F_S = 0, F_IN = 1, F_CNT = 2, F_TMP = 3, F_A = 4, F_D = 5 };
 
 // s = o + delta for matched pixels (code 1), o for filled ones (code 2), or
@@ -1373,25 +1373,6 @@ __device__ __forceinline__ double box_in(const PostPair &P, const BoxArgs &A, si
   const uint8_t mk = gro(P.mb[A.src])[k];
   if (A.in == BOX_IN_MASK) return mk ? 1.0 : 0.0;
   return mk ? hc_s_at(P, k, mk, A.osrc, A.use_delta) : 0.0;
-}
-
-// Research mode: plane F_S <- s on valid pixels (0 elsewhere), F_IN <- the
-// same, and with `counts` F_D <- the mask.
-template <bool B>
-__global__ void hc_init_kernel(PostPair one, const PostPair *__restrict__ many, int src, int osrc,
-                               int use_delta, int counts) {
-  PAIR;
-  const int W = P.W, H = P.H;
-  (void)W;
-  (void)H;
-  for_pixels(P, bp, [&](int x, int y, size_t k) {
-    const size_t N = (size_t)W * H;
-    const uint8_t mk = P.mb[src][k];
-    const double v = mk ? hc_s_at(P, k, mk, osrc, use_delta) : 0.0;
-    P.f[F_S * N + k] = v;
-    P.f[F_IN * N + k] = v;
-    if (counts) P.f[F_D * N + k] = mk ? 1.0 : 0.0;
-  });
 }
 
 // Box sums over a (2R+1) window along columns into plane F_TMP: a thread
@@ -1425,23 +1406,26 @@ __global__ void box_v_kernel(PostPair one, const PostPair *__restrict__ many, Bo
 // Output stage of a box pass with window sum v at pixel k: the counts of
 // valid pixels (mode 0: the box sum of the mask, stored as float - an exact
 // small integer - in plane F_CNT), or the masked mean steps fused into it:
-//   mode 1: a = box(s m)/box(m) (Eq. 1) -> F_A
 //   mode 2: d = a - box(b m)/box(m) (Eq. 3) -> F_D
 //   mode 3: the same d written as the final disparity (NaN where invalid)
 //           and mask
-//   mode 4: mode 1, and b_1 = a - alpha s - (1 - alpha) s (Eq. 2 of the
-//           first iteration, d_prev = s) -> plane out (F_S)
+//   mode 4: a = box(s m)/box(m) (Eq. 1) -> F_A, and b_1 = a - alpha s -
+//           (1 - alpha) s (Eq. 2 of the first iteration, d_prev = s) ->
+//           plane out
 //   mode 5: the next iteration's b = a - alpha s - (1 - alpha) d (Eq. 2)
 //           with d = a - box(b m)/box(m) (Eq. 3), formed as
 //           c + (1 - alpha) box(b m)/box(m) with c = alpha (a - s) =
 //           alpha b_1 (plane F_S) -> plane out
+//   mode 6: (re-search, where s changes between iterations) a -> F_A as in
+//           mode 4, and b = a - alpha s - (1 - alpha) d_prev (Eq. 2) with
+//           d_prev the previous iteration's d (plane F_D) -> plane out
 // (b and a are 0 on invalid pixels, as the masked sums need.)  The inputs
 // the stage reads are gathered first (box_store_in), so that a caller can
 // load them ahead of time.
 struct BoxStoreIn {
   uint8_t mk;
   float cnt;
-  double a, s;  // a; s (mode 4) or b_1 (mode 5)
+  double a, s;  // a (d_prev in mode 6); s (modes 4, 6) or b_1 (mode 5)
 };
 __device__ __forceinline__ BoxStoreIn box_store_in(const PostPair &P, const BoxArgs &A, size_t N,
                                                    size_t k) {
@@ -1455,7 +1439,8 @@ __device__ __forceinline__ BoxStoreIn box_store_in(const PostPair &P, const BoxA
   if (!A.counts) q.cnt = ((const GLOBAL float *)(gro(P.f) + (size_t)F_CNT * N))[k];
   if (A.mode == 2 || A.mode == 3) q.a = gro(P.f)[(size_t)F_A * N + k];
   if (A.mode == 5) q.s = gro(P.f)[(size_t)F_S * N + k];
-  if (A.mode == 4) {
+  if (A.mode == 6) q.a = gro(P.f)[(size_t)F_D * N + k];
+  if (A.mode == 4 || A.mode == 6) {
     // s without a branch on the mask: both loads issue at once
     if (P.s_in) {
       q.s = (double)gro(P.s_in)[k];
@@ -1475,14 +1460,14 @@ __device__ __forceinline__ void box_store(const PostPair &P, const BoxArgs &A, s
   }
   const uint8_t mk = q.mk;
   const double mean = v / (double)q.cnt;
-  if (A.mode == 1 || A.mode == 4) {
+  if (A.mode == 4 || A.mode == 6) {
     P.f[(size_t)F_A * N + k] = mk ? mean : 0.0;
-    if (A.mode == 4) {
-      // b_1 = a - alpha s - (1 - alpha) d_0 with d_0 = s; the later passes
-      // take c = alpha (a - s) = alpha b_1 from this plane
-      const double s = mk ? q.s : 0.0;
-      P.f[(size_t)A.out * N + k] = mk ? mean - A.alpha * s - (1.0 - A.alpha) * s : 0.0;
-    }
+    // b_1 = a - alpha s - (1 - alpha) d_0 with d_0 = s (the later passes of
+    // the plain path take c = alpha (a - s) = alpha b_1 from this plane), or
+    // b = a - alpha s - (1 - alpha) d_prev
+    const double s = mk ? q.s : 0.0;
+    const double dp = A.mode == 4 ? s : q.a;
+    P.f[(size_t)A.out * N + k] = mk ? mean - A.alpha * s - (1.0 - A.alpha) * dp : 0.0;
     return;
   }
   if (A.mode == 5) {
@@ -1895,21 +1880,6 @@ __global__ void hc_copy_kernel(PostPair one, const PostPair *__restrict__ many, 
 }
 
 
-// b = a - alpha*s - (1-alpha)*d_prev on valid pixels, 0 elsewhere (Eq. 2);
-// d_prev is s in the first iteration.
-template <bool B>
-__global__ void hc_b_kernel(PostPair one, const PostPair *__restrict__ many, int src, double alpha, int first) {
-  PAIR;
-  const int W = P.W, H = P.H;
-  (void)W;
-  (void)H;
-  for_pixels(P, bp, [&](int x, int y, size_t k) {
-    const size_t N = (size_t)W * H;
-    const double s = P.f[F_S * N + k];
-    const double dp = first ? s : P.f[F_D * N + k];
-    P.f[F_IN * N + k] = P.mb[src][k] ? P.f[F_A * N + k] - alpha * s - (1.0 - alpha) * dp : 0.0;
-  });
-}
 
 
 
@@ -2108,12 +2078,15 @@ hipError_t post_hc(const PostLaunch &L, int src, int R, int K, float alpha, int 
     }
     return hipGetLastError();
   }
-  box2d(L, args(BOX_IN_MASK, F_CNT, 0));  // counts of valid pixels
+  // per iteration two passes: a = box(o m) / box(m) from the current o (s
+  // formed on the fly) with b = a - alpha o - (1 - alpha) d_prev in its
+  // output stage (the first also boxes the mask for the counts), then
+  // d = a - box(b m) / box(m)
   for (int it = 0; it < K; ++it) {
-    LAUNCH(hc_init_kernel, pixgrid(L), dim3(PIX_T), src, ocur, use_delta, 0);
-    box2d(L, args(F_IN, F_IN, 1));  // a = box(o m) / box(m)
-    LAUNCH(hc_b_kernel, pixgrid(L), dim3(PIX_T), src, (double)alpha, it == 0 ? 1 : 0);
-    box2d(L, args(F_IN, F_IN, it == K - 1 ? 3 : 2));  // d = a - box(b m) / box(m)
+    BoxArgs ab = args(BOX_IN_S, F_IN, it == 0 ? 4 : 6);
+    ab.counts = it == 0 ? 1 : 0;
+    box2d(L, ab);
+    box2d(L, args(F_IN, F_IN, it == K - 1 ? 3 : 2));
     if (it < K - 1) {
       launch_research(L, ocur, src, oalt, (int)F_D, range, (double)eta);
       if (trace && !L.many && it < trace->n) {

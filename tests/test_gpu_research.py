@@ -91,9 +91,11 @@ def test_research_step_pitched(B, orc):
     assert len(bad) <= 3
 
 
-@pytest.mark.parametrize("K", [3, 4])
-def test_research_pipeline(B, orc, K):
-    """The whole path with Eqs. (1)-(4) (radius 15), checked iteration by
+@pytest.mark.parametrize("K,rad,shape", [(3, 15, (160, 400)), (4, 15, (160, 400)),
+                                         (3, 64, (120, 260))])
+def test_research_pipeline(B, orc, K, rad, shape):
+    """The whole path with Eqs. (1)-(4) (radius 15, and 64, the largest the
+    re-search mode takes), checked iteration by
     iteration on the GPU's own state: each smoothing step from the GPU's
     (o, d) must give the GPU's next d (FP64 on both sides), each re-search
     around that d the GPU's next o (a differing pixel only where both
@@ -101,11 +103,11 @@ def test_research_pipeline(B, orc, K):
     within the smoothing bar.  Before the loop, every stage is checked as
     in the plain pipeline."""
     import torch
-    p = synth.make_pair(160, 400, 63, 77)
+    p = synth.make_pair(shape[0], shape[1], 63, 77)
     L, R = p["left"], p["right"]
     Hh, Ww = L.shape
-    prm = B.preset("full", research=1, smooth_iters=K)
-    po = orc.params_c2(research=1, smooth_iters=K)
+    prm = B.preset("full", research=1, smooth_iters=K, smooth_radius=rad)
+    po = orc.params_c2(research=1, smooth_iters=K, smooth_radius=rad)
     h = B.Handle(0)
     try:
         g = e2e.run_debug(B, L, R, 0, 63, 11, prm, handle=h)
@@ -125,7 +127,7 @@ def test_research_pipeline(B, orc, K):
     o, d = g["o_post"], np.where(v, g["o_post"], 0).astype(np.float64)
     ties = 0
     for j in range(1, K + 1):
-        dref, _ = orc.hc_research(L, R, 0, 63, 11, o, m, 15, 1, alpha, eta, 5, d_init=d)
+        dref, _ = orc.hc_research(L, R, 0, 63, 11, o, m, rad, 1, alpha, eta, 5, d_init=d)
         if j == K:
             err = np.abs(g["disp"][v] - dref[v])
             assert (err <= e2e.smooth_bar(dref[v])).all(), err.max()
