@@ -63,6 +63,32 @@ def test_research_step_matches_oracle(B, orc, win, rng_, eta, chess, spread):
     assert (g != o).any()  # the step moved some pixels
 
 
+def test_research_step_full_frame(B, orc):
+    """One re-search step on the 960x540 frame of the 30-frame workload, in
+    the launch shape of the pipeline (every block of the frame): o the
+    rounded ground truth, d that plus noise, 5 % of the pixels masked."""
+    import torch
+    fr = synth.c2_sequence(1)[0]
+    L, R = fr["left"], fr["right"]
+    gt = fr["gt_left"]
+    r = np.random.default_rng(540)
+    o = np.where(np.isnan(gt), 0, np.rint(np.nan_to_num(gt))).astype(np.int16)
+    m = (~np.isnan(gt) & (r.random(L.shape) >= 0.05)).astype(np.uint8)
+    d = o.astype(np.float64) + r.uniform(-2.0, 2.0, size=L.shape)
+    g = np_(B.st_research(cu(L), cu(R), 0, 127, 11, cu(o), cu(m),
+                          torch.tensor(d, dtype=torch.float64, device="cuda"), 5, 0.01))
+    eta32 = float(np.float32(0.01))
+    want = orc.research(L, R, 0, 127, 11, o.astype(np.int32), m, d, 5, eta32)
+    bad = np.argwhere(g != want)
+    for (y, x) in bad:
+        cg = _cost(L, R, y, x, int(g[y, x]), d[y, x], 11, eta32)
+        cw = _cost(L, R, y, x, int(want[y, x]), d[y, x], 11, eta32)
+        assert abs(cg - cw) < 1e-9, (y, x, g[y, x], want[y, x], cg, cw)
+    assert len(bad) <= 3
+    assert np.array_equal(g[m == 0], o[m == 0])
+    assert (g != o).mean() > 0.01
+
+
 def test_research_step_pitched(B, orc):
     """Rows at an odd pitch (every row at another byte alignment), a ragged
     band and block at both ends."""
