@@ -63,6 +63,33 @@ def test_research_step_matches_oracle(B, orc, win, rng_, eta, chess, spread):
     assert (g != o).any()  # the step moved some pixels
 
 
+@pytest.mark.parametrize("win,chess", [(15, False), (9, True)])
+def test_research_step_widest_stage(B, orc, win, chess):
+    """256 disparities, range 64 and d spread over the whole range: a block's
+    candidates span up to 255 disparities, the widest R stage (the largest
+    LDS allocation of the kernel)."""
+    import torch
+    p = synth.make_pair(40, 420, 255, 91)
+    L, R = p["left"], p["right"]
+    r = np.random.default_rng(256 + win)
+    o = r.integers(0, 256, size=L.shape).astype(np.int16)
+    m = (r.random(L.shape) >= 0.05).astype(np.uint8)
+    d = r.uniform(-10.0, 265.0, size=L.shape)
+    g = np_(B.st_research(cu(L), cu(R), 0, 255, win, cu(o), cu(m),
+                          torch.tensor(d, dtype=torch.float64, device="cuda"), 64, 0.01,
+                          chess=chess))
+    eta32 = float(np.float32(0.01))
+    want = orc.research(L, R, 0, 255, win, o.astype(np.int32), m, d, 64, eta32, chess=chess)
+    bad = np.argwhere(g != want)
+    for (y, x) in bad:
+        cg = _cost(L, R, y, x, int(g[y, x]), d[y, x], win, eta32, chess)
+        cw = _cost(L, R, y, x, int(want[y, x]), d[y, x], win, eta32, chess)
+        assert abs(cg - cw) < 1e-9, (y, x, g[y, x], want[y, x], cg, cw)
+    assert len(bad) <= 3
+    assert np.array_equal(g[m == 0], o[m == 0])
+    assert (g != o).mean() > 0.3
+
+
 def test_research_step_full_frame(B, orc):
     """One re-search step on the 960x540 frame of the 30-frame workload, in
     the launch shape of the pipeline (every block of the frame): o the
