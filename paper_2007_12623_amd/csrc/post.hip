@@ -1707,9 +1707,10 @@ __global__ __launch_bounds__(256) void box_h_lds_kernel(PostPair one, const Post
 // Window sums of the candidates c0 .. c0 + 3 of a pixel whose window starts
 // at packed row r0 and L stage column tx; rs is the R stage column of window
 // column 0 at candidate c0 + 3 (candidate c0 + e at rs + 3 - e).  Reads
-// stage columns rs .. rs + WIN + 2 of the R part: in the row even where a
-// candidate past the pixel's last one reaches below column 0 (its sum is
-// not used).
+// stage columns rs .. rs + WIN + 2 of the R part.  When c0 + 3 is past the
+// block's largest candidate, rs is down to -3: those reads land in the L
+// part of the same packed row (inside the stage), and only the sums of the
+// candidates past the pixel's last one, which are never used, take them.
 template <int WIN, bool CH>
 __device__ __forceinline__ void rs_sums4(const uint32_t *Pk, int S, int QL, int r0, int tx, int rs,
                                          uint32_t (&acc)[4]) {
