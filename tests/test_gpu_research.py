@@ -90,6 +90,31 @@ def test_research_step_widest_stage(B, orc, win, chess):
     assert (g != o).mean() > 0.3
 
 
+@pytest.mark.parametrize("H,W,far", [(11, 30, False), (11, 30, True), (13, 140, False)])
+def test_research_step_degenerate(B, orc, H, W, far):
+    """A frame one window high (a single row of pixels can have candidates,
+    one band, one partial block) and one whose smoothed d lie far outside
+    the range (no pixel has a candidate: the output is o)."""
+    import torch
+    r = np.random.default_rng(H * W)
+    L = r.integers(0, 256, size=(H, W)).astype(np.uint8)
+    R = np.roll(L, -3, axis=1)
+    o = r.integers(0, 8, size=(H, W)).astype(np.int16)
+    m = (r.random((H, W)) >= 0.1).astype(np.uint8)
+    d = np.full((H, W), 1e4) if far else r.uniform(-1.0, 8.0, size=(H, W))
+    g = np_(B.st_research(cu(L), cu(R), 0, 7, 11, cu(o), cu(m),
+                          torch.tensor(d, dtype=torch.float64, device="cuda"), 5, 0.01))
+    eta32 = float(np.float32(0.01))
+    want = orc.research(L, R, 0, 7, 11, o.astype(np.int32), m, d, 5, eta32)
+    for (y, x) in np.argwhere(g != want):
+        cg = _cost(L, R, y, x, int(g[y, x]), d[y, x], 11, eta32)
+        cw = _cost(L, R, y, x, int(want[y, x]), d[y, x], 11, eta32)
+        assert abs(cg - cw) < 1e-9, (y, x, g[y, x], want[y, x], cg, cw)
+    assert (g != want).sum() <= 1
+    if far:
+        assert np.array_equal(g, o)
+
+
 def test_research_step_full_frame(B, orc):
     """One re-search step on the 960x540 frame of the 30-frame workload, in
     the launch shape of the pipeline (every block of the frame): o the
