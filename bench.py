@@ -210,7 +210,7 @@ def main():
         cpu_worker(args.cpu_seconds)
         return
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported in this build "
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this script "
               "(pairs and row bands would shard across GPUs with no exchange).", file=sys.stderr)
         sys.exit(2)
     import torch

@@ -42,7 +42,7 @@ typedef enum {
   ST_ENOMEM = -2,       /* device scratch could not be allocated */
   ST_EHIP = -3,         /* a HIP runtime call or kernel launch failed */
   ST_ENODEV = -4,       /* no usable gfx950 device */
-  ST_EUNSUPPORTED = -5  /* valid request this build does not implement */
+  ST_EUNSUPPORTED = -5  /* valid request the library does not implement */
 } st_status;
 
 typedef enum { ST_FP32 = 0, ST_FP16 = 1, ST_BF16 = 2 } st_precision;

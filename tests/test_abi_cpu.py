@@ -67,7 +67,7 @@ def test_stereo_match_argument_errors(kw, msg):
 
 @pytest.mark.parametrize("dmax", [0, 3, 6])
 def test_short_ranges_are_unsupported(dmax):
-    """Fewer than 8 candidates is a valid request that this build does not
+    """Fewer than 8 candidates is a valid request that the library does not
     implement: ST_EUNSUPPORTED, before any device call, also in a batch."""
     assert _match(dmin=0, dmax=dmax) == B.ST_EUNSUPPORTED
     assert "fewer than 8" in B.st_last_error()
