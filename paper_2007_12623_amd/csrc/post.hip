@@ -156,10 +156,11 @@ constexpr int SPB_T = 256, SPB_TY = 8, SP_NPT = SPB_TY * SP_TX / SPB_T;
 __host__ __device__ inline int sp_groups(int win) { return (win + 3) / 4; }
 __host__ __device__ inline int sp_quads_l(int win) { return (SP_TX + win - 1 + 3) / 4; }
 __host__ __device__ inline int sp_quads_r(int win, int range) { return (SP_TX + range + 2 + win - 1 + 3) / 4; }
-// LDS bytes of the packed stage for windows up to maxWin and maxD disparities
-static size_t sp_lds_bytes(int maxWin, int maxD) {
+// LDS bytes of the packed stage for windows up to maxWin and maxD
+// disparities, bands of ty rows
+static size_t sp_lds_bytes(int maxWin, int maxD, int ty = SPB_TY) {
   const size_t S = 4 * (size_t)(sp_quads_l(maxWin) + sp_quads_r(maxWin, maxD - 1));
-  return (size_t)(SPB_TY + 4 * (sp_groups(maxWin) - 1)) * S * 4;
+  return (size_t)(ty + 4 * (sp_groups(maxWin) - 1)) * S * 4;
 }
 
 // The dword-aligned dword at byte offset a of base[0, span) (base + a is
@@ -1774,26 +1775,30 @@ __device__ __forceinline__ int rs_best(const PostPair &P, const uint32_t *Pk, in
   return onew;
 }
 
-// Pk: the packed stage in dynamic LDS, sp_lds_bytes(win, dmax - dmin + 1)
-// bytes at least (the block's candidates lie in [dmin, dmax]).
-template <bool B>
+// Pk: the packed stage in dynamic LDS, sp_lds_bytes(win, dmax - dmin + 1,
+// TY) bytes at least (the block's candidates lie in [dmin, dmax]).  TY: rows
+// per band, 8 as in the sub-pixel kernel, or 4 for launches with few blocks
+// (a single pair), where the shorter bands' extra packing costs less than
+// the idle SIMDs.
+template <bool B, int TY>
 __global__ __launch_bounds__(SPB_T) void research_kernel(PostPair one, const PostPair *__restrict__ many,
                                                          int osrc, int msrc, int odst, int dplane,
                                                          int range, double eta) {
+  constexpr int NPT = TY * SP_TX / SPB_T;  // pixels per thread (rows ty + 2 j)
   PAIR;
   uint32_t *Pk = sp_dyn;
   __shared__ int s_cmin, s_cmax;
   const int tid = threadIdx.x, tx = tid & (SP_TX - 1), ty = tid / SP_TX;
-  const int x0 = bp.x * SP_TX, y0 = bp.y * SPB_TY;
+  const int x0 = bp.x * SP_TX, y0 = bp.y * TY;
   if (x0 >= P.W || y0 >= P.H) return;  // uniform per block
   const int W = P.W, H = P.H, win = P.win, h = win / 2;
   const int x = x0 + tx;
   const size_t N = (size_t)W * H;
-  int lo[SP_NPT], hi[SP_NPT];
-  double dd[SP_NPT];
+  int lo[NPT], hi[NPT];
+  double dd[NPT];
   int cl = 1 << 30, chi = -(1 << 30);
 #pragma unroll
-  for (int j = 0; j < SP_NPT; ++j) {
+  for (int j = 0; j < NPT; ++j) {
     const int y = y0 + ty + 2 * j;
     const size_t k = (size_t)y * W + x;
     // pixels whose own window is inside the image can have a defined
@@ -1830,13 +1835,13 @@ __global__ __launch_bounds__(SPB_T) void research_kernel(PostPair one, const Pos
   const int QL = sp_quads_l(win), QR = cmin <= cmax ? sp_quads_r(win, cmax - cmin) : 0;
   const int S = 4 * (QL + QR);
   if (cmin <= cmax) {
-    const int PR = min(SPB_TY, H - y0) + 4 * (sp_groups(win) - 1);
+    const int PR = min(TY, H - y0) + 4 * (sp_groups(win) - 1);
     sp_pack(Pk, S, PR, gro(P.left), gro(P.right), P.pitch, (long long)(H - 1) * P.pitch + W, y0 - h,
             x0 - h, QL, x0 - cmax - h, QR, tid);
   }
   __syncthreads();
 #pragma unroll
-  for (int j = 0; j < SP_NPT; ++j) {
+  for (int j = 0; j < NPT; ++j) {
     const int r0 = ty + 2 * j, y = y0 + r0;
     if (x >= W || y >= H) continue;
     const size_t k = (size_t)y * W + x;
@@ -2021,14 +2026,19 @@ static void box2d(const PostLaunch &L, BoxArgs A) {
 // disparity (NaN where invalid) and valid_mask.
 static void launch_research(const PostLaunch &L, int osrc, int msrc, int odst, int dplane, int range,
                             double eta) {
-  const dim3 grid(ceil_div(L.maxW, SP_TX), ceil_div(L.maxH, SPB_TY), L.npairs);
-  const size_t lds = sp_lds_bytes(L.maxWin, L.maxD);
-  if (L.many)
-    hipLaunchKernelGGL(research_kernel<true>, grid, dim3(SPB_T), lds, L.s, L.one, L.many, osrc, msrc,
-                       odst, dplane, range, eta);
-  else
-    hipLaunchKernelGGL(research_kernel<false>, grid, dim3(SPB_T), lds, L.s, L.one, L.many, osrc, msrc,
-                       odst, dplane, range, eta);
+  const int gx = ceil_div(L.maxW, SP_TX);
+  const bool shortb = (long long)gx * ceil_div(L.maxH, SPB_TY) * L.npairs < 1024;
+  const int ty = shortb ? 4 : SPB_TY;
+  const dim3 grid(gx, ceil_div(L.maxH, ty), L.npairs);
+  const size_t lds = sp_lds_bytes(L.maxWin, L.maxD, ty);
+#define RSL(b, t) \
+  hipLaunchKernelGGL((research_kernel<b, t>), grid, dim3(SPB_T), lds, L.s, L.one, L.many, osrc, msrc, odst, dplane, range, eta)
+  if (L.many) {
+    if (shortb) RSL(true, 4); else RSL(true, SPB_TY);
+  } else {
+    if (shortb) RSL(false, 4); else RSL(false, SPB_TY);
+  }
+#undef RSL
 }
 hipError_t post_research(const PostLaunch &L, int osrc, int msrc, int odst, int dplane, int range,
                          float eta) {

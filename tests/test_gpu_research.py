@@ -115,6 +115,30 @@ def test_research_step_degenerate(B, orc, H, W, far):
         assert np.array_equal(g, o)
 
 
+def test_research_step_eight_row_bands(B, orc):
+    """A frame large enough that the single-pair launch takes 8-row bands
+    (1088 x 1024: 9 x 128 blocks; smaller launches take 4-row bands)."""
+    import torch
+    p = synth.make_pair(1024, 1088, 63, 1024)
+    L, R = p["left"], p["right"]
+    gt = p["gt_left"]
+    r = np.random.default_rng(1088)
+    o = np.where(np.isnan(gt), 0, np.rint(np.nan_to_num(gt))).astype(np.int16)
+    m = (~np.isnan(gt) & (r.random(L.shape) >= 0.05)).astype(np.uint8)
+    d = o.astype(np.float64) + r.uniform(-3.0, 3.0, size=L.shape)
+    g = np_(B.st_research(cu(L), cu(R), 0, 63, 11, cu(o), cu(m),
+                          torch.tensor(d, dtype=torch.float64, device="cuda"), 5, 0.01))
+    eta32 = float(np.float32(0.01))
+    want = orc.research(L, R, 0, 63, 11, o.astype(np.int32), m, d, 5, eta32)
+    bad = np.argwhere(g != want)
+    for (y, x) in bad:
+        cg = _cost(L, R, y, x, int(g[y, x]), d[y, x], 11, eta32)
+        cw = _cost(L, R, y, x, int(want[y, x]), d[y, x], 11, eta32)
+        assert abs(cg - cw) < 1e-9, (y, x, g[y, x], want[y, x], cg, cw)
+    assert len(bad) <= 3
+    assert (g != o).mean() > 0.01
+
+
 def test_research_step_full_frame(B, orc):
     """One re-search step on the 960x540 frame of the 30-frame workload, in
     the launch shape of the pipeline (every block of the frame): o the
