@@ -151,7 +151,7 @@ __global__ void mark_invalid_kernel(const int16_t *__restrict__ o, const uint8_t
 // lane.  Stage columns 0 .. 4 QL - 1 are L(., x0 - h + c); the next 4 QR
 // are R(., x0 - omax - 1 - h + c), omax the largest disparity of the block.
 constexpr int SP_TX = 128, SP_MAXWIN = 15;
-constexpr int SPB_T = 256, SPB_TY = 8, SP_NPT = SPB_TY * SP_TX / SPB_T;
+constexpr int SPB_T = 256, SPB_TY = 8;
 
 __host__ __device__ inline int sp_groups(int win) { return (win + 3) / 4; }
 __host__ __device__ inline int sp_quads_l(int win) { return (SP_TX + win - 1 + 3) / 4; }
@@ -305,21 +305,23 @@ __device__ __forceinline__ int ld32(const int32_t *p, uint32_t off) {
   return *(const GLOBAL int32_t *)((const GLOBAL char *)p + off);
 }
 
-// Per-pixel state of the sub-pixel block: the WTA disparity and whether it
-// is a valid candidate.
+// Per-pixel state of the sub-pixel block (bands of TY rows, NPT pixels a
+// thread): the WTA disparity and whether it is a valid candidate.
+template <int TY>
 struct SpPix {
-  int o[SP_NPT];
-  bool valid[SP_NPT];
+  static constexpr int NPT = TY * SP_TX / SPB_T;
+  int o[NPT];
+  bool valid[NPT];
 };
 
-template <int WIN, bool CH>
+template <int WIN, bool CH, int TY>
 __device__ __forceinline__ void sp_finish(const PostPair &P, const uint32_t *Pk, int S, int QL,
-                                          const SpPix &X, int tx, int ty, int x, int y0, int omax) {
+                                          const SpPix<TY> &X, int tx, int ty, int x, int y0, int omax) {
   const long long n = CH ? ((long long)WIN * WIN + 1) / 2 : (long long)WIN * WIN;
   const double qn = __builtin_nan("");
   const int W = P.W, H = P.H;
 #pragma unroll
-  for (int j = 0; j < SP_NPT; ++j) {
+  for (int j = 0; j < SpPix<TY>::NPT; ++j) {
     const int r0 = ty + 2 * j, y = y0 + r0;
     if (x >= W || y >= H) continue;
     const size_t k = (size_t)y * W + x;
@@ -389,19 +391,22 @@ __device__ __forceinline__ void sp_finish(const PostPair &P, const uint32_t *Pk,
   }
 }
 
-// Pk: the packed stage in dynamic LDS, sp_lds_bytes(win, dmax - dmin + 1)
-// bytes at least.
+// Pk: the packed stage in dynamic LDS, sp_lds_bytes(win, dmax - dmin + 1,
+// TY) bytes at least.  TY: rows per band (SPB_TY, or 4 in launches with few
+// blocks).
+template <int TY>
 __device__ __forceinline__ void subpixel_block(const PostPair &P, const BlockPos &bp, uint32_t *Pk) {
+  constexpr int NPT = SpPix<TY>::NPT;
   __shared__ int s_omin, s_omax;
   const int tid = threadIdx.x, tx = tid & (SP_TX - 1), ty = tid / SP_TX;
-  const int x0 = bp.x * SP_TX, y0 = bp.y * SPB_TY;
+  const int x0 = bp.x * SP_TX, y0 = bp.y * TY;
   if (x0 >= P.W || y0 >= P.H) return;  // uniform per block
   const int W = P.W, H = P.H, win = P.win, h = win / 2;
   const int x = x0 + tx;
-  SpPix X;
+  SpPix<TY> X;
   int lo = 1 << 30, hi = -(1 << 30);
 #pragma unroll
-  for (int j = 0; j < SP_NPT; ++j) {
+  for (int j = 0; j < NPT; ++j) {
     const int y = y0 + ty + 2 * j;
     const bool in = x < W && y < H;
     const size_t k = (size_t)y * W + x;
@@ -433,15 +438,15 @@ __device__ __forceinline__ void subpixel_block(const PostPair &P, const BlockPos
   const int S = 4 * (QL + QR);
   if (omin <= omax) {
     // a valid pixel's window rows lie inside the band's rows plus the halo
-    const int PR = min(SPB_TY, H - y0) + 4 * (sp_groups(win) - 1);
+    const int PR = min(TY, H - y0) + 4 * (sp_groups(win) - 1);
     sp_pack(Pk, S, PR, gro(P.left), gro(P.right), P.pitch, (long long)(H - 1) * P.pitch + W, y0 - h,
             x0 - h, QL, x0 - omax - 1 - h, QR, tid);
   }
   __syncthreads();
 #define SPF(w)                                                               \
   case w:                                                                    \
-    if (P.chess) sp_finish<w, true>(P, Pk, S, QL, X, tx, ty, x, y0, omax);   \
-    else sp_finish<w, false>(P, Pk, S, QL, X, tx, ty, x, y0, omax);          \
+    if (P.chess) sp_finish<w, true, TY>(P, Pk, S, QL, X, tx, ty, x, y0, omax);   \
+    else sp_finish<w, false, TY>(P, Pk, S, QL, X, tx, ty, x, y0, omax);          \
     break
   switch (win) {
     SPF(3);
@@ -451,8 +456,8 @@ __device__ __forceinline__ void subpixel_block(const PostPair &P, const BlockPos
     SPF(11);
     SPF(13);
     default:
-      if (P.chess) sp_finish<15, true>(P, Pk, S, QL, X, tx, ty, x, y0, omax);
-      else sp_finish<15, false>(P, Pk, S, QL, X, tx, ty, x, y0, omax);
+      if (P.chess) sp_finish<15, true, TY>(P, Pk, S, QL, X, tx, ty, x, y0, omax);
+      else sp_finish<15, false, TY>(P, Pk, S, QL, X, tx, ty, x, y0, omax);
       break;
   }
 #undef SPF
@@ -463,7 +468,7 @@ extern __shared__ __align__(16) uint32_t sp_dyn[];
 template <bool B>
 __global__ __launch_bounds__(SPB_T) void subpixel_kernel(PostPair one, const PostPair *__restrict__ many) {
   PAIR;
-  subpixel_block(P, bp, sp_dyn);
+  subpixel_block<SPB_TY>(P, bp, sp_dyn);
 }
 
 // ---------------------------------------------------------------- LR check
@@ -512,7 +517,7 @@ __global__ void lr_check_kernel(PostPair one, const PostPair *__restrict__ many,
 // Sub-pixel fit and left-right check in one launch (independent work on the
 // same maps): the first nsp blocks of a pair run the sub-pixel blocks (nspx
 // of them per row band), the rest the check (nlrx per row).
-template <bool B>
+template <bool B, int TY>
 __global__ __launch_bounds__(SPB_T) void subpixel_lr_kernel(PostPair one, const PostPair *__restrict__ many,
                                                            int nspx, int nsp, int nlrx, int tol, int dst) {
   PAIR;
@@ -520,7 +525,7 @@ __global__ __launch_bounds__(SPB_T) void subpixel_lr_kernel(PostPair one, const 
   if (bp.x < nsp) {
     q.x = bp.x % nspx;
     q.y = bp.x / nspx;
-    subpixel_block(P, q, sp_dyn);
+    subpixel_block<TY>(P, q, sp_dyn);
   } else {
     const int i = bp.x - nsp;
     q.x = i % nlrx;
@@ -1927,16 +1932,22 @@ hipError_t post_subpixel(const PostLaunch &L) {
   return hipGetLastError();
 }
 hipError_t post_subpixel_lr(const PostLaunch &L, int tol, int dst) {
-  const int nspx = ceil_div(L.maxW, SP_TX), nsp = nspx * ceil_div(L.maxH, SPB_TY);
+  // 4-row bands when the sub-pixel blocks would be fewer than 1024 (a single
+  // pair): the extra packing costs less than the idle SIMDs
+  const int nspx = ceil_div(L.maxW, SP_TX);
+  const bool shortb = (long long)nspx * ceil_div(L.maxH, SPB_TY) * L.npairs < 1024;
+  const int ty = shortb ? 4 : SPB_TY, nsp = nspx * ceil_div(L.maxH, ty);
   const int nlrx = ceil_div(L.maxW, PIX_SEG), nlr = nlrx * L.maxH;
   const dim3 grid(nsp + nlr, 1, L.npairs);
-  const size_t lds = sp_lds_bytes(L.maxWin, L.maxD);
-  if (L.many)
-    hipLaunchKernelGGL(subpixel_lr_kernel<true>, grid, dim3(SPB_T), lds, L.s, L.one, L.many, nspx, nsp,
-                       nlrx, tol, dst);
-  else
-    hipLaunchKernelGGL(subpixel_lr_kernel<false>, grid, dim3(SPB_T), lds, L.s, L.one, L.many, nspx, nsp,
-                       nlrx, tol, dst);
+  const size_t lds = sp_lds_bytes(L.maxWin, L.maxD, ty);
+#define SPL(b, t) \
+  hipLaunchKernelGGL((subpixel_lr_kernel<b, t>), grid, dim3(SPB_T), lds, L.s, L.one, L.many, nspx, nsp, nlrx, tol, dst)
+  if (L.many) {
+    if (shortb) SPL(true, 4); else SPL(true, SPB_TY);
+  } else {
+    if (shortb) SPL(false, 4); else SPL(false, SPB_TY);
+  }
+#undef SPL
   return hipGetLastError();
 }
 hipError_t post_lr(const PostLaunch &L, int tol, int dst) {
