@@ -1424,7 +1424,8 @@ __global__ void box_v_kernel(PostPair one, const PostPair *__restrict__ many, Bo
 //           alpha b_1 (plane F_S) -> plane out
 //   mode 6: (re-search, where s changes between iterations) a -> F_A as in
 //           mode 4, and b = a - alpha s - (1 - alpha) d_prev (Eq. 2) with
-//           d_prev the previous iteration's d (plane F_D) -> plane out
+//           d_prev the previous iteration's d (plane F_D) and s from plane
+//           F_S, the re-search's output -> plane out
 // (b and a are 0 on invalid pixels, as the masked sums need.)  The inputs
 // the stage reads are gathered first (box_store_in), so that a caller can
 // load them ahead of time.
@@ -1445,8 +1446,11 @@ __device__ __forceinline__ BoxStoreIn box_store_in(const PostPair &P, const BoxA
   if (!A.counts) q.cnt = ((const GLOBAL float *)(gro(P.f) + (size_t)F_CNT * N))[k];
   if (A.mode == 2 || A.mode == 3) q.a = gro(P.f)[(size_t)F_A * N + k];
   if (A.mode == 5) q.s = gro(P.f)[(size_t)F_S * N + k];
-  if (A.mode == 6) q.a = gro(P.f)[(size_t)F_D * N + k];
-  if (A.mode == 4 || A.mode == 6) {
+  if (A.mode == 6) {
+    q.a = gro(P.f)[(size_t)F_D * N + k];
+    q.s = gro(P.f)[(size_t)F_S * N + k];
+  }
+  if (A.mode == 4) {
     // s without a branch on the mask: both loads issue at once
     if (P.s_in) {
       q.s = (double)gro(P.s_in)[k];
@@ -1784,11 +1788,12 @@ __device__ __forceinline__ int rs_best(const PostPair &P, const uint32_t *Pk, in
 // TY) bytes at least (the block's candidates lie in [dmin, dmax]).  TY: rows
 // per band, 8 as in the sub-pixel kernel, or 4 for launches with few blocks
 // (a single pair), where the shorter bands' extra packing costs less than
-// the idle SIMDs.
+// the idle SIMDs.  splane: also write the new o on valid pixels (0
+// elsewhere) as FP64 into plane F_S, the next smoothing pass's input.
 template <bool B, int TY>
 __global__ __launch_bounds__(SPB_T) void research_kernel(PostPair one, const PostPair *__restrict__ many,
                                                          int osrc, int msrc, int odst, int dplane,
-                                                         int range, double eta) {
+                                                         int range, double eta, int splane) {
   constexpr int NPT = TY * SP_TX / SPB_T;  // pixels per thread (rows ty + 2 j)
   PAIR;
   uint32_t *Pk = sp_dyn;
@@ -1872,6 +1877,7 @@ __global__ __launch_bounds__(SPB_T) void research_kernel(PostPair one, const Pos
 #undef RSB
     }
     P.ob[odst][k] = (int16_t)onew;
+    if (splane) P.f[(size_t)F_S * N + k] = P.mb[msrc][k] ? (double)onew : 0.0;
   }
 }
 
@@ -2036,14 +2042,14 @@ static void box2d(const PostLaunch &L, BoxArgs A) {
 // Improved Laplacian smoothing of (ob[src], delta, mb[src]) or s_in; writes
 // disparity (NaN where invalid) and valid_mask.
 static void launch_research(const PostLaunch &L, int osrc, int msrc, int odst, int dplane, int range,
-                            double eta) {
+                            double eta, int splane) {
   const int gx = ceil_div(L.maxW, SP_TX);
   const bool shortb = (long long)gx * ceil_div(L.maxH, SPB_TY) * L.npairs < 1024;
   const int ty = shortb ? 4 : SPB_TY;
   const dim3 grid(gx, ceil_div(L.maxH, ty), L.npairs);
   const size_t lds = sp_lds_bytes(L.maxWin, L.maxD, ty);
 #define RSL(b, t) \
-  hipLaunchKernelGGL((research_kernel<b, t>), grid, dim3(SPB_T), lds, L.s, L.one, L.many, osrc, msrc, odst, dplane, range, eta)
+  hipLaunchKernelGGL((research_kernel<b, t>), grid, dim3(SPB_T), lds, L.s, L.one, L.many, osrc, msrc, odst, dplane, range, eta, splane)
   if (L.many) {
     if (shortb) RSL(true, 4); else RSL(true, SPB_TY);
   } else {
@@ -2053,7 +2059,7 @@ static void launch_research(const PostLaunch &L, int osrc, int msrc, int odst, i
 }
 hipError_t post_research(const PostLaunch &L, int osrc, int msrc, int odst, int dplane, int range,
                          float eta) {
-  launch_research(L, osrc, msrc, odst, dplane, range, (double)eta);
+  launch_research(L, osrc, msrc, odst, dplane, range, (double)eta, 0);
   return hipGetLastError();
 }
 
@@ -2100,17 +2106,18 @@ hipError_t post_hc(const PostLaunch &L, int src, int R, int K, float alpha, int 
     }
     return hipGetLastError();
   }
-  // per iteration two passes: a = box(o m) / box(m) from the current o (s
-  // formed on the fly) with b = a - alpha o - (1 - alpha) d_prev in its
-  // output stage (the first also boxes the mask for the counts), then
-  // d = a - box(b m) / box(m)
+  // per iteration two passes: a = box(o m) / box(m) from the current o
+  // (formed on the fly from the map in the first iteration, later read from
+  // the plane F_S that the re-search writes) with b = a - alpha o -
+  // (1 - alpha) d_prev in its output stage (the first pass also boxes the
+  // mask for the counts), then d = a - box(b m) / box(m)
   for (int it = 0; it < K; ++it) {
-    BoxArgs ab = args(BOX_IN_S, F_IN, it == 0 ? 4 : 6);
+    BoxArgs ab = args(it == 0 ? (int)BOX_IN_S : (int)F_S, F_IN, it == 0 ? 4 : 6);
     ab.counts = it == 0 ? 1 : 0;
     box2d(L, ab);
     box2d(L, args(F_IN, F_IN, it == K - 1 ? 3 : 2));
     if (it < K - 1) {
-      launch_research(L, ocur, src, oalt, (int)F_D, range, (double)eta);
+      launch_research(L, ocur, src, oalt, (int)F_D, range, (double)eta, 1);
       if (trace && !L.many && it < trace->n) {
         const size_t N = (size_t)L.one.H * L.one.W;
         hipError_t e = hipMemcpyAsync(trace->o + it * N, L.one.ob[oalt], 2 * N,
